@@ -1,0 +1,134 @@
+"""The 3x3 block Jacobian and its sub-blocks (oracle; test infrastructure only).
+
+A_h = [[M, C_ms, 0], [C_sm, S, C_sf], [C_fm, C_fs, F]] with the unknowns
+ordered (mesh, solid, fluid), paper Section 3.4 (the block matrix A_h).
+The solid block is split as S = [[S_vv, S_vu], [S_uv, S_uu]] over
+(v_s, u_s) (Section 4.3) and the fluid block as F = [[A_f, G], [D, 0]] over
+(v_f, p) (Section 4.4).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+NAMES = ("M", "C_ms", "C_sm", "S", "C_sf", "C_fm", "C_fs", "F")
+
+
+def to_scipy(b) -> sp.csr_matrix:
+    """fsigen.Csr -> scipy CSR (same arrays, canonical order)."""
+    m = sp.csr_matrix((b.val, b.col.astype(np.int64), b.rowptr), shape=(b.nrows, b.ncols))
+    m.sort_indices()
+    return m
+
+
+def spmv(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
+    """y_i = sum_k val[k] * x[col[k]] over row i, summed in storage order.
+
+    Pinned against dense mat-vec and unit columns (tests/test_oracle_blocks).
+    """
+    rows = np.repeat(np.arange(A.shape[0]), np.diff(A.indptr))
+    return np.bincount(rows, weights=A.data * x[A.indices], minlength=A.shape[0])
+
+
+class BlockSystem:
+    """A_h with its block views, built from one fsigen.FsiSystem."""
+
+    def __init__(self, sysm):
+        self.sys = sysm
+        self.dim = sysm.dim
+        self.n_m, self.n_s, self.n_f = sysm.n_m, sysm.n_s, sysm.n_f
+        self.n_vs, self.n_vf, self.n_p = sysm.n_vs, sysm.n_vf, sysm.n_p
+        self.N = sysm.N
+        self.dt_theta = sysm.dt_theta
+        self.B = {k: to_scipy(v) for k, v in sysm.blocks.items()}
+        nvs, nvf = self.n_vs, self.n_vf
+        S, F = self.B["S"], self.B["F"]
+        # solid sub-blocks over (v_s | u_s)
+        self.S_vv = S[:nvs, :nvs].tocsr()
+        self.S_vu = S[:nvs, nvs:].tocsr()
+        self.S_uv = S[nvs:, :nvs].tocsr()
+        self.S_uu = S[nvs:, nvs:].tocsr()
+        # fluid sub-blocks over (v_f | p)
+        self.A_f = F[:nvf, :nvf].tocsr()
+        self.G = F[:nvf, nvf:].tocsr()
+        self.D = F[nvf:, :nvf].tocsr()
+        self.F_pp = F[nvf:, nvf:].tocsr()
+        for m in (self.S_vv, self.S_vu, self.S_uv, self.S_uu, self.A_f, self.G, self.D, self.F_pp):
+            m.sort_indices()
+
+    # -- splitting ---------------------------------------------------------
+    def split(self, x):
+        a, b = self.n_m, self.n_m + self.n_s
+        return x[:a], x[a:b], x[b:]
+
+    def join(self, xm, xs, xf):
+        return np.concatenate([xm, xs, xf])
+
+    # -- block mat-vec, Section 3.4 ------------------------------------------
+    def matvec(self, x: np.ndarray) -> np.ndarray:
+        """y = A_h x over the eight stored blocks (C_sm included)."""
+        B = self.B
+        xm, xs, xf = self.split(x)
+        ym = spmv(B["M"], xm) + spmv(B["C_ms"], xs)
+        ys = spmv(B["C_sm"], xm) + spmv(B["S"], xs) + spmv(B["C_sf"], xf)
+        yf = spmv(B["C_fm"], xm) + spmv(B["C_fs"], xs) + spmv(B["F"], xf)
+        return self.join(ym, ys, yf)
+
+    def dense(self, drop_csm: bool = False) -> np.ndarray:
+        """Dense A_h (tiny systems only), optionally with C_sm := 0."""
+        N = self.N
+        A = np.zeros((N, N))
+        o = (0, self.n_m, self.n_m + self.n_s, N)
+        place = {"M": (0, 0), "C_ms": (0, 1), "C_sm": (1, 0), "S": (1, 1), "C_sf": (1, 2),
+                 "C_fm": (2, 0), "C_fs": (2, 1), "F": (2, 2)}
+        for name, (i, j) in place.items():
+            if drop_csm and name == "C_sm":
+                continue
+            A[o[i]:o[i + 1], o[j]:o[j + 1]] = self.B[name].toarray()
+        return A
+
+    # -- derived operators ---------------------------------------------------
+    def solid_schur(self) -> sp.csr_matrix:
+        """Sigma_s = S_vv + dt*theta*S_vu.
+
+        Eliminating u_s with S_uu = M and S_uv = -dt*theta*M (equal-order
+        mass matrices, Section 4.3) gives x_u = M^{-1} r_u + dt*theta*x_v and
+        hence (S_vv + dt*theta*S_vu) x_v = r_v - S_vu M^{-1} r_u.  On rows of
+        pure solid nodes this is rho_s M + dt^2 theta^2 K of Section 4.3.
+        Pinned by the dense solid-equivalence test.
+        """
+        m = (self.S_vv + self.dt_theta * self.S_vu).tocsr()
+        m.sort_indices()
+        return m
+
+    def fluid_schur(self) -> sp.csr_matrix:
+        """S_p = -D diag(A_f)^{-1} G (SIMPLE-type pressure Schur approximation).
+
+        The paper applies to the fluid block the same Schur-complement
+        elimination as for the solid (Section 4.4) without stating the
+        approximation; this is the reading recorded in the design notes.
+        Pinned: equals the exact Schur complement -D A_f^{-1} G when A_f is
+        diagonal (test), and is symmetric because G = -D^T.
+        """
+        dinv = 1.0 / self.A_f.diagonal()
+        m = (-(self.D @ sp.diags(dinv) @ self.G)).tocsr()
+        if self.F_pp.nnz:
+            m = (m + self.F_pp).tocsr()
+        m.eliminate_zeros()
+        m.sort_indices()
+        return m
+
+    def mesh_scalar(self) -> sp.csr_matrix:
+        """Scalar Laplacian L with M = L (x) I_d (frozen Jacobian-scaled mesh).
+
+        Raises if M does not have that structure.
+        """
+        d = self.dim
+        M = self.B["M"]
+        L = M[0::d, 0::d].tocsr()
+        L.sort_indices()
+        K = sp.kron(L, sp.identity(d), format="csr")
+        diff = abs(K - M)
+        if diff.nnz and diff.max() > 0.0:
+            raise ValueError("mesh block is not L (x) I_d")
+        return L

@@ -1,0 +1,121 @@
+"""Approximate block-LDU preconditioner (oracle; test infrastructure only).
+
+Algorithm "Evaluation of P^{-1} r" of the paper's Section 4.1, obtained from
+the block LDU factorisation of A_h after dropping C_sm and approximating the
+fluid Schur complement X by F:
+
+  1. x_m = M^{-1} r_m
+  2. x_s = S^{-1} r_s
+  3. x_f = F^{-1} (r_f - C_fm x_m - C_fs x_s)
+  4. x_s = x_s - S^{-1} C_sf x_f
+  5. x_m = x_m - M^{-1} C_ms x_s
+
+with the approximate inverses
+
+* M^{-1}: one AMG V-cycle on the scalar Laplacian L (M = L (x) I_d), applied
+  to each displacement component (Section 4.2);
+* S^{-1}: the solid Schur-complement algorithm of Section 4.3 with AMG on
+  Sigma_s = S_vv + dt theta S_vu and on the mass block S_uu:
+      y = V_Ms(r_u);  x_v = V_Sigma(r_v - S_vu y);  x_u = V_Ms(r_u - S_uv x_v);
+* F^{-1}: the same Schur-complement (Uzawa-like) elimination on
+  F = [[A_f, G], [D, 0]] with the pressure Schur approximation
+  S_p = -D diag(A_f)^{-1} G (Section 4.4, reading in the design notes):
+      y = V_A(r_v);  x_p = V_p(r_p - D y);  x_v = V_A(r_v - G x_p).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import amg
+from .blocks import BlockSystem
+
+H_NAMES = ("H_M", "H_SIG", "H_MS", "H_A", "H_P")
+
+
+def build_hierarchies(bs: BlockSystem, eps0=amg.EPS0, max_coarse=amg.MAX_COARSE,
+                      max_levels=amg.MAX_LEVELS) -> dict:
+    """The five SA hierarchies of the preconditioner."""
+    d = bs.dim
+    sysm = bs.sys
+    o = sysm.offsets
+    # coordinates of the solid velocity nodes (rigid-body modes of Sigma_s)
+    vs_nodes = sysm.dof_node[o[1]:o[1] + bs.n_vs:d]
+    xyz = sysm.coords[vs_nodes]
+    kw = dict(eps0=eps0, max_coarse=max_coarse, max_levels=max_levels)
+    L = bs.mesh_scalar()
+    H = {
+        "H_M": amg.setup(L, 1, amg.constant_modes(L.shape[0]), **kw),
+        "H_SIG": amg.setup(bs.solid_schur(), d, amg.rigid_body_modes(xyz), **kw),
+        "H_MS": amg.setup(bs.S_uu, 1, amg.constant_modes(bs.n_vs), **kw),
+        "H_A": amg.setup(bs.A_f, d, amg.translation_modes(bs.n_vf // d, d), **kw),
+        "H_P": amg.setup(bs.fluid_schur(), 1, amg.constant_modes(bs.n_p), **kw),
+    }
+    return H
+
+
+class BlockLDU:
+    """P^{-1} r by the paper's algorithm, with pluggable sub-inverses.
+
+    ``mesh_inv``, ``solid_inv`` and ``fluid_inv`` map a residual of the
+    corresponding block to an approximate solution.  ``cfs`` is the coupling
+    used in step 3 (C_fs in the paper's algorithm; the exact factorisation
+    uses C_fs - C_fm M^{-1} C_ms there) and ``fluid_inv`` may be replaced by
+    an exact inverse of the Schur complement X for identity tests.
+    """
+
+    def __init__(self, bs: BlockSystem, mesh_inv, solid_inv, fluid_inv, cfs=None):
+        self.bs = bs
+        self.mesh_inv, self.solid_inv, self.fluid_inv = mesh_inv, solid_inv, fluid_inv
+        self.cfs = cfs
+
+    def apply(self, r: np.ndarray) -> np.ndarray:
+        bs = self.bs
+        B = bs.B
+        r_m, r_s, r_f = bs.split(r)
+        x_m = self.mesh_inv(r_m)
+        x_s = self.solid_inv(r_s)
+        cfs_xs = self.cfs(x_s) if self.cfs is not None else B["C_fs"] @ x_s
+        x_f = self.fluid_inv(r_f - B["C_fm"] @ x_m - cfs_xs)
+        x_s = x_s - self.solid_inv(B["C_sf"] @ x_f)
+        x_m = x_m - self.mesh_inv(B["C_ms"] @ x_s)
+        return bs.join(x_m, x_s, x_f)
+
+    __call__ = apply
+
+
+def solid_schur_solve(bs: BlockSystem, ms_inv, sig_inv, r_s: np.ndarray) -> np.ndarray:
+    """Solid algorithm of Section 4.3 (u_s eliminated, then recovered)."""
+    nvs = bs.n_vs
+    r_v, r_u = r_s[:nvs], r_s[nvs:]
+    y = ms_inv(r_u)
+    x_v = sig_inv(r_v - bs.S_vu @ y)
+    x_u = ms_inv(r_u - bs.S_uv @ x_v)
+    return np.concatenate([x_v, x_u])
+
+
+def fluid_schur_solve(bs: BlockSystem, a_inv, p_inv, r_f: np.ndarray) -> np.ndarray:
+    """Uzawa-like Schur elimination of the fluid saddle point (Section 4.4)."""
+    nvf = bs.n_vf
+    r_v, r_p = r_f[:nvf], r_f[nvf:]
+    y = a_inv(r_v)
+    x_p = p_inv(r_p - bs.D @ y)
+    x_v = a_inv(r_v - bs.G @ x_p)
+    return np.concatenate([x_v, x_p])
+
+
+def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
+    """M^{-1} r_m with M = L (x) I_d: the scalar inverse per component."""
+    d = bs.dim
+    x = np.empty_like(r_m)
+    for c in range(d):
+        x[c::d] = l_inv(np.ascontiguousarray(r_m[c::d]))
+    return x
+
+
+def amg_preconditioner(bs: BlockSystem, H: dict) -> BlockLDU:
+    """The preconditioner of the hot path: every inverse one V(1,1) cycle."""
+    V = {k: (lambda h: (lambda b: amg.vcycle(h, b)))(h) for k, h in H.items()}
+    mesh = lambda r: mesh_solve(bs, V["H_M"], r)
+    solid = lambda r: solid_schur_solve(bs, V["H_MS"], V["H_SIG"], r)
+    fluid = lambda r: fluid_schur_solve(bs, V["H_A"], V["H_P"], r)
+    return BlockLDU(bs, mesh, solid, fluid)

@@ -1,0 +1,165 @@
+"""Oracle pins: the block-LDU algebra of Section 4 and the solid/fluid Schur steps.
+
+With exact sub-inverses the preconditioner's algebra has closed-form
+consequences that GMRES iteration counts expose exactly:
+  * the full LDU of A' = A_h with C_sm := 0 (exact X and C~_fs) gives P = A'
+    and one iteration;
+  * the block upper factor D U with the exact Schur complement leaves a unit
+    lower block-triangular A' P^{-1}: at most two iterations;
+  * a saddle point preconditioned by diag(A_f, -D A_f^{-1} G) has three
+    eigenvalues (Murphy, Golub, Wathen): at most three iterations;
+  * the paper's algorithm with exact inverses differs from A_h^{-1} by a
+    low-rank interface term: iterations <= 1 + rank(A_h P^{-1} - I).
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from conftest import system
+
+from oracle import blocks, krylov, precond
+
+
+def _bs(name):
+    return blocks.BlockSystem(system(name, seed=2))
+
+
+def _inv(A):
+    Ai = np.linalg.inv(A.toarray() if sp.issparse(A) else A)
+    return lambda r: Ai @ r
+
+
+def _iters(A, P, b, level=1e-7, gap=True, maxit=20):
+    """Iterations until the Arnoldi residual estimate drops from O(1) to the
+    rounding level of the exact inverses (kappa(blocks) * eps ~ 1e-10 here)."""
+    x, info = krylov.fgmres(lambda v: A @ v, P, b, tol=1e-30, restart=maxit, maxit=maxit)
+    hist = np.array(info.history)
+    hit = np.nonzero(hist <= level)[0]
+    assert hit.size, hist
+    k = int(hit[0])
+    if gap:  # a clear drop to the rounding level, not slow convergence
+        assert k == 0 or hist[k - 1] > 1e3 * level
+    return k + 1
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "tiny3d_unit", "tiny2d"])
+def test_full_ldu_one_iteration(name):
+    bs = _bs(name)
+    A1 = bs.dense(drop_csm=True)
+    B = {k: v.toarray() for k, v in bs.B.items()}
+    Mi, Si = np.linalg.inv(B["M"]), np.linalg.inv(B["S"])
+    Cfs_t = B["C_fs"] - B["C_fm"] @ Mi @ B["C_ms"]
+    X = B["F"] - Cfs_t @ Si @ B["C_sf"]
+    # L^{-1}: y_f = r_f - C_fm M^{-1} r_m - C~_fs S^{-1} r_s, then D^{-1}, then U^{-1}:
+    # exactly the paper's algorithm with F^{-1} -> X^{-1} and C_fs -> C~_fs.
+    P = precond.BlockLDU(bs, lambda r: Mi @ r, lambda r: Si @ r, _inv(X), cfs=lambda x: Cfs_t @ x)
+    b = np.random.default_rng(0).standard_normal(bs.N)
+    assert np.allclose(P(A1 @ b), b, rtol=1e-8, atol=1e-8 * np.abs(b).max())
+    assert _iters(A1, P, b) == 1
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "tiny3d_unit"])
+def test_upper_factor_two_iterations(name):
+    bs = _bs(name)
+    A1 = bs.dense(drop_csm=True)
+    B = {k: v.toarray() for k, v in bs.B.items()}
+    Mi, Si = np.linalg.inv(B["M"]), np.linalg.inv(B["S"])
+    Cfs_t = B["C_fs"] - B["C_fm"] @ Mi @ B["C_ms"]
+    Xi = np.linalg.inv(B["F"] - Cfs_t @ Si @ B["C_sf"])
+
+    def P(r):  # (D U)^{-1} r
+        rm, rs, rf = bs.split(r)
+        xf = Xi @ rf
+        xs = Si @ (rs - B["C_sf"] @ xf)
+        xm = Mi @ (rm - B["C_ms"] @ xs)
+        return bs.join(xm, xs, xf)
+
+    b = np.random.default_rng(1).standard_normal(bs.N)
+    assert _iters(A1, P, b) <= 2
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "tiny3d_unit", "c1"])
+def test_saddle_point_block_diagonal_three_iterations(name):
+    bs = _bs(name)
+    Af = bs.A_f.toarray()
+    G, D = bs.G.toarray(), bs.D.toarray()
+    F = bs.B["F"].toarray()
+    Afi = np.linalg.inv(Af)
+    Sp = -D @ Afi @ G
+    Spi = np.linalg.inv(Sp)
+    nvf = bs.n_vf
+
+    def P(r):
+        return np.concatenate([Afi @ r[:nvf], Spi @ r[nvf:]])
+
+    b = np.random.default_rng(2).standard_normal(F.shape[0])
+    assert _iters(F, P, b) <= 3
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "tiny3d_unit"])
+def test_paper_algorithm_exact_inverses_interface_rank_bound(name):
+    bs = _bs(name)
+    A = bs.dense()
+    B = {k: v.toarray() for k, v in bs.B.items()}
+    P = precond.BlockLDU(bs, _inv(B["M"]), _inv(B["S"]), _inv(B["F"]))
+    Pm = np.column_stack([P(e) for e in np.eye(bs.N)])
+    E = A @ Pm - np.eye(bs.N)
+    rank = np.linalg.matrix_rank(E, tol=1e-9 * np.abs(E).max())
+    assert rank < bs.N // 2  # the defect lives on interface couplings only
+    b = np.random.default_rng(3).standard_normal(bs.N)
+    assert _iters(A, P, b, gap=False, maxit=rank + 2) <= rank + 1
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "tiny3d", "c1"])
+def test_solid_schur_algorithm_is_exact_with_exact_inverses(name):
+    bs = _bs(name)
+    Sd = bs.B["S"].toarray()
+    r = np.random.default_rng(4).standard_normal(bs.n_s)
+    x = precond.solid_schur_solve(bs, _inv(bs.S_uu), _inv(bs.solid_schur()), r)
+    xe = np.linalg.solve(Sd, r)
+    assert np.linalg.norm(x - xe) <= 1e-10 * np.linalg.norm(xe)
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "c1"])
+def test_fluid_schur_algorithm_is_exact_with_exact_schur(name):
+    bs = _bs(name)
+    Af = bs.A_f.toarray()
+    Sp = -bs.D.toarray() @ np.linalg.solve(Af, bs.G.toarray())
+    r = np.random.default_rng(5).standard_normal(bs.n_f)
+    x = precond.fluid_schur_solve(bs, _inv(Af), _inv(Sp), r)
+    xe = np.linalg.solve(bs.B["F"].toarray(), r)
+    assert np.linalg.norm(x - xe) <= 1e-9 * np.linalg.norm(xe)
+
+
+def test_pressure_schur_approximation():
+    bs = _bs("c1")
+    Sp = bs.fluid_schur().toarray()
+    D, G = bs.D.toarray(), bs.G.toarray()
+    dA = bs.A_f.diagonal()
+    assert np.allclose(Sp, -D @ np.diag(1 / dA) @ G, rtol=1e-13, atol=1e-13 * np.abs(Sp).max())
+    assert np.abs(Sp - Sp.T).max() <= 1e-12 * np.abs(Sp).max()
+    np.linalg.cholesky(Sp)  # G = -D^T and diag(A_f) > 0: SPD
+    # with a diagonal A_f it is the exact Schur complement -D A_f^{-1} G
+    assert np.all(dA > 0)
+
+
+def test_mesh_inverse_per_component():
+    bs = _bs("c1")
+    L = bs.mesh_scalar()
+    Li = np.linalg.inv(L.toarray())
+    r = np.random.default_rng(6).standard_normal(bs.n_m)
+    x = precond.mesh_solve(bs, lambda v: Li @ v, r)
+    assert np.allclose(bs.B["M"] @ x, r, rtol=1e-10, atol=1e-10 * np.abs(r).max())
+
+
+def test_amg_preconditioned_solve_c1():
+    bs = _bs("c1")
+    H = precond.build_hierarchies(bs)
+    P = precond.amg_preconditioner(bs, H)
+    b = bs.sys.b
+    x, info = krylov.fgmres(bs.matvec, P, b, tol=1e-8, restart=50, maxit=300)
+    assert info.converged
+    assert np.linalg.norm(b - bs.matvec(x)) <= 1e-8 * np.linalg.norm(b)
+    # agrees with the direct solution within the conditioning of the problem
+    xd = np.linalg.solve(bs.dense(), b)
+    assert np.linalg.norm(x - xd) <= 1e-4 * np.linalg.norm(xd)
