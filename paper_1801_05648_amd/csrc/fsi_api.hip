@@ -1,0 +1,1018 @@
+// C ABI of the MI355X FSI Jacobian solver: context, validation, device
+// upload, the block-LDU preconditioner application and the FGMRES driver.
+//
+// Solve path (all on one HIP stream):
+//   FGMRES(m), right preconditioned (flexible: z_j = P^{-1} v_j stored),
+//   per iteration:
+//     z_j = P^{-1} v_j      block LDU algorithm of Section 4.1 with the AMG
+//                           sub-inverses of Sections 4.2-4.4
+//     w   = A_h z_j         one CSR pass over the monolithic A_h
+//     classical Gram-Schmidt with one reorthogonalisation (three fused passes)
+//     j+2 FP64 scalars to the host for the Givens least squares
+//   restart / acceptance on the recomputed FP64 true residual.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/fsi.h"
+#include "host_csr.hpp"
+#include "kernels.hpp"
+#include "sa_setup.hpp"
+
+namespace fsi {
+
+// ------------------------------------------------------------------ errors
+struct Error : std::runtime_error {
+  fsi_status code;
+  Error(fsi_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIP_TRY(expr)                                                                         \
+  do {                                                                                        \
+    hipError_t e_ = (expr);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      throw ::fsi::Error(e_ == hipErrorOutOfMemory ? FSI_ERR_OOM : FSI_ERR_HIP,               \
+                         std::string(#expr) + ": " + hipGetErrorString(e_));                  \
+  } while (0)
+
+// ---------------------------------------------------------- device memory
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+  void alloc(size_t b) {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = b;
+    if (b) HIP_TRY(hipMalloc(&p, b));
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+template <typename T>
+struct DCsr {
+  int64_t nrows = 0, ncols = 0, nnz = 0;
+  int group = 8;
+  std::shared_ptr<DevBuf> rp, ci, val;
+  const int64_t* drp() const { return rp->as<int64_t>(); }
+  const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
+  const T* dval() const { return val ? val->as<T>() : nullptr; }
+  double bytes() const { return double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8; }
+};
+
+int pick_group(int64_t nnz, int64_t nrows) {
+  const double avg = nrows ? double(nnz) / double(nrows) : 1.0;
+  int g = 4;
+  while (g < 64 && g * 3 < avg) g *= 2;
+  return g;
+}
+
+template <typename T>
+DCsr<T> upload(const HCsr& A, hipStream_t s) {
+  DCsr<T> D;
+  D.nrows = A.nrows;
+  D.ncols = A.ncols;
+  D.nnz = A.nnz();
+  D.group = pick_group(D.nnz, D.nrows);
+  D.rp = std::make_shared<DevBuf>();
+  D.rp->alloc(sizeof(int64_t) * (A.nrows + 1));
+  HIP_TRY(hipMemcpyAsync(D.rp->p, A.rp.data(), sizeof(int64_t) * (A.nrows + 1), hipMemcpyHostToDevice, s));
+  if (D.nnz) {
+    D.ci = std::make_shared<DevBuf>();
+    D.ci->alloc(sizeof(int32_t) * D.nnz);
+    HIP_TRY(hipMemcpyAsync(D.ci->p, A.ci.data(), sizeof(int32_t) * D.nnz, hipMemcpyHostToDevice, s));
+    D.val = std::make_shared<DevBuf>();
+    D.val->alloc(sizeof(T) * D.nnz);
+    if (sizeof(T) == sizeof(double)) {
+      HIP_TRY(hipMemcpyAsync(D.val->p, A.v.data(), sizeof(double) * D.nnz, hipMemcpyHostToDevice, s));
+    } else {
+      std::vector<T> tmp(A.v.begin(), A.v.end());
+      HIP_TRY(hipMemcpyAsync(D.val->p, tmp.data(), sizeof(T) * D.nnz, hipMemcpyHostToDevice, s));
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+  }
+  return D;
+}
+
+template <typename T>
+std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) {
+  auto b = std::make_shared<DevBuf>();
+  b->alloc(sizeof(T) * v.size());
+  if (v.empty()) return b;
+  if (sizeof(T) == sizeof(double)) {
+    HIP_TRY(hipMemcpyAsync(b->p, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, s));
+  } else {
+    std::vector<T> tmp(v.begin(), v.end());
+    HIP_TRY(hipMemcpyAsync(b->p, tmp.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return b;
+}
+
+inline unsigned grid_for(int64_t n, int per_block) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return unsigned(std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 30)));
+}
+
+// Launch a row-grouped CSR product with epilogue.
+template <typename T, int NV, class Gather, class Epi>
+void launch_rows(const DCsr<T>& A, Gather g, Epi e, hipStream_t s) {
+  if (A.nrows == 0) return;
+  const int G = A.group;
+  const unsigned grid = grid_for(A.nrows, kBlock / G);
+  switch (G) {
+    case 4: csr_rows_kernel<T, 4, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
+    case 8: csr_rows_kernel<T, 8, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
+    case 16: csr_rows_kernel<T, 16, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
+    case 32: csr_rows_kernel<T, 32, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
+    default: csr_rows_kernel<T, 64, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
+  }
+}
+
+template <typename T, int NV = 1>
+void spmv(const DCsr<T>& A, const T* x, T* y, hipStream_t s) {
+  launch_rows<T, NV>(A, GatherPlain<T, NV>{x}, EpiStore<T, NV>{y}, s);
+}
+template <typename T, int NV = 1>
+void spmv_sub(const DCsr<T>& A, const T* x, const T* r, T* y, hipStream_t s) {
+  launch_rows<T, NV>(A, GatherPlain<T, NV>{x}, EpiSub<T, NV>{r, y}, s);
+}
+
+template <typename T>
+void vsub(int64_t n, T* y, const T* x, hipStream_t s) {
+  if (n) vsub_kernel<T><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, y, x);
+}
+
+// ---------------------------------------------------------------- AMG on device
+template <typename T>
+struct DLevel {
+  DCsr<T> A, P, R;
+  std::shared_ptr<DevBuf> dinv, x, y, r, b;
+  T omega = T(0);
+  int64_t n = 0;
+};
+
+template <typename T>
+struct DHier {
+  int nv = 1;  // interleaved right-hand sides (d for the mesh Laplacian)
+  std::vector<DLevel<T>> lev;
+  std::shared_ptr<DevBuf> cinv;
+  int64_t nc = 0;
+  double bytes_per_cycle = 0.0;
+};
+
+template <typename T>
+DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s) {
+  DHier<T> D;
+  D.nv = nv;
+  const int L = int(H.levels.size()) - 1;
+  for (int l = 0; l <= L; ++l) {
+    const SaLevel& h = H.levels[l];
+    DLevel<T> d;
+    d.n = h.A.nrows;
+    d.omega = T(h.omega);
+    if (l < L) {
+      d.A = upload<T>(h.A, s);
+      d.P = upload<T>(h.P, s);
+      d.R = upload<T>(h.R, s);
+      d.dinv = upload_vec<T>(h.dinv, s);
+      D.bytes_per_cycle += 2 * d.A.bytes() + d.P.bytes() + d.R.bytes() + double(d.n) * sizeof(T) * (1 + 6 * nv);
+    }
+    auto mk = [&](int64_t cnt) {
+      auto b = std::make_shared<DevBuf>();
+      b->alloc(sizeof(T) * std::max<int64_t>(cnt, 1));
+      return b;
+    };
+    d.x = mk(d.n * nv);
+    d.y = mk(d.n * nv);
+    d.r = mk(d.n * nv);
+    d.b = mk(d.n * nv);
+    D.lev.push_back(std::move(d));
+  }
+  D.nc = H.levels.back().A.nrows;
+  D.cinv = upload_vec<double>(H.coarse_inv, s);
+  D.bytes_per_cycle += double(D.nc) * D.nc * 8;
+  return D;
+}
+
+template <typename T, int NV>
+void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s) {
+  const int L = int(H.lev.size()) - 1;
+  if (l == L) {
+    const int64_t n = H.nc;
+    dense_gemv_kernel<T, T, NV><<<grid_for(n, kBlock / 64), kBlock, 0, s>>>(n, H.cinv->template as<double>(), b, out);
+    return;
+  }
+  DLevel<T>& d = H.lev[l];
+  DLevel<T>& c = H.lev[l + 1];
+  const T* dinv = d.dinv->template as<T>();
+  T* x = d.x->template as<T>();
+  T* r = d.r->template as<T>();
+  launch_rows<T, NV>(d.A, GatherJacobi0<T, NV>{b, dinv, d.omega}, EpiJacobi0<T, NV>{b, dinv, d.omega, x, r}, s);
+  spmv<T, NV>(d.R, r, c.b->template as<T>(), s);
+  vcycle_rec<T, NV>(H, l + 1, c.b->template as<T>(), c.y->template as<T>(), s);
+  launch_rows<T, NV>(d.P, GatherPlain<T, NV>{c.y->template as<T>()}, EpiAcc<T, NV>{x}, s);
+  launch_rows<T, NV>(d.A, GatherPlain<T, NV>{x}, EpiJacobiPost<T, NV>{b, x, dinv, d.omega, out}, s);
+}
+
+template <typename T>
+void vcycle(DHier<T>& H, const T* b, T* out, hipStream_t s) {
+  switch (H.nv) {
+    case 1: vcycle_rec<T, 1>(H, 0, b, out, s); break;
+    case 2: vcycle_rec<T, 2>(H, 0, b, out, s); break;
+    default: vcycle_rec<T, 3>(H, 0, b, out, s); break;
+  }
+}
+
+// ------------------------------------------------------ block preconditioner
+template <typename T>
+struct Precond {
+  int d = 2;
+  int64_t n_m = 0, n_s = 0, n_f = 0, n_vs = 0, n_vf = 0, n_p = 0, N = 0;
+  DHier<T> H[FSI_NHIER];
+  DCsr<T> S_vu, S_uv, Cfms, Csf, Cms, Dm, Gm;
+  std::shared_ptr<DevBuf> tu, tu2, tv, tf, ta, ta2, tp, ts, ts2, tm, tm2, rT, zT;
+
+  void alloc_tmp() {
+    auto mk = [](int64_t n) {
+      auto b = std::make_shared<DevBuf>();
+      b->alloc(sizeof(T) * std::max<int64_t>(n, 1));
+      return b;
+    };
+    tu = mk(n_vs); tu2 = mk(n_vs); tv = mk(n_vs);
+    tf = mk(n_f); ta = mk(n_vf); ta2 = mk(n_vf); tp = mk(n_p);
+    ts = mk(n_s); ts2 = mk(n_s); tm = mk(n_m); tm2 = mk(n_m);
+    if (sizeof(T) != sizeof(double)) { rT = mk(N); zT = mk(N); }
+  }
+
+  // Solid algorithm of Section 4.3 (u_s eliminated through Sigma_s):
+  //   y = M_s^{-1} r_u;  x_v = Sigma_s^{-1} (r_v - S_vu y);  x_u = M_s^{-1} (r_u - S_uv x_v)
+  void solid(const T* r_s, T* z_s, hipStream_t s) {
+    const T* r_v = r_s;
+    const T* r_u = r_s + n_vs;
+    T* z_v = z_s;
+    T* z_u = z_s + n_vs;
+    vcycle(H[FSI_H_MS], r_u, tu->as<T>(), s);
+    spmv_sub<T>(S_vu, tu->as<T>(), r_v, tv->as<T>(), s);
+    vcycle(H[FSI_H_SIG], tv->as<T>(), z_v, s);
+    spmv_sub<T>(S_uv, z_v, r_u, tu2->as<T>(), s);
+    vcycle(H[FSI_H_MS], tu2->as<T>(), z_u, s);
+  }
+
+  // Uzawa-like elimination of the fluid saddle point (Section 4.4):
+  //   y = A_f^{-1} r_v;  x_p = S_p^{-1} (r_p - D y);  x_v = A_f^{-1} (r_v - G x_p)
+  void fluid(const T* r_f, T* z_f, hipStream_t s) {
+    const T* r_v = r_f;
+    const T* r_p = r_f + n_vf;
+    vcycle(H[FSI_H_A], r_v, ta->as<T>(), s);
+    spmv_sub<T>(Dm, ta->as<T>(), r_p, tp->as<T>(), s);
+    vcycle(H[FSI_H_P], tp->as<T>(), z_f + n_vf, s);
+    spmv_sub<T>(Gm, z_f + n_vf, r_v, ta2->as<T>(), s);
+    vcycle(H[FSI_H_A], ta2->as<T>(), z_f, s);
+  }
+
+  // Block LDU algorithm of Section 4.1 ("Evaluation of P^{-1} r").
+  void apply(const T* r, T* z, hipStream_t s) {
+    const T* r_m = r;
+    const T* r_s = r + n_m;
+    const T* r_f = r + n_m + n_s;
+    T* z_m = z;
+    T* z_s = z + n_m;
+    T* z_f = z + n_m + n_s;
+    vcycle(H[FSI_H_M], r_m, z_m, s);                         // 1. x_m = M^{-1} r_m
+    solid(r_s, z_s, s);                                      // 2. x_s = S^{-1} r_s
+    spmv_sub<T>(Cfms, z, r_f, tf->as<T>(), s);               // 3. r_f - C_fm x_m - C_fs x_s
+    fluid(tf->as<T>(), z_f, s);                              //    x_f = F^{-1} (...)
+    spmv<T>(Csf, z_f, ts->as<T>(), s);                       // 4. x_s -= S^{-1} C_sf x_f
+    solid(ts->as<T>(), ts2->as<T>(), s);
+    vsub<T>(n_s, z_s, ts2->as<T>(), s);
+    spmv<T>(Cms, z_s, tm->as<T>(), s);                       // 5. x_m -= M^{-1} C_ms x_s
+    vcycle(H[FSI_H_M], tm->as<T>(), tm2->as<T>(), s);
+    vsub<T>(n_m, z_m, tm2->as<T>(), s);
+  }
+};
+
+}  // namespace fsi
+
+using namespace fsi;
+
+// ------------------------------------------------------------------ context
+struct fsi_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string err;
+  // system
+  bool have_system = false, have_precond = false;
+  int d = 2;
+  int64_t n_m = 0, n_s = 0, n_f = 0, n_vs = 0, n_vf = 0, n_p = 0, N = 0;
+  double dt_theta = 0.0;
+  std::vector<double> coords;
+  std::vector<int32_t> dof_node;
+  HCsr blk[FSI_NBLK];
+  DCsr<double> Ah;
+  // preconditioner
+  int precision = FSI_P_F64;
+  SaHierarchy host_h[FSI_NHIER];
+  std::unique_ptr<Precond<double>> p64;
+  std::unique_ptr<Precond<float>> p32;
+  // Krylov workspace
+  int m_alloc = -1;
+  DevBuf V, Z, part, dh, dy, flag;
+  double* hpin = nullptr;
+  ~fsi_ctx() {
+    if (hpin) (void)hipHostFree(hpin);
+  }
+};
+
+namespace {
+
+thread_local std::string g_create_err;
+
+fsi_status set_err(fsi_ctx* c, fsi_status code, const std::string& m) {
+  if (c) c->err = m;
+  return code;
+}
+
+template <class F>
+fsi_status guarded(fsi_ctx* c, F&& f) {
+  if (!c) return FSI_ERR_ARG;
+  try {
+    HIP_TRY(hipSetDevice(c->device));
+    fsi_status st = f();
+    if (st >= 0) c->err.clear();
+    return st;
+  } catch (const Error& e) {
+    return set_err(c, e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_err(c, FSI_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(c, FSI_ERR_HIP, e.what());
+  }
+}
+
+void check_device_ptr(const void* p, const char* what) {
+  if (!p) throw Error(FSI_ERR_ARG, std::string(what) + " is NULL");
+  hipPointerAttribute_t at;
+  if (hipPointerGetAttributes(&at, p) != hipSuccess || at.type != hipMemoryTypeDevice) {
+    (void)hipGetLastError();
+    throw Error(FSI_ERR_ARG, std::string(what) + " is not a device pointer");
+  }
+}
+
+// Rigid-body modes of the solid velocity nodes, centred at their centroid:
+// d translations, then rotations (2D: (-y, x); 3D: about x, y, z).
+std::vector<double> rigid_modes(const fsi_ctx& c, int& k) {
+  const int d = c.d;
+  const int64_t nn = c.n_vs / d;
+  std::vector<double> xyz(nn * d), cen(d, 0.0);
+  for (int64_t i = 0; i < nn; ++i) {
+    const int32_t node = c.dof_node[c.n_m + i * d];
+    for (int a = 0; a < d; ++a) xyz[i * d + a] = c.coords[int64_t(node) * d + a];
+  }
+  for (int64_t i = 0; i < nn; ++i)
+    for (int a = 0; a < d; ++a) cen[a] += xyz[i * d + a];
+  for (int a = 0; a < d; ++a) cen[a] /= double(nn);
+  k = d == 2 ? 3 : 6;
+  std::vector<double> B(size_t(c.n_vs) * k, 0.0);
+  for (int64_t i = 0; i < nn; ++i) {
+    const double x = xyz[i * d] - cen[0], y = xyz[i * d + 1] - cen[1];
+    const double z = d == 3 ? xyz[i * d + 2] - cen[2] : 0.0;
+    auto at = [&](int comp, int col) -> double& { return B[size_t(i * d + comp) * k + col]; };
+    for (int t = 0; t < d; ++t) at(t, t) = 1.0;
+    if (d == 2) {
+      at(0, 2) = -y;
+      at(1, 2) = x;
+    } else {
+      at(1, 3) = -z; at(2, 3) = y;
+      at(0, 4) = z;  at(2, 4) = -x;
+      at(0, 5) = -y; at(1, 5) = x;
+    }
+  }
+  return B;
+}
+
+template <typename T>
+std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
+  auto P = std::make_unique<Precond<T>>();
+  hipStream_t s = c.stream;
+  P->d = c.d;
+  P->n_m = c.n_m; P->n_s = c.n_s; P->n_f = c.n_f; P->n_vs = c.n_vs; P->n_vf = c.n_vf;
+  P->n_p = c.n_p; P->N = c.N;
+  for (int h = 0; h < FSI_NHIER; ++h)
+    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s);
+  const HCsr& S = c.blk[FSI_S];
+  const HCsr& F = c.blk[FSI_F];
+  P->S_vu = upload<T>(sub_block(S, 0, c.n_vs, c.n_vs, c.n_s), s);
+  P->S_uv = upload<T>(sub_block(S, c.n_vs, c.n_s, 0, c.n_vs), s);
+  P->Dm = upload<T>(sub_block(F, c.n_vf, c.n_f, 0, c.n_vf), s);
+  P->Gm = upload<T>(sub_block(F, 0, c.n_vf, c.n_vf, c.n_f), s);
+  P->Csf = upload<T>(c.blk[FSI_CSF], s);
+  P->Cms = upload<T>(c.blk[FSI_CMS], s);
+  // C_fm and C_fs merged into one product over the contiguous [x_m | x_s]
+  {
+    const HCsr& A = c.blk[FSI_CFM];
+    const HCsr& B = c.blk[FSI_CFS];
+    HCsr M;
+    M.nrows = c.n_f;
+    M.ncols = c.n_m + c.n_s;
+    M.rp.assign(c.n_f + 1, 0);
+    for (int64_t i = 0; i < c.n_f; ++i) {
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) { M.ci.push_back(A.ci[k]); M.v.push_back(A.v[k]); }
+      for (int64_t k = B.rp[i]; k < B.rp[i + 1]; ++k) {
+        M.ci.push_back(int32_t(B.ci[k] + c.n_m));
+        M.v.push_back(B.v[k]);
+      }
+      M.rp[i + 1] = int64_t(M.ci.size());
+    }
+    P->Cfms = upload<T>(M, s);
+  }
+  P->alloc_tmp();
+  HIP_TRY(hipStreamSynchronize(s));
+  return P;
+}
+
+void apply_precond(fsi_ctx& c, const double* r, double* z) {
+  hipStream_t s = c.stream;
+  if (c.precision == FSI_P_F64) {
+    c.p64->apply(r, z, s);
+  } else {
+    Precond<float>& P = *c.p32;
+    cast_kernel<double, float><<<grid_for(c.N, kBlock * 4), kBlock, 0, s>>>(c.N, r, P.rT->as<float>());
+    P.apply(P.rT->as<float>(), P.zT->as<float>(), s);
+    cast_kernel<float, double><<<grid_for(c.N, kBlock * 4), kBlock, 0, s>>>(c.N, P.zT->as<float>(), z);
+  }
+}
+
+template <typename T>
+DHier<T>& hier_of(fsi_ctx& c, int which) {
+  if constexpr (sizeof(T) == sizeof(double)) return c.p64->H[which];
+  else return c.p32->H[which];
+}
+
+void ensure_krylov(fsi_ctx& c, int m) {
+  if (c.m_alloc == m) return;
+  c.V.alloc(sizeof(double) * size_t(m + 1) * c.N);
+  c.Z.alloc(sizeof(double) * size_t(m) * c.N);
+  c.part.alloc(sizeof(double) * size_t(kGsBlocks) * (m + 2));
+  c.dh.alloc(sizeof(double) * 3 * size_t(m + 2));
+  c.dy.alloc(sizeof(double) * size_t(m + 1));
+  c.flag.alloc(sizeof(int));
+  if (!c.hpin) HIP_TRY(hipHostMalloc((void**)&c.hpin, sizeof(double) * 3 * (kMaxBasis + 2)));
+  c.m_alloc = m;
+}
+
+// Deterministic dot / norm passes: pass(mode, nv, w, h) -> out[0..nv]
+void gs_pass(fsi_ctx& c, int mode, int nv, double* w, const double* h, double* out) {
+  hipStream_t s = c.stream;
+  gs_pass_kernel<<<kGsBlocks, kBlock, 0, s>>>(c.N, nv, c.V.as<double>(), c.N, w, h, mode, c.part.as<double>());
+  gs_reduce_kernel<<<nv + 1, kBlock, 0, s>>>(kGsBlocks, nv, c.part.as<double>(), out);
+}
+
+void givens(double a, double b, double& cs, double& sn) {
+  if (b == 0.0) { cs = 1.0; sn = 0.0; return; }
+  if (std::fabs(b) > std::fabs(a)) {
+    const double t = a / b;
+    sn = 1.0 / std::sqrt(1.0 + t * t);
+    cs = sn * t;
+  } else {
+    const double t = b / a;
+    cs = 1.0 / std::sqrt(1.0 + t * t);
+    sn = cs * t;
+  }
+}
+
+fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_opts& o, fsi_solve_info& info) {
+  hipStream_t s = c.stream;
+  const int64_t N = c.N;
+  const int m = o.restart;
+  ensure_krylov(c, m);
+  double* V = c.V.as<double>();
+  double* Z = c.Z.as<double>();
+  double* dh = c.dh.as<double>();
+  double* hp = c.hpin;
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  HIP_TRY(hipEventRecord(e0, s));
+  auto fetch = [&](const double* src, int cnt) {
+    HIP_TRY(hipMemcpyAsync(hp, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+  };
+  // ||b|| and finiteness of b and x0
+  HIP_TRY(hipMemsetAsync(c.flag.p, 0, sizeof(int), s));
+  nonfinite_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, b, c.flag.as<int>());
+  nonfinite_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, x, c.flag.as<int>());
+  gs_pass(c, 0, 0, const_cast<double*>(b), nullptr, dh);
+  {
+    int flag = 0;
+    HIP_TRY(hipMemcpyAsync(&flag, c.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+    fetch(dh, 1);
+    if (flag) throw Error(FSI_ERR_NUMERIC, "b or the initial guess holds NaN or Inf");
+  }
+  const double bnorm = std::sqrt(hp[0]);
+  info = fsi_solve_info{};
+  if (bnorm == 0.0) {
+    HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    info.converged = 1;
+    info.true_rel_resid = 0.0;
+    return FSI_OK;
+  }
+  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  auto Hat = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
+  int iters = 0, restarts = 0;
+  bool converged = false;
+  double rel = 0.0;
+  while (true) {
+    // true residual r = b - A x into V_0
+    spmv_sub<double>(c.Ah, x, b, V, s);
+    gs_pass(c, 0, 0, V, nullptr, dh);
+    fetch(dh, 1);
+    const double beta = std::sqrt(hp[0]);
+    rel = beta / bnorm;
+    if (!std::isfinite(rel)) throw Error(FSI_ERR_NUMERIC, "non-finite residual");
+    if (rel <= o.tol) { converged = true; break; }
+    if (iters >= o.maxit) break;
+    scale_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, V, 1.0 / beta);  // V_0 = r / beta
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    int k = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = V + size_t(j) * N;
+      double* zj = Z + size_t(j) * N;
+      double* w = V + size_t(j + 1) * N;
+      apply_precond(c, vj, zj);
+      spmv<double>(c.Ah, zj, w, s);
+      // CGS2: h1 = V^T w (+ w.w); w -= V h1, h2 = V^T w; w -= V h2, |w|^2
+      double* h1 = dh;
+      double* h2 = dh + (m + 2);
+      double* h3 = dh + 2 * (m + 2);
+      gs_pass(c, 0, j + 1, w, nullptr, h1);
+      gs_pass(c, 1, j + 1, w, h1, h2);
+      gs_pass_kernel<<<kGsBlocks, kBlock, 0, s>>>(N, j + 1, V, N, w, h2, 2, c.part.as<double>());
+      gs_reduce_kernel<<<1, kBlock, 0, s>>>(kGsBlocks, j + 1, c.part.as<double>() + (j + 1), h3 + (j + 1));
+      HIP_TRY(hipMemcpyAsync(hp, dh, sizeof(double) * 3 * (m + 2), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      const double wbefore = std::sqrt(hp[j + 1]);
+      for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[(m + 2) + i];
+      const double hn = std::sqrt(std::max(hp[2 * (m + 2) + j + 1], 0.0));
+      Hat(j + 1, j) = hn;
+      const bool breakdown = !(hn > 1e-14 * wbefore);
+      if (!breakdown) scale_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, w, 1.0 / hn);
+      for (int i = 0; i < j; ++i) {
+        const double a = Hat(i, j), bb = Hat(i + 1, j);
+        Hat(i, j) = cs[i] * a + sn[i] * bb;
+        Hat(i + 1, j) = -sn[i] * a + cs[i] * bb;
+      }
+      givens(Hat(j, j), Hat(j + 1, j), cs[j], sn[j]);
+      Hat(j, j) = cs[j] * Hat(j, j) + sn[j] * Hat(j + 1, j);
+      Hat(j + 1, j) = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++iters;
+      k = j + 1;
+      if (std::fabs(g[j + 1]) / bnorm <= o.tol || breakdown || iters >= o.maxit) break;
+    }
+    for (int i = k - 1; i >= 0; --i) {
+      double sum = g[i];
+      for (int l = i + 1; l < k; ++l) sum -= Hat(i, l) * y[l];
+      if (Hat(i, i) == 0.0) throw Error(FSI_ERR_NUMERIC, "singular Hessenberg matrix");
+      y[i] = sum / Hat(i, i);
+    }
+    HIP_TRY(hipMemcpyAsync(c.dy.p, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
+    multi_axpy_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, k, Z, N, c.dy.as<double>(), x);
+    HIP_TRY(hipStreamSynchronize(s));  // y lives on the host stack frame
+    ++restarts;
+  }
+  HIP_TRY(hipEventRecord(e1, s));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0.0f;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  info.iters = iters;
+  info.restarts = restarts;
+  info.converged = converged ? 1 : 0;
+  info.true_rel_resid = rel;
+  info.t_total_ms = ms;
+  return converged ? FSI_OK : FSI_NOT_CONVERGED;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+extern "C" {
+
+void fsi_default_precond_opts(fsi_precond_opts* o) {
+  if (!o) return;
+  *o = fsi_precond_opts{};
+  o->precision = FSI_P_F64;
+  o->max_coarse = 500;
+  o->max_levels = 10;
+  o->strength0 = 0.08;
+}
+
+void fsi_default_solve_opts(fsi_solve_opts* o) {
+  if (!o) return;
+  o->tol = 1e-8;
+  o->restart = 50;
+  o->maxit = 2000;
+}
+
+fsi_status fsi_create(fsi_ctx** ctx, int device, void* hip_stream) {
+  if (!ctx) return FSI_ERR_ARG;
+  *ctx = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+    g_create_err = "no HIP device available";
+    return FSI_ERR_HIP;
+  }
+  if (device < 0 || device >= n) {
+    g_create_err = "device index out of range";
+    return FSI_ERR_ARG;
+  }
+  auto* c = new (std::nothrow) fsi_ctx();
+  if (!c) return FSI_ERR_OOM;
+  c->device = device;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  if (hipSetDevice(device) != hipSuccess) {
+    delete c;
+    g_create_err = "hipSetDevice failed";
+    return FSI_ERR_HIP;
+  }
+  *ctx = c;
+  return FSI_OK;
+}
+
+fsi_status fsi_destroy(fsi_ctx* ctx) {
+  if (!ctx) return FSI_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+  delete ctx;
+  return FSI_OK;
+}
+
+const char* fsi_last_error(const fsi_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : g_create_err.c_str();
+}
+
+fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk[FSI_NBLK], int mem) {
+  return guarded(ctx, [&]() -> fsi_status {
+    if (!L || !blk) throw Error(FSI_ERR_ARG, "layout or blocks is NULL");
+    if (mem != 0) throw Error(FSI_ERR_ARG, "only host CSR input (mem = 0) is supported");
+    const int d = L->dim;
+    if (d != 2 && d != 3) throw Error(FSI_ERR_ARG, "dim must be 2 or 3");
+    if (L->n_m < 0 || L->n_s <= 0 || L->n_f <= 0 || L->n_vs <= 0 || L->n_vf <= 0)
+      throw Error(FSI_ERR_ARG, "block sizes must be positive");
+    if (L->n_s != 2 * L->n_vs) throw Error(FSI_ERR_ARG, "n_s must equal 2 n_vs");
+    if (L->n_vf >= L->n_f) throw Error(FSI_ERR_ARG, "n_vf must be smaller than n_f");
+    if (L->n_m % d || L->n_vs % d || L->n_vf % d) throw Error(FSI_ERR_ARG, "vector blocks must be multiples of dim");
+    if (!(L->dt_theta > 0.0)) throw Error(FSI_ERR_ARG, "dt_theta must be positive");
+    const int64_t N = L->n_m + L->n_s + L->n_f;
+    if (N >= (int64_t(1) << 31)) throw Error(FSI_ERR_ARG, "N must be below 2^31");
+    if (!L->coords || !L->dof_node || L->n_nodes <= 0) throw Error(FSI_ERR_ARG, "coords and dof_node are required");
+    const int64_t sz[3] = {L->n_m, L->n_s, L->n_f};
+    const int bi[FSI_NBLK] = {0, 0, 1, 1, 1, 2, 2, 2};
+    const int bj[FSI_NBLK] = {0, 1, 0, 1, 2, 0, 1, 2};
+    static const char* names[FSI_NBLK] = {"M", "C_ms", "C_sm", "S", "C_sf", "C_fm", "C_fs", "F"};
+    for (int b = 0; b < FSI_NBLK; ++b) {
+      const fsi_csr& A = blk[b];
+      if (A.nrows != sz[bi[b]] || A.ncols != sz[bj[b]])
+        throw Error(FSI_ERR_ARG, std::string("block ") + names[b] + " has the wrong shape");
+      std::string m = csr_check(A.nrows, A.ncols, A.nnz, A.rowptr, A.col, A.val);
+      if (!m.empty()) throw Error(FSI_ERR_CSR, std::string("block ") + names[b] + ": " + m);
+    }
+    for (int64_t i = 0; i < N; ++i)
+      if (L->dof_node[i] < 0 || L->dof_node[i] >= L->n_nodes) throw Error(FSI_ERR_ARG, "dof_node out of range");
+    // host copies (the context is only modified once everything validated)
+    HCsr H[FSI_NBLK];
+    for (int b = 0; b < FSI_NBLK; ++b) H[b] = csr_copy(blk[b].nrows, blk[b].ncols, blk[b].rowptr, blk[b].col, blk[b].val);
+    // structural identities
+    const int64_t nvs = L->n_vs, nvf = L->n_vf;
+    {
+      HCsr Suv = sub_block(H[FSI_S], nvs, 2 * nvs, 0, nvs);
+      HCsr Suu = sub_block(H[FSI_S], nvs, 2 * nvs, nvs, 2 * nvs);
+      double mx = 0.0;
+      for (double v : Suu.v) mx = std::max(mx, std::fabs(v));
+      HCsr diff = add(Suv, Suu, L->dt_theta);
+      double dmax = 0.0;
+      for (double v : diff.v) dmax = std::max(dmax, std::fabs(v));
+      if (!(dmax <= 1e-12 * L->dt_theta * mx))
+        throw Error(FSI_ERR_STRUCT, "S_uv != -dt_theta S_uu (equal-order solid mass identity)");
+      HCsr Fpp = sub_block(H[FSI_F], nvf, L->n_f, nvf, L->n_f);
+      if (Fpp.nnz() != 0) throw Error(FSI_ERR_STRUCT, "pressure-pressure block of F must be empty");
+      // M = L (x) I_d
+      const HCsr& M = H[FSI_M];
+      for (int64_t i = 0; i < M.nrows; ++i) {
+        const int64_t I = i / d, ci = i % d;
+        const int64_t r0 = I * d;
+        if (M.rp[i + 1] - M.rp[i] != M.rp[r0 + 1] - M.rp[r0])
+          throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
+        for (int64_t k = M.rp[i], k0 = M.rp[r0]; k < M.rp[i + 1]; ++k, ++k0) {
+          if (M.ci[k] % d != ci || M.ci[k] / d != M.ci[k0] / d || M.v[k] != M.v[k0])
+            throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
+        }
+      }
+    }
+    // monolithic A_h with global columns for the outer product
+    HCsr Ah;
+    Ah.nrows = Ah.ncols = N;
+    Ah.rp.assign(N + 1, 0);
+    {
+      const int64_t off[3] = {0, L->n_m, L->n_m + L->n_s};
+      int64_t total = 0;
+      for (int b = 0; b < FSI_NBLK; ++b) total += H[b].nnz();
+      Ah.ci.reserve(total);
+      Ah.v.reserve(total);
+      for (int r = 0; r < 3; ++r) {
+        for (int64_t i = 0; i < sz[r]; ++i) {
+          for (int b = 0; b < FSI_NBLK; ++b) {
+            if (bi[b] != r) continue;
+            const HCsr& A = H[b];
+            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+              Ah.ci.push_back(int32_t(A.ci[k] + off[bj[b]]));
+              Ah.v.push_back(A.v[k]);
+            }
+          }
+          Ah.rp[off[r] + i + 1] = int64_t(Ah.ci.size());
+        }
+      }
+    }
+    DCsr<double> dAh = upload<double>(Ah, ctx->stream);
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    // commit
+    fsi_ctx& c = *ctx;
+    c.d = d;
+    c.n_m = L->n_m; c.n_s = L->n_s; c.n_f = L->n_f; c.n_vs = nvs; c.n_vf = nvf;
+    c.n_p = L->n_f - nvf; c.N = N;
+    c.dt_theta = L->dt_theta;
+    c.coords.assign(L->coords, L->coords + L->n_nodes * d);
+    c.dof_node.assign(L->dof_node, L->dof_node + N);
+    for (int b = 0; b < FSI_NBLK; ++b) c.blk[b] = std::move(H[b]);
+    c.Ah = dAh;
+    c.have_system = true;
+    c.have_precond = false;
+    c.p64.reset();
+    c.p32.reset();
+    c.m_alloc = -1;
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
+    fsi_precond_opts o;
+    fsi_default_precond_opts(&o);
+    if (opts) o = *opts;
+    if (o.precision != FSI_P_F64 && o.precision != FSI_P_F32) throw Error(FSI_ERR_ARG, "unknown precision");
+    if (o.max_coarse < 1 || o.max_levels < 1 || o.max_levels > 16 || !(o.strength0 >= 0.0))
+      throw Error(FSI_ERR_ARG, "bad AMG options");
+    SaParams prm;
+    prm.eps0 = o.strength0;
+    prm.max_coarse = o.max_coarse;
+    prm.max_levels = o.max_levels;
+    const int d = c.d;
+    const HCsr& S = c.blk[FSI_S];
+    const HCsr& F = c.blk[FSI_F];
+    // operators of the five hierarchies
+    HCsr Lm;  // scalar L of M = L (x) I_d
+    {
+      const HCsr& M = c.blk[FSI_M];
+      Lm.nrows = Lm.ncols = M.nrows / d;
+      Lm.rp.assign(Lm.nrows + 1, 0);
+      for (int64_t I = 0; I < Lm.nrows; ++I) {
+        const int64_t i = I * d;
+        for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) {
+          Lm.ci.push_back(M.ci[k] / d);
+          Lm.v.push_back(M.v[k]);
+        }
+        Lm.rp[I + 1] = int64_t(Lm.ci.size());
+      }
+    }
+    HCsr Svv = sub_block(S, 0, c.n_vs, 0, c.n_vs);
+    HCsr Svu = sub_block(S, 0, c.n_vs, c.n_vs, c.n_s);
+    HCsr Sig = add(Svv, Svu, c.dt_theta);            // Sigma_s = S_vv + dt theta S_vu
+    HCsr Suu = sub_block(S, c.n_vs, c.n_s, c.n_vs, c.n_s);
+    HCsr Af = sub_block(F, 0, c.n_vf, 0, c.n_vf);
+    HCsr Dm = sub_block(F, c.n_vf, c.n_f, 0, c.n_vf);
+    HCsr Gm = sub_block(F, 0, c.n_vf, c.n_vf, c.n_f);
+    HCsr Sp;  // -D diag(A_f)^{-1} G
+    {
+      std::vector<double> dA = diagonal(Af);
+      std::vector<double> dinv(dA.size());
+      for (size_t i = 0; i < dA.size(); ++i) {
+        if (dA[i] == 0.0) throw Error(FSI_ERR_NUMERIC, "zero diagonal in the fluid velocity block");
+        dinv[i] = 1.0 / dA[i];
+      }
+      HCsr Ds = Dm;
+      scale_cols(Ds, dinv);
+      Sp = spgemm(Ds, Gm);
+      for (double& v : Sp.v) v = -v;
+      drop_zeros(Sp);
+    }
+    int krig = 0;
+    std::vector<double> Brig = rigid_modes(c, krig);
+    std::vector<double> Bt(size_t(c.n_vf) * d, 0.0);
+    for (int64_t i = 0; i < c.n_vf; ++i) Bt[size_t(i) * d + (i % d)] = 1.0;
+    const HCsr* ops[FSI_NHIER] = {&Lm, &Sig, &Suu, &Af, &Sp};
+    const int blocks[FSI_NHIER] = {1, d, 1, d, 1};
+    const std::vector<double> ones_m(Lm.nrows, 1.0), ones_s(c.n_vs, 1.0), ones_p(c.n_p, 1.0);
+    const std::vector<double>* Bs[FSI_NHIER] = {&ones_m, &Brig, &ones_s, &Bt, &ones_p};
+    const int ks[FSI_NHIER] = {1, krig, 1, d, 1};
+    static const char* hn[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
+    SaHierarchy hh[FSI_NHIER];
+    for (int h = 0; h < FSI_NHIER; ++h) {
+      std::string m = sa_setup(*ops[h], blocks[h], *Bs[h], ks[h], prm, hh[h]);
+      if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
+    }
+    for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
+    c.precision = o.precision;
+    c.p64.reset();
+    c.p32.reset();
+    if (o.precision == FSI_P_F64) c.p64 = make_precond<double>(c);
+    else c.p32 = make_precond<float>(c);
+    c.have_precond = true;
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_solve(fsi_ctx* ctx, const double* b, double* x, const fsi_solve_opts* opts, fsi_solve_info* info) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    fsi_solve_opts o;
+    fsi_default_solve_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.tol > 0.0) || o.restart < 1 || o.restart > kMaxBasis - 8 || o.maxit < 0)
+      throw Error(FSI_ERR_ARG, "bad solve options");
+    check_device_ptr(b, "b");
+    check_device_ptr(x, "x");
+    if (b == x) throw Error(FSI_ERR_ARG, "b and x must not alias");
+    fsi_solve_info local;
+    fsi_status st = solve_impl(c, b, x, o, local);
+    if (info) *info = local;
+    return st;
+  });
+}
+
+fsi_status fsi_spmv(fsi_ctx* ctx, const double* x, double* y) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
+    check_device_ptr(x, "x");
+    check_device_ptr(y, "y");
+    if (x == y) throw Error(FSI_ERR_ARG, "x and y must not alias");
+    spmv<double>(c.Ah, x, y, c.stream);
+    HIP_TRY(hipGetLastError());
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_apply_precond(fsi_ctx* ctx, const double* r, double* z) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    check_device_ptr(r, "r");
+    check_device_ptr(z, "z");
+    if (r == z) throw Error(FSI_ERR_ARG, "r and z must not alias");
+    apply_precond(c, r, z);
+    HIP_TRY(hipGetLastError());
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_vcycle(fsi_ctx* ctx, int which, const double* b, double* x) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (which < 0 || which >= FSI_NHIER) throw Error(FSI_ERR_ARG, "unknown hierarchy");
+    check_device_ptr(b, "b");
+    check_device_ptr(x, "x");
+    if (b == x) throw Error(FSI_ERR_ARG, "b and x must not alias");
+    hipStream_t s = c.stream;
+    if (c.precision == FSI_P_F64) {
+      vcycle(c.p64->H[which], b, x, s);
+    } else {
+      DHier<float>& H = c.p32->H[which];
+      const int64_t n = H.lev[0].n * H.nv;
+      Precond<float>& P = *c.p32;
+      cast_kernel<double, float><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, b, P.rT->as<float>());
+      vcycle(H, P.rT->as<float>(), P.zT->as<float>(), s);
+      cast_kernel<float, double><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, P.zT->as<float>(), x);
+    }
+    HIP_TRY(hipGetLastError());
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A, const fsi_csr* P,
+                             const fsi_csr* R, const double* omega) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (which < 0 || which >= FSI_NHIER || nlev < 1 || nlev > 16 || !A) throw Error(FSI_ERR_ARG, "bad arguments");
+    if (nlev > 1 && (!P || !R || !omega)) throw Error(FSI_ERR_ARG, "P, R and omega are required");
+    SaHierarchy H;
+    const int64_t n0 = c.host_h[which].levels[0].A.nrows;
+    for (int l = 0; l < nlev; ++l) {
+      std::string m = csr_check(A[l].nrows, A[l].ncols, A[l].nnz, A[l].rowptr, A[l].col, A[l].val);
+      if (!m.empty()) throw Error(FSI_ERR_CSR, "level matrix: " + m);
+      if (A[l].nrows != A[l].ncols) throw Error(FSI_ERR_ARG, "level matrices must be square");
+      if (l == 0 && A[l].nrows != n0) throw Error(FSI_ERR_ARG, "finest level size mismatch");
+      SaLevel L;
+      L.A = csr_copy(A[l].nrows, A[l].ncols, A[l].rowptr, A[l].col, A[l].val);
+      if (l < nlev - 1) {
+        m = csr_check(P[l].nrows, P[l].ncols, P[l].nnz, P[l].rowptr, P[l].col, P[l].val);
+        if (!m.empty()) throw Error(FSI_ERR_CSR, "prolongator: " + m);
+        m = csr_check(R[l].nrows, R[l].ncols, R[l].nnz, R[l].rowptr, R[l].col, R[l].val);
+        if (!m.empty()) throw Error(FSI_ERR_CSR, "restriction: " + m);
+        if (P[l].nrows != A[l].nrows || P[l].ncols != A[l + 1].nrows || R[l].nrows != A[l + 1].nrows ||
+            R[l].ncols != A[l].nrows)
+          throw Error(FSI_ERR_ARG, "prolongator/restriction shapes do not chain");
+        if (!std::isfinite(omega[l])) throw Error(FSI_ERR_ARG, "non-finite omega");
+        L.P = csr_copy(P[l].nrows, P[l].ncols, P[l].rowptr, P[l].col, P[l].val);
+        L.R = csr_copy(R[l].nrows, R[l].ncols, R[l].rowptr, R[l].col, R[l].val);
+        L.omega = omega[l];
+      }
+      H.levels.push_back(std::move(L));
+    }
+    std::string m = sa_finalize(H);
+    if (!m.empty()) throw Error(FSI_ERR_NUMERIC, m);
+    const int nv = which == FSI_H_M ? c.d : 1;
+    if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream);
+    else c.p32->H[which] = upload_hier<float>(H, nv, c.stream);
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    c.host_h[which] = std::move(H);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_hierarchy_info(fsi_ctx* ctx, int which, int32_t* nlev, int64_t* n, int64_t* nnz, double* omega) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (which < 0 || which >= FSI_NHIER || !nlev) throw Error(FSI_ERR_ARG, "bad arguments");
+    const SaHierarchy& H = c.host_h[which];
+    *nlev = int32_t(H.levels.size());
+    for (size_t l = 0; l < H.levels.size() && l < 16; ++l) {
+      if (n) n[l] = H.levels[l].A.nrows;
+      if (nnz) nnz[l] = H.levels[l].A.nnz();
+      if (omega) omega[l] = H.levels[l].omega;
+    }
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_get_level(fsi_ctx* ctx, int which, int level, int what, int64_t* nrows, int64_t* ncols, int64_t* nnz,
+                         int64_t* rowptr, int32_t* col, double* val) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (which < 0 || which >= FSI_NHIER) throw Error(FSI_ERR_ARG, "unknown hierarchy");
+    const SaHierarchy& H = c.host_h[which];
+    if (level < 0 || level >= int(H.levels.size())) throw Error(FSI_ERR_ARG, "level out of range");
+    if (what == 1 && level == int(H.levels.size()) - 1) throw Error(FSI_ERR_ARG, "the coarsest level has no prolongator");
+    if (what != 0 && what != 1) throw Error(FSI_ERR_ARG, "what must be 0 (A) or 1 (P)");
+    const HCsr& A = what == 0 ? H.levels[level].A : H.levels[level].P;
+    if (nrows) *nrows = A.nrows;
+    if (ncols) *ncols = A.ncols;
+    if (nnz) *nnz = A.nnz();
+    if (rowptr) std::memcpy(rowptr, A.rp.data(), sizeof(int64_t) * (A.nrows + 1));
+    if (col) std::memcpy(col, A.ci.data(), sizeof(int32_t) * A.nnz());
+    if (val) std::memcpy(val, A.v.data(), sizeof(double) * A.nnz());
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_get_aggregates(fsi_ctx* ctx, int which, int level, int32_t* agg, int64_t* count) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (which < 0 || which >= FSI_NHIER) throw Error(FSI_ERR_ARG, "unknown hierarchy");
+    const SaHierarchy& H = c.host_h[which];
+    if (level < 0 || level >= int(H.levels.size()) - 1) throw Error(FSI_ERR_ARG, "level out of range");
+    const auto& a = H.levels[level].agg;
+    if (a.empty()) throw Error(FSI_ERR_STATE, "aggregates unknown for an imported hierarchy");
+    if (count) *count = int64_t(a.size());
+    if (agg) std::memcpy(agg, a.data(), sizeof(int32_t) * a.size());
+    return FSI_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,43 @@
+// Host-side CSR containers and the sparse kernels the preconditioner setup
+// needs (transpose, sparse products, sums, sub-blocks).  Setup only: nothing
+// here runs inside the solve.
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <string>
+#include <vector>
+
+namespace fsi {
+
+struct HCsr {
+  int64_t nrows = 0, ncols = 0;
+  std::vector<int64_t> rp{0};
+  std::vector<int32_t> ci;
+  std::vector<double> v;
+  int64_t nnz() const { return int64_t(ci.size()); }
+};
+
+// Run f(begin, end) over [0, n) on the host's hardware threads.
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
+
+// Well-formedness: row pointers, column range, strictly increasing columns,
+// finite values.  Returns an empty string when valid.
+std::string csr_check(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* rp, const int32_t* ci,
+                      const double* v);
+
+HCsr csr_copy(int64_t nrows, int64_t ncols, const int64_t* rp, const int32_t* ci, const double* v);
+HCsr transpose(const HCsr& A);
+// C = A B; entry (i, j) summed over the stored entries of row i of A in
+// storage order, each contributing A_ik * B_kj in the storage order of row k.
+HCsr spgemm(const HCsr& A, const HCsr& B);
+// C = A + alpha B (union pattern, exact zeros dropped).
+HCsr add(const HCsr& A, const HCsr& B, double alpha);
+HCsr sub_block(const HCsr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1);
+void drop_zeros(HCsr& A);
+void scale_rows(HCsr& A, const std::vector<double>& s);
+void scale_cols(HCsr& A, const std::vector<double>& s);
+std::vector<double> diagonal(const HCsr& A);
+void matvec(const HCsr& A, const double* x, double* y);
+
+}  // namespace fsi

@@ -1,0 +1,42 @@
+// Smoothed-aggregation AMG setup on the host (preconditioner build only).
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "host_csr.hpp"
+
+namespace fsi {
+
+struct SaParams {
+  double eps0 = 0.08;      // strength threshold on the finest level, halved per level
+  int max_coarse = 500;    // coarsest level size bound
+  int max_levels = 10;     // level bound (the coarsest included)
+};
+
+struct SaLevel {
+  HCsr A, P, R;
+  std::vector<double> dinv;
+  double omega = 0.0;
+  int block = 1;
+  std::vector<int32_t> agg;  // aggregate of every node (levels that are not the coarsest)
+};
+
+struct SaHierarchy {
+  std::vector<SaLevel> levels;
+  std::vector<double> coarse_inv;  // dense inverse of the coarsest matrix, row-major
+};
+
+// Build the hierarchy of A with node block size `block` and near-nullspace B
+// (row-major n x k).  Returns an empty string on success, else a message.
+std::string sa_setup(const HCsr& A, int block, const std::vector<double>& B, int k, const SaParams& prm,
+                     SaHierarchy& H);
+
+// Dense inverse (LU with partial pivoting, smallest row index on ties) of the
+// n x n row-major matrix a; returns false on a zero pivot.
+bool dense_inverse(std::vector<double> a, int64_t n, std::vector<double>& inv);
+
+// Finalise a caller-provided hierarchy (diagonal inverses, coarse inverse).
+std::string sa_finalize(SaHierarchy& H);
+
+}  // namespace fsi

@@ -1,0 +1,288 @@
+"""Python binding of libfsi (argument marshalling only).
+
+Every step of the solve runs in the HIP library behind the C ABI declared in
+``include/fsi.h``; this module converts numpy / torch arguments to plain
+pointers and sizes and turns status codes into exceptions.  PyTorch provides
+device memory and the HIP stream.  There is no fallback: if ``libfsi.so`` is
+missing the import fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfsi.so")
+
+BLOCKS = ("M", "C_ms", "C_sm", "S", "C_sf", "C_fm", "C_fs", "F")
+HIERARCHIES = {"H_M": 0, "H_SIG": 1, "H_MS": 2, "H_A": 3, "H_P": 4}
+PRECISION = {"f64": 0, "f32": 1}
+
+STATUS = {0: "FSI_OK", 1: "FSI_NOT_CONVERGED", -1: "FSI_ERR_ARG", -2: "FSI_ERR_CSR",
+          -3: "FSI_ERR_STRUCT", -4: "FSI_ERR_HIP", -5: "FSI_ERR_OOM", -6: "FSI_ERR_NUMERIC",
+          -7: "FSI_ERR_STATE"}
+
+
+class FsiError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = STATUS.get(code, str(code))
+
+
+class CCsr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rowptr", ctypes.c_void_p), ("col", ctypes.c_void_p), ("val", ctypes.c_void_p)]
+
+
+class CLayout(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n_m", ctypes.c_int64), ("n_s", ctypes.c_int64), ("n_f", ctypes.c_int64),
+                ("n_vs", ctypes.c_int64), ("n_vf", ctypes.c_int64), ("dt_theta", ctypes.c_double),
+                ("n_nodes", ctypes.c_int64), ("coords", ctypes.c_void_p), ("dof_node", ctypes.c_void_p)]
+
+
+class CPrecondOpts(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
+                ("max_levels", ctypes.c_int32), ("pad", ctypes.c_int32), ("strength0", ctypes.c_double)]
+
+
+class CSolveOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32)]
+
+
+class CSolveInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("pad", ctypes.c_int32), ("true_rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class SolveInfo:
+    status: str
+    iters: int
+    restarts: int
+    converged: bool
+    true_rel_resid: float
+    t_total_ms: float
+
+
+def _declare(lib):
+    P = ctypes.c_void_p
+    i32, i64 = ctypes.c_int, ctypes.c_int64
+    sig = {
+        "fsi_create": ([ctypes.POINTER(P), i32, P], i32),
+        "fsi_destroy": ([P], i32),
+        "fsi_last_error": ([P], ctypes.c_char_p),
+        "fsi_setup_blocks": ([P, ctypes.POINTER(CLayout), ctypes.POINTER(CCsr), i32], i32),
+        "fsi_build_precond": ([P, ctypes.POINTER(CPrecondOpts)], i32),
+        "fsi_solve": ([P, P, P, ctypes.POINTER(CSolveOpts), ctypes.POINTER(CSolveInfo)], i32),
+        "fsi_spmv": ([P, P, P], i32),
+        "fsi_apply_precond": ([P, P, P], i32),
+        "fsi_vcycle": ([P, i32, P, P], i32),
+        "fsi_set_hierarchy": ([P, i32, i32, ctypes.POINTER(CCsr), ctypes.POINTER(CCsr), ctypes.POINTER(CCsr), P], i32),
+        "fsi_hierarchy_info": ([P, i32, P, P, P, P], i32),
+        "fsi_get_level": ([P, i32, i32, i32, P, P, P, P, P, P], i32),
+        "fsi_get_aggregates": ([P, i32, i32, P, P], i32),
+        "fsi_default_precond_opts": ([ctypes.POINTER(CPrecondOpts)], None),
+        "fsi_default_solve_opts": ([ctypes.POINTER(CSolveOpts)], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    return lib
+
+
+_lib = None
+
+
+def load():
+    """Load libfsi.so (built by __graft_entry__.build()); raises if absent."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        _lib = _declare(ctypes.CDLL(LIB_PATH))
+    return _lib
+
+
+def exported_symbols():
+    """Names of the C ABI entry points this binding declares."""
+    return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_build_precond",
+            "fsi_solve", "fsi_spmv", "fsi_apply_precond", "fsi_vcycle", "fsi_set_hierarchy",
+            "fsi_hierarchy_info", "fsi_get_level", "fsi_get_aggregates", "fsi_default_precond_opts",
+            "fsi_default_solve_opts"]
+
+
+def _csr_struct(nrows, ncols, rowptr, col, val, keep):
+    rp = np.ascontiguousarray(rowptr, dtype=np.int64)
+    ci = np.ascontiguousarray(col, dtype=np.int32)
+    vv = np.ascontiguousarray(val, dtype=np.float64)
+    keep.extend([rp, ci, vv])
+    return CCsr(int(nrows), int(ncols), int(ci.shape[0]), rp.ctypes.data, ci.ctypes.data, vv.ctypes.data)
+
+
+def _dptr(t, n, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float64:
+        raise TypeError(f"{name} must be a CUDA float64 tensor")
+    if not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name} must be contiguous with {n} entries")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class FsiSolver:
+    """One linearised FSI system on one GPU.
+
+    ``blocks``: mapping of the eight block names to (nrows, ncols, rowptr, col,
+    val) host arrays or objects with those attributes; ``layout``: mapping with
+    dim, n_m, n_s, n_f, n_vs, n_vf, dt_theta, coords (n_nodes x dim) and
+    dof_node (N).
+    """
+
+    def __init__(self, blocks, layout, device: int = 0, stream=None):
+        import torch
+        self.lib = load()
+        self.torch = torch
+        self.device = device
+        if stream is None:
+            stream = torch.cuda.current_stream(device)
+        self.stream = stream
+        ctx = ctypes.c_void_p()
+        rc = self.lib.fsi_create(ctypes.byref(ctx), device, ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise FsiError(rc, self.lib.fsi_last_error(None).decode())
+        self.ctx = ctx
+        self.N = int(layout["n_m"] + layout["n_s"] + layout["n_f"])
+        self.layout = dict(layout)
+        keep = []
+        arr = (CCsr * 8)()
+        for i, name in enumerate(BLOCKS):
+            b = blocks[name]
+            if isinstance(b, tuple):
+                nr, ncl, rp, ci, vv = b
+            else:
+                nr, ncl, rp, ci, vv = b.nrows, b.ncols, b.rowptr, b.col, b.val
+            arr[i] = _csr_struct(nr, ncl, rp, ci, vv, keep)
+        coords = np.ascontiguousarray(layout["coords"], dtype=np.float64)
+        dof_node = np.ascontiguousarray(layout["dof_node"], dtype=np.int32)
+        lay = CLayout(int(layout["dim"]), 0, int(layout["n_m"]), int(layout["n_s"]), int(layout["n_f"]),
+                      int(layout["n_vs"]), int(layout["n_vf"]), float(layout["dt_theta"]),
+                      int(coords.shape[0]), coords.ctypes.data, dof_node.ctypes.data)
+        self._check(self.lib.fsi_setup_blocks(self.ctx, ctypes.byref(lay), arr, 0))
+
+    @classmethod
+    def from_system(cls, sysm, **kw):
+        layout = dict(dim=sysm.dim, n_m=sysm.n_m, n_s=sysm.n_s, n_f=sysm.n_f, n_vs=sysm.n_vs,
+                      n_vf=sysm.n_vf, dt_theta=sysm.dt_theta, coords=sysm.coords, dof_node=sysm.dof_node)
+        return cls(sysm.blocks, layout, **kw)
+
+    # -- plumbing ------------------------------------------------------------
+    def _check(self, rc):
+        if rc < 0:
+            raise FsiError(rc, self.lib.fsi_last_error(self.ctx).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.fsi_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _hier_len(self, which: int) -> int:
+        n, _, _ = self.hierarchy_info(which)
+        return int(n[0]) * (self.layout["dim"] if which == 0 else 1)
+
+    # -- calls -----------------------------------------------------------------
+    def build_precond(self, precision: str = "f64", max_coarse: int = 500, max_levels: int = 10,
+                      strength0: float = 0.08):
+        o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, 0, strength0)
+        self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
+
+    def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000):
+        torch = self.torch
+        if x is None:
+            x = torch.zeros(self.N, dtype=torch.float64, device=b.device)
+        o = CSolveOpts(tol, restart, maxit)
+        info = CSolveInfo()
+        rc = self._check(self.lib.fsi_solve(self.ctx, _dptr(b, self.N, "b"), _dptr(x, self.N, "x"),
+                                            ctypes.byref(o), ctypes.byref(info)))
+        return x, SolveInfo(STATUS[rc], info.iters, info.restarts, bool(info.converged),
+                            info.true_rel_resid, info.t_total_ms)
+
+    def spmv(self, x, y=None):
+        if y is None:
+            y = self.torch.empty_like(x)
+        self._check(self.lib.fsi_spmv(self.ctx, _dptr(x, self.N, "x"), _dptr(y, self.N, "y")))
+        return y
+
+    def apply_precond(self, r, z=None):
+        if z is None:
+            z = self.torch.empty_like(r)
+        self._check(self.lib.fsi_apply_precond(self.ctx, _dptr(r, self.N, "r"), _dptr(z, self.N, "z")))
+        return z
+
+    def vcycle(self, which, b, x=None):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        n = self._hier_len(w)
+        if x is None:
+            x = self.torch.empty_like(b)
+        self._check(self.lib.fsi_vcycle(self.ctx, w, _dptr(b, n, "b"), _dptr(x, n, "x")))
+        return x
+
+    def set_hierarchy(self, which, A, P, R, omega):
+        """A, P, R: lists of (nrows, ncols, rowptr, col, val); omega: list of floats."""
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        keep = []
+        nl = len(A)
+        Aa = (CCsr * nl)(*[_csr_struct(*a, keep) for a in A])
+        Pa = (CCsr * max(nl - 1, 1))(*[_csr_struct(*p, keep) for p in P])
+        Ra = (CCsr * max(nl - 1, 1))(*[_csr_struct(*r, keep) for r in R])
+        om = np.ascontiguousarray(list(omega) + [0.0], dtype=np.float64)
+        self._check(self.lib.fsi_set_hierarchy(self.ctx, w, nl, Aa, Pa, Ra, om.ctypes.data))
+
+    def hierarchy_info(self, which):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        nl = ctypes.c_int32()
+        n = np.zeros(16, np.int64)
+        nnz = np.zeros(16, np.int64)
+        om = np.zeros(16, np.float64)
+        self._check(self.lib.fsi_hierarchy_info(self.ctx, w, ctypes.byref(nl), n.ctypes.data,
+                                                nnz.ctypes.data, om.ctypes.data))
+        k = nl.value
+        return n[:k].copy(), nnz[:k].copy(), om[:k].copy()
+
+    def get_level(self, which, level: int, what: str = "A"):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        wt = {"A": 0, "P": 1}[what]
+        nr, nc, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.fsi_get_level(self.ctx, w, level, wt, ctypes.byref(nr), ctypes.byref(nc),
+                                           ctypes.byref(nz), None, None, None))
+        rp = np.empty(nr.value + 1, np.int64)
+        ci = np.empty(nz.value, np.int32)
+        vv = np.empty(nz.value, np.float64)
+        self._check(self.lib.fsi_get_level(self.ctx, w, level, wt, None, None, None, rp.ctypes.data,
+                                           ci.ctypes.data, vv.ctypes.data))
+        return nr.value, nc.value, rp, ci, vv
+
+    def get_aggregates(self, which, level: int):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        cnt = ctypes.c_int64()
+        self._check(self.lib.fsi_get_aggregates(self.ctx, w, level, None, ctypes.byref(cnt)))
+        a = np.empty(cnt.value, np.int32)
+        self._check(self.lib.fsi_get_aggregates(self.ctx, w, level, a.ctypes.data, None))
+        return a
