@@ -106,15 +106,22 @@ typedef struct {
   double tol;       /* stop when ||b - A_h x||_2 <= tol ||b||_2 (default 1e-8)  */
   int32_t restart;  /* GMRES restart length m (default 50, at most 200)         */
   int32_t maxit;    /* total iteration bound (default 2000)                     */
+  int32_t timing;   /* 1: time every Arnoldi step's phases with HIP events    */
+  int32_t pad;
 } fsi_solve_opts;
 
 typedef struct {
   int32_t iters, restarts, converged, pad;
   double true_rel_resid;   /* recomputed FP64 ||b - A_h x|| / ||b||             */
   double t_total_ms;       /* wall time of the solve, stream-synchronised        */
+  /* with opts.timing: summed device time of each phase over the timed Arnoldi
+   * steps (n_timed of them): P^{-1} v, the A_h product, Gram-Schmidt */
+  double t_precond_ms, t_spmv_ms, t_gs_ms;
+  int32_t n_timed, pad2;
 } fsi_solve_info;
 
-/* Defaults for the option structs (tol 1e-8, m 50, maxit 2000; AMG as above). */
+/* Defaults for the option structs (tol 1e-8, m 50, maxit 2000, no timing;
+ * AMG as above). */
 void fsi_default_precond_opts(fsi_precond_opts* o);
 void fsi_default_solve_opts(fsi_solve_opts* o);
 
@@ -172,6 +179,12 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
  * (arrays of at least 16 entries), omega[l] (0 on the coarsest level). */
 fsi_status fsi_hierarchy_info(fsi_ctx* ctx, int which, int32_t* nlev, int64_t* n, int64_t* nnz,
                               double* omega);
+
+/* Bytes one V(1,1) cycle of hierarchy `which` moves as executed: per level
+ * the down-sweep matrices (A D^{-1}, Q = R (I - omega A D^{-1})), the
+ * up-sweep matrices (P, A P), the diagonal and the level vectors, plus the
+ * dense coarsest inverse.  Used to report achieved bandwidth. */
+fsi_status fsi_vcycle_bytes(fsi_ctx* ctx, int which, double* bytes);
 
 /* Copy level `level` of hierarchy `which` to host buffers: what = 0 the level
  * matrix A_l, 1 the prolongator P_l.  Pass NULL buffers to query only the

@@ -16,8 +16,10 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <type_traits>
 #include <new>
 #include <stdexcept>
 #include <string>
@@ -128,19 +130,26 @@ inline unsigned grid_for(int64_t n, int per_block) {
   return unsigned(std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 30)));
 }
 
+template <class F>
+void with_group(int G, F&& f) {
+  switch (G) {
+    case 4: f(std::integral_constant<int, 4>{}); break;
+    case 8: f(std::integral_constant<int, 8>{}); break;
+    case 16: f(std::integral_constant<int, 16>{}); break;
+    case 32: f(std::integral_constant<int, 32>{}); break;
+    default: f(std::integral_constant<int, 64>{}); break;
+  }
+}
+
 // Launch a row-grouped CSR product with epilogue.
 template <typename T, int NV, class Gather, class Epi>
 void launch_rows(const DCsr<T>& A, Gather g, Epi e, hipStream_t s) {
   if (A.nrows == 0) return;
-  const int G = A.group;
-  const unsigned grid = grid_for(A.nrows, kBlock / G);
-  switch (G) {
-    case 4: csr_rows_kernel<T, 4, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
-    case 8: csr_rows_kernel<T, 8, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
-    case 16: csr_rows_kernel<T, 16, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
-    case 32: csr_rows_kernel<T, 32, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
-    default: csr_rows_kernel<T, 64, NV><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e); break;
-  }
+  with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    csr_rows_kernel<T, G, NV><<<grid_for(A.nrows, kBlock / G), kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(),
+                                                                                A.dval(), g, e);
+  });
 }
 
 template <typename T, int NV = 1>
@@ -160,10 +169,11 @@ void vsub(int64_t n, T* y, const T* x, hipStream_t s) {
 // ---------------------------------------------------------------- AMG on device
 template <typename T>
 struct DLevel {
-  DCsr<T> A, P, R;
-  std::shared_ptr<DevBuf> dinv, x, y, r, b;
+  DCsr<T> AD, Q, P, AP;  // A D^{-1}, Q = R (I - omega A D^{-1}), prolongator, A P
+  std::shared_ptr<DevBuf> dinv, y, r, b;
   T omega = T(0);
   int64_t n = 0;
+  int gdown = 8, gdownq = 64, gup = 8;
 };
 
 template <typename T>
@@ -172,7 +182,7 @@ struct DHier {
   std::vector<DLevel<T>> lev;
   std::shared_ptr<DevBuf> cinv;
   int64_t nc = 0;
-  double bytes_per_cycle = 0.0;
+  double bytes_per_cycle = 0.0;  // algorithmic bytes of one cycle as executed
 };
 
 template <typename T>
@@ -186,18 +196,33 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s) {
     d.n = h.A.nrows;
     d.omega = T(h.omega);
     if (l < L) {
-      d.A = upload<T>(h.A, s);
+      // setup-time products for the two-launch level sweeps
+      HCsr AP = spgemm(h.A, h.P);
+      HCsr RA = spgemm(h.R, h.A);
+      std::vector<double> wd(h.dinv.size());
+      for (size_t i = 0; i < wd.size(); ++i) wd[i] = h.omega * h.dinv[i];
+      scale_cols(RA, wd);
+      HCsr Q = add(h.R, RA, -1.0);
+      HCsr AD = h.A;
+      scale_cols(AD, h.dinv);
+      d.AD = upload<T>(AD, s);
+      d.Q = upload<T>(Q, s);
       d.P = upload<T>(h.P, s);
-      d.R = upload<T>(h.R, s);
+      d.AP = upload<T>(AP, s);
       d.dinv = upload_vec<T>(h.dinv, s);
-      D.bytes_per_cycle += 2 * d.A.bytes() + d.P.bytes() + d.R.bytes() + double(d.n) * sizeof(T) * (1 + 6 * nv);
+      d.gdown = pick_group(d.AD.nnz, d.AD.nrows);
+      d.gdownq = pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16;
+      d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1));
+      const double vb = double(sizeof(T)) * nv;
+      // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
+      D.bytes_per_cycle += d.AD.bytes() + d.Q.bytes() + d.P.bytes() + d.AP.bytes() +
+                           double(d.n) * (2 * sizeof(T) + 5 * vb) + double(h.P.ncols) * 2 * vb;
     }
     auto mk = [&](int64_t cnt) {
       auto b = std::make_shared<DevBuf>();
       b->alloc(sizeof(T) * std::max<int64_t>(cnt, 1));
       return b;
     };
-    d.x = mk(d.n * nv);
     d.y = mk(d.n * nv);
     d.r = mk(d.n * nv);
     d.b = mk(d.n * nv);
@@ -209,6 +234,8 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s) {
   return D;
 }
 
+// One V(1,1) cycle from level l: two launches per level (down, up) and a
+// dense product with the coarsest inverse.
 template <typename T, int NV>
 void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s) {
   const int L = int(H.lev.size()) - 1;
@@ -220,13 +247,29 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s) {
   DLevel<T>& d = H.lev[l];
   DLevel<T>& c = H.lev[l + 1];
   const T* dinv = d.dinv->template as<T>();
-  T* x = d.x->template as<T>();
   T* r = d.r->template as<T>();
-  launch_rows<T, NV>(d.A, GatherJacobi0<T, NV>{b, dinv, d.omega}, EpiJacobi0<T, NV>{b, dinv, d.omega, x, r}, s);
-  spmv<T, NV>(d.R, r, c.b->template as<T>(), s);
-  vcycle_rec<T, NV>(H, l + 1, c.b->template as<T>(), c.y->template as<T>(), s);
-  launch_rows<T, NV>(d.P, GatherPlain<T, NV>{c.y->template as<T>()}, EpiAcc<T, NV>{x}, s);
-  launch_rows<T, NV>(d.A, GatherPlain<T, NV>{x}, EpiJacobiPost<T, NV>{b, x, dinv, d.omega, out}, s);
+  T* bc = c.b->template as<T>();
+  with_group(d.gdown, [&](auto gc) {
+    constexpr int GA = decltype(gc)::value;
+    const unsigned na = grid_for(d.AD.nrows, kBlock / GA);
+    auto go = [&](auto gq) {
+      constexpr int GQ = decltype(gq)::value;
+      const unsigned nq = grid_for(d.Q.nrows, kBlock / GQ);
+      vdown_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
+                                                              d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
+                                                              d.omega, r, bc, na);
+    };
+    if (d.gdownq == 64) go(std::integral_constant<int, 64>{});
+    else go(std::integral_constant<int, 16>{});
+  });
+  T* e = c.y->template as<T>();
+  vcycle_rec<T, NV>(H, l + 1, bc, e, s);
+  with_group(d.gup, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    vup_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(d.n, d.P.drp(), d.P.dci(), d.P.dval(),
+                                                                      d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b,
+                                                                      dinv, d.omega, r, out);
+  });
 }
 
 template <typename T>
@@ -333,8 +376,31 @@ struct fsi_ctx {
   int m_alloc = -1;
   DevBuf V, Z, part, dh, dy, flag;
   double* hpin = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  // one captured HIP graph per Arnoldi step j (its kernels depend on j);
+  // captured on a private stream, launched on the context stream
+  bool use_graphs = true;
+  hipStream_t cap_stream = nullptr;
+  std::vector<hipGraphExec_t> step_graph;  // whole step j
+  std::vector<hipGraphExec_t> pre_graph;   // timed mode: P^{-1} v_j
+  std::vector<hipGraphExec_t> gs_graph;    // timed mode: Gram-Schmidt + copy of step j
+  hipEvent_t tev[2][4] = {};  // phase events of the two in-flight Arnoldi steps
+  void drop_graphs() {
+    for (auto* v : {&step_graph, &pre_graph, &gs_graph}) {
+      for (auto& g : *v)
+        if (g) (void)hipGraphExecDestroy(g);
+      v->clear();
+    }
+  }
   ~fsi_ctx() {
+    drop_graphs();
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (hpin) (void)hipHostFree(hpin);
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    for (auto& r : tev)
+      for (auto& e : r)
+        if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -445,8 +511,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   return P;
 }
 
-void apply_precond(fsi_ctx& c, const double* r, double* z) {
-  hipStream_t s = c.stream;
+void apply_precond(fsi_ctx& c, const double* r, double* z, hipStream_t s) {
   if (c.precision == FSI_P_F64) {
     c.p64->apply(r, z, s);
   } else {
@@ -465,21 +530,30 @@ DHier<T>& hier_of(fsi_ctx& c, int which) {
 
 void ensure_krylov(fsi_ctx& c, int m) {
   if (c.m_alloc == m) return;
+  c.drop_graphs();
   c.V.alloc(sizeof(double) * size_t(m + 1) * c.N);
   c.Z.alloc(sizeof(double) * size_t(m) * c.N);
   c.part.alloc(sizeof(double) * size_t(kGsBlocks) * (m + 2));
-  c.dh.alloc(sizeof(double) * 3 * size_t(m + 2));
+  c.dh.alloc(sizeof(double) * 2 * size_t(3 * (m + 2)));
   c.dy.alloc(sizeof(double) * size_t(m + 1));
   c.flag.alloc(sizeof(int));
-  if (!c.hpin) HIP_TRY(hipHostMalloc((void**)&c.hpin, sizeof(double) * 3 * (kMaxBasis + 2)));
+  if (!c.hpin) HIP_TRY(hipHostMalloc((void**)&c.hpin, sizeof(double) * 2 * 3 * (kMaxBasis + 2)));
+  for (auto& e : c.ev)
+    if (!e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& r : c.tev)
+    for (auto& e : r)
+      if (!e) HIP_TRY(hipEventCreate(&e));
+  c.step_graph.assign(m, nullptr);
+  c.pre_graph.assign(m, nullptr);
+  c.gs_graph.assign(m, nullptr);
   c.m_alloc = m;
 }
 
-// Deterministic dot / norm passes: pass(mode, nv, w, h) -> out[0..nv]
-void gs_pass(fsi_ctx& c, int mode, int nv, double* w, const double* h, double* out) {
-  hipStream_t s = c.stream;
+// One fused Gram-Schmidt pass and its reduction: out[first..nv] on the device.
+void gs_pass(fsi_ctx& c, int mode, int nv, double* w, const double* h, double* out, hipStream_t s) {
   gs_pass_kernel<<<kGsBlocks, kBlock, 0, s>>>(c.N, nv, c.V.as<double>(), c.N, w, h, mode, c.part.as<double>());
-  gs_reduce_kernel<<<nv + 1, kBlock, 0, s>>>(kGsBlocks, nv, c.part.as<double>(), out);
+  const int first = mode == 2 ? nv : 0;
+  gs_reduce_kernel<<<nv + 1 - first, kBlock, 0, s>>>(kGsBlocks, first, c.part.as<double>(), out);
 }
 
 void givens(double a, double b, double& cs, double& sn) {
@@ -495,6 +569,10 @@ void givens(double a, double b, double& cs, double& sn) {
   }
 }
 
+// FGMRES(m), right preconditioned, CGS2 Arnoldi.  The host-side Givens
+// update of column j runs while the device already executes iteration j+1
+// (its scalars travel in one asynchronous copy per iteration); when column j
+// meets the stopping test the speculative iteration j+1 is simply discarded.
 fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_opts& o, fsi_solve_info& info) {
   hipStream_t s = c.stream;
   const int64_t N = c.N;
@@ -504,26 +582,25 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   double* Z = c.Z.as<double>();
   double* dh = c.dh.as<double>();
   double* hp = c.hpin;
+  const int slot = 3 * (m + 2);  // per iteration: h1 | h2 | h3
   hipEvent_t e0, e1;
   HIP_TRY(hipEventCreate(&e0));
   HIP_TRY(hipEventCreate(&e1));
   HIP_TRY(hipEventRecord(e0, s));
-  auto fetch = [&](const double* src, int cnt) {
-    HIP_TRY(hipMemcpyAsync(hp, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, s));
+  auto fetch1 = [&](const double* src) {
+    HIP_TRY(hipMemcpyAsync(hp, src, sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return hp[0];
   };
   // ||b|| and finiteness of b and x0
   HIP_TRY(hipMemsetAsync(c.flag.p, 0, sizeof(int), s));
   nonfinite_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, b, c.flag.as<int>());
   nonfinite_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, x, c.flag.as<int>());
-  gs_pass(c, 0, 0, const_cast<double*>(b), nullptr, dh);
-  {
-    int flag = 0;
-    HIP_TRY(hipMemcpyAsync(&flag, c.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
-    fetch(dh, 1);
-    if (flag) throw Error(FSI_ERR_NUMERIC, "b or the initial guess holds NaN or Inf");
-  }
-  const double bnorm = std::sqrt(hp[0]);
+  gs_pass(c, 0, 0, const_cast<double*>(b), nullptr, dh, s);
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, c.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  const double bnorm = std::sqrt(fetch1(dh));
+  if (flag) throw Error(FSI_ERR_NUMERIC, "b or the initial guess holds NaN or Inf");
   info = fsi_solve_info{};
   if (bnorm == 0.0) {
     HIP_TRY(hipMemsetAsync(x, 0, sizeof(double) * N, s));
@@ -537,12 +614,119 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   int iters = 0, restarts = 0;
   bool converged = false;
   double rel = 0.0;
+  // device work of Arnoldi step j (scalars of column j into slot j % 2)
+  const bool timing = o.timing != 0;
+  double t_pre = 0.0, t_spmv = 0.0, t_gs = 0.0;
+  int n_timed = 0;
+  auto record_pre = [&](int j, hipStream_t st) {
+    apply_precond(c, V + size_t(j) * N, Z + size_t(j) * N, st);
+  };
+  auto record_spmv = [&](int j, hipStream_t st) {
+    spmv<double>(c.Ah, Z + size_t(j) * N, V + size_t(j + 1) * N, st);
+  };
+  auto record_gs = [&](int j, hipStream_t st) {
+    double* w = V + size_t(j + 1) * N;
+    double* h1 = dh + (j % 2) * slot;
+    double* h2 = h1 + (m + 2);
+    double* h3 = h2 + (m + 2);
+    gs_pass(c, 0, j + 1, w, nullptr, h1, st);  // h1 = V^T w, |w|^2 before
+    gs_pass(c, 1, j + 1, w, h1, h2, st);       // w -= V h1; h2 = V^T w
+    gs_pass(c, 2, j + 1, w, h2, h3, st);       // w -= V h2; |w|^2 after
+    gs_normalise_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, st>>>(N, w, h3 + (j + 1), h1 + (j + 1));
+    HIP_TRY(hipMemcpyAsync(hp + (j % 2) * slot, h1, sizeof(double) * slot, hipMemcpyDeviceToHost, st));
+  };
+  // capture `rec` into an executable graph (private capture stream)
+  auto capture = [&](hipGraphExec_t& ex, auto&& rec) {
+    if (ex) return;
+    if (!c.cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c.cap_stream, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIP_TRY(hipStreamBeginCapture(c.cap_stream, hipStreamCaptureModeThreadLocal));
+    try {
+      rec(c.cap_stream);
+    } catch (...) {
+      (void)hipStreamEndCapture(c.cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      throw;
+    }
+    HIP_TRY(hipStreamEndCapture(c.cap_stream, &g));
+    hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    HIP_TRY(e);
+  };
+  // timed mode: the phases are separated by events recorded between launches
+  // (events inside a captured graph carry no timestamps), the A_h product is
+  // launched on its own between the two graphs of the step
+  auto launch_step = [&](int j) {
+    hipEvent_t* te = c.tev[j % 2];
+    if (c.use_graphs && !timing) {
+      capture(c.step_graph[j], [&](hipStream_t st) {
+        record_pre(j, st);
+        record_spmv(j, st);
+        record_gs(j, st);
+      });
+      HIP_TRY(hipGraphLaunch(c.step_graph[j], s));
+    } else if (c.use_graphs) {
+      capture(c.pre_graph[j], [&](hipStream_t st) { record_pre(j, st); });
+      capture(c.gs_graph[j], [&](hipStream_t st) { record_gs(j, st); });
+      HIP_TRY(hipEventRecord(te[0], s));
+      HIP_TRY(hipGraphLaunch(c.pre_graph[j], s));
+      HIP_TRY(hipEventRecord(te[1], s));
+      record_spmv(j, s);
+      HIP_TRY(hipEventRecord(te[2], s));
+      HIP_TRY(hipGraphLaunch(c.gs_graph[j], s));
+      HIP_TRY(hipEventRecord(te[3], s));
+    } else {
+      if (timing) HIP_TRY(hipEventRecord(te[0], s));
+      record_pre(j, s);
+      if (timing) HIP_TRY(hipEventRecord(te[1], s));
+      record_spmv(j, s);
+      if (timing) HIP_TRY(hipEventRecord(te[2], s));
+      record_gs(j, s);
+      if (timing) HIP_TRY(hipEventRecord(te[3], s));
+    }
+    HIP_TRY(hipEventRecord(c.ev[j % 2], s));
+  };
+  // host part of step j: Hessenberg column, Givens rotations; true = stop
+  auto finish_step = [&](int j) -> bool {
+    HIP_TRY(hipEventSynchronize(c.ev[j % 2]));
+    if (timing) {
+      float a = 0.f, b2 = 0.f, c3 = 0.f;
+      hipEvent_t* te = c.tev[j % 2];
+      HIP_TRY(hipEventElapsedTime(&a, te[0], te[1]));
+      HIP_TRY(hipEventElapsedTime(&b2, te[1], te[2]));
+      HIP_TRY(hipEventElapsedTime(&c3, te[2], te[3]));
+      t_pre += a;
+      t_spmv += b2;
+      t_gs += c3;
+      ++n_timed;
+    }
+    const double* q1 = hp + (j % 2) * slot;
+    const double* q2 = q1 + (m + 2);
+    const double* q3 = q2 + (m + 2);
+    const double wbefore = std::sqrt(q1[j + 1]);
+    for (int i = 0; i <= j; ++i) Hat(i, j) = q1[i] + q2[i];
+    const double hn = std::sqrt(q3[j + 1] > 0.0 ? q3[j + 1] : 0.0);
+    Hat(j + 1, j) = hn;
+    const bool breakdown = !(hn > 1e-14 * wbefore);
+    for (int i = 0; i < j; ++i) {
+      const double a = Hat(i, j), bb = Hat(i + 1, j);
+      Hat(i, j) = cs[i] * a + sn[i] * bb;
+      Hat(i + 1, j) = -sn[i] * a + cs[i] * bb;
+    }
+    givens(Hat(j, j), Hat(j + 1, j), cs[j], sn[j]);
+    Hat(j, j) = cs[j] * Hat(j, j) + sn[j] * Hat(j + 1, j);
+    Hat(j + 1, j) = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+    ++iters;
+    if (!std::isfinite(g[j + 1])) throw Error(FSI_ERR_NUMERIC, "non-finite Arnoldi coefficients");
+    return std::fabs(g[j + 1]) / bnorm <= o.tol || breakdown || iters >= o.maxit;
+  };
   while (true) {
     // true residual r = b - A x into V_0
     spmv_sub<double>(c.Ah, x, b, V, s);
-    gs_pass(c, 0, 0, V, nullptr, dh);
-    fetch(dh, 1);
-    const double beta = std::sqrt(hp[0]);
+    gs_pass(c, 0, 0, V, nullptr, dh, s);
+    const double beta = std::sqrt(fetch1(dh));
     rel = beta / bnorm;
     if (!std::isfinite(rel)) throw Error(FSI_ERR_NUMERIC, "non-finite residual");
     if (rel <= o.tol) { converged = true; break; }
@@ -551,41 +735,13 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
     int k = 0;
+    launch_step(0);
     for (int j = 0; j < m; ++j) {
-      double* vj = V + size_t(j) * N;
-      double* zj = Z + size_t(j) * N;
-      double* w = V + size_t(j + 1) * N;
-      apply_precond(c, vj, zj);
-      spmv<double>(c.Ah, zj, w, s);
-      // CGS2: h1 = V^T w (+ w.w); w -= V h1, h2 = V^T w; w -= V h2, |w|^2
-      double* h1 = dh;
-      double* h2 = dh + (m + 2);
-      double* h3 = dh + 2 * (m + 2);
-      gs_pass(c, 0, j + 1, w, nullptr, h1);
-      gs_pass(c, 1, j + 1, w, h1, h2);
-      gs_pass_kernel<<<kGsBlocks, kBlock, 0, s>>>(N, j + 1, V, N, w, h2, 2, c.part.as<double>());
-      gs_reduce_kernel<<<1, kBlock, 0, s>>>(kGsBlocks, j + 1, c.part.as<double>() + (j + 1), h3 + (j + 1));
-      HIP_TRY(hipMemcpyAsync(hp, dh, sizeof(double) * 3 * (m + 2), hipMemcpyDeviceToHost, s));
-      HIP_TRY(hipStreamSynchronize(s));
-      const double wbefore = std::sqrt(hp[j + 1]);
-      for (int i = 0; i <= j; ++i) Hat(i, j) = hp[i] + hp[(m + 2) + i];
-      const double hn = std::sqrt(std::max(hp[2 * (m + 2) + j + 1], 0.0));
-      Hat(j + 1, j) = hn;
-      const bool breakdown = !(hn > 1e-14 * wbefore);
-      if (!breakdown) scale_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, w, 1.0 / hn);
-      for (int i = 0; i < j; ++i) {
-        const double a = Hat(i, j), bb = Hat(i + 1, j);
-        Hat(i, j) = cs[i] * a + sn[i] * bb;
-        Hat(i + 1, j) = -sn[i] * a + cs[i] * bb;
-      }
-      givens(Hat(j, j), Hat(j + 1, j), cs[j], sn[j]);
-      Hat(j, j) = cs[j] * Hat(j, j) + sn[j] * Hat(j + 1, j);
-      Hat(j + 1, j) = 0.0;
-      g[j + 1] = -sn[j] * g[j];
-      g[j] = cs[j] * g[j];
-      ++iters;
+      const bool more = j + 1 < m && iters + 1 < o.maxit;
+      if (more) launch_step(j + 1);  // speculative: overlaps the host work below
+      const bool stop = finish_step(j);
       k = j + 1;
-      if (std::fabs(g[j + 1]) / bnorm <= o.tol || breakdown || iters >= o.maxit) break;
+      if (stop || !more) break;
     }
     for (int i = k - 1; i >= 0; --i) {
       double sum = g[i];
@@ -595,7 +751,7 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     }
     HIP_TRY(hipMemcpyAsync(c.dy.p, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     multi_axpy_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, k, Z, N, c.dy.as<double>(), x);
-    HIP_TRY(hipStreamSynchronize(s));  // y lives on the host stack frame
+    HIP_TRY(hipStreamSynchronize(s));  // y lives in host memory
     ++restarts;
   }
   HIP_TRY(hipEventRecord(e1, s));
@@ -605,6 +761,10 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   info.iters = iters;
+  info.t_precond_ms = t_pre;
+  info.t_spmv_ms = t_spmv;
+  info.t_gs_ms = t_gs;
+  info.n_timed = n_timed;
   info.restarts = restarts;
   info.converged = converged ? 1 : 0;
   info.true_rel_resid = rel;
@@ -631,6 +791,8 @@ void fsi_default_solve_opts(fsi_solve_opts* o) {
   o->tol = 1e-8;
   o->restart = 50;
   o->maxit = 2000;
+  o->timing = 0;
+  o->pad = 0;
 }
 
 fsi_status fsi_create(fsi_ctx** ctx, int device, void* hip_stream) {
@@ -649,6 +811,7 @@ fsi_status fsi_create(fsi_ctx** ctx, int device, void* hip_stream) {
   if (!c) return FSI_ERR_OOM;
   c->device = device;
   c->stream = static_cast<hipStream_t>(hip_stream);
+  if (const char* g = std::getenv("FSI_GRAPHS")) c->use_graphs = std::strcmp(g, "0") != 0;
   if (hipSetDevice(device) != hipSuccess) {
     delete c;
     g_create_err = "hipSetDevice failed";
@@ -766,6 +929,8 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     c.Ah = dAh;
     c.have_system = true;
     c.have_precond = false;
+    c.drop_graphs();
+    c.m_alloc = -1;
     c.p64.reset();
     c.p32.reset();
     c.m_alloc = -1;
@@ -843,6 +1008,8 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     }
     for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
     c.precision = o.precision;
+    c.drop_graphs();
+    c.m_alloc = -1;
     c.p64.reset();
     c.p32.reset();
     if (o.precision == FSI_P_F64) c.p64 = make_precond<double>(c);
@@ -891,7 +1058,7 @@ fsi_status fsi_apply_precond(fsi_ctx* ctx, const double* r, double* z) {
     check_device_ptr(r, "r");
     check_device_ptr(z, "z");
     if (r == z) throw Error(FSI_ERR_ARG, "r and z must not alias");
-    apply_precond(c, r, z);
+    apply_precond(c, r, z, c.stream);
     HIP_TRY(hipGetLastError());
     return FSI_OK;
   });
@@ -955,6 +1122,8 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
     std::string m = sa_finalize(H);
     if (!m.empty()) throw Error(FSI_ERR_NUMERIC, m);
     const int nv = which == FSI_H_M ? c.d : 1;
+    c.drop_graphs();
+    c.m_alloc = -1;
     if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream);
     else c.p32->H[which] = upload_hier<float>(H, nv, c.stream);
     HIP_TRY(hipStreamSynchronize(c.stream));
@@ -975,6 +1144,16 @@ fsi_status fsi_hierarchy_info(fsi_ctx* ctx, int which, int32_t* nlev, int64_t* n
       if (nnz) nnz[l] = H.levels[l].A.nnz();
       if (omega) omega[l] = H.levels[l].omega;
     }
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_vcycle_bytes(fsi_ctx* ctx, int which, double* bytes) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (which < 0 || which >= FSI_NHIER || !bytes) throw Error(FSI_ERR_ARG, "bad arguments");
+    *bytes = c.precision == FSI_P_F64 ? c.p64->H[which].bytes_per_cycle : c.p32->H[which].bytes_per_cycle;
     return FSI_OK;
   });
 }

@@ -32,17 +32,6 @@ struct GatherPlain {
   __device__ __forceinline__ T operator()(int32_t c, int n) const { return x[int64_t(c) * NV + n]; }
 };
 
-// x_j = omega * dinv_j * b_j formed on the fly (first pre-smoothing sweep
-// from a zero initial guess).
-template <typename T, int NV>
-struct GatherJacobi0 {
-  const T* b;
-  const T* dinv;
-  T omega;
-  __device__ __forceinline__ T operator()(int32_t c, int n) const {
-    return omega * dinv[c] * b[int64_t(c) * NV + n];
-  }
-};
 
 template <typename T, int NV>
 struct EpiStore {  // y = A x
@@ -72,54 +61,14 @@ struct EpiAcc {  // y += A x
   }
 };
 
-// Pre-smoothing from zero: x = omega D^{-1} b and r = b - A x in one pass.
-template <typename T, int NV>
-struct EpiJacobi0 {
-  const T* b;
-  const T* dinv;
-  T omega;
-  T* x;
-  T* r;
-  __device__ __forceinline__ void operator()(int64_t i, const T* acc) const {
-    const T wd = omega * dinv[i];
-#pragma unroll
-    for (int n = 0; n < NV; ++n) {
-      const T bi = b[i * NV + n];
-      x[i * NV + n] = wd * bi;
-      r[i * NV + n] = bi - acc[n];
-    }
-  }
-};
-
-// Post-smoothing: y = x + omega D^{-1} (b - A x).  y must not alias x.
-template <typename T, int NV>
-struct EpiJacobiPost {
-  const T* b;
-  const T* x;
-  const T* dinv;
-  T omega;
-  T* y;
-  __device__ __forceinline__ void operator()(int64_t i, const T* acc) const {
-    const T wd = omega * dinv[i];
-#pragma unroll
-    for (int n = 0; n < NV; ++n) y[i * NV + n] = x[i * NV + n] + wd * (b[i * NV + n] - acc[n]);
-  }
-};
-
-template <typename T, int G, int NV, class Gather, class Epi>
-__global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const int64_t* __restrict__ rp,
-                                                           const int32_t* __restrict__ ci,
-                                                           const T* __restrict__ val, Gather gx, Epi epi) {
-  constexpr int RPB = kBlock / G;  // rows per block
-  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
-  const int lane = threadIdx.x % G;
-  if (row >= nrows) return;  // whole groups leave together (G divides 64)
-  T acc[NV];
-#pragma unroll
-  for (int n = 0; n < NV; ++n) acc[n] = T(0);
+// Accumulate row `row` of a CSR matrix into acc[NV] with the G lanes of a
+// group (lane strides by G; two entries in flight per lane).
+template <typename T, int G, int NV, class Gather>
+__device__ __forceinline__ void row_accumulate(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                               const T* __restrict__ val, int64_t row, int lane,
+                                               const Gather& gx, T* acc) {
   const int64_t b = rp[row], e = rp[row + 1];
   int64_t k = b + lane;
-  // two entries in flight per lane
   for (; k + G < e; k += 2 * G) {
     const int32_t c0 = ci[k], c1 = ci[k + G];
     const T a0 = val[k], a1 = val[k + G];
@@ -132,11 +81,99 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
 #pragma unroll
     for (int n = 0; n < NV; ++n) acc[n] += a0 * gx(c0, n);
   }
+}
+
+template <typename T, int G, int NV>
+__device__ __forceinline__ void group_reduce(T* acc) {
 #pragma unroll
   for (int off = G / 2; off > 0; off >>= 1)
 #pragma unroll
     for (int n = 0; n < NV; ++n) acc[n] += __shfl_xor(acc[n], off, G);
+}
+
+template <typename T, int G, int NV, class Gather, class Epi>
+__global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const int64_t* __restrict__ rp,
+                                                           const int32_t* __restrict__ ci,
+                                                           const T* __restrict__ val, Gather gx, Epi epi) {
+  constexpr int RPB = kBlock / G;  // rows per block
+  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= nrows) return;  // whole groups leave together (G divides 64)
+  T acc[NV];
+#pragma unroll
+  for (int n = 0; n < NV; ++n) acc[n] = T(0);
+  row_accumulate<T, G, NV>(rp, ci, val, row, lane, gx, acc);
+  group_reduce<T, G, NV>(acc);
   if (lane == 0) epi(row, acc);
+}
+
+// ------------------------------------------------ fused V-cycle level sweeps
+// Down-sweep of a V(1,1) level with a zero initial guess: the pre-smoothed
+// x = omega D^{-1} b gives the residual r = b - omega (A D^{-1}) b on the fine
+// rows (A D^{-1}: A with its columns scaled at setup), and the restricted
+// residual b_c = R r = Q b on the coarse rows, Q = R (I - omega A D^{-1})
+// formed at setup.  Both read only b, so one launch covers both row sets
+// (blocks [0, nblk_a) the fine rows, the rest the coarse rows).
+template <typename T, int GA, int GQ, int NV>
+__global__ __launch_bounds__(kBlock) void vdown_kernel(
+    int64_t na, const int64_t* __restrict__ rpa, const int32_t* __restrict__ cia, const T* __restrict__ va,
+    int64_t nq, const int64_t* __restrict__ rpq, const int32_t* __restrict__ ciq, const T* __restrict__ vq,
+    const T* __restrict__ b, T omega, T* __restrict__ r, T* __restrict__ bc, unsigned nblk_a) {
+  T acc[NV];
+#pragma unroll
+  for (int n = 0; n < NV; ++n) acc[n] = T(0);
+  const unsigned blk = blockIdx.x;
+  if (blk < nblk_a) {
+    const int64_t row = int64_t(blk) * (kBlock / GA) + threadIdx.x / GA;
+    const int lane = threadIdx.x % GA;
+    if (row >= na) return;
+    row_accumulate<T, GA, NV>(rpa, cia, va, row, lane, GatherPlain<T, NV>{b}, acc);
+    group_reduce<T, GA, NV>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int n = 0; n < NV; ++n) r[row * NV + n] = b[row * NV + n] - omega * acc[n];
+  } else {
+    const int64_t row = int64_t(blk - nblk_a) * (kBlock / GQ) + threadIdx.x / GQ;
+    const int lane = threadIdx.x % GQ;
+    if (row >= nq) return;
+    row_accumulate<T, GQ, NV>(rpq, ciq, vq, row, lane, GatherPlain<T, NV>{b}, acc);
+    group_reduce<T, GQ, NV>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int n = 0; n < NV; ++n) bc[row * NV + n] = acc[n];
+  }
+}
+
+// Up-sweep: with x = omega D^{-1} b + P e (prolongated coarse correction) the
+// post-smoothing step x + omega D^{-1} (b - A x) equals
+//   y = omega D^{-1} b + P e + omega D^{-1} (r - (A P) e),
+// r from the down-sweep and A P formed at setup: one pass over the rows of P
+// and A P.  y may alias b.
+template <typename T, int G, int NV>
+__global__ __launch_bounds__(kBlock) void vup_kernel(
+    int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
+    const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
+    const T* __restrict__ e, const T* b, const T* __restrict__ dinv, T omega, const T* __restrict__ r, T* y) {
+  constexpr int RPB = kBlock / G;
+  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  T ap[NV], pe[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = T(0);
+  const GatherPlain<T, NV> ge{e};
+  row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
+  row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
+  group_reduce<T, G, NV>(pe);
+  group_reduce<T, G, NV>(ap);
+  if (lane == 0) {
+    const T wd = omega * dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const T bi = b[row * NV + q];
+      y[row * NV + q] = wd * bi + pe[q] + wd * (r[row * NV + q] - ap[q]);
+    }
+  }
 }
 
 // -------------------------------------------------------------- coarse solve
@@ -186,64 +223,148 @@ __global__ __launch_bounds__(kBlock) void scale_kernel(int64_t n, double* y, dou
 }
 
 // ---------------------------------------------------------- Gram-Schmidt
-// Partial dots of w with nv basis vectors V_i (V_i = V + i * ld) plus w.w,
-// over a fixed grid (deterministic), written to part[block * (nv + 1) + i].
-constexpr int kGsBlocks = 512;
+// One fused pass over the Krylov basis V (vectors V_i = V + i * ld) and the
+// new vector w on a fixed grid; every block writes one partial per output
+// into part[i * gridDim.x + block], and gs_reduce_kernel adds them in block
+// order (bit-reproducible; no cross-block synchronisation inside a kernel,
+// which would need a device-scope release, i.e. an L2 write-back, per block).
+//   mode 0: out[i] = V_i . w (i < nv),            out[nv] = w . w
+//   mode 1: w -= sum_i h_i V_i, then out[i] = V_i . w, out[nv] = w . w
+//   mode 2: w -= sum_i h_i V_i, then                  out[nv] = w . w
+constexpr int kGsBlocks = 1024;
 constexpr int kMaxBasis = 208;
+constexpr int kWaves = kBlock / 64;
+constexpr int kGsTile = 8;
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x == 0)
-    for (int i = 0; i < kBlock / 64; ++i) s += sh[i];
-  return s;  // valid in thread 0
+  return v;
 }
 
-// mode 0: dots V_i . w and w . w
-// mode 1: w -= sum_i h_i V_i, then dots V_i . w and w . w of the updated w
-// mode 2: w -= sum_i h_i V_i, then only w . w (written at index nv)
 __global__ __launch_bounds__(kBlock) void gs_pass_kernel(int64_t n, int nv, const double* __restrict__ V,
                                                           int64_t ld, double* __restrict__ w,
                                                           const double* __restrict__ h, int mode,
                                                           double* __restrict__ part) {
-  __shared__ double sh[kBlock / 64];
   __shared__ double hs[kMaxBasis];
+  __shared__ double ws[kWaves][kMaxBasis + 1];
+  const int tid = threadIdx.x, wid = tid / 64, lane = tid % 64;
   if (mode != 0)
-    for (int i = threadIdx.x; i < nv; i += kBlock) hs[i] = h[i];
+    for (int i = tid; i < nv; i += kBlock) hs[i] = h[i];
   __syncthreads();
   const int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
   const int64_t lo = int64_t(blockIdx.x) * chunk;
   const int64_t hi = lo + chunk < n ? lo + chunk : n;
   if (mode != 0) {
-    for (int64_t k = lo + threadIdx.x; k < hi; k += kBlock) {
-      double s = w[k];
-      for (int i = 0; i < nv; ++i) s -= hs[i] * V[i * ld + k];
-      w[k] = s;
+    // w -= V h with kGsTile independent loads per element
+    for (int64_t k = lo + tid; k < hi; k += kBlock) {
+      double acc[kGsTile];
+#pragma unroll
+      for (int t = 0; t < kGsTile; ++t) acc[t] = 0.0;
+      int i0 = 0;
+      for (; i0 + kGsTile <= nv; i0 += kGsTile)
+#pragma unroll
+        for (int t = 0; t < kGsTile; ++t) acc[t] += hs[i0 + t] * V[(i0 + t) * ld + k];
+      for (int i = i0; i < nv; ++i) acc[i - i0] += hs[i] * V[i * ld + k];
+      double s = 0.0;
+#pragma unroll
+      for (int t = 0; t < kGsTile; ++t) s += acc[t];
+      w[k] = w[k] - s;
     }
-    __syncthreads();
   }
-  for (int i = mode == 2 ? nv : 0; i <= nv; ++i) {
-    const double* vi = i < nv ? V + i * ld : w;
-    double s = 0.0;
-    for (int64_t k = lo + threadIdx.x; k < hi; k += kBlock) s += vi[k] * w[k];
-    s = block_sum(s, sh);
-    if (threadIdx.x == 0) part[int64_t(blockIdx.x) * (nv + 1) + i] = s;
+  // dots in tiles of kGsTile vectors (kGsTile independent loads per element,
+  // no branches inside the element loop)
+  const int first = mode == 2 ? nv : 0;
+  int i0 = first;
+  for (; i0 + kGsTile <= nv; i0 += kGsTile) {
+    double acc[kGsTile];
+#pragma unroll
+    for (int t = 0; t < kGsTile; ++t) acc[t] = 0.0;
+    const double* vt = V + i0 * ld;
+    for (int64_t k = lo + tid; k < hi; k += kBlock) {
+      const double wk = w[k];
+#pragma unroll
+      for (int t = 0; t < kGsTile; ++t) acc[t] += vt[t * ld + k] * wk;
+    }
+#pragma unroll
+    for (int t = 0; t < kGsTile; ++t) {
+      const double sv = wave_sum(acc[t]);
+      if (lane == 0) ws[wid][i0 + t] = sv;
+    }
+  }
+  {
+    // tail: the remaining cnt < kGsTile vectors and w . w (index nv); loads
+    // of the unused slots are clamped to a valid vector and masked out
+    const int cnt = nv - i0;
+    double acc[kGsTile];
+    double aw = 0.0;
+#pragma unroll
+    for (int t = 0; t < kGsTile; ++t) acc[t] = 0.0;
+    if (cnt > 0) {
+      for (int64_t k = lo + tid; k < hi; k += kBlock) {
+        const double wk = w[k];
+        aw += wk * wk;
+#pragma unroll
+        for (int t = 0; t < kGsTile; ++t) {
+          const int i = t < cnt ? i0 + t : nv - 1;
+          const double m = t < cnt ? 1.0 : 0.0;
+          acc[t] += m * (V[i * ld + k] * wk);
+        }
+      }
+    } else {
+      for (int64_t k = lo + tid; k < hi; k += kBlock) {
+        const double wk = w[k];
+        aw += wk * wk;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kGsTile; ++t) {
+      if (t < cnt) {
+        const double sv = wave_sum(acc[t]);
+        if (lane == 0) ws[wid][i0 + t] = sv;
+      }
+    }
+    const double sw = wave_sum(aw);
+    if (lane == 0) ws[wid][nv] = sw;
+  }
+  __syncthreads();
+  for (int i = first + tid; i <= nv; i += kBlock) {
+    double p = 0.0;
+    for (int q = 0; q < kWaves; ++q) p += ws[q][i];
+    part[int64_t(i) * gridDim.x + blockIdx.x] = p;
   }
 }
 
-// out[i] = sum over blocks of part[b * (nv + 1) + i], fixed order.
-__global__ __launch_bounds__(kBlock) void gs_reduce_kernel(int nblocks, int nv, const double* __restrict__ part,
+// out[first + b] = sum over the nb block partials of output first + b, in
+// block order (one block per output).
+__global__ __launch_bounds__(kBlock) void gs_reduce_kernel(int nb, int first, const double* __restrict__ part,
                                                             double* __restrict__ out) {
-  __shared__ double sh[kBlock / 64];
-  const int i = blockIdx.x;
+  __shared__ double sh[kWaves];
+  const int i = first + blockIdx.x;
+  const double* p = part + int64_t(i) * nb;
   double s = 0.0;
-  for (int b = threadIdx.x; b < nblocks; b += kBlock) s += part[int64_t(b) * (nv + 1) + i];
-  s = block_sum(s, sh);
-  if (threadIdx.x == 0) out[i] = s;
+  for (int b = threadIdx.x; b < nb; b += kBlock) s += p[b];
+  s = wave_sum(s);
+  if (threadIdx.x % 64 == 0) sh[threadIdx.x / 64] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int q = 0; q < kWaves; ++q) t += sh[q];
+    out[i] = t;
+  }
+}
+
+// V_{j+1} = w / ||w|| with the norm read on the device (out of the last
+// Gram-Schmidt pass); left untouched on a breakdown (||w|| <= 1e-14 of its
+// norm before orthogonalisation), which the host detects with the same test.
+__global__ __launch_bounds__(kBlock) void gs_normalise_kernel(int64_t n, double* w, const double* __restrict__ nrm2,
+                                                               const double* __restrict__ nrm2_before) {
+  const double hn = sqrt(nrm2[0] > 0.0 ? nrm2[0] : 0.0);
+  const double wb = sqrt(nrm2_before[0]);
+  if (!(hn > 1e-14 * wb)) return;
+  const double f = 1.0 / hn;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    w[i] = w[i] * f;
 }
 
 // x += sum_i y_i Z_i

@@ -51,12 +51,15 @@ class CPrecondOpts(ctypes.Structure):
 
 
 class CSolveOpts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("restart", ctypes.c_int32), ("maxit", ctypes.c_int32),
+                ("timing", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class CSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("true_rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+                ("pad", ctypes.c_int32), ("true_rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double),
+                ("t_precond_ms", ctypes.c_double), ("t_spmv_ms", ctypes.c_double), ("t_gs_ms", ctypes.c_double),
+                ("n_timed", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 @dataclasses.dataclass
@@ -67,6 +70,10 @@ class SolveInfo:
     converged: bool
     true_rel_resid: float
     t_total_ms: float
+    t_precond_ms: float = 0.0
+    t_spmv_ms: float = 0.0
+    t_gs_ms: float = 0.0
+    n_timed: int = 0
 
 
 def _declare(lib):
@@ -86,6 +93,7 @@ def _declare(lib):
         "fsi_hierarchy_info": ([P, i32, P, P, P, P], i32),
         "fsi_get_level": ([P, i32, i32, i32, P, P, P, P, P, P], i32),
         "fsi_get_aggregates": ([P, i32, i32, P, P], i32),
+        "fsi_vcycle_bytes": ([P, i32, P], i32),
         "fsi_default_precond_opts": ([ctypes.POINTER(CPrecondOpts)], None),
         "fsi_default_solve_opts": ([ctypes.POINTER(CSolveOpts)], None),
     }
@@ -113,7 +121,8 @@ def exported_symbols():
     """Names of the C ABI entry points this binding declares."""
     return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_build_precond",
             "fsi_solve", "fsi_spmv", "fsi_apply_precond", "fsi_vcycle", "fsi_set_hierarchy",
-            "fsi_hierarchy_info", "fsi_get_level", "fsi_get_aggregates", "fsi_default_precond_opts",
+            "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_get_level", "fsi_get_aggregates",
+            "fsi_default_precond_opts",
             "fsi_default_solve_opts"]
 
 
@@ -213,16 +222,18 @@ class FsiSolver:
         o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, 0, strength0)
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
 
-    def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000):
+    def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,
+              timing: bool = False):
         torch = self.torch
         if x is None:
             x = torch.zeros(self.N, dtype=torch.float64, device=b.device)
-        o = CSolveOpts(tol, restart, maxit)
+        o = CSolveOpts(tol, restart, maxit, int(timing), 0)
         info = CSolveInfo()
         rc = self._check(self.lib.fsi_solve(self.ctx, _dptr(b, self.N, "b"), _dptr(x, self.N, "x"),
                                             ctypes.byref(o), ctypes.byref(info)))
         return x, SolveInfo(STATUS[rc], info.iters, info.restarts, bool(info.converged),
-                            info.true_rel_resid, info.t_total_ms)
+                            info.true_rel_resid, info.t_total_ms, info.t_precond_ms, info.t_spmv_ms,
+                            info.t_gs_ms, info.n_timed)
 
     def spmv(self, x, y=None):
         if y is None:
@@ -265,6 +276,12 @@ class FsiSolver:
                                                 nnz.ctypes.data, om.ctypes.data))
         k = nl.value
         return n[:k].copy(), nnz[:k].copy(), om[:k].copy()
+
+    def vcycle_bytes(self, which) -> float:
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        b = ctypes.c_double()
+        self._check(self.lib.fsi_vcycle_bytes(self.ctx, w, ctypes.byref(b)))
+        return b.value
 
     def get_level(self, which, level: int, what: str = "A"):
         w = HIERARCHIES[which] if isinstance(which, str) else int(which)

@@ -194,3 +194,41 @@ def test_solve_c2_full_size():
     assert r <= 1e-8 * 1.001
     print(f"c2: iters={info.iters} t={info.t_total_ms:.1f} ms resid={r:.2e}")
     s.close()
+
+
+def test_graph_replays_match_eager_launches(monkeypatch):
+    """Each Arnoldi step runs as a captured HIP graph, replayed every
+    iteration and every solve.  Two solves through the graphs (with eager work
+    in between) and one with plain launches give bit-identical iterates."""
+    from oracle import blocks
+    sysm = system("c1")
+    bs = blocks.BlockSystem(sysm)
+    b = _dev(sysm.b)
+    s = _solver("c1")
+    x1, i1 = s.solve(b)
+    junk = s.spmv(torch.randn(bs.N, dtype=torch.float64, device="cuda:0"))  # eager work between replays
+    torch.cuda.synchronize()
+    x2, i2 = s.solve(b)
+    s.close()
+    monkeypatch.setenv("FSI_GRAPHS", "0")
+    e = _solver("c1")
+    x3, i3 = e.solve(b)
+    e.close()
+    assert i1.iters == i2.iters == i3.iters
+    assert torch.equal(x1, x2) and torch.equal(x1, x3)
+    assert torch.isfinite(junk).all()
+
+
+def test_timed_solve_matches_and_reports_phases():
+    """The timed mode (two graphs per step, events between them) computes the
+    same iterates and reports positive phase times for every iteration."""
+    sysm = system("c1")
+    b = _dev(sysm.b)
+    s = _solver("c1")
+    x1, i1 = s.solve(b)
+    x2, i2 = s.solve(b, timing=True)
+    s.close()
+    assert torch.equal(x1, x2) and i1.iters == i2.iters
+    assert i2.n_timed == i2.iters
+    assert i2.t_spmv_ms > 0 and i2.t_precond_ms > 0 and i2.t_gs_ms > 0
+    assert i2.t_spmv_ms + i2.t_precond_ms + i2.t_gs_ms <= i2.t_total_ms * 1.05
