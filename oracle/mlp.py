@@ -1,0 +1,110 @@
+"""Per-node MLP smoother, FP64 reference (oracle; test infrastructure only).
+
+The learned part of the workload replaces one damped-Jacobi sweep of the AMG
+cycles on the mesh-motion and solid levels by a small network applied node by
+node: the input of node i is the Jacobi-scaled residual D^{-1} b at the 3^d
+lattice nodes around i (d components each, zero where the neighbour is not an
+unknown of the operator), the output is the correction at node i.  The
+network has three bias-free layers with ReLU between them,
+
+    delta = W3^T relu(W2^T relu(W1^T z)),
+
+so it is positively homogeneous (delta(a z) = a delta(z), a > 0) and needs
+no input normalisation.  Training minimises the diagonal-weighted squared
+error L = (1/n) sum_i w_i ||delta_i - e_i||^2 against exact corrections e,
+with Adam (beta = 0.9, 0.999, eps = 1e-8).
+
+Every function is plain FP64 numpy.  ``round_bf16`` reproduces the storage
+precision of the GPU path (round to nearest even to 8 significant bits) so
+that both sides can be fed the same values.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def round_bf16(x: np.ndarray) -> np.ndarray:
+    """Round FP32-representable values to bfloat16 (nearest, ties to even)."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (r.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def stencil_inputs(v: np.ndarray, nbr: np.ndarray) -> np.ndarray:
+    """z[i, s*d + c] = v[nbr[i, s], c] (0 where nbr[i, s] < 0).
+
+    v: (n, d) node values; nbr: (n, S) neighbour indices in lattice-offset
+    order (S = 3^d).
+    """
+    n, S = nbr.shape
+    d = v.shape[1]
+    z = np.zeros((n, S * d))
+    for s in range(S):
+        ok = nbr[:, s] >= 0
+        z[ok, s * d:(s + 1) * d] = v[nbr[ok, s]]
+    return z
+
+
+def forward(W, z, act_round=None):
+    """Returns (y, cache).  act_round optionally rounds the hidden
+    activations (the GPU stores them in bfloat16 between layers)."""
+    W1, W2, W3 = W
+    a1 = z @ W1
+    h1 = np.maximum(a1, 0.0)
+    if act_round is not None:
+        h1 = act_round(h1)
+    a2 = h1 @ W2
+    h2 = np.maximum(a2, 0.0)
+    if act_round is not None:
+        h2 = act_round(h2)
+    y = h2 @ W3
+    return y, (z, a1, h1, a2, h2)
+
+
+def loss(y, e, w):
+    """(1/n) sum_i w_i ||y_i - e_i||^2."""
+    return float(np.sum(w[:, None] * (y - e) ** 2) / y.shape[0])
+
+
+def backward(W, cache, dy):
+    """Gradients of sum(dy * y) with respect to W1, W2, W3 (chain rule by hand)."""
+    W1, W2, W3 = W
+    z, a1, h1, a2, h2 = cache
+    dW3 = h2.T @ dy
+    dh2 = dy @ W3.T
+    da2 = dh2 * (a2 > 0.0)
+    dW2 = h1.T @ da2
+    dh1 = da2 @ W2.T
+    da1 = dh1 * (a1 > 0.0)
+    dW1 = z.T @ da1
+    return dW1, dW2, dW3
+
+
+def loss_and_grad(W, z, e, w, act_round=None):
+    y, cache = forward(W, z, act_round)
+    dy = (2.0 / y.shape[0]) * w[:, None] * (y - e)
+    return loss(y, e, w), backward(W, cache, dy)
+
+
+def adam_step(W, G, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba), step counter t starting at 1."""
+    out_W, out_m, out_v = [], [], []
+    for p, g, mm, vv in zip(W, G, m, v):
+        mm = b1 * mm + (1.0 - b1) * g
+        vv = b2 * vv + (1.0 - b2) * g * g
+        mh = mm / (1.0 - b1 ** t)
+        vh = vv / (1.0 - b2 ** t)
+        out_W.append(p - lr * mh / (np.sqrt(vh) + eps))
+        out_m.append(mm)
+        out_v.append(vv)
+    return out_W, out_m, out_v
+
+
+def init_weights(k_in: int, hidden: int, d: int, seed: int):
+    """He-style seeded initial weights (the random draws are inputs)."""
+    rng = np.random.default_rng(seed)
+    W1 = rng.standard_normal((k_in, hidden)) * np.sqrt(2.0 / k_in)
+    W2 = rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)
+    W3 = rng.standard_normal((hidden, d)) * np.sqrt(1.0 / hidden)
+    return [W1, W2, W3]

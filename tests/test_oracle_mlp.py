@@ -1,0 +1,92 @@
+"""Oracle pins for the per-node MLP smoother: hand-written gradients against
+central differences, positive homogeneity, closed forms, Adam's first step."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _case(seed, n=40, k=18, h=16, d=2):
+    rng = np.random.default_rng(seed)
+    W = mlp.init_weights(k, h, d, seed)
+    z = rng.standard_normal((n, k))
+    e = rng.standard_normal((n, d))
+    w = rng.random(n) + 0.5
+    return W, z, e, w
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_gradients_match_central_differences(seed):
+    W, z, e, w = _case(seed)
+    L, G = mlp.loss_and_grad(W, z, e, w)
+    rng = np.random.default_rng(seed + 10)
+    h = 1e-6
+    for li in range(3):
+        for _ in range(6):
+            i = rng.integers(W[li].shape[0])
+            j = rng.integers(W[li].shape[1])
+            Wp = [x.copy() for x in W]
+            Wm = [x.copy() for x in W]
+            Wp[li][i, j] += h
+            Wm[li][i, j] -= h
+            fd = (mlp.loss_and_grad(Wp, z, e, w)[0] - mlp.loss_and_grad(Wm, z, e, w)[0]) / (2 * h)
+            assert abs(fd - G[li][i, j]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_positive_homogeneity_and_zero_input():
+    W, z, e, w = _case(3)
+    y, _ = mlp.forward(W, z)
+    for a in (0.5, 3.0, 1e-3):
+        ya, _ = mlp.forward(W, a * z)
+        assert np.allclose(ya, a * y, rtol=1e-13, atol=1e-15)
+    y0, _ = mlp.forward(W, np.zeros_like(z))
+    assert not y0.any()
+
+
+def test_linear_regime_closed_form():
+    """All pre-activations positive: the network is the product W1 W2 W3."""
+    rng = np.random.default_rng(4)
+    W = [np.abs(rng.standard_normal((5, 4))), np.abs(rng.standard_normal((4, 4))), rng.standard_normal((4, 2))]
+    z = np.abs(rng.standard_normal((7, 5)))
+    y, _ = mlp.forward(W, z)
+    assert np.allclose(y, z @ W[0] @ W[1] @ W[2], rtol=1e-14)
+
+
+def test_adam_first_step_moves_by_lr_times_sign():
+    """At t = 1 the bias-corrected step is lr * g / (|g| + eps)."""
+    W = [np.ones((2, 3))]
+    G = [np.array([[1.0, -2.0, 0.5], [-1e-3, 3.0, -4.0]])]
+    m = [np.zeros((2, 3))]
+    v = [np.zeros((2, 3))]
+    W1, m1, v1 = mlp.adam_step(W, G, m, v, 1, lr=0.01)
+    assert np.allclose(W1[0], 1.0 - 0.01 * G[0] / (np.abs(G[0]) + 1e-8), rtol=1e-12)
+
+
+def test_stencil_inputs_layout():
+    v = np.arange(12.0).reshape(6, 2)
+    nbr = np.array([[0, 1, -1], [5, -1, 2]])
+    z = mlp.stencil_inputs(v, nbr)
+    assert z.tolist() == [[0, 1, 2, 3, 0, 0], [10, 11, 0, 0, 4, 5]]
+
+
+def test_bf16_rounding():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -9, -2.5, 3.14159265, 0.0])
+    r = mlp.round_bf16(x)
+    assert r[0] == 1.0 and r[1] == 1.0  # ties to even
+    assert r[2] == 1.0 + 2 ** -7
+    assert r[3] == -2.5 and r[5] == 0.0
+    assert abs(r[4] - 3.140625) < 1e-12
+
+
+def test_training_reduces_the_loss():
+    """A few Adam steps on a learnable target (the target is itself an MLP)."""
+    W_true, z, _, w = _case(5, n=200)
+    e, _ = mlp.forward(W_true, z)
+    W = mlp.init_weights(18, 16, 2, 99)
+    m = [np.zeros_like(x) for x in W]
+    v = [np.zeros_like(x) for x in W]
+    L0 = mlp.loss_and_grad(W, z, e, w)[0]
+    for t in range(1, 301):
+        L, G = mlp.loss_and_grad(W, z, e, w)
+        W, m, v = mlp.adam_step(W, G, m, v, t, lr=3e-3)
+    assert L < 0.2 * L0
