@@ -88,6 +88,8 @@ typedef struct {
   int64_t n_nodes;           /* number of lattice nodes                          */
   const double* coords;      /* n_nodes * dim node coordinates (rigid modes)     */
   const int32_t* dof_node;   /* N = n_m + n_s + n_f: node of every dof           */
+  const int32_t* node_ijk;   /* n_nodes * dim lattice indices (the learned
+                                smoother's 3^d stencils); may be NULL            */
 } fsi_layout;
 
 enum { FSI_P_F64 = 0, FSI_P_F32 = 1 };
@@ -117,7 +119,8 @@ typedef struct {
   /* with opts.timing: summed device time of each phase over the timed Arnoldi
    * steps (n_timed of them): P^{-1} v, the A_h product, Gram-Schmidt */
   double t_precond_ms, t_spmv_ms, t_gs_ms;
-  int32_t n_timed, pad2;
+  int32_t n_timed;
+  int32_t mlp_fallbacks;   /* learned pre-smoothing sweeps replaced by Jacobi     */
 } fsi_solve_info;
 
 /* Defaults for the option structs (tol 1e-8, m 50, maxit 2000, no timing;
@@ -195,6 +198,58 @@ fsi_status fsi_get_level(fsi_ctx* ctx, int which, int level, int what, int64_t* 
 /* Aggregate id of every node of level `level` (< nlev-1) of hierarchy `which`
  * (host int32 buffer of n_l / block_l entries; *count receives that number). */
 fsi_status fsi_get_aggregates(fsi_ctx* ctx, int which, int level, int32_t* agg, int64_t* count);
+
+/* ---- learned smoother ------------------------------------------------------
+ * A per-node MLP may replace the first damped-Jacobi sweep on the finest level
+ * of FSI_H_M (mesh motion) and FSI_H_SIG (solid Schur matrix).  For node i,
+ * z_i = (D^{-1} b) at the 3^d lattice nodes around i (d components each, 0 for
+ * absent neighbours, offsets in lexicographic order of (di, dj[, dk]) in
+ * {-1,0,1}^d), K = 3^d d inputs; delta_i = W3^T relu(W2^T relu(W1^T z_i)),
+ * W1: K x 64, W2: 64 x 64, W3: 64 x d, row-major FP32 at the ABI, stored and
+ * applied in BF16 with FP32 accumulation (matrix cores).  If the network's
+ * correction x gives ||b - A x|| > ||b|| the Jacobi sweep is used instead
+ * (counted in fsi_solve_info.mlp_fallbacks).  Requires layout.node_ijk.
+ * `which` is FSI_H_M or FSI_H_SIG. */
+typedef struct {
+  int32_t steps;        /* Adam steps (default 400)                               */
+  int32_t batch;        /* samples per step (default 16384)                       */
+  double lr;            /* Adam step size (default 1e-3)                          */
+  double exact_tol;     /* relative residual of the exact corrections (1e-10)     */
+  int32_t exact_maxit;  /* V-cycle iterations allowed for them (default 300)      */
+  uint32_t seed;        /* sample shuffling                                       */
+} fsi_mlp_train_opts;
+
+typedef struct {
+  int32_t vectors[2];   /* recorded residuals used (H_M, H_SIG)                   */
+  int64_t samples[2];   /* node samples                                           */
+  double loss_first[2], loss_last[2];  /* mean weighted loss, first / last step   */
+} fsi_mlp_train_info;
+
+void fsi_default_mlp_train_opts(fsi_mlp_train_opts* o);
+/* Set the network weights (host FP32, shapes above); resets the optimiser
+ * state; does not enable the network. */
+fsi_status fsi_mlp_set_weights(fsi_ctx* ctx, int which, const float* W1, const float* W2, const float* W3);
+/* Current (FP32 master) weights into host buffers of the shapes above. */
+fsi_status fsi_mlp_get_weights(fsi_ctx* ctx, int which, float* W1, float* W2, float* W3);
+/* Use (1) or stop using (0) the network in the V-cycles. */
+fsi_status fsi_mlp_enable(fsi_ctx* ctx, int which, int enable);
+/* x = network correction for the residual b of hierarchy `which`'s finest
+ * level (device FP64 vectors of that level's size). */
+fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x);
+/* One pass of the training kernels over m samples (host FP32: Z m x K, E m x d,
+ * w m): loss = (1/m) sum w ||delta - e||^2 and its gradients G1, G2, G3 (host,
+ * shapes of W1, W2, W3). */
+fsi_status fsi_mlp_loss_grad(fsi_ctx* ctx, int which, int64_t m, const float* Z, const float* E, const float* w,
+                             float* G1, float* G2, float* G3, double* loss);
+/* Record the finest-level inputs of the FSI_H_M and FSI_H_SIG V-cycles during
+ * the following solves (every `every`-th cycle, at most max_vectors each);
+ * max_vectors = 0 stops recording and drops the records. */
+fsi_status fsi_mlp_collect(fsi_ctx* ctx, int max_vectors, int every);
+/* Train both networks on the recorded residuals: exact corrections by
+ * V-cycle iteration to opts.exact_tol, then Adam on the node samples (on the
+ * device); enables the trained networks.  Needs weights set first (the
+ * initial weights are an input).  opts/info may be NULL. */
+fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_train_info* info);
 
 #ifdef __cplusplus
 }

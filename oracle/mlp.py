@@ -12,7 +12,8 @@ network has three bias-free layers with ReLU between them,
 so it is positively homogeneous (delta(a z) = a delta(z), a > 0) and needs
 no input normalisation.  Training minimises the diagonal-weighted squared
 error L = (1/n) sum_i w_i ||delta_i - e_i||^2 against exact corrections e,
-with Adam (beta = 0.9, 0.999, eps = 1e-8).
+with Adam (beta = 0.9, 0.999, eps = 1e-8).  If the network's correction
+would increase the residual norm the damped-Jacobi sweep is used instead.
 
 Every function is plain FP64 numpy.  ``round_bf16`` reproduces the storage
 precision of the GPU path (round to nearest even to 8 significant bits) so
@@ -108,3 +109,23 @@ def init_weights(k_in: int, hidden: int, d: int, seed: int):
     W2 = rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)
     W3 = rng.standard_normal((hidden, d)) * np.sqrt(1.0 / hidden)
     return [W1, W2, W3]
+
+
+def learned_vcycle(H, B: np.ndarray, X0: np.ndarray) -> np.ndarray:
+    """V(1,1) cycle of an AMG hierarchy on the columns of B (n x c) whose
+    first pre-smoothing sweep on the finest level is the network's correction
+    X0 instead of damped Jacobi.  If X0 does not reduce the residual,
+    ||B - A X0||_F > ||B||_F (or is not finite), the plain cycle is used.
+    With X0 = omega D^{-1} B this is exactly the plain V(1,1) cycle."""
+    from . import amg
+    L = H.levels[0]
+    B = np.asarray(B, dtype=np.float64).reshape(L.A.shape[0], -1)
+    R0 = B - L.A @ X0 if np.all(np.isfinite(X0)) else None
+    if R0 is None or not np.linalg.norm(R0) <= np.linalg.norm(B):
+        return np.column_stack([amg.vcycle(H, B[:, c]) for c in range(B.shape[1])])
+    if H.nlevels == 1:
+        raise ValueError("a learned pre-smoother needs at least two levels")
+    Bc = L.R @ R0
+    E = np.column_stack([amg.vcycle(H, Bc[:, c], 1) for c in range(B.shape[1])])
+    X = X0 + L.P @ E
+    return X + L.omega * (L.dinv[:, None] * (B - L.A @ X))

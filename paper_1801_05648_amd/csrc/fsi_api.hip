@@ -21,6 +21,7 @@
 #include <memory>
 #include <type_traits>
 #include <new>
+#include <random>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -28,6 +29,7 @@
 #include "../../include/fsi.h"
 #include "host_csr.hpp"
 #include "kernels.hpp"
+#include "mlp.hpp"
 #include "sa_setup.hpp"
 
 namespace fsi {
@@ -167,9 +169,31 @@ void vsub(int64_t n, T* y, const T* x, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------- AMG on device
+// Device view of the learned pre-smoother of a hierarchy's finest level.
+struct MlpUse {
+  bool enabled = false;
+  int d = 2;
+  bool per_dof = false;  // inverse diagonal per dof (block operator) or per node (L (x) I_d)
+  int64_t n_nodes = 0;
+  const int32_t* nbr = nullptr;
+  MlpW w{};
+  double* npart = nullptr;
+  int* flag = nullptr;
+  int* fallbacks = nullptr;
+};
+
+// Recording of finest-level V-cycle inputs (training data of the smoother).
+struct MlpRecord {
+  bool active = false;
+  int max_vectors = 0, every = 1;
+  long calls = 0;
+  std::vector<std::shared_ptr<DevBuf>> vecs;  // FP64 copies
+};
+
 template <typename T>
 struct DLevel {
   DCsr<T> AD, Q, P, AP;  // A D^{-1}, Q = R (I - omega A D^{-1}), prolongator, A P
+  DCsr<T> A0, R0;        // finest level with a learned smoother: A and R themselves
   std::shared_ptr<DevBuf> dinv, y, r, b;
   T omega = T(0);
   int64_t n = 0;
@@ -183,10 +207,13 @@ struct DHier {
   std::shared_ptr<DevBuf> cinv;
   int64_t nc = 0;
   double bytes_per_cycle = 0.0;  // algorithmic bytes of one cycle as executed
+  MlpUse* mlp = nullptr;         // learned pre-smoother of level 0 (if any)
+  MlpRecord* rec = nullptr;      // recording of level-0 inputs (if any)
+  std::shared_ptr<DevBuf> xm, rm;  // its correction and residual
 };
 
 template <typename T>
-DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s) {
+DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false) {
   DHier<T> D;
   D.nv = nv;
   const int L = int(H.levels.size()) - 1;
@@ -210,6 +237,14 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s) {
       d.P = upload<T>(h.P, s);
       d.AP = upload<T>(AP, s);
       d.dinv = upload_vec<T>(h.dinv, s);
+      if (l == 0 && keep_a0) {
+        d.A0 = upload<T>(h.A, s);
+        d.R0 = upload<T>(h.R, s);
+        D.xm = std::make_shared<DevBuf>();
+        D.xm->alloc(sizeof(T) * d.n * nv);
+        D.rm = std::make_shared<DevBuf>();
+        D.rm->alloc(sizeof(T) * d.n * nv);
+      }
       d.gdown = pick_group(d.AD.nnz, d.AD.nrows);
       d.gdownq = pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16;
       d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1));
@@ -234,10 +269,34 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s) {
   return D;
 }
 
-// One V(1,1) cycle from level l: two launches per level (down, up) and a
-// dense product with the coarsest inverse.
+// Learned pre-smoothing of level 0: x_m = MLP(stencil(D^{-1} b)),
+// r_m = b - A x_m, and the device-side choice between x_m and the Jacobi
+// sweep (flag), counted when falling back.
 template <typename T, int NV>
-void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s) {
+void mlp_presmooth(DHier<T>& H, const T* b, hipStream_t s) {
+  MlpUse& u = *H.mlp;
+  DLevel<T>& d0 = H.lev[0];
+  T* xm = H.xm->template as<T>();
+  T* rm = H.rm->template as<T>();
+  const T* dinv = d0.dinv->template as<T>();
+  const unsigned grid = grid_for(u.n_nodes, 64);
+  if (u.d == 2) {
+    if (u.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
+    else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
+  } else {
+    if (u.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
+    else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
+  }
+  launch_rows<T, NV>(d0.A0, GatherPlain<T, NV>{xm}, EpiSub<T, NV>{b, rm}, s);
+  norm_pair_partial_kernel<T><<<kNormBlocks, 256, 0, s>>>(d0.n * NV, rm, b, u.npart);
+  mlp_flag_kernel<<<1, 64, 0, s>>>(kNormBlocks, u.npart, u.flag, u.fallbacks);
+}
+
+// One V(1,1) cycle from level l: two launches per level (down, up) and a
+// dense product with the coarsest inverse.  `plain` disables the learned
+// pre-smoother (used for the exact corrections it is trained on).
+template <typename T, int NV>
+void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plain = false) {
   const int L = int(H.lev.size()) - 1;
   if (l == L) {
     const int64_t n = H.nc;
@@ -246,6 +305,8 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s) {
   }
   DLevel<T>& d = H.lev[l];
   DLevel<T>& c = H.lev[l + 1];
+  const bool learned = l == 0 && !plain && H.mlp && H.mlp->enabled && H.xm;
+  if (learned) mlp_presmooth<T, NV>(H, b, s);
   const T* dinv = d.dinv->template as<T>();
   T* r = d.r->template as<T>();
   T* bc = c.b->template as<T>();
@@ -255,29 +316,52 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s) {
     auto go = [&](auto gq) {
       constexpr int GQ = decltype(gq)::value;
       const unsigned nq = grid_for(d.Q.nrows, kBlock / GQ);
-      vdown_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
-                                                              d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
-                                                              d.omega, r, bc, na);
+      if (learned)
+        vdown_sel_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(
+            d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
+            d.R0.drp(), d.R0.dci(), d.R0.dval(), b, d.omega, r, bc, H.rm->template as<T>(), H.mlp->flag, na);
+      else
+        vdown_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
+                                                                d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
+                                                                d.omega, r, bc, na);
     };
     if (d.gdownq == 64) go(std::integral_constant<int, 64>{});
     else go(std::integral_constant<int, 16>{});
   });
   T* e = c.y->template as<T>();
-  vcycle_rec<T, NV>(H, l + 1, bc, e, s);
+  vcycle_rec<T, NV>(H, l + 1, bc, e, s, plain);
   with_group(d.gup, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
-    vup_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(d.n, d.P.drp(), d.P.dci(), d.P.dval(),
-                                                                      d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b,
-                                                                      dinv, d.omega, r, out);
+    if (learned)
+      vup_sel_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(
+          d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b, dinv, d.omega, r,
+          H.xm->template as<T>(), H.rm->template as<T>(), H.mlp->flag, out);
+    else
+      vup_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(d.n, d.P.drp(), d.P.dci(), d.P.dval(),
+                                                                        d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b,
+                                                                        dinv, d.omega, r, out);
   });
 }
 
+// Record the input of this cycle (every `every`-th call) for training.
 template <typename T>
-void vcycle(DHier<T>& H, const T* b, T* out, hipStream_t s) {
+void record_input(DHier<T>& H, const T* b, hipStream_t s) {
+  MlpRecord& R = *H.rec;
+  if (++R.calls % R.every != 0 || int(R.vecs.size()) >= R.max_vectors) return;
+  const int64_t n = H.lev[0].n * H.nv;
+  auto v = std::make_shared<DevBuf>();
+  v->alloc(sizeof(double) * n);
+  cast_kernel<T, double><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, b, v->as<double>());
+  R.vecs.push_back(v);
+}
+
+template <typename T>
+void vcycle(DHier<T>& H, const T* b, T* out, hipStream_t s, bool plain = false) {
+  if (H.rec && H.rec->active && !plain) record_input(H, b, s);
   switch (H.nv) {
-    case 1: vcycle_rec<T, 1>(H, 0, b, out, s); break;
-    case 2: vcycle_rec<T, 2>(H, 0, b, out, s); break;
-    default: vcycle_rec<T, 3>(H, 0, b, out, s); break;
+    case 1: vcycle_rec<T, 1>(H, 0, b, out, s, plain); break;
+    case 2: vcycle_rec<T, 2>(H, 0, b, out, s, plain); break;
+    default: vcycle_rec<T, 3>(H, 0, b, out, s, plain); break;
   }
 }
 
@@ -353,6 +437,25 @@ struct Precond {
 
 using namespace fsi;
 
+// Learned smoother of one hierarchy (index 0: H_M, 1: H_SIG): weights,
+// optimiser state, stencil table, training samples and recording.  It
+// survives fsi_setup_blocks / fsi_build_precond (a trained network is reused
+// on the next Newton systems of the same lattice).
+struct MlpState {
+  bool have_weights = false;
+  int d = 0;
+  int64_t n_nodes = 0;
+  MlpUse use;
+  MlpRecord rec;
+  std::vector<float> wnode;  // node weights of the loss (mean diagonal / operator mean)
+  DevBuf nbr, npart, flag, fallbacks;
+  DevBuf wm, m1, m2, g, loss, w1t, w2t, w2, w3t, w3, part, part_loss;
+  int adam_t = 0;
+  int nparam() const { return d == 2 ? MlpDims<2>::NPARAM : MlpDims<3>::NPARAM; }
+  int kp() const { return d == 2 ? MlpDims<2>::KP : MlpDims<3>::KP; }
+  int kin() const { return d == 2 ? MlpDims<2>::KIN : MlpDims<3>::KIN; }
+};
+
 // ------------------------------------------------------------------ context
 struct fsi_ctx {
   int device = 0;
@@ -365,7 +468,9 @@ struct fsi_ctx {
   double dt_theta = 0.0;
   std::vector<double> coords;
   std::vector<int32_t> dof_node;
+  std::vector<int32_t> node_ijk;  // empty: no lattice, no learned smoother
   HCsr blk[FSI_NBLK];
+  MlpState mlp[2];
   DCsr<double> Ah;
   // preconditioner
   int precision = FSI_P_F64;
@@ -471,6 +576,18 @@ std::vector<double> rigid_modes(const fsi_ctx& c, int& k) {
   return B;
 }
 
+// Point the finest levels of H_M and H_SIG at their learned smoothers (or at
+// none when the hierarchy has a single level).
+template <typename T>
+void link_mlp(fsi_ctx& c, Precond<T>& P) {
+  for (int i = 0; i < 2; ++i) {
+    DHier<T>& H = P.H[i == 0 ? FSI_H_M : FSI_H_SIG];
+    const bool ok = H.xm && c.mlp[i].n_nodes > 0;
+    H.mlp = ok ? &c.mlp[i].use : nullptr;
+    H.rec = ok ? &c.mlp[i].rec : nullptr;
+  }
+}
+
 template <typename T>
 std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   auto P = std::make_unique<Precond<T>>();
@@ -478,8 +595,11 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   P->d = c.d;
   P->n_m = c.n_m; P->n_s = c.n_s; P->n_f = c.n_f; P->n_vs = c.n_vs; P->n_vf = c.n_vf;
   P->n_p = c.n_p; P->N = c.N;
-  for (int h = 0; h < FSI_NHIER; ++h)
-    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s);
+  for (int h = 0; h < FSI_NHIER; ++h) {
+    const bool learned_capable = !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG);
+    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable);
+  }
+  link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.blk[FSI_F];
   P->S_vu = upload<T>(sub_block(S, 0, c.n_vs, c.n_vs, c.n_s), s);
@@ -575,6 +695,10 @@ void givens(double a, double b, double& cs, double& sn) {
 // meets the stopping test the speculative iteration j+1 is simply discarded.
 fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_opts& o, fsi_solve_info& info) {
   hipStream_t s = c.stream;
+  for (auto& M : c.mlp)
+    if (M.fallbacks.p) HIP_TRY(hipMemsetAsync(M.fallbacks.p, 0, sizeof(int), s));
+  const bool recording = c.mlp[0].rec.active || c.mlp[1].rec.active;
+  const bool graphs = c.use_graphs && !recording;  // recording copies vectors from the host side
   const int64_t N = c.N;
   const int m = o.restart;
   ensure_krylov(c, m);
@@ -658,14 +782,14 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   // launched on its own between the two graphs of the step
   auto launch_step = [&](int j) {
     hipEvent_t* te = c.tev[j % 2];
-    if (c.use_graphs && !timing) {
+    if (graphs && !timing) {
       capture(c.step_graph[j], [&](hipStream_t st) {
         record_pre(j, st);
         record_spmv(j, st);
         record_gs(j, st);
       });
       HIP_TRY(hipGraphLaunch(c.step_graph[j], s));
-    } else if (c.use_graphs) {
+    } else if (graphs) {
       capture(c.pre_graph[j], [&](hipStream_t st) { record_pre(j, st); });
       capture(c.gs_graph[j], [&](hipStream_t st) { record_gs(j, st); });
       HIP_TRY(hipEventRecord(te[0], s));
@@ -761,6 +885,13 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   info.iters = iters;
+  info.mlp_fallbacks = 0;
+  for (auto& M : c.mlp)
+    if (M.fallbacks.p) {
+      int fb = 0;
+      HIP_TRY(hipMemcpy(&fb, M.fallbacks.p, sizeof(int), hipMemcpyDeviceToHost));
+      info.mlp_fallbacks += fb;
+    }
   info.t_precond_ms = t_pre;
   info.t_spmv_ms = t_spmv;
   info.t_gs_ms = t_gs;
@@ -770,6 +901,366 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   info.true_rel_resid = rel;
   info.t_total_ms = ms;
   return converged ? FSI_OK : FSI_NOT_CONVERGED;
+}
+
+// ------------------------------------------------------- learned smoother
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u);
+  return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Stencil tables of the finest levels of H_M (nodes = rows of L) and H_SIG
+// (nodes = solid velocity nodes): for every node the operator index of its 3^d
+// lattice neighbours (lexicographic offsets in {-1,0,1}^d), -1 where absent.
+void prepare_mlp(fsi_ctx& c) {
+  for (int i = 0; i < 2; ++i) {
+    MlpState& M = c.mlp[i];
+    const int h = i == 0 ? FSI_H_M : FSI_H_SIG;
+    const SaHierarchy& HH = c.host_h[h];
+    const int d = c.d;
+    if (c.node_ijk.empty() || HH.levels.size() < 2) {
+      M.n_nodes = 0;
+      M.use.n_nodes = 0;
+      M.use.enabled = false;
+      continue;
+    }
+    const int64_t n_nodes = i == 0 ? c.n_m / d : c.n_vs / d;
+    if (M.d != d) {
+      M.have_weights = false;
+      M.adam_t = 0;
+      M.use.enabled = false;
+    }
+    if (M.n_nodes != n_nodes || M.d != d) M.rec.vecs.clear();
+    M.d = d;
+    M.n_nodes = n_nodes;
+    const int S = d == 2 ? 9 : 27;
+    const int64_t total = int64_t(c.node_ijk.size()) / d;
+    std::vector<int32_t> gnode(n_nodes), opnode(total, -1);
+    for (int64_t k = 0; k < n_nodes; ++k) {
+      gnode[k] = c.dof_node[(i == 0 ? 0 : c.n_m) + k * d];
+      opnode[gnode[k]] = int32_t(k);
+    }
+    int64_t ext[3] = {1, 1, 1};
+    for (int64_t g = 0; g < total; ++g)
+      for (int a = 0; a < d; ++a) ext[a] = std::max<int64_t>(ext[a], c.node_ijk[g * d + a] + 1);
+    std::vector<int32_t> lat(size_t(ext[0] * ext[1] * ext[2]), -1);
+    auto lidx = [&](const int* I) { return (int64_t(I[0]) * ext[1] + I[1]) * ext[2] + (d == 3 ? I[2] : 0); };
+    for (int64_t g = 0; g < total; ++g) {
+      int I[3] = {0, 0, 0};
+      for (int a = 0; a < d; ++a) I[a] = c.node_ijk[g * d + a];
+      lat[lidx(I)] = int32_t(g);
+    }
+    std::vector<int32_t> nbr(size_t(n_nodes) * S, -1);
+    for (int64_t k = 0; k < n_nodes; ++k) {
+      for (int sidx = 0; sidx < S; ++sidx) {
+        int off[3] = {0, 0, 0}, r = sidx;
+        for (int a = d - 1; a >= 0; --a) { off[a] = r % 3 - 1; r /= 3; }
+        int I[3] = {0, 0, 0};
+        bool inside = true;
+        for (int a = 0; a < d; ++a) {
+          I[a] = c.node_ijk[int64_t(gnode[k]) * d + a] + off[a];
+          inside = inside && I[a] >= 0 && I[a] < ext[a];
+        }
+        if (!inside) continue;
+        const int32_t g2 = lat[lidx(I)];
+        if (g2 >= 0) nbr[k * S + sidx] = opnode[g2];
+      }
+    }
+    // loss weights: the node's mean diagonal entry relative to the mean
+    const std::vector<double>& dv = HH.levels[0].dinv;
+    M.wnode.assign(n_nodes, 0.f);
+    double mean = 0.0;
+    std::vector<double> dn(n_nodes);
+    for (int64_t k = 0; k < n_nodes; ++k) {
+      double a = 0.0;
+      if (i == 0) a = 1.0 / dv[k];
+      else {
+        for (int q = 0; q < d; ++q) a += 1.0 / dv[k * d + q];
+        a /= d;
+      }
+      dn[k] = a;
+      mean += a;
+    }
+    mean /= double(n_nodes);
+    for (int64_t k = 0; k < n_nodes; ++k) M.wnode[k] = float(dn[k] / mean);
+    M.nbr.alloc(sizeof(int32_t) * nbr.size());
+    HIP_TRY(hipMemcpyAsync(M.nbr.p, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice, c.stream));
+    if (!M.npart.p) M.npart.alloc(sizeof(double) * 2 * kNormBlocks);
+    if (!M.flag.p) M.flag.alloc(sizeof(int));
+    if (!M.fallbacks.p) {
+      M.fallbacks.alloc(sizeof(int));
+      HIP_TRY(hipMemsetAsync(M.fallbacks.p, 0, sizeof(int), c.stream));
+    }
+    const size_t np = size_t(M.nparam());
+    if (M.wm.bytes != sizeof(float) * np) {
+      for (DevBuf* b : {&M.wm, &M.m1, &M.m2, &M.g}) {
+        b->alloc(sizeof(float) * np);
+        HIP_TRY(hipMemsetAsync(b->p, 0, sizeof(float) * np, c.stream));
+      }
+      M.loss.alloc(sizeof(float));
+      const int kp = M.kp();
+      M.w1t.alloc(2 * 64 * kp);
+      M.w2t.alloc(2 * 64 * 64);
+      M.w2.alloc(2 * 64 * 64);
+      M.w3t.alloc(2 * 16 * 64);
+      M.w3.alloc(2 * 64 * 16);
+      for (DevBuf* b : {&M.w1t, &M.w2t, &M.w2, &M.w3t, &M.w3}) HIP_TRY(hipMemsetAsync(b->p, 0, b->bytes, c.stream));
+      M.have_weights = false;
+      M.use.enabled = false;
+    }
+    M.use.d = d;
+    M.use.per_dof = i == 1;
+    M.use.n_nodes = n_nodes;
+    M.use.nbr = M.nbr.as<int32_t>();
+    M.use.w = MlpW{M.w1t.as<unsigned short>(), M.w2t.as<unsigned short>(), M.w2.as<unsigned short>(),
+                   M.w3t.as<unsigned short>(), M.w3.as<unsigned short>()};
+    M.use.npart = M.npart.as<double>();
+    M.use.flag = M.flag.as<int>();
+    M.use.fallbacks = M.fallbacks.as<int>();
+  }
+  HIP_TRY(hipStreamSynchronize(c.stream));
+}
+
+MlpState& mlp_state(fsi_ctx& c, int which) {
+  if (which != FSI_H_M && which != FSI_H_SIG) throw Error(FSI_ERR_ARG, "which must be FSI_H_M or FSI_H_SIG");
+  if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+  MlpState& M = c.mlp[which == FSI_H_M ? 0 : 1];
+  if (M.n_nodes == 0)
+    throw Error(FSI_ERR_STATE, "no learned smoother here: needs layout.node_ijk and at least two AMG levels");
+  return M;
+}
+
+// Master FP32 weights (padded layouts [k][hid], [in][out], [hid][16]) from
+// natural FP32 W1 (K x 64), W2 (64 x 64), W3 (64 x d), and their BF16 copies.
+void mlp_upload_weights(fsi_ctx& c, MlpState& M, const float* W1, const float* W2, const float* W3) {
+  const int kp = M.kp(), kin = M.kin(), d = M.d, H = 64, NP = 16;
+  std::vector<float> wm(size_t(M.nparam()), 0.f);
+  std::vector<uint16_t> w1t(size_t(H) * kp, 0), w2t(H * H, 0), w2(H * H, 0), w3t(NP * H, 0), w3(H * NP, 0);
+  for (int k = 0; k < kin; ++k)
+    for (int h = 0; h < H; ++h) {
+      wm[size_t(k) * H + h] = W1[k * H + h];
+      w1t[size_t(h) * kp + k] = host_bf16(W1[k * H + h]);
+    }
+  float* m2 = wm.data() + size_t(kp) * H;
+  for (int a = 0; a < H; ++a)
+    for (int b = 0; b < H; ++b) {
+      m2[a * H + b] = W2[a * H + b];
+      w2[a * H + b] = host_bf16(W2[a * H + b]);
+      w2t[b * H + a] = host_bf16(W2[a * H + b]);
+    }
+  float* m3 = m2 + H * H;
+  for (int h = 0; h < H; ++h)
+    for (int q = 0; q < d; ++q) {
+      m3[h * NP + q] = W3[h * d + q];
+      w3[h * NP + q] = host_bf16(W3[h * d + q]);
+      w3t[q * H + h] = host_bf16(W3[h * d + q]);
+    }
+  hipStream_t s = c.stream;
+  HIP_TRY(hipMemcpyAsync(M.wm.p, wm.data(), sizeof(float) * wm.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemsetAsync(M.m1.p, 0, M.m1.bytes, s));
+  HIP_TRY(hipMemsetAsync(M.m2.p, 0, M.m2.bytes, s));
+  HIP_TRY(hipMemcpyAsync(M.w1t.p, w1t.data(), 2 * w1t.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(M.w2t.p, w2t.data(), 2 * w2t.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(M.w2.p, w2.data(), 2 * w2.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(M.w3t.p, w3t.data(), 2 * w3t.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipMemcpyAsync(M.w3.p, w3.data(), 2 * w3.size(), hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  M.adam_t = 0;
+  M.have_weights = true;
+}
+
+// One gradient pass over m samples already on the device (Z [m][KP] BF16,
+// E [m][d], W [m]) starting at `first`: gradient into M.g, loss sum into M.loss.
+void mlp_grad_pass(fsi_ctx& c, MlpState& M, const unsigned short* Z, const float* E, const float* W, int64_t first,
+                   int64_t m, float coef) {
+  hipStream_t s = c.stream;
+  const int tpw = 4;
+  const int64_t tiles = (m + 15) / 16;
+  const int64_t waves = (tiles + tpw - 1) / tpw;
+  const int64_t blocks = (waves + 3) / 4;
+  const int64_t nwv = blocks * 4;
+  const size_t need = sizeof(float) * size_t(nwv) * M.nparam();
+  if (M.part.bytes < need) M.part.alloc(need);
+  if (M.part_loss.bytes < sizeof(float) * nwv) M.part_loss.alloc(sizeof(float) * nwv);
+  const MlpW& w = M.use.w;
+  if (M.d == 2)
+    mlp_train_kernel<2><<<unsigned(blocks), 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, M.part.as<float>(),
+                                                          M.part_loss.as<float>());
+  else
+    mlp_train_kernel<3><<<unsigned(blocks), 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, M.part.as<float>(),
+                                                          M.part_loss.as<float>());
+  mlp_grad_reduce_kernel<<<unsigned((M.nparam() + 255) / 256), 256, 0, s>>>(
+      int(nwv), M.nparam(), M.part.as<float>(), M.part_loss.as<float>(), M.g.as<float>(), M.loss.as<float>());
+}
+
+void mlp_adam(fsi_ctx& c, MlpState& M, float lr) {
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  ++M.adam_t;
+  const float bc1 = 1.f - std::pow(b1, float(M.adam_t)), bc2 = 1.f - std::pow(b2, float(M.adam_t));
+  const unsigned grid = unsigned((M.nparam() + 255) / 256);
+  auto u16 = [](DevBuf& b) { return b.as<unsigned short>(); };
+  if (M.d == 2)
+    mlp_adam_kernel<2><<<grid, 256, 0, c.stream>>>(M.wm.as<float>(), M.m1.as<float>(), M.m2.as<float>(),
+                                                   M.g.as<float>(), lr, b1, b2, eps, bc1, bc2, u16(M.w1t),
+                                                   u16(M.w2t), u16(M.w2), u16(M.w3t), u16(M.w3));
+  else
+    mlp_adam_kernel<3><<<grid, 256, 0, c.stream>>>(M.wm.as<float>(), M.m1.as<float>(), M.m2.as<float>(),
+                                                   M.g.as<float>(), lr, b1, b2, eps, bc1, bc2, u16(M.w1t),
+                                                   u16(M.w2t), u16(M.w2), u16(M.w3t), u16(M.w3));
+}
+
+// Exact correction e = A0^{-1} b of a recorded residual by iterating plain
+// V-cycles (e += V(b - A0 e)) to a relative residual tol; false if it does
+// not get there within maxit cycles.
+template <typename T, int NV>
+bool exact_correction(fsi_ctx& c, DHier<T>& H, const double* b, double* e, double tol, int maxit) {
+  hipStream_t s = c.stream;
+  DLevel<T>& d0 = H.lev[0];
+  const int64_t n = d0.n * NV;
+  DevBuf bt, et, rt, ct, np;
+  bt.alloc(sizeof(T) * n);
+  et.alloc(sizeof(T) * n);
+  rt.alloc(sizeof(T) * n);
+  ct.alloc(sizeof(T) * n);
+  np.alloc(sizeof(double) * 2 * kNormBlocks);
+  const unsigned g = grid_for(n, kBlock * 4);
+  cast_kernel<double, T><<<g, kBlock, 0, s>>>(n, b, bt.as<T>());
+  HIP_TRY(hipMemsetAsync(et.p, 0, sizeof(T) * n, s));
+  HIP_TRY(hipMemcpyAsync(rt.p, bt.p, sizeof(T) * n, hipMemcpyDeviceToDevice, s));
+  std::vector<double> hpart(2 * kNormBlocks);
+  bool ok = false;
+  for (int it = 1; it <= maxit; ++it) {
+    vcycle_rec<T, NV>(H, 0, rt.as<T>(), ct.as<T>(), s, true);
+    vadd_kernel<T><<<g, kBlock, 0, s>>>(n, et.as<T>(), ct.as<T>());  // e += V(r)
+    launch_rows<T, NV>(d0.A0, GatherPlain<T, NV>{et.as<T>()}, EpiSub<T, NV>{bt.as<T>(), rt.as<T>()}, s);
+    if (it % 5 == 0 || it == maxit) {
+      norm_pair_partial_kernel<T><<<kNormBlocks, 256, 0, s>>>(n, rt.as<T>(), bt.as<T>(), np.as<double>());
+      HIP_TRY(hipMemcpyAsync(hpart.data(), np.p, sizeof(double) * hpart.size(), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double rr = 0.0, bb = 0.0;
+      for (int k = 0; k < kNormBlocks; ++k) {
+        rr += hpart[2 * k];
+        bb += hpart[2 * k + 1];
+      }
+      if (!(rr <= 1e6 * bb)) break;  // diverging or NaN
+      if (std::sqrt(rr) <= tol * std::sqrt(bb)) {
+        ok = true;
+        break;
+      }
+    }
+  }
+  cast_kernel<T, double><<<g, kBlock, 0, s>>>(n, et.as<T>(), e);
+  HIP_TRY(hipStreamSynchronize(s));
+  return ok;
+}
+
+template <typename T>
+void mlp_samples(const MlpState& M, const T* b, const T* dinv, const double* e, const float* wn, float scale,
+                 unsigned short* Z, float* E, float* W, hipStream_t s) {
+  const unsigned g = grid_for(M.n_nodes, 256);
+  const int32_t* nbr = M.nbr.as<int32_t>();
+  if (M.d == 2) {
+    if (M.use.per_dof) mlp_samples_kernel<2, true, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, e, wn, scale, Z, E, W);
+    else mlp_samples_kernel<2, false, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, e, wn, scale, Z, E, W);
+  } else {
+    if (M.use.per_dof) mlp_samples_kernel<3, true, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, e, wn, scale, Z, E, W);
+    else mlp_samples_kernel<3, false, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, e, wn, scale, Z, E, W);
+  }
+}
+
+// Train the learned smoothers on the recorded finest-level residuals.
+template <typename T>
+void mlp_train_impl(fsi_ctx& c, Precond<T>& P, const fsi_mlp_train_opts& o, fsi_mlp_train_info& info) {
+  hipStream_t s = c.stream;
+  for (int i = 0; i < 2; ++i) {
+    MlpState& M = c.mlp[i];
+    info.vectors[i] = 0;
+    info.samples[i] = 0;
+    info.loss_first[i] = info.loss_last[i] = 0.0;
+    if (M.n_nodes == 0 || !M.have_weights || M.rec.vecs.empty()) continue;
+    const int h = i == 0 ? FSI_H_M : FSI_H_SIG;
+    DHier<T>& H = P.H[h];
+    if (!H.xm) continue;
+    const int d = M.d, kp = M.kp();
+    const int64_t n_dof = M.n_nodes * d;
+    const int64_t maxm = int64_t(M.rec.vecs.size()) * M.n_nodes;
+    DevBuf Z, E, W, Z2, E2, W2, e, wn, bt, perm;
+    Z.alloc(2 * size_t(maxm) * kp);
+    E.alloc(4 * size_t(maxm) * d);
+    W.alloc(4 * size_t(maxm));
+    e.alloc(8 * size_t(n_dof));
+    bt.alloc(sizeof(T) * size_t(n_dof));
+    wn.alloc(4 * size_t(M.n_nodes));
+    HIP_TRY(hipMemcpyAsync(wn.p, M.wnode.data(), 4 * M.wnode.size(), hipMemcpyHostToDevice, s));
+    const std::vector<double>& dv = c.host_h[h].levels[0].dinv;
+    const T* dinv = H.lev[0].dinv->template as<T>();
+    std::vector<double> hb(n_dof);
+    int64_t m = 0;
+    for (auto& v : M.rec.vecs) {
+      HIP_TRY(hipMemcpyAsync(hb.data(), v->p, 8 * size_t(n_dof), hipMemcpyDeviceToHost, s));
+      HIP_TRY(hipStreamSynchronize(s));
+      double ss = 0.0;
+      for (int64_t k = 0; k < n_dof; ++k) {
+        const double z = (i == 0 ? dv[k / d] : dv[k]) * hb[k];
+        ss += z * z;
+      }
+      const double rms = std::sqrt(ss / double(n_dof));
+      if (!(rms > 0.0) || !std::isfinite(rms)) continue;
+      bool ok;
+      if (H.nv == 1) ok = exact_correction<T, 1>(c, H, v->as<double>(), e.as<double>(), o.exact_tol, o.exact_maxit);
+      else if (H.nv == 2) ok = exact_correction<T, 2>(c, H, v->as<double>(), e.as<double>(), o.exact_tol, o.exact_maxit);
+      else ok = exact_correction<T, 3>(c, H, v->as<double>(), e.as<double>(), o.exact_tol, o.exact_maxit);
+      if (!ok) continue;
+      cast_kernel<double, T><<<grid_for(n_dof, kBlock * 4), kBlock, 0, s>>>(n_dof, v->as<double>(), bt.as<T>());
+      mlp_samples<T>(M, bt.as<T>(), dinv, e.as<double>(), wn.as<float>(), float(1.0 / rms),
+                     Z.as<unsigned short>() + size_t(m) * kp, E.as<float>() + size_t(m) * d, W.as<float>() + m, s);
+      m += M.n_nodes;
+      ++info.vectors[i];
+    }
+    info.samples[i] = m;
+    if (m == 0) continue;
+    // seeded shuffle of the node samples
+    std::vector<int64_t> pm(m);
+    for (int64_t k = 0; k < m; ++k) pm[k] = k;
+    std::mt19937_64 rng(uint64_t(o.seed) * 2 + uint64_t(i));
+    for (int64_t k = m - 1; k > 0; --k) std::swap(pm[k], pm[int64_t(rng() % uint64_t(k + 1))]);
+    perm.alloc(8 * size_t(m));
+    Z2.alloc(2 * size_t(m) * kp);
+    E2.alloc(4 * size_t(m) * d);
+    W2.alloc(4 * size_t(m));
+    HIP_TRY(hipMemcpyAsync(perm.p, pm.data(), 8 * size_t(m), hipMemcpyHostToDevice, s));
+    if (d == 2)
+      mlp_gather_samples_kernel<MlpDims<2>::KP, 2><<<grid_for(m, 256), 256, 0, s>>>(
+          m, perm.as<int64_t>(), Z.as<unsigned short>(), E.as<float>(), W.as<float>(), Z2.as<unsigned short>(),
+          E2.as<float>(), W2.as<float>());
+    else
+      mlp_gather_samples_kernel<MlpDims<3>::KP, 3><<<grid_for(m, 256), 256, 0, s>>>(
+          m, perm.as<int64_t>(), Z.as<unsigned short>(), E.as<float>(), W.as<float>(), Z2.as<unsigned short>(),
+          E2.as<float>(), W2.as<float>());
+    const int64_t batch = std::min<int64_t>(o.batch, m);
+    float lossv = 0.f;
+    for (int step = 0; step < o.steps; ++step) {
+      const int64_t first = (int64_t(step) * batch) % m;
+      const int64_t mb = std::min<int64_t>(batch, m - first);
+      mlp_grad_pass(c, M, Z2.as<unsigned short>(), E2.as<float>(), W2.as<float>(), first, mb, float(2.0 / double(mb)));
+      if (step == 0) {
+        HIP_TRY(hipMemcpyAsync(&lossv, M.loss.p, 4, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        info.loss_first[i] = double(lossv) / double(mb);
+      }
+      mlp_adam(c, M, float(o.lr));
+    }
+    const int64_t mb = std::min<int64_t>(batch, m);
+    mlp_grad_pass(c, M, Z2.as<unsigned short>(), E2.as<float>(), W2.as<float>(), 0, mb, float(2.0 / double(mb)));
+    HIP_TRY(hipMemcpyAsync(&lossv, M.loss.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    info.loss_last[i] = double(lossv) / double(mb);
+    M.use.enabled = true;
+  }
+  c.drop_graphs();
+  c.m_alloc = -1;
 }
 
 }  // namespace
@@ -861,6 +1352,9 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     }
     for (int64_t i = 0; i < N; ++i)
       if (L->dof_node[i] < 0 || L->dof_node[i] >= L->n_nodes) throw Error(FSI_ERR_ARG, "dof_node out of range");
+    if (L->node_ijk)
+      for (int64_t i = 0; i < L->n_nodes * d; ++i)
+        if (L->node_ijk[i] < 0 || L->node_ijk[i] > (1 << 20)) throw Error(FSI_ERR_ARG, "node_ijk out of range");
     // host copies (the context is only modified once everything validated)
     HCsr H[FSI_NBLK];
     for (int b = 0; b < FSI_NBLK; ++b) H[b] = csr_copy(blk[b].nrows, blk[b].ncols, blk[b].rowptr, blk[b].col, blk[b].val);
@@ -924,6 +1418,8 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     c.n_p = L->n_f - nvf; c.N = N;
     c.dt_theta = L->dt_theta;
     c.coords.assign(L->coords, L->coords + L->n_nodes * d);
+    if (L->node_ijk) c.node_ijk.assign(L->node_ijk, L->node_ijk + L->n_nodes * d);
+    else c.node_ijk.clear();
     c.dof_node.assign(L->dof_node, L->dof_node + N);
     for (int b = 0; b < FSI_NBLK; ++b) c.blk[b] = std::move(H[b]);
     c.Ah = dAh;
@@ -1007,6 +1503,7 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
     }
     for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
+    prepare_mlp(c);
     c.precision = o.precision;
     c.drop_graphs();
     c.m_alloc = -1;
@@ -1122,12 +1619,18 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
     std::string m = sa_finalize(H);
     if (!m.empty()) throw Error(FSI_ERR_NUMERIC, m);
     const int nv = which == FSI_H_M ? c.d : 1;
+    const bool learned_capable = !c.node_ijk.empty() && (which == FSI_H_M || which == FSI_H_SIG);
     c.drop_graphs();
     c.m_alloc = -1;
-    if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream);
-    else c.p32->H[which] = upload_hier<float>(H, nv, c.stream);
+    if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream, learned_capable);
+    else c.p32->H[which] = upload_hier<float>(H, nv, c.stream, learned_capable);
     HIP_TRY(hipStreamSynchronize(c.stream));
     c.host_h[which] = std::move(H);
+    if (learned_capable) {
+      prepare_mlp(c);
+      if (c.precision == FSI_P_F64) link_mlp(c, *c.p64);
+      else link_mlp(c, *c.p32);
+    }
     return FSI_OK;
   });
 }
@@ -1190,6 +1693,170 @@ fsi_status fsi_get_aggregates(fsi_ctx* ctx, int which, int level, int32_t* agg, 
     if (a.empty()) throw Error(FSI_ERR_STATE, "aggregates unknown for an imported hierarchy");
     if (count) *count = int64_t(a.size());
     if (agg) std::memcpy(agg, a.data(), sizeof(int32_t) * a.size());
+    return FSI_OK;
+  });
+}
+
+void fsi_default_mlp_train_opts(fsi_mlp_train_opts* o) {
+  if (!o) return;
+  o->steps = 400;
+  o->batch = 16384;
+  o->lr = 1e-3;
+  o->exact_tol = 1e-10;
+  o->exact_maxit = 300;
+  o->seed = 0;
+}
+
+fsi_status fsi_mlp_set_weights(fsi_ctx* ctx, int which, const float* W1, const float* W2, const float* W3) {
+  return guarded(ctx, [&]() -> fsi_status {
+    MlpState& M = mlp_state(*ctx, which);
+    if (!W1 || !W2 || !W3) throw Error(FSI_ERR_ARG, "weights are NULL");
+    mlp_upload_weights(*ctx, M, W1, W2, W3);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_get_weights(fsi_ctx* ctx, int which, float* W1, float* W2, float* W3) {
+  return guarded(ctx, [&]() -> fsi_status {
+    MlpState& M = mlp_state(*ctx, which);
+    if (!W1 || !W2 || !W3) throw Error(FSI_ERR_ARG, "weights are NULL");
+    if (!M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    std::vector<float> wm(size_t(M.nparam()));
+    HIP_TRY(hipMemcpyAsync(wm.data(), M.wm.p, 4 * wm.size(), hipMemcpyDeviceToHost, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    const int kp = M.kp(), kin = M.kin(), d = M.d;
+    for (int k = 0; k < kin; ++k)
+      for (int h = 0; h < 64; ++h) W1[k * 64 + h] = wm[size_t(k) * 64 + h];
+    const float* m2 = wm.data() + size_t(kp) * 64;
+    for (int a = 0; a < 64 * 64; ++a) W2[a] = m2[a];
+    const float* m3 = m2 + 64 * 64;
+    for (int h = 0; h < 64; ++h)
+      for (int q = 0; q < d; ++q) W3[h * d + q] = m3[h * 16 + q];
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_enable(fsi_ctx* ctx, int which, int enable) {
+  return guarded(ctx, [&]() -> fsi_status {
+    MlpState& M = mlp_state(*ctx, which);
+    if (enable && !M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    if (M.use.enabled != (enable != 0)) {
+      M.use.enabled = enable != 0;
+      ctx->drop_graphs();  // the captured kernel sequence changes
+      ctx->m_alloc = -1;
+    }
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    MlpState& M = mlp_state(c, which);
+    if (!M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    check_device_ptr(b, "b");
+    check_device_ptr(x, "x");
+    hipStream_t s = c.stream;
+    const unsigned grid = grid_for(M.n_nodes, 64);
+    const int32_t* nbr = M.nbr.as<int32_t>();
+    auto run = [&](auto tag, const auto* bb, const auto* dinv, auto* xx) {
+      using T = decltype(tag);
+      if (M.d == 2) {
+        if (M.use.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+        else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+      } else {
+        if (M.use.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+        else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+      }
+    };
+    if (c.precision == FSI_P_F64) {
+      DHier<double>& H = c.p64->H[which];
+      run(double(0), b, H.lev[0].dinv->as<double>(), x);
+    } else {
+      DHier<float>& H = c.p32->H[which];
+      const int64_t n = M.n_nodes * M.d;
+      DevBuf bf, xf;
+      bf.alloc(4 * n);
+      xf.alloc(4 * n);
+      cast_kernel<double, float><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, b, bf.as<float>());
+      run(float(0), bf.as<float>(), H.lev[0].dinv->as<float>(), xf.as<float>());
+      cast_kernel<float, double><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, xf.as<float>(), x);
+      HIP_TRY(hipStreamSynchronize(s));
+    }
+    HIP_TRY(hipGetLastError());
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_loss_grad(fsi_ctx* ctx, int which, int64_t m, const float* Z, const float* E, const float* w,
+                             float* G1, float* G2, float* G3, double* loss) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    MlpState& M = mlp_state(c, which);
+    if (!M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    if (m <= 0 || !Z || !E || !w || !G1 || !G2 || !G3 || !loss) throw Error(FSI_ERR_ARG, "bad arguments");
+    hipStream_t s = c.stream;
+    const int kp = M.kp(), kin = M.kin(), d = M.d;
+    std::vector<uint16_t> zb(size_t(m) * kp, 0);
+    for (int64_t i = 0; i < m; ++i)
+      for (int k = 0; k < kin; ++k) zb[size_t(i) * kp + k] = host_bf16(Z[i * kin + k]);
+    DevBuf dZ, dE, dW;
+    dZ.alloc(2 * zb.size());
+    dE.alloc(4 * size_t(m) * d);
+    dW.alloc(4 * size_t(m));
+    HIP_TRY(hipMemcpyAsync(dZ.p, zb.data(), 2 * zb.size(), hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dE.p, E, 4 * size_t(m) * d, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(dW.p, w, 4 * size_t(m), hipMemcpyHostToDevice, s));
+    mlp_grad_pass(c, M, dZ.as<unsigned short>(), dE.as<float>(), dW.as<float>(), 0, m, float(2.0 / double(m)));
+    std::vector<float> g(size_t(M.nparam()));
+    float lsum = 0.f;
+    HIP_TRY(hipMemcpyAsync(g.data(), M.g.p, 4 * g.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(&lsum, M.loss.p, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int k = 0; k < kin; ++k)
+      for (int h = 0; h < 64; ++h) G1[k * 64 + h] = g[size_t(k) * 64 + h];
+    const float* g2 = g.data() + size_t(kp) * 64;
+    for (int a = 0; a < 64 * 64; ++a) G2[a] = g2[a];
+    const float* g3 = g2 + 64 * 64;
+    for (int h = 0; h < 64; ++h)
+      for (int q = 0; q < d; ++q) G3[h * d + q] = g3[h * 16 + q];
+    *loss = double(lsum) / double(m);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_collect(fsi_ctx* ctx, int max_vectors, int every) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (max_vectors < 0 || every < 1) throw Error(FSI_ERR_ARG, "bad arguments");
+    for (auto& M : c.mlp) {
+      M.rec.active = max_vectors > 0;
+      M.rec.max_vectors = max_vectors;
+      M.rec.every = every;
+      M.rec.calls = 0;
+      if (max_vectors == 0) M.rec.vecs.clear();
+    }
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_train_info* info) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    fsi_mlp_train_opts o;
+    fsi_default_mlp_train_opts(&o);
+    if (opts) o = *opts;
+    if (o.steps < 0 || o.batch < 16 || !(o.lr > 0.0) || !(o.exact_tol > 0.0) || o.exact_maxit < 1)
+      throw Error(FSI_ERR_ARG, "bad training options");
+    bool any = false;
+    for (auto& M : c.mlp) any = any || (M.n_nodes > 0 && M.have_weights && !M.rec.vecs.empty());
+    if (!any) throw Error(FSI_ERR_STATE, "nothing to train: set weights and record residuals first");
+    for (auto& M : c.mlp) M.rec.active = false;
+    fsi_mlp_train_info local{};
+    if (c.precision == FSI_P_F64) mlp_train_impl<double>(c, *c.p64, o, local);
+    else mlp_train_impl<float>(c, *c.p32, o, local);
+    if (info) *info = local;
     return FSI_OK;
   });
 }

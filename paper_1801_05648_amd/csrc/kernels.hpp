@@ -176,6 +176,77 @@ __global__ __launch_bounds__(kBlock) void vup_kernel(
   }
 }
 
+// Finest-level sweeps with the learned pre-smoothing (flag[0] = 1) or its
+// Jacobi fallback (flag[0] = 0).  With the network's correction x_m the
+// residual r_m = b - A x_m is formed beforehand; the down-sweep then only
+// restricts it (b_c = R r_m) and the up-sweep starts from x_m:
+//   y = x_m + P e + omega D^{-1} (r_m - (A P) e).
+// With the fallback both sweeps are exactly vdown/vup above.
+template <typename T, int GA, int GQ, int NV>
+__global__ __launch_bounds__(kBlock) void vdown_sel_kernel(
+    int64_t na, const int64_t* __restrict__ rpa, const int32_t* __restrict__ cia, const T* __restrict__ va,
+    int64_t nq, const int64_t* __restrict__ rpq, const int32_t* __restrict__ ciq, const T* __restrict__ vq,
+    const int64_t* __restrict__ rpr, const int32_t* __restrict__ cir, const T* __restrict__ vr,
+    const T* __restrict__ b, T omega, T* __restrict__ r, T* __restrict__ bc, const T* __restrict__ r_m,
+    const int* __restrict__ flag, unsigned nblk_a) {
+  const bool learned = flag[0] != 0;
+  T acc[NV];
+#pragma unroll
+  for (int n = 0; n < NV; ++n) acc[n] = T(0);
+  if (blockIdx.x < nblk_a) {
+    if (learned) return;  // r_m is already formed
+    const int64_t row = int64_t(blockIdx.x) * (kBlock / GA) + threadIdx.x / GA;
+    const int lane = threadIdx.x % GA;
+    if (row >= na) return;
+    row_accumulate<T, GA, NV>(rpa, cia, va, row, lane, GatherPlain<T, NV>{b}, acc);
+    group_reduce<T, GA, NV>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int n = 0; n < NV; ++n) r[row * NV + n] = b[row * NV + n] - omega * acc[n];
+  } else {
+    const int64_t row = int64_t(blockIdx.x - nblk_a) * (kBlock / GQ) + threadIdx.x / GQ;
+    const int lane = threadIdx.x % GQ;
+    if (row >= nq) return;
+    if (learned) row_accumulate<T, GQ, NV>(rpr, cir, vr, row, lane, GatherPlain<T, NV>{r_m}, acc);
+    else row_accumulate<T, GQ, NV>(rpq, ciq, vq, row, lane, GatherPlain<T, NV>{b}, acc);
+    group_reduce<T, GQ, NV>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int n = 0; n < NV; ++n) bc[row * NV + n] = acc[n];
+  }
+}
+
+template <typename T, int G, int NV>
+__global__ __launch_bounds__(kBlock) void vup_sel_kernel(
+    int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
+    const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
+    const T* __restrict__ e, const T* b, const T* __restrict__ dinv, T omega, const T* __restrict__ r,
+    const T* __restrict__ x_m, const T* __restrict__ r_m, const int* __restrict__ flag, T* y) {
+  constexpr int RPB = kBlock / G;
+  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  const bool learned = flag[0] != 0;
+  T ap[NV], pe[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = T(0);
+  const GatherPlain<T, NV> ge{e};
+  row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
+  row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
+  group_reduce<T, G, NV>(pe);
+  group_reduce<T, G, NV>(ap);
+  if (lane == 0) {
+    const T wd = omega * dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t k = row * NV + q;
+      const T x0 = learned ? x_m[k] : wd * b[k];
+      const T rr = learned ? r_m[k] : r[k];
+      y[k] = x0 + pe[q] + wd * (rr - ap[q]);
+    }
+  }
+}
+
 // -------------------------------------------------------------- coarse solve
 // X = Ainv B with a dense row-major n x n inverse (FP64); one wavefront per
 // row; B, X hold NV interleaved columns.  X must not alias B.
@@ -208,6 +279,12 @@ template <typename T>
 __global__ __launch_bounds__(kBlock) void vsub_kernel(int64_t n, T* __restrict__ y, const T* __restrict__ x) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
     y[i] = y[i] - x[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void vadd_kernel(int64_t n, T* __restrict__ y, const T* __restrict__ x) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    y[i] = y[i] + x[i];
 }
 
 template <typename TI, typename TO>

@@ -59,6 +59,14 @@ struct MlpW {
   const unsigned short *w1t, *w2t, *w2, *w3t, *w3;
 };
 
+// Order the LDS writes of a wavefront before its other lanes read them (the
+// waves of a block run different numbers of tiles, so no block barrier).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ bf16x4_t load4(const unsigned short* p) {
   return *reinterpret_cast<const bf16x4_t*>(p);
 }
@@ -224,8 +232,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(int64_t first, int64_t m
 #pragma unroll
       for (int i = 0; i < 4; ++i) da1T[(16 * mb + 4 * q + i) * 16 + n] = f2bf(tl.a1[mb][i] > 0.f ? acc[i] : 0.f);
     }
-    __builtin_amdgcn_s_waitcnt(0);
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();
     // weight gradients, contracting over the 16 nodes of the tile:
     //   dW1 += Z^T dA1, dW2 += H1^T dA2, dW3 += H2^T dY
 #pragma unroll
@@ -240,7 +247,7 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(int64_t first, int64_t m
     const bf16x4_t bdy = load4(dyT + n * 16 + 4 * q);
 #pragma unroll
     for (int mb = 0; mb < M::HB; ++mb) g3[mb] = mfma16(load4(h2T + (16 * mb + n) * 16 + 4 * q), bdy, g3[mb]);
-    __builtin_amdgcn_wave_barrier();
+    wave_sync();  // the next tile overwrites this wave's LDS rows
   }
   float* out = part + wave * M::NPARAM;
 #pragma unroll
@@ -321,6 +328,92 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float* __restrict__ wm, f
     w3[hid * M::NP + c] = h;
     w3t[c * M::H + hid] = h;
   }
+}
+
+// Training samples of one recorded residual b with its exact correction e:
+// Z row = scale * z(b) in BF16 (zero padded to KP), E row = scale * e, and the
+// weight of the node (its mean diagonal entry relative to the operator's
+// mean, precomputed on the host in wnode).
+template <int D, bool PER_DOF, typename T>
+__global__ __launch_bounds__(256) void mlp_samples_kernel(int64_t n_nodes, const int32_t* __restrict__ nbr,
+                                                           const T* __restrict__ b, const T* __restrict__ dinv,
+                                                           const double* __restrict__ e, const float* __restrict__ wnode,
+                                                           float scale, unsigned short* __restrict__ Z,
+                                                           float* __restrict__ E, float* __restrict__ W) {
+  using M = MlpDims<D>;
+  const int64_t node = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= n_nodes) return;
+  for (int k = 0; k < M::KP; ++k) {
+    float v = 0.f;
+    if (k < M::KIN) {
+      const int s = k / D, c = k % D;
+      const int32_t nb = nbr[node * M::S + s];
+      if (nb >= 0) v = scale * float((PER_DOF ? dinv[int64_t(nb) * D + c] : dinv[nb]) * b[int64_t(nb) * D + c]);
+    }
+    Z[node * M::KP + k] = f2bf(v);
+  }
+  for (int c = 0; c < D; ++c) E[node * D + c] = scale * float(e[node * D + c]);
+  W[node] = wnode[node];
+}
+
+// Rows `perm` of a sample set into a shuffled copy.
+template <int KP, int D>
+__global__ __launch_bounds__(256) void mlp_gather_samples_kernel(int64_t m, const int64_t* __restrict__ perm,
+                                                                  const unsigned short* __restrict__ Zi,
+                                                                  const float* __restrict__ Ei, const float* __restrict__ Wi,
+                                                                  unsigned short* __restrict__ Zo, float* __restrict__ Eo,
+                                                                  float* __restrict__ Wo) {
+  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (i >= m) return;
+  const int64_t s = perm[i];
+  for (int k = 0; k < KP; ++k) Zo[i * KP + k] = Zi[s * KP + k];
+  for (int c = 0; c < D; ++c) Eo[i * D + c] = Ei[s * D + c];
+  Wo[i] = Wi[s];
+}
+
+// Fallback test of the learned pre-smoothing: per-block partials of r.r and
+// b.b, then one block adds them in block order and sets flag = 1 (use the
+// network's correction) iff ||b - A x_mlp|| <= ||b||; otherwise the damped
+// Jacobi sweep is used and the fallback counter is incremented.
+constexpr int kNormBlocks = 256;
+
+template <typename T>
+__global__ __launch_bounds__(256) void norm_pair_partial_kernel(int64_t n, const T* __restrict__ r,
+                                                                 const T* __restrict__ b, double* __restrict__ part) {
+  __shared__ double sh[2][4];
+  double rr = 0.0, bb = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const double ri = double(r[i]), bi = double(b[i]);
+    rr += ri * ri;
+    bb += bi * bi;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    rr += __shfl_xor(rr, off, 64);
+    bb += __shfl_xor(bb, off, 64);
+  }
+  if (threadIdx.x % 64 == 0) {
+    sh[0][threadIdx.x / 64] = rr;
+    sh[1][threadIdx.x / 64] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
+    part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
+  }
+}
+
+__global__ void mlp_flag_kernel(int nb, const double* __restrict__ part, int* __restrict__ flag,
+                                int* __restrict__ fallbacks) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double rr = 0.0, bb = 0.0;
+  for (int i = 0; i < nb; ++i) {
+    rr += part[2 * i];
+    bb += part[2 * i + 1];
+  }
+  const int ok = (rr <= bb) ? 1 : 0;  // NaN -> fall back
+  flag[0] = ok;
+  if (!ok) fallbacks[0] = fallbacks[0] + 1;
 }
 
 }  // namespace fsi

@@ -42,7 +42,8 @@ class CLayout(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("pad", ctypes.c_int32),
                 ("n_m", ctypes.c_int64), ("n_s", ctypes.c_int64), ("n_f", ctypes.c_int64),
                 ("n_vs", ctypes.c_int64), ("n_vf", ctypes.c_int64), ("dt_theta", ctypes.c_double),
-                ("n_nodes", ctypes.c_int64), ("coords", ctypes.c_void_p), ("dof_node", ctypes.c_void_p)]
+                ("n_nodes", ctypes.c_int64), ("coords", ctypes.c_void_p), ("dof_node", ctypes.c_void_p),
+                ("node_ijk", ctypes.c_void_p)]
 
 
 class CPrecondOpts(ctypes.Structure):
@@ -59,7 +60,17 @@ class CSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("true_rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_precond_ms", ctypes.c_double), ("t_spmv_ms", ctypes.c_double), ("t_gs_ms", ctypes.c_double),
-                ("n_timed", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("n_timed", ctypes.c_int32), ("mlp_fallbacks", ctypes.c_int32)]
+
+
+class CMlpTrainOpts(ctypes.Structure):
+    _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
+                ("exact_tol", ctypes.c_double), ("exact_maxit", ctypes.c_int32), ("seed", ctypes.c_uint32)]
+
+
+class CMlpTrainInfo(ctypes.Structure):
+    _fields_ = [("vectors", ctypes.c_int32 * 2), ("samples", ctypes.c_int64 * 2),
+                ("loss_first", ctypes.c_double * 2), ("loss_last", ctypes.c_double * 2)]
 
 
 @dataclasses.dataclass
@@ -74,6 +85,7 @@ class SolveInfo:
     t_spmv_ms: float = 0.0
     t_gs_ms: float = 0.0
     n_timed: int = 0
+    mlp_fallbacks: int = 0
 
 
 def _declare(lib):
@@ -94,6 +106,14 @@ def _declare(lib):
         "fsi_get_level": ([P, i32, i32, i32, P, P, P, P, P, P], i32),
         "fsi_get_aggregates": ([P, i32, i32, P, P], i32),
         "fsi_vcycle_bytes": ([P, i32, P], i32),
+        "fsi_default_mlp_train_opts": ([ctypes.POINTER(CMlpTrainOpts)], None),
+        "fsi_mlp_set_weights": ([P, i32, P, P, P], i32),
+        "fsi_mlp_get_weights": ([P, i32, P, P, P], i32),
+        "fsi_mlp_enable": ([P, i32, i32], i32),
+        "fsi_mlp_forward": ([P, i32, P, P], i32),
+        "fsi_mlp_loss_grad": ([P, i32, i64, P, P, P, P, P, P, P], i32),
+        "fsi_mlp_collect": ([P, i32, i32], i32),
+        "fsi_mlp_train": ([P, ctypes.POINTER(CMlpTrainOpts), ctypes.POINTER(CMlpTrainInfo)], i32),
         "fsi_default_precond_opts": ([ctypes.POINTER(CPrecondOpts)], None),
         "fsi_default_solve_opts": ([ctypes.POINTER(CSolveOpts)], None),
     }
@@ -122,8 +142,9 @@ def exported_symbols():
     return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_build_precond",
             "fsi_solve", "fsi_spmv", "fsi_apply_precond", "fsi_vcycle", "fsi_set_hierarchy",
             "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_get_level", "fsi_get_aggregates",
-            "fsi_default_precond_opts",
-            "fsi_default_solve_opts"]
+            "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
+            "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
+            "fsi_mlp_loss_grad", "fsi_mlp_collect", "fsi_mlp_train"]
 
 
 def _csr_struct(nrows, ncols, rowptr, col, val, keep):
@@ -165,6 +186,11 @@ class FsiSolver:
         if rc != 0:
             raise FsiError(rc, self.lib.fsi_last_error(None).decode())
         self.ctx = ctx
+        self.set_system(blocks, layout)
+
+    def set_system(self, blocks, layout):
+        """Replace the linear system (fsi_setup_blocks); invalidates the
+        preconditioner, keeps a learned smoother's weights."""
         self.N = int(layout["n_m"] + layout["n_s"] + layout["n_f"])
         self.layout = dict(layout)
         keep = []
@@ -178,16 +204,26 @@ class FsiSolver:
             arr[i] = _csr_struct(nr, ncl, rp, ci, vv, keep)
         coords = np.ascontiguousarray(layout["coords"], dtype=np.float64)
         dof_node = np.ascontiguousarray(layout["dof_node"], dtype=np.int32)
+        ijk = layout.get("node_ijk")
+        ijk = None if ijk is None else np.ascontiguousarray(ijk, dtype=np.int32)
         lay = CLayout(int(layout["dim"]), 0, int(layout["n_m"]), int(layout["n_s"]), int(layout["n_f"]),
                       int(layout["n_vs"]), int(layout["n_vf"]), float(layout["dt_theta"]),
-                      int(coords.shape[0]), coords.ctypes.data, dof_node.ctypes.data)
+                      int(coords.shape[0]), coords.ctypes.data, dof_node.ctypes.data,
+                      None if ijk is None else ijk.ctypes.data)
         self._check(self.lib.fsi_setup_blocks(self.ctx, ctypes.byref(lay), arr, 0))
+
+    @staticmethod
+    def layout_of(sysm):
+        return dict(dim=sysm.dim, n_m=sysm.n_m, n_s=sysm.n_s, n_f=sysm.n_f, n_vs=sysm.n_vs,
+                    n_vf=sysm.n_vf, dt_theta=sysm.dt_theta, coords=sysm.coords, dof_node=sysm.dof_node,
+                    node_ijk=sysm.node_ijk)
 
     @classmethod
     def from_system(cls, sysm, **kw):
-        layout = dict(dim=sysm.dim, n_m=sysm.n_m, n_s=sysm.n_s, n_f=sysm.n_f, n_vs=sysm.n_vs,
-                      n_vf=sysm.n_vf, dt_theta=sysm.dt_theta, coords=sysm.coords, dof_node=sysm.dof_node)
-        return cls(sysm.blocks, layout, **kw)
+        return cls(sysm.blocks, cls.layout_of(sysm), **kw)
+
+    def set_from_system(self, sysm):
+        self.set_system(sysm.blocks, self.layout_of(sysm))
 
     # -- plumbing ------------------------------------------------------------
     def _check(self, rc):
@@ -233,7 +269,7 @@ class FsiSolver:
                                             ctypes.byref(o), ctypes.byref(info)))
         return x, SolveInfo(STATUS[rc], info.iters, info.restarts, bool(info.converged),
                             info.true_rel_resid, info.t_total_ms, info.t_precond_ms, info.t_spmv_ms,
-                            info.t_gs_ms, info.n_timed)
+                            info.t_gs_ms, info.n_timed, info.mlp_fallbacks)
 
     def spmv(self, x, y=None):
         if y is None:
@@ -303,3 +339,49 @@ class FsiSolver:
         a = np.empty(cnt.value, np.int32)
         self._check(self.lib.fsi_get_aggregates(self.ctx, w, level, a.ctypes.data, None))
         return a
+
+    # -- learned smoother ---------------------------------------------------------
+    def mlp_set_weights(self, which, W1, W2, W3):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        a = [np.ascontiguousarray(x, dtype=np.float32) for x in (W1, W2, W3)]
+        self._check(self.lib.fsi_mlp_set_weights(self.ctx, w, *[x.ctypes.data for x in a]))
+
+    def mlp_get_weights(self, which, k_in: int, d: int):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        a = [np.empty((k_in, 64), np.float32), np.empty((64, 64), np.float32), np.empty((64, d), np.float32)]
+        self._check(self.lib.fsi_mlp_get_weights(self.ctx, w, *[x.ctypes.data for x in a]))
+        return a
+
+    def mlp_enable(self, which, enable: bool = True):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        self._check(self.lib.fsi_mlp_enable(self.ctx, w, int(enable)))
+
+    def mlp_forward(self, which, b, x=None):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        n = self._hier_len(w)
+        if x is None:
+            x = self.torch.empty_like(b)
+        self._check(self.lib.fsi_mlp_forward(self.ctx, w, _dptr(b, n, "b"), _dptr(x, n, "x")))
+        return x
+
+    def mlp_loss_grad(self, which, Z, E, wgt, d: int):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        Z = np.ascontiguousarray(Z, dtype=np.float32)
+        E = np.ascontiguousarray(E, dtype=np.float32)
+        wgt = np.ascontiguousarray(wgt, dtype=np.float32)
+        m, k_in = Z.shape
+        G = [np.empty((k_in, 64), np.float32), np.empty((64, 64), np.float32), np.empty((64, d), np.float32)]
+        loss = ctypes.c_double()
+        self._check(self.lib.fsi_mlp_loss_grad(self.ctx, w, m, Z.ctypes.data, E.ctypes.data, wgt.ctypes.data,
+                                               *[g.ctypes.data for g in G], ctypes.byref(loss)))
+        return loss.value, G
+
+    def mlp_collect(self, max_vectors: int, every: int = 1):
+        self._check(self.lib.fsi_mlp_collect(self.ctx, int(max_vectors), int(every)))
+
+    def mlp_train(self, steps=400, batch=16384, lr=1e-3, exact_tol=1e-10, exact_maxit=300, seed=0):
+        o = CMlpTrainOpts(int(steps), int(batch), float(lr), float(exact_tol), int(exact_maxit), int(seed))
+        info = CMlpTrainInfo()
+        self._check(self.lib.fsi_mlp_train(self.ctx, ctypes.byref(o), ctypes.byref(info)))
+        return dict(vectors=list(info.vectors), samples=list(info.samples),
+                    loss_first=list(info.loss_first), loss_last=list(info.loss_last))

@@ -71,7 +71,7 @@ def test_null_context_arguments_are_rejected(lib):
 def test_ctypes_structs_match_the_header_layout():
     from paper_1801_05648_amd import fsi
     assert ctypes.sizeof(fsi.CCsr) == 48
-    assert ctypes.sizeof(fsi.CLayout) == 4 + 4 + 5 * 8 + 8 + 8 + 8 + 8
+    assert ctypes.sizeof(fsi.CLayout) == 4 + 4 + 5 * 8 + 8 + 8 + 8 + 8 + 8
     assert ctypes.sizeof(fsi.CPrecondOpts) == 24
     assert ctypes.sizeof(fsi.CSolveOpts) == 24
     assert ctypes.sizeof(fsi.CSolveInfo) == 64

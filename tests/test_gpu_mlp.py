@@ -1,0 +1,317 @@
+"""Learned per-node MLP smoother on the GPU, against the FP64 oracle.
+
+The network runs in BF16 on the matrix cores with FP32 accumulation; the
+oracle is fed the same BF16-rounded weights and inputs and rounds its hidden
+activations to BF16 as the GPU stores them, so forward results agree to FP32
+accumulation error (a rare flip of one activation's BF16 rounding aside).  The
+backward pass also stores dY, dA2 and dA1 in BF16, which bounds the gradient
+agreement at a few BF16 roundings (2^-9 relative each)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from conftest import system
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+HID = 64
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _nodes(sysm, which):
+    d = sysm.dim
+    if which == "H_M":
+        base, n = 0, sysm.n_m // d
+    else:
+        base, n = sysm.n_m, sysm.n_vs // d
+    return sysm.dof_node[base + np.arange(n) * d].astype(np.int64)
+
+
+def _stencil(sysm, which):
+    """Operator index of the 3^d lattice neighbours of every operator node
+    (offsets in lexicographic order, last axis fastest; -1 where absent)."""
+    d = sysm.dim
+    gnode = _nodes(sysm, which)
+    ijk = np.asarray(sysm.node_ijk, dtype=np.int64)
+    op = {int(g): k for k, g in enumerate(gnode)}
+    where = {tuple(ijk[g]): g for g in range(ijk.shape[0])}
+    offs = list(itertools.product((-1, 0, 1), repeat=d))
+    nbr = -np.ones((len(gnode), len(offs)), dtype=np.int64)
+    for k, g in enumerate(gnode):
+        for s, o in enumerate(offs):
+            g2 = where.get(tuple(ijk[g] + np.array(o)))
+            if g2 is not None and g2 in op:
+                nbr[k, s] = op[g2]
+    return nbr
+
+
+def _level0(bs, which):
+    return bs.mesh_scalar() if which == "H_M" else bs.solid_schur()
+
+
+def _net_inputs(bs, sysm, which, b):
+    """z of every node from the residual b of the finest level: the stencil
+    values of D^{-1} b (D per node for the scalar mesh operator acting on d
+    interleaved components, per dof for the solid Schur matrix)."""
+    from oracle import mlp
+    d = sysm.dim
+    A0 = _level0(bs, which)
+    dg = A0.diagonal()
+    if which == "H_M":
+        v = (b.reshape(-1, d) / dg[:, None])
+    else:
+        v = (b / dg).reshape(-1, d)
+    return mlp.stencil_inputs(v, _stencil(sysm, which))
+
+
+def _bf16_weights(W):
+    from oracle import mlp
+    return [mlp.round_bf16(w.astype(np.float32)) for w in W]
+
+
+def _oracle_forward(W, z):
+    from oracle import mlp
+    y, _ = mlp.forward(_bf16_weights(W), mlp.round_bf16(z.astype(np.float32)), act_round=mlp.round_bf16)
+    return y
+
+
+def _solver(name, max_coarse=500, precision="f64"):
+    from paper_1801_05648_amd import FsiSolver
+    s = FsiSolver.from_system(system(name), device=0)
+    s.build_precond(precision, max_coarse=max_coarse)
+    return s
+
+
+def _jacobi_like(k_in, d, omega, noise, seed):
+    """Weights whose network is (nearly) omega times the centre value of z:
+    h1 = relu(+-z_centre), h2 = h1, delta = omega (h2+ - h2-), plus small
+    seeded noise on every weight so that all MFMA fragments carry data."""
+    rng = np.random.default_rng(seed)
+    S = k_in // d
+    centre = (S // 2) * d
+    W1 = noise * rng.standard_normal((k_in, HID))
+    W2 = noise * rng.standard_normal((HID, HID))
+    W3 = noise * rng.standard_normal((HID, d))
+    for c in range(d):
+        W1[centre + c, 2 * c] += 1.0
+        W1[centre + c, 2 * c + 1] -= 1.0
+        W2[2 * c, 2 * c] += 1.0
+        W2[2 * c + 1, 2 * c + 1] += 1.0
+        W3[2 * c, c] += omega
+        W3[2 * c + 1, c] -= omega
+    return [W1, W2, W3]
+
+
+CASES = [("c1", "H_M", 500), ("c1", "H_SIG", 40), ("tiny3d", "H_M", 10), ("tiny3d", "H_SIG", 10)]
+
+
+@pytest.mark.parametrize("name,which,max_coarse", CASES)
+def test_forward_matches_oracle(name, which, max_coarse):
+    from oracle import blocks, mlp
+    sysm = system(name)
+    bs = blocks.BlockSystem(sysm)
+    d = sysm.dim
+    k_in = 3 ** d * d
+    s = _solver(name, max_coarse)
+    n = _level0(bs, which).shape[0] * (d if which == "H_M" else 1)
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(n)
+    W = mlp.init_weights(k_in, HID, d, seed=11)
+    s.mlp_set_weights(which, *[w.astype(np.float32) for w in W])
+    x = s.mlp_forward(which, _dev(b)).cpu().numpy().reshape(-1, d)
+    ref = _oracle_forward(W, _net_inputs(bs, sysm, which, b))
+    print(f"{name} {which}: {x.shape[0]} nodes, max|y| {np.abs(ref).max():.3e}")
+    scale = np.abs(ref).max()
+    assert np.linalg.norm(x - ref) <= 1e-3 * np.linalg.norm(ref)
+    assert np.abs(x - ref).max() <= 1e-2 * scale
+    # the read-back master weights are the FP32 values set
+    G = s.mlp_get_weights(which, k_in, d)
+    for a, w in zip(G, W):
+        assert np.array_equal(a, w.astype(np.float32))
+    s.close()
+
+
+@pytest.mark.parametrize("d,m", [(2, 1007), (3, 333), (2, 16)])
+def test_loss_and_gradients_match_oracle(d, m):
+    from oracle import mlp
+    name, which, mc = ("c1", "H_M", 500) if d == 2 else ("tiny3d", "H_M", 10)
+    k_in = 3 ** d * d
+    s = _solver(name, mc)
+    rng = np.random.default_rng(5 + d)
+    W = mlp.init_weights(k_in, HID, d, seed=21)
+    Z = rng.standard_normal((m, k_in)).astype(np.float32)
+    E = rng.standard_normal((m, d)).astype(np.float32)
+    w = (0.5 + rng.random(m)).astype(np.float32)
+    s.mlp_set_weights(which, *[x.astype(np.float32) for x in W])
+    loss, G = s.mlp_loss_grad(which, Z, E, w, d)
+    lref, Gref = mlp.loss_and_grad(_bf16_weights(W), mlp.round_bf16(Z), E.astype(np.float64),
+                                   w.astype(np.float64), act_round=mlp.round_bf16)
+    print(f"d={d} m={m}: loss {loss:.6e} oracle {lref:.6e}")
+    assert abs(loss - lref) <= 1e-4 * lref
+    for g, gr in zip(G, Gref):
+        rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+        cos = float(np.sum(g * gr) / (np.linalg.norm(g) * np.linalg.norm(gr)))
+        print(f"   grad rel err {rel:.2e} cos {cos:.6f}")
+        assert rel <= 2e-2
+        assert cos >= 0.999
+    s.close()
+
+
+def _import(s, H, names):
+    import test_gpu_parity as tp
+    tp._import_oracle_hierarchies(s, {k: H[k] for k in names})
+
+
+@pytest.mark.parametrize("name,which,max_coarse", CASES)
+def test_learned_vcycle_matches_oracle(name, which, max_coarse):
+    """One V-cycle with the network as the first sweep (weights close to a
+    damped-Jacobi sweep, so the learned branch is taken), on the oracle's own
+    hierarchy imported into the library."""
+    from oracle import blocks, mlp, precond
+    sysm = system(name)
+    bs = blocks.BlockSystem(sysm)
+    d = sysm.dim
+    H = precond.build_hierarchies(bs, max_coarse=max_coarse)
+    h = H[which]
+    assert h.nlevels >= 2
+    s = _solver(name, max_coarse)
+    _import(s, H, [which])
+    W = _jacobi_like(3 ** d * d, d, 0.5, 1e-2, seed=4)
+    s.mlp_set_weights(which, *[w.astype(np.float32) for w in W])
+    s.mlp_enable(which, True)
+    rng = np.random.default_rng(8)
+    n0 = h.levels[0].A.shape[0]
+    nv = d if which == "H_M" else 1
+    b = rng.standard_normal(n0 * nv)
+    x = s.vcycle(which, _dev(b)).cpu().numpy()
+    X0 = _oracle_forward(W, _net_inputs(bs, sysm, which, b)).reshape(n0, nv)
+    B = b.reshape(n0, nv)
+    assert np.linalg.norm(B - h.levels[0].A @ X0) <= np.linalg.norm(B), "expected the learned branch"
+    ref = mlp.learned_vcycle(h, B, X0).reshape(-1)
+    err = np.linalg.norm(x - ref) / np.linalg.norm(ref)
+    print(f"{name} {which}: learned V-cycle rel. err {err:.2e}")
+    assert err <= 1e-4
+    # disabled again: the plain cycle, at FP64 parity
+    s.mlp_enable(which, False)
+    from oracle import amg
+    x2 = s.vcycle(which, _dev(b)).cpu().numpy().reshape(n0, nv)
+    ref2 = np.column_stack([amg.vcycle(h, B[:, c]) for c in range(nv)])
+    assert np.linalg.norm(x2 - ref2) <= 1e-12 * np.linalg.norm(ref2)
+    s.close()
+
+
+@pytest.mark.parametrize("poison", ["nan", "huge"])
+def test_poisoned_weights_fall_back_to_jacobi(poison):
+    """A network whose correction is not finite or increases the residual
+    is replaced by the Jacobi sweep on the device: the solve takes exactly
+    the iterations of the plain solve and counts every fallback."""
+    from oracle import mlp
+    sysm = system("c1")
+    d = sysm.dim
+    s = _solver("c1", 40)
+    b = _dev(sysm.b)
+    x0, i0 = s.solve(b, tol=1e-8)
+    assert i0.converged
+    W = mlp.init_weights(3 ** d * d, HID, d, seed=2)
+    if poison == "nan":
+        W[2][5, 0] = np.nan
+    else:
+        W[2] *= 1e6
+    for which in ("H_M", "H_SIG"):
+        s.mlp_set_weights(which, *[w.astype(np.float32) for w in W])
+        s.mlp_enable(which, True)
+    x1, i1 = s.solve(b, tol=1e-8)
+    print(f"plain {i0.iters} it; poisoned ({poison}) {i1.iters} it, {i1.mlp_fallbacks} fallbacks")
+    assert i1.converged and i1.iters == i0.iters
+    assert i1.mlp_fallbacks >= 4 * i1.iters  # two H_M and two H_SIG cycles per application
+    x0h, x1h = x0.cpu().numpy(), x1.cpu().numpy()
+    assert np.abs(x1h - x0h).max() <= 1e-13 * np.abs(x0h).max()
+    s.close()
+
+
+def test_learned_solve_matches_oracle_fgmres():
+    """Full FGMRES with the network in the H_M and H_SIG cycles on the
+    oracle's hierarchies, against the oracle FGMRES with the same learned
+    cycles: both reach 1e-8 and agree in the solution."""
+    from oracle import blocks, krylov, mlp, precond
+    sysm = system("c1")
+    bs = blocks.BlockSystem(sysm)
+    d = sysm.dim
+    H = precond.build_hierarchies(bs, max_coarse=40)
+    s = _solver("c1", 40)
+    _import(s, H, list(H.keys()))
+    W = _jacobi_like(3 ** d * d, d, 0.5, 1e-2, seed=6)
+    for which in ("H_M", "H_SIG"):
+        s.mlp_set_weights(which, *[w.astype(np.float32) for w in W])
+        s.mlp_enable(which, True)
+    xg, info = s.solve(_dev(sysm.b), tol=1e-8)
+    assert info.converged
+
+    def learned(which):
+        h = H[which]
+        n0 = h.levels[0].A.shape[0]
+        nv = d if which == "H_M" else 1
+
+        def inv(r):
+            X0 = _oracle_forward(W, _net_inputs(bs, sysm, which, r)).reshape(n0, nv)
+            return mlp.learned_vcycle(h, r.reshape(n0, nv), X0).reshape(-1)
+        return inv
+
+    mesh_inv = learned("H_M")
+    sig_inv = learned("H_SIG")
+    solid = lambda r: precond.solid_schur_solve(bs, lambda v: amg_v(H["H_MS"], v), sig_inv, r)
+    fluid = lambda r: precond.fluid_schur_solve(bs, lambda v: amg_v(H["H_A"], v), lambda v: amg_v(H["H_P"], v), r)
+    P = precond.BlockLDU(bs, mesh_inv, solid, fluid)
+    xo, oinfo = krylov.fgmres(bs.matvec, P.apply, sysm.b, tol=1e-8, restart=50, maxit=2000)
+    err = np.linalg.norm(xg.cpu().numpy() - xo) / np.linalg.norm(xo)
+    print(f"learned FGMRES: GPU {info.iters} it, oracle {oinfo.iters} it, solution rel. diff {err:.2e}, "
+          f"{info.mlp_fallbacks} fallbacks")
+    assert abs(info.iters - oinfo.iters) <= 2
+    assert err <= 1e-6
+    s.close()
+
+
+def amg_v(h, v):
+    from oracle import amg
+    return amg.vcycle(h, v)
+
+
+def test_training_lowers_the_loss_and_the_trained_network_solves():
+    """Record the finest-level residuals of a few solves, train both
+    networks on the device, then solve a later pseudo-time system with them."""
+    import fsigen
+    from oracle import mlp
+    sysm = system("c1", t_phase=fsigen.pseudo_time_phase(0, 0))
+    d = sysm.dim
+    s = _solver("c1", 40)
+    s.set_from_system(sysm)
+    s.build_precond("f64", max_coarse=40)
+    W = mlp.init_weights(3 ** d * d, HID, d, seed=0)
+    for which in ("H_M", "H_SIG"):
+        s.mlp_set_weights(which, *[w.astype(np.float32) for w in W])
+    s.mlp_collect(max_vectors=48, every=1)
+    _, i0 = s.solve(_dev(sysm.b), tol=1e-8)
+    info = s.mlp_train(steps=300, batch=4096, lr=2e-3, seed=1)
+    print("training:", info)
+    for k in range(2):
+        assert info["vectors"][k] > 0
+        assert info["loss_last"][k] < 0.5 * info["loss_first"][k]
+    later = system("c1", t_phase=fsigen.pseudo_time_phase(3, 1))
+    s.set_from_system(later)
+    s.build_precond("f64", max_coarse=40)
+    b = _dev(later.b)
+    for which in ("H_M", "H_SIG"):
+        s.mlp_enable(which, False)
+    _, ip = s.solve(b, tol=1e-8)
+    for which in ("H_M", "H_SIG"):
+        s.mlp_enable(which, True)
+    x, il = s.solve(b, tol=1e-8)
+    print(f"later system: plain {ip.iters} it, learned {il.iters} it, {il.mlp_fallbacks} fallbacks")
+    assert il.converged and il.true_rel_resid <= 1e-8
+    s.close()

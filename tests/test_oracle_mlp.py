@@ -90,3 +90,46 @@ def test_training_reduces_the_loss():
         L, G = mlp.loss_and_grad(W, z, e, w)
         W, m, v = mlp.adam_step(W, G, m, v, t, lr=3e-3)
     assert L < 0.2 * L0
+
+
+def _small_hierarchy():
+    from oracle import amg
+    import scipy.sparse as sp
+    n = 60
+    A = sp.diags([-np.ones(n - 1), 2.0 + 0.1 * np.arange(n) / n, -np.ones(n - 1)], [-1, 0, 1]).tocsr()
+    return amg.setup(A, 1, amg.constant_modes(n), max_coarse=8)
+
+
+def test_learned_vcycle_with_jacobi_correction_is_the_plain_cycle():
+    """Feeding the damped-Jacobi sweep omega D^{-1} b as the network's output
+    must reproduce the standard V(1,1) cycle: the learned branch changes only
+    where the first sweep comes from."""
+    from oracle import amg
+    H = _small_hierarchy()
+    assert H.nlevels >= 2
+    rng = np.random.default_rng(0)
+    B = rng.standard_normal((60, 2))
+    L = H.levels[0]
+    X0 = L.omega * L.dinv[:, None] * B
+    out = mlp.learned_vcycle(H, B, X0)
+    ref = np.column_stack([amg.vcycle(H, B[:, c]) for c in range(2)])
+    assert np.allclose(out, ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+
+
+def test_learned_vcycle_falls_back_on_bad_corrections():
+    from oracle import amg
+    H = _small_hierarchy()
+    rng = np.random.default_rng(1)
+    b = rng.standard_normal((60, 1))
+    ref = amg.vcycle(H, b[:, 0])[:, None]
+    for X0 in (np.full((60, 1), np.nan), 1e3 * rng.standard_normal((60, 1))):
+        assert np.array_equal(mlp.learned_vcycle(H, b, X0), ref)
+    # a zero correction keeps the residual norm: the learned branch is taken
+    # and gives the V(0,1) cycle, which differs from V(1,1)
+    z = mlp.learned_vcycle(H, b, np.zeros((60, 1)))
+    L = H.levels[0]
+    e = amg.vcycle(H, L.R @ b[:, 0], 1)
+    x = L.P @ e
+    x = x + L.omega * L.dinv * (b[:, 0] - L.A @ x)
+    assert np.allclose(z[:, 0], x, rtol=0, atol=1e-14 * np.abs(x).max())
+    assert not np.allclose(z, ref)
