@@ -210,19 +210,31 @@ fsi_status fsi_get_aggregates(fsi_ctx* ctx, int which, int level, int32_t* agg, 
  * correction x gives ||b - A x|| > ||b|| the Jacobi sweep is used instead
  * (counted in fsi_solve_info.mlp_fallbacks).  Requires layout.node_ijk.
  * `which` is FSI_H_M or FSI_H_SIG. */
+/* Training losses.  FSI_MLP_LOSS_L2: (1/n) sum_i w_i ||delta_i - e_i||^2
+ * against the exact corrections e = A^{-1} b (w_i: node's diagonal relative
+ * to the mean).  FSI_MLP_LOSS_ENERGY: the A-norm error left after delta and an
+ * exact coarse-grid correction, L = ||(I - P A_1^{-1} R A)(e - delta)||_A^2 - e.b,
+ * evaluated as -delta.b - delta.r - rc.c with r = b - A delta, rc = R r,
+ * c = A_1^{-1} rc; gradient -2 (r - A P c) (A taken as symmetric, R = P^T).
+ * Each recorded residual is scaled to ||b||_{D^{-1}} = 1 first. */
+enum { FSI_MLP_LOSS_L2 = 0, FSI_MLP_LOSS_ENERGY = 1 };
+
 typedef struct {
   int32_t steps;        /* Adam steps (default 400)                               */
-  int32_t batch;        /* samples per step (default 16384)                       */
+  int32_t batch;        /* samples (nodes) per step (default 16384)               */
   double lr;            /* Adam step size (default 1e-3)                          */
-  double exact_tol;     /* relative residual of the exact corrections (1e-10)     */
-  int32_t exact_maxit;  /* V-cycle iterations allowed for them (default 300)      */
+  double exact_tol;     /* L2 loss: relative residual of the exact corrections    */
+  int32_t exact_maxit;  /* L2 loss: V-cycle iterations allowed for them (300)     */
   uint32_t seed;        /* sample shuffling                                       */
+  int32_t loss;         /* FSI_MLP_LOSS_* (default ENERGY)                        */
+  int32_t coarse_cycles;/* energy loss: V-cycles for A_1^{-1} when level 1 is not
+                           the coarsest (default 4; exact dense solve otherwise)  */
 } fsi_mlp_train_opts;
 
 typedef struct {
   int32_t vectors[2];   /* recorded residuals used (H_M, H_SIG)                   */
   int64_t samples[2];   /* node samples                                           */
-  double loss_first[2], loss_last[2];  /* mean weighted loss, first / last step   */
+  double loss_first[2], loss_last[2];  /* mean loss before / after training      */
 } fsi_mlp_train_info;
 
 void fsi_default_mlp_train_opts(fsi_mlp_train_opts* o);
@@ -241,6 +253,11 @@ fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x);
  * shapes of W1, W2, W3). */
 fsi_status fsi_mlp_loss_grad(fsi_ctx* ctx, int which, int64_t m, const float* Z, const float* E, const float* w,
                              float* G1, float* G2, float* G3, double* loss);
+/* Energy loss (FSI_MLP_LOSS_ENERGY, as is: b not rescaled) of the network's
+ * correction for one residual b (device FP64, level-0 size of `which`) and its
+ * gradients (host, shapes of W1, W2, W3); A_1^{-1} as in the training. */
+fsi_status fsi_mlp_energy_grad(fsi_ctx* ctx, int which, const double* b, int coarse_cycles, float* G1, float* G2,
+                               float* G3, double* loss);
 /* Record the finest-level inputs of the FSI_H_M and FSI_H_SIG V-cycles during
  * the following solves (every `every`-th cycle, at most max_vectors each);
  * max_vectors = 0 stops recording and drops the records. */

@@ -129,3 +129,33 @@ def learned_vcycle(H, B: np.ndarray, X0: np.ndarray) -> np.ndarray:
     E = np.column_stack([amg.vcycle(H, Bc[:, c], 1) for c in range(B.shape[1])])
     X = X0 + L.P @ E
     return X + L.omega * (L.dinv[:, None] * (B - L.A @ X))
+
+
+def two_grid_energy(delta: np.ndarray, b: np.ndarray, A, P, Ac) -> tuple:
+    """Energy training loss of a pre-smoother correction delta for the
+    residual b (both n x c, one column per right-hand side):
+
+        L = ||(I - P Ac^{-1} P^T A)(e - delta)||_A^2 - e.b,   e = A^{-1} b,
+
+    the A-norm error left after delta and an exact coarse-grid correction
+    (Ac = P^T A P), shifted by the constant e.b.  Returns (L, dL/d delta);
+    A is taken as symmetric, so the projection is A-orthogonal and the
+    gradient is -2 A (I - P Ac^{-1} P^T A)(e - delta).  Dense solves."""
+    Ad = A.toarray() if hasattr(A, "toarray") else np.asarray(A)
+    Pd = P.toarray() if hasattr(P, "toarray") else np.asarray(P)
+    Acd = Ac.toarray() if hasattr(Ac, "toarray") else np.asarray(Ac)
+    b = np.asarray(b, dtype=np.float64).reshape(Ad.shape[0], -1)
+    delta = np.asarray(delta, dtype=np.float64).reshape(b.shape)
+    e = np.linalg.solve(Ad, b)
+    u = e - delta
+    w = u - Pd @ np.linalg.solve(Acd, Pd.T @ (Ad @ u))
+    L = float(np.sum(w * (Ad @ w)) - np.sum(e * b))
+    return L, -2.0 * (Ad @ w)
+
+
+def energy_loss_and_grad(W, z, b, A, P, Ac, act_round=None):
+    """Network-level energy loss: delta = forward(W, z) (one row per node, d
+    components, node-major like b), then two_grid_energy and the chain rule."""
+    y, cache = forward(W, z, act_round)
+    L, g = two_grid_energy(y.reshape(-1), b, A, P, Ac)
+    return L, backward(W, cache, g.reshape(y.shape))

@@ -193,7 +193,7 @@ struct MlpRecord {
 template <typename T>
 struct DLevel {
   DCsr<T> AD, Q, P, AP;  // A D^{-1}, Q = R (I - omega A D^{-1}), prolongator, A P
-  DCsr<T> A0, R0;        // finest level with a learned smoother: A and R themselves
+  DCsr<T> A0, R0;        // with a learned smoother: A (levels 0, 1) and R (level 0) themselves
   std::shared_ptr<DevBuf> dinv, y, r, b;
   T omega = T(0);
   int64_t n = 0;
@@ -237,6 +237,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       d.P = upload<T>(h.P, s);
       d.AP = upload<T>(AP, s);
       d.dinv = upload_vec<T>(h.dinv, s);
+      if (l == 1 && keep_a0) d.A0 = upload<T>(h.A, s);  // exact coarse solves of the training loss
       if (l == 0 && keep_a0) {
         d.A0 = upload<T>(h.A, s);
         d.R0 = upload<T>(h.R, s);
@@ -1074,10 +1075,10 @@ void mlp_upload_weights(fsi_ctx& c, MlpState& M, const float* W1, const float* W
 // One gradient pass over m samples already on the device (Z [m][KP] BF16,
 // E [m][d], W [m]) starting at `first`: gradient into M.g, loss sum into M.loss.
 void mlp_grad_pass(fsi_ctx& c, MlpState& M, const unsigned short* Z, const float* E, const float* W, int64_t first,
-                   int64_t m, float coef) {
+                   int64_t m, float coef, bool given = false) {
   hipStream_t s = c.stream;
-  const int tpw = 4;
   const int64_t tiles = (m + 15) / 16;
+  const int tpw = int(std::max<int64_t>(4, (tiles + 2047) / 2048));  // at most ~2048 partial gradients
   const int64_t waves = (tiles + tpw - 1) / tpw;
   const int64_t blocks = (waves + 3) / 4;
   const int64_t nwv = blocks * 4;
@@ -1085,12 +1086,16 @@ void mlp_grad_pass(fsi_ctx& c, MlpState& M, const unsigned short* Z, const float
   if (M.part.bytes < need) M.part.alloc(need);
   if (M.part_loss.bytes < sizeof(float) * nwv) M.part_loss.alloc(sizeof(float) * nwv);
   const MlpW& w = M.use.w;
-  if (M.d == 2)
-    mlp_train_kernel<2><<<unsigned(blocks), 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, M.part.as<float>(),
-                                                          M.part_loss.as<float>());
-  else
-    mlp_train_kernel<3><<<unsigned(blocks), 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, M.part.as<float>(),
-                                                          M.part_loss.as<float>());
+  float* part = M.part.as<float>();
+  float* pl = M.part_loss.as<float>();
+  const unsigned nb = unsigned(blocks);
+  if (M.d == 2) {
+    if (given) mlp_train_kernel<2, true><<<nb, 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, part, pl);
+    else mlp_train_kernel<2, false><<<nb, 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, part, pl);
+  } else {
+    if (given) mlp_train_kernel<3, true><<<nb, 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, part, pl);
+    else mlp_train_kernel<3, false><<<nb, 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, part, pl);
+  }
   mlp_grad_reduce_kernel<<<unsigned((M.nparam() + 255) / 256), 256, 0, s>>>(
       int(nwv), M.nparam(), M.part.as<float>(), M.part_loss.as<float>(), M.g.as<float>(), M.loss.as<float>());
 }
@@ -1170,9 +1175,10 @@ void mlp_samples(const MlpState& M, const T* b, const T* dinv, const double* e, 
   }
 }
 
-// Train the learned smoothers on the recorded finest-level residuals.
+// Train the learned smoothers on the recorded finest-level residuals with
+// the squared-error loss against exact corrections (FSI_MLP_LOSS_L2).
 template <typename T>
-void mlp_train_impl(fsi_ctx& c, Precond<T>& P, const fsi_mlp_train_opts& o, fsi_mlp_train_info& info) {
+void mlp_train_l2(fsi_ctx& c, Precond<T>& P, const fsi_mlp_train_opts& o, fsi_mlp_train_info& info) {
   hipStream_t s = c.stream;
   for (int i = 0; i < 2; ++i) {
     MlpState& M = c.mlp[i];
@@ -1261,6 +1267,243 @@ void mlp_train_impl(fsi_ctx& c, Precond<T>& P, const fsi_mlp_train_opts& o, fsi_
   }
   c.drop_graphs();
   c.m_alloc = -1;
+}
+
+// ------------------------------------------------ two-grid energy training
+// For a residual b of level 0 (exact correction e = A^{-1} b) and the
+// network's correction delta, the loss is the A-norm error that is left once
+// an exact coarse-grid correction follows delta, minus a constant:
+//     L = ||(I - P A_1^{-1} R A)(e - delta)||_A^2 - e.b .
+// With r = b - A delta, rc = R r and c = A_1^{-1} rc this is
+//     L = -delta.b - delta.r - rc.c,   dL/d delta = -2 (r - A P c)
+// (A symmetric, R = P^T; no exact solve on level 0 is needed).  Minimising it
+// asks the network for the error the coarse grid cannot represent, which is
+// what a pre-smoother has to remove.
+struct EnergyWork {
+  DevBuf r, g, rc, cc, t, t2;
+  template <typename T>
+  void alloc(int64_t n, int64_t nc) {
+    for (DevBuf* b : {&r, &g}) b->alloc(sizeof(T) * size_t(n));
+    for (DevBuf* b : {&rc, &cc, &t, &t2}) b->alloc(sizeof(T) * size_t(nc));
+  }
+};
+
+// cc = A_1^{-1} rc: the dense inverse when level 1 is the coarsest, otherwise
+// `cycles` Richardson steps with plain V-cycles from level 1.
+template <typename T, int NV>
+void coarse_solve(DHier<T>& H, const T* rc, T* cc, T* t, T* t2, int cycles, hipStream_t s) {
+  if (H.lev.size() == 2) {
+    dense_gemv_kernel<T, T, NV><<<grid_for(H.nc, kBlock / 64), kBlock, 0, s>>>(H.nc, H.cinv->template as<double>(), rc, cc);
+    return;
+  }
+  DLevel<T>& d1 = H.lev[1];
+  const int64_t n = d1.n * NV;
+  vcycle_rec<T, NV>(H, 1, rc, cc, s, true);
+  for (int k = 1; k < cycles; ++k) {
+    launch_rows<T, NV>(d1.A0, GatherPlain<T, NV>{cc}, EpiSub<T, NV>{rc, t}, s);
+    vcycle_rec<T, NV>(H, 1, t, t2, s, true);
+    vadd_kernel<T><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, cc, t2);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void scale_to_f32_kernel(int64_t n, const T* __restrict__ x, double f,
+                                                              float* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    y[i] = float(f * double(x[i]));
+}
+
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void cast_scale_kernel(int64_t n, const TI* __restrict__ x, double f,
+                                                            TO* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    y[i] = TO(f * double(x[i]));
+}
+
+// x.y of two device vectors, summed on the host in FP64 (loss reporting only).
+template <typename T>
+double host_dot(int64_t n, const T* pa, const T* pb, hipStream_t s) {
+  std::vector<T> x(n), y(n);
+  HIP_TRY(hipMemcpyAsync(x.data(), pa, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(y.data(), pb, sizeof(T) * n, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  double acc = 0.0;
+  for (int64_t i = 0; i < n; ++i) acc += double(x[i]) * double(y[i]);
+  return acc;
+}
+
+// dy = coef dL/d delta (FP32) for one residual b; *loss = L if requested.
+template <typename T, int NV>
+void energy_grad(DHier<T>& H, EnergyWork& w, const T* delta, const T* b, double coef, float* dy, int cycles,
+                 hipStream_t s, double* loss) {
+  DLevel<T>& d0 = H.lev[0];
+  const int64_t n = d0.n * NV, nc = H.lev[1].n * NV;
+  T* r = w.r.as<T>();
+  T* g = w.g.as<T>();
+  T* rc = w.rc.as<T>();
+  T* cc = w.cc.as<T>();
+  launch_rows<T, NV>(d0.A0, GatherPlain<T, NV>{delta}, EpiSub<T, NV>{b, r}, s);  // r = b - A delta
+  launch_rows<T, NV>(d0.R0, GatherPlain<T, NV>{r}, EpiStore<T, NV>{rc}, s);      // rc = R r
+  coarse_solve<T, NV>(H, rc, cc, w.t.as<T>(), w.t2.as<T>(), cycles, s);         // cc = A_1^{-1} rc
+  launch_rows<T, NV>(d0.AP, GatherPlain<T, NV>{cc}, EpiSub<T, NV>{r, g}, s);     // g = r - A P cc
+  scale_to_f32_kernel<T><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, g, -2.0 * coef, dy);
+  if (loss) {
+    const double db = host_dot<T>(n, delta, b, s);
+    const double dr = host_dot<T>(n, delta, r, s);
+    const double rcc = host_dot<T>(nc, rc, cc, s);
+    *loss = -db - dr - rcc;
+  }
+}
+
+// Network inputs (BF16 rows) of one level-0 vector b of learned smoother M.
+template <typename T>
+void mlp_inputs(const MlpState& M, const T* b, const T* dinv, unsigned short* Z, hipStream_t s) {
+  const unsigned g = grid_for(M.n_nodes, 256);
+  const int32_t* nbr = M.nbr.as<int32_t>();
+  if (M.d == 2) {
+    if (M.use.per_dof) mlp_inputs_kernel<2, true, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, Z);
+    else mlp_inputs_kernel<2, false, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, Z);
+  } else {
+    if (M.use.per_dof) mlp_inputs_kernel<3, true, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, Z);
+    else mlp_inputs_kernel<3, false, T><<<g, 256, 0, s>>>(M.n_nodes, nbr, b, dinv, Z);
+  }
+}
+
+template <typename T>
+void mlp_forward_rows(const MlpState& M, int64_t m, const unsigned short* Z, T* y, hipStream_t s) {
+  const unsigned g = grid_for(m, 64);
+  if (M.d == 2) mlp_forward_rows_kernel<2, T><<<g, 256, 0, s>>>(m, Z, M.use.w, y);
+  else mlp_forward_rows_kernel<3, T><<<g, 256, 0, s>>>(m, Z, M.use.w, y);
+}
+
+template <typename T, int NV>
+void energy_fit(fsi_ctx& c, MlpState& M, DHier<T>& H, const std::vector<double>& dv, bool per_node,
+                const fsi_mlp_train_opts& o, int which, fsi_mlp_train_info& info) {
+  hipStream_t s = c.stream;
+  const int kp = M.kp();
+  const int64_t nn = M.n_nodes, n = H.lev[0].n * NV, nc = H.lev[1].n * NV;
+  const T* dinv = H.lev[0].dinv->template as<T>();
+  // recorded residuals in a seeded random order, scaled to ||b||_{D^{-1}} = 1
+  std::vector<size_t> order(M.rec.vecs.size());
+  for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+  std::mt19937_64 rng(uint64_t(o.seed) * 2 + uint64_t(which));
+  for (size_t k = order.size(); k > 1; --k) std::swap(order[k - 1], order[size_t(rng() % k)]);
+  std::vector<double> hb(n), scale;
+  std::vector<size_t> keep;
+  for (size_t k : order) {
+    HIP_TRY(hipMemcpyAsync(hb.data(), M.rec.vecs[k]->p, 8 * size_t(n), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    double ss = 0.0;
+    for (int64_t q = 0; q < n; ++q) ss += hb[q] * hb[q] * (per_node ? dv[q / NV] : dv[q]);
+    if (!(ss > 0.0) || !std::isfinite(ss)) continue;
+    keep.push_back(k);
+    scale.push_back(1.0 / std::sqrt(ss));
+  }
+  const int64_t nvec = int64_t(keep.size());
+  info.vectors[which] = int32_t(nvec);
+  info.samples[which] = nvec * nn;
+  if (nvec == 0) return;
+  DevBuf Bs, Z, Y, DY;
+  Bs.alloc(sizeof(T) * size_t(n) * nvec);
+  Z.alloc(2 * size_t(nn) * kp * nvec);
+  for (int64_t j = 0; j < nvec; ++j) {
+    T* bj = Bs.as<T>() + j * n;
+    cast_scale_kernel<double, T><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, M.rec.vecs[keep[j]]->as<double>(),
+                                                                          scale[j], bj);
+    mlp_inputs<T>(M, bj, dinv, Z.as<unsigned short>() + size_t(j) * nn * kp, s);
+  }
+  const int64_t k = std::min<int64_t>(nvec, std::max<int64_t>(1, (int64_t(o.batch) + nn - 1) / nn));
+  Y.alloc(sizeof(T) * size_t(n) * k);
+  DY.alloc(4 * size_t(n) * k);
+  EnergyWork w;
+  w.alloc<T>(n, nc);
+  const int cyc = std::max(1, o.coarse_cycles);
+  auto eval = [&]() {
+    double acc = 0.0;
+    for (int64_t j0 = 0; j0 < nvec; j0 += k) {
+      const int64_t kk = std::min<int64_t>(k, nvec - j0);
+      mlp_forward_rows<T>(M, kk * nn, Z.as<unsigned short>() + size_t(j0) * nn * kp, Y.as<T>(), s);
+      for (int64_t j = 0; j < kk; ++j) {
+        double l = 0.0;
+        energy_grad<T, NV>(H, w, Y.as<T>() + j * n, Bs.as<T>() + (j0 + j) * n, 1.0, DY.as<float>(), cyc, s, &l);
+        acc += l;
+      }
+    }
+    return acc / double(nvec);
+  };
+  info.loss_first[which] = eval();
+  for (int step = 0; step < o.steps; ++step) {
+    const int64_t j0 = (int64_t(step) * k) % nvec;
+    const int64_t kk = std::min<int64_t>(k, nvec - j0);
+    const unsigned short* Zb = Z.as<unsigned short>() + size_t(j0) * nn * kp;
+    mlp_forward_rows<T>(M, kk * nn, Zb, Y.as<T>(), s);
+    for (int64_t j = 0; j < kk; ++j)
+      energy_grad<T, NV>(H, w, Y.as<T>() + j * n, Bs.as<T>() + (j0 + j) * n, 1.0 / double(kk),
+                         DY.as<float>() + j * n, cyc, s, nullptr);
+    mlp_grad_pass(c, M, Zb, DY.as<float>(), nullptr, 0, kk * nn, 1.f, true);
+    mlp_adam(c, M, float(o.lr));
+  }
+  info.loss_last[which] = eval();
+  M.use.enabled = true;
+}
+
+template <typename T>
+void mlp_train_energy(fsi_ctx& c, Precond<T>& P, const fsi_mlp_train_opts& o, fsi_mlp_train_info& info) {
+  for (int i = 0; i < 2; ++i) {
+    MlpState& M = c.mlp[i];
+    info.vectors[i] = 0;
+    info.samples[i] = 0;
+    info.loss_first[i] = info.loss_last[i] = 0.0;
+    if (M.n_nodes == 0 || !M.have_weights || M.rec.vecs.empty()) continue;
+    const int h = i == 0 ? FSI_H_M : FSI_H_SIG;
+    DHier<T>& H = P.H[h];
+    if (!H.xm || H.lev.size() < 2) continue;
+    const std::vector<double>& dv = c.host_h[h].levels[0].dinv;
+    const bool per_node = i == 0;
+    if (H.nv == 1) energy_fit<T, 1>(c, M, H, dv, per_node, o, i, info);
+    else if (H.nv == 2) energy_fit<T, 2>(c, M, H, dv, per_node, o, i, info);
+    else energy_fit<T, 3>(c, M, H, dv, per_node, o, i, info);
+  }
+  c.drop_graphs();
+  c.m_alloc = -1;
+}
+
+// Gradient of the energy loss for one level-0 residual b (device FP64),
+// copied out in the natural weight layouts.
+template <typename T, int NV>
+double energy_grad_once(fsi_ctx& c, MlpState& M, DHier<T>& H, const double* b, int cycles) {
+  hipStream_t s = c.stream;
+  const int64_t nn = M.n_nodes, n = H.lev[0].n * NV, nc = H.lev[1].n * NV;
+  DevBuf bt, Z, Y, DY;
+  bt.alloc(sizeof(T) * size_t(n));
+  Z.alloc(2 * size_t(nn) * M.kp());
+  Y.alloc(sizeof(T) * size_t(n));
+  DY.alloc(4 * size_t(n));
+  cast_kernel<double, T><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, b, bt.as<T>());
+  mlp_inputs<T>(M, bt.as<T>(), H.lev[0].dinv->template as<T>(), Z.as<unsigned short>(), s);
+  mlp_forward_rows<T>(M, nn, Z.as<unsigned short>(), Y.as<T>(), s);
+  EnergyWork w;
+  w.alloc<T>(n, nc);
+  double loss = 0.0;
+  energy_grad<T, NV>(H, w, Y.as<T>(), bt.as<T>(), 1.0, DY.as<float>(), cycles, s, &loss);
+  mlp_grad_pass(c, M, Z.as<unsigned short>(), DY.as<float>(), nullptr, 0, nn, 1.f, true);
+  HIP_TRY(hipStreamSynchronize(s));
+  return loss;
+}
+
+// Copy M.g (padded layouts) to natural W1 (K x 64), W2 (64 x 64), W3 (64 x d).
+void unpack_grad(fsi_ctx& c, MlpState& M, float* G1, float* G2, float* G3) {
+  const int kp = M.kp(), kin = M.kin(), d = M.d;
+  std::vector<float> g(size_t(M.nparam()));
+  HIP_TRY(hipMemcpyAsync(g.data(), M.g.p, 4 * g.size(), hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  for (int k = 0; k < kin; ++k)
+    for (int h = 0; h < 64; ++h) G1[k * 64 + h] = g[size_t(k) * 64 + h];
+  const float* g2 = g.data() + size_t(kp) * 64;
+  for (int a = 0; a < 64 * 64; ++a) G2[a] = g2[a];
+  const float* g3 = g2 + 64 * 64;
+  for (int h = 0; h < 64; ++h)
+    for (int q = 0; q < d; ++q) G3[h * d + q] = g3[h * 16 + q];
 }
 
 }  // namespace
@@ -1705,6 +1948,8 @@ void fsi_default_mlp_train_opts(fsi_mlp_train_opts* o) {
   o->exact_tol = 1e-10;
   o->exact_maxit = 300;
   o->seed = 0;
+  o->loss = FSI_MLP_LOSS_ENERGY;
+  o->coarse_cycles = 4;
 }
 
 fsi_status fsi_mlp_set_weights(fsi_ctx* ctx, int which, const float* W1, const float* W2, const float* W3) {
@@ -1808,19 +2053,36 @@ fsi_status fsi_mlp_loss_grad(fsi_ctx* ctx, int which, int64_t m, const float* Z,
     HIP_TRY(hipMemcpyAsync(dE.p, E, 4 * size_t(m) * d, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(dW.p, w, 4 * size_t(m), hipMemcpyHostToDevice, s));
     mlp_grad_pass(c, M, dZ.as<unsigned short>(), dE.as<float>(), dW.as<float>(), 0, m, float(2.0 / double(m)));
-    std::vector<float> g(size_t(M.nparam()));
     float lsum = 0.f;
-    HIP_TRY(hipMemcpyAsync(g.data(), M.g.p, 4 * g.size(), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(&lsum, M.loss.p, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    for (int k = 0; k < kin; ++k)
-      for (int h = 0; h < 64; ++h) G1[k * 64 + h] = g[size_t(k) * 64 + h];
-    const float* g2 = g.data() + size_t(kp) * 64;
-    for (int a = 0; a < 64 * 64; ++a) G2[a] = g2[a];
-    const float* g3 = g2 + 64 * 64;
-    for (int h = 0; h < 64; ++h)
-      for (int q = 0; q < d; ++q) G3[h * d + q] = g3[h * 16 + q];
+    unpack_grad(c, M, G1, G2, G3);
     *loss = double(lsum) / double(m);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_energy_grad(fsi_ctx* ctx, int which, const double* b, int coarse_cycles, float* G1, float* G2,
+                               float* G3, double* loss) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    MlpState& M = mlp_state(c, which);
+    if (!M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    if (!G1 || !G2 || !G3 || !loss || coarse_cycles < 1) throw Error(FSI_ERR_ARG, "bad arguments");
+    check_device_ptr(b, "b");
+    double l = 0.0;
+    if (c.precision == FSI_P_F64) {
+      DHier<double>& H = c.p64->H[which];
+      if (H.nv == 1) l = energy_grad_once<double, 1>(c, M, H, b, coarse_cycles);
+      else if (H.nv == 2) l = energy_grad_once<double, 2>(c, M, H, b, coarse_cycles);
+      else l = energy_grad_once<double, 3>(c, M, H, b, coarse_cycles);
+    } else {
+      DHier<float>& H = c.p32->H[which];
+      if (H.nv == 1) l = energy_grad_once<float, 1>(c, M, H, b, coarse_cycles);
+      else if (H.nv == 2) l = energy_grad_once<float, 2>(c, M, H, b, coarse_cycles);
+      else l = energy_grad_once<float, 3>(c, M, H, b, coarse_cycles);
+    }
+    unpack_grad(c, M, G1, G2, G3);
+    *loss = l;
     return FSI_OK;
   });
 }
@@ -1847,15 +2109,21 @@ fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_t
     fsi_mlp_train_opts o;
     fsi_default_mlp_train_opts(&o);
     if (opts) o = *opts;
-    if (o.steps < 0 || o.batch < 16 || !(o.lr > 0.0) || !(o.exact_tol > 0.0) || o.exact_maxit < 1)
+    if (o.steps < 0 || o.batch < 16 || !(o.lr > 0.0) || !(o.exact_tol > 0.0) || o.exact_maxit < 1 ||
+        (o.loss != FSI_MLP_LOSS_L2 && o.loss != FSI_MLP_LOSS_ENERGY) || o.coarse_cycles < 1)
       throw Error(FSI_ERR_ARG, "bad training options");
     bool any = false;
     for (auto& M : c.mlp) any = any || (M.n_nodes > 0 && M.have_weights && !M.rec.vecs.empty());
     if (!any) throw Error(FSI_ERR_STATE, "nothing to train: set weights and record residuals first");
     for (auto& M : c.mlp) M.rec.active = false;
     fsi_mlp_train_info local{};
-    if (c.precision == FSI_P_F64) mlp_train_impl<double>(c, *c.p64, o, local);
-    else mlp_train_impl<float>(c, *c.p32, o, local);
+    if (o.loss == FSI_MLP_LOSS_L2) {
+      if (c.precision == FSI_P_F64) mlp_train_l2<double>(c, *c.p64, o, local);
+      else mlp_train_l2<float>(c, *c.p32, o, local);
+    } else {
+      if (c.precision == FSI_P_F64) mlp_train_energy<double>(c, *c.p64, o, local);
+      else mlp_train_energy<float>(c, *c.p32, o, local);
+    }
     if (info) *info = local;
     return FSI_OK;
   });

@@ -110,6 +110,18 @@ struct MlpTile {
 // z from b through the stencil table nbr [n][S] (-1: no neighbour) and the
 // inverse diagonal (per node when PER_DOF is false: the scalar Laplacian
 // acting on D interleaved components; per dof otherwise).
+// Input k (= s D + c) of node `node`: component c of D^{-1} b at stencil node s.
+template <int D, bool PER_DOF, typename T>
+__device__ __forceinline__ float node_input(int64_t node, int k, const int32_t* __restrict__ nbr,
+                                            const T* __restrict__ b, const T* __restrict__ dinv) {
+  using M = MlpDims<D>;
+  if (k >= M::KIN) return 0.f;
+  const int s = k / D, c = k % D;
+  const int32_t nb = nbr[node * M::S + s];
+  if (nb < 0) return 0.f;
+  return float((PER_DOF ? dinv[int64_t(nb) * D + c] : dinv[nb]) * b[int64_t(nb) * D + c]);
+}
+
 template <int D, bool PER_DOF, typename T>
 __global__ __launch_bounds__(256) void mlp_infer_kernel(int64_t n_nodes, const int32_t* __restrict__ nbr,
                                                          const T* __restrict__ b, const T* __restrict__ dinv,
@@ -121,24 +133,37 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(int64_t n_nodes, const i
   if (tile * 16 >= n_nodes) return;  // whole wave leaves together
   bf16x4_t zf[M::KB];
 #pragma unroll
-  for (int kb = 0; kb < M::KB; ++kb) {
+  for (int kb = 0; kb < M::KB; ++kb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int k = 16 * kb + 4 * q + j;
-      float v = 0.f;
-      if (node < n_nodes && k < M::KIN) {
-        const int s = k / D, c = k % D;
-        const int32_t nb = nbr[node * M::S + s];
-        if (nb >= 0) v = float((PER_DOF ? dinv[int64_t(nb) * D + c] : dinv[nb]) * b[int64_t(nb) * D + c]);
-      }
-      zf[kb][j] = short(f2bf(v));
-    }
-  }
+    for (int j = 0; j < 4; ++j)
+      zf[kb][j] = short(f2bf(node < n_nodes ? node_input<D, PER_DOF, T>(node, 16 * kb + 4 * q + j, nbr, b, dinv) : 0.f));
   MlpTile<D> t;
   t.forward(w, zf, n, q);
   if (q == 0 && node < n_nodes)
 #pragma unroll
     for (int i = 0; i < D; ++i) x[node * D + i] = T(t.y[i]);
+}
+
+// Forward over m stored input rows (Z [m][KP] BF16): y[row * D + c].
+template <int D, typename T>
+__global__ __launch_bounds__(256) void mlp_forward_rows_kernel(int64_t m, const unsigned short* __restrict__ Z, MlpW w,
+                                                                T* __restrict__ y) {
+  using M = MlpDims<D>;
+  const int lane = threadIdx.x % 64, n = lane % 16, q = lane / 16;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+  const int64_t row = tile * 16 + n;
+  if (tile * 16 >= m) return;
+  bf16x4_t zf[M::KB];
+#pragma unroll
+  for (int kb = 0; kb < M::KB; ++kb) {
+    if (row < m) zf[kb] = load4(Z + row * M::KP + 16 * kb + 4 * q);
+    else zf[kb] = bf16x4_t{0, 0, 0, 0};
+  }
+  MlpTile<D> t;
+  t.forward(w, zf, n, q);
+  if (q == 0 && row < m)
+#pragma unroll
+    for (int i = 0; i < D; ++i) y[row * D + i] = T(t.y[i]);
 }
 
 // Training: loss and weight gradients of (coef) * sum_s w_s ||delta(z_s) - e_s||^2
@@ -147,7 +172,8 @@ __global__ __launch_bounds__(256) void mlp_infer_kernel(int64_t n_nodes, const i
 // 16-sample tiles starting at sample `first`, accumulates its gradient in
 // registers and writes it to part[wave][NPARAM] (layouts [k][hid], [in][out],
 // [hid][NP]) plus its loss to part_loss[wave].
-template <int D>
+// With GIVEN, E holds dL/dy itself (scaled by coef) and wgt is unused.
+template <int D, bool GIVEN>
 __global__ __launch_bounds__(256) void mlp_train_kernel(int64_t first, int64_t m, int tiles_per_wave,
                                                          const unsigned short* __restrict__ Z,
                                                          const float* __restrict__ E, const float* __restrict__ wgt,
@@ -194,12 +220,17 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(int64_t first, int64_t m
     // dY^T: lane holds dy[node n][c = 4 q + i]
     f32x4_t dy = {0.f, 0.f, 0.f, 0.f};
     if (q == 0 && valid) {
-      const float ws = wgt[smp];
+      if (GIVEN) {
 #pragma unroll
-      for (int i = 0; i < D; ++i) {
-        const float r = tl.y[i] - E[smp * D + i];
-        lsum += ws * r * r;
-        dy[i] = coef * ws * r;
+        for (int i = 0; i < D; ++i) dy[i] = coef * E[smp * D + i];
+      } else {
+        const float ws = wgt[smp];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+          const float r = tl.y[i] - E[smp * D + i];
+          lsum += ws * r * r;
+          dy[i] = coef * ws * r;
+        }
       }
     }
     bf16x4_t dyf;
@@ -343,17 +374,20 @@ __global__ __launch_bounds__(256) void mlp_samples_kernel(int64_t n_nodes, const
   using M = MlpDims<D>;
   const int64_t node = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (node >= n_nodes) return;
-  for (int k = 0; k < M::KP; ++k) {
-    float v = 0.f;
-    if (k < M::KIN) {
-      const int s = k / D, c = k % D;
-      const int32_t nb = nbr[node * M::S + s];
-      if (nb >= 0) v = scale * float((PER_DOF ? dinv[int64_t(nb) * D + c] : dinv[nb]) * b[int64_t(nb) * D + c]);
-    }
-    Z[node * M::KP + k] = f2bf(v);
-  }
+  for (int k = 0; k < M::KP; ++k) Z[node * M::KP + k] = f2bf(scale * node_input<D, PER_DOF, T>(node, k, nbr, b, dinv));
   for (int c = 0; c < D; ++c) E[node * D + c] = scale * float(e[node * D + c]);
   W[node] = wnode[node];
+}
+
+// Network inputs of every node for one residual b: Z [n][KP] BF16.
+template <int D, bool PER_DOF, typename T>
+__global__ __launch_bounds__(256) void mlp_inputs_kernel(int64_t n_nodes, const int32_t* __restrict__ nbr,
+                                                          const T* __restrict__ b, const T* __restrict__ dinv,
+                                                          unsigned short* __restrict__ Z) {
+  using M = MlpDims<D>;
+  const int64_t node = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (node >= n_nodes) return;
+  for (int k = 0; k < M::KP; ++k) Z[node * M::KP + k] = f2bf(node_input<D, PER_DOF, T>(node, k, nbr, b, dinv));
 }
 
 // Rows `perm` of a sample set into a shuffled copy.

@@ -65,7 +65,11 @@ class CSolveInfo(ctypes.Structure):
 
 class CMlpTrainOpts(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_double),
-                ("exact_tol", ctypes.c_double), ("exact_maxit", ctypes.c_int32), ("seed", ctypes.c_uint32)]
+                ("exact_tol", ctypes.c_double), ("exact_maxit", ctypes.c_int32), ("seed", ctypes.c_uint32),
+                ("loss", ctypes.c_int32), ("coarse_cycles", ctypes.c_int32)]
+
+
+MLP_LOSS = {"l2": 0, "energy": 1}
 
 
 class CMlpTrainInfo(ctypes.Structure):
@@ -112,6 +116,7 @@ def _declare(lib):
         "fsi_mlp_enable": ([P, i32, i32], i32),
         "fsi_mlp_forward": ([P, i32, P, P], i32),
         "fsi_mlp_loss_grad": ([P, i32, i64, P, P, P, P, P, P, P], i32),
+        "fsi_mlp_energy_grad": ([P, i32, P, i32, P, P, P, P], i32),
         "fsi_mlp_collect": ([P, i32, i32], i32),
         "fsi_mlp_train": ([P, ctypes.POINTER(CMlpTrainOpts), ctypes.POINTER(CMlpTrainInfo)], i32),
         "fsi_default_precond_opts": ([ctypes.POINTER(CPrecondOpts)], None),
@@ -144,7 +149,7 @@ def exported_symbols():
             "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_get_level", "fsi_get_aggregates",
             "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
             "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
-            "fsi_mlp_loss_grad", "fsi_mlp_collect", "fsi_mlp_train"]
+            "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train"]
 
 
 def _csr_struct(nrows, ncols, rowptr, col, val, keep):
@@ -376,11 +381,23 @@ class FsiSolver:
                                                *[g.ctypes.data for g in G], ctypes.byref(loss)))
         return loss.value, G
 
+    def mlp_energy_grad(self, which, b, d: int, coarse_cycles: int = 4):
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        n = self._hier_len(w)
+        k_in = 3 ** d * d
+        G = [np.empty((k_in, 64), np.float32), np.empty((64, 64), np.float32), np.empty((64, d), np.float32)]
+        loss = ctypes.c_double()
+        self._check(self.lib.fsi_mlp_energy_grad(self.ctx, w, _dptr(b, n, "b"), int(coarse_cycles),
+                                                 *[g.ctypes.data for g in G], ctypes.byref(loss)))
+        return loss.value, G
+
     def mlp_collect(self, max_vectors: int, every: int = 1):
         self._check(self.lib.fsi_mlp_collect(self.ctx, int(max_vectors), int(every)))
 
-    def mlp_train(self, steps=400, batch=16384, lr=1e-3, exact_tol=1e-10, exact_maxit=300, seed=0):
-        o = CMlpTrainOpts(int(steps), int(batch), float(lr), float(exact_tol), int(exact_maxit), int(seed))
+    def mlp_train(self, steps=400, batch=16384, lr=1e-3, exact_tol=1e-10, exact_maxit=300, seed=0,
+                  loss="energy", coarse_cycles=4):
+        o = CMlpTrainOpts(int(steps), int(batch), float(lr), float(exact_tol), int(exact_maxit), int(seed),
+                          MLP_LOSS[loss], int(coarse_cycles))
         info = CMlpTrainInfo()
         self._check(self.lib.fsi_mlp_train(self.ctx, ctypes.byref(o), ctypes.byref(info)))
         return dict(vectors=list(info.vectors), samples=list(info.samples),

@@ -68,13 +68,32 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.fsi_destroy(None) == 0
 
 
-def test_ctypes_structs_match_the_header_layout():
+STRUCTS = [("fsi_csr", "CCsr"), ("fsi_layout", "CLayout"), ("fsi_precond_opts", "CPrecondOpts"),
+           ("fsi_solve_opts", "CSolveOpts"), ("fsi_solve_info", "CSolveInfo"),
+           ("fsi_mlp_train_opts", "CMlpTrainOpts"), ("fsi_mlp_train_info", "CMlpTrainInfo")]
+
+
+def test_ctypes_structs_match_the_header_layout(tmp_path):
+    """Size and every field offset of the binding's structs equal what a C
+    compiler makes of the header."""
     from paper_1801_05648_amd import fsi
-    assert ctypes.sizeof(fsi.CCsr) == 48
-    assert ctypes.sizeof(fsi.CLayout) == 4 + 4 + 5 * 8 + 8 + 8 + 8 + 8 + 8
-    assert ctypes.sizeof(fsi.CPrecondOpts) == 24
-    assert ctypes.sizeof(fsi.CSolveOpts) == 24
-    assert ctypes.sizeof(fsi.CSolveInfo) == 64
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "fsi.h"', 'int main(void) {']
+    for cname, pname in STRUCTS:
+        lines.append(f'  printf("{pname} size %zu\\n", sizeof({cname}));')
+        for f, _ in getattr(fsi, pname)._fields_:
+            lines.append(f'  printf("{pname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines += ['  return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for _, pname in STRUCTS:
+        cls = getattr(fsi, pname)
+        assert got[(pname, "size")] == ctypes.sizeof(cls), pname
+        for f, _ in cls._fields_:
+            assert got[(pname, f)] == getattr(cls, f).offset, (pname, f)
 
 
 def test_header_compiles_as_c99(tmp_path):

@@ -133,3 +133,90 @@ def test_learned_vcycle_falls_back_on_bad_corrections():
     x = x + L.omega * L.dinv * (b[:, 0] - L.A @ x)
     assert np.allclose(z[:, 0], x, rtol=0, atol=1e-14 * np.abs(x).max())
     assert not np.allclose(z, ref)
+
+
+def _spd_case(seed=0, n=30, nc=7):
+    rng = np.random.default_rng(seed)
+    A = np.diag(2.0 + rng.random(n)) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    P = np.zeros((n, nc))
+    for i in range(n):  # piecewise-linear interpolation from nc coarse points
+        t = i * (nc - 1) / (n - 1)
+        k = min(int(t), nc - 2)
+        P[i, k] += 1 - (t - k)
+        P[i, k + 1] += t - k
+    return A, P, P.T @ A @ P, rng
+
+
+def test_energy_gradient_matches_central_differences():
+    A, P, Ac, rng = _spd_case()
+    b = rng.standard_normal((30, 2))
+    delta = rng.standard_normal((30, 2))
+    L, g = mlp.two_grid_energy(delta, b, A, P, Ac)
+    h = 1e-6
+    for _ in range(10):
+        i, c = rng.integers(30), rng.integers(2)
+        dp, dm = delta.copy(), delta.copy()
+        dp[i, c] += h
+        dm[i, c] -= h
+        fd = (mlp.two_grid_energy(dp, b, A, P, Ac)[0] - mlp.two_grid_energy(dm, b, A, P, Ac)[0]) / (2 * h)
+        assert abs(fd - g[i, c]) <= 1e-6 * max(1.0, abs(fd))
+
+
+def test_energy_minimum_is_the_coarse_complement_of_the_error():
+    """L + e.b >= 0 everywhere, = 0 with zero gradient at delta = e - P Ac^{-1} P^T b
+    (the part of the error the coarse grid cannot represent), and with
+    P = I the coarse correction is exact for every delta."""
+    A, P, Ac, rng = _spd_case(1)
+    b = rng.standard_normal((30, 1))
+    e = np.linalg.solve(A, b)
+    eb = float(np.sum(e * b))
+    for _ in range(5):
+        L, _ = mlp.two_grid_energy(rng.standard_normal((30, 1)), b, A, P, Ac)
+        assert L + eb >= -1e-12 * eb
+    dstar = e - P @ np.linalg.solve(Ac, P.T @ b)
+    L, g = mlp.two_grid_energy(dstar, b, A, P, Ac)
+    assert abs(L + eb) <= 1e-12 * eb
+    assert np.abs(g).max() <= 1e-12 * np.abs(b).max()
+    I = np.eye(30)
+    for _ in range(3):
+        L, _ = mlp.two_grid_energy(rng.standard_normal((30, 1)), b, A, I, A)
+        assert abs(L + eb) <= 1e-10 * eb
+    # a zero correction leaves exactly the coarse-grid complement of e
+    L0, _ = mlp.two_grid_energy(np.zeros((30, 1)), b, A, P, Ac)
+    w = e - P @ np.linalg.solve(Ac, P.T @ b)
+    assert abs(L0 + eb - float(np.sum(w * (A @ w)))) <= 1e-12 * eb
+
+
+def test_energy_residual_form_identity():
+    """For symmetric A the loss equals -delta.b - delta.r - rc.c with
+    r = b - A delta, rc = P^T r, c = Ac^{-1} rc, and the gradient is
+    -2 (r - A P c): the form a device evaluates without solving on level 0."""
+    A, P, Ac, rng = _spd_case(2)
+    b = rng.standard_normal((30, 1))
+    delta = rng.standard_normal((30, 1))
+    L, g = mlp.two_grid_energy(delta, b, A, P, Ac)
+    r = b - A @ delta
+    rc = P.T @ r
+    c = np.linalg.solve(Ac, rc)
+    L2 = -float(np.sum(delta * b)) - float(np.sum(delta * r)) - float(np.sum(rc * c))
+    assert abs(L - L2) <= 1e-10 * max(1.0, abs(L))
+    assert np.allclose(g, -2.0 * (r - A @ P @ c), rtol=0, atol=1e-10 * np.abs(g).max())
+
+
+def test_network_energy_gradient_matches_central_differences():
+    A, P, Ac, rng = _spd_case(3, n=24)
+    d = 2
+    W = mlp.init_weights(18, 8, d, 4)
+    z = rng.standard_normal((12, 18))
+    b = rng.standard_normal(24)
+    L, G = mlp.energy_loss_and_grad(W, z, b, A, P, Ac)
+    h = 1e-6
+    for li in range(3):
+        for _ in range(4):
+            i, j = rng.integers(W[li].shape[0]), rng.integers(W[li].shape[1])
+            Wp = [x.copy() for x in W]
+            Wm = [x.copy() for x in W]
+            Wp[li][i, j] += h
+            Wm[li][i, j] -= h
+            fd = (mlp.energy_loss_and_grad(Wp, z, b, A, P, Ac)[0] - mlp.energy_loss_and_grad(Wm, z, b, A, P, Ac)[0]) / (2 * h)
+            assert abs(fd - G[li][i, j]) <= 1e-6 * max(1.0, abs(fd))
