@@ -76,6 +76,113 @@ def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def he_init(k_in: int, hidden: int, d: int, seed: int):
+    """Seeded He-style initial weights of the smoother network (the random
+    draws are inputs of the training)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    return [(rng.standard_normal((k_in, hidden)) * np.sqrt(2.0 / k_in)).astype(np.float32),
+            (rng.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)).astype(np.float32),
+            (rng.standard_normal((hidden, d)) * np.sqrt(1.0 / hidden)).astype(np.float32)]
+
+
+def learned_run(args, cfg):
+    """Pseudo-time workload of the learned smoother: record the finest-level
+    V-cycle inputs of the H_M and H_SIG cycles over the Newton solves of the
+    first `train_steps` pseudo-time steps, train both networks on the device
+    (two-grid energy loss), then time the solves of later steps with the plain
+    and with the learned cycles, both to a 1e-8 FP64 true residual."""
+    import numpy as np
+    import torch
+
+    import fsigen
+    from paper_1801_05648_amd import FsiSolver
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream(dev)
+    phase = fsigen.pseudo_time_phase
+    train = [(k, i) for k in range(args.train_steps) for i in range(3)]
+    evals = [(k, 0) for k in args.eval_steps]
+    progress(f"{cfg.name}: training on {len(train)} Newton systems, evaluating {len(evals)}")
+    sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
+    solver = FsiSolver.from_system(sysm, device=0, stream=stream)
+    solver.build_precond(args.precision)
+    d = sysm.dim
+    W = he_init(3 ** d * d, 64, d, seed=args.seed)
+    for which in ("H_M", "H_SIG"):
+        solver.mlp_set_weights(which, *W)
+    solver.mlp_collect(max_vectors=args.max_vectors, every=args.record_every)
+    t_rec = time.perf_counter()
+    for n, (k, i) in enumerate(train):
+        if n:
+            sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
+            solver.set_from_system(sysm)
+            solver.build_precond(args.precision)
+        b = torch.from_numpy(sysm.b).to(dev)
+        _, info = solver.solve(b)
+        progress(f"recorded step {k} solve {i}: {info.iters} iterations")
+    t_rec = time.perf_counter() - t_rec
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tinfo = solver.mlp_train(steps=args.train_iters, batch=16384, lr=2e-3, seed=args.seed, loss="energy")
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3
+    progress(f"trained in {train_ms:.0f} ms: {tinfo}")
+    rows = []
+    for k, i in evals:
+        sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
+        solver.set_from_system(sysm)
+        solver.build_precond(args.precision)
+        b = torch.from_numpy(sysm.b).to(dev)
+        res = {}
+        for mode in ("plain", "learned"):
+            for which in ("H_M", "H_SIG"):
+                solver.mlp_enable(which, mode == "learned")
+            x = torch.zeros_like(b)
+            for _ in range(args.warmup):
+                x.zero_()
+                solver.solve(b, x)
+            times = []
+            for _ in range(args.steps):
+                x.zero_()
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = solver.solve(b, x)
+                torch.cuda.synchronize()
+                times.append((time.perf_counter() - t0) * 1e3)
+                if not info.converged:
+                    raise SystemExit(f"{mode} solve did not converge: {info}")
+            res[mode] = (statistics.mean(times), info, x.clone())
+        diff = float(torch.linalg.norm(res["learned"][2] - res["plain"][2]) / torch.linalg.norm(res["plain"][2]))
+        row = {"step": k, "solve": i,
+               "plain_ms": round(res["plain"][0], 3), "plain_iters": res["plain"][1].iters,
+               "learned_ms": round(res["learned"][0], 3), "learned_iters": res["learned"][1].iters,
+               "learned_fallbacks": res["learned"][1].mlp_fallbacks,
+               "learned_true_rel_resid": res["learned"][1].true_rel_resid,
+               "solution_rel_diff": diff}
+        progress(f"step {k}: {row}")
+        rows.append(row)
+    solver.close()
+    pm = statistics.mean(r["plain_ms"] for r in rows)
+    lm = statistics.mean(r["learned_ms"] for r in rows)
+    line = {
+        "metric": "FGMRES time-to-solution per Newton solve @1e-8 resid, learned vs plain V-cycle smoothing",
+        "value": round(lm, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(lm, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if args.precision == "f64" else "f64-krylov/f32-precond",
+        "data": "synthetic",
+        "config": {"workload": f"pseudo-time FSI Jacobians {'x'.join(map(str, cfg.cells))} cells",
+                   "name": cfg.name, "seed": args.seed, "train_systems": len(train),
+                   "eval_steps": list(args.eval_steps)},
+        "plain_ms": round(pm, 3), "learned_over_plain_time": round(lm / pm, 4),
+        "plain_iters_mean": statistics.mean(r["plain_iters"] for r in rows),
+        "learned_iters_mean": statistics.mean(r["learned_iters"] for r in rows),
+        "record_s": round(t_rec, 1), "train_ms": round(train_ms, 1), "training": tinfo, "per_system": rows,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +192,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned", action="store_true",
+                    help="pseudo-time workload of the learned smoother (plain vs learned cycles)")
+    ap.add_argument("--train-steps", type=int, default=10)
+    ap.add_argument("--eval-steps", type=int, nargs="+", default=[10, 20, 30, 40, 49])
+    ap.add_argument("--train-iters", type=int, default=600)
+    ap.add_argument("--max-vectors", type=int, default=192)
+    ap.add_argument("--record-every", type=int, default=37)
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the A_h product 20 times and a 256 MiB device copy "
                          "(for hardware byte counters); prints nothing else")
@@ -101,6 +215,9 @@ def main():
     from paper_1801_05648_amd import FsiSolver
 
     cfg = fsigen.config(args.config)
+    if args.learned:
+        learned_run(args, cfg)
+        return
     progress(f"generating {cfg.name} seed {args.seed}")
     sysm = fsigen.generate(cfg, seed=args.seed)
     progress(f"N={sysm.N} nnz={sysm.nnz}")
