@@ -280,7 +280,7 @@ void mlp_presmooth(DHier<T>& H, const T* b, hipStream_t s) {
   T* xm = H.xm->template as<T>();
   T* rm = H.rm->template as<T>();
   const T* dinv = d0.dinv->template as<T>();
-  const unsigned grid = grid_for(u.n_nodes, 64);
+  const unsigned grid = mlp_infer_grid(u.n_nodes);
   if (u.d == 2) {
     if (u.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
     else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
@@ -288,9 +288,12 @@ void mlp_presmooth(DHier<T>& H, const T* b, hipStream_t s) {
     if (u.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
     else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
   }
-  launch_rows<T, NV>(d0.A0, GatherPlain<T, NV>{xm}, EpiSub<T, NV>{b, rm}, s);
-  norm_pair_partial_kernel<T><<<kNormBlocks, 256, 0, s>>>(d0.n * NV, rm, b, u.npart);
-  mlp_flag_kernel<<<1, 64, 0, s>>>(kNormBlocks, u.npart, u.flag, u.fallbacks);
+  const DCsr<T>& A = d0.A0;
+  with_group(A.group, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    learned_resid_kernel<T, G, NV><<<kDecideBlocks, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), xm, b,
+                                                                     rm, u.npart);
+  });
 }
 
 // One V(1,1) cycle from level l: two launches per level (down, up) and a
@@ -320,7 +323,8 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
       if (learned)
         vdown_sel_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(
             d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
-            d.R0.drp(), d.R0.dci(), d.R0.dval(), b, d.omega, r, bc, H.rm->template as<T>(), H.mlp->flag, na);
+            d.R0.drp(), d.R0.dci(), d.R0.dval(), b, d.omega, r, bc, H.rm->template as<T>(), H.mlp->npart,
+            H.mlp->flag, H.mlp->fallbacks, na);
       else
         vdown_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
                                                                 d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
@@ -450,7 +454,7 @@ struct MlpState {
   MlpRecord rec;
   std::vector<float> wnode;  // node weights of the loss (mean diagonal / operator mean)
   DevBuf nbr, npart, flag, fallbacks;
-  DevBuf wm, m1, m2, g, loss, w1t, w2t, w2, w3t, w3, part, part_loss;
+  DevBuf wm, m1, m2, g, loss, w1t, w2t, w2, w3t, w3, part, part_loss, part2, loss2;
   int adam_t = 0;
   int nparam() const { return d == 2 ? MlpDims<2>::NPARAM : MlpDims<3>::NPARAM; }
   int kp() const { return d == 2 ? MlpDims<2>::KP : MlpDims<3>::KP; }
@@ -988,7 +992,7 @@ void prepare_mlp(fsi_ctx& c) {
     for (int64_t k = 0; k < n_nodes; ++k) M.wnode[k] = float(dn[k] / mean);
     M.nbr.alloc(sizeof(int32_t) * nbr.size());
     HIP_TRY(hipMemcpyAsync(M.nbr.p, nbr.data(), sizeof(int32_t) * nbr.size(), hipMemcpyHostToDevice, c.stream));
-    if (!M.npart.p) M.npart.alloc(sizeof(double) * 2 * kNormBlocks);
+    if (!M.npart.p) M.npart.alloc(sizeof(double) * 2 * kDecideBlocks);
     if (!M.flag.p) M.flag.alloc(sizeof(int));
     if (!M.fallbacks.p) {
       M.fallbacks.alloc(sizeof(int));
@@ -1078,7 +1082,7 @@ void mlp_grad_pass(fsi_ctx& c, MlpState& M, const unsigned short* Z, const float
                    int64_t m, float coef, bool given = false) {
   hipStream_t s = c.stream;
   const int64_t tiles = (m + 15) / 16;
-  const int tpw = int(std::max<int64_t>(4, (tiles + 2047) / 2048));  // at most ~2048 partial gradients
+  const int tpw = int(std::max<int64_t>(4, (tiles + 1023) / 1024));  // at most ~1024 partial gradients
   const int64_t waves = (tiles + tpw - 1) / tpw;
   const int64_t blocks = (waves + 3) / 4;
   const int64_t nwv = blocks * 4;
@@ -1096,8 +1100,15 @@ void mlp_grad_pass(fsi_ctx& c, MlpState& M, const unsigned short* Z, const float
     if (given) mlp_train_kernel<3, true><<<nb, 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, part, pl);
     else mlp_train_kernel<3, false><<<nb, 256, 0, s>>>(first, m, tpw, Z, E, W, coef, w, part, pl);
   }
-  mlp_grad_reduce_kernel<<<unsigned((M.nparam() + 255) / 256), 256, 0, s>>>(
-      int(nwv), M.nparam(), M.part.as<float>(), M.part_loss.as<float>(), M.g.as<float>(), M.loss.as<float>());
+  if (M.part2.bytes < sizeof(float) * size_t(kGradChunks) * M.nparam()) {
+    M.part2.alloc(sizeof(float) * size_t(kGradChunks) * M.nparam());
+    M.loss2.alloc(sizeof(float) * kGradChunks);
+  }
+  const unsigned pb = unsigned((M.nparam() + 255) / 256);
+  mlp_grad_chunk_kernel<<<dim3(pb, kGradChunks), 256, 0, s>>>(int(nwv), M.nparam(), part, pl, M.part2.as<float>(),
+                                                               M.loss2.as<float>());
+  mlp_grad_reduce_kernel<<<pb, 256, 0, s>>>(M.nparam(), M.part2.as<float>(), M.loss2.as<float>(), M.g.as<float>(),
+                                            M.loss.as<float>());
 }
 
 void mlp_adam(fsi_ctx& c, MlpState& M, float lr) {
@@ -2002,7 +2013,7 @@ fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x) 
     check_device_ptr(b, "b");
     check_device_ptr(x, "x");
     hipStream_t s = c.stream;
-    const unsigned grid = grid_for(M.n_nodes, 64);
+    const unsigned grid = mlp_infer_grid(M.n_nodes);
     const int32_t* nbr = M.nbr.as<int32_t>();
     auto run = [&](auto tag, const auto* bb, const auto* dinv, auto* xx) {
       using T = decltype(tag);

@@ -176,8 +176,95 @@ __global__ __launch_bounds__(kBlock) void vup_kernel(
   }
 }
 
-// Finest-level sweeps with the learned pre-smoothing (flag[0] = 1) or its
-// Jacobi fallback (flag[0] = 0).  With the network's correction x_m the
+// Residual of the learned pre-smoother's correction and the partials of its
+// acceptance test: r = b - A x on every row (fixed grid of kDecideBlocks
+// blocks striding over the rows), part[2 k] = sum of r^2 and part[2 k + 1] =
+// sum of b^2 over the rows of block k, summed in a fixed order.
+constexpr int kDecideBlocks = 1024;
+
+template <typename T, int G, int NV>
+__global__ __launch_bounds__(kBlock) void learned_resid_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                                const int32_t* __restrict__ ci,
+                                                                const T* __restrict__ val, const T* __restrict__ x,
+                                                                const T* __restrict__ b, T* __restrict__ r,
+                                                                double* __restrict__ part) {
+  constexpr int RPB = kBlock / G;
+  __shared__ double sh[2][kBlock / 64];
+  const int lane = threadIdx.x % G;
+  double rr = 0.0, bb = 0.0;
+  for (int64_t row0 = int64_t(blockIdx.x) * RPB; row0 < n; row0 += int64_t(gridDim.x) * RPB) {
+    const int64_t row = row0 + threadIdx.x / G;
+    T acc[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = T(0);
+    if (row < n) row_accumulate<T, G, NV>(rp, ci, val, row, lane, GatherPlain<T, NV>{x}, acc);
+    group_reduce<T, G, NV>(acc);
+    if (lane == 0 && row < n)
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const T bi = b[row * NV + q];
+        const T ri = bi - acc[q];
+        r[row * NV + q] = ri;
+        rr += double(ri) * double(ri);
+        bb += double(bi) * double(bi);
+      }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    rr += __shfl_xor(rr, off, 64);
+    bb += __shfl_xor(bb, off, 64);
+  }
+  if (threadIdx.x % 64 == 0) {
+    sh[0][threadIdx.x / 64] = rr;
+    sh[1][threadIdx.x / 64] = bb;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+#pragma unroll
+    for (int w = 0; w < kBlock / 64; ++w) {
+      a += sh[0][w];
+      c += sh[1][w];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = c;
+  }
+}
+
+// Acceptance of the learned correction: ||r|| <= ||b|| (NaN: rejected), from
+// the partials above.  Every block evaluates it in the same order, so all
+// agree; the owner block stores it in flag[0] and counts a rejection.
+__device__ __forceinline__ bool learned_accept(const double* __restrict__ part, int* flag, int* fallbacks,
+                                               bool owner) {
+  __shared__ int s_ok;
+  if (threadIdx.x < 64) {
+    double rr = 0.0, bb = 0.0;
+#pragma unroll
+    for (int i = 0; i < kDecideBlocks / 64; ++i) {
+      rr += part[2 * (threadIdx.x + 64 * i)];
+      bb += part[2 * (threadIdx.x + 64 * i) + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      rr += __shfl_xor(rr, off, 64);
+      bb += __shfl_xor(bb, off, 64);
+    }
+    if (threadIdx.x == 0) {
+      const int ok = (rr <= bb) ? 1 : 0;
+      s_ok = ok;
+      if (owner) {
+        flag[0] = ok;
+        if (!ok) fallbacks[0] = fallbacks[0] + 1;
+      }
+    }
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+// Finest-level sweeps with the learned pre-smoothing (accepted) or its
+// Jacobi fallback (rejected); the down-sweep decides (learned_accept) and
+// leaves the decision in flag[0] for the up-sweep.  With the network's correction x_m the
 // residual r_m = b - A x_m is formed beforehand; the down-sweep then only
 // restricts it (b_c = R r_m) and the up-sweep starts from x_m:
 //   y = x_m + P e + omega D^{-1} (r_m - (A P) e).
@@ -188,8 +275,8 @@ __global__ __launch_bounds__(kBlock) void vdown_sel_kernel(
     int64_t nq, const int64_t* __restrict__ rpq, const int32_t* __restrict__ ciq, const T* __restrict__ vq,
     const int64_t* __restrict__ rpr, const int32_t* __restrict__ cir, const T* __restrict__ vr,
     const T* __restrict__ b, T omega, T* __restrict__ r, T* __restrict__ bc, const T* __restrict__ r_m,
-    const int* __restrict__ flag, unsigned nblk_a) {
-  const bool learned = flag[0] != 0;
+    const double* __restrict__ part, int* flag, int* fallbacks, unsigned nblk_a) {
+  const bool learned = learned_accept(part, flag, fallbacks, blockIdx.x == 0);
   T acc[NV];
 #pragma unroll
   for (int n = 0; n < NV; ++n) acc[n] = T(0);

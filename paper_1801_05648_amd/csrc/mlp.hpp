@@ -71,21 +71,40 @@ __device__ __forceinline__ bf16x4_t load4(const unsigned short* p) {
   return *reinterpret_cast<const bf16x4_t*>(p);
 }
 
+// Weight fragments of one lane, loaded once and kept in registers (inference).
+template <int D>
+struct MlpFrag {
+  using M = MlpDims<D>;
+  bf16x4_t w1[M::HB][M::KB], w2[M::HB][M::HB], w3[M::HB];
+  __device__ __forceinline__ void load(const MlpW& w, int n, int q) {
+#pragma unroll
+    for (int mb = 0; mb < M::HB; ++mb) {
+#pragma unroll
+      for (int kb = 0; kb < M::KB; ++kb) w1[mb][kb] = load4(w.w1t + (16 * mb + n) * M::KP + 16 * kb + 4 * q);
+#pragma unroll
+      for (int kb = 0; kb < M::HB; ++kb) w2[mb][kb] = load4(w.w2t + (16 * mb + n) * M::H + 16 * kb + 4 * q);
+      w3[mb] = load4(w.w3t + n * M::H + 16 * mb + 4 * q);
+    }
+  }
+};
+
 // Forward of one 16-node tile given the input fragments zf[kb] (B layout:
 // lane holds z[node n][k = 16 kb + 4 q + j]).  Keeps the pre-activations
-// (for the ReLU masks) and the BF16 activation fragments.
+// (for the ReLU masks) and the BF16 activation fragments.  The weight
+// fragments come from f1(mb, kb), f2(mb, kb), f3(kb) (A layout).
 template <int D>
 struct MlpTile {
   using M = MlpDims<D>;
   f32x4_t a1[M::HB], a2[M::HB], y;
   bf16x4_t h1[M::HB], h2[M::HB];
 
-  __device__ __forceinline__ void forward(const MlpW& w, const bf16x4_t* zf, int n, int q) {
+  template <class F1, class F2, class F3>
+  __device__ __forceinline__ void run(const F1& f1, const F2& f2, const F3& f3, const bf16x4_t* zf) {
 #pragma unroll
     for (int mb = 0; mb < M::HB; ++mb) {
       f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kb = 0; kb < M::KB; ++kb) acc = mfma16(load4(w.w1t + (16 * mb + n) * M::KP + 16 * kb + 4 * q), zf[kb], acc);
+      for (int kb = 0; kb < M::KB; ++kb) acc = mfma16(f1(mb, kb), zf[kb], acc);
       a1[mb] = acc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) h1[mb][i] = short(f2bf(acc[i] > 0.f ? acc[i] : 0.f));
@@ -94,22 +113,29 @@ struct MlpTile {
     for (int mb = 0; mb < M::HB; ++mb) {
       f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int kb = 0; kb < M::HB; ++kb) acc = mfma16(load4(w.w2t + (16 * mb + n) * M::H + 16 * kb + 4 * q), h1[kb], acc);
+      for (int kb = 0; kb < M::HB; ++kb) acc = mfma16(f2(mb, kb), h1[kb], acc);
       a2[mb] = acc;
 #pragma unroll
       for (int i = 0; i < 4; ++i) h2[mb][i] = short(f2bf(acc[i] > 0.f ? acc[i] : 0.f));
     }
     f32x4_t acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kb = 0; kb < M::HB; ++kb) acc = mfma16(load4(w.w3t + n * M::H + 16 * kb + 4 * q), h2[kb], acc);
+    for (int kb = 0; kb < M::HB; ++kb) acc = mfma16(f3(kb), h2[kb], acc);
     y = acc;  // lane holds y[node n][c = 4 q + i]; only q == 0, i < D are outputs
+  }
+
+  // weights read from memory as they are needed (training: registers are short)
+  __device__ __forceinline__ void forward(const MlpW& w, const bf16x4_t* zf, int n, int q) {
+    run([&](int mb, int kb) { return load4(w.w1t + (16 * mb + n) * M::KP + 16 * kb + 4 * q); },
+        [&](int mb, int kb) { return load4(w.w2t + (16 * mb + n) * M::H + 16 * kb + 4 * q); },
+        [&](int kb) { return load4(w.w3t + n * M::H + 16 * kb + 4 * q); }, zf);
+  }
+  __device__ __forceinline__ void forward(const MlpFrag<D>& f, const bf16x4_t* zf) {
+    run([&](int mb, int kb) { return f.w1[mb][kb]; }, [&](int mb, int kb) { return f.w2[mb][kb]; },
+        [&](int kb) { return f.w3[kb]; }, zf);
   }
 };
 
-// Inference over the nodes of an operator: x[node * D + c] = delta_c(z_node),
-// z from b through the stencil table nbr [n][S] (-1: no neighbour) and the
-// inverse diagonal (per node when PER_DOF is false: the scalar Laplacian
-// acting on D interleaved components; per dof otherwise).
 // Input k (= s D + c) of node `node`: component c of D^{-1} b at stencil node s.
 template <int D, bool PER_DOF, typename T>
 __device__ __forceinline__ float node_input(int64_t node, int k, const int32_t* __restrict__ nbr,
@@ -122,26 +148,43 @@ __device__ __forceinline__ float node_input(int64_t node, int k, const int32_t* 
   return float((PER_DOF ? dinv[int64_t(nb) * D + c] : dinv[nb]) * b[int64_t(nb) * D + c]);
 }
 
+// Inference over the nodes of an operator: x[node * D + c] = delta_c(z_node),
+// z from b through the stencil table nbr [n][S] (-1: no neighbour) and the
+// inverse diagonal (per node when PER_DOF is false: the scalar Laplacian
+// acting on D interleaved components; per dof otherwise).  Each wavefront
+// loads the weights once and walks 16-node tiles with a grid stride.
 template <int D, bool PER_DOF, typename T>
 __global__ __launch_bounds__(256) void mlp_infer_kernel(int64_t n_nodes, const int32_t* __restrict__ nbr,
                                                          const T* __restrict__ b, const T* __restrict__ dinv,
                                                          MlpW w, T* __restrict__ x) {
   using M = MlpDims<D>;
   const int lane = threadIdx.x % 64, n = lane % 16, q = lane / 16;
-  const int64_t tile = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
-  const int64_t node = tile * 16 + n;
-  if (tile * 16 >= n_nodes) return;  // whole wave leaves together
-  bf16x4_t zf[M::KB];
+  const int64_t ntiles = (n_nodes + 15) / 16, nwaves = int64_t(gridDim.x) * 4;
+  int64_t tile = int64_t(blockIdx.x) * 4 + threadIdx.x / 64;
+  if (tile >= ntiles) return;  // whole wave leaves together
+  MlpFrag<D> f;
+  f.load(w, n, q);
+  for (; tile < ntiles; tile += nwaves) {
+    const int64_t node = tile * 16 + n;
+    bf16x4_t zf[M::KB];
 #pragma unroll
-  for (int kb = 0; kb < M::KB; ++kb)
+    for (int kb = 0; kb < M::KB; ++kb)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
-      zf[kb][j] = short(f2bf(node < n_nodes ? node_input<D, PER_DOF, T>(node, 16 * kb + 4 * q + j, nbr, b, dinv) : 0.f));
-  MlpTile<D> t;
-  t.forward(w, zf, n, q);
-  if (q == 0 && node < n_nodes)
+      for (int j = 0; j < 4; ++j)
+        zf[kb][j] = short(f2bf(node < n_nodes ? node_input<D, PER_DOF, T>(node, 16 * kb + 4 * q + j, nbr, b, dinv) : 0.f));
+    MlpTile<D> t;
+    t.forward(f, zf);
+    if (q == 0 && node < n_nodes)
 #pragma unroll
-    for (int i = 0; i < D; ++i) x[node * D + i] = T(t.y[i]);
+      for (int i = 0; i < D; ++i) x[node * D + i] = T(t.y[i]);
+  }
+}
+
+// Blocks of mlp_infer_kernel for n nodes: one tile per wave (the gathers of
+// all tiles in flight at once) up to 4096 blocks.
+inline unsigned mlp_infer_grid(int64_t n_nodes) {
+  const int64_t blocks = ((n_nodes + 15) / 16 + 3) / 4;
+  return unsigned(blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks));
 }
 
 // Forward over m stored input rows (Z [m][KP] BF16): y[row * D + c].
@@ -304,19 +347,41 @@ __global__ __launch_bounds__(256) void mlp_train_kernel(int64_t first, int64_t m
   if (lane == 0) part_loss[wave] = lsum;
 }
 
-// g[p] = sum over waves of part[wave][p] in wave order; loss likewise.
-__global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(int nwaves, int nparam, const float* __restrict__ part,
-                                                               const float* __restrict__ part_loss,
+// Two-stage sum of the per-wave gradients in a fixed order: stage 1 adds the
+// waves of chunk blockIdx.y (kGradChunks chunks of consecutive waves) into
+// part2[chunk][p]; stage 2 adds the chunks in order into g[p].  Loss likewise.
+constexpr int kGradChunks = 32;
+
+__global__ __launch_bounds__(256) void mlp_grad_chunk_kernel(int nwaves, int nparam, const float* __restrict__ part,
+                                                              const float* __restrict__ part_loss,
+                                                              float* __restrict__ part2, float* __restrict__ loss2) {
+  const int p = blockIdx.x * 256 + threadIdx.x;
+  const int per = (nwaves + kGradChunks - 1) / kGradChunks;
+  const int w0 = blockIdx.y * per, w1 = min(nwaves, w0 + per);
+  if (p < nparam) {
+    float s = 0.f;
+    for (int wv = w0; wv < w1; ++wv) s += part[int64_t(wv) * nparam + p];
+    part2[int64_t(blockIdx.y) * nparam + p] = s;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float s = 0.f;
+    for (int wv = w0; wv < w1; ++wv) s += part_loss[wv];
+    loss2[blockIdx.y] = s;
+  }
+}
+
+__global__ __launch_bounds__(256) void mlp_grad_reduce_kernel(int nparam, const float* __restrict__ part2,
+                                                               const float* __restrict__ loss2,
                                                                float* __restrict__ g, float* __restrict__ loss) {
   const int p = blockIdx.x * 256 + threadIdx.x;
   if (p < nparam) {
     float s = 0.f;
-    for (int wv = 0; wv < nwaves; ++wv) s += part[int64_t(wv) * nparam + p];
+    for (int c = 0; c < kGradChunks; ++c) s += part2[int64_t(c) * nparam + p];
     g[p] = s;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     float s = 0.f;
-    for (int wv = 0; wv < nwaves; ++wv) s += part_loss[wv];
+    for (int c = 0; c < kGradChunks; ++c) s += loss2[c];
     loss[0] = s;
   }
 }
@@ -405,10 +470,7 @@ __global__ __launch_bounds__(256) void mlp_gather_samples_kernel(int64_t m, cons
   Wo[i] = Wi[s];
 }
 
-// Fallback test of the learned pre-smoothing: per-block partials of r.r and
-// b.b, then one block adds them in block order and sets flag = 1 (use the
-// network's correction) iff ||b - A x_mlp|| <= ||b||; otherwise the damped
-// Jacobi sweep is used and the fallback counter is incremented.
+// Per-block partial sums of r.r and b.b (exact corrections' convergence test).
 constexpr int kNormBlocks = 256;
 
 template <typename T>
@@ -435,19 +497,6 @@ __global__ __launch_bounds__(256) void norm_pair_partial_kernel(int64_t n, const
     part[2 * blockIdx.x] = sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3];
     part[2 * blockIdx.x + 1] = sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3];
   }
-}
-
-__global__ void mlp_flag_kernel(int nb, const double* __restrict__ part, int* __restrict__ flag,
-                                int* __restrict__ fallbacks) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double rr = 0.0, bb = 0.0;
-  for (int i = 0; i < nb; ++i) {
-    rr += part[2 * i];
-    bb += part[2 * i + 1];
-  }
-  const int ok = (rr <= bb) ? 1 : 0;  // NaN -> fall back
-  flag[0] = ok;
-  if (!ok) fallbacks[0] = fallbacks[0] + 1;
 }
 
 }  // namespace fsi
