@@ -41,6 +41,10 @@ Setup of level l (matrix A_l, node block size b_l, near-nullspace B_l, n_l x k):
 V(1,1) cycle: vcycle(l, b) = LU^{-1} b at l = L, otherwise
   x = omega_l D_l^{-1} b;  r = b - A_l x;  x += P_l vcycle(l+1, R_l r);
   x += omega_l D_l^{-1} (b - A_l x).
+
+Chebyshev variant (vcycle_cheb): both sweeps are k steps of the Chebyshev
+iteration for D_l^{-1} A_l on [lam/30, lam], lam = 1.1 rho_l (the power
+estimate underestimates the spectral radius), instead of one Jacobi sweep.
 """
 from __future__ import annotations
 
@@ -56,6 +60,8 @@ POWER_ITERS = 30
 RANK_TOL = 1e-10
 TIE_REL = 1e-8
 MAX_DENSE_COARSE = 6000
+CHEB_RATIO = 30.0
+CHEB_BOOST = 1.1
 
 
 # ----------------------------------------------------------------- dense LU
@@ -328,6 +334,42 @@ def vcycle(H: Hierarchy, b: np.ndarray, l: int = 0) -> np.ndarray:
     x = x + L.P @ vcycle(H, L.R @ r, l + 1)
     x = x + L.omega * (L.dinv * (b - L.A @ x))
     return x
+
+
+def chebyshev(A, dinv: np.ndarray, b: np.ndarray, x: np.ndarray, degree: int, lam_max: float,
+              ratio: float = CHEB_RATIO) -> np.ndarray:
+    """`degree` steps of the Chebyshev iteration for A x = b preconditioned by
+    D^{-1}, tuned to the interval [lam_max/ratio, lam_max] of D^{-1} A
+    (three-term recurrence of the scaled Chebyshev polynomials), from x.
+    The error after the k steps is T_k((theta - D^{-1}A)/delta) /
+    T_k(theta/delta) applied to the initial error, theta and delta the
+    centre and half-width of the interval."""
+    lam_min = lam_max / ratio
+    theta = 0.5 * (lam_max + lam_min)
+    delta = 0.5 * (lam_max - lam_min)
+    sigma = theta / delta
+    rho = 1.0 / sigma
+    r = b - A @ x
+    d = (dinv * r) / theta
+    x = x + d
+    for _ in range(degree - 1):
+        r = r - A @ d
+        rho_new = 1.0 / (2.0 * sigma - rho)
+        d = (rho_new * rho) * d + (2.0 * rho_new / delta) * (dinv * r)
+        x = x + d
+        rho = rho_new
+    return x
+
+
+def vcycle_cheb(H: Hierarchy, b: np.ndarray, degree: int, l: int = 0) -> np.ndarray:
+    """V-cycle with `degree` Chebyshev steps as pre- and post-smoother."""
+    if l == H.nlevels - 1:
+        return lu_solve(H.coarse_lu, b)
+    L = H.levels[l]
+    lam = CHEB_BOOST * L.rho
+    x = chebyshev(L.A, L.dinv, b, np.zeros_like(b), degree, lam)
+    x = x + L.P @ vcycle_cheb(H, L.R @ (b - L.A @ x), degree, l + 1)
+    return chebyshev(L.A, L.dinv, b, x, degree, lam)
 
 
 # ------------------------------------------------------- near-nullspaces

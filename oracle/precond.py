@@ -112,9 +112,18 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
     return x
 
 
-def amg_preconditioner(bs: BlockSystem, H: dict) -> BlockLDU:
-    """The preconditioner of the hot path: every inverse one V(1,1) cycle."""
-    V = {k: (lambda h: (lambda b: amg.vcycle(h, b)))(h) for k, h in H.items()}
+def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None) -> BlockLDU:
+    """The preconditioner of the hot path: every inverse one V(1,1) cycle
+    (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
+    named in `cheb`)."""
+    cheb = cheb or {}
+
+    def inv(name, h):
+        if name in cheb:
+            k = cheb[name]
+            return lambda b: amg.vcycle_cheb(h, b, k)
+        return lambda b: amg.vcycle(h, b)
+    V = {k: inv(k, h) for k, h in H.items()}
     mesh = lambda r: mesh_solve(bs, V["H_M"], r)
     solid = lambda r: solid_schur_solve(bs, V["H_MS"], V["H_SIG"], r)
     fluid = lambda r: fluid_schur_solve(bs, V["H_A"], V["H_P"], r)

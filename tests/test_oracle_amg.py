@@ -115,3 +115,50 @@ def test_vcycle_coarsest_is_exact():
     assert h.nlevels == 1
     b = np.arange(30.0)
     assert np.allclose(A @ amg.vcycle(h, b), b, rtol=1e-12)
+
+
+@pytest.mark.parametrize("degree", [1, 2, 3, 5])
+def test_chebyshev_error_is_the_scaled_chebyshev_polynomial(degree):
+    """With A = diag(lambda), D = I and b = 0 the iterate is the error, and
+    after k steps it equals T_k((theta - lambda)/delta) / T_k(theta/delta)
+    times the initial error (T_k evaluated by numpy's Chebyshev series)."""
+    from numpy.polynomial import chebyshev as C
+    lam = np.linspace(0.01, 2.0, 40)
+    A = sp.diags(lam).tocsr()
+    x0 = 1.0 + np.arange(40) / 40.0
+    lmax, ratio = 2.2, 30.0
+    x = amg.chebyshev(A, np.ones(40), np.zeros(40), x0, degree, lmax, ratio)
+    lmin = lmax / ratio
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    Tk = np.zeros(degree + 1)
+    Tk[degree] = 1.0
+    ref = C.chebval((theta - lam) / delta, Tk) / C.chebval(theta / delta, Tk) * x0
+    assert np.allclose(x, ref, rtol=0, atol=1e-13 * np.abs(x0).max())
+    # inside the interval the error is bounded by 1 / T_k(theta / delta)
+    inside = lam >= lmin
+    assert np.all(np.abs(x[inside] / x0[inside]) <= 1.0 / C.chebval(theta / delta, Tk) * (1 + 1e-12))
+
+
+def test_chebyshev_degree_one_is_damped_jacobi():
+    A = lap1d(20)
+    dinv = 1.0 / A.diagonal()
+    b = np.sin(np.arange(20.0))
+    lmax = 2.2
+    theta = 0.5 * (lmax + lmax / amg.CHEB_RATIO)
+    assert np.allclose(amg.chebyshev(A, dinv, b, np.zeros(20), 1, lmax), dinv * b / theta, rtol=1e-15)
+
+
+@pytest.mark.parametrize("hname", ["H_M", "H_MS", "H_P"])
+def test_chebyshev_vcycle_symmetric_and_contracting(hname):
+    """The same polynomial before and after the coarse correction keeps the
+    cycle symmetric for symmetric A; it contracts in the A-norm."""
+    bs, H = _hierarchies("c1", 40)
+    h = H[hname]
+    A = h.levels[0].A.toarray()
+    n = A.shape[0]
+    V = np.column_stack([amg.vcycle_cheb(h, e, 3) for e in np.eye(n)])
+    assert np.abs(V - V.T).max() <= 1e-10 * np.abs(V).max()
+    E = np.eye(n) - V @ A
+    Lc = np.linalg.cholesky(A)
+    Ea = Lc.T @ E @ np.linalg.inv(Lc.T)
+    assert np.linalg.norm(Ea, 2) < 1.0
