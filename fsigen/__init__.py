@@ -99,6 +99,7 @@ CONFIGS = {
     "tiny3d": Config("tiny3d", 3, (4, 2, 2), (2.5, 0.41, 0.41), (1, 0, 0), (3, 1, 1)),
     "c1": Config("c1", 2, (32, 8), (2.0, 0.5), (12, 0), (20, 2)),
     "c2": Config("c2", 2, (256, 64), (2.0, 0.5), (96, 0), (160, 16)),
+    "m3": Config("m3", 3, (32, 8, 8), (2.5, 0.41, 0.41), (8, 0, 2), (16, 1, 6)),
     "c3": Config("c3", 3, (64, 16, 16), (2.5, 0.41, 0.41), (16, 0, 4), (32, 2, 12)),
     "c4": Config("c4", 3, (128, 32, 32), (2.5, 0.41, 0.41), (32, 0, 8), (64, 4, 24)),
 }

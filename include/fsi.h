@@ -100,8 +100,16 @@ typedef struct {
                           Krylov loop, A_h products and coarsest solves stay FP64 */
   int32_t max_coarse;  /* AMG: coarsest level size bound (default 500)          */
   int32_t max_levels;  /* AMG: level bound (default 10)                         */
-  int32_t pad;
+  int32_t cheb_degree; /* 0 (default): one damped-Jacobi sweep before and after
+                          the coarse correction; k in 1..8: k Chebyshev steps for
+                          D^{-1} A on [lam/30, lam], lam = 1.1 x the power
+                          estimate of its spectral radius, on the hierarchies
+                          in cheb_mask                                           */
   double strength0;    /* AMG: strength threshold on the finest level (0.08)    */
+  int32_t cheb_mask;   /* bit FSI_H_*: hierarchies with Chebyshev sweeps
+                          (default H_MS | H_SIG | H_P; H_A is rejected: its
+                          operator is nonsymmetric)                             */
+  int32_t pad;
 } fsi_precond_opts;
 
 typedef struct {

@@ -193,11 +193,14 @@ struct MlpRecord {
 template <typename T>
 struct DLevel {
   DCsr<T> AD, Q, P, AP;  // A D^{-1}, Q = R (I - omega A D^{-1}), prolongator, A P
-  DCsr<T> A0, R0;        // with a learned smoother: A (levels 0, 1) and R (level 0) themselves
+  DCsr<T> A0, R0;        // A and R themselves: learned smoother (A: levels 0, 1; R: level 0) or Chebyshev levels
   std::shared_ptr<DevBuf> dinv, y, r, b;
   T omega = T(0);
   int64_t n = 0;
   int gdown = 8, gdownq = 64, gup = 8;
+  int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
+  std::vector<T> ca, cc;               // recurrence coefficients a_j, c_j, j = 1..cheb
+  std::shared_ptr<DevBuf> d0, d1, r1;  // Chebyshev directions and second residual buffer
 };
 
 template <typename T>
@@ -212,8 +215,30 @@ struct DHier {
   std::shared_ptr<DevBuf> xm, rm;  // its correction and residual
 };
 
+// Chebyshev recurrence of degree k for D^{-1} A on [lam/30, lam], lam = 1.1 rho
+// (rho = (4/3)/omega, the setup's power estimate): a_1 = 0, c_1 = 1/theta,
+// rho_0 = delta/theta, rho_j = 1/(2 theta/delta - rho_{j-1}), a_j = rho_j rho_{j-1},
+// c_j = 2 rho_j / delta.
+constexpr double kChebRatio = 30.0, kChebBoost = 1.1;
+
 template <typename T>
-DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false) {
+void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c) {
+  const double lmax = kChebBoost * (4.0 / 3.0) / omega, lmin = lmax / kChebRatio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  a.assign(k + 1, T(0));
+  c.assign(k + 1, T(0));
+  c[1] = T(1.0 / theta);
+  double rho = 1.0 / sigma;
+  for (int j = 2; j <= k; ++j) {
+    const double rn = 1.0 / (2.0 * sigma - rho);
+    a[j] = T(rn * rho);
+    c[j] = T(2.0 * rn / delta);
+    rho = rn;
+  }
+}
+
+template <typename T>
+DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0) {
   DHier<T> D;
   D.nv = nv;
   const int L = int(H.levels.size()) - 1;
@@ -222,7 +247,31 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
     DLevel<T> d;
     d.n = h.A.nrows;
     d.omega = T(h.omega);
-    if (l < L) {
+    if (l < L && cheb > 0) {
+      if (!(h.omega > 0.0)) throw Error(FSI_ERR_NUMERIC, "Chebyshev smoothing needs a positive spectral estimate");
+      HCsr AP = spgemm(h.A, h.P);
+      d.cheb = cheb;
+      cheb_coefficients<T>(h.omega, cheb, d.ca, d.cc);
+      d.A0 = upload<T>(h.A, s);
+      d.R0 = upload<T>(h.R, s);
+      d.P = upload<T>(h.P, s);
+      d.AP = upload<T>(AP, s);
+      d.dinv = upload_vec<T>(h.dinv, s);
+      d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1));
+      auto mkv = [&]() {
+        auto b = std::make_shared<DevBuf>();
+        b->alloc(sizeof(T) * std::max<int64_t>(d.n * nv, 1));
+        return b;
+      };
+      d.d0 = mkv();
+      d.d1 = mkv();
+      d.r1 = mkv();
+      const double vb = double(sizeof(T)) * nv;
+      // pre: cheb steps over A + R; post: P, AP, cheb - 1 steps over A; per step
+      // d, r, dinv gathered and d, r, x written at the row
+      D.bytes_per_cycle += d.A0.bytes() * (2 * cheb - 1) + d.R0.bytes() + d.P.bytes() + d.AP.bytes() +
+                           double(d.n) * (6.0 * cheb * vb + 2 * sizeof(T)) + double(h.P.ncols) * 2 * vb;
+    } else if (l < L) {
       // setup-time products for the two-launch level sweeps
       HCsr AP = spgemm(h.A, h.P);
       HCsr RA = spgemm(h.R, h.A);
@@ -296,11 +345,67 @@ void mlp_presmooth(DHier<T>& H, const T* b, hipStream_t s) {
   });
 }
 
+template <typename T, int NV>
+void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plain);
+
+// A level with Chebyshev sweeps of degree k: k step launches (the first from
+// x = 0), the restriction b_c = R r_k, the coarse cycle, the coarse
+// correction (x += P e, r -= A P e), then k - 1 step launches of which the last
+// also applies step k.  out must not alias b.
+template <typename T, int NV>
+void cheb_level(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plain) {
+  DLevel<T>& d = H.lev[l];
+  DLevel<T>& c = H.lev[l + 1];
+  if (out == b) throw Error(FSI_ERR_ARG, "a Chebyshev V-cycle cannot run in place");
+  const int k = d.cheb;
+  const T* dinv = d.dinv->template as<T>();
+  T* rb[2] = {d.r->template as<T>(), d.r1->template as<T>()};
+  T* db[2] = {d.d0->template as<T>(), d.d1->template as<T>()};
+  const DCsr<T>& A = d.A0;
+  auto step = [&](const T* dp, const T* rp, T a, T cj, T* dout, T* rout, int xinit, int fuse, T a2, T c2) {
+    with_group(A.group, [&](auto gc) {
+      constexpr int G = decltype(gc)::value;
+      cheb_step_kernel<T, G, NV><<<grid_for(A.nrows, kBlock / G), kBlock, 0, s>>>(
+          A.nrows, A.drp(), A.dci(), A.dval(), ChebGather<T, NV>{dp, rp, dinv, a, cj}, dout, rout, out, xinit, fuse,
+          a2, c2);
+    });
+  };
+  const T* rp = b;
+  const T* dp = nullptr;
+  int cur = 0;
+  for (int j = 1; j <= k; ++j) {  // pre-smoothing from x = 0
+    step(dp, rp, d.ca[j], d.cc[j], db[cur], rb[cur], j == 1, 0, T(0), T(0));
+    dp = db[cur];
+    rp = rb[cur];
+    cur ^= 1;
+  }
+  T* rk = rb[cur ^ 1];
+  T* bc = c.b->template as<T>();
+  launch_rows<T, NV>(d.R0, GatherPlain<T, NV>{rk}, EpiStore<T, NV>{bc}, s);
+  T* e = c.y->template as<T>();
+  vcycle_rec<T, NV>(H, l + 1, bc, e, s, plain);
+  with_group(d.gup, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    cheb_prolong_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(
+        d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, dinv, out, rk, k == 1,
+        d.cc[1]);
+  });
+  dp = nullptr;
+  rp = rk;
+  for (int j = 1; j < k; ++j) {  // post-smoothing; the last launch also applies step k
+    const bool last = j == k - 1;
+    step(dp, rp, d.ca[j], d.cc[j], db[cur], rb[cur], 0, last, last ? d.ca[k] : T(0), last ? d.cc[k] : T(0));
+    dp = db[cur];
+    rp = rb[cur];
+    cur ^= 1;
+  }
+}
+
 // One V(1,1) cycle from level l: two launches per level (down, up) and a
 // dense product with the coarsest inverse.  `plain` disables the learned
 // pre-smoother (used for the exact corrections it is trained on).
 template <typename T, int NV>
-void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plain = false) {
+void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plain) {
   const int L = int(H.lev.size()) - 1;
   if (l == L) {
     const int64_t n = H.nc;
@@ -309,6 +414,10 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   }
   DLevel<T>& d = H.lev[l];
   DLevel<T>& c = H.lev[l + 1];
+  if (d.cheb > 0) {
+    cheb_level<T, NV>(H, l, b, out, s, plain);
+    return;
+  }
   const bool learned = l == 0 && !plain && H.mlp && H.mlp->enabled && H.xm;
   if (learned) mlp_presmooth<T, NV>(H, b, s);
   const T* dinv = d.dinv->template as<T>();
@@ -479,6 +588,7 @@ struct fsi_ctx {
   DCsr<double> Ah;
   // preconditioner
   int precision = FSI_P_F64;
+  int cheb[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev degree per hierarchy (0: Jacobi)
   SaHierarchy host_h[FSI_NHIER];
   std::unique_ptr<Precond<double>> p64;
   std::unique_ptr<Precond<float>> p32;
@@ -581,6 +691,12 @@ std::vector<double> rigid_modes(const fsi_ctx& c, int& k) {
   return B;
 }
 
+// The learned pre-smoother exists for H_M and H_SIG with Jacobi sweeps and
+// lattice indices of the nodes.
+bool learned_capable(const fsi_ctx& c, int h) {
+  return !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG) && c.cheb[h] == 0;
+}
+
 // Point the finest levels of H_M and H_SIG at their learned smoothers (or at
 // none when the hierarchy has a single level).
 template <typename T>
@@ -600,10 +716,8 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   P->d = c.d;
   P->n_m = c.n_m; P->n_s = c.n_s; P->n_f = c.n_f; P->n_vs = c.n_vs; P->n_vf = c.n_vf;
   P->n_p = c.n_p; P->N = c.N;
-  for (int h = 0; h < FSI_NHIER; ++h) {
-    const bool learned_capable = !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG);
-    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable);
-  }
+  for (int h = 0; h < FSI_NHIER; ++h)
+    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable(c, h), c.cheb[h]);
   link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.blk[FSI_F];
@@ -925,7 +1039,7 @@ void prepare_mlp(fsi_ctx& c) {
     const int h = i == 0 ? FSI_H_M : FSI_H_SIG;
     const SaHierarchy& HH = c.host_h[h];
     const int d = c.d;
-    if (c.node_ijk.empty() || HH.levels.size() < 2) {
+    if (!learned_capable(c, h) || HH.levels.size() < 2) {
       M.n_nodes = 0;
       M.use.n_nodes = 0;
       M.use.enabled = false;
@@ -1529,6 +1643,8 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->max_coarse = 500;
   o->max_levels = 10;
   o->strength0 = 0.08;
+  o->cheb_degree = 0;
+  o->cheb_mask = (1 << FSI_H_MS) | (1 << FSI_H_SIG) | (1 << FSI_H_P);
 }
 
 void fsi_default_solve_opts(fsi_solve_opts* o) {
@@ -1698,6 +1814,10 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     if (o.precision != FSI_P_F64 && o.precision != FSI_P_F32) throw Error(FSI_ERR_ARG, "unknown precision");
     if (o.max_coarse < 1 || o.max_levels < 1 || o.max_levels > 16 || !(o.strength0 >= 0.0))
       throw Error(FSI_ERR_ARG, "bad AMG options");
+    if (o.cheb_degree < 0 || o.cheb_degree > 8 || (o.cheb_mask & ~0x1f) != 0)
+      throw Error(FSI_ERR_ARG, "bad Chebyshev options");
+    if (o.cheb_degree > 0 && (o.cheb_mask & (1 << FSI_H_A)))
+      throw Error(FSI_ERR_ARG, "Chebyshev sweeps need a real spectrum: not for the nonsymmetric H_A");
     SaParams prm;
     prm.eps0 = o.strength0;
     prm.max_coarse = o.max_coarse;
@@ -1756,7 +1876,10 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       std::string m = sa_setup(*ops[h], blocks[h], *Bs[h], ks[h], prm, hh[h]);
       if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
     }
-    for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
+    for (int h = 0; h < FSI_NHIER; ++h) {
+      c.host_h[h] = std::move(hh[h]);
+      c.cheb[h] = (o.cheb_degree > 0 && (o.cheb_mask >> h) & 1) ? o.cheb_degree : 0;
+    }
     prepare_mlp(c);
     c.precision = o.precision;
     c.drop_graphs();
@@ -1873,14 +1996,14 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
     std::string m = sa_finalize(H);
     if (!m.empty()) throw Error(FSI_ERR_NUMERIC, m);
     const int nv = which == FSI_H_M ? c.d : 1;
-    const bool learned_capable = !c.node_ijk.empty() && (which == FSI_H_M || which == FSI_H_SIG);
+    const bool lc = learned_capable(c, which);
     c.drop_graphs();
     c.m_alloc = -1;
-    if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream, learned_capable);
-    else c.p32->H[which] = upload_hier<float>(H, nv, c.stream, learned_capable);
+    if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream, lc, c.cheb[which]);
+    else c.p32->H[which] = upload_hier<float>(H, nv, c.stream, lc, c.cheb[which]);
     HIP_TRY(hipStreamSynchronize(c.stream));
     c.host_h[which] = std::move(H);
-    if (learned_capable) {
+    if (lc) {
       prepare_mlp(c);
       if (c.precision == FSI_P_F64) link_mlp(c, *c.p64);
       else link_mlp(c, *c.p32);

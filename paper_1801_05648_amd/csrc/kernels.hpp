@@ -334,6 +334,96 @@ __global__ __launch_bounds__(kBlock) void vup_sel_kernel(
   }
 }
 
+// ------------------------------------------------ Chebyshev level sweeps
+// Chebyshev smoothing of a level (D^{-1} A on [lam/ratio, lam]) with the
+// three-term recurrence
+//   d_j = a_j d_{j-1} + c_j D^{-1} r_{j-1},  x_j = x_{j-1} + d_j,  r_j = r_{j-1} - A d_j
+// (a_1 = 0, c_1 = 1/theta).  One launch per step: the step's direction is
+// formed at every gathered column from the previous step's d and r, so a
+// launch reads only vectors of the step before it.
+template <typename T, int NV>
+struct ChebGather {
+  const T* d;     // d_{j-1} (unused when a == 0)
+  const T* r;     // r_{j-1}
+  const T* dinv;  // per row (shared by the NV interleaved columns)
+  T a, c;
+  __device__ __forceinline__ T operator()(int32_t col, int n) const {
+    const T v = c * dinv[col] * r[int64_t(col) * NV + n];
+    return a != T(0) ? a * d[int64_t(col) * NV + n] + v : v;
+  }
+};
+
+// Step j on every row: d_j, r_j stored (dout, rout), x += d_j (x = d_j when
+// xinit).  With `fuse` the next step's direction d_{j+1} = a2 d_j + c2 D^{-1}
+// r_j (which needs row i only) is added to x as well and d_j, r_j are not
+// stored: the last step of a post-smoothing sweep.
+template <typename T, int G, int NV>
+__global__ __launch_bounds__(kBlock) void cheb_step_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                            const int32_t* __restrict__ ci,
+                                                            const T* __restrict__ val, ChebGather<T, NV> g,
+                                                            T* __restrict__ dout, T* __restrict__ rout, T* x,
+                                                            int xinit, int fuse, T a2, T c2) {
+  constexpr int RPB = kBlock / G;
+  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  T acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = T(0);
+  row_accumulate<T, G, NV>(rp, ci, val, row, lane, g, acc);
+  group_reduce<T, G, NV>(acc);
+  if (lane == 0) {
+    const T di = g.dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t k = row * NV + q;
+      const T dj = g(int32_t(row), q);
+      const T rj = g.r[k] - acc[q];
+      if (fuse) {
+        x[k] = x[k] + dj + (a2 * dj + c2 * di * rj);
+      } else {
+        dout[k] = dj;
+        rout[k] = rj;
+        x[k] = xinit ? dj : x[k] + dj;
+      }
+    }
+  }
+}
+
+// Coarse correction of a Chebyshev level: x += P e, r -= (A P) e (r in place;
+// both only at the row itself).  With `fuse` (degree 1) the post-smoothing
+// step x += c1 D^{-1} r follows in the same pass.
+template <typename T, int G, int NV>
+__global__ __launch_bounds__(kBlock) void cheb_prolong_kernel(
+    int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
+    const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
+    const T* __restrict__ e, const T* __restrict__ dinv, T* x, T* r, int fuse, T c1) {
+  constexpr int RPB = kBlock / G;
+  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= n) return;
+  T ap[NV], pe[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = T(0);
+  const GatherPlain<T, NV> ge{e};
+  row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
+  row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
+  group_reduce<T, G, NV>(pe);
+  group_reduce<T, G, NV>(ap);
+  if (lane == 0) {
+    const T di = dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t k = row * NV + q;
+      const T rk = r[k] - ap[q];
+      T xk = x[k] + pe[q];
+      if (fuse) xk = xk + c1 * di * rk;
+      x[k] = xk;
+      r[k] = rk;
+    }
+  }
+}
+
 // -------------------------------------------------------------- coarse solve
 // X = Ainv B with a dense row-major n x n inverse (FP64); one wavefront per
 // row; B, X hold NV interleaved columns.  X must not alias B.
