@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both scales read off a
 # 256 MiB device copy in the same runs); see profiles/c2_spmv_hbm_traffic.md.
 # Valid only for the kernel and workload it was measured on.
-MEASURED_TRAFFIC = {("c2", 0): 180572657}
+MEASURED_TRAFFIC = {"c2": 180572657}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
 
@@ -38,10 +38,11 @@ def spmv_bytes(sysm) -> float:
     return 12.0 * nnz + 8.0 * (N + 1) + 8.0 * N + 8.0 * N
 
 
-def cpu_baseline(sysm, gpu_iters: int, sample_iters: int = 25):
+def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
     """The CPU oracle, as it stands, on a bounded sample: its AMG setup and
-    `sample_iters` FGMRES iterations; the per-iteration time is scaled to the
-    iteration count of a full solve."""
+    `sample_iters` FGMRES iterations with the benchmarked preconditioner
+    (same coarse-grid bound and smoothers); the per-iteration time is scaled
+    to the GPU's iteration count on the same system."""
     import numpy as np
     try:
         from threadpoolctl import threadpool_limits
@@ -52,9 +53,10 @@ def cpu_baseline(sysm, gpu_iters: int, sample_iters: int = 25):
     try:
         bs = blocks.BlockSystem(sysm)
         t0 = time.perf_counter()
-        H = precond.build_hierarchies(bs)
+        H = precond.build_hierarchies(bs, max_coarse=args.max_coarse)
         t_setup = time.perf_counter() - t0
-        P = precond.amg_preconditioner(bs, H)
+        cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
+        P = precond.amg_preconditioner(bs, H, cheb=cheb)
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
         t_iter = (time.perf_counter() - t0) / max(info.iters, 1)
@@ -67,13 +69,26 @@ def cpu_baseline(sysm, gpu_iters: int, sample_iters: int = 25):
         "cores": 1,
         "kind": "oracle",
         "sample": f"oracle AMG setup ({t_setup:.1f} s, not counted) + {info.iters} FGMRES iterations "
-                  f"on the same system ({t_iter * 1e3:.0f} ms/iteration, numpy/scipy, 1 thread), "
-                  f"scaled to the {gpu_iters} iterations of a full solve",
+                  f"on the seed-{sysm.seed} system ({t_iter * 1e3:.0f} ms/iteration, numpy/scipy, 1 thread), "
+                  f"scaled to the {gpu_iters} iterations of the GPU's solve of it",
     }
 
 
 def progress(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cheb_on(args) -> tuple:
+    return tuple(h for h in args.cheb_on.split(",") if h)
+
+
+def precond_name(args) -> str:
+    if args.cheb <= 0:
+        return "block-LDU + SA-AMG V(1,1) Jacobi"
+    on = cheb_on(args)
+    off = [h for h in ("H_M", "H_SIG", "H_MS", "H_A", "H_P") if h not in on]
+    return (f"block-LDU + SA-AMG V-cycles: Chebyshev({args.cheb}) on {'/'.join(on)}, "
+            f"Jacobi V(1,1) on {'/'.join(off)}")
 
 
 def he_init(k_in: int, hidden: int, d: int, seed: int):
@@ -107,7 +122,7 @@ def learned_run(args, cfg):
     progress(f"{cfg.name}: training on {len(train)} Newton systems, evaluating {len(evals)}")
     sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
     solver = FsiSolver.from_system(sysm, device=0, stream=stream)
-    solver.build_precond(args.precision)
+    solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -118,7 +133,7 @@ def learned_run(args, cfg):
         if n:
             sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
             solver.set_from_system(sysm)
-            solver.build_precond(args.precision)
+            solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -133,7 +148,7 @@ def learned_run(args, cfg):
     for k, i in evals:
         sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
         solver.set_from_system(sysm)
-        solver.build_precond(args.precision)
+        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -174,6 +189,7 @@ def learned_run(args, cfg):
         "data": "synthetic",
         "config": {"workload": f"pseudo-time FSI Jacobians {'x'.join(map(str, cfg.cells))} cells",
                    "name": cfg.name, "seed": args.seed, "train_systems": len(train),
+                   "precond": precond_name(args),
                    "eval_steps": list(args.eval_steps)},
         "plain_ms": round(pm, 3), "learned_over_plain_time": round(lm / pm, 4),
         "plain_iters_mean": statistics.mean(r["plain_iters"] for r in rows),
@@ -186,12 +202,21 @@ def learned_run(args, cfg):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="c2")
-    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--seed", type=int, default=0, help="seed of the learned-smoother workload")
+    ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2],
+                    help="seeds of the linearisation state; the timed solves cycle through them")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cheb", type=int, default=None,
+                    help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
+                         "default 4, and 0 with --learned (the learned smoother replaces a Jacobi sweep)")
+    ap.add_argument("--max-coarse", type=int, default=None,
+                    help="AMG: coarsest level size bound (dense inverse below it); default 2000, 500 with --learned")
+    ap.add_argument("--cheb-on", default="H_MS,H_SIG,H_P",
+                    help="comma-separated hierarchies that get the Chebyshev sweeps")
     ap.add_argument("--learned", action="store_true",
                     help="pseudo-time workload of the learned smoother (plain vs learned cycles)")
     ap.add_argument("--train-steps", type=int, default=10)
@@ -215,17 +240,19 @@ def main():
     from paper_1801_05648_amd import FsiSolver
 
     cfg = fsigen.config(args.config)
+    if args.cheb is None:
+        args.cheb = 0 if args.learned else 4
+    if args.max_coarse is None:
+        args.max_coarse = 500 if args.learned else 2000
     if args.learned:
         learned_run(args, cfg)
         return
-    progress(f"generating {cfg.name} seed {args.seed}")
-    sysm = fsigen.generate(cfg, seed=args.seed)
-    progress(f"N={sysm.N} nnz={sysm.nnz}")
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
-    solver = FsiSolver.from_system(sysm, device=0, stream=stream)
     if args.pmc_probe:
+        sysm = fsigen.generate(cfg, seed=args.seeds[0])
+        solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         xs = torch.randn(sysm.N, dtype=torch.float64, device=dev)
         ys = torch.empty_like(xs)
         for _ in range(20):
@@ -238,29 +265,45 @@ def main():
         print(json.dumps({"pmc_probe": True, "spmv_bytes": spmv_bytes(sysm), "copy_bytes": 2 * 256 * 2 ** 20}))
         solver.close()
         return
-    t0 = time.perf_counter()
-    progress("building the preconditioner")
-    solver.build_precond(args.precision)
+    # one solver per seed of the linearisation state, built and warmed up
+    # before the timed region; the timed steps cycle through the seeds
+    runs = []
+    for sd in args.seeds:
+        progress(f"generating {cfg.name} seed {sd}")
+        sysm = fsigen.generate(cfg, seed=sd)
+        progress(f"N={sysm.N} nnz={sysm.nnz}")
+        solver = FsiSolver.from_system(sysm, device=0, stream=stream)
+        t0 = time.perf_counter()
+        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
+        torch.cuda.synchronize()
+        setup_ms = (time.perf_counter() - t0) * 1e3
+        progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")
+        b = torch.from_numpy(sysm.b).to(dev)
+        x = torch.zeros_like(b)
+        for _ in range(args.warmup):
+            x.zero_()
+            solver.solve(b, x)
+        runs.append({"seed": sd, "sysm": sysm, "solver": solver, "b": b, "x": x, "setup_ms": setup_ms,
+                     "N": sysm.N, "nnz": sysm.nnz, "bytes": spmv_bytes(sysm)})
+        if len(runs) > 1:
+            sysm.blocks = None  # host copy of the matrix no longer needed
     torch.cuda.synchronize()
-    setup_ms = (time.perf_counter() - t0) * 1e3
-    progress(f"preconditioner built in {setup_ms:.0f} ms")
-
-    b = torch.from_numpy(sysm.b).to(dev)
-    x = torch.zeros_like(b)
-    for _ in range(args.warmup):
-        x.zero_()
-        solver.solve(b, x)
-    torch.cuda.synchronize()
+    sysm = runs[0]["sysm"]
+    solver = runs[0]["solver"]
+    setup_ms = statistics.mean(r["setup_ms"] for r in runs)
     times, iters, resid = [], [], []
     t_pre = t_spmv = t_gs = 0.0
     n_timed = 0
+    nbytes_sum = 0.0
     progress("warm-up done")
     t_all = time.perf_counter()
-    for _ in range(args.steps):
-        x.zero_()
+    for k in range(args.steps):
+        r = runs[k % len(runs)]
+        nbytes_sum += r["bytes"] * 1.0
+        r["x"].zero_()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info = solver.solve(b, x, timing=True)
+        _, info = r["solver"].solve(r["b"], r["x"], timing=True)
         torch.cuda.synchronize()
         times.append((time.perf_counter() - t0) * 1e3)
         iters.append(info.iters)
@@ -269,6 +312,7 @@ def main():
         t_spmv += info.t_spmv_ms
         t_gs += info.t_gs_ms
         n_timed += info.n_timed
+        r["iters"] = info.iters
         if not info.converged:
             raise SystemExit(f"solve did not converge: {info}")
     t_all = (time.perf_counter() - t_all) * 1e3
@@ -277,7 +321,7 @@ def main():
     # dominant kernel: the A_h CSR product, timed inside the timed solves by
     # HIP events recorded on the solver's stream around every launch of it
     spmv_ms = t_spmv / max(n_timed, 1)
-    nbytes = spmv_bytes(sysm)
+    nbytes = nbytes_sum / max(args.steps, 1)  # all seeds share the sparsity pattern
     achieved = nbytes / (spmv_ms * 1e-3) / 1e9
 
     # one V(1,1) cycle of the fluid-velocity hierarchy (largest V-cycle),
@@ -314,10 +358,10 @@ def main():
         "config": {
             "workload": (f"2D FSI Jacobian {cfg.cells[0]}x{cfg.cells[1]} Q2/Q1 cells" if cfg.dim == 2 else
                          f"3D FSI Jacobian {'x'.join(map(str, cfg.cells))} Q2/Q1 cells"),
-            "name": cfg.name, "seed": args.seed, "N": sysm.N, "nnz": sysm.nnz,
-            "tol": 1e-8, "restart": 50, "precond": "block-LDU + SA-AMG V(1,1) Jacobi",
+            "name": cfg.name, "seeds": list(args.seeds), "N": sysm.N, "nnz": sysm.nnz,
+            "tol": 1e-8, "restart": 50, "precond": precond_name(args), "max_coarse": args.max_coarse,
         },
-        "iters": iters[0],
+        "iters": {str(r["seed"]): r.get("iters") for r in runs},
         "true_rel_resid": max(resid),
         "ms_min": round(min(times), 3),
         "setup_ms": round(setup_ms, 1),
@@ -331,7 +375,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": MEASURED_TRAFFIC.get((cfg.name, args.seed)),
+            "traffic": MEASURED_TRAFFIC.get(cfg.name),
             "algorithmic_bytes": int(nbytes),
             "kernel_ms": round(spmv_ms, 5),
         },
@@ -344,8 +388,9 @@ def main():
     }
     if not args.no_cpu_baseline:
         progress("timing the CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline(sysm, iters[0])
-    solver.close()
+        line["cpu_baseline"] = cpu_baseline(runs[0]["sysm"], runs[0]["iters"], args)
+    for r in runs:
+        r["solver"].close()
     print(json.dumps(line), flush=True)
 
 

@@ -11,8 +11,10 @@
 #include "sa_setup.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <thread>
 #include <unordered_map>
 
 namespace fsi {
@@ -243,45 +245,86 @@ HCsr filtered(const HCsr& A, int b, const Strength& S) {
 
 }  // namespace
 
+namespace {
+
+// Barrier of a fixed team of host threads (spinning with yields: the team
+// lives only for one dense inversion).
+struct SpinBarrier {
+  explicit SpinBarrier(int n) : n_(n) {}
+  void wait() {
+    const int g = gen_.load();
+    if (count_.fetch_add(1) + 1 == n_) {
+      count_.store(0);
+      gen_.fetch_add(1);
+    } else {
+      while (gen_.load() == g) std::this_thread::yield();
+    }
+  }
+  int n_;
+  std::atomic<int> count_{0}, gen_{0};
+};
+
+}  // namespace
+
+// LU with partial pivoting (largest magnitude, smallest row on ties), then
+// the columns of the identity through the triangular factors.  The row
+// updates of each elimination step and the column solves are shared among
+// host threads; every entry goes through the same operations in the same
+// order as in a single-threaded run, so the result does not depend on the
+// thread count.
 bool dense_inverse(std::vector<double> a, int64_t n, std::vector<double>& inv) {
   std::vector<int64_t> piv(n);
-  for (int64_t k = 0; k < n; ++k) {
-    int64_t p = k;
-    double best = std::fabs(a[k * n + k]);
-    for (int64_t r = k + 1; r < n; ++r)
-      if (std::fabs(a[r * n + k]) > best) { best = std::fabs(a[r * n + k]); p = r; }
-    if (a[p * n + k] == 0.0) return false;
-    piv[k] = p;
-    if (p != k)
-      for (int64_t c = 0; c < n; ++c) std::swap(a[k * n + c], a[p * n + c]);
-    const double akk = a[k * n + k];
-    for (int64_t r = k + 1; r < n; ++r) {
-      const double l = a[r * n + k] / akk;
-      a[r * n + k] = l;
-      if (l != 0.0)
-        for (int64_t c = k + 1; c < n; ++c) a[r * n + c] -= l * a[k * n + c];
-    }
-  }
-  // solve for the columns of the identity
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const int nt = n < 256 ? 1 : int(std::min<unsigned>(16u, hw));
+  SpinBarrier bar(nt);
+  std::atomic<bool> singular{false};
   inv.assign(size_t(n) * n, 0.0);
-  std::vector<double> x(n);
-  for (int64_t col = 0; col < n; ++col) {
-    for (int64_t i = 0; i < n; ++i) x[i] = i == col ? 1.0 : 0.0;
-    for (int64_t k = 0; k < n; ++k)
-      if (piv[k] != k) std::swap(x[k], x[piv[k]]);
-    for (int64_t i = 0; i < n; ++i) {
-      double s = x[i];
-      for (int64_t c = 0; c < i; ++c) s -= a[i * n + c] * x[c];
-      x[i] = s;
+  auto work = [&](int tid) {
+    for (int64_t k = 0; k < n; ++k) {
+      if (tid == 0) {
+        int64_t p = k;
+        double best = std::fabs(a[k * n + k]);
+        for (int64_t r = k + 1; r < n; ++r)
+          if (std::fabs(a[r * n + k]) > best) { best = std::fabs(a[r * n + k]); p = r; }
+        if (a[p * n + k] == 0.0) singular.store(true);
+        piv[k] = p;
+        if (p != k)
+          for (int64_t c = 0; c < n; ++c) std::swap(a[k * n + c], a[p * n + c]);
+      }
+      bar.wait();
+      if (singular.load()) return;
+      const double akk = a[k * n + k];
+      for (int64_t r = k + 1 + tid; r < n; r += nt) {
+        const double l = a[r * n + k] / akk;
+        a[r * n + k] = l;
+        if (l != 0.0)
+          for (int64_t c = k + 1; c < n; ++c) a[r * n + c] -= l * a[k * n + c];
+      }
+      bar.wait();
     }
-    for (int64_t i = n - 1; i >= 0; --i) {
-      double s = x[i];
-      for (int64_t c = i + 1; c < n; ++c) s -= a[i * n + c] * x[c];
-      x[i] = s / a[i * n + i];
+    std::vector<double> x(n);
+    for (int64_t col = tid; col < n; col += nt) {
+      for (int64_t i = 0; i < n; ++i) x[i] = i == col ? 1.0 : 0.0;
+      for (int64_t k = 0; k < n; ++k)
+        if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+      for (int64_t i = 0; i < n; ++i) {
+        double s = x[i];
+        for (int64_t c = 0; c < i; ++c) s -= a[i * n + c] * x[c];
+        x[i] = s;
+      }
+      for (int64_t i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int64_t c = i + 1; c < n; ++c) s -= a[i * n + c] * x[c];
+        x[i] = s / a[i * n + i];
+      }
+      for (int64_t i = 0; i < n; ++i) inv[i * n + col] = x[i];
     }
-    for (int64_t i = 0; i < n; ++i) inv[i * n + col] = x[i];
-  }
-  return true;
+  };
+  std::vector<std::thread> team;
+  for (int t = 1; t < nt; ++t) team.emplace_back(work, t);
+  work(0);
+  for (auto& t : team) t.join();
+  return !singular.load();
 }
 
 std::string sa_finalize(SaHierarchy& H) {
