@@ -71,6 +71,7 @@ template <typename T>
 struct DCsr {
   int64_t nrows = 0, ncols = 0, nnz = 0;
   int group = 8;
+  bool deep = false;  // four entries in flight per lane (large streamed matrices)
   std::shared_ptr<DevBuf> rp, ci, val;
   const int64_t* drp() const { return rp->as<int64_t>(); }
   const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
@@ -78,10 +79,14 @@ struct DCsr {
   double bytes() const { return double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8; }
 };
 
-int pick_group(int64_t nnz, int64_t nrows) {
+// Lanes per row of a CSR product: the smallest power of two in [4, 64] with
+// `per_lane` x lanes >= the mean row length.  Small matrices take 3 entries
+// per lane (short latency chains); the monolithic A_h product, a pure HBM
+// stream, takes 8 (measured best on the 2D and 3D workloads).
+int pick_group(int64_t nnz, int64_t nrows, int per_lane = 3) {
   const double avg = nrows ? double(nnz) / double(nrows) : 1.0;
   int g = 4;
-  while (g < 64 && g * 3 < avg) g *= 2;
+  while (g < 64 && g * per_lane < avg) g *= 2;
   return g;
 }
 
@@ -149,8 +154,11 @@ void launch_rows(const DCsr<T>& A, Gather g, Epi e, hipStream_t s) {
   if (A.nrows == 0) return;
   with_group(A.group, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
-    csr_rows_kernel<T, G, NV><<<grid_for(A.nrows, kBlock / G), kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(),
-                                                                                A.dval(), g, e);
+    const unsigned grid = grid_for(A.nrows, kBlock / G);
+    if (A.deep)
+      csr_rows_kernel<T, G, NV, Gather, Epi, true><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e);
+    else
+      csr_rows_kernel<T, G, NV, Gather, Epi, false><<<grid, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), g, e);
   });
 }
 
@@ -1780,6 +1788,8 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
       }
     }
     DCsr<double> dAh = upload<double>(Ah, ctx->stream);
+    dAh.group = pick_group(dAh.nnz, dAh.nrows, 8);
+    dAh.deep = true;
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     // commit
     fsi_ctx& c = *ctx;

@@ -62,18 +62,36 @@ struct EpiAcc {  // y += A x
 };
 
 // Accumulate row `row` of a CSR matrix into acc[NV] with the G lanes of a
-// group (lane strides by G; two entries in flight per lane).
-template <typename T, int G, int NV, class Gather>
+// group (lane strides by G).  DEEP: four entries in flight per lane, then
+// two, then one (long rows of large streamed matrices); otherwise two, then
+// one (short latency-bound rows).
+template <typename T, int G, int NV, class Gather, bool DEEP = false>
 __device__ __forceinline__ void row_accumulate(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
                                                const T* __restrict__ val, int64_t row, int lane,
                                                const Gather& gx, T* acc) {
   const int64_t b = rp[row], e = rp[row + 1];
   int64_t k = b + lane;
-  for (; k + G < e; k += 2 * G) {
-    const int32_t c0 = ci[k], c1 = ci[k + G];
-    const T a0 = val[k], a1 = val[k + G];
+  if (DEEP) {
+    for (; k + 3 * G < e; k += 4 * G) {
+      const int32_t c0 = ci[k], c1 = ci[k + G], c2 = ci[k + 2 * G], c3 = ci[k + 3 * G];
+      const T a0 = val[k], a1 = val[k + G], a2 = val[k + 2 * G], a3 = val[k + 3 * G];
 #pragma unroll
-    for (int n = 0; n < NV; ++n) acc[n] += a0 * gx(c0, n) + a1 * gx(c1, n);
+      for (int n = 0; n < NV; ++n) acc[n] += (a0 * gx(c0, n) + a1 * gx(c1, n)) + (a2 * gx(c2, n) + a3 * gx(c3, n));
+    }
+    if (k + G < e) {
+      const int32_t c0 = ci[k], c1 = ci[k + G];
+      const T a0 = val[k], a1 = val[k + G];
+#pragma unroll
+      for (int n = 0; n < NV; ++n) acc[n] += a0 * gx(c0, n) + a1 * gx(c1, n);
+      k += 2 * G;
+    }
+  } else {
+    for (; k + G < e; k += 2 * G) {
+      const int32_t c0 = ci[k], c1 = ci[k + G];
+      const T a0 = val[k], a1 = val[k + G];
+#pragma unroll
+      for (int n = 0; n < NV; ++n) acc[n] += a0 * gx(c0, n) + a1 * gx(c1, n);
+    }
   }
   if (k < e) {
     const int32_t c0 = ci[k];
@@ -91,7 +109,7 @@ __device__ __forceinline__ void group_reduce(T* acc) {
     for (int n = 0; n < NV; ++n) acc[n] += __shfl_xor(acc[n], off, G);
 }
 
-template <typename T, int G, int NV, class Gather, class Epi>
+template <typename T, int G, int NV, class Gather, class Epi, bool DEEP = false>
 __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const int64_t* __restrict__ rp,
                                                            const int32_t* __restrict__ ci,
                                                            const T* __restrict__ val, Gather gx, Epi epi) {
@@ -102,7 +120,7 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
   T acc[NV];
 #pragma unroll
   for (int n = 0; n < NV; ++n) acc[n] = T(0);
-  row_accumulate<T, G, NV>(rp, ci, val, row, lane, gx, acc);
+  row_accumulate<T, G, NV, Gather, DEEP>(rp, ci, val, row, lane, gx, acc);
   group_reduce<T, G, NV>(acc);
   if (lane == 0) epi(row, acc);
 }
