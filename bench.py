@@ -56,7 +56,8 @@ def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
         H = precond.build_hierarchies(bs, max_coarse=args.max_coarse)
         t_setup = time.perf_counter() - t0
         cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
-        P = precond.amg_preconditioner(bs, H, cheb=cheb)
+        poly = {h: (args.poly_degree, 8.0) for h in poly_on(args)}
+        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly)
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
         t_iter = (time.perf_counter() - t0) / max(info.iters, 1)
@@ -79,16 +80,22 @@ def progress(msg: str) -> None:
 
 
 def cheb_on(args) -> tuple:
-    return tuple(h for h in args.cheb_on.split(",") if h)
+    return tuple(h for h in args.cheb_on.split(",") if h and h not in poly_on(args))
+
+
+def poly_on(args) -> tuple:
+    return tuple(h for h in (args.poly_on or "").split(",") if h)
 
 
 def precond_name(args) -> str:
+    poly = poly_on(args)
+    ptxt = f"; {'/'.join(poly)} by {args.poly_degree} Chebyshev steps alone" if poly else ""
     if args.cheb <= 0:
-        return "block-LDU + SA-AMG V(1,1) Jacobi"
+        return "block-LDU + SA-AMG V(1,1) Jacobi" + ptxt
     on = cheb_on(args)
-    off = [h for h in ("H_M", "H_SIG", "H_MS", "H_A", "H_P") if h not in on]
+    off = [h for h in ("H_M", "H_SIG", "H_MS", "H_A", "H_P") if h not in on and h not in poly]
     return (f"block-LDU + SA-AMG V-cycles: Chebyshev({args.cheb}) on {'/'.join(on)}, "
-            f"Jacobi V(1,1) on {'/'.join(off)}")
+            f"Jacobi V(1,1) on {'/'.join(off)}" + ptxt)
 
 
 def he_init(k_in: int, hidden: int, d: int, seed: int):
@@ -122,7 +129,8 @@ def learned_run(args, cfg):
     progress(f"{cfg.name}: training on {len(train)} Newton systems, evaluating {len(evals)}")
     sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
     solver = FsiSolver.from_system(sysm, device=0, stream=stream)
-    solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
+    solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+                             poly=poly_on(args), poly_degree=args.poly_degree)
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -133,7 +141,8 @@ def learned_run(args, cfg):
         if n:
             sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
             solver.set_from_system(sysm)
-            solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
+            solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+                             poly=poly_on(args), poly_degree=args.poly_degree)
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -148,7 +157,8 @@ def learned_run(args, cfg):
     for k, i in evals:
         sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
         solver.set_from_system(sysm)
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
+        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+                             poly=poly_on(args), poly_degree=args.poly_degree)
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -217,6 +227,10 @@ def main():
                     help="AMG: coarsest level size bound (dense inverse below it); default 2000, 500 with --learned")
     ap.add_argument("--cheb-on", default="H_MS,H_SIG,H_P",
                     help="comma-separated hierarchies that get the Chebyshev sweeps")
+    ap.add_argument("--poly-on", default=None,
+                    help="comma-separated hierarchies inverted by Chebyshev steps alone "
+                         "(default H_MS, none with --learned)")
+    ap.add_argument("--poly-degree", type=int, default=3)
     ap.add_argument("--learned", action="store_true",
                     help="pseudo-time workload of the learned smoother (plain vs learned cycles)")
     ap.add_argument("--train-steps", type=int, default=10)
@@ -244,6 +258,8 @@ def main():
         args.cheb = 0 if args.learned else 4
     if args.max_coarse is None:
         args.max_coarse = 500 if args.learned else 2000
+    if args.poly_on is None:
+        args.poly_on = "" if args.learned else "H_MS"
     if args.learned:
         learned_run(args, cfg)
         return
@@ -274,7 +290,8 @@ def main():
         progress(f"N={sysm.N} nnz={sysm.nnz}")
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         t0 = time.perf_counter()
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args))
+        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+                             poly=poly_on(args), poly_degree=args.poly_degree)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")

@@ -109,7 +109,14 @@ typedef struct {
   int32_t cheb_mask;   /* bit FSI_H_*: hierarchies with Chebyshev sweeps
                           (default H_MS | H_SIG | H_P; H_A is rejected: its
                           operator is nonsymmetric)                             */
+  int32_t poly_mask;   /* bit FSI_H_*: inverses taken as poly_degree Chebyshev
+                          steps alone on the finest matrix, no coarse grid
+                          (default none; meant for the solid mass matrix M_s,
+                          whose D^{-1} M_s has a bounded spectrum), on
+                          [lam/poly_ratio, lam]; H_A is rejected               */
+  int32_t poly_degree; /* 2..16 (default 3); k - 1 launches per inverse        */
   int32_t pad;
+  double poly_ratio;   /* > 1 (default 8)                                       */
 } fsi_precond_opts;
 
 typedef struct {

@@ -112,13 +112,21 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
     return x
 
 
-def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None) -> BlockLDU:
+def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None) -> BlockLDU:
     """The preconditioner of the hot path: every inverse one V(1,1) cycle
     (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
-    named in `cheb`)."""
+    named in `cheb`).  For the names in `poly`, {name: (k, ratio)}, the
+    inverse is instead k Chebyshev steps alone on the finest matrix (no coarse
+    grid), on [lam/ratio, lam] with lam = 1.1 rho of that level."""
     cheb = cheb or {}
+    poly = poly or {}
 
     def inv(name, h):
+        if name in poly and h.nlevels > 1:
+            k, ratio = poly[name]
+            L0 = h.levels[0]
+            lam = amg.CHEB_BOOST * L0.rho
+            return lambda b: amg.chebyshev(L0.A, L0.dinv, b, np.zeros_like(b), k, lam, ratio)
         if name in cheb:
             k = cheb[name]
             return lambda b: amg.vcycle_cheb(h, b, k)

@@ -218,6 +218,7 @@ struct DHier {
   std::shared_ptr<DevBuf> cinv;
   int64_t nc = 0;
   double bytes_per_cycle = 0.0;  // algorithmic bytes of one cycle as executed
+  bool poly = false;             // inverse = level 0's Chebyshev steps alone (no coarse grid)
   MlpUse* mlp = nullptr;         // learned pre-smoother of level 0 (if any)
   MlpRecord* rec = nullptr;      // recording of level-0 inputs (if any)
   std::shared_ptr<DevBuf> xm, rm;  // its correction and residual
@@ -230,8 +231,8 @@ struct DHier {
 constexpr double kChebRatio = 30.0, kChebBoost = 1.1;
 
 template <typename T>
-void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c) {
-  const double lmax = kChebBoost * (4.0 / 3.0) / omega, lmin = lmax / kChebRatio;
+void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c, double ratio = kChebRatio) {
+  const double lmax = kChebBoost * (4.0 / 3.0) / omega, lmin = lmax / ratio;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   a.assign(k + 1, T(0));
   c.assign(k + 1, T(0));
@@ -246,10 +247,39 @@ void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c
 }
 
 template <typename T>
-DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0) {
+DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
+                     int poly = 0, double poly_ratio = 8.0) {
   DHier<T> D;
   D.nv = nv;
   const int L = int(H.levels.size()) - 1;
+  if (poly > 0 && L > 0) {
+    // Chebyshev steps alone on the finest matrix: the other levels are not used
+    const SaLevel& h = H.levels[0];
+    if (!(h.omega > 0.0)) throw Error(FSI_ERR_NUMERIC, "Chebyshev steps need a positive spectral estimate");
+    DLevel<T> d;
+    d.n = h.A.nrows;
+    d.omega = T(h.omega);
+    d.cheb = poly;
+    cheb_coefficients<T>(h.omega, poly, d.ca, d.cc, poly_ratio);
+    d.A0 = upload<T>(h.A, s);
+    d.dinv = upload_vec<T>(h.dinv, s);
+    auto mkv = [&]() {
+      auto b = std::make_shared<DevBuf>();
+      b->alloc(sizeof(T) * std::max<int64_t>(d.n * nv, 1));
+      return b;
+    };
+    d.d0 = mkv();
+    d.d1 = mkv();
+    d.r1 = mkv();
+    d.r = mkv();
+    d.y = mkv();
+    d.b = mkv();
+    D.bytes_per_cycle = (d.A0.bytes() + double(d.n) * (6.0 * sizeof(T) * nv + sizeof(T))) * (poly - 1);
+    D.lev.push_back(std::move(d));
+    D.poly = true;
+    D.nc = 0;
+    return D;
+  }
   for (int l = 0; l <= L; ++l) {
     const SaLevel& h = H.levels[l];
     DLevel<T> d;
@@ -409,11 +439,44 @@ void cheb_level(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   }
 }
 
+// Inverse by k Chebyshev steps alone on the finest matrix (x = 0 start): k - 1
+// launches, the last one also applying step k (it needs the row's own
+// residual only).  out must not alias b.
+template <typename T, int NV>
+void cheb_only(DHier<T>& H, const T* b, T* out, hipStream_t s) {
+  DLevel<T>& d = H.lev[0];
+  if (out == b) throw Error(FSI_ERR_ARG, "a Chebyshev inverse cannot run in place");
+  const int k = d.cheb;
+  const T* dinv = d.dinv->template as<T>();
+  T* rb[2] = {d.r->template as<T>(), d.r1->template as<T>()};
+  T* db[2] = {d.d0->template as<T>(), d.d1->template as<T>()};
+  const DCsr<T>& A = d.A0;
+  const T* rp = b;
+  const T* dp = nullptr;
+  int cur = 0;
+  for (int j = 1; j < k; ++j) {
+    const bool last = j == k - 1;
+    with_group(A.group, [&](auto gc) {
+      constexpr int G = decltype(gc)::value;
+      cheb_step_kernel<T, G, NV><<<grid_for(A.nrows, kBlock / G), kBlock, 0, s>>>(
+          A.nrows, A.drp(), A.dci(), A.dval(), ChebGather<T, NV>{dp, rp, dinv, d.ca[j], d.cc[j]}, db[cur], rb[cur],
+          out, j == 1, last, last ? d.ca[k] : T(0), last ? d.cc[k] : T(0));
+    });
+    dp = db[cur];
+    rp = rb[cur];
+    cur ^= 1;
+  }
+}
+
 // One V(1,1) cycle from level l: two launches per level (down, up) and a
 // dense product with the coarsest inverse.  `plain` disables the learned
 // pre-smoother (used for the exact corrections it is trained on).
 template <typename T, int NV>
 void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plain) {
+  if (H.poly) {
+    cheb_only<T, NV>(H, b, out, s);
+    return;
+  }
   const int L = int(H.lev.size()) - 1;
   if (l == L) {
     const int64_t n = H.nc;
@@ -597,6 +660,8 @@ struct fsi_ctx {
   // preconditioner
   int precision = FSI_P_F64;
   int cheb[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev degree per hierarchy (0: Jacobi)
+  int poly[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev steps alone, no coarse grid (0: off)
+  double poly_ratio = 8.0;
   SaHierarchy host_h[FSI_NHIER];
   std::unique_ptr<Precond<double>> p64;
   std::unique_ptr<Precond<float>> p32;
@@ -702,7 +767,7 @@ std::vector<double> rigid_modes(const fsi_ctx& c, int& k) {
 // The learned pre-smoother exists for H_M and H_SIG with Jacobi sweeps and
 // lattice indices of the nodes.
 bool learned_capable(const fsi_ctx& c, int h) {
-  return !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG) && c.cheb[h] == 0;
+  return !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG) && c.cheb[h] == 0 && c.poly[h] == 0;
 }
 
 // Point the finest levels of H_M and H_SIG at their learned smoothers (or at
@@ -725,7 +790,8 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   P->n_m = c.n_m; P->n_s = c.n_s; P->n_f = c.n_f; P->n_vs = c.n_vs; P->n_vf = c.n_vf;
   P->n_p = c.n_p; P->N = c.N;
   for (int h = 0; h < FSI_NHIER; ++h)
-    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable(c, h), c.cheb[h]);
+    P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable(c, h), c.cheb[h], c.poly[h],
+                             c.poly_ratio);
   link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.blk[FSI_F];
@@ -1653,6 +1719,9 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->strength0 = 0.08;
   o->cheb_degree = 0;
   o->cheb_mask = (1 << FSI_H_MS) | (1 << FSI_H_SIG) | (1 << FSI_H_P);
+  o->poly_mask = 0;
+  o->poly_degree = 3;
+  o->poly_ratio = 8.0;
 }
 
 void fsi_default_solve_opts(fsi_solve_opts* o) {
@@ -1828,6 +1897,9 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       throw Error(FSI_ERR_ARG, "bad Chebyshev options");
     if (o.cheb_degree > 0 && (o.cheb_mask & (1 << FSI_H_A)))
       throw Error(FSI_ERR_ARG, "Chebyshev sweeps need a real spectrum: not for the nonsymmetric H_A");
+    if ((o.poly_mask & ~0x1f) != 0 || (o.poly_mask && (o.poly_degree < 2 || o.poly_degree > 16)) ||
+        (o.poly_mask && !(o.poly_ratio > 1.0)) || (o.poly_mask & (1 << FSI_H_A)))
+      throw Error(FSI_ERR_ARG, "bad Chebyshev-only options (degree 2..16, ratio > 1, not H_A)");
     SaParams prm;
     prm.eps0 = o.strength0;
     prm.max_coarse = o.max_coarse;
@@ -1888,8 +1960,10 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     }
     for (int h = 0; h < FSI_NHIER; ++h) {
       c.host_h[h] = std::move(hh[h]);
-      c.cheb[h] = (o.cheb_degree > 0 && (o.cheb_mask >> h) & 1) ? o.cheb_degree : 0;
+      c.poly[h] = ((o.poly_mask >> h) & 1) ? o.poly_degree : 0;
+      c.cheb[h] = (c.poly[h] == 0 && o.cheb_degree > 0 && (o.cheb_mask >> h) & 1) ? o.cheb_degree : 0;
     }
+    c.poly_ratio = o.poly_ratio;
     prepare_mlp(c);
     c.precision = o.precision;
     c.drop_graphs();
@@ -2009,8 +2083,10 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
     const bool lc = learned_capable(c, which);
     c.drop_graphs();
     c.m_alloc = -1;
-    if (c.precision == FSI_P_F64) c.p64->H[which] = upload_hier<double>(H, nv, c.stream, lc, c.cheb[which]);
-    else c.p32->H[which] = upload_hier<float>(H, nv, c.stream, lc, c.cheb[which]);
+    if (c.precision == FSI_P_F64)
+      c.p64->H[which] = upload_hier<double>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio);
+    else
+      c.p32->H[which] = upload_hier<float>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio);
     HIP_TRY(hipStreamSynchronize(c.stream));
     c.host_h[which] = std::move(H);
     if (lc) {

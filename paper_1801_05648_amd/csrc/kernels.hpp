@@ -33,10 +33,14 @@ struct GatherPlain {
 };
 
 
+// Epilogues of a row product.  load(i, pre) reads what the row's result
+// needs besides A x before the product starts, so those loads overlap the
+// row's own memory chain instead of following the reduction.
 template <typename T, int NV>
 struct EpiStore {  // y = A x
   T* y;
-  __device__ __forceinline__ void operator()(int64_t i, const T* acc) const {
+  __device__ __forceinline__ void load(int64_t, T*) const {}
+  __device__ __forceinline__ void operator()(int64_t i, const T* acc, const T*) const {
 #pragma unroll
     for (int n = 0; n < NV; ++n) y[i * NV + n] = acc[n];
   }
@@ -46,18 +50,26 @@ template <typename T, int NV>
 struct EpiSub {  // y = r - A x   (y may alias r)
   const T* r;
   T* y;
-  __device__ __forceinline__ void operator()(int64_t i, const T* acc) const {
+  __device__ __forceinline__ void load(int64_t i, T* pre) const {
 #pragma unroll
-    for (int n = 0; n < NV; ++n) y[i * NV + n] = r[i * NV + n] - acc[n];
+    for (int n = 0; n < NV; ++n) pre[n] = r[i * NV + n];
+  }
+  __device__ __forceinline__ void operator()(int64_t i, const T* acc, const T* pre) const {
+#pragma unroll
+    for (int n = 0; n < NV; ++n) y[i * NV + n] = pre[n] - acc[n];
   }
 };
 
 template <typename T, int NV>
 struct EpiAcc {  // y += A x
   T* y;
-  __device__ __forceinline__ void operator()(int64_t i, const T* acc) const {
+  __device__ __forceinline__ void load(int64_t i, T* pre) const {
 #pragma unroll
-    for (int n = 0; n < NV; ++n) y[i * NV + n] = y[i * NV + n] + acc[n];
+    for (int n = 0; n < NV; ++n) pre[n] = y[i * NV + n];
+  }
+  __device__ __forceinline__ void operator()(int64_t i, const T* acc, const T* pre) const {
+#pragma unroll
+    for (int n = 0; n < NV; ++n) y[i * NV + n] = pre[n] + acc[n];
   }
 };
 
@@ -117,12 +129,13 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= nrows) return;  // whole groups leave together (G divides 64)
-  T acc[NV];
+  T acc[NV], pre[NV];
 #pragma unroll
-  for (int n = 0; n < NV; ++n) acc[n] = T(0);
+  for (int n = 0; n < NV; ++n) acc[n] = pre[n] = T(0);
+  if (lane == 0) epi.load(row, pre);
   row_accumulate<T, G, NV, Gather, DEEP>(rp, ci, val, row, lane, gx, acc);
   group_reduce<T, G, NV>(acc);
-  if (lane == 0) epi(row, acc);
+  if (lane == 0) epi(row, acc, pre);
 }
 
 // ------------------------------------------------ fused V-cycle level sweeps
@@ -145,11 +158,14 @@ __global__ __launch_bounds__(kBlock) void vdown_kernel(
     const int64_t row = int64_t(blk) * (kBlock / GA) + threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
     if (row >= na) return;
+    T bi[NV];
+#pragma unroll
+    for (int n = 0; n < NV; ++n) bi[n] = lane == 0 ? b[row * NV + n] : T(0);
     row_accumulate<T, GA, NV>(rpa, cia, va, row, lane, GatherPlain<T, NV>{b}, acc);
     group_reduce<T, GA, NV>(acc);
     if (lane == 0)
 #pragma unroll
-      for (int n = 0; n < NV; ++n) r[row * NV + n] = b[row * NV + n] - omega * acc[n];
+      for (int n = 0; n < NV; ++n) r[row * NV + n] = bi[n] - omega * acc[n];
   } else {
     const int64_t row = int64_t(blk - nblk_a) * (kBlock / GQ) + threadIdx.x / GQ;
     const int lane = threadIdx.x % GQ;
@@ -176,22 +192,26 @@ __global__ __launch_bounds__(kBlock) void vup_kernel(
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
-  T ap[NV], pe[NV];
+  T ap[NV], pe[NV], bi[NV], ri[NV];
+  T wd = T(0);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = T(0);
+  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = bi[q] = ri[q] = T(0);
+  if (lane == 0) {  // the row's own values, loaded ahead of the products
+    wd = omega * dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      bi[q] = b[row * NV + q];
+      ri[q] = r[row * NV + q];
+    }
+  }
   const GatherPlain<T, NV> ge{e};
   row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
   row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
   group_reduce<T, G, NV>(pe);
   group_reduce<T, G, NV>(ap);
-  if (lane == 0) {
-    const T wd = omega * dinv[row];
+  if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const T bi = b[row * NV + q];
-      y[row * NV + q] = wd * bi + pe[q] + wd * (r[row * NV + q] - ap[q]);
-    }
-  }
+    for (int q = 0; q < NV; ++q) y[row * NV + q] = wd * bi[q] + pe[q] + wd * (ri[q] - ap[q]);
 }
 
 // Residual of the learned pre-smoother's correction and the partials of its
@@ -303,11 +323,14 @@ __global__ __launch_bounds__(kBlock) void vdown_sel_kernel(
     const int64_t row = int64_t(blockIdx.x) * (kBlock / GA) + threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
     if (row >= na) return;
+    T bi[NV];
+#pragma unroll
+    for (int n = 0; n < NV; ++n) bi[n] = lane == 0 ? b[row * NV + n] : T(0);
     row_accumulate<T, GA, NV>(rpa, cia, va, row, lane, GatherPlain<T, NV>{b}, acc);
     group_reduce<T, GA, NV>(acc);
     if (lane == 0)
 #pragma unroll
-      for (int n = 0; n < NV; ++n) r[row * NV + n] = b[row * NV + n] - omega * acc[n];
+      for (int n = 0; n < NV; ++n) r[row * NV + n] = bi[n] - omega * acc[n];
   } else {
     const int64_t row = int64_t(blockIdx.x - nblk_a) * (kBlock / GQ) + threadIdx.x / GQ;
     const int lane = threadIdx.x % GQ;
@@ -331,25 +354,28 @@ __global__ __launch_bounds__(kBlock) void vup_sel_kernel(
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
-  const bool learned = flag[0] != 0;
-  T ap[NV], pe[NV];
+  T ap[NV], pe[NV], x0[NV], rr[NV];
+  T wd = T(0);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = T(0);
+  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = x0[q] = rr[q] = T(0);
+  if (lane == 0) {  // the row's own values, loaded ahead of the products
+    const bool learned = flag[0] != 0;
+    wd = omega * dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t k = row * NV + q;
+      x0[q] = learned ? x_m[k] : wd * b[k];
+      rr[q] = learned ? r_m[k] : r[k];
+    }
+  }
   const GatherPlain<T, NV> ge{e};
   row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
   row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
   group_reduce<T, G, NV>(pe);
   group_reduce<T, G, NV>(ap);
-  if (lane == 0) {
-    const T wd = omega * dinv[row];
+  if (lane == 0)
 #pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      const int64_t k = row * NV + q;
-      const T x0 = learned ? x_m[k] : wd * b[k];
-      const T rr = learned ? r_m[k] : r[k];
-      y[k] = x0 + pe[q] + wd * (rr - ap[q]);
-    }
-  }
+    for (int q = 0; q < NV; ++q) y[row * NV + q] = x0[q] + pe[q] + wd * (rr[q] - ap[q]);
 }
 
 // ------------------------------------------------ Chebyshev level sweeps
@@ -385,24 +411,33 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(int64_t n, const int6
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
-  T acc[NV];
+  T acc[NV], dj[NV], rp0[NV], xi[NV];
+  T di = T(0);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) acc[q] = T(0);
-  row_accumulate<T, G, NV>(rp, ci, val, row, lane, g, acc);
-  group_reduce<T, G, NV>(acc);
-  if (lane == 0) {
-    const T di = g.dinv[row];
+  for (int q = 0; q < NV; ++q) acc[q] = dj[q] = rp0[q] = xi[q] = T(0);
+  if (lane == 0) {  // the row's own values, loaded ahead of the product
+    di = g.dinv[row];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int64_t k = row * NV + q;
-      const T dj = g(int32_t(row), q);
-      const T rj = g.r[k] - acc[q];
+      dj[q] = g(int32_t(row), q);
+      rp0[q] = g.r[k];
+      xi[q] = xinit ? T(0) : x[k];
+    }
+  }
+  row_accumulate<T, G, NV>(rp, ci, val, row, lane, g, acc);
+  group_reduce<T, G, NV>(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int64_t k = row * NV + q;
+      const T rj = rp0[q] - acc[q];
       if (fuse) {
-        x[k] = x[k] + dj + (a2 * dj + c2 * di * rj);
+        x[k] = xi[q] + dj[q] + (a2 * dj[q] + c2 * di * rj);
       } else {
-        dout[k] = dj;
+        dout[k] = dj[q];
         rout[k] = rj;
-        x[k] = xinit ? dj : x[k] + dj;
+        x[k] = xinit ? dj[q] : xi[q] + dj[q];
       }
     }
   }
@@ -420,21 +455,29 @@ __global__ __launch_bounds__(kBlock) void cheb_prolong_kernel(
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
-  T ap[NV], pe[NV];
+  T ap[NV], pe[NV], x0[NV], r0[NV];
+  T di = T(0);
 #pragma unroll
-  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = T(0);
+  for (int q = 0; q < NV; ++q) ap[q] = pe[q] = x0[q] = r0[q] = T(0);
+  if (lane == 0) {  // the row's own values, loaded ahead of the products
+    di = dinv[row];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      x0[q] = x[row * NV + q];
+      r0[q] = r[row * NV + q];
+    }
+  }
   const GatherPlain<T, NV> ge{e};
   row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
   row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
   group_reduce<T, G, NV>(pe);
   group_reduce<T, G, NV>(ap);
   if (lane == 0) {
-    const T di = dinv[row];
 #pragma unroll
     for (int q = 0; q < NV; ++q) {
       const int64_t k = row * NV + q;
-      const T rk = r[k] - ap[q];
-      T xk = x[k] + pe[q];
+      const T rk = r0[q] - ap[q];
+      T xk = x0[q] + pe[q];
       if (fuse) xk = xk + c1 * di * rk;
       x[k] = xk;
       r[k] = rk;

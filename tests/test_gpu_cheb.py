@@ -121,3 +121,52 @@ def test_chebyshev_on_the_fluid_velocity_hierarchy_is_rejected():
     with pytest.raises(FsiError):
         s.build_precond("f64", cheb_degree=2, cheb=("H_A",))
     s.close()
+
+
+@pytest.mark.parametrize("deg,ratio", [(2, 8.0), (3, 8.0), (5, 4.0)])
+@pytest.mark.parametrize("hname", ["H_MS", "H_SIG", "H_M"])
+@pytest.mark.parametrize("name,mc", [("c1", 40), ("tiny3d", 10)])
+def test_chebyshev_only_inverse_parity(name, mc, hname, deg, ratio):
+    """k Chebyshev steps alone on the finest matrix (no coarse grid), the
+    option meant for the solid mass matrix."""
+    from oracle import amg, precond
+    from paper_1801_05648_amd import FsiSolver
+    bs, H = _oracle(name, mc)
+    h = H[hname]
+    assert h.nlevels >= 2
+    s = FsiSolver.from_system(system(name), device=0)
+    s.build_precond("f64", max_coarse=mc, poly=(hname,), poly_degree=deg, poly_ratio=ratio)
+    _import(s, H, [hname])
+    L0 = h.levels[0]
+    inv = lambda v: amg.chebyshev(L0.A, L0.dinv, v, np.zeros_like(v), deg, amg.CHEB_BOOST * L0.rho, ratio)
+    rng = np.random.default_rng(6)
+    if hname == "H_M":
+        b = rng.standard_normal(bs.n_m)
+        ref = precond.mesh_solve(bs, inv, b)
+    else:
+        b = rng.standard_normal(L0.A.shape[0])
+        ref = inv(b)
+    x = s.vcycle(hname, _dev(b)).cpu().numpy()
+    err = _rel(x, ref)
+    print(f"{name} {hname} Chebyshev-only k={deg} ratio {ratio}: rel. err {err:.2e}")
+    assert err <= 1e-12
+    s.close()
+
+
+def test_chebyshev_only_mass_inverse_solve_matches_oracle():
+    """C1, 40-row coarse grids: M_s by 3 Chebyshev steps alone, Chebyshev(4)
+    V-cycles on H_SIG and H_P; the GPU solution at 1e-8 against the oracle's
+    1e-12 solution with the same hierarchies and inverses."""
+    from oracle import krylov, precond
+    from paper_1801_05648_amd import FsiSolver
+    bs, H = _oracle("c1", 40)
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4, "H_P": 4}, poly={"H_MS": (3, 8.0)})
+    xo, io = krylov.fgmres(bs.matvec, P, bs.sys.b, tol=1e-12, restart=50, maxit=2000)
+    s = FsiSolver.from_system(system("c1"), device=0)
+    s.build_precond("f64", max_coarse=40, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3)
+    _import(s, H, list(H.keys()))
+    x, info = s.solve(_dev(bs.sys.b), tol=1e-8)
+    err = _rel(x.cpu().numpy(), xo)
+    print(f"c1 M_s Chebyshev-only: GPU {info.iters} it, oracle {io.iters} it to 1e-12, rel. diff {err:.2e}")
+    assert info.converged and err <= 1e-6
+    s.close()
