@@ -206,6 +206,7 @@ struct DLevel {
   T omega = T(0);
   int64_t n = 0;
   int gdown = 8, gdownq = 64, gup = 8;
+  bool deep = false;                   // large level: four loads in flight per lane
   int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
   std::vector<T> ca, cc;               // recurrence coefficients a_j, c_j, j = 1..cheb
   std::shared_ptr<DevBuf> d0, d1, r1;  // Chebyshev directions and second residual buffer
@@ -245,6 +246,8 @@ void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c
     rho = rn;
   }
 }
+
+constexpr int64_t kDeepNnz = int64_t(1) << 21;
 
 template <typename T>
 DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
@@ -333,9 +336,13 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
         D.rm = std::make_shared<DevBuf>();
         D.rm->alloc(sizeof(T) * d.n * nv);
       }
-      d.gdown = pick_group(d.AD.nnz, d.AD.nrows);
-      d.gdownq = pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16;
-      d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1));
+      // large levels are bandwidth streams (about six entries per lane, four
+      // loads in flight); small ones latency chains (about three per lane)
+      d.deep = d.AD.nnz >= kDeepNnz;
+      const int per_lane = d.deep ? 6 : 3;
+      d.gdown = pick_group(d.AD.nnz, d.AD.nrows, per_lane);
+      d.gdownq = d.deep ? 16 : (pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16);
+      d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1), per_lane);
       const double vb = double(sizeof(T)) * nv;
       // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
       D.bytes_per_cycle += d.AD.bytes() + d.Q.bytes() + d.P.bytes() + d.AP.bytes() +
@@ -505,6 +512,10 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
             d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
             d.R0.drp(), d.R0.dci(), d.R0.dval(), b, d.omega, r, bc, H.rm->template as<T>(), H.mlp->npart,
             H.mlp->flag, H.mlp->fallbacks, na);
+      else if (d.deep)
+        vdown_kernel<T, GA, GQ, NV, true><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
+                                                                      d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
+                                                                      b, d.omega, r, bc, na);
       else
         vdown_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
                                                                 d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
@@ -521,6 +532,9 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
       vup_sel_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(
           d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b, dinv, d.omega, r,
           H.xm->template as<T>(), H.rm->template as<T>(), H.mlp->flag, out);
+    else if (d.deep)
+      vup_kernel<T, G, NV, true><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(
+          d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b, dinv, d.omega, r, out);
     else
       vup_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(d.n, d.P.drp(), d.P.dci(), d.P.dval(),
                                                                         d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b,

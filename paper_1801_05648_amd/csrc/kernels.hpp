@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
 // residual b_c = R r = Q b on the coarse rows, Q = R (I - omega A D^{-1})
 // formed at setup.  Both read only b, so one launch covers both row sets
 // (blocks [0, nblk_a) the fine rows, the rest the coarse rows).
-template <typename T, int GA, int GQ, int NV>
+template <typename T, int GA, int GQ, int NV, bool DEEP = false>
 __global__ __launch_bounds__(kBlock) void vdown_kernel(
     int64_t na, const int64_t* __restrict__ rpa, const int32_t* __restrict__ cia, const T* __restrict__ va,
     int64_t nq, const int64_t* __restrict__ rpq, const int32_t* __restrict__ ciq, const T* __restrict__ vq,
@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kBlock) void vdown_kernel(
     T bi[NV];
 #pragma unroll
     for (int n = 0; n < NV; ++n) bi[n] = lane == 0 ? b[row * NV + n] : T(0);
-    row_accumulate<T, GA, NV>(rpa, cia, va, row, lane, GatherPlain<T, NV>{b}, acc);
+    row_accumulate<T, GA, NV, GatherPlain<T, NV>, DEEP>(rpa, cia, va, row, lane, GatherPlain<T, NV>{b}, acc);
     group_reduce<T, GA, NV>(acc);
     if (lane == 0)
 #pragma unroll
@@ -170,7 +170,7 @@ __global__ __launch_bounds__(kBlock) void vdown_kernel(
     const int64_t row = int64_t(blk - nblk_a) * (kBlock / GQ) + threadIdx.x / GQ;
     const int lane = threadIdx.x % GQ;
     if (row >= nq) return;
-    row_accumulate<T, GQ, NV>(rpq, ciq, vq, row, lane, GatherPlain<T, NV>{b}, acc);
+    row_accumulate<T, GQ, NV, GatherPlain<T, NV>, DEEP>(rpq, ciq, vq, row, lane, GatherPlain<T, NV>{b}, acc);
     group_reduce<T, GQ, NV>(acc);
     if (lane == 0)
 #pragma unroll
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kBlock) void vdown_kernel(
 //   y = omega D^{-1} b + P e + omega D^{-1} (r - (A P) e),
 // r from the down-sweep and A P formed at setup: one pass over the rows of P
 // and A P.  y may alias b.
-template <typename T, int G, int NV>
+template <typename T, int G, int NV, bool DEEP = false>
 __global__ __launch_bounds__(kBlock) void vup_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
@@ -205,8 +205,8 @@ __global__ __launch_bounds__(kBlock) void vup_kernel(
     }
   }
   const GatherPlain<T, NV> ge{e};
-  row_accumulate<T, G, NV>(rpp, cip, vp, row, lane, ge, pe);
-  row_accumulate<T, G, NV>(rpap, ciap, vap, row, lane, ge, ap);
+  row_accumulate<T, G, NV, GatherPlain<T, NV>, DEEP>(rpp, cip, vp, row, lane, ge, pe);
+  row_accumulate<T, G, NV, GatherPlain<T, NV>, DEEP>(rpap, ciap, vap, row, lane, ge, ap);
   group_reduce<T, G, NV>(pe);
   group_reduce<T, G, NV>(ap);
   if (lane == 0)
