@@ -96,7 +96,8 @@ DCsr<T> upload(const HCsr& A, hipStream_t s) {
   D.nrows = A.nrows;
   D.ncols = A.ncols;
   D.nnz = A.nnz();
-  D.group = pick_group(D.nnz, D.nrows);
+  D.deep = D.nnz >= (int64_t(1) << 21);  // large: a bandwidth stream
+  D.group = pick_group(D.nnz, D.nrows, D.deep ? 8 : 3);
   D.rp = std::make_shared<DevBuf>();
   D.rp->alloc(sizeof(int64_t) * (A.nrows + 1));
   HIP_TRY(hipMemcpyAsync(D.rp->p, A.rp.data(), sizeof(int64_t) * (A.nrows + 1), hipMemcpyHostToDevice, s));
