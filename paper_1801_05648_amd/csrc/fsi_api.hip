@@ -72,6 +72,7 @@ struct DCsr {
   int64_t nrows = 0, ncols = 0, nnz = 0;
   int group = 8;
   bool deep = false;  // four entries in flight per lane (large streamed matrices)
+  RowSegments seg{};  // nseg > 0: row segments with their own lanes per row
   std::shared_ptr<DevBuf> rp, ci, val;
   const int64_t* drp() const { return rp->as<int64_t>(); }
   const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
@@ -153,6 +154,13 @@ void with_group(int G, F&& f) {
 template <typename T, int NV, class Gather, class Epi>
 void launch_rows(const DCsr<T>& A, Gather g, Epi e, hipStream_t s) {
   if (A.nrows == 0) return;
+  if constexpr (NV == 1) {
+    if (A.seg.nseg > 0) {
+      csr_segments_kernel<T, Gather, Epi><<<A.seg.blk0[A.seg.nseg], kBlock, 0, s>>>(A.seg, A.drp(), A.dci(),
+                                                                                    A.dval(), g, e);
+      return;
+    }
+  }
   with_group(A.group, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
     const unsigned grid = grid_for(A.nrows, kBlock / G);
@@ -1874,6 +1882,28 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     DCsr<double> dAh = upload<double>(Ah, ctx->stream);
     dAh.group = pick_group(dAh.nnz, dAh.nrows, 8);
     dAh.deep = true;
+    {
+      // mesh, solid, fluid-velocity and pressure rows: about twelve entries
+      // per lane each (measured best for the long rows; at least 4 lanes)
+      const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
+      RowSegments sg{};
+      sg.nseg = 0;
+      sg.blk0[0] = 0;
+      sg.row0[0] = 0;
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r0 = bounds[q], r1 = bounds[q + 1];
+        if (r1 <= r0) continue;
+        const int64_t nz = Ah.rp[r1] - Ah.rp[r0];
+        const double avg = double(nz) / double(r1 - r0);
+        int g = 4;
+        while (g < 32 && g * 12 < avg) g *= 2;
+        const int k = sg.nseg++;
+        sg.g[k] = g;
+        sg.row0[k + 1] = r1;
+        sg.blk0[k + 1] = sg.blk0[k] + unsigned((r1 - r0 + kBlock / g - 1) / (kBlock / g));
+      }
+      dAh.seg = sg;
+    }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     // commit
     fsi_ctx& c = *ctx;

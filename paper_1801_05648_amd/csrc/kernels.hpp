@@ -138,6 +138,47 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
   if (lane == 0) epi(row, acc, pre);
 }
 
+// Row product over up to four consecutive row segments, each with its own
+// lanes per row (blocks [seg_blk[s], seg_blk[s+1]) serve segment s); for a
+// matrix whose row blocks have very different lengths, e.g. the mesh, solid,
+// fluid-velocity and pressure rows of A_h.  Four loads in flight per lane.
+struct RowSegments {
+  int64_t row0[5];    // segment s: rows [row0[s], row0[s+1])
+  unsigned blk0[5];   // segment s: blocks [blk0[s], blk0[s+1])
+  int g[4];           // lanes per row (4, 8, 16 or 32)
+  int nseg;
+};
+
+template <typename T, int G, class Gather, class Epi>
+__device__ __forceinline__ void segment_rows(int64_t r0, int64_t r1, unsigned blk, const int64_t* __restrict__ rp,
+                                             const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                             const Gather& gx, const Epi& epi) {
+  const int64_t row = r0 + int64_t(blk) * (kBlock / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  if (row >= r1) return;
+  T acc[1] = {T(0)}, pre[1] = {T(0)};
+  if (lane == 0) epi.load(row, pre);
+  row_accumulate<T, G, 1, Gather, true>(rp, ci, val, row, lane, gx, acc);
+  group_reduce<T, G, 1>(acc);
+  if (lane == 0) epi(row, acc, pre);
+}
+
+template <typename T, class Gather, class Epi>
+__global__ __launch_bounds__(kBlock) void csr_segments_kernel(RowSegments sg, const int64_t* __restrict__ rp,
+                                                               const int32_t* __restrict__ ci,
+                                                               const T* __restrict__ val, Gather gx, Epi epi) {
+  int s = 0;
+  while (s + 1 < sg.nseg && blockIdx.x >= sg.blk0[s + 1]) ++s;
+  const unsigned blk = blockIdx.x - sg.blk0[s];
+  const int64_t r0 = sg.row0[s], r1 = sg.row0[s + 1];
+  switch (sg.g[s]) {
+    case 4: segment_rows<T, 4>(r0, r1, blk, rp, ci, val, gx, epi); break;
+    case 8: segment_rows<T, 8>(r0, r1, blk, rp, ci, val, gx, epi); break;
+    case 16: segment_rows<T, 16>(r0, r1, blk, rp, ci, val, gx, epi); break;
+    default: segment_rows<T, 32>(r0, r1, blk, rp, ci, val, gx, epi); break;
+  }
+}
+
 // ------------------------------------------------ fused V-cycle level sweeps
 // Down-sweep of a V(1,1) level with a zero initial guess: the pre-smoothed
 // x = omega D^{-1} b gives the residual r = b - omega (A D^{-1}) b on the fine
