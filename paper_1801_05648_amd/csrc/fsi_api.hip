@@ -682,6 +682,7 @@ struct fsi_ctx {
   DCsr<double> Ah;
   // preconditioner
   int precision = FSI_P_F64;
+  int gs_blocks = kGsBlocks;
   int cheb[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev degree per hierarchy (0: Jacobi)
   int poly[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev steps alone, no coarse grid (0: off)
   double poly_ratio = 8.0;
@@ -869,6 +870,9 @@ void ensure_krylov(fsi_ctx& c, int m) {
   c.drop_graphs();
   c.V.alloc(sizeof(double) * size_t(m + 1) * c.N);
   c.Z.alloc(sizeof(double) * size_t(m) * c.N);
+  // Gram-Schmidt blocks: about four elements per thread (one reduction per
+  // tile of vectors is shared by more elements), at most kGsBlocks
+  c.gs_blocks = int(std::min<int64_t>(kGsBlocks, std::max<int64_t>(64, (c.N + 4 * kBlock - 1) / (4 * kBlock))));
   c.part.alloc(sizeof(double) * size_t(kGsBlocks) * (m + 2));
   c.dh.alloc(sizeof(double) * 2 * size_t(3 * (m + 2)));
   c.dy.alloc(sizeof(double) * size_t(m + 1));
@@ -887,9 +891,9 @@ void ensure_krylov(fsi_ctx& c, int m) {
 
 // One fused Gram-Schmidt pass and its reduction: out[first..nv] on the device.
 void gs_pass(fsi_ctx& c, int mode, int nv, double* w, const double* h, double* out, hipStream_t s) {
-  gs_pass_kernel<<<kGsBlocks, kBlock, 0, s>>>(c.N, nv, c.V.as<double>(), c.N, w, h, mode, c.part.as<double>());
+  gs_pass_kernel<<<c.gs_blocks, kBlock, 0, s>>>(c.N, nv, c.V.as<double>(), c.N, w, h, mode, c.part.as<double>());
   const int first = mode == 2 ? nv : 0;
-  gs_reduce_kernel<<<nv + 1 - first, kBlock, 0, s>>>(kGsBlocks, first, c.part.as<double>(), out);
+  gs_reduce_kernel<<<nv + 1 - first, kBlock, 0, s>>>(c.gs_blocks, first, c.part.as<double>(), out);
 }
 
 void givens(double a, double b, double& cs, double& sn) {

@@ -539,7 +539,15 @@ __global__ __launch_bounds__(kBlock) void dense_gemv_kernel(int64_t n, const dou
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   const double* a = Ainv + row * n;
-  for (int64_t j = lane; j < n; j += 64) {
+  int64_t j = lane;
+  for (; j + 192 < n; j += 256) {  // four independent loads in flight per lane
+    const double a0 = a[j], a1 = a[j + 64], a2 = a[j + 128], a3 = a[j + 192];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      acc[v] += (a0 * double(B[j * NV + v]) + a1 * double(B[(j + 64) * NV + v])) +
+                (a2 * double(B[(j + 128) * NV + v]) + a3 * double(B[(j + 192) * NV + v]));
+  }
+  for (; j < n; j += 64) {
     const double aj = a[j];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += aj * double(B[j * NV + v]);
