@@ -74,7 +74,7 @@ struct DCsr {
   bool deep = false;  // four entries in flight per lane (large streamed matrices)
   RowSegments seg{};  // nseg > 0: row segments with their own lanes per row
   std::shared_ptr<DevBuf> rp, ci, val;
-  const int64_t* drp() const { return rp->as<int64_t>(); }
+  const int64_t* drp() const { return rp ? rp->as<int64_t>() : nullptr; }
   const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
   const T* dval() const { return val ? val->as<T>() : nullptr; }
   double bytes() const { return double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8; }
@@ -216,6 +216,7 @@ struct DLevel {
   int64_t n = 0;
   int gdown = 8, gdownq = 64, gup = 8;
   bool deep = false;                   // large level: four loads in flight per lane
+  bool split = false;                  // restriction by R in its own launch (no Q)
   int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
   std::vector<T> ca, cc;               // recurrence coefficients a_j, c_j, j = 1..cheb
   std::shared_ptr<DevBuf> d0, d1, r1;  // Chebyshev directions and second residual buffer
@@ -257,6 +258,7 @@ void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c
 }
 
 constexpr int64_t kDeepNnz = int64_t(1) << 21;
+constexpr int64_t kSplitNnz = int64_t(1) << 21;
 
 template <typename T>
 DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
@@ -332,7 +334,12 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       HCsr AD = h.A;
       scale_cols(AD, h.dinv);
       d.AD = upload<T>(AD, s);
-      d.Q = upload<T>(Q, s);
+      // Restricting through Q fuses the restriction into the down-sweep but
+      // reads nnz(Q) instead of nnz(R) entries; where the difference costs
+      // more than a launch, restrict the residual with R in a launch of its own.
+      d.split = !(l == 0 && keep_a0) && Q.nnz() - h.R.nnz() >= kSplitNnz;
+      if (d.split) d.R0 = upload<T>(h.R, s);
+      else d.Q = upload<T>(Q, s);
       d.P = upload<T>(h.P, s);
       d.AP = upload<T>(AP, s);
       d.dinv = upload_vec<T>(h.dinv, s);
@@ -350,12 +357,12 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       d.deep = d.AD.nnz >= kDeepNnz;
       const int per_lane = d.deep ? 6 : 3;
       d.gdown = pick_group(d.AD.nnz, d.AD.nrows, per_lane);
-      d.gdownq = d.deep ? 16 : (pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16);
+      d.gdownq = d.deep || d.split ? 16 : (pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16);
       d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1), per_lane);
       const double vb = double(sizeof(T)) * nv;
       // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
-      D.bytes_per_cycle += d.AD.bytes() + d.Q.bytes() + d.P.bytes() + d.AP.bytes() +
-                           double(d.n) * (2 * sizeof(T) + 5 * vb) + double(h.P.ncols) * 2 * vb;
+      D.bytes_per_cycle += d.AD.bytes() + (d.split ? d.R0.bytes() + double(d.n) * vb : d.Q.bytes()) + d.P.bytes() +
+                           d.AP.bytes() + double(d.n) * (2 * sizeof(T) + 5 * vb) + double(h.P.ncols) * 2 * vb;
     }
     auto mk = [&](int64_t cnt) {
       auto b = std::make_shared<DevBuf>();
@@ -515,7 +522,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
     const unsigned na = grid_for(d.AD.nrows, kBlock / GA);
     auto go = [&](auto gq) {
       constexpr int GQ = decltype(gq)::value;
-      const unsigned nq = grid_for(d.Q.nrows, kBlock / GQ);
+      const unsigned nq = d.split ? 0u : grid_for(d.Q.nrows, kBlock / GQ);
       if (learned)
         vdown_sel_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(
             d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
@@ -533,6 +540,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
     if (d.gdownq == 64) go(std::integral_constant<int, 64>{});
     else go(std::integral_constant<int, 16>{});
   });
+  if (d.split) launch_rows<T, NV>(d.R0, GatherPlain<T, NV>{r}, EpiStore<T, NV>{bc}, s);  // b_c = R r
   T* e = c.y->template as<T>();
   vcycle_rec<T, NV>(H, l + 1, bc, e, s, plain);
   with_group(d.gup, [&](auto gc) {

@@ -232,3 +232,27 @@ def test_timed_solve_matches_and_reports_phases():
     assert i2.n_timed == i2.iters
     assert i2.t_spmv_ms > 0 and i2.t_precond_ms > 0 and i2.t_gs_ms > 0
     assert i2.t_spmv_ms + i2.t_precond_ms + i2.t_gs_ms <= i2.t_total_ms * 1.05
+
+
+@pytest.mark.parametrize("hname", ["H_A", "H_M", "H_SIG"])
+def test_vcycle_parity_3d_with_large_levels(hname):
+    """32x8x8-cell 3D system: levels large enough for the four-deep loads and,
+    on H_A, for restricting with R in a launch of its own (no fused Q)."""
+    from oracle import amg, blocks, precond
+    from paper_1801_05648_amd import FsiSolver
+    bs = blocks.BlockSystem(system("m3"))
+    H = precond.build_hierarchies(bs, max_coarse=2000)
+    s = FsiSolver.from_system(system("m3"), device=0)
+    s.build_precond("f64", max_coarse=2000)
+    _import_oracle_hierarchies(s, {hname: H[hname]})
+    h = H[hname]
+    rng = np.random.default_rng(12)
+    if hname == "H_M":
+        b = rng.standard_normal(bs.n_m)
+        ref = precond.mesh_solve(bs, lambda v: amg.vcycle(h, v), b)
+    else:
+        b = rng.standard_normal(h.levels[0].A.shape[0])
+        ref = amg.vcycle(h, b)
+    x = s.vcycle(hname, _dev(b)).cpu().numpy()
+    assert _rel(x, ref) <= 1e-12, _rel(x, ref)
+    s.close()
