@@ -352,10 +352,10 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
         D.rm = std::make_shared<DevBuf>();
         D.rm->alloc(sizeof(T) * d.n * nv);
       }
-      // large levels are bandwidth streams (about six entries per lane, four
+      // large levels are bandwidth streams (about ten entries per lane, four
       // loads in flight); small ones latency chains (about three per lane)
       d.deep = d.AD.nnz >= kDeepNnz;
-      const int per_lane = d.deep ? 6 : 3;
+      const int per_lane = d.deep ? 10 : 3;
       d.gdown = pick_group(d.AD.nnz, d.AD.nrows, per_lane);
       d.gdownq = d.deep || d.split ? 16 : (pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16);
       d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1), per_lane);
