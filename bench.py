@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0
 # counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both scales read off a
 # 256 MiB device copy in the same runs); see profiles/a_h_spmv_hbm_traffic.md.
 # Valid only for the kernel and workload it was measured on.
-MEASURED_TRAFFIC = {}
+MEASURED_TRAFFIC = {"c2": 191122665, "c3": 2250991934}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
 
