@@ -386,7 +386,7 @@ def main():
         "phase_ms_per_iter": {"precond": round(t_pre / max(n_timed, 1), 4),
                               "spmv": round(spmv_ms, 4), "gram_schmidt": round(t_gs / max(n_timed, 1), 4)},
         "roofline": {
-            "kernel": "csr_rows_kernel (A_h product inside the solve)",
+            "kernel": "csr_segments_kernel (A_h product inside the solve)",
             "bound": "hbm",
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
