@@ -197,9 +197,8 @@ class FsiSolver:
 
     def set_system(self, blocks, layout):
         """Replace the linear system (fsi_setup_blocks); invalidates the
-        preconditioner, keeps a learned smoother's weights."""
-        self.N = int(layout["n_m"] + layout["n_s"] + layout["n_f"])
-        self.layout = dict(layout)
+        preconditioner, keeps a learned smoother's weights.  On failure the
+        previous system stays in place."""
         keep = []
         arr = (CCsr * 8)()
         for i, name in enumerate(BLOCKS):
@@ -218,6 +217,8 @@ class FsiSolver:
                       int(coords.shape[0]), coords.ctypes.data, dof_node.ctypes.data,
                       None if ijk is None else ijk.ctypes.data)
         self._check(self.lib.fsi_setup_blocks(self.ctx, ctypes.byref(lay), arr, 0))
+        self.N = int(layout["n_m"] + layout["n_s"] + layout["n_f"])
+        self.layout = dict(layout)
 
     @staticmethod
     def layout_of(sysm):

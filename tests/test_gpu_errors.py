@@ -1,0 +1,122 @@
+"""Failure handling through the C ABI: every error is a status code with a
+message, the context keeps its previous state, and the solver stays usable."""
+import copy
+
+import numpy as np
+import pytest
+
+from conftest import system
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+
+
+def _solver(name="c1"):
+    from paper_1801_05648_amd import FsiSolver
+    s = FsiSolver.from_system(system(name), device=0)
+    s.build_precond("f64")
+    return s
+
+
+def test_iteration_bound_returns_the_best_iterate():
+    from oracle import blocks
+    sysm = system("c1")
+    bs = blocks.BlockSystem(sysm)
+    s = _solver()
+    x, info = s.solve(_dev(sysm.b), maxit=3)
+    assert info.status == "FSI_NOT_CONVERGED" and not info.converged and info.iters == 3
+    xh = x.cpu().numpy()
+    r = np.linalg.norm(sysm.b - bs.matvec(xh)) / np.linalg.norm(sysm.b)
+    assert np.all(np.isfinite(xh)) and r < 1.0
+    assert abs(info.true_rel_resid - r) <= 1e-6 * r
+    x2, info2 = s.solve(_dev(sysm.b))  # still usable
+    assert info2.converged
+    s.close()
+
+
+def test_zero_rhs_gives_zero_solution_without_iterations():
+    s = _solver()
+    b = torch.zeros(s.N, dtype=torch.float64, device="cuda:0")
+    x, info = s.solve(b)
+    assert info.converged and info.iters == 0
+    assert torch.count_nonzero(x).item() == 0
+    s.close()
+
+
+def test_non_finite_rhs_is_rejected():
+    from paper_1801_05648_amd import FsiError
+    sysm = system("c1")
+    s = _solver()
+    b = sysm.b.copy()
+    b[17] = np.nan
+    with pytest.raises(FsiError) as e:
+        s.solve(_dev(b))
+    assert e.value.name == "FSI_ERR_NUMERIC"
+    _, info = s.solve(_dev(sysm.b))
+    assert info.converged
+    s.close()
+
+
+def test_out_of_range_column_is_rejected_and_the_system_kept():
+    from paper_1801_05648_amd import FsiError, FsiSolver
+    sysm = system("c1")
+    s = _solver()
+    _, info0 = s.solve(_dev(sysm.b))
+    bad = copy.deepcopy(sysm.blocks)
+    blk = bad["F"]
+    blk.col = blk.col.copy()
+    blk.col[5] = blk.ncols  # one past the last column
+    with pytest.raises(FsiError) as e:
+        s.set_system(bad, FsiSolver.layout_of(sysm))
+    assert e.value.name == "FSI_ERR_CSR"
+    _, info1 = s.solve(_dev(sysm.b))  # the previous system and preconditioner are intact
+    assert info1.converged and info1.iters == info0.iters
+    s.close()
+
+
+def test_zero_diagonal_is_rejected_at_preconditioner_build():
+    from paper_1801_05648_amd import FsiError, FsiSolver
+    sysm = system("c1")
+    bad = copy.deepcopy(sysm.blocks)
+    M = bad["M"]
+    M.val = M.val.copy()
+    d = sysm.dim
+    for row in range(d):  # node 0 of the mesh: both components, keeping M = L (x) I_d
+        for k in range(M.rowptr[row], M.rowptr[row + 1]):
+            if M.col[k] == row:
+                M.val[k] = 0.0
+    s = FsiSolver(bad, FsiSolver.layout_of(sysm), device=0)
+    with pytest.raises(FsiError) as e:
+        s.build_precond("f64")
+    assert e.value.name == "FSI_ERR_NUMERIC"
+    s.close()
+
+
+def test_call_order_and_argument_checks():
+    from paper_1801_05648_amd import FsiError, FsiSolver
+    sysm = system("c1")
+    s = FsiSolver.from_system(sysm, device=0)
+    with pytest.raises(FsiError) as e:
+        s.solve(_dev(sysm.b))
+    assert e.value.name == "FSI_ERR_STATE"
+    s.build_precond("f64")
+    with pytest.raises(TypeError):
+        s.solve(torch.from_numpy(sysm.b))  # host tensor
+    with pytest.raises(FsiError) as e:
+        s.solve(_dev(sysm.b), tol=-1.0)
+    assert e.value.name == "FSI_ERR_ARG"
+    b = _dev(sysm.b)
+    with pytest.raises(FsiError) as e:
+        s.solve(b, b)  # x aliases b
+    assert e.value.name == "FSI_ERR_ARG"
+    with pytest.raises(FsiError) as e:
+        s.build_precond("f64", cheb_degree=3, cheb=("H_A",))
+    assert e.value.name == "FSI_ERR_ARG"
+    _, info = s.solve(_dev(sysm.b))  # the failed calls left the preconditioner in place
+    assert info.converged
+    s.close()
