@@ -9,8 +9,10 @@
  * (Jodlbauer, Langer, Wick, Section 3.4: unknowns ordered mesh motion, solid,
  * fluid) by flexible GMRES, right-preconditioned with the approximate block
  * LDU factorisation of Section 4.1 ("Evaluation of P^{-1} r"): C_sm dropped,
- * fluid Schur complement approximated by F, every inverse replaced by
- * smoothed-aggregation AMG V(1,1) cycles (Sections 4.2-4.4).
+ * fluid Schur complement approximated by F, every inverse replaced by one
+ * smoothed-aggregation AMG V-cycle (Sections 4.2-4.4; damped-Jacobi or
+ * Chebyshev smoothing per hierarchy, see fsi_precond_opts), or, for the
+ * hierarchies so selected, by Chebyshev steps alone.
  *
  * Conventions shared by every call
  *   - Status: every call returns fsi_status.  A negative value is an error;

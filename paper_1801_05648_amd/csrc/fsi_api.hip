@@ -1540,20 +1540,6 @@ void coarse_solve(DHier<T>& H, const T* rc, T* cc, T* t, T* t2, int cycles, hipS
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kBlock) void scale_to_f32_kernel(int64_t n, const T* __restrict__ x, double f,
-                                                              float* __restrict__ y) {
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    y[i] = float(f * double(x[i]));
-}
-
-template <typename TI, typename TO>
-__global__ __launch_bounds__(kBlock) void cast_scale_kernel(int64_t n, const TI* __restrict__ x, double f,
-                                                            TO* __restrict__ y) {
-  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    y[i] = TO(f * double(x[i]));
-}
-
 // x.y of two device vectors, summed on the host in FP64 (loss reporting only).
 template <typename T>
 double host_dot(int64_t n, const T* pa, const T* pb, hipStream_t s) {
@@ -1580,7 +1566,7 @@ void energy_grad(DHier<T>& H, EnergyWork& w, const T* delta, const T* b, double 
   launch_rows<T, NV>(d0.R0, GatherPlain<T, NV>{r}, EpiStore<T, NV>{rc}, s);      // rc = R r
   coarse_solve<T, NV>(H, rc, cc, w.t.as<T>(), w.t2.as<T>(), cycles, s);         // cc = A_1^{-1} rc
   launch_rows<T, NV>(d0.AP, GatherPlain<T, NV>{cc}, EpiSub<T, NV>{r, g}, s);     // g = r - A P cc
-  scale_to_f32_kernel<T><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, g, -2.0 * coef, dy);
+  cast_scale_kernel<T, float><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, g, -2.0 * coef, dy);
   if (loss) {
     const double db = host_dot<T>(n, delta, b, s);
     const double dr = host_dot<T>(n, delta, r, s);

@@ -580,6 +580,14 @@ __global__ __launch_bounds__(kBlock) void cast_kernel(int64_t n, const TI* __res
     y[i] = TO(x[i]);
 }
 
+// y = f x, converted to TO (f applied in FP64)
+template <typename TI, typename TO>
+__global__ __launch_bounds__(kBlock) void cast_scale_kernel(int64_t n, const TI* __restrict__ x, double f,
+                                                            TO* __restrict__ y) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    y[i] = TO(f * double(x[i]));
+}
+
 // y *= f (in place)
 __global__ __launch_bounds__(kBlock) void scale_kernel(int64_t n, double* y, double f) {
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
