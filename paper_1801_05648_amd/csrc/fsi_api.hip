@@ -961,7 +961,7 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     info.true_rel_resid = 0.0;
     return FSI_OK;
   }
-  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), rhist(m + 2);
   auto Hat = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
   int iters = 0, restarts = 0;
   bool converged = false;
@@ -1070,6 +1070,7 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     Hat(j + 1, j) = 0.0;
     g[j + 1] = -sn[j] * g[j];
     g[j] = cs[j] * g[j];
+    rhist[j + 1] = std::fabs(g[j + 1]);  // residual estimate after step j
     ++iters;
     if (!std::isfinite(g[j + 1])) throw Error(FSI_ERR_NUMERIC, "non-finite Arnoldi coefficients");
     return std::fabs(g[j + 1]) / bnorm <= o.tol || breakdown || iters >= o.maxit;
@@ -1086,11 +1087,30 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     scale_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, V, 1.0 / beta);  // V_0 = r / beta
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
+    rhist.assign(m + 2, 0.0);
+    rhist[0] = beta;
     int k = 0;
     launch_step(0);
+    int launched = 0;
     for (int j = 0; j < m; ++j) {
+      if (launched < j) {  // not launched ahead: the previous step was expected to converge
+        launch_step(j);
+        launched = j;
+      }
       const bool more = j + 1 < m && iters + 1 < o.maxit;
-      if (more) launch_step(j + 1);  // speculative: overlaps the host work below
+      // Step j+1 is launched ahead (it overlaps the host work of step j)
+      // unless the residual estimate, extrapolated by its last reduction
+      // factor, already meets the tolerance after step j: then the
+      // speculative step would most likely be thrown away.
+      bool ahead = more;
+      if (ahead && j >= 2) {
+        const double r1 = rhist[j], r0 = rhist[j - 1];  // estimates after steps j-1, j-2
+        ahead = !(r0 > 0.0 && r1 * (r1 / r0) <= o.tol * bnorm);
+      }
+      if (ahead) {
+        launch_step(j + 1);
+        launched = j + 1;
+      }
       const bool stop = finish_step(j);
       k = j + 1;
       if (stop || !more) break;
