@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -101,3 +102,12 @@ def test_header_compiles_as_c99(tmp_path):
     src.write_text('#include "fsi.h"\nint main(void) { fsi_solve_opts o; fsi_default_solve_opts(&o); return 0; }\n')
     subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-fsyntax-only", "-I", os.path.join(ROOT, "include"),
                     str(src)], check=True)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark runs on one GPU; asked for more it exits with a message
+    (before touching a device)."""
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
