@@ -26,13 +26,14 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch of the A_h product measured with rocprofv3 hardware
 # counters (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, both scales read off a
 # 256 MiB device copy in the same runs); see profiles/a_h_spmv_hbm_traffic.md.
-# Valid only for the kernel and workload it was measured on.
-MEASURED_TRAFFIC = {"c2": 191122665, "c3": 2250991934}
+# Valid only for the kernel and workload it was measured on (empty: the
+# kernel changed since the counters were taken).
+MEASURED_TRAFFIC = {}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
 
-def spmv_bytes(sysm) -> float:
-    """Algorithmic bytes of y = A_h x (FP64 CSR, int32 columns, int64 row
+def csr_bytes(sysm) -> float:
+    """Bytes of y = A_h x in plain CSR (FP64 values, int32 columns, int64 row
     pointers): 12 nnz + 8 (N + 1) + 8 N (x once) + 8 N (y)."""
     N, nnz = sysm.N, sysm.nnz
     return 12.0 * nnz + 8.0 * (N + 1) + 8.0 * N + 8.0 * N
@@ -278,7 +279,7 @@ def main():
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": True, "spmv_bytes": spmv_bytes(sysm), "copy_bytes": 2 * 256 * 2 ** 20}))
+        print(json.dumps({"pmc_probe": True, "spmv_bytes": solver.spmv_bytes(), "csr_bytes": csr_bytes(sysm), "copy_bytes": 2 * 256 * 2 ** 20}))
         solver.close()
         return
     # one solver per seed of the linearisation state, built and warmed up
@@ -301,7 +302,7 @@ def main():
             x.zero_()
             solver.solve(b, x)
         runs.append({"seed": sd, "sysm": sysm, "solver": solver, "b": b, "x": x, "setup_ms": setup_ms,
-                     "N": sysm.N, "nnz": sysm.nnz, "bytes": spmv_bytes(sysm)})
+                     "N": sysm.N, "nnz": sysm.nnz, "bytes": solver.spmv_bytes(), "csr_bytes": csr_bytes(sysm)})
         if len(runs) > 1:
             sysm.blocks = None  # host copy of the matrix no longer needed
     torch.cuda.synchronize()
@@ -394,6 +395,7 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": MEASURED_TRAFFIC.get(cfg.name),
             "algorithmic_bytes": int(nbytes),
+            "csr_bytes": int(runs[0]["csr_bytes"]),
             "kernel_ms": round(spmv_ms, 5),
         },
         "vcycle_H_A": {

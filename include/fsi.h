@@ -178,6 +178,14 @@ fsi_status fsi_solve(fsi_ctx* ctx, const double* b, double* x, const fsi_solve_o
 /* y = A_h x (all eight blocks, C_sm included).  Device vectors of length N. */
 fsi_status fsi_spmv(fsi_ctx* ctx, const double* x, double* y);
 
+/* Bytes one y = A_h x moves as the library stores A_h (Section 3.4's block
+ * matrix): values, column indices and row (or row-group) pointers once, x
+ * once and y written.  The fluid-velocity rows are stored in groups of d
+ * rows sharing one column list, so this is below the plain CSR figure
+ * 12 nnz + 8 (N + 1) + 16 N.  Used to report achieved bandwidth.
+ * FSI_ERR_STATE before fsi_setup_blocks. */
+fsi_status fsi_spmv_bytes(fsi_ctx* ctx, double* bytes);
+
 /* z = P^{-1} r, the block LDU algorithm of Section 4.1 with the AMG
  * sub-inverses.  Device vectors of length N. */
 fsi_status fsi_apply_precond(fsi_ctx* ctx, const double* r, double* z);

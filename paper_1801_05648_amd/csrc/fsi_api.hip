@@ -74,10 +74,14 @@ struct DCsr {
   bool deep = false;  // four entries in flight per lane (large streamed matrices)
   RowSegments seg{};  // nseg > 0: row segments with their own lanes per row
   std::shared_ptr<DevBuf> rp, ci, val;
+  std::shared_ptr<DevBuf> grp_rp[4], grp_ci[4], grp_val[4];  // grouped segments
+  double seg_bytes = 0.0;  // bytes of one product as stored (segmented matrices)
   const int64_t* drp() const { return rp ? rp->as<int64_t>() : nullptr; }
   const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
   const T* dval() const { return val ? val->as<T>() : nullptr; }
-  double bytes() const { return double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8; }
+  double bytes() const {
+    return seg.nseg > 0 ? seg_bytes : double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8;
+  }
 };
 
 // Lanes per row of a CSR product: the smallest power of two in [4, 64] with
@@ -117,6 +121,16 @@ DCsr<T> upload(const HCsr& A, hipStream_t s) {
     }
   }
   return D;
+}
+
+// Device copy of a host array (setup only; synchronous, so the host array may
+// be released right after).
+template <typename U>
+std::shared_ptr<DevBuf> upload_raw(const std::vector<U>& v) {
+  auto b = std::make_shared<DevBuf>();
+  b->alloc(sizeof(U) * std::max<size_t>(v.size(), 1));
+  if (!v.empty()) HIP_TRY(hipMemcpy(b->p, v.data(), sizeof(U) * v.size(), hipMemcpyHostToDevice));
+  return b;
 }
 
 template <typename T>
@@ -1902,25 +1916,47 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     dAh.deep = true;
     {
       // mesh, solid, fluid-velocity and pressure rows: about twelve entries
-      // per lane each (measured best for the long rows; at least 4 lanes)
+      // per lane each (measured best for the long rows; at least 4 lanes).
+      // The d velocity rows of a fluid node share their columns (the stress
+      // couples the components; no fill measured): they are stored as groups
+      // of d rows, one column index per d values.
       const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
       RowSegments sg{};
       sg.nseg = 0;
       sg.blk0[0] = 0;
       sg.row0[0] = 0;
+      double bytes = 8.0 * double(N);  // y written
       for (int q = 0; q < 4; ++q) {
         const int64_t r0 = bounds[q], r1 = bounds[q + 1];
         if (r1 <= r0) continue;
-        const int64_t nz = Ah.rp[r1] - Ah.rp[r0];
-        const double avg = double(nz) / double(r1 - r0);
+        const int k = sg.nseg++;
+        const int gr = q == 2 ? d : 1;
+        int64_t units = r1 - r0, nz = Ah.rp[r1] - Ah.rp[r0];
+        if (gr > 1) {
+          std::vector<double> gv;
+          HCsr Gm = group_rows(Ah, r0, r1, gr, gv);
+          units = Gm.nrows;
+          nz = Gm.nnz();
+          dAh.grp_rp[k] = upload_raw(Gm.rp);
+          dAh.grp_ci[k] = upload_raw(Gm.ci);
+          dAh.grp_val[k] = upload_raw(gv);
+          sg.grp_rp[k] = dAh.grp_rp[k]->as<int64_t>();
+          sg.grp_ci[k] = dAh.grp_ci[k]->as<int32_t>();
+          sg.grp_val[k] = dAh.grp_val[k]->as<double>();
+          bytes += double(nz) * (4.0 + 8.0 * gr) + 8.0 * double(units + 1);
+        } else {
+          bytes += double(nz) * 12.0 + 8.0 * double(units + 1);
+        }
+        sg.grp[k] = gr;
+        const double avg = double(nz) / double(units);
         int g = 4;
         while (g < 32 && g * 12 < avg) g *= 2;
-        const int k = sg.nseg++;
         sg.g[k] = g;
         sg.row0[k + 1] = r1;
-        sg.blk0[k + 1] = sg.blk0[k] + unsigned((r1 - r0 + kBlock / g - 1) / (kBlock / g));
+        sg.blk0[k + 1] = sg.blk0[k] + unsigned((units + kBlock / g - 1) / (kBlock / g));
       }
       dAh.seg = sg;
+      dAh.seg_bytes = bytes + 8.0 * double(N);  // x read once
     }
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     // commit
@@ -2173,6 +2209,16 @@ fsi_status fsi_hierarchy_info(fsi_ctx* ctx, int which, int32_t* nlev, int64_t* n
       if (nnz) nnz[l] = H.levels[l].A.nnz();
       if (omega) omega[l] = H.levels[l].omega;
     }
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_spmv_bytes(fsi_ctx* ctx, double* bytes) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
+    if (!bytes) throw Error(FSI_ERR_ARG, "bad arguments");
+    *bytes = c.Ah.bytes();
     return FSI_OK;
   });
 }

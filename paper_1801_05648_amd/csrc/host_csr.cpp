@@ -227,4 +227,30 @@ void matvec(const HCsr& A, const double* x, double* y) {
   }
 }
 
+HCsr group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, std::vector<double>& val) {
+  HCsr G;
+  G.nrows = (r1 - r0) / g;
+  G.ncols = A.ncols;
+  G.rp.assign(G.nrows + 1, 0);
+  val.clear();
+  std::vector<int64_t> k(g);
+  for (int64_t q = 0; q < G.nrows; ++q) {
+    const int64_t row = r0 + q * g;
+    for (int r = 0; r < g; ++r) k[r] = A.rp[row + r];
+    while (true) {  // merge the g sorted column lists
+      int32_t c = INT32_MAX;
+      for (int r = 0; r < g; ++r)
+        if (k[r] < A.rp[row + r + 1]) c = std::min(c, A.ci[k[r]]);
+      if (c == INT32_MAX) break;
+      G.ci.push_back(c);
+      for (int r = 0; r < g; ++r) {
+        if (k[r] < A.rp[row + r + 1] && A.ci[k[r]] == c) val.push_back(A.v[k[r]++]);
+        else val.push_back(0.0);
+      }
+    }
+    G.rp[q + 1] = int64_t(G.ci.size());
+  }
+  return G;
+}
+
 }  // namespace fsi

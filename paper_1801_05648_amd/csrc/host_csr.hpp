@@ -37,6 +37,12 @@ HCsr sub_block(const HCsr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1);
 void drop_zeros(HCsr& A);
 void scale_rows(HCsr& A, const std::vector<double>& s);
 void scale_cols(HCsr& A, const std::vector<double>& s);
+
+// Rows [r0, r1) of A in groups of g consecutive rows sharing one column list
+// (the union of the group's columns): the result has (r1 - r0) / g rows with
+// that list, and val holds, per listed entry, the g values of the group's
+// rows (0 where a row has no entry in that column).
+HCsr group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, std::vector<double>& val);
 std::vector<double> diagonal(const HCsr& A);
 void matvec(const HCsr& A, const double* x, double* y);
 

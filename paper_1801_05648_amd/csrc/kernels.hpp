@@ -139,13 +139,20 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
 }
 
 // Row product over up to four consecutive row segments, each with its own
-// lanes per row (blocks [seg_blk[s], seg_blk[s+1]) serve segment s); for a
-// matrix whose row blocks have very different lengths, e.g. the mesh, solid,
-// fluid-velocity and pressure rows of A_h.  Four loads in flight per lane.
+// lanes per row (blocks [blk0[s], blk0[s+1]) serve segment s); for a matrix
+// whose row blocks have very different lengths, e.g. the mesh, solid,
+// fluid-velocity and pressure rows of A_h.  A segment may store its rows in
+// groups of grp consecutive rows sharing one column list (values of the
+// group's rows side by side): one column index and one gathered x serve grp
+// rows.  Four loads in flight per lane.
 struct RowSegments {
-  int64_t row0[5];    // segment s: rows [row0[s], row0[s+1])
-  unsigned blk0[5];   // segment s: blocks [blk0[s], blk0[s+1])
-  int g[4];           // lanes per row (4, 8, 16 or 32)
+  int64_t row0[5];            // segment s: rows [row0[s], row0[s+1])
+  unsigned blk0[5];           // segment s: blocks [blk0[s], blk0[s+1])
+  int g[4];                   // lanes per row or group (4, 8, 16 or 32)
+  int grp[4];                 // rows per group: 1 (the matrix's own CSR rows), 2 or 3
+  const int64_t* grp_rp[4];   // grouped segments: group pointers (segment-local)
+  const int32_t* grp_ci[4];   //   column list per group entry
+  const void* grp_val[4];     //   grp values per entry (T)
   int nseg;
 };
 
@@ -163,6 +170,64 @@ __device__ __forceinline__ void segment_rows(int64_t r0, int64_t r1, unsigned bl
   if (lane == 0) epi(row, acc, pre);
 }
 
+template <typename T, int G, int GR, class Gather, class Epi>
+__device__ __forceinline__ void segment_groups(int64_t r0, int64_t r1, unsigned blk, const int64_t* __restrict__ rp,
+                                               const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                               const Gather& gx, const Epi& epi) {
+  const int64_t grp = int64_t(blk) * (kBlock / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const int64_t row = r0 + grp * GR;
+  if (row >= r1) return;
+  T acc[GR], pre[GR];
+#pragma unroll
+  for (int r = 0; r < GR; ++r) acc[r] = pre[r] = T(0);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < GR; ++r) epi.load(row + r, pre + r);
+  const int64_t b = rp[grp], e = rp[grp + 1];
+  int64_t k = b + lane;
+  for (; k + 3 * G < e; k += 4 * G) {
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = ci[k + u * G];
+    T a[4][GR];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < GR; ++r) a[u][r] = val[(k + u * G) * GR + r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T xv = gx(c[u], 0);
+#pragma unroll
+      for (int r = 0; r < GR; ++r) acc[r] += a[u][r] * xv;
+    }
+  }
+  for (; k < e; k += G) {
+    const T xv = gx(ci[k], 0);
+#pragma unroll
+    for (int r = 0; r < GR; ++r) acc[r] += val[k * GR + r] * xv;
+  }
+  group_reduce<T, G, GR>(acc);
+  if (lane == 0)
+#pragma unroll
+    for (int r = 0; r < GR; ++r) epi(row + r, acc + r, pre + r);
+}
+
+template <typename T, int G, class Gather, class Epi>
+__device__ __forceinline__ void segment_any(const RowSegments& sg, int s, unsigned blk, const int64_t* rp,
+                                            const int32_t* ci, const T* val, const Gather& gx, const Epi& epi) {
+  const int64_t r0 = sg.row0[s], r1 = sg.row0[s + 1];
+  switch (sg.grp[s]) {
+    case 2:
+      segment_groups<T, G, 2>(r0, r1, blk, sg.grp_rp[s], sg.grp_ci[s], static_cast<const T*>(sg.grp_val[s]), gx, epi);
+      break;
+    case 3:
+      segment_groups<T, G, 3>(r0, r1, blk, sg.grp_rp[s], sg.grp_ci[s], static_cast<const T*>(sg.grp_val[s]), gx, epi);
+      break;
+    default: segment_rows<T, G>(r0, r1, blk, rp, ci, val, gx, epi); break;
+  }
+}
+
 template <typename T, class Gather, class Epi>
 __global__ __launch_bounds__(kBlock) void csr_segments_kernel(RowSegments sg, const int64_t* __restrict__ rp,
                                                                const int32_t* __restrict__ ci,
@@ -170,12 +235,11 @@ __global__ __launch_bounds__(kBlock) void csr_segments_kernel(RowSegments sg, co
   int s = 0;
   while (s + 1 < sg.nseg && blockIdx.x >= sg.blk0[s + 1]) ++s;
   const unsigned blk = blockIdx.x - sg.blk0[s];
-  const int64_t r0 = sg.row0[s], r1 = sg.row0[s + 1];
   switch (sg.g[s]) {
-    case 4: segment_rows<T, 4>(r0, r1, blk, rp, ci, val, gx, epi); break;
-    case 8: segment_rows<T, 8>(r0, r1, blk, rp, ci, val, gx, epi); break;
-    case 16: segment_rows<T, 16>(r0, r1, blk, rp, ci, val, gx, epi); break;
-    default: segment_rows<T, 32>(r0, r1, blk, rp, ci, val, gx, epi); break;
+    case 4: segment_any<T, 4>(sg, s, blk, rp, ci, val, gx, epi); break;
+    case 8: segment_any<T, 8>(sg, s, blk, rp, ci, val, gx, epi); break;
+    case 16: segment_any<T, 16>(sg, s, blk, rp, ci, val, gx, epi); break;
+    default: segment_any<T, 32>(sg, s, blk, rp, ci, val, gx, epi); break;
   }
 }
 

@@ -112,6 +112,7 @@ def _declare(lib):
         "fsi_get_level": ([P, i32, i32, i32, P, P, P, P, P, P], i32),
         "fsi_get_aggregates": ([P, i32, i32, P, P], i32),
         "fsi_vcycle_bytes": ([P, i32, P], i32),
+        "fsi_spmv_bytes": ([P, P], i32),
         "fsi_default_mlp_train_opts": ([ctypes.POINTER(CMlpTrainOpts)], None),
         "fsi_mlp_set_weights": ([P, i32, P, P, P], i32),
         "fsi_mlp_get_weights": ([P, i32, P, P, P], i32),
@@ -148,7 +149,7 @@ def exported_symbols():
     """Names of the C ABI entry points this binding declares."""
     return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_build_precond",
             "fsi_solve", "fsi_spmv", "fsi_apply_precond", "fsi_vcycle", "fsi_set_hierarchy",
-            "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_get_level", "fsi_get_aggregates",
+            "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_spmv_bytes", "fsi_get_level", "fsi_get_aggregates",
             "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
             "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
             "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train"]
@@ -327,6 +328,11 @@ class FsiSolver:
                                                 nnz.ctypes.data, om.ctypes.data))
         k = nl.value
         return n[:k].copy(), nnz[:k].copy(), om[:k].copy()
+
+    def spmv_bytes(self) -> float:
+        b = ctypes.c_double()
+        self._check(self.lib.fsi_spmv_bytes(self.ctx, ctypes.byref(b)))
+        return b.value
 
     def vcycle_bytes(self, which) -> float:
         w = HIERARCHIES[which] if isinstance(which, str) else int(which)

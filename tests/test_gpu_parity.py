@@ -78,6 +78,39 @@ def test_spmv_parity(name):
 
 
 @pytest.mark.parametrize("name", ["c1", "tiny3d"])
+def test_spmv_bytes_counts_the_stored_format(name):
+    """fsi_spmv_bytes against a count made here from the block structure: the
+    fluid-velocity rows in groups of d rows (one column index per distinct
+    column of the group, d values each), all other rows in CSR."""
+    import scipy.sparse as sp
+    from oracle import blocks
+    sysm = system(name)
+    bs = blocks.BlockSystem(sysm)
+    B = bs.B
+    A = sp.bmat([[B["M"], B["C_ms"], None], [B["C_sm"], B["S"], B["C_sf"]],
+                 [B["C_fm"], B["C_fs"], B["F"]]], format="csr")
+    d, N = sysm.dim, sysm.N
+    assert A.nnz == sysm.nnz
+    bounds = [0, sysm.n_m, sysm.n_m + sysm.n_s, sysm.n_m + sysm.n_s + sysm.n_vf, N]
+    expect = 16.0 * N
+    for q in range(4):
+        r0, r1 = bounds[q], bounds[q + 1]
+        if q != 2:
+            expect += 12.0 * (A.indptr[r1] - A.indptr[r0]) + 8.0 * (r1 - r0 + 1)
+            continue
+        ng = (r1 - r0) // d
+        gnz = sum(np.unique(A.indices[A.indptr[r0 + g * d]:A.indptr[r0 + g * d + d]]).size for g in range(ng))
+        expect += gnz * (4.0 + 8.0 * d) + 8.0 * (ng + 1)
+    s = _solver(name)
+    got = s.spmv_bytes()
+    s.close()
+    csr = 12.0 * A.nnz + 8.0 * (N + 1) + 16.0 * N
+    print(f"{name}: {got:.0f} B stored, {csr:.0f} B as CSR")
+    assert got == expect
+    assert got < csr
+
+
+@pytest.mark.parametrize("name", ["c1", "tiny3d"])
 @pytest.mark.parametrize("hname", ["H_M", "H_SIG", "H_MS", "H_A", "H_P"])
 def test_vcycle_parity_on_imported_hierarchy(name, hname):
     from oracle import amg, precond
