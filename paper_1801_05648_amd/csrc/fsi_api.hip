@@ -76,11 +76,14 @@ struct DCsr {
   std::shared_ptr<DevBuf> rp, ci, val;
   std::shared_ptr<DevBuf> grp_rp[4], grp_ci[4], grp_val[4];  // grouped segments
   double seg_bytes = 0.0;  // bytes of one product as stored (segmented matrices)
+  int rgroup = 1;          // > 1: rows stored in groups of rgroup (nnz counts column-list entries)
   const int64_t* drp() const { return rp ? rp->as<int64_t>() : nullptr; }
   const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
   const T* dval() const { return val ? val->as<T>() : nullptr; }
   double bytes() const {
-    return seg.nseg > 0 ? seg_bytes : double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8;
+    if (seg.nseg > 0) return seg_bytes;
+    if (rgroup > 1) return double(nnz) * (4.0 + sizeof(T) * rgroup) + double(nrows / rgroup + 1) * 8;
+    return double(nnz) * (sizeof(T) + 4) + double(nrows + 1) * 8;
   }
 };
 
@@ -133,6 +136,43 @@ std::shared_ptr<DevBuf> upload_raw(const std::vector<U>& v) {
   return b;
 }
 
+// A in groups of g consecutive rows sharing one column list (g values per
+// entry), for the grouped level sweeps; with `as_segment` also described as a
+// one-segment RowSegments, so that launch_rows runs it.
+template <typename T>
+DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
+  std::vector<double> gv;
+  const HCsr G = group_rows(A, 0, A.nrows, g, gv);
+  DCsr<T> D;
+  D.nrows = A.nrows;
+  D.ncols = A.ncols;
+  D.nnz = G.nnz();
+  D.rgroup = g;
+  D.deep = true;
+  D.rp = upload_raw(G.rp);
+  D.ci = upload_raw(G.ci);
+  D.val = upload_raw(std::vector<T>(gv.begin(), gv.end()));
+  if (as_segment) {
+    const int64_t units = G.nrows;
+    const double avg = units ? double(D.nnz) / double(units) : 1.0;
+    int lanes = 4;
+    while (lanes < 32 && lanes * 12 < avg) lanes *= 2;
+    RowSegments& sg = D.seg;
+    sg.nseg = 1;
+    sg.row0[0] = 0;
+    sg.row0[1] = A.nrows;
+    sg.blk0[0] = 0;
+    sg.blk0[1] = unsigned((units + kBlock / lanes - 1) / (kBlock / lanes));
+    sg.g[0] = lanes;
+    sg.grp[0] = g;
+    sg.grp_rp[0] = D.drp();
+    sg.grp_ci[0] = D.dci();
+    sg.grp_val[0] = D.dval();
+    D.seg_bytes = double(D.nnz) * (4.0 + sizeof(T) * g) + double(units + 1) * 8;
+  }
+  return D;
+}
+
 template <typename T>
 std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) {
   auto b = std::make_shared<DevBuf>();
@@ -146,6 +186,13 @@ std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) 
     HIP_TRY(hipStreamSynchronize(s));
   }
   return b;
+}
+
+// Rows per group of a grouped level (the components of a node).
+template <class F>
+void with_rgroup(int g, F&& f) {
+  if (g == 2) f(std::integral_constant<int, 2>{});
+  else f(std::integral_constant<int, 3>{});
 }
 
 inline unsigned grid_for(int64_t n, int per_block) {
@@ -229,6 +276,7 @@ struct DLevel {
   T omega = T(0);
   int64_t n = 0;
   int gdown = 8, gdownq = 64, gup = 8;
+  int rgroup = 1;                      // > 1: AD, Q (or R), P, AP stored in groups of rgroup rows
   bool deep = false;                   // large level: four loads in flight per lane
   bool split = false;                  // restriction by R in its own launch (no Q)
   int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
@@ -276,7 +324,7 @@ constexpr int64_t kSplitNnz = int64_t(1) << 21;
 
 template <typename T>
 DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
-                     int poly = 0, double poly_ratio = 8.0) {
+                     int poly = 0, double poly_ratio = 8.0, int group = 1) {
   DHier<T> D;
   D.nv = nv;
   const int L = int(H.levels.size()) - 1;
@@ -347,15 +395,34 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       HCsr Q = add(h.R, RA, -1.0);
       HCsr AD = h.A;
       scale_cols(AD, h.dinv);
-      d.AD = upload<T>(AD, s);
       // Restricting through Q fuses the restriction into the down-sweep but
       // reads nnz(Q) instead of nnz(R) entries; where the difference costs
       // more than a launch, restrict the residual with R in a launch of its own.
       d.split = !(l == 0 && keep_a0) && Q.nnz() - h.R.nnz() >= kSplitNnz;
-      if (d.split) d.R0 = upload<T>(h.R, s);
-      else d.Q = upload<T>(Q, s);
-      d.P = upload<T>(h.P, s);
-      d.AP = upload<T>(AP, s);
+      // Large levels of a vector problem (group = components per node): where
+      // the rows of a node share their columns in all four matrices (at most
+      // 5% zero fill), store them in groups of `group` rows.  Decided on the
+      // structure alone, so imported hierarchies take the same path.
+      const HCsr& Rq = d.split ? h.R : Q;
+      auto fits = [&](const HCsr& M) {
+        return M.nrows % group == 0 && double(group_entries(M, 0, M.nrows, group)) * group <= 1.05 * double(M.nnz());
+      };
+      if (group > 1 && nv == 1 && !(l == 0 && keep_a0) && AD.nnz() >= kDeepNnz && fits(AD) && fits(Rq) &&
+          fits(h.P) && fits(AP))
+        d.rgroup = group;
+      if (d.rgroup > 1) {
+        d.AD = upload_grouped<T>(AD, group);
+        if (d.split) d.R0 = upload_grouped<T>(h.R, group, true);
+        else d.Q = upload_grouped<T>(Q, group);
+        d.P = upload_grouped<T>(h.P, group);
+        d.AP = upload_grouped<T>(AP, group);
+      } else {
+        d.AD = upload<T>(AD, s);
+        if (d.split) d.R0 = upload<T>(h.R, s);
+        else d.Q = upload<T>(Q, s);
+        d.P = upload<T>(h.P, s);
+        d.AP = upload<T>(AP, s);
+      }
       d.dinv = upload_vec<T>(h.dinv, s);
       if (l == 1 && keep_a0) d.A0 = upload<T>(h.A, s);  // exact coarse solves of the training loss
       if (l == 0 && keep_a0) {
@@ -368,11 +435,12 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       }
       // large levels are bandwidth streams (about ten entries per lane, four
       // loads in flight); small ones latency chains (about three per lane)
-      d.deep = d.AD.nnz >= kDeepNnz;
+      d.deep = AD.nnz() >= kDeepNnz;
       const int per_lane = d.deep ? 10 : 3;
-      d.gdown = pick_group(d.AD.nnz, d.AD.nrows, per_lane);
+      const int64_t units = d.n / d.rgroup;  // rows or row groups
+      d.gdown = pick_group(d.AD.nnz, units, per_lane);
       d.gdownq = d.deep || d.split ? 16 : (pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16);
-      d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1), per_lane);
+      d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(units, 1), per_lane);
       const double vb = double(sizeof(T)) * nv;
       // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
       D.bytes_per_cycle += d.AD.bytes() + (d.split ? d.R0.bytes() + double(d.n) * vb : d.Q.bytes()) + d.P.bytes() +
@@ -531,6 +599,34 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   const T* dinv = d.dinv->template as<T>();
   T* r = d.r->template as<T>();
   T* bc = c.b->template as<T>();
+  if constexpr (NV == 1) {
+    if (d.rgroup > 1) {  // grouped level (never a learned one)
+      with_group(d.gdown, [&](auto gc) {
+        constexpr int GA = decltype(gc)::value;
+        const unsigned na = grid_for(d.n / d.rgroup, kBlock / GA);
+        const unsigned nq = d.split ? 0u : grid_for(d.Q.nrows / d.rgroup, kBlock / 16);
+        with_rgroup(d.rgroup, [&](auto gr) {
+          constexpr int GR = decltype(gr)::value;
+          vdown_grp_kernel<T, GA, 16, GR><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
+                                                                      d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
+                                                                      d.omega, r, bc, na);
+        });
+      });
+      if (d.split) launch_rows<T, 1>(d.R0, GatherPlain<T, 1>{r}, EpiStore<T, 1>{bc}, s);  // b_c = R r
+      T* e = c.y->template as<T>();
+      vcycle_rec<T, NV>(H, l + 1, bc, e, s, plain);
+      with_group(d.gup, [&](auto gc) {
+        constexpr int G = decltype(gc)::value;
+        with_rgroup(d.rgroup, [&](auto gr) {
+          constexpr int GR = decltype(gr)::value;
+          vup_grp_kernel<T, G, GR><<<grid_for(d.n / d.rgroup, kBlock / G), kBlock, 0, s>>>(
+              d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b, dinv, d.omega, r,
+              out);
+        });
+      });
+      return;
+    }
+  }
   with_group(d.gdown, [&](auto gc) {
     constexpr int GA = decltype(gc)::value;
     const unsigned na = grid_for(d.AD.nrows, kBlock / GA);
@@ -810,6 +906,13 @@ std::vector<double> rigid_modes(const fsi_ctx& c, int& k) {
   return B;
 }
 
+// Components per node of the operator of hierarchy h: d for the vector
+// blocks (solid Schur matrix, solid mass block, fluid velocity block), 1 for
+// the scalar mesh Laplacian and the pressure Schur approximation.
+int node_components(const fsi_ctx& c, int h) {
+  return h == FSI_H_SIG || h == FSI_H_MS || h == FSI_H_A ? c.d : 1;
+}
+
 // The learned pre-smoother exists for H_M and H_SIG with Jacobi sweeps and
 // lattice indices of the nodes.
 bool learned_capable(const fsi_ctx& c, int h) {
@@ -837,7 +940,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   P->n_p = c.n_p; P->N = c.N;
   for (int h = 0; h < FSI_NHIER; ++h)
     P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable(c, h), c.cheb[h], c.poly[h],
-                             c.poly_ratio);
+                             c.poly_ratio, node_components(c, h));
   link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.blk[FSI_F];
@@ -2183,9 +2286,11 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
     c.drop_graphs();
     c.m_alloc = -1;
     if (c.precision == FSI_P_F64)
-      c.p64->H[which] = upload_hier<double>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio);
+      c.p64->H[which] = upload_hier<double>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio,
+                                            node_components(c, which));
     else
-      c.p32->H[which] = upload_hier<float>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio);
+      c.p32->H[which] = upload_hier<float>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio,
+                                           node_components(c, which));
     HIP_TRY(hipStreamSynchronize(c.stream));
     c.host_h[which] = std::move(H);
     if (lc) {

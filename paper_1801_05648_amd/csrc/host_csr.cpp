@@ -1,6 +1,7 @@
 #include "host_csr.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdio>
 #include <thread>
@@ -251,6 +252,29 @@ HCsr group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, std::vector<double
     G.rp[q + 1] = int64_t(G.ci.size());
   }
   return G;
+}
+
+int64_t group_entries(const HCsr& A, int64_t r0, int64_t r1, int g) {
+  std::atomic<int64_t> total{0};
+  parallel_for((r1 - r0) / g, [&](int64_t q0, int64_t q1) {
+    int64_t cnt = 0;
+    std::vector<int64_t> k(g);
+    for (int64_t q = q0; q < q1; ++q) {
+      const int64_t row = r0 + q * g;
+      for (int r = 0; r < g; ++r) k[r] = A.rp[row + r];
+      while (true) {
+        int32_t c = INT32_MAX;
+        for (int r = 0; r < g; ++r)
+          if (k[r] < A.rp[row + r + 1]) c = std::min(c, A.ci[k[r]]);
+        if (c == INT32_MAX) break;
+        ++cnt;
+        for (int r = 0; r < g; ++r)
+          if (k[r] < A.rp[row + r + 1] && A.ci[k[r]] == c) ++k[r];
+      }
+    }
+    total += cnt;
+  });
+  return total.load();
 }
 
 }  // namespace fsi

@@ -43,6 +43,11 @@ void scale_cols(HCsr& A, const std::vector<double>& s);
 // that list, and val holds, per listed entry, the g values of the group's
 // rows (0 where a row has no entry in that column).
 HCsr group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, std::vector<double>& val);
+
+// Column-list entries of rows [r0, r1) stored in groups of g rows, i.e. the
+// number of distinct columns of each group summed over the groups (the
+// grouped form holds g times as many values).
+int64_t group_entries(const HCsr& A, int64_t r0, int64_t r1, int g);
 std::vector<double> diagonal(const HCsr& A);
 void matvec(const HCsr& A, const double* x, double* y);
 

@@ -145,6 +145,39 @@ __global__ __launch_bounds__(kBlock) void csr_rows_kernel(int64_t nrows, const i
 // groups of grp consecutive rows sharing one column list (values of the
 // group's rows side by side): one column index and one gathered x serve grp
 // rows.  Four loads in flight per lane.
+// Accumulate the GR rows of row group `grp` of a grouped matrix (one column
+// list per group, the GR rows' values of an entry side by side) into acc[GR]
+// with the G lanes of a group: one column index and one gathered x value
+// serve GR products.  Four entries in flight per lane.
+template <typename T, int G, int GR, class Gather>
+__device__ __forceinline__ void group_accumulate(const int64_t* __restrict__ rp, const int32_t* __restrict__ ci,
+                                                 const T* __restrict__ val, int64_t grp, int lane, const Gather& gx,
+                                                 T* acc) {
+  const int64_t b = rp[grp], e = rp[grp + 1];
+  int64_t k = b + lane;
+  for (; k + 3 * G < e; k += 4 * G) {
+    int32_t c[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c[u] = ci[k + u * G];
+    T a[4][GR];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int r = 0; r < GR; ++r) a[u][r] = val[(k + u * G) * GR + r];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const T xv = gx(c[u], 0);
+#pragma unroll
+      for (int r = 0; r < GR; ++r) acc[r] += a[u][r] * xv;
+    }
+  }
+  for (; k < e; k += G) {
+    const T xv = gx(ci[k], 0);
+#pragma unroll
+    for (int r = 0; r < GR; ++r) acc[r] += val[k * GR + r] * xv;
+  }
+}
+
 struct RowSegments {
   int64_t row0[5];            // segment s: rows [row0[s], row0[s+1])
   unsigned blk0[5];           // segment s: blocks [blk0[s], blk0[s+1])
@@ -184,29 +217,7 @@ __device__ __forceinline__ void segment_groups(int64_t r0, int64_t r1, unsigned 
   if (lane == 0)
 #pragma unroll
     for (int r = 0; r < GR; ++r) epi.load(row + r, pre + r);
-  const int64_t b = rp[grp], e = rp[grp + 1];
-  int64_t k = b + lane;
-  for (; k + 3 * G < e; k += 4 * G) {
-    int32_t c[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) c[u] = ci[k + u * G];
-    T a[4][GR];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int r = 0; r < GR; ++r) a[u][r] = val[(k + u * G) * GR + r];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const T xv = gx(c[u], 0);
-#pragma unroll
-      for (int r = 0; r < GR; ++r) acc[r] += a[u][r] * xv;
-    }
-  }
-  for (; k < e; k += G) {
-    const T xv = gx(ci[k], 0);
-#pragma unroll
-    for (int r = 0; r < GR; ++r) acc[r] += val[k * GR + r] * xv;
-  }
+  group_accumulate<T, G, GR>(rp, ci, val, grp, lane, gx, acc);
   group_reduce<T, G, GR>(acc);
   if (lane == 0)
 #pragma unroll
@@ -317,6 +328,74 @@ __global__ __launch_bounds__(kBlock) void vup_kernel(
   if (lane == 0)
 #pragma unroll
     for (int q = 0; q < NV; ++q) y[row * NV + q] = wd * bi[q] + pe[q] + wd * (ri[q] - ap[q]);
+}
+
+// The two level sweeps above for matrices stored in groups of GR rows (the
+// GR components of a node; fine and coarse levels with the same block size):
+// A D^{-1}, Q, P and A P each read one column index per GR values.
+template <typename T, int GA, int GQ, int GR>
+__global__ __launch_bounds__(kBlock) void vdown_grp_kernel(
+    int64_t na, const int64_t* __restrict__ rpa, const int32_t* __restrict__ cia, const T* __restrict__ va,
+    int64_t nq, const int64_t* __restrict__ rpq, const int32_t* __restrict__ ciq, const T* __restrict__ vq,
+    const T* __restrict__ b, T omega, T* __restrict__ r, T* __restrict__ bc, unsigned nblk_a) {
+  T acc[GR];
+#pragma unroll
+  for (int q = 0; q < GR; ++q) acc[q] = T(0);
+  const unsigned blk = blockIdx.x;
+  const GatherPlain<T, 1> gb{b};
+  if (blk < nblk_a) {
+    const int64_t grp = int64_t(blk) * (kBlock / GA) + threadIdx.x / GA;
+    const int lane = threadIdx.x % GA;
+    const int64_t row = grp * GR;
+    if (row >= na) return;
+    T bi[GR];
+#pragma unroll
+    for (int q = 0; q < GR; ++q) bi[q] = lane == 0 ? b[row + q] : T(0);
+    group_accumulate<T, GA, GR>(rpa, cia, va, grp, lane, gb, acc);
+    group_reduce<T, GA, GR>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < GR; ++q) r[row + q] = bi[q] - omega * acc[q];
+  } else {
+    const int64_t grp = int64_t(blk - nblk_a) * (kBlock / GQ) + threadIdx.x / GQ;
+    const int lane = threadIdx.x % GQ;
+    const int64_t row = grp * GR;
+    if (row >= nq) return;
+    group_accumulate<T, GQ, GR>(rpq, ciq, vq, grp, lane, gb, acc);
+    group_reduce<T, GQ, GR>(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int q = 0; q < GR; ++q) bc[row + q] = acc[q];
+  }
+}
+
+template <typename T, int G, int GR>
+__global__ __launch_bounds__(kBlock) void vup_grp_kernel(
+    int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
+    const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
+    const T* __restrict__ e, const T* b, const T* __restrict__ dinv, T omega, const T* __restrict__ r, T* y) {
+  const int64_t grp = int64_t(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
+  const int lane = threadIdx.x % G;
+  const int64_t row = grp * GR;
+  if (row >= n) return;
+  T ap[GR], pe[GR], bi[GR], ri[GR], wd[GR];
+#pragma unroll
+  for (int q = 0; q < GR; ++q) ap[q] = pe[q] = bi[q] = ri[q] = wd[q] = T(0);
+  if (lane == 0)  // the rows' own values, loaded ahead of the products
+#pragma unroll
+    for (int q = 0; q < GR; ++q) {
+      wd[q] = omega * dinv[row + q];
+      bi[q] = b[row + q];
+      ri[q] = r[row + q];
+    }
+  const GatherPlain<T, 1> ge{e};
+  group_accumulate<T, G, GR>(rpp, cip, vp, grp, lane, ge, pe);
+  group_accumulate<T, G, GR>(rpap, ciap, vap, grp, lane, ge, ap);
+  group_reduce<T, G, GR>(pe);
+  group_reduce<T, G, GR>(ap);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < GR; ++q) y[row + q] = wd[q] * bi[q] + pe[q] + wd[q] * (ri[q] - ap[q]);
 }
 
 // Residual of the learned pre-smoother's correction and the partials of its

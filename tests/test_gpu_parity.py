@@ -291,6 +291,71 @@ def test_vcycle_parity_3d_with_large_levels(hname):
     s.close()
 
 
+def _cycle_bytes(h, g, allow_groups=True):
+    """Bytes of one Jacobi V(1,1) cycle of the FP64 library as executed, with
+    the levels of at least 2^21 entries whose A D^{-1}, Q (or R), P and A P
+    take at most 5% zero fill in groups of g rows stored grouped, the others
+    as CSR; Q's structure is that of R + R A."""
+    import scipy.sparse as sp
+
+    def entries(M, rows_per):
+        M = M.tocsr()
+        M.sort_indices()
+        return sum(np.unique(M.indices[M.indptr[q * rows_per]:M.indptr[q * rows_per + rows_per]]).size
+                   for q in range(M.shape[0] // rows_per))
+
+    total = 0.0
+    for lev in h.levels[:-1]:
+        A, P, R = lev.A.tocsr(), lev.P.tocsr(), lev.R.tocsr()
+        n, nc = A.shape[0], P.shape[1]
+        absA, absR = abs(A), abs(R)
+        Q = (absR + absR @ absA).tocsr()
+        AP = (absA @ abs(P)).tocsr()
+        split = Q.nnz - R.nnz >= 2 ** 21
+        Rq = R if split else Q
+        mats = [A, Rq, P, AP]
+        grouped = allow_groups and A.nnz >= 2 ** 21 and all(M.shape[0] % g == 0 for M in mats)
+        if grouped:
+            ents = [entries(M, g) for M in mats]
+            grouped = all(e * g <= 1.05 * M.nnz for e, M in zip(ents, mats))
+        for k, M in enumerate(mats):
+            if grouped:
+                total += ents[k] * (4.0 + 8.0 * g) + 8.0 * (M.shape[0] // g + 1)
+            else:
+                total += 12.0 * M.nnz + 8.0 * (M.shape[0] + 1)
+        total += (8.0 * n if split else 0.0) + n * (2 * 8 + 5 * 8) + nc * 2 * 8
+    nL = h.levels[-1].A.shape[0]
+    return total + 8.0 * nL * nL
+
+
+@pytest.mark.parametrize("name", ["c2", "m3"])
+def test_grouped_levels_match_oracle(name):
+    """H_A's large levels stored in groups of d rows (the velocity components
+    of a node share their columns): on the oracle's imported hierarchy the
+    V-cycle matches the oracle, and the bytes the library reports for the
+    cycle are the grouped layout's (so the grouped kernels did run)."""
+    from oracle import amg, blocks, precond
+    from paper_1801_05648_amd import FsiSolver
+    sysm = system(name)
+    bs = blocks.BlockSystem(sysm)
+    H = precond.build_hierarchies(bs, max_coarse=2000)
+    h = H["H_A"]
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f64", max_coarse=2000)
+    _import_oracle_hierarchies(s, {"H_A": h})
+    b = np.random.default_rng(13).standard_normal(h.levels[0].A.shape[0])
+    x = s.vcycle("H_A", _dev(b)).cpu().numpy()
+    ref = amg.vcycle(h, b)
+    got = s.vcycle_bytes("H_A")
+    s.close()
+    assert _rel(x, ref) <= 1e-12, _rel(x, ref)
+    expect = _cycle_bytes(h, sysm.dim)
+    plain = _cycle_bytes(h, sysm.dim, allow_groups=False)
+    print(f"{name}: cycle bytes {got:.0f}, grouped layout {expect:.0f}, all CSR {plain:.0f}")
+    assert abs(got - expect) <= 2e-3 * expect
+    assert plain - expect >= 5e-2 * expect  # the two layouts are told apart
+
+
 BENCH_OPTS = dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3)
 
 
