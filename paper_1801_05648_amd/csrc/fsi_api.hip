@@ -173,6 +173,56 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
   return D;
 }
 
+// A as up to four consecutive row segments [bounds[q], bounds[q+1]) that
+// start at row 0, each with its own lanes per row or row group (about twelve
+// entries per lane, 4 to 32 lanes; measured best for long rows); segment q is
+// stored in groups of group[q] rows where that costs at most 5% zero fill.
+// bytes(): the matrix as stored plus vec_bytes (the vectors of one product).
+template <typename T>
+DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, double vec_bytes,
+                        hipStream_t s) {
+  DCsr<T> D = upload<T>(A, s);
+  D.deep = true;
+  RowSegments sg{};
+  sg.nseg = 0;
+  sg.blk0[0] = 0;
+  sg.row0[0] = bounds[0];
+  double bytes = vec_bytes;
+  for (int q = 0; q < nseg; ++q) {
+    const int64_t r0 = bounds[q], r1 = bounds[q + 1];
+    if (r1 <= r0) continue;
+    const int k = sg.nseg++;
+    int64_t units = r1 - r0, nz = A.rp[r1] - A.rp[r0];
+    int gr = group[q];
+    if (gr > 1 && (units % gr != 0 || double(group_entries(A, r0, r1, gr)) * gr > 1.05 * double(nz))) gr = 1;
+    if (gr > 1) {
+      std::vector<double> gv;
+      const HCsr Gm = group_rows(A, r0, r1, gr, gv);
+      units = Gm.nrows;
+      nz = Gm.nnz();
+      D.grp_rp[k] = upload_raw(Gm.rp);
+      D.grp_ci[k] = upload_raw(Gm.ci);
+      D.grp_val[k] = upload_raw(std::vector<T>(gv.begin(), gv.end()));
+      sg.grp_rp[k] = D.grp_rp[k]->template as<int64_t>();
+      sg.grp_ci[k] = D.grp_ci[k]->template as<int32_t>();
+      sg.grp_val[k] = D.grp_val[k]->template as<T>();
+      bytes += double(nz) * (4.0 + sizeof(T) * gr) + 8.0 * double(units + 1);
+    } else {
+      bytes += double(nz) * (4.0 + sizeof(T)) + 8.0 * double(units + 1);
+    }
+    sg.grp[k] = gr;
+    const double avg = double(nz) / double(units);
+    int g = 4;
+    while (g < 32 && g * 12 < avg) g *= 2;
+    sg.g[k] = g;
+    sg.row0[k + 1] = r1;
+    sg.blk0[k + 1] = sg.blk0[k] + unsigned((units + kBlock / g - 1) / (kBlock / g));
+  }
+  D.seg = sg;
+  D.seg_bytes = bytes;
+  return D;
+}
+
 template <typename T>
 std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) {
   auto b = std::make_shared<DevBuf>();
@@ -966,7 +1016,11 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
       }
       M.rp[i + 1] = int64_t(M.ci.size());
     }
-    P->Cfms = upload<T>(M, s);
+    // velocity rows in groups of d (a node's rows share their columns), then
+    // the pressure rows
+    const int64_t bounds[3] = {0, c.n_vf, c.n_f};
+    const int groups[2] = {c.d, 1};
+    P->Cfms = upload_segments<T>(M, bounds, groups, 2, double(sizeof(T)) * double(M.ncols + 2 * c.n_f), s);
   }
   P->alloc_tmp();
   HIP_TRY(hipStreamSynchronize(s));
@@ -2014,53 +2068,13 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
         }
       }
     }
-    DCsr<double> dAh = upload<double>(Ah, ctx->stream);
-    dAh.group = pick_group(dAh.nnz, dAh.nrows, 8);
-    dAh.deep = true;
-    {
-      // mesh, solid, fluid-velocity and pressure rows: about twelve entries
-      // per lane each (measured best for the long rows; at least 4 lanes).
-      // The d velocity rows of a fluid node share their columns (the stress
-      // couples the components; no fill measured): they are stored as groups
-      // of d rows, one column index per d values.
-      const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
-      RowSegments sg{};
-      sg.nseg = 0;
-      sg.blk0[0] = 0;
-      sg.row0[0] = 0;
-      double bytes = 8.0 * double(N);  // y written
-      for (int q = 0; q < 4; ++q) {
-        const int64_t r0 = bounds[q], r1 = bounds[q + 1];
-        if (r1 <= r0) continue;
-        const int k = sg.nseg++;
-        const int gr = q == 2 ? d : 1;
-        int64_t units = r1 - r0, nz = Ah.rp[r1] - Ah.rp[r0];
-        if (gr > 1) {
-          std::vector<double> gv;
-          HCsr Gm = group_rows(Ah, r0, r1, gr, gv);
-          units = Gm.nrows;
-          nz = Gm.nnz();
-          dAh.grp_rp[k] = upload_raw(Gm.rp);
-          dAh.grp_ci[k] = upload_raw(Gm.ci);
-          dAh.grp_val[k] = upload_raw(gv);
-          sg.grp_rp[k] = dAh.grp_rp[k]->as<int64_t>();
-          sg.grp_ci[k] = dAh.grp_ci[k]->as<int32_t>();
-          sg.grp_val[k] = dAh.grp_val[k]->as<double>();
-          bytes += double(nz) * (4.0 + 8.0 * gr) + 8.0 * double(units + 1);
-        } else {
-          bytes += double(nz) * 12.0 + 8.0 * double(units + 1);
-        }
-        sg.grp[k] = gr;
-        const double avg = double(nz) / double(units);
-        int g = 4;
-        while (g < 32 && g * 12 < avg) g *= 2;
-        sg.g[k] = g;
-        sg.row0[k + 1] = r1;
-        sg.blk0[k + 1] = sg.blk0[k] + unsigned((units + kBlock / g - 1) / (kBlock / g));
-      }
-      dAh.seg = sg;
-      dAh.seg_bytes = bytes + 8.0 * double(N);  // x read once
-    }
+    // mesh, solid, fluid-velocity and pressure rows as four segments; the d
+    // velocity rows of a fluid node share their columns (the stress couples
+    // the components): stored as groups of d rows, one column index per d
+    // values.  Solid rows differ in about half their columns: plain rows.
+    const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
+    const int groups[4] = {1, 1, d, 1};
+    DCsr<double> dAh = upload_segments<double>(Ah, bounds, groups, 4, 16.0 * double(N), ctx->stream);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     // commit
     fsi_ctx& c = *ctx;
