@@ -29,6 +29,7 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel and workload it was measured on (empty: the
 # kernel changed since the counters were taken).
 MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563}
+DTYPE = {"f64": "f64", "f32": "f64-krylov/f32-precond", "f32-bf16diag": "f64-krylov/f32-precond/bf16-diag"}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
 
@@ -196,7 +197,7 @@ def learned_run(args, cfg):
         "metric": "FGMRES time-to-solution per Newton solve @1e-8 resid, learned vs plain V-cycle smoothing",
         "value": round(lm, 3), "unit": "ms", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(lm, 3), "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "f64-krylov/f32-precond",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {"workload": f"pseudo-time FSI Jacobians {'x'.join(map(str, cfg.cells))} cells",
                    "name": cfg.name, "seed": args.seed, "train_systems": len(train),
@@ -219,7 +220,7 @@ def main():
     ap.add_argument("--seed", type=int, default=0, help="seed of the learned-smoother workload")
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2],
                     help="seeds of the linearisation state; the timed solves cycle through them")
-    ap.add_argument("--precision", default="f64", choices=["f64", "f32"])
+    ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f32-bf16diag"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cheb", type=int, default=None,
                     help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
@@ -388,7 +389,7 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "f64" else "f64-krylov/f32-precond",
+        "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {
             "workload": (f"2D FSI Jacobian {cfg.cells[0]}x{cfg.cells[1]} Q2/Q1 cells" if cfg.dim == 2 else

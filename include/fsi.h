@@ -94,12 +94,19 @@ typedef struct {
                                 smoother's 3^d stencils); may be NULL            */
 } fsi_layout;
 
-enum { FSI_P_F64 = 0, FSI_P_F32 = 1 };
+enum { FSI_P_F64 = 0, FSI_P_F32 = 1, FSI_P_F32_BF16DIAG = 2 };
 
 typedef struct {
   int32_t precision;   /* FSI_P_F64 (default) or FSI_P_F32: precision of the
                           preconditioner's V-cycles and coupling products; the
-                          Krylov loop, A_h products and coarsest solves stay FP64 */
+                          Krylov loop, A_h products and coarsest solves stay FP64.
+                          FSI_P_F32_BF16DIAG: FSI_P_F32 with the smoothers'
+                          inverse diagonals D^{-1} stored in BF16 (rounded to
+                          nearest even through FP32; the setup products A D^{-1}
+                          and R (I - omega A D^{-1}) use the same rounded values,
+                          so each sweep is the Jacobi or Chebyshev sweep of the
+                          hierarchy with that diagonal).  The learned smoother
+                          is not available with it.                              */
   int32_t max_coarse;  /* AMG: coarsest level size bound (default 500)          */
   int32_t max_levels;  /* AMG: level bound (default 10)                         */
   int32_t cheb_degree; /* 0 (default): one damped-Jacobi sweep before and after

@@ -323,6 +323,7 @@ struct DLevel {
   DCsr<T> AD, Q, P, AP;  // A D^{-1}, Q = R (I - omega A D^{-1}), prolongator, A P
   DCsr<T> A0, R0;        // A and R themselves: learned smoother (A: levels 0, 1; R: level 0) or Chebyshev levels
   std::shared_ptr<DevBuf> dinv, y, r, b;
+  std::shared_ptr<DevBuf> dinv_h;  // BF16-stored inverse diagonal (in place of dinv)
   T omega = T(0);
   int64_t n = 0;
   int gdown = 8, gdownq = 64, gup = 8;
@@ -332,6 +333,9 @@ struct DLevel {
   int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
   std::vector<T> ca, cc;               // recurrence coefficients a_j, c_j, j = 1..cheb
   std::shared_ptr<DevBuf> d0, d1, r1;  // Chebyshev directions and second residual buffer
+  Diag<T> diag() const {
+    return Diag<T>{dinv ? dinv->template as<T>() : nullptr, dinv_h ? dinv_h->template as<uint16_t>() : nullptr};
+  }
 };
 
 template <typename T>
@@ -346,6 +350,20 @@ struct DHier {
   MlpRecord* rec = nullptr;      // recording of level-0 inputs (if any)
   std::shared_ptr<DevBuf> xm, rm;  // its correction and residual
 };
+
+// BF16 bit pattern of f, rounded to nearest even (f finite), and its value.
+inline uint16_t bf16_bits(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return uint16_t(u >> 16);
+}
+inline double bf16_round(float f) {
+  const uint32_t u = uint32_t(bf16_bits(f)) << 16;
+  float r;
+  std::memcpy(&r, &u, 4);
+  return double(r);
+}
 
 // Chebyshev recurrence of degree k for D^{-1} A on [lam/30, lam], lam = 1.1 rho
 // (rho = (4/3)/omega, the setup's power estimate): a_1 = 0, c_1 = 1/theta,
@@ -374,9 +392,29 @@ constexpr int64_t kSplitNnz = int64_t(1) << 21;
 
 template <typename T>
 DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
-                     int poly = 0, double poly_ratio = 8.0, int group = 1) {
+                     int poly = 0, double poly_ratio = 8.0, int group = 1, bool bf16diag = false) {
   DHier<T> D;
   D.nv = nv;
+  // BF16-stored inverse diagonals: every use of D^{-1} (the sweeps and the
+  // setup products A D^{-1}, Q) takes the values rounded to BF16 (through
+  // FP32, nearest even), so the smoother is the same Jacobi/Chebyshev
+  // smoother with a perturbed diagonal
+  const double db = bf16diag ? 2.0 : double(sizeof(T));  // bytes per diagonal entry
+  auto level_dinv = [&](const std::vector<double>& dv) {
+    if (!bf16diag) return dv;
+    std::vector<double> r(dv.size());
+    for (size_t i = 0; i < dv.size(); ++i) r[i] = bf16_round(float(dv[i]));
+    return r;
+  };
+  auto put_dinv = [&](DLevel<T>& d, const std::vector<double>& dv) {
+    if (!bf16diag) {
+      d.dinv = upload_vec<T>(dv, s);
+      return;
+    }
+    std::vector<uint16_t> bits(dv.size());
+    for (size_t i = 0; i < dv.size(); ++i) bits[i] = bf16_bits(float(dv[i]));
+    d.dinv_h = upload_raw(bits);
+  };
   const int L = int(H.levels.size()) - 1;
   if (poly > 0 && L > 0) {
     // Chebyshev steps alone on the finest matrix: the other levels are not used
@@ -388,7 +426,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
     d.cheb = poly;
     cheb_coefficients<T>(h.omega, poly, d.ca, d.cc, poly_ratio);
     d.A0 = upload<T>(h.A, s);
-    d.dinv = upload_vec<T>(h.dinv, s);
+    put_dinv(d, level_dinv(h.dinv));
     auto mkv = [&]() {
       auto b = std::make_shared<DevBuf>();
       b->alloc(sizeof(T) * std::max<int64_t>(d.n * nv, 1));
@@ -400,7 +438,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
     d.r = mkv();
     d.y = mkv();
     d.b = mkv();
-    D.bytes_per_cycle = (d.A0.bytes() + double(d.n) * (6.0 * sizeof(T) * nv + sizeof(T))) * (poly - 1);
+    D.bytes_per_cycle = (d.A0.bytes() + double(d.n) * (6.0 * sizeof(T) * nv + db)) * (poly - 1);
     D.lev.push_back(std::move(d));
     D.poly = true;
     D.nc = 0;
@@ -420,7 +458,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       d.R0 = upload<T>(h.R, s);
       d.P = upload<T>(h.P, s);
       d.AP = upload<T>(AP, s);
-      d.dinv = upload_vec<T>(h.dinv, s);
+      put_dinv(d, level_dinv(h.dinv));
       d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(d.AP.nrows, 1));
       auto mkv = [&]() {
         auto b = std::make_shared<DevBuf>();
@@ -434,17 +472,18 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       // pre: cheb steps over A + R; post: P, AP, cheb - 1 steps over A; per step
       // d, r, dinv gathered and d, r, x written at the row
       D.bytes_per_cycle += d.A0.bytes() * (2 * cheb - 1) + d.R0.bytes() + d.P.bytes() + d.AP.bytes() +
-                           double(d.n) * (6.0 * cheb * vb + 2 * sizeof(T)) + double(h.P.ncols) * 2 * vb;
+                           double(d.n) * (6.0 * cheb * vb + 2 * db) + double(h.P.ncols) * 2 * vb;
     } else if (l < L) {
       // setup-time products for the two-launch level sweeps
       HCsr AP = spgemm(h.A, h.P);
       HCsr RA = spgemm(h.R, h.A);
-      std::vector<double> wd(h.dinv.size());
-      for (size_t i = 0; i < wd.size(); ++i) wd[i] = h.omega * h.dinv[i];
+      const std::vector<double> dv = level_dinv(h.dinv);
+      std::vector<double> wd(dv.size());
+      for (size_t i = 0; i < wd.size(); ++i) wd[i] = h.omega * dv[i];
       scale_cols(RA, wd);
       HCsr Q = add(h.R, RA, -1.0);
       HCsr AD = h.A;
-      scale_cols(AD, h.dinv);
+      scale_cols(AD, dv);
       // Restricting through Q fuses the restriction into the down-sweep but
       // reads nnz(Q) instead of nnz(R) entries; where the difference costs
       // more than a launch, restrict the residual with R in a launch of its own.
@@ -473,7 +512,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
         d.P = upload<T>(h.P, s);
         d.AP = upload<T>(AP, s);
       }
-      d.dinv = upload_vec<T>(h.dinv, s);
+      put_dinv(d, dv);
       if (l == 1 && keep_a0) d.A0 = upload<T>(h.A, s);  // exact coarse solves of the training loss
       if (l == 0 && keep_a0) {
         d.A0 = upload<T>(h.A, s);
@@ -494,7 +533,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       const double vb = double(sizeof(T)) * nv;
       // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
       D.bytes_per_cycle += d.AD.bytes() + (d.split ? d.R0.bytes() + double(d.n) * vb : d.Q.bytes()) + d.P.bytes() +
-                           d.AP.bytes() + double(d.n) * (2 * sizeof(T) + 5 * vb) + double(h.P.ncols) * 2 * vb;
+                           d.AP.bytes() + double(d.n) * (2 * db + 5 * vb) + double(h.P.ncols) * 2 * vb;
     }
     auto mk = [&](int64_t cnt) {
       auto b = std::make_shared<DevBuf>();
@@ -551,7 +590,7 @@ void cheb_level(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   DLevel<T>& c = H.lev[l + 1];
   if (out == b) throw Error(FSI_ERR_ARG, "a Chebyshev V-cycle cannot run in place");
   const int k = d.cheb;
-  const T* dinv = d.dinv->template as<T>();
+  const Diag<T> dinv = d.diag();
   T* rb[2] = {d.r->template as<T>(), d.r1->template as<T>()};
   T* db[2] = {d.d0->template as<T>(), d.d1->template as<T>()};
   const DCsr<T>& A = d.A0;
@@ -602,7 +641,7 @@ void cheb_only(DHier<T>& H, const T* b, T* out, hipStream_t s) {
   DLevel<T>& d = H.lev[0];
   if (out == b) throw Error(FSI_ERR_ARG, "a Chebyshev inverse cannot run in place");
   const int k = d.cheb;
-  const T* dinv = d.dinv->template as<T>();
+  const Diag<T> dinv = d.diag();
   T* rb[2] = {d.r->template as<T>(), d.r1->template as<T>()};
   T* db[2] = {d.d0->template as<T>(), d.d1->template as<T>()};
   const DCsr<T>& A = d.A0;
@@ -646,7 +685,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   }
   const bool learned = l == 0 && !plain && H.mlp && H.mlp->enabled && H.xm;
   if (learned) mlp_presmooth<T, NV>(H, b, s);
-  const T* dinv = d.dinv->template as<T>();
+  const Diag<T> dinv = d.diag();
   T* r = d.r->template as<T>();
   T* bc = c.b->template as<T>();
   if constexpr (NV == 1) {
@@ -966,7 +1005,8 @@ int node_components(const fsi_ctx& c, int h) {
 // The learned pre-smoother exists for H_M and H_SIG with Jacobi sweeps and
 // lattice indices of the nodes.
 bool learned_capable(const fsi_ctx& c, int h) {
-  return !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG) && c.cheb[h] == 0 && c.poly[h] == 0;
+  return !c.node_ijk.empty() && (h == FSI_H_M || h == FSI_H_SIG) && c.cheb[h] == 0 && c.poly[h] == 0 &&
+         c.precision != FSI_P_F32_BF16DIAG;
 }
 
 // Point the finest levels of H_M and H_SIG at their learned smoothers (or at
@@ -990,7 +1030,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   P->n_p = c.n_p; P->N = c.N;
   for (int h = 0; h < FSI_NHIER; ++h)
     P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable(c, h), c.cheb[h], c.poly[h],
-                             c.poly_ratio, node_components(c, h));
+                             c.poly_ratio, node_components(c, h), c.precision == FSI_P_F32_BF16DIAG);
   link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.blk[FSI_F];
@@ -1447,7 +1487,9 @@ MlpState& mlp_state(fsi_ctx& c, int which) {
   if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
   MlpState& M = c.mlp[which == FSI_H_M ? 0 : 1];
   if (M.n_nodes == 0)
-    throw Error(FSI_ERR_STATE, "no learned smoother here: needs layout.node_ijk and at least two AMG levels");
+    throw Error(FSI_ERR_STATE,
+                "no learned smoother here: needs layout.node_ijk, Jacobi sweeps, at least two AMG levels and FP64 or "
+                "FP32 diagonals");
   return M;
 }
 
@@ -2106,7 +2148,8 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     fsi_precond_opts o;
     fsi_default_precond_opts(&o);
     if (opts) o = *opts;
-    if (o.precision != FSI_P_F64 && o.precision != FSI_P_F32) throw Error(FSI_ERR_ARG, "unknown precision");
+    if (o.precision != FSI_P_F64 && o.precision != FSI_P_F32 && o.precision != FSI_P_F32_BF16DIAG)
+      throw Error(FSI_ERR_ARG, "unknown precision");
     if (o.max_coarse < 1 || o.max_levels < 1 || o.max_levels > 16 || !(o.strength0 >= 0.0))
       throw Error(FSI_ERR_ARG, "bad AMG options");
     if (o.cheb_degree < 0 || o.cheb_degree > 8 || (o.cheb_mask & ~0x1f) != 0)
@@ -2180,8 +2223,8 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       c.cheb[h] = (c.poly[h] == 0 && o.cheb_degree > 0 && (o.cheb_mask >> h) & 1) ? o.cheb_degree : 0;
     }
     c.poly_ratio = o.poly_ratio;
+    c.precision = o.precision;  // before prepare_mlp: it decides which hierarchies can learn
     prepare_mlp(c);
-    c.precision = o.precision;
     c.drop_graphs();
     c.m_alloc = -1;
     c.p64.reset();
@@ -2304,7 +2347,7 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
                                             node_components(c, which));
     else
       c.p32->H[which] = upload_hier<float>(H, nv, c.stream, lc, c.cheb[which], c.poly[which], c.poly_ratio,
-                                           node_components(c, which));
+                                           node_components(c, which), c.precision == FSI_P_F32_BF16DIAG);
     HIP_TRY(hipStreamSynchronize(c.stream));
     c.host_h[which] = std::move(H);
     if (lc) {

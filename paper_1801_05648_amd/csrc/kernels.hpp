@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 namespace fsi {
 
@@ -70,6 +71,20 @@ struct EpiAcc {  // y += A x
   __device__ __forceinline__ void operator()(int64_t i, const T* acc, const T* pre) const {
 #pragma unroll
     for (int n = 0; n < NV; ++n) y[i * NV + n] = pre[n] + acc[n];
+  }
+};
+
+// Inverse diagonal of a level as the smoothers read it: T values, or, for
+// FP32 levels with BF16-stored diagonals, BF16 values widened on load.
+template <typename T>
+struct Diag {
+  const T* v = nullptr;
+  const uint16_t* h = nullptr;  // BF16 bit patterns (FP32 levels only) when not null
+  __device__ __forceinline__ T operator[](int64_t i) const {
+    if constexpr (std::is_same<T, float>::value) {
+      if (h) return __uint_as_float(uint32_t(h[i]) << 16);
+    }
+    return v[i];
   }
 };
 
@@ -303,7 +318,7 @@ template <typename T, int G, int NV, bool DEEP = false>
 __global__ __launch_bounds__(kBlock) void vup_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
-    const T* __restrict__ e, const T* b, const T* __restrict__ dinv, T omega, const T* __restrict__ r, T* y) {
+    const T* __restrict__ e, const T* b, Diag<T> dinv, T omega, const T* __restrict__ r, T* y) {
   constexpr int RPB = kBlock / G;
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
@@ -373,7 +388,7 @@ template <typename T, int G, int GR>
 __global__ __launch_bounds__(kBlock) void vup_grp_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
-    const T* __restrict__ e, const T* b, const T* __restrict__ dinv, T omega, const T* __restrict__ r, T* y) {
+    const T* __restrict__ e, const T* b, Diag<T> dinv, T omega, const T* __restrict__ r, T* y) {
   const int64_t grp = int64_t(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   const int64_t row = grp * GR;
@@ -532,7 +547,7 @@ template <typename T, int G, int NV>
 __global__ __launch_bounds__(kBlock) void vup_sel_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
-    const T* __restrict__ e, const T* b, const T* __restrict__ dinv, T omega, const T* __restrict__ r,
+    const T* __restrict__ e, const T* b, Diag<T> dinv, T omega, const T* __restrict__ r,
     const T* __restrict__ x_m, const T* __restrict__ r_m, const int* __restrict__ flag, T* y) {
   constexpr int RPB = kBlock / G;
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
@@ -573,7 +588,7 @@ template <typename T, int NV>
 struct ChebGather {
   const T* d;     // d_{j-1} (unused when a == 0)
   const T* r;     // r_{j-1}
-  const T* dinv;  // per row (shared by the NV interleaved columns)
+  Diag<T> dinv;  // per row (shared by the NV interleaved columns)
   T a, c;
   __device__ __forceinline__ T operator()(int32_t col, int n) const {
     const T v = c * dinv[col] * r[int64_t(col) * NV + n];
@@ -634,7 +649,7 @@ template <typename T, int G, int NV>
 __global__ __launch_bounds__(kBlock) void cheb_prolong_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
-    const T* __restrict__ e, const T* __restrict__ dinv, T* x, T* r, int fuse, T c1) {
+    const T* __restrict__ e, Diag<T> dinv, T* x, T* r, int fuse, T c1) {
   constexpr int RPB = kBlock / G;
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;

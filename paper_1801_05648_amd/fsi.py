@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libfsi.so")
 
 BLOCKS = ("M", "C_ms", "C_sm", "S", "C_sf", "C_fm", "C_fs", "F")
 HIERARCHIES = {"H_M": 0, "H_SIG": 1, "H_MS": 2, "H_A": 3, "H_P": 4}
-PRECISION = {"f64": 0, "f32": 1}
+PRECISION = {"f64": 0, "f32": 1, "f32-bf16diag": 2}
 
 STATUS = {0: "FSI_OK", 1: "FSI_NOT_CONVERGED", -1: "FSI_ERR_ARG", -2: "FSI_ERR_CSR",
           -3: "FSI_ERR_STRUCT", -4: "FSI_ERR_HIP", -5: "FSI_ERR_OOM", -6: "FSI_ERR_NUMERIC",

@@ -1,7 +1,8 @@
 """Mixed precision: FP32 preconditioner (V-cycles, coupling products) inside
 the FP64 FGMRES loop (Arnoldi, Givens, A_h products, true residual and the
-coarsest solves stay FP64).  The error against the FP64 oracle is stated for
-every result."""
+coarsest solves stay FP64), optionally with the smoothers' inverse diagonals
+stored in BF16.  The error against the FP64 oracle is stated for every
+result."""
 import numpy as np
 import pytest
 
@@ -93,21 +94,22 @@ def test_fp32_preconditioner_in_the_benchmark_configuration(name):
     bs = blocks.BlockSystem(sysm)
     b = _dev(sysm.b)
     res = {}
-    for prec in ("f64", "f32"):
+    for prec in ("f64", "f32", "f32-bf16diag"):
         s = FsiSolver.from_system(sysm, device=0)
         s.build_precond(prec, **BENCH_PRECOND)
         x, info = s.solve(b)
         s.close()
         assert info.converged
         res[prec] = (x.cpu().numpy(), info)
-    xr = res["f32"][0]
-    r = np.linalg.norm(sysm.b - bs.matvec(xr)) / np.linalg.norm(sysm.b)
-    err = _rel(xr, res["f64"][0])
-    print(f"{name}: f64 {res['f64'][1].iters} it {res['f64'][1].t_total_ms:.1f} ms | f32-precond "
-          f"{res['f32'][1].iters} it {res['f32'][1].t_total_ms:.1f} ms | rel. diff {err:.2e}")
-    assert r <= 1e-8 * 1.001
-    assert err <= 1e-6 if name == "c2" else err <= 1e-5
-    assert res["f32"][1].iters <= 1.2 * res["f64"][1].iters + 2
+    for prec in ("f32", "f32-bf16diag"):
+        xr = res[prec][0]
+        r = np.linalg.norm(sysm.b - bs.matvec(xr)) / np.linalg.norm(sysm.b)
+        err = _rel(xr, res["f64"][0])
+        print(f"{name}: f64 {res['f64'][1].iters} it {res['f64'][1].t_total_ms:.1f} ms | {prec} "
+              f"{res[prec][1].iters} it {res[prec][1].t_total_ms:.1f} ms | rel. diff {err:.2e}")
+        assert r <= 1e-8 * 1.001
+        assert err <= 1e-6 if name == "c2" else err <= 1e-5
+        assert res[prec][1].iters <= 1.2 * res["f64"][1].iters + 2
 
 
 @pytest.mark.parametrize("hname,deg", [("H_SIG", 4), ("H_P", 4)])
@@ -130,3 +132,78 @@ def test_fp32_chebyshev_vcycle_error_vs_fp64_oracle(hname, deg):
     print(f"{hname}: FP32 Chebyshev({deg}) V-cycle rel. error vs FP64 oracle {err:.2e}")
     assert err <= 1e-4
     s.close()
+
+
+def _bf16_diagonals(h):
+    """The oracle hierarchy with every inverse diagonal rounded to BF16 as the
+    BF16-diagonal precision stores it (through FP32, nearest even)."""
+    import copy
+    from oracle import mlp
+    g = copy.copy(h)
+    g.levels = [copy.copy(lev) for lev in h.levels]
+    for lev in g.levels:
+        if lev.dinv is not None:
+            lev.dinv = mlp.round_bf16(lev.dinv)
+    return g
+
+
+@pytest.mark.parametrize("name,hname,deg", [("c1", "H_M", 0), ("c1", "H_SIG", 0), ("c1", "H_MS", 0),
+                                            ("c1", "H_A", 0), ("c1", "H_P", 0), ("c1", "H_SIG", 4),
+                                            ("c1", "H_P", 4), ("m3", "H_A", 0)])
+def test_bf16_diagonal_vcycle_vs_oracle(name, hname, deg):
+    """FP32 V-cycle with BF16-stored D^{-1} against the FP64 oracle cycle on
+    the same (imported) hierarchy with its diagonals rounded the same way:
+    FP32 rounding only (~1e3 unit roundoffs).  Against the oracle with exact
+    diagonals the cycle differs by the BF16 perturbation of the smoother, far
+    more, which shows the rounded diagonal is the one in use.  m3's H_A also
+    runs the grouped large levels."""
+    from oracle import amg, blocks, precond
+    from paper_1801_05648_amd import FsiSolver
+    mc = 40 if name == "c1" else 2000
+    bs = blocks.BlockSystem(system(name))
+    H = precond.build_hierarchies(bs, max_coarse=mc)
+    s = FsiSolver.from_system(system(name), device=0)
+    s.build_precond("f32-bf16diag", max_coarse=mc, cheb_degree=deg, cheb=(hname,) if deg else ())
+    import test_gpu_parity as tp
+    tp._import_oracle_hierarchies(s, {hname: H[hname]})
+    h, hb = H[hname], _bf16_diagonals(H[hname])
+    cyc = (lambda g, v: amg.vcycle_cheb(g, v, deg)) if deg else amg.vcycle
+    rng = np.random.default_rng(17)
+    if hname == "H_M":
+        b = rng.standard_normal(bs.n_m)
+        ref = precond.mesh_solve(bs, lambda v: cyc(hb, v), b)
+        exact = precond.mesh_solve(bs, lambda v: cyc(h, v), b)
+    else:
+        b = rng.standard_normal(h.levels[0].A.shape[0])
+        ref, exact = cyc(hb, b), cyc(h, b)
+    x = s.vcycle(hname, _dev(b)).cpu().numpy()
+    s.close()
+    err, pert = _rel(x, ref), _rel(x, exact)
+    print(f"{name} {hname} deg {deg}: vs BF16-diagonal oracle {err:.2e}, vs exact-diagonal oracle {pert:.2e}")
+    assert err <= 1e-4
+    # where rounding moves a diagonal used by a smoothing level (not, e.g., the
+    # solid mass diagonals 900, 1800, ... that BF16 holds exactly) the cycle
+    # must follow the rounded diagonal
+    moved = max(float(np.max(np.abs(lb.dinv / lv.dinv - 1.0))) for lv, lb in zip(h.levels[:-1], hb.levels[:-1]))
+    if moved > 1e-6:
+        assert pert >= 10 * err
+
+
+def test_bf16_diagonals_store_fewer_bytes_and_refuse_the_learned_smoother():
+    """Per cycle the BF16 diagonals save 2 bytes per diagonal entry read; the
+    learned smoother (which reads the diagonal in its inputs) is refused."""
+    from paper_1801_05648_amd import FsiError, FsiSolver
+    b = {}
+    for prec in ("f32", "f32-bf16diag"):
+        s = FsiSolver.from_system(system("c1"), device=0)
+        s.build_precond(prec, max_coarse=40)
+        b[prec] = s.vcycle_bytes("H_A")
+        n = s.hierarchy_info("H_A")[0]
+        if prec == "f32-bf16diag":
+            W = [np.zeros((18, 64), np.float32), np.zeros((64, 64), np.float32), np.zeros((64, 2), np.float32)]
+            with pytest.raises(FsiError, match="no learned smoother"):
+                s.mlp_set_weights("H_M", *W)
+        s.close()
+    # two diagonal reads per row of every smoothing level, 4 -> 2 bytes each
+    assert len(n) >= 2
+    assert b["f32"] - b["f32-bf16diag"] == 4 * int(np.sum(n[:-1]))
