@@ -223,6 +223,36 @@ DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, 
   return D;
 }
 
+// R and R A of a Chebyshev level on the union of their column patterns, the
+// two values of an entry side by side (0 where a matrix has no entry).
+template <typename T>
+DCsr<T> upload_pair(const HCsr& R, const HCsr& RA) {
+  DCsr<T> D;
+  D.nrows = R.nrows;
+  D.ncols = R.ncols;
+  std::vector<int64_t> rp(R.nrows + 1, 0);
+  std::vector<int32_t> ci;
+  std::vector<T> v;
+  for (int64_t i = 0; i < R.nrows; ++i) {
+    int64_t a = R.rp[i], b = RA.rp[i];
+    while (a < R.rp[i + 1] || b < RA.rp[i + 1]) {
+      const int32_t ca = a < R.rp[i + 1] ? R.ci[a] : INT32_MAX;
+      const int32_t cb = b < RA.rp[i + 1] ? RA.ci[b] : INT32_MAX;
+      const int32_t c = std::min(ca, cb);
+      ci.push_back(c);
+      v.push_back(T(ca == c ? R.v[a++] : 0.0));
+      v.push_back(T(cb == c ? RA.v[b++] : 0.0));
+    }
+    rp[i + 1] = int64_t(ci.size());
+  }
+  D.nnz = int64_t(ci.size());
+  D.rp = upload_raw(rp);
+  D.ci = upload_raw(ci);
+  D.val = upload_raw(v);
+  D.group = pick_group(D.nnz, std::max<int64_t>(D.nrows, 1));
+  return D;
+}
+
 template <typename T>
 std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) {
   auto b = std::make_shared<DevBuf>();
@@ -331,6 +361,8 @@ struct DLevel {
   bool deep = false;                   // large level: four loads in flight per lane
   bool split = false;                  // restriction by R in its own launch (no Q)
   int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
+  DCsr<T> RRA;                         // Chebyshev levels: R and R A on one column list (fused restriction)
+  int gres = 16;                       //   its lanes per coarse row
   std::vector<T> ca, cc;               // recurrence coefficients a_j, c_j, j = 1..cheb
   std::shared_ptr<DevBuf> d0, d1, r1;  // Chebyshev directions and second residual buffer
   Diag<T> diag() const {
@@ -389,6 +421,7 @@ void cheb_coefficients(double omega, int k, std::vector<T>& a, std::vector<T>& c
 
 constexpr int64_t kDeepNnz = int64_t(1) << 21;
 constexpr int64_t kSplitNnz = int64_t(1) << 21;
+constexpr int64_t kFuseRestrictNnz = int64_t(1) << 18;
 
 template <typename T>
 DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
@@ -455,7 +488,18 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       d.cheb = cheb;
       cheb_coefficients<T>(h.omega, cheb, d.ca, d.cc);
       d.A0 = upload<T>(h.A, s);
-      d.R0 = upload<T>(h.R, s);
+      // small finest levels (latency-bound launches): the restriction joins
+      // the last pre-smoothing step's launch, reading R and R A instead of R.
+      // Above 2^18 entries of R A, or on coarser levels (where R A's rows are
+      // long next to the level's own), the fused coarse rows outlast the
+      // launch saved (measured on the 2D and 3D workloads).
+      const HCsr RA = spgemm(h.R, h.A);
+      if (l == 0 && RA.nnz() < kFuseRestrictNnz) {
+        d.RRA = upload_pair<T>(h.R, RA);
+        d.gres = d.RRA.group >= 32 ? 64 : 16;
+      } else {
+        d.R0 = upload<T>(h.R, s);
+      }
       d.P = upload<T>(h.P, s);
       d.AP = upload<T>(AP, s);
       put_dinv(d, level_dinv(h.dinv));
@@ -471,7 +515,9 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       const double vb = double(sizeof(T)) * nv;
       // pre: cheb steps over A + R; post: P, AP, cheb - 1 steps over A; per step
       // d, r, dinv gathered and d, r, x written at the row
-      D.bytes_per_cycle += d.A0.bytes() * (2 * cheb - 1) + d.R0.bytes() + d.P.bytes() + d.AP.bytes() +
+      const double rbytes = d.RRA.rp ? double(d.RRA.nnz) * (4.0 + 2.0 * sizeof(T)) + 8.0 * double(d.RRA.nrows + 1)
+                                     : d.R0.bytes();
+      D.bytes_per_cycle += d.A0.bytes() * (2 * cheb - 1) + rbytes + d.P.bytes() + d.AP.bytes() +
                            double(d.n) * (6.0 * cheb * vb + 2 * db) + double(h.P.ncols) * 2 * vb;
     } else if (l < L) {
       // setup-time products for the two-launch level sweeps
@@ -605,15 +651,32 @@ void cheb_level(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   const T* rp = b;
   const T* dp = nullptr;
   int cur = 0;
+  T* bc = c.b->template as<T>();
+  const bool fused = bool(d.RRA.rp);
   for (int j = 1; j <= k; ++j) {  // pre-smoothing from x = 0
-    step(dp, rp, d.ca[j], d.cc[j], db[cur], rb[cur], j == 1, 0, T(0), T(0));
+    if (j == k && fused) {  // with b_c = R r_{k-1} - (R A) d_k in the same launch
+      with_group(A.group, [&](auto gc) {
+        constexpr int G = decltype(gc)::value;
+        const unsigned nf = grid_for(A.nrows, kBlock / G);
+        auto go = [&](auto gq) {
+          constexpr int GC = decltype(gq)::value;
+          const unsigned ncb = grid_for(d.RRA.nrows, kBlock / GC);
+          cheb_step_restrict_kernel<T, G, GC, NV><<<nf + ncb, kBlock, 0, s>>>(
+              A.nrows, A.drp(), A.dci(), A.dval(), ChebGather<T, NV>{dp, rp, dinv, d.ca[j], d.cc[j]}, db[cur],
+              rb[cur], out, j == 1, d.RRA.nrows, d.RRA.drp(), d.RRA.dci(), d.RRA.dval(), bc, nf);
+        };
+        if (d.gres == 64) go(std::integral_constant<int, 64>{});
+        else go(std::integral_constant<int, 16>{});
+      });
+    } else {
+      step(dp, rp, d.ca[j], d.cc[j], db[cur], rb[cur], j == 1, 0, T(0), T(0));
+    }
     dp = db[cur];
     rp = rb[cur];
     cur ^= 1;
   }
   T* rk = rb[cur ^ 1];
-  T* bc = c.b->template as<T>();
-  launch_rows<T, NV>(d.R0, GatherPlain<T, NV>{rk}, EpiStore<T, NV>{bc}, s);
+  if (!fused) launch_rows<T, NV>(d.R0, GatherPlain<T, NV>{rk}, EpiStore<T, NV>{bc}, s);
   T* e = c.y->template as<T>();
   vcycle_rec<T, NV>(H, l + 1, bc, e, s, plain);
   with_group(d.gup, [&](auto gc) {

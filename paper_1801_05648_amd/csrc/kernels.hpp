@@ -642,6 +642,68 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(int64_t n, const int6
   }
 }
 
+// The last pre-smoothing step of a Chebyshev level with the restriction in
+// the same launch: blocks [0, nblk_f) run the step on the fine rows (d_k, r_k
+// stored, x updated), the others compute the coarse right-hand side
+//   b_c = R r_k = R r_{k-1} - (R A) d_k
+// with d_k formed at every gathered column like the fine rows do.  R and R A
+// share one column list (the union pattern), their two values side by side.
+template <typename T, int G, int GC, int NV>
+__global__ __launch_bounds__(kBlock) void cheb_step_restrict_kernel(
+    int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ ci, const T* __restrict__ val,
+    ChebGather<T, NV> g, T* __restrict__ dout, T* __restrict__ rout, T* x, int xinit, int64_t nc,
+    const int64_t* __restrict__ rpc, const int32_t* __restrict__ cic, const T* __restrict__ vrc, T* __restrict__ bc,
+    unsigned nblk_f) {
+  if (blockIdx.x < nblk_f) {
+    constexpr int RPB = kBlock / G;
+    const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+    const int lane = threadIdx.x % G;
+    if (row >= n) return;
+    T acc[NV], dj[NV], rp0[NV], xi[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] = dj[q] = rp0[q] = xi[q] = T(0);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int64_t k = row * NV + q;
+        dj[q] = g(int32_t(row), q);
+        rp0[q] = g.r[k];
+        xi[q] = xinit ? T(0) : x[k];
+      }
+    }
+    row_accumulate<T, G, NV>(rp, ci, val, row, lane, g, acc);
+    group_reduce<T, G, NV>(acc);
+    if (lane == 0) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        const int64_t k = row * NV + q;
+        dout[k] = dj[q];
+        rout[k] = rp0[q] - acc[q];
+        x[k] = xinit ? dj[q] : xi[q] + dj[q];
+      }
+    }
+    return;
+  }
+  constexpr int RPB = kBlock / GC;
+  const int64_t row = int64_t(blockIdx.x - nblk_f) * RPB + threadIdx.x / GC;
+  const int lane = threadIdx.x % GC;
+  if (row >= nc) return;
+  T acc[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) acc[q] = T(0);
+  const int64_t b = rpc[row], e = rpc[row + 1];
+  for (int64_t k = b + lane; k < e; k += GC) {
+    const int32_t c = cic[k];
+    const T rv = vrc[2 * k], rav = vrc[2 * k + 1];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) acc[q] += rv * g.r[int64_t(c) * NV + q] - rav * g(c, q);
+  }
+  group_reduce<T, GC, NV>(acc);
+  if (lane == 0)
+#pragma unroll
+    for (int q = 0; q < NV; ++q) bc[row * NV + q] = acc[q];
+}
+
 // Coarse correction of a Chebyshev level: x += P e, r -= (A P) e (r in place;
 // both only at the row itself).  With `fuse` (degree 1) the post-smoothing
 // step x += c1 D^{-1} r follows in the same pass.

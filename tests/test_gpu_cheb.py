@@ -170,3 +170,53 @@ def test_chebyshev_only_mass_inverse_solve_matches_oracle():
     print(f"c1 M_s Chebyshev-only: GPU {info.iters} it, oracle {io.iters} it to 1e-12, rel. diff {err:.2e}")
     assert info.converged and err <= 1e-6
     s.close()
+
+
+def _cheb_cycle_bytes(h, deg, fuse_below=2 ** 18):
+    """Bytes of one FP64 Chebyshev(deg) V-cycle as the library counts them:
+    per smoothing level 2 deg - 1 products with A, the restriction (R alone,
+    or R and R A on their union pattern, 4 + 16 bytes per entry, where R A
+    has fewer than 2^18 entries and the restriction joins the last
+    pre-smoothing launch; finest level only), P and A P, six vectors per
+    step, two diagonal reads, the coarse vectors; the dense coarsest
+    inverse."""
+    total = 0.0
+    for l, lev in enumerate(h.levels[:-1]):
+        A, P, R = lev.A.tocsr(), lev.P.tocsr(), lev.R.tocsr()
+        n, nc = A.shape[0], P.shape[1]
+        csr = lambda M: 12.0 * M.nnz + 8.0 * (M.shape[0] + 1)
+        RA = (abs(R) @ abs(A)).tocsr()
+        if l == 0 and RA.nnz < fuse_below:
+            U = (abs(R) + RA).tocsr()
+            rbytes = 20.0 * U.nnz + 8.0 * (nc + 1)
+        else:
+            rbytes = csr(R)
+        AP = (abs(A) @ abs(P)).tocsr()
+        total += csr(A) * (2 * deg - 1) + rbytes + csr(P) + csr(AP) + n * (6.0 * deg * 8 + 2 * 8) + nc * 2 * 8
+    nL = h.levels[-1].A.shape[0]
+    return total + 8.0 * nL * nL
+
+
+@pytest.mark.parametrize("hname", ["H_SIG", "H_P"])
+def test_fused_restriction_at_full_size(hname):
+    """2D 256x64-cell system, 2000-row coarse grids, Chebyshev(4): the small
+    finest levels of H_SIG and H_P restrict inside the last pre-smoothing
+    launch (b_c = R r_{k-1} - (R A) d_k).  The cycle on the oracle's imported
+    hierarchy matches the oracle's, and the bytes the library reports are the
+    fused layout's (so the fused kernel ran)."""
+    from oracle import amg
+    bs, H = _oracle("c2", 2000)
+    h = H[hname]
+    s = _solver("c2", 2000, 4, (hname,))
+    _import(s, H, [hname])
+    b = np.random.default_rng(23).standard_normal(h.levels[0].A.shape[0])
+    x = s.vcycle(hname, _dev(b)).cpu().numpy()
+    got = s.vcycle_bytes(hname)
+    s.close()
+    ref = amg.vcycle_cheb(h, b, 4)
+    assert _rel(x, ref) <= 1e-12, _rel(x, ref)
+    expect = _cheb_cycle_bytes(h, 4)
+    plain = _cheb_cycle_bytes(h, 4, fuse_below=0)
+    print(f"{hname}: cycle bytes {got:.0f}, fused layout {expect:.0f}, separate restriction {plain:.0f}")
+    assert abs(got - expect) <= 2e-3 * expect
+    assert abs(plain - expect) >= 2e-2 * expect  # the two layouts are told apart
