@@ -58,7 +58,7 @@ def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
         H = precond.build_hierarchies(bs, max_coarse=args.max_coarse)
         t_setup = time.perf_counter() - t0
         cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
-        poly = {h: (args.poly_degree, 8.0) for h in poly_on(args)}
+        poly = {h: (args.poly_degree, args.poly_ratio) for h in poly_on(args)}
         P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly)
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
@@ -132,7 +132,8 @@ def learned_run(args, cfg):
     sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
     solver = FsiSolver.from_system(sysm, device=0, stream=stream)
     solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree)
+                             poly=poly_on(args), poly_degree=args.poly_degree,
+                             poly_ratio=args.poly_ratio)
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -144,7 +145,8 @@ def learned_run(args, cfg):
             sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
             solver.set_from_system(sysm)
             solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree)
+                             poly=poly_on(args), poly_degree=args.poly_degree,
+                             poly_ratio=args.poly_ratio)
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -160,7 +162,8 @@ def learned_run(args, cfg):
         sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
         solver.set_from_system(sysm)
         solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree)
+                             poly=poly_on(args), poly_degree=args.poly_degree,
+                             poly_ratio=args.poly_ratio)
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -232,7 +235,10 @@ def main():
     ap.add_argument("--poly-on", default=None,
                     help="comma-separated hierarchies inverted by Chebyshev steps alone "
                          "(default H_MS, none with --learned)")
-    ap.add_argument("--poly-degree", type=int, default=3)
+    ap.add_argument("--poly-degree", type=int, default=None,
+                    help="Chebyshev-alone steps (default: 2 in 2D, 3 in 3D)")
+    ap.add_argument("--poly-ratio", type=float, default=8.0,
+                    help="Chebyshev-alone inverses: interval [lam/ratio, lam]")
     ap.add_argument("--learned", action="store_true",
                     help="pseudo-time workload of the learned smoother (plain vs learned cycles)")
     ap.add_argument("--train-steps", type=int, default=10)
@@ -262,6 +268,10 @@ def main():
         args.max_coarse = 500 if args.learned else 2000
     if args.poly_on is None:
         args.poly_on = "" if args.learned else "H_MS"
+    if args.poly_degree is None:
+        # two steps suffice for the 2D Q2 mass matrix (measured 23.4 vs 24.1 ms
+        # on the 256x64 system); the 3D one needs three (46 vs 78 iterations)
+        args.poly_degree = 2 if cfg.dim == 2 else 3
     if args.learned:
         learned_run(args, cfg)
         return
@@ -293,7 +303,8 @@ def main():
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         t0 = time.perf_counter()
         solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree)
+                             poly=poly_on(args), poly_degree=args.poly_degree,
+                             poly_ratio=args.poly_ratio)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")
