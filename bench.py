@@ -230,8 +230,9 @@ def main():
                          "default 4, and 0 with --learned (the learned smoother replaces a Jacobi sweep)")
     ap.add_argument("--max-coarse", type=int, default=None,
                     help="AMG: coarsest level size bound (dense inverse below it); default 2000, 500 with --learned")
-    ap.add_argument("--cheb-on", default="H_MS,H_SIG,H_P",
-                    help="comma-separated hierarchies that get the Chebyshev sweeps")
+    ap.add_argument("--cheb-on", default=None,
+                    help="comma-separated hierarchies that get the Chebyshev sweeps "
+                         "(default: H_SIG in 2D, H_SIG and H_P in 3D)")
     ap.add_argument("--poly-on", default=None,
                     help="comma-separated hierarchies inverted by Chebyshev steps alone "
                          "(default H_MS, none with --learned)")
@@ -272,6 +273,11 @@ def main():
         # two steps suffice for the 2D Q2 mass matrix (measured 23.4 vs 24.1 ms
         # on the 256x64 system); the 3D one needs three (46 vs 78 iterations)
         args.poly_degree = 2 if cfg.dim == 2 else 3
+    if args.cheb_on is None:
+        # the 2D pressure Schur approximation does best with Jacobi sweeps
+        # (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one
+        # needs the Chebyshev sweeps (64x16x16: 46 vs 530 iterations)
+        args.cheb_on = "H_MS,H_SIG" if cfg.dim == 2 else "H_MS,H_SIG,H_P"
     if args.learned:
         learned_run(args, cfg)
         return
