@@ -55,7 +55,7 @@ def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
     try:
         bs = blocks.BlockSystem(sysm)
         t0 = time.perf_counter()
-        H = precond.build_hierarchies(bs, max_coarse=args.max_coarse)
+        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse)
         t_setup = time.perf_counter() - t0
         cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
         poly = {h: (args.poly_degree, args.poly_ratio) for h in poly_on(args)}
@@ -131,7 +131,8 @@ def learned_run(args, cfg):
     progress(f"{cfg.name}: training on {len(train)} Newton systems, evaluating {len(evals)}")
     sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
     solver = FsiSolver.from_system(sysm, device=0, stream=stream)
-    solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+    solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
+                             cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio)
     d = sysm.dim
@@ -144,7 +145,8 @@ def learned_run(args, cfg):
         if n:
             sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
             solver.set_from_system(sysm)
-            solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+            solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
+                             cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio)
         b = torch.from_numpy(sysm.b).to(dev)
@@ -161,7 +163,8 @@ def learned_run(args, cfg):
     for k, i in evals:
         sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
         solver.set_from_system(sysm)
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+        solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
+                             cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio)
         b = torch.from_numpy(sysm.b).to(dev)
@@ -236,6 +239,8 @@ def main():
     ap.add_argument("--poly-on", default=None,
                     help="comma-separated hierarchies inverted by Chebyshev steps alone "
                          "(default H_MS, none with --learned)")
+    ap.add_argument("--strength", type=float, default=0.08,
+                    help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
                     help="Chebyshev-alone steps (default: 2 in 2D, 3 in 3D)")
     ap.add_argument("--poly-ratio", type=float, default=8.0,
@@ -308,7 +313,8 @@ def main():
         progress(f"N={sysm.N} nnz={sysm.nnz}")
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         t0 = time.perf_counter()
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, cheb_degree=args.cheb, cheb=cheb_on(args),
+        solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
+                             cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio)
         torch.cuda.synchronize()
