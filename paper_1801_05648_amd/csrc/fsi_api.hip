@@ -181,6 +181,8 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
 template <typename T>
 DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, double vec_bytes,
                         hipStream_t s) {
+  if (nseg < 1 || nseg > 4 || bounds[0] != 0 || bounds[nseg] != A.nrows)
+    throw Error(FSI_ERR_ARG, "row segments must cover the matrix in at most four parts");
   DCsr<T> D = upload<T>(A, s);
   D.deep = true;
   RowSegments sg{};
