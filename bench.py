@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0
 # Valid only for the kernel and workload it was measured on (empty: the
 # kernel changed since the counters were taken).
 MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563}
+# The same for one H_A V-cycle of the benchmark preconditioner (bench.py
+# --pmc-vcycle); see profiles/h_a_vcycle_hbm_traffic.md.
+MEASURED_VCYCLE_TRAFFIC = {"c2": 129161151, "c3": 1614689335}
 DTYPE = {"f64": "f64", "f32": "f64-krylov/f32-precond", "f32-bf16diag": "f64-krylov/f32-precond/bf16-diag"}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
@@ -460,7 +463,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": MEASURED_TRAFFIC.get(cfg.name),
+            "traffic": MEASURED_TRAFFIC.get(cfg.name),  # the A_h product is FP64 in every precision
             "algorithmic_bytes": int(nbytes),
             "csr_bytes": int(runs[0]["csr_bytes"]),
             "kernel_ms": round(spmv_ms, 5),
@@ -470,6 +473,8 @@ def main():
             "GB/s": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1),
             "frac": round(vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "levels": int(len(solver.hierarchy_info("H_A")[0])),
+            "traffic": (MEASURED_VCYCLE_TRAFFIC.get(cfg.name)
+                        if (args.precision, args.max_coarse, args.strength) == ("f64", 2000, 0.08) else None),
         },
     }
     if not args.no_cpu_baseline:
