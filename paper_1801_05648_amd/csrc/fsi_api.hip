@@ -576,7 +576,10 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       const int per_lane = d.deep ? 10 : 3;
       const int64_t units = d.n / d.rgroup;  // rows or row groups
       d.gdown = pick_group(d.AD.nnz, units, per_lane);
-      d.gdownq = d.deep || d.split ? 16 : (pick_group(d.Q.nnz, d.Q.nrows) >= 32 ? 64 : 16);
+      // coarse rows of Q: 64 lanes where they are long (the few coarse rows of
+      // a large level otherwise outlast its many fine rows), else 16
+      const int64_t qunits = std::max<int64_t>(d.Q.nrows / d.rgroup, 1);
+      d.gdownq = d.split ? 16 : (pick_group(d.Q.nnz, qunits, d.deep ? 12 : 3) >= 32 ? 64 : 16);
       d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(units, 1), per_lane);
       const double vb = double(sizeof(T)) * nv;
       // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
@@ -758,13 +761,18 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
       with_group(d.gdown, [&](auto gc) {
         constexpr int GA = decltype(gc)::value;
         const unsigned na = grid_for(d.n / d.rgroup, kBlock / GA);
-        const unsigned nq = d.split ? 0u : grid_for(d.Q.nrows / d.rgroup, kBlock / 16);
-        with_rgroup(d.rgroup, [&](auto gr) {
-          constexpr int GR = decltype(gr)::value;
-          vdown_grp_kernel<T, GA, 16, GR><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
-                                                                      d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
-                                                                      d.omega, r, bc, na);
-        });
+        auto go = [&](auto gq) {
+          constexpr int GQ = decltype(gq)::value;
+          const unsigned nq = d.split ? 0u : grid_for(d.Q.nrows / d.rgroup, kBlock / GQ);
+          with_rgroup(d.rgroup, [&](auto gr) {
+            constexpr int GR = decltype(gr)::value;
+            vdown_grp_kernel<T, GA, GQ, GR><<<na + nq, kBlock, 0, s>>>(
+                d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(), b,
+                d.omega, r, bc, na);
+          });
+        };
+        if (d.gdownq == 64) go(std::integral_constant<int, 64>{});
+        else go(std::integral_constant<int, 16>{});
       });
       if (d.split) launch_rows<T, 1>(d.R0, GatherPlain<T, 1>{r}, EpiStore<T, 1>{bc}, s);  // b_c = R r
       T* e = c.y->template as<T>();
