@@ -255,8 +255,8 @@ def main():
     ap.add_argument("--train-iters", type=int, default=600)
     ap.add_argument("--max-vectors", type=int, default=192)
     ap.add_argument("--record-every", type=int, default=37)
-    ap.add_argument("--pmc-vcycle", action="store_true",
-                    help="counter probe: 25 H_A V-cycles and a 256 MiB copy, then exit")
+    ap.add_argument("--pmc-vcycle", nargs="?", const="H_A", default=None,
+                    help="counter probe: 25 V-cycles of a hierarchy (default H_A) and a 256 MiB copy, then exit")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="only launch the A_h product 20 times and a 256 MiB device copy "
                          "(for hardware byte counters); prints nothing else")
@@ -295,25 +295,27 @@ def main():
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     if args.pmc_vcycle:
-        # hardware-counter probe of the largest V-cycle: the benchmark's
-        # preconditioner, 25 H_A cycles (the only kernels of the run after the
-        # host-side setup), then a plain 256 MiB copy for the counter scale
+        # hardware-counter probe of one hierarchy's V-cycle (default H_A, the
+        # largest): the benchmark's preconditioner, 25 cycles (the only kernels
+        # of the run after the host-side setup), then a plain 256 MiB copy for
+        # the counter scale
         sysm = fsigen.generate(cfg, seed=args.seeds[0])
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args), poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio)
-        nv = int(solver.hierarchy_info("H_A")[0][0])
+        hn = args.pmc_vcycle
+        nv = int(solver.hierarchy_info(hn)[0][0]) * (sysm.dim if hn == "H_M" else 1)
         bv = torch.randn(nv, dtype=torch.float64, device=dev)
         xv = torch.empty_like(bv)
         for _ in range(25):
-            solver.vcycle("H_A", bv, xv)
+            solver.vcycle(hn, bv, xv)
         src = torch.ones(256 * 2 ** 20 // 8, dtype=torch.float64, device=dev)
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_vcycle": True, "cycles": 25, "vcycle_bytes": solver.vcycle_bytes("H_A"),
+        print(json.dumps({"pmc_vcycle": hn, "cycles": 25, "vcycle_bytes": solver.vcycle_bytes(hn),
                           "copy_bytes": 2 * 256 * 2 ** 20}))
         solver.close()
         return
