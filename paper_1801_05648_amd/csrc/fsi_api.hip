@@ -362,6 +362,8 @@ struct DLevel {
   int rgroup = 1;                      // > 1: AD, Q (or R), P, AP stored in groups of rgroup rows
   bool deep = false;                   // large level: four loads in flight per lane
   bool split = false;                  // restriction by R in its own launch (no Q)
+  bool split_plain = false;            // the learned smoother's level: Q kept for its own
+                                       //   sweep, the plain cycle restricts by R apart
   int cheb = 0;                        // Chebyshev degree of this level's sweeps (0: Jacobi)
   DCsr<T> RRA;                         // Chebyshev levels: R and R A on one column list (fused restriction)
   int gres = 16;                       //   its lanes per coarse row
@@ -535,7 +537,9 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       // Restricting through Q fuses the restriction into the down-sweep but
       // reads nnz(Q) instead of nnz(R) entries; where the difference costs
       // more than a launch, restrict the residual with R in a launch of its own.
-      d.split = !(l == 0 && keep_a0) && Q.nnz() - h.R.nnz() >= kSplitNnz;
+      const bool split_worthy = Q.nnz() - h.R.nnz() >= kSplitNnz;
+      d.split = !(l == 0 && keep_a0) && split_worthy;
+      d.split_plain = l == 0 && keep_a0 && split_worthy;  // R is uploaded for that level below
       // Large levels of a vector problem (group = components per node): where
       // the rows of a node share their columns in all four matrices (at most
       // 5% zero fill), store them in groups of `group` rows.  Decided on the
@@ -583,7 +587,9 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       d.gup = pick_group(d.AP.nnz + d.P.nnz, std::max<int64_t>(units, 1), per_lane);
       const double vb = double(sizeof(T)) * nv;
       // down: A, Q, dinv, b (x1 + gathers), r and b_c writes; up: P, AP, e, b, r, dinv, y
-      D.bytes_per_cycle += d.AD.bytes() + (d.split ? d.R0.bytes() + double(d.n) * vb : d.Q.bytes()) + d.P.bytes() +
+      // (the plain cycle's bytes: with split_plain the restriction by R apart)
+      const bool apart = d.split || d.split_plain;
+      D.bytes_per_cycle += d.AD.bytes() + (apart ? d.R0.bytes() + double(d.n) * vb : d.Q.bytes()) + d.P.bytes() +
                            d.AP.bytes() + double(d.n) * (2 * db + 5 * vb) + double(h.P.ncols) * 2 * vb;
     }
     auto mk = [&](int64_t cnt) {
@@ -789,12 +795,13 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
       return;
     }
   }
+  const bool apart = d.split || (d.split_plain && !learned);  // restriction by R in a launch of its own
   with_group(d.gdown, [&](auto gc) {
     constexpr int GA = decltype(gc)::value;
     const unsigned na = grid_for(d.AD.nrows, kBlock / GA);
     auto go = [&](auto gq) {
       constexpr int GQ = decltype(gq)::value;
-      const unsigned nq = d.split ? 0u : grid_for(d.Q.nrows, kBlock / GQ);
+      const unsigned nq = apart ? 0u : grid_for(d.Q.nrows, kBlock / GQ);
       if (learned)
         vdown_sel_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(
             d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
@@ -812,7 +819,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
     if (d.gdownq == 64) go(std::integral_constant<int, 64>{});
     else go(std::integral_constant<int, 16>{});
   });
-  if (d.split) launch_rows<T, NV>(d.R0, GatherPlain<T, NV>{r}, EpiStore<T, NV>{bc}, s);  // b_c = R r
+  if (apart) launch_rows<T, NV>(d.R0, GatherPlain<T, NV>{r}, EpiStore<T, NV>{bc}, s);  // b_c = R r
   T* e = c.y->template as<T>();
   vcycle_rec<T, NV>(H, l + 1, bc, e, s, plain);
   with_group(d.gup, [&](auto gc) {

@@ -291,6 +291,30 @@ def test_vcycle_parity_3d_with_large_levels(hname):
     s.close()
 
 
+def test_vcycle_parity_c3_mesh_restricting_apart():
+    """3D 64x16x16-cell mesh hierarchy: its finest level is the learned
+    smoother's and keeps Q for that sweep, but its Q has 5M more entries than
+    R, so the plain cycle restricts with R in a launch of its own.  One cycle
+    on the oracle's imported hierarchy against the oracle's cycle."""
+    from oracle import amg, blocks, precond
+    from paper_1801_05648_amd import FsiSolver
+    sysm = system("c3")
+    bs = blocks.BlockSystem(sysm)
+    L = bs.mesh_scalar()
+    h = amg.setup(L, 1, amg.constant_modes(L.shape[0]), max_coarse=2000)
+    lev = h.levels[0]
+    Qp = (abs(lev.R) + abs(lev.R) @ abs(lev.A)).tocsr()
+    assert Qp.nnz - lev.R.nnz >= 2 ** 21  # the case this test is for
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f64", max_coarse=2000)
+    _import_oracle_hierarchies(s, {"H_M": h})
+    b = np.random.default_rng(29).standard_normal(bs.n_m)
+    x = s.vcycle("H_M", _dev(b)).cpu().numpy()
+    s.close()
+    ref = precond.mesh_solve(bs, lambda v: amg.vcycle(h, v), b)
+    assert _rel(x, ref) <= 1e-12, _rel(x, ref)
+
+
 def _cycle_bytes(h, g, allow_groups=True):
     """Bytes of one Jacobi V(1,1) cycle of the FP64 library as executed, with
     the levels of at least 2^21 entries whose A D^{-1}, Q (or R), P and A P
