@@ -75,7 +75,7 @@ struct DCsr {
   RowSegments seg{};  // nseg > 0: row segments with their own lanes per row
   std::shared_ptr<DevBuf> rp, ci, val;
   std::shared_ptr<DevBuf> grp_rp[4], grp_ci[4], grp_val[4];  // grouped segments
-  double seg_bytes = 0.0;  // bytes of one product as stored (segmented matrices)
+  double seg_bytes = 0.0;  // segmented matrices: bytes of the matrix as stored
   int rgroup = 1;          // > 1: rows stored in groups of rgroup (nnz counts column-list entries)
   const int64_t* drp() const { return rp ? rp->as<int64_t>() : nullptr; }
   const int32_t* dci() const { return ci ? ci->as<int32_t>() : nullptr; }
@@ -177,10 +177,9 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
 // start at row 0, each with its own lanes per row or row group (about twelve
 // entries per lane, 4 to 32 lanes; measured best for long rows); segment q is
 // stored in groups of group[q] rows where that costs at most 5% zero fill.
-// bytes(): the matrix as stored plus vec_bytes (the vectors of one product).
+// bytes(): the matrix as stored (values, column lists, row or group pointers).
 template <typename T>
-DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, double vec_bytes,
-                        hipStream_t s) {
+DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, hipStream_t s) {
   if (nseg < 1 || nseg > 4 || bounds[0] != 0 || bounds[nseg] != A.nrows)
     throw Error(FSI_ERR_ARG, "row segments must cover the matrix in at most four parts");
   DCsr<T> D = upload<T>(A, s);
@@ -189,7 +188,7 @@ DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, 
   sg.nseg = 0;
   sg.blk0[0] = 0;
   sg.row0[0] = bounds[0];
-  double bytes = vec_bytes;
+  double bytes = 0.0;
   for (int q = 0; q < nseg; ++q) {
     const int64_t r0 = bounds[q], r1 = bounds[q + 1];
     if (r1 <= r0) continue;
@@ -1140,7 +1139,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     // the pressure rows
     const int64_t bounds[3] = {0, c.n_vf, c.n_f};
     const int groups[2] = {c.d, 1};
-    P->Cfms = upload_segments<T>(M, bounds, groups, 2, double(sizeof(T)) * double(M.ncols + 2 * c.n_f), s);
+    P->Cfms = upload_segments<T>(M, bounds, groups, 2, s);
   }
   P->alloc_tmp();
   HIP_TRY(hipStreamSynchronize(s));
@@ -2196,7 +2195,7 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     // values.  Solid rows differ in about half their columns: plain rows.
     const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
     const int groups[4] = {1, 1, d, 1};
-    DCsr<double> dAh = upload_segments<double>(Ah, bounds, groups, 4, 16.0 * double(N), ctx->stream);
+    DCsr<double> dAh = upload_segments<double>(Ah, bounds, groups, 4, ctx->stream);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     // commit
     fsi_ctx& c = *ctx;
@@ -2460,7 +2459,7 @@ fsi_status fsi_spmv_bytes(fsi_ctx* ctx, double* bytes) {
     fsi_ctx& c = *ctx;
     if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
     if (!bytes) throw Error(FSI_ERR_ARG, "bad arguments");
-    *bytes = c.Ah.bytes();
+    *bytes = c.Ah.bytes() + 16.0 * double(c.N);  // the matrix, x read once, y written
     return FSI_OK;
   });
 }
