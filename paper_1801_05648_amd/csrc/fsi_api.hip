@@ -339,6 +339,7 @@ struct MlpUse {
   double* npart = nullptr;
   int* flag = nullptr;
   int* fallbacks = nullptr;
+  int* streak = nullptr;  // consecutive rejections in the current solve
 };
 
 // Recording of finest-level V-cycle inputs (training data of the smoother).
@@ -619,17 +620,21 @@ void mlp_presmooth(DHier<T>& H, const T* b, hipStream_t s) {
   const T* dinv = d0.dinv->template as<T>();
   const unsigned grid = mlp_infer_grid(u.n_nodes);
   if (u.d == 2) {
-    if (u.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
-    else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
+    if (u.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm, u.streak,
+                                                                       kLearnedStreak);
+    else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm, u.streak,
+                                                                       kLearnedStreak);
   } else {
-    if (u.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
-    else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm);
+    if (u.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm, u.streak,
+                                                                       kLearnedStreak);
+    else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(u.n_nodes, u.nbr, b, dinv, u.w, xm, u.streak,
+                                                                       kLearnedStreak);
   }
   const DCsr<T>& A = d0.A0;
   with_group(A.group, [&](auto gc) {
     constexpr int G = decltype(gc)::value;
     learned_resid_kernel<T, G, NV><<<kDecideBlocks, kBlock, 0, s>>>(A.nrows, A.drp(), A.dci(), A.dval(), xm, b,
-                                                                     rm, u.npart);
+                                                                     rm, u.npart, u.streak);
   });
 }
 
@@ -805,7 +810,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
         vdown_sel_kernel<T, GA, GQ, NV><<<na + nq, kBlock, 0, s>>>(
             d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(), d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
             d.R0.drp(), d.R0.dci(), d.R0.dval(), b, d.omega, r, bc, H.rm->template as<T>(), H.mlp->npart,
-            H.mlp->flag, H.mlp->fallbacks, na);
+            H.mlp->flag, H.mlp->fallbacks, H.mlp->streak, na);
       else if (d.deep)
         vdown_kernel<T, GA, GQ, NV, true><<<na + nq, kBlock, 0, s>>>(d.AD.nrows, d.AD.drp(), d.AD.dci(), d.AD.dval(),
                                                                       d.Q.nrows, d.Q.drp(), d.Q.dci(), d.Q.dval(),
@@ -826,7 +831,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
     if (learned)
       vup_sel_kernel<T, G, NV><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(
           d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b, dinv, d.omega, r,
-          H.xm->template as<T>(), H.rm->template as<T>(), H.mlp->flag, out);
+          H.xm->template as<T>(), H.rm->template as<T>(), H.mlp->flag, H.mlp->streak, out);
     else if (d.deep)
       vup_kernel<T, G, NV, true><<<grid_for(d.n, kBlock / G), kBlock, 0, s>>>(
           d.n, d.P.drp(), d.P.dci(), d.P.dval(), d.AP.drp(), d.AP.dci(), d.AP.dval(), e, b, dinv, d.omega, r, out);
@@ -942,7 +947,7 @@ struct MlpState {
   MlpUse use;
   MlpRecord rec;
   std::vector<float> wnode;  // node weights of the loss (mean diagonal / operator mean)
-  DevBuf nbr, npart, flag, fallbacks;
+  DevBuf nbr, npart, flag, fallbacks, streak;
   DevBuf wm, m1, m2, g, loss, w1t, w2t, w2, w3t, w3, part, part_loss, part2, loss2;
   int adam_t = 0;
   int nparam() const { return d == 2 ? MlpDims<2>::NPARAM : MlpDims<3>::NPARAM; }
@@ -1214,7 +1219,8 @@ void givens(double a, double b, double& cs, double& sn) {
 fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_opts& o, fsi_solve_info& info) {
   hipStream_t s = c.stream;
   for (auto& M : c.mlp)
-    if (M.fallbacks.p) HIP_TRY(hipMemsetAsync(M.fallbacks.p, 0, sizeof(int), s));
+    for (DevBuf* b : {&M.fallbacks, &M.streak})
+      if (b->p) HIP_TRY(hipMemsetAsync(b->p, 0, sizeof(int), s));
   const bool recording = c.mlp[0].rec.active || c.mlp[1].rec.active;
   const bool graphs = c.use_graphs && !recording;  // recording copies vectors from the host side
   const int64_t N = c.N;
@@ -1531,6 +1537,10 @@ void prepare_mlp(fsi_ctx& c) {
       M.fallbacks.alloc(sizeof(int));
       HIP_TRY(hipMemsetAsync(M.fallbacks.p, 0, sizeof(int), c.stream));
     }
+    if (!M.streak.p) {
+      M.streak.alloc(sizeof(int));
+      HIP_TRY(hipMemsetAsync(M.streak.p, 0, sizeof(int), c.stream));
+    }
     const size_t np = size_t(M.nparam());
     if (M.wm.bytes != sizeof(float) * np) {
       for (DevBuf* b : {&M.wm, &M.m1, &M.m2, &M.g}) {
@@ -1557,6 +1567,7 @@ void prepare_mlp(fsi_ctx& c) {
     M.use.npart = M.npart.as<double>();
     M.use.flag = M.flag.as<int>();
     M.use.fallbacks = M.fallbacks.as<int>();
+    M.use.streak = M.streak.as<int>();
   }
   HIP_TRY(hipStreamSynchronize(c.stream));
 }
@@ -2527,6 +2538,8 @@ fsi_status fsi_mlp_set_weights(fsi_ctx* ctx, int which, const float* W1, const f
     MlpState& M = mlp_state(*ctx, which);
     if (!W1 || !W2 || !W3) throw Error(FSI_ERR_ARG, "weights are NULL");
     mlp_upload_weights(*ctx, M, W1, W2, W3);
+    HIP_TRY(hipMemsetAsync(M.streak.p, 0, sizeof(int), ctx->stream));  // new weights are tried again
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
     return FSI_OK;
   });
 }
@@ -2555,6 +2568,8 @@ fsi_status fsi_mlp_enable(fsi_ctx* ctx, int which, int enable) {
   return guarded(ctx, [&]() -> fsi_status {
     MlpState& M = mlp_state(*ctx, which);
     if (enable && !M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    HIP_TRY(hipMemsetAsync(M.streak.p, 0, sizeof(int), ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
     if (M.use.enabled != (enable != 0)) {
       M.use.enabled = enable != 0;
       ctx->drop_graphs();  // the captured kernel sequence changes
@@ -2694,6 +2709,9 @@ fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_t
       if (c.precision == FSI_P_F64) mlp_train_energy<double>(c, *c.p64, o, local);
       else mlp_train_energy<float>(c, *c.p32, o, local);
     }
+    for (auto& M : c.mlp)  // the trained networks are tried again
+      if (M.streak.p) HIP_TRY(hipMemsetAsync(M.streak.p, 0, sizeof(int), c.stream));
+    HIP_TRY(hipStreamSynchronize(c.stream));
     if (info) *info = local;
     return FSI_OK;
   });

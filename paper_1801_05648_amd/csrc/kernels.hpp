@@ -418,13 +418,20 @@ __global__ __launch_bounds__(kBlock) void vup_grp_kernel(
 // blocks striding over the rows), part[2 k] = sum of r^2 and part[2 k + 1] =
 // sum of b^2 over the rows of block k, summed in a fixed order.
 constexpr int kDecideBlocks = 1024;
+// After this many consecutive rejections in a solve the learned pre-smoother
+// is not tried again until the next solve (or new weights): its inference
+// and residual kernels return at once and the down-sweep takes the Jacobi
+// branch.  The count lives in device memory, advanced by the up-sweep.
+constexpr int kLearnedStreak = 8;
 
 template <typename T, int G, int NV>
 __global__ __launch_bounds__(kBlock) void learned_resid_kernel(int64_t n, const int64_t* __restrict__ rp,
                                                                 const int32_t* __restrict__ ci,
                                                                 const T* __restrict__ val, const T* __restrict__ x,
                                                                 const T* __restrict__ b, T* __restrict__ r,
-                                                                double* __restrict__ part) {
+                                                                double* __restrict__ part,
+                                                                const int* __restrict__ streak) {
+  if (streak[0] >= kLearnedStreak) return;  // not tried any more in this solve
   constexpr int RPB = kBlock / G;
   __shared__ double sh[2][kBlock / 64];
   const int lane = threadIdx.x % G;
@@ -472,8 +479,15 @@ __global__ __launch_bounds__(kBlock) void learned_resid_kernel(int64_t n, const 
 // the partials above.  Every block evaluates it in the same order, so all
 // agree; the owner block stores it in flag[0] and counts a rejection.
 __device__ __forceinline__ bool learned_accept(const double* __restrict__ part, int* flag, int* fallbacks,
-                                               bool owner) {
+                                               const int* __restrict__ streak, bool owner) {
   __shared__ int s_ok;
+  if (streak[0] >= kLearnedStreak) {  // not tried (the partials are stale): Jacobi
+    if (threadIdx.x == 0 && owner) {
+      flag[0] = 0;
+      fallbacks[0] = fallbacks[0] + 1;
+    }
+    return false;
+  }
   if (threadIdx.x < 64) {
     double rr = 0.0, bb = 0.0;
 #pragma unroll
@@ -512,8 +526,8 @@ __global__ __launch_bounds__(kBlock) void vdown_sel_kernel(
     int64_t nq, const int64_t* __restrict__ rpq, const int32_t* __restrict__ ciq, const T* __restrict__ vq,
     const int64_t* __restrict__ rpr, const int32_t* __restrict__ cir, const T* __restrict__ vr,
     const T* __restrict__ b, T omega, T* __restrict__ r, T* __restrict__ bc, const T* __restrict__ r_m,
-    const double* __restrict__ part, int* flag, int* fallbacks, unsigned nblk_a) {
-  const bool learned = learned_accept(part, flag, fallbacks, blockIdx.x == 0);
+    const double* __restrict__ part, int* flag, int* fallbacks, const int* __restrict__ streak, unsigned nblk_a) {
+  const bool learned = learned_accept(part, flag, fallbacks, streak, blockIdx.x == 0);
   T acc[NV];
 #pragma unroll
   for (int n = 0; n < NV; ++n) acc[n] = T(0);
@@ -548,10 +562,12 @@ __global__ __launch_bounds__(kBlock) void vup_sel_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
     const T* __restrict__ e, const T* b, Diag<T> dinv, T omega, const T* __restrict__ r,
-    const T* __restrict__ x_m, const T* __restrict__ r_m, const int* __restrict__ flag, T* y) {
+    const T* __restrict__ x_m, const T* __restrict__ r_m, const int* __restrict__ flag, int* streak, T* y) {
   constexpr int RPB = kBlock / G;
   const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
+  if (blockIdx.x == 0 && threadIdx.x == 0)  // consecutive rejections (read by the next cycle)
+    streak[0] = flag[0] ? 0 : (streak[0] < kLearnedStreak ? streak[0] + 1 : kLearnedStreak);
   if (row >= n) return;
   T ap[NV], pe[NV], x0[NV], rr[NV];
   T wd = T(0);

@@ -156,7 +156,9 @@ __device__ __forceinline__ float node_input(int64_t node, int k, const int32_t* 
 template <int D, bool PER_DOF, typename T>
 __global__ __launch_bounds__(256) void mlp_infer_kernel(int64_t n_nodes, const int32_t* __restrict__ nbr,
                                                          const T* __restrict__ b, const T* __restrict__ dinv,
-                                                         MlpW w, T* __restrict__ x) {
+                                                         MlpW w, T* __restrict__ x,
+                                                         const int* __restrict__ streak = nullptr, int limit = 0) {
+  if (streak && streak[0] >= limit) return;  // the solver stopped trying the network
   using M = MlpDims<D>;
   const int lane = threadIdx.x % 64, n = lane % 16, q = lane / 16;
   const int64_t ntiles = (n_nodes + 15) / 16, nwaves = int64_t(gridDim.x) * 4;
