@@ -240,7 +240,9 @@ fsi_status fsi_get_aggregates(fsi_ctx* ctx, int which, int level, int32_t* agg, 
  * W1: K x 64, W2: 64 x 64, W3: 64 x d, row-major FP32 at the ABI, stored and
  * applied in BF16 with FP32 accumulation (matrix cores).  If the network's
  * correction x gives ||b - A x|| > ||b|| the Jacobi sweep is used instead
- * (counted in fsi_solve_info.mlp_fallbacks).  Requires layout.node_ijk.
+ * (counted in fsi_solve_info.mlp_fallbacks); after 8 consecutive such cycles
+ * the network is not tried again until the next fsi_solve, new weights or
+ * training (those cycles count as fallbacks too).  Requires layout.node_ijk.
  * `which` is FSI_H_M or FSI_H_SIG. */
 /* Training losses.  FSI_MLP_LOSS_L2: (1/n) sum_i w_i ||delta_i - e_i||^2
  * against the exact corrections e = A^{-1} b (w_i: node's diagonal relative
