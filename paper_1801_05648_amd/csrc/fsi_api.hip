@@ -281,6 +281,16 @@ inline unsigned grid_for(int64_t n, int per_block) {
   return unsigned(std::max<int64_t>(1, std::min<int64_t>(g, int64_t(1) << 30)));
 }
 
+// X = Ainv B with the dense coarsest inverse: a workgroup per row from 768
+// rows on (at least three entries per lane), else a wavefront per row.
+template <typename TI, typename TO, int NV>
+void dense_gemv(int64_t n, const double* Ainv, const TI* B, TO* X, hipStream_t s) {
+  if (n >= 768)
+    dense_gemv_kernel<TI, TO, NV, kBlock / 64><<<grid_for(n, 1), kBlock, 0, s>>>(n, Ainv, B, X);
+  else
+    dense_gemv_kernel<TI, TO, NV, 1><<<grid_for(n, kBlock / 64), kBlock, 0, s>>>(n, Ainv, B, X);
+}
+
 template <class F>
 void with_group(int G, F&& f) {
   switch (G) {
@@ -752,7 +762,7 @@ void vcycle_rec(DHier<T>& H, int l, const T* b, T* out, hipStream_t s, bool plai
   const int L = int(H.lev.size()) - 1;
   if (l == L) {
     const int64_t n = H.nc;
-    dense_gemv_kernel<T, T, NV><<<grid_for(n, kBlock / 64), kBlock, 0, s>>>(n, H.cinv->template as<double>(), b, out);
+    dense_gemv<T, T, NV>(n, H.cinv->template as<double>(), b, out, s);
     return;
   }
   DLevel<T>& d = H.lev[l];
@@ -1850,7 +1860,7 @@ struct EnergyWork {
 template <typename T, int NV>
 void coarse_solve(DHier<T>& H, const T* rc, T* cc, T* t, T* t2, int cycles, hipStream_t s) {
   if (H.lev.size() == 2) {
-    dense_gemv_kernel<T, T, NV><<<grid_for(H.nc, kBlock / 64), kBlock, 0, s>>>(H.nc, H.cinv->template as<double>(), rc, cc);
+    dense_gemv<T, T, NV>(H.nc, H.cinv->template as<double>(), rc, cc, s);
     return;
   }
   DLevel<T>& d1 = H.lev[1];

@@ -763,38 +763,60 @@ __global__ __launch_bounds__(kBlock) void cheb_prolong_kernel(
 }
 
 // -------------------------------------------------------------- coarse solve
-// X = Ainv B with a dense row-major n x n inverse (FP64); one wavefront per
-// row; B, X hold NV interleaved columns.  X must not alias B.
-template <typename TI, typename TO, int NV>
+// X = Ainv B with a dense row-major n x n inverse (FP64); WPR wavefronts per
+// row (one for short rows; four, the whole workgroup, for long ones, so each
+// lane's chain of dependent loads stays short); B, X hold NV interleaved
+// columns.  X must not alias B.
+template <typename TI, typename TO, int NV, int WPR = 1>
 __global__ __launch_bounds__(kBlock) void dense_gemv_kernel(int64_t n, const double* __restrict__ Ainv,
                                                              const TI* __restrict__ B, TO* __restrict__ X) {
-  const int64_t row = int64_t(blockIdx.x) * (kBlock / 64) + threadIdx.x / 64;
-  const int lane = threadIdx.x % 64;
-  if (row >= n) return;
+  constexpr int LPR = 64 * WPR;  // lanes per row
+  const int64_t row = int64_t(blockIdx.x) * (kBlock / LPR) + threadIdx.x / LPR;
+  const int lane = threadIdx.x % LPR;
+  const bool valid = row < n;  // uniform per row (WPR > 1: one row per workgroup)
+  if (WPR == 1 && !valid) return;
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-  const double* a = Ainv + row * n;
-  int64_t j = lane;
-  for (; j + 192 < n; j += 256) {  // four independent loads in flight per lane
-    const double a0 = a[j], a1 = a[j + 64], a2 = a[j + 128], a3 = a[j + 192];
+  if (valid) {
+    const double* a = Ainv + row * n;
+    int64_t j = lane;
+    for (; j + 3 * LPR < n; j += 4 * LPR) {  // four independent loads in flight per lane
+      const double a0 = a[j], a1 = a[j + LPR], a2 = a[j + 2 * LPR], a3 = a[j + 3 * LPR];
 #pragma unroll
-    for (int v = 0; v < NV; ++v)
-      acc[v] += (a0 * double(B[j * NV + v]) + a1 * double(B[(j + 64) * NV + v])) +
-                (a2 * double(B[(j + 128) * NV + v]) + a3 * double(B[(j + 192) * NV + v]));
-  }
-  for (; j < n; j += 64) {
-    const double aj = a[j];
+      for (int v = 0; v < NV; ++v)
+        acc[v] += (a0 * double(B[j * NV + v]) + a1 * double(B[(j + LPR) * NV + v])) +
+                  (a2 * double(B[(j + 2 * LPR) * NV + v]) + a3 * double(B[(j + 3 * LPR) * NV + v]));
+    }
+    for (; j < n; j += LPR) {
+      const double aj = a[j];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] += aj * double(B[j * NV + v]);
+      for (int v = 0; v < NV; ++v) acc[v] += aj * double(B[j * NV + v]);
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1)
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] += __shfl_xor(acc[v], off, 64);
-  if (lane == 0)
+  if constexpr (WPR > 1) {
+    __shared__ double red[WPR][NV];
+    if (threadIdx.x % 64 == 0)
 #pragma unroll
-    for (int v = 0; v < NV; ++v) X[row * NV + v] = TO(acc[v]);
+      for (int v = 0; v < NV; ++v) red[threadIdx.x / 64][v] = acc[v];
+    __syncthreads();
+    if (threadIdx.x == 0 && valid)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < WPR; ++w) t += red[w][v];
+        X[row * NV + v] = TO(t);
+      }
+  } else {
+    if (lane == 0)
+#pragma unroll
+      for (int v = 0; v < NV; ++v) X[row * NV + v] = TO(acc[v]);
+  }
 }
 
 // -------------------------------------------------------------- vector ops
