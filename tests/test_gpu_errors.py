@@ -117,6 +117,21 @@ def test_call_order_and_argument_checks():
     with pytest.raises(FsiError) as e:
         s.build_precond("f64", cheb_degree=3, cheb=("H_A",))
     assert e.value.name == "FSI_ERR_ARG"
+    # an unknown precision code is refused (the three known: FP64, FP32, FP32 + BF16 diagonals)
+    import ctypes
+    from paper_1801_05648_amd import fsi as F
+    o = F.CPrecondOpts()
+    s.lib.fsi_default_precond_opts(ctypes.byref(o))
+    o.precision = 7
+    assert F.STATUS[s.lib.fsi_build_precond(s.ctx, ctypes.byref(o))] == "FSI_ERR_ARG"
     _, info = s.solve(_dev(sysm.b))  # the failed calls left the preconditioner in place
     assert info.converged
+    assert s.spmv_bytes() > 0
     s.close()
+    # queries before the system is set up
+    ctx = ctypes.c_void_p()
+    assert F.STATUS[F.load().fsi_create(ctypes.byref(ctx), 0, None)] == "FSI_OK"
+    b = ctypes.c_double()
+    assert F.STATUS[F.load().fsi_spmv_bytes(ctx, ctypes.byref(b))] == "FSI_ERR_STATE"
+    assert F.STATUS[F.load().fsi_spmv_bytes(ctx, None)] == "FSI_ERR_STATE"
+    F.load().fsi_destroy(ctx)
