@@ -1184,8 +1184,11 @@ void ensure_krylov(fsi_ctx& c, int m) {
   c.V.alloc(sizeof(double) * size_t(m + 1) * c.N);
   c.Z.alloc(sizeof(double) * size_t(m) * c.N);
   // Gram-Schmidt blocks: about four elements per thread (one reduction per
-  // tile of vectors is shared by more elements), at most kGsBlocks
-  c.gs_blocks = int(std::min<int64_t>(kGsBlocks, std::max<int64_t>(64, (c.N + 4 * kBlock - 1) / (4 * kBlock))));
+  // tile of vectors is shared by more elements), two below 2^19 rows (more
+  // blocks in flight on the smaller systems; measured on the 2D and 3D
+  // workloads), at most kGsBlocks
+  const int64_t per = c.N < (int64_t(1) << 19) ? 2 : 4;
+  c.gs_blocks = int(std::min<int64_t>(kGsBlocks, std::max<int64_t>(64, (c.N + per * kBlock - 1) / (per * kBlock))));
   c.part.alloc(sizeof(double) * size_t(kGsBlocks) * (m + 2));
   c.dh.alloc(sizeof(double) * 2 * size_t(3 * (m + 2)));
   c.dy.alloc(sizeof(double) * size_t(m + 1));
