@@ -58,7 +58,7 @@ def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
     try:
         bs = blocks.BlockSystem(sysm)
         t0 = time.perf_counter()
-        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse)
+        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=args.schur)
         t_setup = time.perf_counter() - t0
         cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
         poly = {h: (args.poly_degree, args.poly_ratio) for h in poly_on(args)}
@@ -95,6 +95,7 @@ def poly_on(args) -> tuple:
 def precond_name(args) -> str:
     poly = poly_on(args)
     ptxt = f"; {'/'.join(poly)} by {args.poly_degree} Chebyshev steps alone" if poly else ""
+    ptxt += f"; S_p {args.schur.upper()}"
     if args.cheb <= 0:
         return "block-LDU + SA-AMG V(1,1) Jacobi" + ptxt
     on = cheb_on(args)
@@ -137,7 +138,7 @@ def learned_run(args, cfg):
     solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio)
+                             poly_ratio=args.poly_ratio, schur=args.schur)
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -151,7 +152,7 @@ def learned_run(args, cfg):
             solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio)
+                             poly_ratio=args.poly_ratio, schur=args.schur)
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -169,7 +170,7 @@ def learned_run(args, cfg):
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio)
+                             poly_ratio=args.poly_ratio, schur=args.schur)
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -242,6 +243,9 @@ def main():
     ap.add_argument("--poly-on", default=None,
                     help="comma-separated hierarchies inverted by Chebyshev steps alone "
                          "(default H_MS, none with --learned)")
+    ap.add_argument("--schur", default=None, choices=["simple", "simplec"],
+                    help="pressure Schur approximation -D W^{-1} G: W = diag(A_f) (simple) or its "
+                         "absolute row sums (simplec); default simple in 2D, simplec in 3D")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
@@ -283,6 +287,11 @@ def main():
         # two steps suffice for the 2D Q2 mass matrix (measured 23.4 vs 24.1 ms
         # on the 256x64 system); the 3D one needs three (46 vs 78 iterations)
         args.poly_degree = 2 if cfg.dim == 2 else 3
+    if args.schur is None:
+        # the 3D Oseen block does better with the absolute row sums (64x16x16:
+        # 36 vs 46 iterations, 72.8 vs 93.8 ms); the 2D one with its diagonal
+        # (256x64: 39 vs 69 iterations in the oracle)
+        args.schur = "simple" if cfg.dim == 2 else "simplec"
     if args.cheb_on is None:
         # the 2D pressure Schur approximation does best with Jacobi sweeps
         # (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one
@@ -303,7 +312,7 @@ def main():
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args), poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio)
+                             poly_ratio=args.poly_ratio, schur=args.schur)
         hn = args.pmc_vcycle
         nv = int(solver.hierarchy_info(hn)[0][0]) * (sysm.dim if hn == "H_M" else 1)
         bv = torch.randn(nv, dtype=torch.float64, device=dev)
@@ -346,7 +355,7 @@ def main():
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio)
+                             poly_ratio=args.poly_ratio, schur=args.schur)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")

@@ -124,9 +124,14 @@ typedef struct {
                           whose D^{-1} M_s has a bounded spectrum), on
                           [lam/poly_ratio, lam]; H_A is rejected               */
   int32_t poly_degree; /* 2..16 (default 3); k - 1 launches per inverse        */
-  int32_t pad;
+  int32_t schur;       /* pressure Schur approximation S_p = -D W^{-1} G of the
+                          fluid step (Section 4.4): FSI_SCHUR_SIMPLE (default),
+                          W = diag(A_f); FSI_SCHUR_SIMPLEC, W = the absolute
+                          row sums of A_f                                      */
   double poly_ratio;   /* > 1 (default 8)                                       */
 } fsi_precond_opts;
+
+enum { FSI_SCHUR_SIMPLE = 0, FSI_SCHUR_SIMPLEC = 1 };
 
 typedef struct {
   double tol;       /* stop when ||b - A_h x||_2 <= tol ||b||_2 (default 1e-8)  */

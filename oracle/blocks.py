@@ -101,16 +101,25 @@ class BlockSystem:
         m.sort_indices()
         return m
 
-    def fluid_schur(self) -> sp.csr_matrix:
-        """S_p = -D diag(A_f)^{-1} G (SIMPLE-type pressure Schur approximation).
+    def fluid_schur(self, variant: str = "simple") -> sp.csr_matrix:
+        """S_p = -D W^{-1} G, a pressure Schur approximation.
 
         The paper applies to the fluid block the same Schur-complement
         elimination as for the solid (Section 4.4) without stating the
         approximation; this is the reading recorded in the design notes.
-        Pinned: equals the exact Schur complement -D A_f^{-1} G when A_f is
-        diagonal (test), and is symmetric because G = -D^T.
+        variant "simple": W = diag(A_f) (SIMPLE); "simplec": W = the diagonal
+        of the absolute row sums sum_j |a_ij| of A_f (SIMPLEC, one of the
+        alternatives the paper lists as open).
+        Pinned: both equal the exact Schur complement -D A_f^{-1} G when A_f is
+        diagonal with a positive diagonal (test), and are symmetric because
+        G = -D^T.
         """
-        dinv = 1.0 / self.A_f.diagonal()
+        if variant == "simple":
+            dinv = 1.0 / self.A_f.diagonal()
+        elif variant == "simplec":
+            dinv = 1.0 / np.asarray(abs(self.A_f).sum(axis=1)).ravel()
+        else:
+            raise ValueError(f"unknown Schur variant {variant!r}")
         m = (-(self.D @ sp.diags(dinv) @ self.G)).tocsr()
         if self.F_pp.nnz:
             m = (m + self.F_pp).tocsr()

@@ -33,8 +33,9 @@ H_NAMES = ("H_M", "H_SIG", "H_MS", "H_A", "H_P")
 
 
 def build_hierarchies(bs: BlockSystem, eps0=amg.EPS0, max_coarse=amg.MAX_COARSE,
-                      max_levels=amg.MAX_LEVELS) -> dict:
-    """The five SA hierarchies of the preconditioner."""
+                      max_levels=amg.MAX_LEVELS, schur: str = "simple") -> dict:
+    """The five SA hierarchies of the preconditioner (`schur`: the pressure
+    Schur approximation, see BlockSystem.fluid_schur)."""
     d = bs.dim
     sysm = bs.sys
     o = sysm.offsets
@@ -48,7 +49,7 @@ def build_hierarchies(bs: BlockSystem, eps0=amg.EPS0, max_coarse=amg.MAX_COARSE,
         "H_SIG": amg.setup(bs.solid_schur(), d, amg.rigid_body_modes(xyz), **kw),
         "H_MS": amg.setup(bs.S_uu, 1, amg.constant_modes(bs.n_vs), **kw),
         "H_A": amg.setup(bs.A_f, d, amg.translation_modes(bs.n_vf // d, d), **kw),
-        "H_P": amg.setup(bs.fluid_schur(), 1, amg.constant_modes(bs.n_p), **kw),
+        "H_P": amg.setup(bs.fluid_schur(schur), 1, amg.constant_modes(bs.n_p), **kw),
     }
     return H
 

@@ -2078,6 +2078,7 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->cheb_mask = (1 << FSI_H_MS) | (1 << FSI_H_SIG) | (1 << FSI_H_P);
   o->poly_mask = 0;
   o->poly_degree = 3;
+  o->schur = FSI_SCHUR_SIMPLE;
   o->poly_ratio = 8.0;
 }
 
@@ -2253,6 +2254,8 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     if (opts) o = *opts;
     if (o.precision != FSI_P_F64 && o.precision != FSI_P_F32 && o.precision != FSI_P_F32_BF16DIAG)
       throw Error(FSI_ERR_ARG, "unknown precision");
+    if (o.schur != FSI_SCHUR_SIMPLE && o.schur != FSI_SCHUR_SIMPLEC)
+      throw Error(FSI_ERR_ARG, "unknown pressure Schur approximation");
     if (o.max_coarse < 1 || o.max_levels < 1 || o.max_levels > 16 || !(o.strength0 >= 0.0))
       throw Error(FSI_ERR_ARG, "bad AMG options");
     if (o.cheb_degree < 0 || o.cheb_degree > 8 || (o.cheb_mask & ~0x1f) != 0)
@@ -2291,13 +2294,18 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     HCsr Af = sub_block(F, 0, c.n_vf, 0, c.n_vf);
     HCsr Dm = sub_block(F, c.n_vf, c.n_f, 0, c.n_vf);
     HCsr Gm = sub_block(F, 0, c.n_vf, c.n_vf, c.n_f);
-    HCsr Sp;  // -D diag(A_f)^{-1} G
+    HCsr Sp;  // -D W^{-1} G: W = diag(A_f) (SIMPLE) or its absolute row sums (SIMPLEC)
     {
       std::vector<double> dA = diagonal(Af);
       std::vector<double> dinv(dA.size());
       for (size_t i = 0; i < dA.size(); ++i) {
         if (dA[i] == 0.0) throw Error(FSI_ERR_NUMERIC, "zero diagonal in the fluid velocity block");
-        dinv[i] = 1.0 / dA[i];
+        double w = dA[i];
+        if (o.schur == FSI_SCHUR_SIMPLEC) {
+          w = 0.0;
+          for (int64_t k = Af.rp[i]; k < Af.rp[i + 1]; ++k) w += std::fabs(Af.v[k]);
+        }
+        dinv[i] = 1.0 / w;
       }
       HCsr Ds = Dm;
       scale_cols(Ds, dinv);

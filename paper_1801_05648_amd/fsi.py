@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libfsi.so")
 BLOCKS = ("M", "C_ms", "C_sm", "S", "C_sf", "C_fm", "C_fs", "F")
 HIERARCHIES = {"H_M": 0, "H_SIG": 1, "H_MS": 2, "H_A": 3, "H_P": 4}
 PRECISION = {"f64": 0, "f32": 1, "f32-bf16diag": 2}
+SCHUR = {"simple": 0, "simplec": 1}
 
 STATUS = {0: "FSI_OK", 1: "FSI_NOT_CONVERGED", -1: "FSI_ERR_ARG", -2: "FSI_ERR_CSR",
           -3: "FSI_ERR_STRUCT", -4: "FSI_ERR_HIP", -5: "FSI_ERR_OOM", -6: "FSI_ERR_NUMERIC",
@@ -50,7 +51,7 @@ class CPrecondOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("strength0", ctypes.c_double),
                 ("cheb_mask", ctypes.c_int32), ("poly_mask", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
-                ("pad", ctypes.c_int32), ("poly_ratio", ctypes.c_double)]
+                ("schur", ctypes.c_int32), ("poly_ratio", ctypes.c_double)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -264,14 +265,14 @@ class FsiSolver:
     # -- calls -----------------------------------------------------------------
     def build_precond(self, precision: str = "f64", max_coarse: int = 500, max_levels: int = 10,
                       strength0: float = 0.08, cheb_degree: int = 0, cheb=("H_MS", "H_SIG", "H_P"),
-                      poly=(), poly_degree: int = 3, poly_ratio: float = 8.0):
+                      poly=(), poly_degree: int = 3, poly_ratio: float = 8.0, schur: str = "simple"):
         def mask_of(names):
             m = 0
             for name in names:
                 m |= 1 << HIERARCHIES[name]
             return m
         o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, int(cheb_degree), strength0, mask_of(cheb),
-                         mask_of(poly), int(poly_degree), 0, float(poly_ratio))
+                         mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio))
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,

@@ -411,7 +411,9 @@ def test_bench_configuration_full_size_matches_oracle():
 def test_3d_bench_configuration_matches_oracle():
     """The 3D benchmark preconditioner (Chebyshev(4) V-cycles on H_SIG and H_P,
     M_s by three Chebyshev steps, 2000-row coarse grids; grouped H_A levels,
-    the mesh level restricting apart) on the 32x8x8-cell system: the GPU
+    the mesh level restricting apart) with the SIMPLE pressure Schur
+    approximation (the SIMPLEC default is checked by
+    test_simplec_pressure_schur_matches_oracle) on the 32x8x8-cell system: the GPU
     solution reaches 1e-8 by the oracle's own mat-vec, takes the oracle's
     iteration count within 3, and agrees with the oracle FGMRES (same
     options, solved to 1e-10) within 1e-6 (measured 3.6e-8, 25 iterations
@@ -433,6 +435,37 @@ def test_3d_bench_configuration_matches_oracle():
     err = _rel(xg, xo)
     print(f"m3 3D bench config: GPU {info.iters} it, oracle {it8} it at 1e-8, true resid {r:.2e}, "
           f"rel. diff to the 1e-10 oracle solution {err:.2e}")
+    assert info.converged and r <= 1e-8 * 1.001
+    assert abs(info.iters - it8) <= 3
+    assert err <= 1e-6
+
+
+def test_simplec_pressure_schur_matches_oracle():
+    """The SIMPLEC pressure Schur approximation as the library builds it (the
+    finest matrix of H_P) against the oracle's, and a 3D solve with it (the
+    benchmark's 3D preconditioner otherwise) against the oracle FGMRES."""
+    import scipy.sparse as sp
+    from oracle import blocks, krylov, precond
+    from paper_1801_05648_amd import FsiSolver
+    sysm = system("m3")
+    bs = blocks.BlockSystem(sysm)
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f64", max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3,
+                    schur="simplec")
+    nr, nc, rp, ci, v = s.get_level("H_P", 0, "A")
+    Sl = sp.csr_matrix((v, ci, rp), shape=(nr, nc))
+    So = bs.fluid_schur("simplec")
+    assert abs(Sl - So).max() <= 1e-13 * abs(So).max()
+    x, info = s.solve(_dev(sysm.b), tol=1e-8)
+    s.close()
+    xg = x.cpu().numpy()
+    r = np.linalg.norm(sysm.b - bs.matvec(xg)) / np.linalg.norm(sysm.b)
+    H = precond.build_hierarchies(bs, max_coarse=2000, schur="simplec")
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4, "H_P": 4}, poly={"H_MS": (3, 8.0)})
+    it8 = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-8, restart=50, maxit=500)[1].iters
+    xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-10, restart=50, maxit=500)
+    err = _rel(xg, xo)
+    print(f"m3 SIMPLEC: GPU {info.iters} it, oracle {it8} it at 1e-8, rel. diff {err:.2e}")
     assert info.converged and r <= 1e-8 * 1.001
     assert abs(info.iters - it8) <= 3
     assert err <= 1e-6

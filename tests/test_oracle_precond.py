@@ -143,6 +143,32 @@ def test_pressure_schur_approximation():
     assert np.all(dA > 0)
 
 
+def test_simplec_pressure_schur_approximation():
+    """SIMPLEC weights by the absolute row sums of A_f, which dominate its
+    (positive) diagonal: the result is SPD, lies below the SIMPLE one in the
+    Loewner order (S_simple - S_simplec = D (W_s^{-1} - W_c^{-1}) D^T >= 0), and
+    with a diagonal A_f both are the exact Schur complement -D A_f^{-1} G."""
+    import copy
+    import scipy.sparse as sp
+    bs = _bs("c1")
+    Ss = bs.fluid_schur("simple").toarray()
+    Sc = bs.fluid_schur("simplec").toarray()
+    assert np.abs(Sc - Sc.T).max() <= 1e-12 * np.abs(Sc).max()
+    np.linalg.cholesky(Sc)
+    ev = np.linalg.eigvalsh(Ss - Sc)
+    assert ev.min() >= -1e-10 * np.abs(ev).max()
+    assert np.abs(Ss - Sc).max() > 1e-6 * np.abs(Ss).max()  # the weights do differ here
+    bd = copy.copy(bs)
+    rng = np.random.default_rng(9)
+    bd.A_f = sp.diags(rng.uniform(1.0, 2.0, bs.n_vf)).tocsr()
+    exact = -bs.D.toarray() @ np.linalg.solve(bd.A_f.toarray(), bs.G.toarray())
+    for variant in ("simple", "simplec"):
+        S = bd.fluid_schur(variant).toarray()
+        assert np.allclose(S, exact, rtol=1e-12, atol=1e-12 * np.abs(exact).max()), variant
+    with pytest.raises(ValueError):
+        bs.fluid_schur("lsc")
+
+
 def test_mesh_inverse_per_component():
     bs = _bs("c1")
     L = bs.mesh_scalar()
