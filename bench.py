@@ -245,7 +245,7 @@ def main():
                          "(default H_MS, none with --learned)")
     ap.add_argument("--schur", default=None, choices=["simple", "simplec"],
                     help="pressure Schur approximation -D W^{-1} G: W = diag(A_f) (simple) or its "
-                         "absolute row sums (simplec); default simple in 2D, simplec in 3D")
+                         "absolute row sums (simplec); default simple")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
@@ -288,10 +288,10 @@ def main():
         # on the 256x64 system); the 3D one needs three (46 vs 78 iterations)
         args.poly_degree = 2 if cfg.dim == 2 else 3
     if args.schur is None:
-        # the 3D Oseen block does better with the absolute row sums (64x16x16:
-        # 36 vs 46 iterations, 72.8 vs 93.8 ms); the 2D one with its diagonal
-        # (256x64: 39 vs 69 iterations in the oracle)
-        args.schur = "simple" if cfg.dim == 2 else "simplec"
+        # SIMPLE throughout: SIMPLEC (absolute row sums) cuts the 64x16x16
+        # solve from 46 to 36 iterations but raises the 128x32x32 one from 47
+        # to 68 and the 2D one from 39 to 69 (oracle), so it stays an option
+        args.schur = "simple"
     if args.cheb_on is None:
         # the 2D pressure Schur approximation does best with Jacobi sweeps
         # (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one

@@ -411,9 +411,8 @@ def test_bench_configuration_full_size_matches_oracle():
 def test_3d_bench_configuration_matches_oracle():
     """The 3D benchmark preconditioner (Chebyshev(4) V-cycles on H_SIG and H_P,
     M_s by three Chebyshev steps, 2000-row coarse grids; grouped H_A levels,
-    the mesh level restricting apart) with the SIMPLE pressure Schur
-    approximation (the SIMPLEC default is checked by
-    test_simplec_pressure_schur_matches_oracle) on the 32x8x8-cell system: the GPU
+    the mesh level restricting apart; the SIMPLE pressure Schur
+    approximation) on the 32x8x8-cell system: the GPU
     solution reaches 1e-8 by the oracle's own mat-vec, takes the oracle's
     iteration count within 3, and agrees with the oracle FGMRES (same
     options, solved to 1e-10) within 1e-6 (measured 3.6e-8, 25 iterations
@@ -441,9 +440,10 @@ def test_3d_bench_configuration_matches_oracle():
 
 
 def test_simplec_pressure_schur_matches_oracle():
-    """The SIMPLEC pressure Schur approximation as the library builds it (the
-    finest matrix of H_P) against the oracle's, and a 3D solve with it (the
-    benchmark's 3D preconditioner otherwise) against the oracle FGMRES."""
+    """The SIMPLEC pressure Schur approximation (an option) as the library
+    builds it (the finest matrix of H_P) against the oracle's, and a 3D solve
+    with it (the benchmark's 3D preconditioner otherwise) against the oracle
+    FGMRES."""
     import scipy.sparse as sp
     from oracle import blocks, krylov, precond
     from paper_1801_05648_amd import FsiSolver
