@@ -21,13 +21,20 @@ with the approximate inverses
   F = [[A_f, G], [D, 0]] with the pressure Schur approximation
   S_p = -D diag(A_f)^{-1} G (Section 4.4, reading in the design notes):
       y = V_A(r_v);  x_p = V_p(r_p - D y);  x_v = V_A(r_v - G x_p).
+  Optionally (the paper's choice for the fluid sub-problem, Section 4.4) F^{-1}
+  is k steps of flexible GMRES on F from zero, right-preconditioned by that
+  Uzawa-like step (fluid_gmres_solve).
 """
 from __future__ import annotations
 
 import numpy as np
 
-from . import amg
+from . import amg, krylov
 from .blocks import BlockSystem
+
+# Inner GMRES of the fluid step: it stops before k steps only when its
+# residual estimate falls to this fraction of ||r_f|| (an exact solve).
+INNER_TOL = 1e-14
 
 H_NAMES = ("H_M", "H_SIG", "H_MS", "H_A", "H_P")
 
@@ -104,6 +111,20 @@ def fluid_schur_solve(bs: BlockSystem, a_inv, p_inv, r_f: np.ndarray) -> np.ndar
     return np.concatenate([x_v, x_p])
 
 
+def fluid_gmres_solve(bs: BlockSystem, uzawa, r_f: np.ndarray, k: int) -> np.ndarray:
+    """F^{-1} r_f as k steps of flexible GMRES on F = [[A_f, G], [D, 0]] from
+    x = 0, right-preconditioned by `uzawa` (the Uzawa-like step): the fluid
+    sub-problem solved by AMG-preconditioned GMRES (Section 4.4; the step
+    count k is a parameter, the paper does not state one).  The result
+    minimises ||r_f - F x|| over x in span{uzawa(v_1), ..., uzawa(v_k)} of the
+    Arnoldi vectors v_j."""
+    if k < 1:
+        raise ValueError("inner GMRES needs k >= 1 steps")
+    F = bs.B["F"]
+    x, _ = krylov.fgmres(lambda v: F @ v, uzawa, r_f, tol=INNER_TOL, restart=k, maxit=k)
+    return x
+
+
 def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
     """M^{-1} r_m with M = L (x) I_d: the scalar inverse per component."""
     d = bs.dim
@@ -113,12 +134,15 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
     return x
 
 
-def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None) -> BlockLDU:
+def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None,
+                       fluid_inner: int = 0) -> BlockLDU:
     """The preconditioner of the hot path: every inverse one V(1,1) cycle
     (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
     named in `cheb`).  For the names in `poly`, {name: (k, ratio)}, the
     inverse is instead k Chebyshev steps alone on the finest matrix (no coarse
-    grid), on [lam/ratio, lam] with lam = 1.1 rho of that level."""
+    grid), on [lam/ratio, lam] with lam = 1.1 rho of that level.  With
+    fluid_inner = k > 0 the fluid inverse is k inner GMRES steps
+    preconditioned by the Uzawa-like step (fluid_gmres_solve)."""
     cheb = cheb or {}
     poly = poly or {}
 
@@ -135,5 +159,8 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     V = {k: inv(k, h) for k, h in H.items()}
     mesh = lambda r: mesh_solve(bs, V["H_M"], r)
     solid = lambda r: solid_schur_solve(bs, V["H_MS"], V["H_SIG"], r)
-    fluid = lambda r: fluid_schur_solve(bs, V["H_A"], V["H_P"], r)
+    uzawa = lambda r: fluid_schur_solve(bs, V["H_A"], V["H_P"], r)
+    fluid = uzawa
+    if fluid_inner > 0:
+        fluid = lambda r: fluid_gmres_solve(bs, uzawa, r, fluid_inner)
     return BlockLDU(bs, mesh, solid, fluid)
