@@ -62,7 +62,7 @@ def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
         t_setup = time.perf_counter() - t0
         cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
         poly = {h: (args.poly_degree, args.poly_ratio) for h in poly_on(args)}
-        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly)
+        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=args.fluid_inner)
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
         t_iter = (time.perf_counter() - t0) / max(info.iters, 1)
@@ -96,6 +96,8 @@ def precond_name(args) -> str:
     poly = poly_on(args)
     ptxt = f"; {'/'.join(poly)} by {args.poly_degree} Chebyshev steps alone" if poly else ""
     ptxt += f"; S_p {args.schur.upper()}"
+    if args.fluid_inner > 0:
+        ptxt += f"; F^-1 by {args.fluid_inner} inner GMRES steps"
     if args.cheb <= 0:
         return "block-LDU + SA-AMG V(1,1) Jacobi" + ptxt
     on = cheb_on(args)
@@ -138,7 +140,8 @@ def learned_run(args, cfg):
     solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur)
+                             poly_ratio=args.poly_ratio, schur=args.schur,
+                             fluid_inner=args.fluid_inner)
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -152,7 +155,8 @@ def learned_run(args, cfg):
             solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur)
+                             poly_ratio=args.poly_ratio, schur=args.schur,
+                             fluid_inner=args.fluid_inner)
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -170,7 +174,8 @@ def learned_run(args, cfg):
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur)
+                             poly_ratio=args.poly_ratio, schur=args.schur,
+                             fluid_inner=args.fluid_inner)
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -246,6 +251,9 @@ def main():
     ap.add_argument("--schur", default=None, choices=["simple", "simplec"],
                     help="pressure Schur approximation -D W^{-1} G: W = diag(A_f) (simple) or its "
                          "absolute row sums (simplec); default simple")
+    ap.add_argument("--fluid-inner", type=int, default=0,
+                    help="inner flexible GMRES steps for the fluid inverse, preconditioned by the "
+                         "Uzawa-like step (0: the Uzawa-like step alone)")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
@@ -312,7 +320,8 @@ def main():
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args), poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur)
+                             poly_ratio=args.poly_ratio, schur=args.schur,
+                             fluid_inner=args.fluid_inner)
         hn = args.pmc_vcycle
         nv = int(solver.hierarchy_info(hn)[0][0]) * (sysm.dim if hn == "H_M" else 1)
         bv = torch.randn(nv, dtype=torch.float64, device=dev)
@@ -355,7 +364,8 @@ def main():
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur)
+                             poly_ratio=args.poly_ratio, schur=args.schur,
+                             fluid_inner=args.fluid_inner)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")

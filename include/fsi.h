@@ -129,6 +129,15 @@ typedef struct {
                           W = diag(A_f); FSI_SCHUR_SIMPLEC, W = the absolute
                           row sums of A_f                                      */
   double poly_ratio;   /* > 1 (default 8)                                       */
+  int32_t fluid_inner; /* 0 (default): F^{-1} is the Uzawa-like step alone;
+                          k in 1..16: k steps of flexible GMRES on the fluid
+                          block F from zero, right-preconditioned by that step
+                          (the fluid sub-problem solved by AMG-preconditioned
+                          GMRES, Section 4.4), classical Gram-Schmidt with one
+                          reorthogonalisation, stopping early only at an exact
+                          solve; the outer FGMRES absorbs the nonlinearity.
+                          Stores F once more and 2k + 1 fluid vectors        */
+  int32_t pad;
 } fsi_precond_opts;
 
 enum { FSI_SCHUR_SIMPLE = 0, FSI_SCHUR_SIMPLEC = 1 };

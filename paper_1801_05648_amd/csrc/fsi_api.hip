@@ -882,6 +882,12 @@ struct Precond {
   DHier<T> H[FSI_NHIER];
   DCsr<T> S_vu, S_uv, Cfms, Csf, Cms, Dm, Gm;
   std::shared_ptr<DevBuf> tu, tu2, tv, tf, ta, ta2, tp, ts, ts2, tm, tm2, rT, zT;
+  // inner GMRES of the fluid step (inner_k > 0): F, Arnoldi vectors V
+  // ((k + 1) x n_f), preconditioned vectors Z (k x n_f), FP64 scalars
+  int inner_k = 0;
+  DCsr<T> Fm;
+  std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ikact;
+  int inner_nb = 1;
 
   void alloc_tmp() {
     auto mk = [](int64_t n) {
@@ -893,7 +899,22 @@ struct Precond {
     tf = mk(n_f); ta = mk(n_vf); ta2 = mk(n_vf); tp = mk(n_p);
     ts = mk(n_s); ts2 = mk(n_s); tm = mk(n_m); tm2 = mk(n_m);
     if (sizeof(T) != sizeof(double)) { rT = mk(N); zT = mk(N); }
+    if (inner_k > 0) {
+      iV = mk((inner_k + 1) * n_f);
+      iZ = mk(inner_k * n_f);
+      inner_nb = int(std::min<int64_t>(kInnerBlocks, std::max<int64_t>(1, (n_f + kBlock - 1) / kBlock)));
+      ipart = std::make_shared<DevBuf>();
+      ipart->alloc(sizeof(double) * (kInnerMax + 1) * inner_nb);
+      iscal = std::make_shared<DevBuf>();
+      iscal->alloc(sizeof(double) * kInnerScal);
+      ikact = std::make_shared<DevBuf>();
+      ikact->alloc(sizeof(int));
+    }
   }
+
+  // FP64 scalars of the inner GMRES: two Gram-Schmidt passes and a norm
+  // (kInnerMax + 2 each), beta, the Hessenberg matrix, y
+  static constexpr int kInnerScal = 3 * (kInnerMax + 2) + 1 + (kInnerMax + 1) * kInnerMax + kInnerMax;
 
   // Solid algorithm of Section 4.3 (u_s eliminated through Sigma_s):
   //   y = M_s^{-1} r_u;  x_v = Sigma_s^{-1} (r_v - S_vu y);  x_u = M_s^{-1} (r_u - S_uv x_v)
@@ -921,6 +942,54 @@ struct Precond {
     vcycle(H[FSI_H_A], ta2->as<T>(), z_f, s);
   }
 
+  // The fluid sub-problem solved by k steps of flexible GMRES on F from zero,
+  // right-preconditioned by the Uzawa-like step (Section 4.4): z_f minimises
+  // ||r_f - F z|| over the span of the preconditioned Arnoldi vectors.
+  // Classical Gram-Schmidt with one reorthogonalisation; every scalar stays
+  // on the device.
+  void inner_dots(int nv, const T* w, double* out, hipStream_t s) {
+    inner_dots_kernel<T><<<inner_nb, kBlock, 0, s>>>(n_f, nv, iV->as<T>(), n_f, w, ipart->as<double>());
+    gs_reduce_kernel<<<nv + 1, kBlock, 0, s>>>(inner_nb, 0, ipart->as<double>(), out);
+  }
+
+  void fluid_gmres(const T* r_f, T* z_f, hipStream_t s) {
+    const int k = inner_k;
+    const int64_t n = n_f;
+    const unsigned g = grid_for(n, kBlock * 4);
+    T* V = iV->as<T>();
+    T* Z = iZ->as<T>();
+    double* a1 = iscal->as<double>();
+    double* a2 = a1 + (kInnerMax + 2);
+    double* nn = a2 + (kInnerMax + 2);
+    double* beta = nn + (kInnerMax + 2);
+    double* Hm = beta + 1;
+    double* y = Hm + (kInnerMax + 1) * kInnerMax;
+    int* kact = ikact->as<int>();
+    inner_dots(0, r_f, nn, s);
+    inner_start_kernel<<<1, 1, 0, s>>>(nn, beta, kact, k);
+    inner_scale_kernel<T><<<g, kBlock, 0, s>>>(n, r_f, beta, kact, 0, V);
+    for (int j = 0; j < k; ++j) {
+      T* vj = V + int64_t(j) * n;
+      T* w = V + int64_t(j + 1) * n;
+      fluid(vj, Z + int64_t(j) * n, s);
+      spmv<T>(Fm, Z + int64_t(j) * n, w, s);
+      inner_dots(j + 1, w, a1, s);
+      inner_update_kernel<T><<<g, kBlock, 0, s>>>(n, j + 1, V, n, a1, w);
+      inner_dots(j + 1, w, a2, s);
+      inner_update_kernel<T><<<g, kBlock, 0, s>>>(n, j + 1, V, n, a2, w);
+      inner_dots(0, w, nn, s);
+      inner_column_kernel<<<1, 1, 0, s>>>(j, k, a1, a2, nn, Hm, kact);
+      inner_scale_kernel<T><<<g, kBlock, 0, s>>>(n, w, Hm + int64_t(j) * (k + 1) + j + 1, kact, j + 1, w);
+    }
+    inner_lsq_kernel<<<1, 1, 0, s>>>(k, Hm, beta, kact, y);
+    inner_combine_kernel<T><<<g, kBlock, 0, s>>>(n, k, Z, n, y, z_f);
+  }
+
+  void fluid_inverse(const T* r_f, T* z_f, hipStream_t s) {
+    if (inner_k > 0 && n_f > 0) fluid_gmres(r_f, z_f, s);
+    else fluid(r_f, z_f, s);
+  }
+
   // Block LDU algorithm of Section 4.1 ("Evaluation of P^{-1} r").
   void apply(const T* r, T* z, hipStream_t s) {
     const T* r_m = r;
@@ -932,7 +1001,7 @@ struct Precond {
     vcycle(H[FSI_H_M], r_m, z_m, s);                         // 1. x_m = M^{-1} r_m
     solid(r_s, z_s, s);                                      // 2. x_s = S^{-1} r_s
     spmv_sub<T>(Cfms, z, r_f, tf->as<T>(), s);               // 3. r_f - C_fm x_m - C_fs x_s
-    fluid(tf->as<T>(), z_f, s);                              //    x_f = F^{-1} (...)
+    fluid_inverse(tf->as<T>(), z_f, s);                      //    x_f = F^{-1} (...)
     spmv<T>(Csf, z_f, ts->as<T>(), s);                       // 4. x_s -= S^{-1} C_sf x_f
     solid(ts->as<T>(), ts2->as<T>(), s);
     vsub<T>(n_s, z_s, ts2->as<T>(), s);
@@ -986,6 +1055,7 @@ struct fsi_ctx {
   int gs_blocks = kGsBlocks;
   int cheb[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev degree per hierarchy (0: Jacobi)
   int poly[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev steps alone, no coarse grid (0: off)
+  int fluid_inner = 0;                     // inner GMRES steps of the fluid inverse (0: off)
   double poly_ratio = 8.0;
   SaHierarchy host_h[FSI_NHIER];
   std::unique_ptr<Precond<double>> p64;
@@ -1155,6 +1225,8 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     const int64_t bounds[3] = {0, c.n_vf, c.n_f};
     const int groups[2] = {c.d, 1};
     P->Cfms = upload_segments<T>(M, bounds, groups, 2, s);
+    P->inner_k = c.fluid_inner;
+    if (c.fluid_inner > 0) P->Fm = upload_segments<T>(c.blk[FSI_F], bounds, groups, 2, s);
   }
   P->alloc_tmp();
   HIP_TRY(hipStreamSynchronize(s));
@@ -2080,6 +2152,7 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->poly_degree = 3;
   o->schur = FSI_SCHUR_SIMPLE;
   o->poly_ratio = 8.0;
+  o->fluid_inner = 0;
 }
 
 void fsi_default_solve_opts(fsi_solve_opts* o) {
@@ -2256,6 +2329,8 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       throw Error(FSI_ERR_ARG, "unknown precision");
     if (o.schur != FSI_SCHUR_SIMPLE && o.schur != FSI_SCHUR_SIMPLEC)
       throw Error(FSI_ERR_ARG, "unknown pressure Schur approximation");
+    if (o.fluid_inner < 0 || o.fluid_inner > kInnerMax)
+      throw Error(FSI_ERR_ARG, "inner GMRES steps of the fluid inverse must be in 0..16");
     if (o.max_coarse < 1 || o.max_levels < 1 || o.max_levels > 16 || !(o.strength0 >= 0.0))
       throw Error(FSI_ERR_ARG, "bad AMG options");
     if (o.cheb_degree < 0 || o.cheb_degree > 8 || (o.cheb_mask & ~0x1f) != 0)
@@ -2334,6 +2409,7 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       c.cheb[h] = (c.poly[h] == 0 && o.cheb_degree > 0 && (o.cheb_mask >> h) & 1) ? o.cheb_degree : 0;
     }
     c.poly_ratio = o.poly_ratio;
+    c.fluid_inner = o.fluid_inner;
     c.precision = o.precision;  // before prepare_mlp: it decides which hierarchies can learn
     prepare_mlp(c);
     c.drop_graphs();

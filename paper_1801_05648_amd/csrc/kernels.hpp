@@ -1011,6 +1011,148 @@ __global__ __launch_bounds__(kBlock) void multi_axpy_kernel(int64_t n, int nv, c
   }
 }
 
+// ------------------------------------------------ inner GMRES of the fluid step
+// k <= kInnerMax steps of flexible GMRES on the fluid block (vectors in the
+// preconditioner's precision T, sums and the Hessenberg matrix in FP64, all
+// scalars kept on the device: no host round trip inside P^{-1}).
+constexpr int kInnerMax = 16;
+constexpr int kInnerBlocks = 512;
+
+// part[i * gridDim.x + block] = V_i . w for i < nv, part[nv * gridDim.x + block]
+// = w . w (block partial sums; gs_reduce_kernel adds them in block order).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void inner_dots_kernel(int64_t n, int nv, const T* __restrict__ V,
+                                                            int64_t ld, const T* __restrict__ w,
+                                                            double* __restrict__ part) {
+  __shared__ double sh[kWaves][kInnerMax + 1];
+  double acc[kInnerMax + 1];
+#pragma unroll
+  for (int i = 0; i <= kInnerMax; ++i) acc[i] = 0.0;
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock) {
+    const double wk = double(w[k]);
+#pragma unroll
+    for (int i = 0; i < kInnerMax; ++i)
+      if (i < nv) acc[i] += double(V[i * ld + k]) * wk;
+    acc[kInnerMax] += wk * wk;
+  }
+  const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
+#pragma unroll
+  for (int i = 0; i <= kInnerMax; ++i) {
+    if (i < nv || i == kInnerMax) {
+      const double t = wave_sum(acc[i]);
+      if (lane == 0) sh[wid][i < nv ? i : kInnerMax] = t;
+    }
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t <= nv) {
+    const int slot = t < nv ? t : kInnerMax;
+    double v = 0.0;
+    for (int q = 0; q < kWaves; ++q) v += sh[q][slot];
+    part[int64_t(t) * gridDim.x + blockIdx.x] = v;
+  }
+}
+
+// w -= sum_{i < nv} h_i V_i
+template <typename T>
+__global__ __launch_bounds__(kBlock) void inner_update_kernel(int64_t n, int nv, const T* __restrict__ V,
+                                                              int64_t ld, const double* __restrict__ h,
+                                                              T* __restrict__ w) {
+  __shared__ double hs[kInnerMax];
+  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock) {
+    double s = double(w[k]);
+    for (int i = 0; i < nv; ++i) s -= hs[i] * double(V[i * ld + k]);
+    w[k] = T(s);
+  }
+}
+
+// Start: st[0] = beta = ||r|| (from rr[0] = r . r), kact[0] = k (0 when r = 0).
+__global__ void inner_start_kernel(const double* __restrict__ rr, double* __restrict__ st,
+                                   int* __restrict__ kact, int k) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double b = sqrt(rr[0] > 0.0 ? rr[0] : 0.0);
+  st[0] = b;
+  kact[0] = b > 0.0 ? k : 0;
+}
+
+// Column j of the Hessenberg matrix (column-major, leading dimension k + 1)
+// from the two Gram-Schmidt passes a1, a2 (a1[j + 1] = ||w||^2 before them)
+// and the final squared norm nn[0]; a breakdown (an exact solve in the
+// current space) truncates the step count to j + 1.
+__global__ void inner_column_kernel(int j, int k, const double* __restrict__ a1, const double* __restrict__ a2,
+                                    const double* __restrict__ nn, double* __restrict__ H,
+                                    int* __restrict__ kact) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double* col = H + int64_t(j) * (k + 1);
+  for (int i = 0; i <= j; ++i) col[i] = a1[i] + a2[i];
+  const double hn = sqrt(nn[0] > 0.0 ? nn[0] : 0.0);
+  const double wb = sqrt(a1[j + 1] > 0.0 ? a1[j + 1] : 0.0);
+  col[j + 1] = hn;
+  if (!(hn > 1e-14 * wb) && kact[0] > j + 1) kact[0] = j + 1;
+}
+
+// y = x / s[0] (0 when s[0] is 0 or the step is past a breakdown); y may be x
+template <typename T>
+__global__ __launch_bounds__(kBlock) void inner_scale_kernel(int64_t n, const T* x,
+                                                             const double* __restrict__ s,
+                                                             const int* __restrict__ kact, int j, T* y) {
+  const double d = s[0];
+  const double f = (d > 0.0 && kact[0] > j) ? 1.0 / d : 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    y[i] = T(double(x[i]) * f);
+}
+
+// Least squares min ||beta e_1 - Hbar y|| over the first kact columns by
+// Givens rotations and back substitution; y_j = 0 for j >= kact.
+__global__ void inner_lsq_kernel(int k, const double* __restrict__ H, const double* __restrict__ st,
+                                 const int* __restrict__ kact, double* __restrict__ y) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double R[kInnerMax + 1][kInnerMax];
+  double g[kInnerMax + 1], cs[kInnerMax], sn[kInnerMax];
+  const int m = kact[0] < k ? kact[0] : k;
+  for (int j = 0; j <= k; ++j) g[j] = 0.0;
+  g[0] = st[0];
+  for (int j = 0; j < m; ++j) {
+    for (int i = 0; i <= j + 1; ++i) R[i][j] = H[int64_t(j) * (k + 1) + i];
+    for (int i = 0; i < j; ++i) {
+      const double a = R[i][j], b = R[i + 1][j];
+      R[i][j] = cs[i] * a + sn[i] * b;
+      R[i + 1][j] = -sn[i] * a + cs[i] * b;
+    }
+    const double a = R[j][j], b = R[j + 1][j];
+    const double r = sqrt(a * a + b * b);
+    cs[j] = r > 0.0 ? a / r : 1.0;
+    sn[j] = r > 0.0 ? b / r : 0.0;
+    R[j][j] = r;
+    R[j + 1][j] = 0.0;
+    g[j + 1] = -sn[j] * g[j];
+    g[j] = cs[j] * g[j];
+  }
+  for (int j = k - 1; j >= 0; --j) {
+    if (j >= m) { y[j] = 0.0; continue; }
+    double t = g[j];
+    for (int i = j + 1; i < m; ++i) t -= R[j][i] * y[i];
+    y[j] = R[j][j] != 0.0 ? t / R[j][j] : 0.0;
+  }
+}
+
+// z = sum_{i < nv} y_i Z_i
+template <typename T>
+__global__ __launch_bounds__(kBlock) void inner_combine_kernel(int64_t n, int nv, const T* __restrict__ Z,
+                                                               int64_t ld, const double* __restrict__ y,
+                                                               T* __restrict__ z) {
+  __shared__ double ys[kInnerMax];
+  if (threadIdx.x < nv) ys[threadIdx.x] = y[threadIdx.x];
+  __syncthreads();
+  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock) {
+    double s = 0.0;
+    for (int i = 0; i < nv; ++i) s += ys[i] * double(Z[i * ld + k]);
+    z[k] = T(s);
+  }
+}
+
 // Non-finite check: flag[0] = 1 if any x_i is NaN or Inf.
 __global__ __launch_bounds__(kBlock) void nonfinite_kernel(int64_t n, const double* __restrict__ x,
                                                             int* __restrict__ flag) {

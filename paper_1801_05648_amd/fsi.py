@@ -51,7 +51,8 @@ class CPrecondOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("max_coarse", ctypes.c_int32),
                 ("max_levels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("strength0", ctypes.c_double),
                 ("cheb_mask", ctypes.c_int32), ("poly_mask", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
-                ("schur", ctypes.c_int32), ("poly_ratio", ctypes.c_double)]
+                ("schur", ctypes.c_int32), ("poly_ratio", ctypes.c_double), ("fluid_inner", ctypes.c_int32),
+                ("pad", ctypes.c_int32)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -265,14 +266,15 @@ class FsiSolver:
     # -- calls -----------------------------------------------------------------
     def build_precond(self, precision: str = "f64", max_coarse: int = 500, max_levels: int = 10,
                       strength0: float = 0.08, cheb_degree: int = 0, cheb=("H_MS", "H_SIG", "H_P"),
-                      poly=(), poly_degree: int = 3, poly_ratio: float = 8.0, schur: str = "simple"):
+                      poly=(), poly_degree: int = 3, poly_ratio: float = 8.0, schur: str = "simple",
+                      fluid_inner: int = 0):
         def mask_of(names):
             m = 0
             for name in names:
                 m |= 1 << HIERARCHIES[name]
             return m
         o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, int(cheb_degree), strength0, mask_of(cheb),
-                         mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio))
+                         mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio), int(fluid_inner), 0)
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,

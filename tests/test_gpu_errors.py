@@ -124,6 +124,10 @@ def test_call_order_and_argument_checks():
     s.lib.fsi_default_precond_opts(ctypes.byref(o))
     o.precision = 7
     assert F.STATUS[s.lib.fsi_build_precond(s.ctx, ctypes.byref(o))] == "FSI_ERR_ARG"
+    for k in (-1, 17):  # inner GMRES steps of the fluid inverse: 0..16
+        with pytest.raises(FsiError) as e:
+            s.build_precond("f64", fluid_inner=k)
+        assert e.value.name == "FSI_ERR_ARG"
     _, info = s.solve(_dev(sysm.b))  # the failed calls left the preconditioner in place
     assert info.converged
     assert s.spmv_bytes() > 0
