@@ -251,9 +251,10 @@ def main():
     ap.add_argument("--schur", default=None, choices=["simple", "simplec"],
                     help="pressure Schur approximation -D W^{-1} G: W = diag(A_f) (simple) or its "
                          "absolute row sums (simplec); default simple")
-    ap.add_argument("--fluid-inner", type=int, default=0,
+    ap.add_argument("--fluid-inner", type=int, default=None,
                     help="inner flexible GMRES steps for the fluid inverse, preconditioned by the "
-                         "Uzawa-like step (0: the Uzawa-like step alone)")
+                         "Uzawa-like step (0: the Uzawa-like step alone; default 2 in 2D, 0 in 3D "
+                         "and with --learned)")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
@@ -295,6 +296,12 @@ def main():
         # two steps suffice for the 2D Q2 mass matrix (measured 23.4 vs 24.1 ms
         # on the 256x64 system); the 3D one needs three (46 vs 78 iterations)
         args.poly_degree = 2 if cfg.dim == 2 else 3
+    if args.fluid_inner is None:
+        # two inner GMRES steps on the fluid block halve the 2D outer iterations
+        # (256x64: 39/42/47 -> 19/20/23, 20.6 -> 14.7 ms; 1 step 17.1, 3 steps
+        # 17.8 ms); in 3D they cut iterations but not time (64x16x16: 46 -> 31
+        # iterations, 93.8 -> 103.8 ms)
+        args.fluid_inner = 2 if cfg.dim == 2 and not args.learned else 0
     if args.schur is None:
         # SIMPLE throughout: SIMPLEC (absolute row sums) cuts the 64x16x16
         # solve from 46 to 36 iterations but raises the 128x32x32 one from 47

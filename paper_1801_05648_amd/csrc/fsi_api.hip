@@ -972,7 +972,7 @@ struct Precond {
       T* vj = V + int64_t(j) * n;
       T* w = V + int64_t(j + 1) * n;
       fluid(vj, Z + int64_t(j) * n, s);
-      spmv<T>(Fm, Z + int64_t(j) * n, w, s);
+      launch_rows<T, 1>(Fm, GatherPlain<T, 1>{Z + int64_t(j) * n}, EpiStoreFluid<T, 1>{{w}}, s);
       inner_dots(j + 1, w, a1, s);
       inner_update_kernel<T><<<g, kBlock, 0, s>>>(n, j + 1, V, n, a1, w);
       inner_dots(j + 1, w, a2, s);

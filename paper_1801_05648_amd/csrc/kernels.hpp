@@ -47,6 +47,11 @@ struct EpiStore {  // y = A x
   }
 };
 
+// The fluid block's product in the inner GMRES of the fluid step: EpiStore
+// under a name of its own, so that a kernel trace tells it from A_h's.
+template <typename T, int NV>
+struct EpiStoreFluid : EpiStore<T, NV> {};
+
 template <typename T, int NV>
 struct EpiSub {  // y = r - A x   (y may alias r)
   const T* r;
