@@ -883,7 +883,8 @@ struct Precond {
   DCsr<T> S_vu, S_uv, Cfms, Csf, Cms, Dm, Gm;
   std::shared_ptr<DevBuf> tu, tu2, tv, tf, ta, ta2, tp, ts, ts2, tm, tm2, rT, zT;
   // inner GMRES of the fluid step (inner_k > 0): F, Arnoldi vectors V
-  // ((k + 1) x n_f), preconditioned vectors Z (k x n_f), FP64 scalars
+  // ((k + 1) x n_f), preconditioned vectors Z (k x n_f), FP64 scalars,
+  // breakdown flags (ikact: one per step, and one for a zero residual)
   int inner_k = 0;
   DCsr<T> Fm;
   std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ikact;
@@ -908,13 +909,13 @@ struct Precond {
       iscal = std::make_shared<DevBuf>();
       iscal->alloc(sizeof(double) * kInnerScal);
       ikact = std::make_shared<DevBuf>();
-      ikact->alloc(sizeof(int));
+      ikact->alloc(sizeof(int) * (kInnerMax + 1));
     }
   }
 
   // FP64 scalars of the inner GMRES: two Gram-Schmidt passes and a norm
-  // (kInnerMax + 2 each), beta, the Hessenberg matrix, y
-  static constexpr int kInnerScal = 3 * (kInnerMax + 2) + 1 + (kInnerMax + 1) * kInnerMax + kInnerMax;
+  // (kInnerMax + 2 each), beta, the Hessenberg matrix
+  static constexpr int kInnerScal = 3 * (kInnerMax + 2) + 1 + (kInnerMax + 1) * kInnerMax;
 
   // Solid algorithm of Section 4.3 (u_s eliminated through Sigma_s):
   //   y = M_s^{-1} r_u;  x_v = Sigma_s^{-1} (r_v - S_vu y);  x_u = M_s^{-1} (r_u - S_uv x_v)
@@ -947,9 +948,11 @@ struct Precond {
   // ||r_f - F z|| over the span of the preconditioned Arnoldi vectors.
   // Classical Gram-Schmidt with one reorthogonalisation; every scalar stays
   // on the device.
-  void inner_dots(int nv, const T* w, double* out, hipStream_t s) {
-    inner_dots_kernel<T><<<inner_nb, kBlock, 0, s>>>(n_f, nv, iV->as<T>(), n_f, w, ipart->as<double>());
-    gs_reduce_kernel<<<nv + 1, kBlock, 0, s>>>(inner_nb, 0, ipart->as<double>(), out);
+  // one Gram-Schmidt pass (update by nu vectors, nd dot products and the
+  // norm) and its block-order reduction into out[0..nd]
+  void inner_pass(int nu, int nd, const double* h, T* w, double* out, hipStream_t s) {
+    inner_pass_kernel<T><<<inner_nb, kBlock, 0, s>>>(n_f, nu, nd, iV->as<T>(), n_f, h, w, ipart->as<double>());
+    gs_reduce_kernel<<<nd + 1, kBlock, 0, s>>>(inner_nb, 0, ipart->as<double>(), out);
   }
 
   void fluid_gmres(const T* r_f, T* z_f, hipStream_t s) {
@@ -963,26 +966,21 @@ struct Precond {
     double* nn = a2 + (kInnerMax + 2);
     double* beta = nn + (kInnerMax + 2);
     double* Hm = beta + 1;
-    double* y = Hm + (kInnerMax + 1) * kInnerMax;
-    int* kact = ikact->as<int>();
-    inner_dots(0, r_f, nn, s);
-    inner_start_kernel<<<1, 1, 0, s>>>(nn, beta, kact, k);
-    inner_scale_kernel<T><<<g, kBlock, 0, s>>>(n, r_f, beta, kact, 0, V);
+    int* brk = ikact->as<int>();
+    // ||r_f||^2 (r_f read as "w" with no update: the pass only reads it)
+    inner_pass(0, 0, nullptr, const_cast<T*>(r_f), nn, s);
+    inner_start_kernel<T><<<g, kBlock, 0, s>>>(n, nn, beta, brk, r_f, V);
     for (int j = 0; j < k; ++j) {
-      T* vj = V + int64_t(j) * n;
+      T* zj = Z + int64_t(j) * n;
       T* w = V + int64_t(j + 1) * n;
-      fluid(vj, Z + int64_t(j) * n, s);
-      launch_rows<T, 1>(Fm, GatherPlain<T, 1>{Z + int64_t(j) * n}, EpiStoreFluid<T, 1>{{w}}, s);
-      inner_dots(j + 1, w, a1, s);
-      inner_update_kernel<T><<<g, kBlock, 0, s>>>(n, j + 1, V, n, a1, w);
-      inner_dots(j + 1, w, a2, s);
-      inner_update_kernel<T><<<g, kBlock, 0, s>>>(n, j + 1, V, n, a2, w);
-      inner_dots(0, w, nn, s);
-      inner_column_kernel<<<1, 1, 0, s>>>(j, k, a1, a2, nn, Hm, kact);
-      inner_scale_kernel<T><<<g, kBlock, 0, s>>>(n, w, Hm + int64_t(j) * (k + 1) + j + 1, kact, j + 1, w);
+      fluid(V + int64_t(j) * n, zj, s);
+      launch_rows<T, 1>(Fm, GatherPlain<T, 1>{zj}, EpiStoreFluid<T, 1>{{w}}, s);
+      inner_pass(0, j + 1, nullptr, w, a1, s);   // h1 = V^T w, ||w||^2
+      inner_pass(j + 1, j + 1, a1, w, a2, s);    // w -= V h1; h2 = V^T w
+      inner_pass(j + 1, 0, a2, w, nn, s);        // w -= V h2; ||w||^2
+      inner_column_kernel<T><<<g, kBlock, 0, s>>>(n, j, k, a1, a2, nn, Hm, brk, w);
     }
-    inner_lsq_kernel<<<1, 1, 0, s>>>(k, Hm, beta, kact, y);
-    inner_combine_kernel<T><<<g, kBlock, 0, s>>>(n, k, Z, n, y, z_f);
+    inner_combine_kernel<T><<<g, kBlock, 0, s>>>(n, k, Z, n, Hm, beta, brk, z_f);
   }
 
   void fluid_inverse(const T* r_f, T* z_f, hipStream_t s) {

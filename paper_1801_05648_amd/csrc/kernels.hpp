@@ -1023,102 +1023,123 @@ __global__ __launch_bounds__(kBlock) void multi_axpy_kernel(int64_t n, int nv, c
 constexpr int kInnerMax = 16;
 constexpr int kInnerBlocks = 512;
 
-// part[i * gridDim.x + block] = V_i . w for i < nv, part[nv * gridDim.x + block]
-// = w . w (block partial sums; gs_reduce_kernel adds them in block order).
+// One Gram-Schmidt pass of the inner GMRES (the pattern of gs_pass_kernel):
+// first w -= sum_{i < nu} h_i V_i (nu = 0: none), then block partial sums
+// part[i * gridDim.x + block] = V_i . w for i < nd and part[nd * gridDim.x +
+// block] = w . w; V_i is read once when both are asked for.  gs_reduce_kernel
+// adds the partial sums in block order.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void inner_dots_kernel(int64_t n, int nv, const T* __restrict__ V,
-                                                            int64_t ld, const T* __restrict__ w,
-                                                            double* __restrict__ part) {
+__global__ __launch_bounds__(kBlock) void inner_pass_kernel(int64_t n, int nu, int nd, const T* __restrict__ V,
+                                                            int64_t ld, const double* __restrict__ h,
+                                                            T* __restrict__ w, double* __restrict__ part) {
+  __shared__ double hs[kInnerMax];
   __shared__ double sh[kWaves][kInnerMax + 1];
+  if (threadIdx.x < nu) hs[threadIdx.x] = h[threadIdx.x];
+  __syncthreads();
+  const int nl = nu > nd ? nu : nd;
   double acc[kInnerMax + 1];
 #pragma unroll
   for (int i = 0; i <= kInnerMax; ++i) acc[i] = 0.0;
   for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock) {
-    const double wk = double(w[k]);
+    double v[kInnerMax];
+#pragma unroll
+    for (int i = 0; i < kInnerMax; ++i) v[i] = i < nl ? double(V[i * ld + k]) : 0.0;
+    double wk = double(w[k]);
+    if (nu > 0) {
+#pragma unroll
+      for (int i = 0; i < kInnerMax; ++i)
+        if (i < nu) wk -= hs[i] * v[i];
+      const T st = T(wk);
+      w[k] = st;
+      wk = double(st);
+    }
 #pragma unroll
     for (int i = 0; i < kInnerMax; ++i)
-      if (i < nv) acc[i] += double(V[i * ld + k]) * wk;
+      if (i < nd) acc[i] += v[i] * wk;
     acc[kInnerMax] += wk * wk;
   }
   const int wid = threadIdx.x / 64, lane = threadIdx.x % 64;
 #pragma unroll
   for (int i = 0; i <= kInnerMax; ++i) {
-    if (i < nv || i == kInnerMax) {
+    if (i < nd || i == kInnerMax) {
       const double t = wave_sum(acc[i]);
-      if (lane == 0) sh[wid][i < nv ? i : kInnerMax] = t;
+      if (lane == 0) sh[wid][i] = t;
     }
   }
   __syncthreads();
   const int t = threadIdx.x;
-  if (t <= nv) {
-    const int slot = t < nv ? t : kInnerMax;
+  if (t <= nd) {
+    const int slot = t < nd ? t : kInnerMax;
     double v = 0.0;
     for (int q = 0; q < kWaves; ++q) v += sh[q][slot];
     part[int64_t(t) * gridDim.x + blockIdx.x] = v;
   }
 }
 
-// w -= sum_{i < nv} h_i V_i
+// Start of the inner GMRES: beta = sqrt(rr[0]); V_0 = r / beta (0 when r = 0).
+// Block 0 records st[0] = beta and brk[kInnerMax] = (beta == 0).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void inner_update_kernel(int64_t n, int nv, const T* __restrict__ V,
-                                                              int64_t ld, const double* __restrict__ h,
-                                                              T* __restrict__ w) {
-  __shared__ double hs[kInnerMax];
-  if (threadIdx.x < nv) hs[threadIdx.x] = h[threadIdx.x];
-  __syncthreads();
-  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock) {
-    double s = double(w[k]);
-    for (int i = 0; i < nv; ++i) s -= hs[i] * double(V[i * ld + k]);
-    w[k] = T(s);
-  }
-}
-
-// Start: st[0] = beta = ||r|| (from rr[0] = r . r), kact[0] = k (0 when r = 0).
-__global__ void inner_start_kernel(const double* __restrict__ rr, double* __restrict__ st,
-                                   int* __restrict__ kact, int k) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__global__ __launch_bounds__(kBlock) void inner_start_kernel(int64_t n, const double* __restrict__ rr,
+                                                             double* __restrict__ st, int* __restrict__ brk,
+                                                             const T* __restrict__ r, T* __restrict__ v0) {
   const double b = sqrt(rr[0] > 0.0 ? rr[0] : 0.0);
-  st[0] = b;
-  kact[0] = b > 0.0 ? k : 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st[0] = b;
+    brk[kInnerMax] = b > 0.0 ? 0 : 1;
+  }
+  const double f = b > 0.0 ? 1.0 / b : 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
+    v0[i] = T(double(r[i]) * f);
 }
 
-// Column j of the Hessenberg matrix (column-major, leading dimension k + 1)
-// from the two Gram-Schmidt passes a1, a2 (a1[j + 1] = ||w||^2 before them)
-// and the final squared norm nn[0]; a breakdown (an exact solve in the
-// current space) truncates the step count to j + 1.
-__global__ void inner_column_kernel(int j, int k, const double* __restrict__ a1, const double* __restrict__ a2,
-                                    const double* __restrict__ nn, double* __restrict__ H,
-                                    int* __restrict__ kact) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  double* col = H + int64_t(j) * (k + 1);
-  for (int i = 0; i <= j; ++i) col[i] = a1[i] + a2[i];
+// End of Arnoldi step j: column j of the Hessenberg matrix (column-major,
+// leading dimension k + 1) from the two passes a1, a2 (a1[j + 1] = ||w||^2
+// before them) and the final squared norm nn[0], written by block 0 with the
+// step's breakdown flag brk[j] (an exact solve in the current space); every
+// block normalises w = V_{j+1}, or zeroes it once a breakdown has happened
+// (brk of earlier steps come from earlier launches).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void inner_column_kernel(int64_t n, int j, int k, const double* __restrict__ a1,
+                                                              const double* __restrict__ a2,
+                                                              const double* __restrict__ nn,
+                                                              double* __restrict__ H, int* __restrict__ brk,
+                                                              T* __restrict__ w) {
   const double hn = sqrt(nn[0] > 0.0 ? nn[0] : 0.0);
   const double wb = sqrt(a1[j + 1] > 0.0 ? a1[j + 1] : 0.0);
-  col[j + 1] = hn;
-  if (!(hn > 1e-14 * wb) && kact[0] > j + 1) kact[0] = j + 1;
-}
-
-// y = x / s[0] (0 when s[0] is 0 or the step is past a breakdown); y may be x
-template <typename T>
-__global__ __launch_bounds__(kBlock) void inner_scale_kernel(int64_t n, const T* x,
-                                                             const double* __restrict__ s,
-                                                             const int* __restrict__ kact, int j, T* y) {
-  const double d = s[0];
-  const double f = (d > 0.0 && kact[0] > j) ? 1.0 / d : 0.0;
+  const bool here = !(hn > 1e-14 * wb);
+  bool before = brk[kInnerMax] != 0;
+  for (int i = 0; i < j; ++i) before = before || brk[i] != 0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    double* col = H + int64_t(j) * (k + 1);
+    for (int i = 0; i <= j; ++i) col[i] = a1[i] + a2[i];
+    col[j + 1] = hn;
+    brk[j] = here ? 1 : 0;
+  }
+  const double f = (before || here) ? 0.0 : 1.0 / hn;
   for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock)
-    y[i] = T(double(x[i]) * f);
+    w[i] = T(double(w[i]) * f);
 }
 
-// Least squares min ||beta e_1 - Hbar y|| over the first kact columns by
-// Givens rotations and back substitution; y_j = 0 for j >= kact.
-__global__ void inner_lsq_kernel(int k, const double* __restrict__ H, const double* __restrict__ st,
-                                 const int* __restrict__ kact, double* __restrict__ y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Least squares min ||beta e_1 - Hbar y|| over the first m columns (m: k, or
+// the step of the first breakdown + 1, or 0 when beta = 0) by Givens
+// rotations and back substitution, y_j = 0 for j >= m; one thread, its work
+// arrays in LDS.
+struct InnerLsqWork {
   double R[kInnerMax + 1][kInnerMax];
   double g[kInnerMax + 1], cs[kInnerMax], sn[kInnerMax];
-  const int m = kact[0] < k ? kact[0] : k;
+};
+
+__device__ void inner_lsq(int k, const double* __restrict__ H, double beta, const int* __restrict__ brk,
+                          InnerLsqWork& wk, double* __restrict__ y) {
+  auto& R = wk.R;
+  double* g = wk.g;
+  double* cs = wk.cs;
+  double* sn = wk.sn;
+  int m = brk[kInnerMax] ? 0 : k;
+  for (int j = 0; j < m; ++j)
+    if (brk[j]) { m = j + 1; break; }
   for (int j = 0; j <= k; ++j) g[j] = 0.0;
-  g[0] = st[0];
+  g[0] = beta;
   for (int j = 0; j < m; ++j) {
     for (int i = 0; i <= j + 1; ++i) R[i][j] = H[int64_t(j) * (k + 1) + i];
     for (int i = 0; i < j; ++i) {
@@ -1143,18 +1164,21 @@ __global__ void inner_lsq_kernel(int k, const double* __restrict__ H, const doub
   }
 }
 
-// z = sum_{i < nv} y_i Z_i
+// z = sum_{i < k} y_i Z_i with y from the least squares above (each block
+// solves the (k + 1) x k problem itself in LDS: no extra launch).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void inner_combine_kernel(int64_t n, int nv, const T* __restrict__ Z,
-                                                               int64_t ld, const double* __restrict__ y,
-                                                               T* __restrict__ z) {
+__global__ __launch_bounds__(kBlock) void inner_combine_kernel(int64_t n, int k, const T* __restrict__ Z, int64_t ld,
+                                                               const double* __restrict__ H,
+                                                               const double* __restrict__ st,
+                                                               const int* __restrict__ brk, T* __restrict__ z) {
   __shared__ double ys[kInnerMax];
-  if (threadIdx.x < nv) ys[threadIdx.x] = y[threadIdx.x];
+  __shared__ InnerLsqWork wk;
+  if (threadIdx.x == 0) inner_lsq(k, H, st[0], brk, wk, ys);
   __syncthreads();
-  for (int64_t k = int64_t(blockIdx.x) * kBlock + threadIdx.x; k < n; k += int64_t(gridDim.x) * kBlock) {
+  for (int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x; i < n; i += int64_t(gridDim.x) * kBlock) {
     double s = 0.0;
-    for (int i = 0; i < nv; ++i) s += ys[i] * double(Z[i * ld + k]);
-    z[k] = T(s);
+    for (int q = 0; q < k; ++q) s += ys[q] * double(Z[q * ld + i]);
+    z[i] = T(s);
   }
 }
 
