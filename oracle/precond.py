@@ -23,7 +23,9 @@ with the approximate inverses
       y = V_A(r_v);  x_p = V_p(r_p - D y);  x_v = V_A(r_v - G x_p).
   Optionally (the paper's choice for the fluid sub-problem, Section 4.4) F^{-1}
   is k steps of flexible GMRES on F from zero, right-preconditioned by that
-  Uzawa-like step (fluid_gmres_solve).
+  Uzawa-like step or by the cheaper block upper-triangular step
+      x_p = V_p(r_p);  x_v = V_A(r_v - G x_p)
+  (fluid_gmres_solve, fluid_triangular_solve).
 """
 from __future__ import annotations
 
@@ -111,6 +113,18 @@ def fluid_schur_solve(bs: BlockSystem, a_inv, p_inv, r_f: np.ndarray) -> np.ndar
     return np.concatenate([x_v, x_p])
 
 
+def fluid_triangular_solve(bs: BlockSystem, a_inv, p_inv, r_f: np.ndarray) -> np.ndarray:
+    """Block upper-triangular step for F = [[A_f, G], [D, 0]]: the inverse of
+    U = [[A_f, G], [0, S]] (S = -D A_f^{-1} G, the Schur complement) with the
+    approximate inverses a_inv ~ A_f^{-1}, p_inv ~ S^{-1}.  F U^{-1} is then
+    unit lower block-triangular: with exact inverses two GMRES steps solve."""
+    nvf = bs.n_vf
+    r_v, r_p = r_f[:nvf], r_f[nvf:]
+    x_p = p_inv(r_p)
+    x_v = a_inv(r_v - bs.G @ x_p)
+    return np.concatenate([x_v, x_p])
+
+
 def fluid_gmres_solve(bs: BlockSystem, uzawa, r_f: np.ndarray, k: int) -> np.ndarray:
     """F^{-1} r_f as k steps of flexible GMRES on F = [[A_f, G], [D, 0]] from
     x = 0, right-preconditioned by `uzawa` (the Uzawa-like step): the fluid
@@ -135,14 +149,15 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
 
 
 def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None,
-                       fluid_inner: int = 0) -> BlockLDU:
+                       fluid_inner: int = 0, fluid_inner_pc: str = "uzawa") -> BlockLDU:
     """The preconditioner of the hot path: every inverse one V(1,1) cycle
     (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
     named in `cheb`).  For the names in `poly`, {name: (k, ratio)}, the
     inverse is instead k Chebyshev steps alone on the finest matrix (no coarse
     grid), on [lam/ratio, lam] with lam = 1.1 rho of that level.  With
     fluid_inner = k > 0 the fluid inverse is k inner GMRES steps
-    preconditioned by the Uzawa-like step (fluid_gmres_solve)."""
+    preconditioned by the Uzawa-like step (fluid_inner_pc = "uzawa") or by
+    the block upper-triangular step ("triangular")."""
     cheb = cheb or {}
     poly = poly or {}
 
@@ -162,5 +177,11 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     uzawa = lambda r: fluid_schur_solve(bs, V["H_A"], V["H_P"], r)
     fluid = uzawa
     if fluid_inner > 0:
-        fluid = lambda r: fluid_gmres_solve(bs, uzawa, r, fluid_inner)
+        if fluid_inner_pc == "uzawa":
+            inner = uzawa
+        elif fluid_inner_pc == "triangular":
+            inner = lambda r: fluid_triangular_solve(bs, V["H_A"], V["H_P"], r)
+        else:
+            raise ValueError(f"unknown inner fluid preconditioner {fluid_inner_pc!r}")
+        fluid = lambda r: fluid_gmres_solve(bs, inner, r, fluid_inner)
     return BlockLDU(bs, mesh, solid, fluid)

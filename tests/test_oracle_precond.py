@@ -260,3 +260,42 @@ def test_amg_preconditioned_solve_c1_inner_gmres():
         assert np.linalg.norm(b - bs.matvec(x)) <= 1e-8 * np.linalg.norm(b)
         its[k] = info.iters
     assert its[3] <= its[0], its
+
+
+@pytest.mark.parametrize("name", ["tiny2d_unit", "c1"])
+def test_fluid_triangular_step_two_gmres_steps(name):
+    """With exact inverses of A_f and of the Schur complement S = -D A_f^{-1} G
+    the block upper-triangular step leaves F U^{-1} unit lower
+    block-triangular, (F U^{-1} - I)^2 = 0: two inner GMRES steps solve
+    F x = r exactly, one step in general does not."""
+    bs = _bs(name)
+    Af = bs.A_f.toarray()
+    S = -bs.D.toarray() @ np.linalg.solve(Af, bs.G.toarray())
+    tri = lambda r: precond.fluid_triangular_solve(bs, _inv(Af), _inv(S), r)
+    r = np.random.default_rng(14).standard_normal(bs.n_f)
+    xe = np.linalg.solve(bs.B["F"].toarray(), r)
+    x2 = precond.fluid_gmres_solve(bs, tri, r, 2)
+    assert np.linalg.norm(x2 - xe) <= 1e-8 * np.linalg.norm(xe)
+    x1 = precond.fluid_gmres_solve(bs, tri, r, 1)
+    assert np.linalg.norm(x1 - xe) > 1e-3 * np.linalg.norm(xe)
+    if bs.n_f > 400:
+        return
+    # F U^{-1} - I is nilpotent of index 2 (its only nonzero block is D A_f^{-1})
+    Fd = bs.B["F"].toarray()
+    U = np.column_stack([tri(e) for e in np.eye(bs.n_f)])
+    E = Fd @ U - np.eye(bs.n_f)
+    assert np.abs(E @ E).max() <= 1e-8 * max(1.0, np.abs(E).max())
+    assert np.abs(E).max() > 1e-6
+
+
+def test_amg_preconditioned_solve_c1_inner_triangular():
+    """The triangular inner preconditioner: the solve converges on C1, and an
+    unknown name is refused."""
+    bs = _bs("c1")
+    H = precond.build_hierarchies(bs)
+    b = bs.sys.b
+    P = precond.amg_preconditioner(bs, H, fluid_inner=2, fluid_inner_pc="triangular")
+    x, info = krylov.fgmres(bs.matvec, P, b, tol=1e-8, restart=50, maxit=300)
+    assert info.converged and np.linalg.norm(b - bs.matvec(x)) <= 1e-8 * np.linalg.norm(b)
+    with pytest.raises(ValueError):
+        precond.amg_preconditioner(bs, H, fluid_inner=2, fluid_inner_pc="lower")
