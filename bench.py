@@ -62,7 +62,8 @@ def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
         t_setup = time.perf_counter() - t0
         cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
         poly = {h: (args.poly_degree, args.poly_ratio) for h in poly_on(args)}
-        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=args.fluid_inner)
+        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=args.fluid_inner,
+                                       fluid_inner_pc=args.fluid_inner_pc)
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
         t_iter = (time.perf_counter() - t0) / max(info.iters, 1)
@@ -97,7 +98,7 @@ def precond_name(args) -> str:
     ptxt = f"; {'/'.join(poly)} by {args.poly_degree} Chebyshev steps alone" if poly else ""
     ptxt += f"; S_p {args.schur.upper()}"
     if args.fluid_inner > 0:
-        ptxt += f"; F^-1 by {args.fluid_inner} inner GMRES steps"
+        ptxt += f"; F^-1 by {args.fluid_inner} inner GMRES steps ({args.fluid_inner_pc} step)"
     if args.cheb <= 0:
         return "block-LDU + SA-AMG V(1,1) Jacobi" + ptxt
     on = cheb_on(args)
@@ -141,7 +142,8 @@ def learned_run(args, cfg):
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner)
+                             fluid_inner=args.fluid_inner,
+                             fluid_inner_pc=args.fluid_inner_pc)
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -156,7 +158,8 @@ def learned_run(args, cfg):
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner)
+                             fluid_inner=args.fluid_inner,
+                             fluid_inner_pc=args.fluid_inner_pc)
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -175,7 +178,8 @@ def learned_run(args, cfg):
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner)
+                             fluid_inner=args.fluid_inner,
+                             fluid_inner_pc=args.fluid_inner_pc)
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -255,6 +259,9 @@ def main():
                     help="inner flexible GMRES steps for the fluid inverse, preconditioned by the "
                          "Uzawa-like step (0: the Uzawa-like step alone; default 2 in 2D, 0 in 3D "
                          "and with --learned)")
+    ap.add_argument("--fluid-inner-pc", default="triangular", choices=["uzawa", "triangular"],
+                    help="preconditioner of the inner fluid GMRES: the Uzawa-like step or the block "
+                         "upper-triangular step (one A_f V-cycle fewer; default)")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
@@ -298,9 +305,11 @@ def main():
         args.poly_degree = 2 if cfg.dim == 2 else 3
     if args.fluid_inner is None:
         # two inner GMRES steps on the fluid block halve the 2D outer iterations
-        # (256x64: 39/42/47 -> 19/20/23, 20.6 -> 14.7 ms; 1 step 17.1, 3 steps
-        # 17.8 ms); in 3D they cut iterations but not time (64x16x16: 46 -> 31
-        # iterations, 93.8 -> 103.8 ms)
+        # (256x64: 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms with the triangular
+        # inner step, 14.4 ms with the Uzawa-like one).  In 3D the Uzawa-like
+        # steps cut iterations but not time (64x16x16: 46 -> 31 iterations,
+        # 93.8 -> 103.8 ms); two triangular ones give 33 iterations, 85.3 ms
+        # there, but stay an option until measured on the 128x32x32 system
         args.fluid_inner = 2 if cfg.dim == 2 and not args.learned else 0
     if args.schur is None:
         # SIMPLE throughout: SIMPLEC (absolute row sums) cuts the 64x16x16
@@ -328,7 +337,8 @@ def main():
         solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                              cheb=cheb_on(args), poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner)
+                             fluid_inner=args.fluid_inner,
+                             fluid_inner_pc=args.fluid_inner_pc)
         hn = args.pmc_vcycle
         nv = int(solver.hierarchy_info(hn)[0][0]) * (sysm.dim if hn == "H_M" else 1)
         bv = torch.randn(nv, dtype=torch.float64, device=dev)
@@ -372,7 +382,8 @@ def main():
                              cheb=cheb_on(args),
                              poly=poly_on(args), poly_degree=args.poly_degree,
                              poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner)
+                             fluid_inner=args.fluid_inner,
+                             fluid_inner_pc=args.fluid_inner_pc)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")

@@ -137,8 +137,14 @@ typedef struct {
                           reorthogonalisation, stopping early only at an exact
                           solve; the outer FGMRES absorbs the nonlinearity.
                           Stores F once more and 2k + 1 fluid vectors        */
-  int32_t pad;
+  int32_t fluid_inner_pc; /* preconditioner of those steps: FSI_INNER_UZAWA
+                          (default; the Uzawa-like step, two A_f V-cycles and
+                          one S_p V-cycle) or FSI_INNER_TRIANGULAR (the block
+                          upper-triangular step x_p = S_p^{-1} r_p,
+                          x_v = A_f^{-1}(r_v - G x_p): one V-cycle of each)  */
 } fsi_precond_opts;
+
+enum { FSI_INNER_UZAWA = 0, FSI_INNER_TRIANGULAR = 1 };
 
 enum { FSI_SCHUR_SIMPLE = 0, FSI_SCHUR_SIMPLEC = 1 };
 

@@ -886,6 +886,7 @@ struct Precond {
   // ((k + 1) x n_f), preconditioned vectors Z (k x n_f), FP64 scalars,
   // breakdown flags (ikact: one per step, and one for a zero residual)
   int inner_k = 0;
+  int inner_pc = FSI_INNER_UZAWA;
   DCsr<T> Fm;
   std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ikact;
   int inner_nb = 1;
@@ -943,6 +944,16 @@ struct Precond {
     vcycle(H[FSI_H_A], ta2->as<T>(), z_f, s);
   }
 
+  // Block upper-triangular step, the inverse of [[A_f, G], [0, S_p]]:
+  //   x_p = S_p^{-1} r_p;  x_v = A_f^{-1} (r_v - G x_p)
+  void fluid_tri(const T* r_f, T* z_f, hipStream_t s) {
+    const T* r_v = r_f;
+    const T* r_p = r_f + n_vf;
+    vcycle(H[FSI_H_P], r_p, z_f + n_vf, s);
+    spmv_sub<T>(Gm, z_f + n_vf, r_v, ta2->as<T>(), s);
+    vcycle(H[FSI_H_A], ta2->as<T>(), z_f, s);
+  }
+
   // The fluid sub-problem solved by k steps of flexible GMRES on F from zero,
   // right-preconditioned by the Uzawa-like step (Section 4.4): z_f minimises
   // ||r_f - F z|| over the span of the preconditioned Arnoldi vectors.
@@ -973,7 +984,8 @@ struct Precond {
     for (int j = 0; j < k; ++j) {
       T* zj = Z + int64_t(j) * n;
       T* w = V + int64_t(j + 1) * n;
-      fluid(V + int64_t(j) * n, zj, s);
+      if (inner_pc == FSI_INNER_TRIANGULAR) fluid_tri(V + int64_t(j) * n, zj, s);
+      else fluid(V + int64_t(j) * n, zj, s);
       launch_rows<T, 1>(Fm, GatherPlain<T, 1>{zj}, EpiStoreFluid<T, 1>{{w}}, s);
       inner_pass(0, j + 1, nullptr, w, a1, s);   // h1 = V^T w, ||w||^2
       inner_pass(j + 1, j + 1, a1, w, a2, s);    // w -= V h1; h2 = V^T w
@@ -1054,6 +1066,7 @@ struct fsi_ctx {
   int cheb[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev degree per hierarchy (0: Jacobi)
   int poly[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev steps alone, no coarse grid (0: off)
   int fluid_inner = 0;                     // inner GMRES steps of the fluid inverse (0: off)
+  int fluid_inner_pc = FSI_INNER_UZAWA;    // their preconditioner
   double poly_ratio = 8.0;
   SaHierarchy host_h[FSI_NHIER];
   std::unique_ptr<Precond<double>> p64;
@@ -1224,6 +1237,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     const int groups[2] = {c.d, 1};
     P->Cfms = upload_segments<T>(M, bounds, groups, 2, s);
     P->inner_k = c.fluid_inner;
+    P->inner_pc = c.fluid_inner_pc;
     if (c.fluid_inner > 0) P->Fm = upload_segments<T>(c.blk[FSI_F], bounds, groups, 2, s);
   }
   P->alloc_tmp();
@@ -2151,6 +2165,7 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->schur = FSI_SCHUR_SIMPLE;
   o->poly_ratio = 8.0;
   o->fluid_inner = 0;
+  o->fluid_inner_pc = FSI_INNER_UZAWA;
 }
 
 void fsi_default_solve_opts(fsi_solve_opts* o) {
@@ -2329,6 +2344,8 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       throw Error(FSI_ERR_ARG, "unknown pressure Schur approximation");
     if (o.fluid_inner < 0 || o.fluid_inner > kInnerMax)
       throw Error(FSI_ERR_ARG, "inner GMRES steps of the fluid inverse must be in 0..16");
+    if (o.fluid_inner_pc != FSI_INNER_UZAWA && o.fluid_inner_pc != FSI_INNER_TRIANGULAR)
+      throw Error(FSI_ERR_ARG, "unknown preconditioner of the inner fluid GMRES");
     if (o.max_coarse < 1 || o.max_levels < 1 || o.max_levels > 16 || !(o.strength0 >= 0.0))
       throw Error(FSI_ERR_ARG, "bad AMG options");
     if (o.cheb_degree < 0 || o.cheb_degree > 8 || (o.cheb_mask & ~0x1f) != 0)
@@ -2408,6 +2425,7 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     }
     c.poly_ratio = o.poly_ratio;
     c.fluid_inner = o.fluid_inner;
+    c.fluid_inner_pc = o.fluid_inner_pc;
     c.precision = o.precision;  // before prepare_mlp: it decides which hierarchies can learn
     prepare_mlp(c);
     c.drop_graphs();

@@ -52,7 +52,7 @@ class CPrecondOpts(ctypes.Structure):
                 ("max_levels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("strength0", ctypes.c_double),
                 ("cheb_mask", ctypes.c_int32), ("poly_mask", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
                 ("schur", ctypes.c_int32), ("poly_ratio", ctypes.c_double), ("fluid_inner", ctypes.c_int32),
-                ("pad", ctypes.c_int32)]
+                ("fluid_inner_pc", ctypes.c_int32)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -74,6 +74,7 @@ class CMlpTrainOpts(ctypes.Structure):
 
 
 MLP_LOSS = {"l2": 0, "energy": 1}
+INNER_PC = {"uzawa": 0, "triangular": 1}
 
 
 class CMlpTrainInfo(ctypes.Structure):
@@ -267,14 +268,15 @@ class FsiSolver:
     def build_precond(self, precision: str = "f64", max_coarse: int = 500, max_levels: int = 10,
                       strength0: float = 0.08, cheb_degree: int = 0, cheb=("H_MS", "H_SIG", "H_P"),
                       poly=(), poly_degree: int = 3, poly_ratio: float = 8.0, schur: str = "simple",
-                      fluid_inner: int = 0):
+                      fluid_inner: int = 0, fluid_inner_pc: str = "uzawa"):
         def mask_of(names):
             m = 0
             for name in names:
                 m |= 1 << HIERARCHIES[name]
             return m
         o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, int(cheb_degree), strength0, mask_of(cheb),
-                         mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio), int(fluid_inner), 0)
+                         mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio), int(fluid_inner),
+                         INNER_PC[fluid_inner_pc])
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,

@@ -128,6 +128,9 @@ def test_call_order_and_argument_checks():
         with pytest.raises(FsiError) as e:
             s.build_precond("f64", fluid_inner=k)
         assert e.value.name == "FSI_ERR_ARG"
+    o.precision = 0
+    o.fluid_inner, o.fluid_inner_pc = 2, 5  # an unknown inner preconditioner
+    assert F.STATUS[s.lib.fsi_build_precond(s.ctx, ctypes.byref(o))] == "FSI_ERR_ARG"
     _, info = s.solve(_dev(sysm.b))  # the failed calls left the preconditioner in place
     assert info.converged
     assert s.spmv_bytes() > 0
