@@ -56,6 +56,9 @@ def test_default_options_without_a_device(lib):
     p = fsi.CPrecondOpts()
     lib.fsi_default_precond_opts(ctypes.byref(p))
     assert (p.precision, p.max_coarse, p.max_levels, p.strength0) == (0, 500, 10, 0.08)
+    # the pressure Schur approximation SIMPLE, the fluid inverse the Uzawa-like step alone
+    assert (p.schur, p.fluid_inner, p.fluid_inner_pc, p.poly_ratio) == (0, 0, 0, 8.0)
+    assert fsi.SCHUR["simple"] == 0 and fsi.INNER_PC == {"uzawa": 0, "triangular": 1}
 
 
 def test_null_context_arguments_are_rejected(lib):
