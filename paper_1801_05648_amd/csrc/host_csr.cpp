@@ -8,11 +8,11 @@
 
 namespace fsi {
 
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f) {
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f, int64_t min_n) {
   if (n <= 0) return;
   unsigned hw = std::thread::hardware_concurrency();
   int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 32));
-  if (n < 4096 || nt == 1) {
+  if (n < min_n || nt == 1) {
     f(0, n);
     return;
   }
@@ -95,7 +95,9 @@ HCsr spgemm(const HCsr& A, const HCsr& B) {
   C.nrows = A.nrows;
   C.ncols = B.ncols;
   const int64_t n = A.nrows;
-  // chunked rows: each chunk builds its own arrays, then they are concatenated
+  // chunked rows: each chunk builds its own arrays, then they are concatenated;
+  // the chunks (at least 256 rows each) run on the host threads, and every
+  // row is formed the same way on any thread
   const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(256, n / 256));
   std::vector<std::vector<int32_t>> cc(nchunk);
   std::vector<std::vector<double>> cv(nchunk);
@@ -133,7 +135,7 @@ HCsr spgemm(const HCsr& A, const HCsr& B) {
         rowlen[i] = len;
       }
     }
-  });
+  }, 2);
   C.rp.assign(n + 1, 0);
   for (int64_t i = 0; i < n; ++i) C.rp[i + 1] = C.rp[i] + rowlen[i];
   C.ci.reserve(C.rp[n]);
@@ -221,11 +223,14 @@ std::vector<double> diagonal(const HCsr& A) {
 }
 
 void matvec(const HCsr& A, const double* x, double* y) {
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    double s = 0.0;
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
-    y[i] = s;
-  }
+  // rows on the host threads; each row summed in storage order on any thread
+  parallel_for(A.nrows, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      double s = 0.0;
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) s += A.v[k] * x[A.ci[k]];
+      y[i] = s;
+    }
+  }, int64_t(1) << 15);
 }
 
 HCsr group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, std::vector<double>& val) {

@@ -18,8 +18,9 @@ struct HCsr {
   int64_t nnz() const { return int64_t(ci.size()); }
 };
 
-// Run f(begin, end) over [0, n) on the host's hardware threads.
-void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f);
+// Run f(begin, end) over [0, n) on the host's hardware threads (on the
+// calling thread alone when n < min_n: items too small to pay for threads).
+void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f, int64_t min_n = 4096);
 
 // Well-formedness: row pointers, column range, strictly increasing columns,
 // finite values.  Returns an empty string when valid.
