@@ -220,25 +220,40 @@ HCsr filtered(const HCsr& A, int b, const Strength& S) {
   F.nrows = A.nrows;
   F.ncols = A.ncols;
   F.rp.assign(A.nrows + 1, 0);
-  for (int64_t i = 0; i < A.nrows; ++i) {
+  auto keep = [&](int64_t i, int64_t k) {
     const int64_t I = i / b;
-    double lump = 0.0;
-    int64_t dpos = -1;
-    const int64_t lo = S.ptr[I], hi = S.ptr[I + 1];
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      const int32_t J = A.ci[k] / b;
-      bool keep = J == I || std::binary_search(S.nbr.begin() + lo, S.nbr.begin() + hi, J);
-      if (!keep) {
-        lump += A.v[k];
-        continue;
-      }
-      if (A.ci[k] == i) dpos = int64_t(F.ci.size());
-      F.ci.push_back(A.ci[k]);
-      F.v.push_back(A.v[k]);
+    const int32_t J = A.ci[k] / b;
+    return J == I || std::binary_search(S.nbr.begin() + S.ptr[I], S.nbr.begin() + S.ptr[I + 1], J);
+  };
+  // rows are independent: count the kept entries, then fill, on the host
+  // threads (each row formed as in a serial pass)
+  parallel_for(A.nrows, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      int64_t c = 0;
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) c += keep(i, k) ? 1 : 0;
+      F.rp[i + 1] = c;
     }
-    if (dpos >= 0) F.v[dpos] = F.v[dpos] + lump;
-    F.rp[i + 1] = int64_t(F.ci.size());
-  }
+  });
+  for (int64_t i = 0; i < A.nrows; ++i) F.rp[i + 1] += F.rp[i];
+  F.ci.resize(size_t(F.rp[A.nrows]));
+  F.v.resize(size_t(F.rp[A.nrows]));
+  parallel_for(A.nrows, [&](int64_t i0, int64_t i1) {
+    for (int64_t i = i0; i < i1; ++i) {
+      double lump = 0.0;
+      int64_t dpos = -1, p = F.rp[i];
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+        if (!keep(i, k)) {
+          lump += A.v[k];
+          continue;
+        }
+        if (A.ci[k] == i) dpos = p;
+        F.ci[size_t(p)] = A.ci[k];
+        F.v[size_t(p)] = A.v[k];
+        ++p;
+      }
+      if (dpos >= 0) F.v[size_t(dpos)] = F.v[size_t(dpos)] + lump;
+    }
+  });
   drop_zeros(F);
   return F;
 }
@@ -356,9 +371,9 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
   if (A.nrows % b != 0) return "matrix size is not a multiple of the node block size";
   while (true) {
     SaLevel L;
-    L.A = A;
+    L.A = std::move(A);  // the level keeps its matrix; Al refers to it below
     L.block = b;
-    std::vector<double> d = diagonal(A);
+    std::vector<double> d = diagonal(L.A);
     L.dinv.resize(d.size());
     for (size_t i = 0; i < d.size(); ++i) {
       if (d[i] == 0.0) return "zero diagonal in an AMG level matrix";
@@ -366,18 +381,19 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
     }
     H.levels.push_back(std::move(L));
     SaLevel& lev = H.levels.back();
-    const int64_t n = A.nrows;
+    const HCsr& Al = lev.A;
+    const int64_t n = Al.nrows;
     if (n <= prm.max_coarse || int(H.levels.size()) == prm.max_levels) break;
-    const double rho = spectral_radius(A, lev.dinv);
+    const double rho = spectral_radius(Al, lev.dinv);
     if (!(rho > 0.0) || !std::isfinite(rho)) return "non-finite spectral radius estimate";
     lev.omega = (4.0 / 3.0) / rho;
-    Strength S = strength(A, b, eps);
+    Strength S = strength(Al, b, eps);
     std::vector<int32_t> agg;
     const int64_t nagg = aggregate(S, n / b, agg);
     HCsr Pt;
     std::vector<double> Bc;
     tentative(agg, nagg, b, B, k, n, Pt, Bc);
-    HCsr AF = filtered(A, b, S);
+    HCsr AF = filtered(Al, b, S);
     std::vector<double> dF = diagonal(AF);
     std::vector<double> scale(n);
     for (int64_t i = 0; i < n; ++i) scale[i] = lev.omega / dF[i];
@@ -391,7 +407,7 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
       break;
     }
     HCsr R = transpose(P);
-    HCsr AP = spgemm(A, P);
+    HCsr AP = spgemm(Al, P);
     HCsr Ac = spgemm(R, AP);
     drop_zeros(Ac);
     // a coarse dof with an empty row (rank-deficient aggregate column) gets 1
