@@ -884,11 +884,11 @@ struct Precond {
   std::shared_ptr<DevBuf> tu, tu2, tv, tf, ta, ta2, tp, ts, ts2, tm, tm2, rT, zT;
   // inner GMRES of the fluid step (inner_k > 0): F, Arnoldi vectors V
   // ((k + 1) x n_f), preconditioned vectors Z (k x n_f), FP64 scalars,
-  // breakdown flags (ikact: one per step, and one for a zero residual)
+  // breakdown flags (ibrk: one per step, and one for a zero residual)
   int inner_k = 0;
   int inner_pc = FSI_INNER_UZAWA;
   DCsr<T> Fm;
-  std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ikact;
+  std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ibrk;
   int inner_nb = 1;
 
   void alloc_tmp() {
@@ -909,8 +909,8 @@ struct Precond {
       ipart->alloc(sizeof(double) * (kInnerMax + 1) * inner_nb);
       iscal = std::make_shared<DevBuf>();
       iscal->alloc(sizeof(double) * kInnerScal);
-      ikact = std::make_shared<DevBuf>();
-      ikact->alloc(sizeof(int) * (kInnerMax + 1));
+      ibrk = std::make_shared<DevBuf>();
+      ibrk->alloc(sizeof(int) * (kInnerMax + 1));
     }
   }
 
@@ -977,7 +977,7 @@ struct Precond {
     double* nn = a2 + (kInnerMax + 2);
     double* beta = nn + (kInnerMax + 2);
     double* Hm = beta + 1;
-    int* brk = ikact->as<int>();
+    int* brk = ibrk->as<int>();
     // ||r_f||^2 (r_f read as "w" with no update: the pass only reads it)
     inner_pass(0, 0, nullptr, const_cast<T*>(r_f), nn, s);
     inner_start_kernel<T><<<g, kBlock, 0, s>>>(n, nn, beta, brk, r_f, V);
