@@ -13,6 +13,10 @@ the near-nullspace, filtered Jacobi prolongator smoothing, Galerkin product):
 * omega = (4/3) / rho from the same power iteration within 1e-10;
 * P, R = P^T and the Galerkin products A_c have the same sparsity pattern and
   values within 1e-11 relative (different summation order).
+
+A second driver pins the coarsest-level inverse `fsi::dense_inverse` (LU with
+partial pivoting, threaded from 256 rows) against A X = I and numpy's inverse,
+and checks that a singular matrix is reported.
 """
 import os
 import subprocess
@@ -191,3 +195,79 @@ def test_library_sa_setup_matches_oracle(driver, name):
             assert abs(g["omega"] - o.omega) <= 1e-10 * o.omega, (hname, l, g["omega"], o.omega)
             assert _same(g["P"], o.P, 1e-11), (hname, l, "P")
             assert _same(g["R"], o.R, 1e-11), (hname, l, "R")
+
+
+INV_DRIVER = r"""
+#include <cstdio>
+#include <vector>
+#include "sa_setup.hpp"
+int main(int argc, char** argv) {
+  FILE* f = fopen(argv[1], "rb");
+  int64_t n;
+  if (fread(&n, 8, 1, f) != 1) return 2;
+  std::vector<double> a(size_t(n) * n), inv;
+  if (n && fread(a.data(), 8, a.size(), f) != a.size()) return 2;
+  fclose(f);
+  const int64_t ok = fsi::dense_inverse(a, n, inv) ? 1 : 0;
+  FILE* o = fopen(argv[2], "wb");
+  fwrite(&ok, 8, 1, o);
+  if (ok) fwrite(inv.data(), 8, inv.size(), o);
+  fclose(o);
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def inv_driver(tmp_path_factory):
+    d = tmp_path_factory.mktemp("denseinv")
+    src = d / "inv.cpp"
+    src.write_text(INV_DRIVER)
+    exe = d / "inv"
+    subprocess.run(["g++", "-std=c++17", "-O2", "-pthread", "-I", CSRC, str(src),
+                    os.path.join(CSRC, "sa_setup.cpp"), os.path.join(CSRC, "host_csr.cpp"), "-o", str(exe)],
+                   check=True)
+    return d, exe
+
+
+def _inverse(inv_driver, a):
+    d, exe = inv_driver
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    n = a.shape[0]
+    with open(d / "a.bin", "wb") as f:
+        np.array([n], np.int64).tofile(f)
+        a.tofile(f)
+    subprocess.run([str(exe), str(d / "a.bin"), str(d / "x.bin")], check=True)
+    raw = open(d / "x.bin", "rb").read()
+    ok = int(np.frombuffer(raw, np.int64, 1)[0])
+    return (np.frombuffer(raw, np.float64, n * n, 8).reshape(n, n) if ok else None)
+
+
+@pytest.mark.parametrize("n", [1, 3, 50, 300])
+def test_dense_inverse_of_the_coarsest_level(inv_driver, n):
+    """The coarsest-level inverse (LU with partial pivoting on the host, the
+    row updates and column solves shared among threads from 256 rows on):
+    A X = I and X = numpy's inverse within rounding, on nonsymmetric systems
+    that need row exchanges (a small diagonal)."""
+    rng = np.random.default_rng(n)
+    a = rng.standard_normal((n, n)) + n ** 0.5 * np.eye(n)
+    a[np.arange(n), np.arange(n)] *= 1e-3  # pivoting needed
+    a += 0.1 * n ** 0.5 * np.eye(n, k=1)
+    x = _inverse(inv_driver, a)
+    assert x is not None
+    cond = np.linalg.cond(a)
+    assert np.abs(a @ x - np.eye(n)).max() <= 1e-13 * cond
+    ref = np.linalg.inv(a)
+    assert np.abs(x - ref).max() <= 1e-13 * cond * np.abs(ref).max()
+
+
+def test_dense_inverse_refuses_a_singular_matrix(inv_driver):
+    """A zero pivot column (here a zero column, in the threaded size range
+    too) is reported, not divided by."""
+    for n in (4, 260):
+        a = np.random.default_rng(5).standard_normal((n, n))
+        a[:, n // 2] = 0.0
+        assert _inverse(inv_driver, a) is None, n
+    # a permutation matrix needs a row exchange at every step and is its own transpose's inverse
+    p = np.eye(6)[[3, 0, 5, 1, 4, 2]]
+    assert np.array_equal(_inverse(inv_driver, p), p.T)
