@@ -143,14 +143,15 @@ def test_pressure_schur_approximation():
     assert np.all(dA > 0)
 
 
-def test_simplec_pressure_schur_approximation():
+@pytest.mark.parametrize("name", ["c1", "tiny3d"])
+def test_simplec_pressure_schur_approximation(name):
     """SIMPLEC weights by the absolute row sums of A_f, which dominate its
     (positive) diagonal: the result is SPD, lies below the SIMPLE one in the
     Loewner order (S_simple - S_simplec = D (W_s^{-1} - W_c^{-1}) D^T >= 0), and
     with a diagonal A_f both are the exact Schur complement -D A_f^{-1} G."""
     import copy
     import scipy.sparse as sp
-    bs = _bs("c1")
+    bs = _bs(name)
     Ss = bs.fluid_schur("simple").toarray()
     Sc = bs.fluid_schur("simplec").toarray()
     assert np.abs(Sc - Sc.T).max() <= 1e-12 * np.abs(Sc).max()
@@ -262,7 +263,7 @@ def test_amg_preconditioned_solve_c1_inner_gmres():
     assert its[3] <= its[0], its
 
 
-@pytest.mark.parametrize("name", ["tiny2d_unit", "c1"])
+@pytest.mark.parametrize("name", ["tiny2d_unit", "tiny3d_unit", "c1"])
 def test_fluid_triangular_step_two_gmres_steps(name):
     """With exact inverses of A_f and of the Schur complement S = -D A_f^{-1} G
     the block upper-triangular step leaves F U^{-1} unit lower
