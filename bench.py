@@ -300,9 +300,11 @@ def main():
     if args.poly_on is None:
         args.poly_on = "" if args.learned else "H_MS"
     if args.poly_degree is None:
-        # two steps suffice for the 2D Q2 mass matrix (measured 23.4 vs 24.1 ms
-        # on the 256x64 system); the 3D one needs three (46 vs 78 iterations)
-        args.poly_degree = 2 if cfg.dim == 2 else 3
+        # three Chebyshev steps for the solid mass matrix: in 3D two raise the
+        # iterations from 46 to 78 (64x16x16); in 2D, with the inner fluid
+        # GMRES, three take 17/18/21 instead of 19/20/23 iterations (256x64:
+        # 11.5 vs 12.3 ms)
+        args.poly_degree = 3
     if args.fluid_inner is None:
         # two inner GMRES steps on the fluid block halve the 2D outer iterations
         # (256x64: 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms with the triangular

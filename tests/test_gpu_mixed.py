@@ -81,11 +81,11 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(name):
 
 def _bench_precond(dim):
     """The benchmarked preconditioner: Chebyshev(4) V-cycles on H_SIG (and on
-    H_P in 3D), M_s by two Chebyshev steps in 2D, three in 3D; in 2D the
+    H_P in 3D), M_s by three Chebyshev steps; in 2D the
     fluid inverse by two inner GMRES steps preconditioned by the block
     upper-triangular step."""
     return dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG",) if dim == 2 else ("H_SIG", "H_P"),
-                poly=("H_MS",), poly_degree=2 if dim == 2 else 3, fluid_inner=2 if dim == 2 else 0,
+                poly=("H_MS",), poly_degree=3, fluid_inner=2 if dim == 2 else 0,
                 fluid_inner_pc="triangular")
 
 

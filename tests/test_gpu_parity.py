@@ -407,13 +407,13 @@ def test_grouped_levels_match_oracle(name):
     assert plain - expect >= 5e-2 * expect  # the two layouts are told apart
 
 
-BENCH_OPTS = dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG",), poly=("H_MS",), poly_degree=2,
+BENCH_OPTS = dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG",), poly=("H_MS",), poly_degree=3,
                   fluid_inner=2, fluid_inner_pc="triangular")  # 2D
 
 
 def test_bench_configuration_full_size_matches_oracle():
     """The benchmarked workload and preconditioner (256x64 cells, Chebyshev
-    V-cycles on H_SIG, M_s by two Chebyshev steps, 2000-row coarse grids, the
+    V-cycles on H_SIG, M_s by three Chebyshev steps, 2000-row coarse grids, the
     fluid inverse by two inner GMRES steps preconditioned by the block
     upper-triangular step):
     the GPU solution reaches 1e-8 by the oracle's own mat-vec and agrees with
@@ -429,7 +429,7 @@ def test_bench_configuration_full_size_matches_oracle():
     xg = x.cpu().numpy()
     r = np.linalg.norm(sysm.b - bs.matvec(xg)) / np.linalg.norm(sysm.b)
     H = precond.build_hierarchies(bs, max_coarse=2000)
-    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4}, poly={"H_MS": (2, 8.0)}, fluid_inner=2,
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4}, poly={"H_MS": (3, 8.0)}, fluid_inner=2,
                                    fluid_inner_pc="triangular")
     xo, io = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-10, restart=50, maxit=500)
     err = _rel(xg, xo)
