@@ -300,7 +300,10 @@ def setup(A: sp.csr_matrix, block: int, B: np.ndarray, eps0: float = EPS0,
         agg, nagg = aggregate(n // b, ptr, nbr, sval)
         Pt, Bc = tentative(agg, nagg, b, Bl)
         AF = filtered(A, b, pairs)
-        scale = lev.omega / AF.diagonal()
+        dF = AF.diagonal()
+        if np.any(dF == 0.0):
+            raise ZeroDivisionError("zero diagonal in the filtered AMG matrix")
+        scale = lev.omega / dF
         P = (Pt - sp.diags(scale) @ (AF @ Pt)).tocsr()
         P.eliminate_zeros()
         P.sort_indices()

@@ -396,7 +396,12 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
     HCsr AF = filtered(Al, b, S);
     std::vector<double> dF = diagonal(AF);
     std::vector<double> scale(n);
-    for (int64_t i = 0; i < n; ++i) scale[i] = lev.omega / dF[i];
+    for (int64_t i = 0; i < n; ++i) {
+      // lumping weak entries can cancel a diagonal: the damped smoothing step
+      // is then undefined
+      if (dF[i] == 0.0) return "zero diagonal in the filtered AMG matrix";
+      scale[i] = lev.omega / dF[i];
+    }
     HCsr T = spgemm(AF, Pt);
     scale_rows(T, scale);
     HCsr P = add(Pt, T, -1.0);
