@@ -30,6 +30,65 @@ def spmv(A: sp.csr_matrix, x: np.ndarray) -> np.ndarray:
     return np.bincount(rows, weights=A.data * x[A.indices], minlength=A.shape[0])
 
 
+class FluidBlock:
+    """A fluid operator in saddle form [[A_f, G], [D, Z]] over (v_f | p): the
+    fluid block F of A_h (Z empty) or an approximation of the Schur
+    complement X of Section 4.1 (BlockSystem.fluid_x)."""
+
+    def __init__(self, F: sp.csr_matrix, n_vf: int):
+        self.F = F.tocsr()
+        self.F.sort_indices()
+        self.n_vf = n_vf
+        self.A_f = self.F[:n_vf, :n_vf].tocsr()
+        self.G = self.F[:n_vf, n_vf:].tocsr()
+        self.D = self.F[n_vf:, :n_vf].tocsr()
+        self.F_pp = self.F[n_vf:, n_vf:].tocsr()
+        for m in (self.A_f, self.G, self.D, self.F_pp):
+            m.sort_indices()
+
+    def schur(self, variant: str = "simple") -> sp.csr_matrix:
+        """S_p = Z - D W^{-1} G, a pressure Schur approximation.
+
+        The paper applies to the fluid block the same Schur-complement
+        elimination as for the solid (Section 4.4) without stating the
+        approximation; this is the reading recorded in the design notes.
+        variant "simple": W = diag(A_f) (SIMPLE); "simplec": W = the diagonal
+        of the absolute row sums sum_j |a_ij| of A_f (SIMPLEC, one of the
+        alternatives the paper lists as open).
+        Pinned: both equal the exact Schur complement Z - D A_f^{-1} G when A_f
+        is diagonal with a positive diagonal (test), and are symmetric because
+        G = -D^T (F itself, Z = 0).
+        """
+        if variant == "simple":
+            dinv = 1.0 / self.A_f.diagonal()
+        elif variant == "simplec":
+            dinv = 1.0 / np.asarray(abs(self.A_f).sum(axis=1)).ravel()
+        else:
+            raise ValueError(f"unknown Schur variant {variant!r}")
+        m = (-(self.D @ sp.diags(dinv) @ self.G)).tocsr()
+        if self.F_pp.nnz:
+            m = (m + self.F_pp).tocsr()
+        m.eliminate_zeros()
+        m.sort_indices()
+        return m
+
+
+def node_block_inverse(A: sp.csr_matrix, b: int) -> sp.csr_matrix:
+    """Inverse of the node-block diagonal of A: the entries (i, j) with
+    i // b == j // b, inverted b x b block by block (dense numpy inverses)."""
+    n = A.shape[0]
+    Ad = A.tocoo()
+    keep = (Ad.row // b) == (Ad.col // b)
+    blocks = np.zeros((n // b, b, b))
+    blocks[Ad.row[keep] // b, Ad.row[keep] % b, Ad.col[keep] % b] = Ad.data[keep]
+    inv = np.linalg.inv(blocks)
+    rows = (np.arange(n // b)[:, None, None] * b + np.arange(b)[None, :, None]) + np.zeros((1, 1, b), dtype=int)
+    cols = (np.arange(n // b)[:, None, None] * b + np.arange(b)[None, None, :]) + np.zeros((1, b, 1), dtype=int)
+    m = sp.csr_matrix((inv.ravel(), (rows.ravel(), cols.ravel())), shape=(n, n))
+    m.sort_indices()
+    return m
+
+
 class BlockSystem:
     """A_h with its block views, built from one fsigen.FsiSystem."""
 
@@ -49,12 +108,14 @@ class BlockSystem:
         self.S_uv = S[nvs:, :nvs].tocsr()
         self.S_uu = S[nvs:, nvs:].tocsr()
         # fluid sub-blocks over (v_f | p)
-        self.A_f = F[:nvf, :nvf].tocsr()
-        self.G = F[:nvf, nvf:].tocsr()
-        self.D = F[nvf:, :nvf].tocsr()
-        self.F_pp = F[nvf:, nvf:].tocsr()
-        for m in (self.S_vv, self.S_vu, self.S_uv, self.S_uu, self.A_f, self.G, self.D, self.F_pp):
+        self.fluid = FluidBlock(F, nvf)
+        self.A_f, self.G, self.D, self.F_pp = self.fluid.A_f, self.fluid.G, self.fluid.D, self.fluid.F_pp
+        for m in (self.S_vv, self.S_vu, self.S_uv, self.S_uu):
             m.sort_indices()
+
+    @property
+    def F(self) -> sp.csr_matrix:
+        return self.B["F"]
 
     # -- splitting ---------------------------------------------------------
     def split(self, x):
@@ -102,30 +163,37 @@ class BlockSystem:
         return m
 
     def fluid_schur(self, variant: str = "simple") -> sp.csr_matrix:
-        """S_p = -D W^{-1} G, a pressure Schur approximation.
+        """The pressure Schur approximation of F (FluidBlock.schur)."""
+        return self.fluid.schur(variant)
 
-        The paper applies to the fluid block the same Schur-complement
-        elimination as for the solid (Section 4.4) without stating the
-        approximation; this is the reading recorded in the design notes.
-        variant "simple": W = diag(A_f) (SIMPLE); "simplec": W = the diagonal
-        of the absolute row sums sum_j |a_ij| of A_f (SIMPLEC, one of the
-        alternatives the paper lists as open).
-        Pinned: both equal the exact Schur complement -D A_f^{-1} G when A_f is
-        diagonal with a positive diagonal (test), and are symmetric because
-        G = -D^T.
-        """
-        if variant == "simple":
-            dinv = 1.0 / self.A_f.diagonal()
-        elif variant == "simplec":
-            dinv = 1.0 / np.asarray(abs(self.A_f).sum(axis=1)).ravel()
-        else:
-            raise ValueError(f"unknown Schur variant {variant!r}")
-        m = (-(self.D @ sp.diags(dinv) @ self.G)).tocsr()
-        if self.F_pp.nnz:
-            m = (m + self.F_pp).tocsr()
-        m.eliminate_zeros()
-        m.sort_indices()
-        return m
+    def fluid_x(self, approx: str = "F") -> FluidBlock:
+        """The fluid operator that the preconditioner inverts in place of the
+        Schur complement X = F - C~_fs S^{-1} C_sf, C~_fs = C_fs - C_fm M^{-1}
+        C_ms, of the factorisation in Section 4.1 (garbled there; the reading
+        in the design notes).
+
+        approx "F": X ~ F, the perturbation dropped (the paper's choice, and
+        the algorithm "Evaluation of P^{-1} r").  approx "blockdiag": S and M
+        replaced by their node-block diagonals (d x d blocks of each field,
+        per node), which are inverted exactly: X ~ F - C~ D_S^{-1} C_sf with
+        C~ = C_fs - C_fm D_M^{-1} C_ms (the block-diagonal approximation the
+        paper cites from Langer and Yang, 2016).  Here the C_fm D_M^{-1} C_ms
+        part adds nothing: C_ms reads only u_s, while D_S^{-1} C_sf has only
+        v_s rows (the u_s rows of C_sf, the solid kinematics, hold no fluid
+        entries, and D_S does not mix the fields).  Pinned: with S and M block
+        diagonal themselves it is the exact X (dense test)."""
+        if approx == "F":
+            return self.fluid
+        if approx != "blockdiag":
+            raise ValueError(f"unknown approximation of X {approx!r}")
+        B = self.B
+        d = self.dim
+        DSi = node_block_inverse(B["S"], d)
+        DMi = node_block_inverse(B["M"], d)
+        Ct = (B["C_fs"] - B["C_fm"] @ DMi @ B["C_ms"]).tocsr()
+        X = (B["F"] - Ct @ DSi @ B["C_sf"]).tocsr()
+        X.eliminate_zeros()
+        return FluidBlock(X, self.n_vf)
 
     def mesh_scalar(self) -> sp.csr_matrix:
         """Scalar Laplacian L with M = L (x) I_d (frozen Jacobian-scaled mesh).

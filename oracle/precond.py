@@ -42,9 +42,10 @@ H_NAMES = ("H_M", "H_SIG", "H_MS", "H_A", "H_P")
 
 
 def build_hierarchies(bs: BlockSystem, eps0=amg.EPS0, max_coarse=amg.MAX_COARSE,
-                      max_levels=amg.MAX_LEVELS, schur: str = "simple") -> dict:
+                      max_levels=amg.MAX_LEVELS, schur: str = "simple", x_approx: str = "F") -> dict:
     """The five SA hierarchies of the preconditioner (`schur`: the pressure
-    Schur approximation, see BlockSystem.fluid_schur)."""
+    Schur approximation, see FluidBlock.schur; `x_approx`: the fluid operator
+    standing for the Schur complement X, see BlockSystem.fluid_x)."""
     d = bs.dim
     sysm = bs.sys
     o = sysm.offsets
@@ -53,12 +54,13 @@ def build_hierarchies(bs: BlockSystem, eps0=amg.EPS0, max_coarse=amg.MAX_COARSE,
     xyz = sysm.coords[vs_nodes]
     kw = dict(eps0=eps0, max_coarse=max_coarse, max_levels=max_levels)
     L = bs.mesh_scalar()
+    fl = bs.fluid_x(x_approx)
     H = {
         "H_M": amg.setup(L, 1, amg.constant_modes(L.shape[0]), **kw),
         "H_SIG": amg.setup(bs.solid_schur(), d, amg.rigid_body_modes(xyz), **kw),
         "H_MS": amg.setup(bs.S_uu, 1, amg.constant_modes(bs.n_vs), **kw),
-        "H_A": amg.setup(bs.A_f, d, amg.translation_modes(bs.n_vf // d, d), **kw),
-        "H_P": amg.setup(bs.fluid_schur(schur), 1, amg.constant_modes(bs.n_p), **kw),
+        "H_A": amg.setup(fl.A_f, d, amg.translation_modes(bs.n_vf // d, d), **kw),
+        "H_P": amg.setup(fl.schur(schur), 1, amg.constant_modes(bs.n_p), **kw),
     }
     return H
 
@@ -134,7 +136,7 @@ def fluid_gmres_solve(bs: BlockSystem, uzawa, r_f: np.ndarray, k: int) -> np.nda
     Arnoldi vectors v_j."""
     if k < 1:
         raise ValueError("inner GMRES needs k >= 1 steps")
-    F = bs.B["F"]
+    F = bs.F
     x, _ = krylov.fgmres(lambda v: F @ v, uzawa, r_f, tol=INNER_TOL, restart=k, maxit=k)
     return x
 
@@ -149,7 +151,7 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
 
 
 def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None,
-                       fluid_inner: int = 0, fluid_inner_pc: str = "uzawa") -> BlockLDU:
+                       fluid_inner: int = 0, fluid_inner_pc: str = "uzawa", x_approx: str = "F") -> BlockLDU:
     """The preconditioner of the hot path: every inverse one V(1,1) cycle
     (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
     named in `cheb`).  For the names in `poly`, {name: (k, ratio)}, the
@@ -157,8 +159,12 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     grid), on [lam/ratio, lam] with lam = 1.1 rho of that level.  With
     fluid_inner = k > 0 the fluid inverse is k inner GMRES steps
     preconditioned by the Uzawa-like step (fluid_inner_pc = "uzawa") or by
-    the block upper-triangular step ("triangular")."""
+    the block upper-triangular step ("triangular").  x_approx: the fluid
+    operator those steps invert in place of the Schur complement X (F, or
+    its block-diagonal approximation; the hierarchies H must be built with
+    the same choice)."""
     cheb = cheb or {}
+    fl = bs.fluid_x(x_approx)
     poly = poly or {}
 
     def inv(name, h):
@@ -174,14 +180,14 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     V = {k: inv(k, h) for k, h in H.items()}
     mesh = lambda r: mesh_solve(bs, V["H_M"], r)
     solid = lambda r: solid_schur_solve(bs, V["H_MS"], V["H_SIG"], r)
-    uzawa = lambda r: fluid_schur_solve(bs, V["H_A"], V["H_P"], r)
+    uzawa = lambda r: fluid_schur_solve(fl, V["H_A"], V["H_P"], r)
     fluid = uzawa
     if fluid_inner > 0:
         if fluid_inner_pc == "uzawa":
             inner = uzawa
         elif fluid_inner_pc == "triangular":
-            inner = lambda r: fluid_triangular_solve(bs, V["H_A"], V["H_P"], r)
+            inner = lambda r: fluid_triangular_solve(fl, V["H_A"], V["H_P"], r)
         else:
             raise ValueError(f"unknown inner fluid preconditioner {fluid_inner_pc!r}")
-        fluid = lambda r: fluid_gmres_solve(bs, inner, r, fluid_inner)
+        fluid = lambda r: fluid_gmres_solve(fl, inner, r, fluid_inner)
     return BlockLDU(bs, mesh, solid, fluid)
