@@ -25,7 +25,9 @@ with the approximate inverses
   is k steps of flexible GMRES on F from zero, right-preconditioned by that
   Uzawa-like step or by the cheaper block upper-triangular step
       x_p = V_p(r_p);  x_v = V_A(r_v - G x_p)
-  (fluid_gmres_solve, fluid_triangular_solve).
+  (fluid_gmres_solve, fluid_triangular_solve).  Or, as Section 4.4 reads,
+  the Uzawa-like step itself with each occurring inverse approximated by k
+  GMRES steps preconditioned by its V-cycle (fluid_schur_gmres_solve).
 """
 from __future__ import annotations
 
@@ -141,6 +143,26 @@ def fluid_gmres_solve(bs: BlockSystem, uzawa, r_f: np.ndarray, k: int) -> np.nda
     return x
 
 
+def gmres_steps(A, pc, b: np.ndarray, k: int) -> np.ndarray:
+    """k steps of right-preconditioned GMRES on A x = b from x = 0 with the
+    preconditioner pc (stopping before k steps only at an exact solve)."""
+    if k < 1:
+        raise ValueError("GMRES needs k >= 1 steps")
+    x, _ = krylov.fgmres(lambda v: A @ v, pc, b, tol=INNER_TOL, restart=k, maxit=k)
+    return x
+
+
+def fluid_schur_gmres_solve(fl, S_p, a_pc, p_pc, r_f: np.ndarray, k: int) -> np.ndarray:
+    """Section 4.4 as written: the Uzawa-like elimination of the fluid saddle
+    point with every occurring inverse approximated by AMG-preconditioned
+    GMRES, here k steps from zero each: A_f^{-1} (twice) by GMRES on A_f
+    preconditioned by the A_f V-cycle a_pc, S_p^{-1} by GMRES on the explicit
+    pressure Schur approximation S_p preconditioned by its V-cycle p_pc."""
+    a_inv = lambda b: gmres_steps(fl.A_f, a_pc, b, k)
+    p_inv = lambda b: gmres_steps(S_p, p_pc, b, k)
+    return fluid_schur_solve(fl, a_inv, p_inv, r_f)
+
+
 def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
     """M^{-1} r_m with M = L (x) I_d: the scalar inverse per component."""
     d = bs.dim
@@ -151,7 +173,8 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
 
 
 def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None,
-                       fluid_inner: int = 0, fluid_inner_pc: str = "uzawa", x_approx: str = "F") -> BlockLDU:
+                       fluid_inner: int = 0, fluid_inner_pc: str = "uzawa", x_approx: str = "F",
+                       uzawa_inner: int = 0) -> BlockLDU:
     """The preconditioner of the hot path: every inverse one V(1,1) cycle
     (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
     named in `cheb`).  For the names in `poly`, {name: (k, ratio)}, the
@@ -162,7 +185,9 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     the block upper-triangular step ("triangular").  x_approx: the fluid
     operator those steps invert in place of the Schur complement X (F, or
     its block-diagonal approximation; the hierarchies H must be built with
-    the same choice)."""
+    the same choice).  uzawa_inner = k > 0: the Uzawa-like step with every
+    occurring inverse taken as k GMRES steps preconditioned by its V-cycle
+    (fluid_schur_gmres_solve; not combined with fluid_inner)."""
     cheb = cheb or {}
     fl = bs.fluid_x(x_approx)
     poly = poly or {}
@@ -182,6 +207,11 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     solid = lambda r: solid_schur_solve(bs, V["H_MS"], V["H_SIG"], r)
     uzawa = lambda r: fluid_schur_solve(fl, V["H_A"], V["H_P"], r)
     fluid = uzawa
+    if uzawa_inner > 0:
+        if fluid_inner > 0:
+            raise ValueError("inner GMRES on F and on the Uzawa step's inverses do not combine")
+        S_p = H["H_P"].levels[0].A
+        fluid = lambda r: fluid_schur_gmres_solve(fl, S_p, V["H_A"], V["H_P"], r, uzawa_inner)
     if fluid_inner > 0:
         if fluid_inner_pc == "uzawa":
             inner = uzawa
