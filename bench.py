@@ -3,13 +3,18 @@
 
 One step = one full FGMRES(50) solve of A_h x = b to a 1e-8 true relative
 residual (x0 = 0), right-preconditioned by the block-LDU algorithm with AMG
-V(1,1) sub-inverses, on the 2D 256x64-cell Q2/Q1 FSI Jacobian (seeded,
-synthetic), inputs resident in HBM.  The preconditioner build (host AMG setup
-+ upload) is reported separately and is not part of a step.
+sub-inverses, inputs resident in HBM.  Default workload: the 3D
+128x32x32-cell Q2/Q1 FSI Jacobian (6.2M unknowns, 1.44e9 entries; seeded,
+synthetic), FP64 throughout.  The preconditioner build (host AMG setup +
+upload) is reported separately and is not part of a step.
 
 Prints one JSON line.  Extra objects: ``roofline`` for the dominant kernel
-(the monolithic A_h CSR product, timed with HIP events on the solver's
-stream), ``cpu_baseline`` (the CPU oracle on a bounded sample, rank 0 only).
+(the A_h block product, timed with HIP events on the solver's stream),
+``vcycle_H_A`` (one V-cycle of the largest hierarchy), ``mixed`` (the same
+solve with the FP32 preconditioner, with and without BF16-stored smoother
+diagonals, against the FP64 solve), ``gpu_c3`` (the 64x16x16-cell system on
+the GPU, the configuration the CPU oracle is timed on) and ``cpu_baseline``
+(the CPU oracle on a bounded sample, rank 0 only).
 """
 import argparse
 import json
@@ -43,46 +48,69 @@ def csr_bytes(sysm) -> float:
     return 12.0 * nnz + 8.0 * (N + 1) + 8.0 * N + 8.0 * N
 
 
-def cpu_baseline(sysm, gpu_iters: int, args, sample_iters: int = 25):
-    """The CPU oracle, as it stands, on a bounded sample: its AMG setup and
-    `sample_iters` FGMRES iterations with the benchmarked preconditioner
-    (same coarse-grid bound and smoothers); the per-iteration time is scaled
-    to the GPU's iteration count on the same system."""
-    import numpy as np
+def cpu_baseline(args, gpu_c3=None, sample_iters: int = 2):
+    """The CPU oracle, as it stands, on a bounded sample.
+
+    The oracle (numpy/scipy, one thread) cannot build its AMG hierarchies for
+    the 128x32x32 system within the benchmark's time, so its sample is the
+    64x16x16-cell system (configuration c3, seed 0) with the benchmarked
+    preconditioner: the AMG setup (timed, not counted) and `sample_iters`
+    FGMRES iterations; the per-iteration time is scaled to the GPU's
+    iteration count on that same system (``gpu_c3``), giving ms per c3 solve.
+    No scaling across configurations."""
+    import platform
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
         threadpool_limits = None
+    import fsigen
     from oracle import blocks, krylov, precond
+    cfg = fsigen.config("c3")
+    sysm = fsigen.generate(cfg, seed=0)
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         bs = blocks.BlockSystem(sysm)
         t0 = time.perf_counter()
         H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=args.schur)
         t_setup = time.perf_counter() - t0
-        cheb = {h: args.cheb for h in cheb_on(args)} if args.cheb > 0 else None
-        poly = {h: (args.poly_degree, args.poly_ratio) for h in poly_on(args)}
-        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=args.fluid_inner,
-                                       fluid_inner_pc=args.fluid_inner_pc)
+        o = precond_opts(args, cfg.dim)
+        cheb = {h: o["cheb_degree"] for h in o["cheb"]} if o["cheb_degree"] > 0 else None
+        poly = {h: (o["poly_degree"], o["poly_ratio"]) for h in o["poly"]}
+        P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=o["fluid_inner"],
+                                       fluid_inner_pc=o["fluid_inner_pc"])
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
         t_iter = (time.perf_counter() - t0) / max(info.iters, 1)
     finally:
         if ctx is not None:
             ctx.__exit__(None, None, None)
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    iters = gpu_c3["iters"] if gpu_c3 else None
     return {
-        "value": round(t_iter * gpu_iters * 1e3, 1),
+        "value": round(t_iter * iters * 1e3, 1) if iters else None,
         "unit": "ms",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"oracle AMG setup ({t_setup:.1f} s, not counted) + {info.iters} FGMRES iterations "
-                  f"on the seed-{sysm.seed} system ({t_iter * 1e3:.0f} ms/iteration, numpy/scipy, 1 thread), "
-                  f"scaled to the {gpu_iters} iterations of the GPU's solve of it",
+        "config": "c3: 3D FSI Jacobian 64x16x16 Q2/Q1 cells, seed 0 (N=%d, nnz=%d)" % (sysm.N, sysm.nnz),
+        "sample": f"oracle AMG setup of c3 ({t_setup:.1f} s, not counted) + {info.iters} FGMRES iterations "
+                  f"({t_iter * 1e3:.0f} ms/iteration, numpy/scipy on 1 thread), scaled to the {iters} iterations "
+                  f"of the GPU's solve of the same c3 system: ms per c3 solve, compare with gpu_c3.ms",
+        "host": {"nproc": os.cpu_count(), "cpu": cpu, "python": platform.python_version()},
     }
 
 
+_T0 = time.perf_counter()
+
+
 def progress(msg: str) -> None:
-    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+    print(f"[bench {time.perf_counter() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
 
 
 def cheb_on(args) -> tuple:
@@ -138,12 +166,7 @@ def learned_run(args, cfg):
     progress(f"{cfg.name}: training on {len(train)} Newton systems, evaluating {len(evals)}")
     sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
     solver = FsiSolver.from_system(sysm, device=0, stream=stream)
-    solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
-                             cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner,
-                             fluid_inner_pc=args.fluid_inner_pc)
+    solver.build_precond(args.precision, **precond_opts(args, cfg.dim))
     d = sysm.dim
     W = he_init(3 ** d * d, 64, d, seed=args.seed)
     for which in ("H_M", "H_SIG"):
@@ -154,12 +177,7 @@ def learned_run(args, cfg):
         if n:
             sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
             solver.set_from_system(sysm)
-            solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
-                             cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner,
-                             fluid_inner_pc=args.fluid_inner_pc)
+            solver.build_precond(args.precision, **precond_opts(args, cfg.dim))
         b = torch.from_numpy(sysm.b).to(dev)
         _, info = solver.solve(b)
         progress(f"recorded step {k} solve {i}: {info.iters} iterations")
@@ -174,12 +192,7 @@ def learned_run(args, cfg):
     for k, i in evals:
         sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
         solver.set_from_system(sysm)
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
-                             cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner,
-                             fluid_inner_pc=args.fluid_inner_pc)
+        solver.build_precond(args.precision, **precond_opts(args, cfg.dim))
         b = torch.from_numpy(sysm.b).to(dev)
         res = {}
         for mode in ("plain", "learned"):
@@ -230,17 +243,75 @@ def learned_run(args, cfg):
     print(json.dumps(line), flush=True)
 
 
+def precond_opts(args, dim: int) -> dict:
+    """build_precond keyword arguments of the benchmarked preconditioner for a
+    workload of dimension `dim` (defaults resolved in main)."""
+    cheb_on = args.cheb_on_arg if args.cheb_on_arg is not None else ("H_MS,H_SIG" if dim == 2 else "H_MS,H_SIG,H_P")
+    fluid_inner = (args.fluid_inner_arg if args.fluid_inner_arg is not None
+                   else (2 if dim == 2 and not args.learned else 0))
+    poly = poly_on(args)
+    return dict(max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
+                cheb=tuple(h for h in cheb_on.split(",") if h and h not in poly), poly=poly,
+                poly_degree=args.poly_degree, poly_ratio=args.poly_ratio, schur=args.schur,
+                fluid_inner=fluid_inner, fluid_inner_pc=args.fluid_inner_pc)
+
+
+def workload_name(cfg) -> str:
+    cells = "x".join(map(str, cfg.cells))
+    return f"{cfg.dim}D FSI Jacobian {cells} Q2/Q1 cells"
+
+
+def cycle_ms(solver, hn, dim, stream, reps=50):
+    """Average time of one V-cycle of hierarchy hn, back to back (HIP events
+    on the solver's stream)."""
+    import torch
+    nv = int(solver.hierarchy_info(hn)[0][0]) * (dim if hn == "H_M" else 1)
+    bv = torch.randn(nv, dtype=torch.float64, device="cuda:0")
+    xv = torch.empty_like(bv)
+    for _ in range(5):
+        solver.vcycle(hn, bv, xv)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        solver.vcycle(hn, bv, xv)
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def timed_solves(solver, b, x, k):
+    """k solves from x0 = 0, each bracketed by device synchronisations;
+    returns (ms list, last info)."""
+    import torch
+    times, info = [], None
+    for _ in range(k):
+        x.zero_()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info = solver.solve(b, x)
+        torch.cuda.synchronize()
+        times.append((time.perf_counter() - t0) * 1e3)
+        if not info.converged:
+            raise SystemExit(f"solve did not converge: {info}")
+    return times, info
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=6)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c4",
+                    help="workload: c4 (3D 128x32x32, the default), c3 (3D 64x16x16), c2 (2D 256x64), ...")
     ap.add_argument("--seed", type=int, default=0, help="seed of the learned-smoother workload")
-    ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1, 2],
-                    help="seeds of the linearisation state; the timed solves cycle through them")
+    ap.add_argument("--seeds", type=int, nargs="+", default=None,
+                    help="seeds of the linearisation state; the timed solves cycle through them "
+                         "(default 0 on c4, 0 1 2 otherwise)")
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f32-bf16diag"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true",
+                    help="skip the FP32-preconditioner solves reported beside the FP64 ones")
     ap.add_argument("--cheb", type=int, default=None,
                     help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
                          "default 4, and 0 with --learned (the learned smoother replaces a Jacobi sweep)")
@@ -256,16 +327,15 @@ def main():
                     help="pressure Schur approximation -D W^{-1} G: W = diag(A_f) (simple) or its "
                          "absolute row sums (simplec); default simple")
     ap.add_argument("--fluid-inner", type=int, default=None,
-                    help="inner flexible GMRES steps for the fluid inverse, preconditioned by the "
-                         "Uzawa-like step (0: the Uzawa-like step alone; default 2 in 2D, 0 in 3D "
-                         "and with --learned)")
+                    help="inner flexible GMRES steps for the fluid inverse (0: the Uzawa-like step "
+                         "alone; default 2 in 2D, 0 in 3D and with --learned)")
     ap.add_argument("--fluid-inner-pc", default="triangular", choices=["uzawa", "triangular"],
                     help="preconditioner of the inner fluid GMRES: the Uzawa-like step or the block "
                          "upper-triangular step (one A_f V-cycle fewer; default)")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
-                    help="Chebyshev-alone steps (default: 2 in 2D, 3 in 3D)")
+                    help="Chebyshev-alone steps (default 3)")
     ap.add_argument("--poly-ratio", type=float, default=8.0,
                     help="Chebyshev-alone inverses: interval [lam/ratio, lam]")
     ap.add_argument("--learned", action="store_true",
@@ -281,18 +351,20 @@ def main():
                     help="only launch the A_h product 20 times and a 256 MiB device copy "
                          "(for hardware byte counters); prints nothing else")
     args = ap.parse_args()
+    args.cheb_on_arg, args.fluid_inner_arg = args.cheb_on, args.fluid_inner
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     import fsigen
     from paper_1801_05648_amd import FsiSolver
 
     cfg = fsigen.config(args.config)
+    if args.seeds is None:
+        args.seeds = [0] if cfg.name == "c4" else [0, 1, 2]
     if args.cheb is None:
         args.cheb = 0 if args.learned else 4
     if args.max_coarse is None:
@@ -305,24 +377,22 @@ def main():
         # GMRES, three take 17/18/21 instead of 19/20/23 iterations (256x64:
         # 11.5 vs 12.3 ms)
         args.poly_degree = 3
-    if args.fluid_inner is None:
-        # two inner GMRES steps on the fluid block halve the 2D outer iterations
-        # (256x64: 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms with the triangular
-        # inner step, 14.4 ms with the Uzawa-like one).  In 3D the Uzawa-like
-        # steps cut iterations but not time (64x16x16: 46 -> 31 iterations,
-        # 93.8 -> 103.8 ms); two triangular ones give 33 iterations, 85.3 ms
-        # there, but stay an option until measured on the 128x32x32 system
-        args.fluid_inner = 2 if cfg.dim == 2 and not args.learned else 0
+    # fluid_inner: two inner GMRES steps on the fluid block halve the 2D outer
+    # iterations (256x64: 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms with the
+    # triangular inner step, 14.4 ms with the Uzawa-like one).  In 3D the
+    # Uzawa-like steps cut iterations but not time (64x16x16: 46 -> 31
+    # iterations, 93.8 -> 103.8 ms).
     if args.schur is None:
         # SIMPLE throughout: SIMPLEC (absolute row sums) cuts the 64x16x16
         # solve from 46 to 36 iterations but raises the 128x32x32 one from 47
         # to 68 and the 2D one from 39 to 69 (oracle), so it stays an option
         args.schur = "simple"
-    if args.cheb_on is None:
-        # the 2D pressure Schur approximation does best with Jacobi sweeps
-        # (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one
-        # needs the Chebyshev sweeps (64x16x16: 46 vs 530 iterations)
-        args.cheb_on = "H_MS,H_SIG" if cfg.dim == 2 else "H_MS,H_SIG,H_P"
+    # cheb_on: the 2D pressure Schur approximation does best with Jacobi
+    # sweeps (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one
+    # needs the Chebyshev sweeps (64x16x16: 46 vs 530 iterations)
+    opts = precond_opts(args, cfg.dim)
+    args.cheb_on = ",".join(opts["cheb"])
+    args.fluid_inner = opts["fluid_inner"]
     if args.learned:
         learned_run(args, cfg)
         return
@@ -336,11 +406,7 @@ def main():
         # the counter scale
         sysm = fsigen.generate(cfg, seed=args.seeds[0])
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
-                             cheb=cheb_on(args), poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner,
-                             fluid_inner_pc=args.fluid_inner_pc)
+        solver.build_precond(args.precision, **opts)
         hn = args.pmc_vcycle
         nv = int(solver.hierarchy_info(hn)[0][0]) * (sysm.dim if hn == "H_M" else 1)
         bv = torch.randn(nv, dtype=torch.float64, device=dev)
@@ -368,7 +434,8 @@ def main():
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
-        print(json.dumps({"pmc_probe": True, "spmv_bytes": solver.spmv_bytes(), "csr_bytes": csr_bytes(sysm), "copy_bytes": 2 * 256 * 2 ** 20}))
+        print(json.dumps({"pmc_probe": True, "spmv_bytes": solver.spmv_bytes(), "csr_bytes": csr_bytes(sysm),
+                          "copy_bytes": 2 * 256 * 2 ** 20}))
         solver.close()
         return
     # one solver per seed of the linearisation state, built and warmed up
@@ -379,13 +446,9 @@ def main():
         sysm = fsigen.generate(cfg, seed=sd)
         progress(f"N={sysm.N} nnz={sysm.nnz}")
         solver = FsiSolver.from_system(sysm, device=0, stream=stream)
+        progress("blocks copied and checked")
         t0 = time.perf_counter()
-        solver.build_precond(args.precision, max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
-                             cheb=cheb_on(args),
-                             poly=poly_on(args), poly_degree=args.poly_degree,
-                             poly_ratio=args.poly_ratio, schur=args.schur,
-                             fluid_inner=args.fluid_inner,
-                             fluid_inner_pc=args.fluid_inner_pc)
+        solver.build_precond(args.precision, **opts)
         torch.cuda.synchronize()
         setup_ms = (time.perf_counter() - t0) * 1e3
         progress(f"seed {sd}: preconditioner built in {setup_ms:.0f} ms")
@@ -399,8 +462,7 @@ def main():
             solver.solve(b, x, timing=True)
         runs.append({"seed": sd, "sysm": sysm, "solver": solver, "b": b, "x": x, "setup_ms": setup_ms,
                      "N": sysm.N, "nnz": sysm.nnz, "bytes": solver.spmv_bytes(), "csr_bytes": csr_bytes(sysm)})
-        if len(runs) > 1:
-            sysm.blocks = None  # host copy of the matrix no longer needed
+        sysm.blocks = None  # the host copy of the matrix is no longer needed
     torch.cuda.synchronize()
     sysm = runs[0]["sysm"]
     solver = runs[0]["solver"]
@@ -423,13 +485,15 @@ def main():
             raise SystemExit(f"solve did not converge: {info}")
     t_all = (time.perf_counter() - t_all) * 1e3
     ms = statistics.mean(times)
+    progress(f"timed: {ms:.3f} ms per solve")
 
     # The same K solves again with the phases separated by HIP events on the
     # solver's stream (the timed mode splits each step's graph into a
     # preconditioner graph, the A_h product launch and a Gram-Schmidt graph,
-    # which costs about 4% per solve, so it stays out of the timed region).
-    # Dominant kernel: the A_h product, every launch of it bracketed.
+    # which costs a few percent per solve, so it stays out of the timed
+    # region).  Dominant kernel: the A_h product, every launch of it bracketed.
     t_pre = t_spmv = t_gs = 0.0
+    b_pre = b_steps = 0.0
     n_timed = 0
     nbytes_sum = 0.0
     times_instr = []
@@ -445,6 +509,8 @@ def main():
         if info.iters != r["iters"]:
             raise SystemExit(f"instrumented solve took {info.iters} iterations, timed one {r['iters']}")
         t_pre += info.t_precond_ms
+        b_pre += info.bytes_precond
+        b_steps += info.bytes_precond / r["solver"].precond_bytes()  # Arnoldi steps launched
         t_spmv += info.t_spmv_ms
         t_gs += info.t_gs_ms
         n_timed += info.n_timed
@@ -452,32 +518,14 @@ def main():
     nbytes = nbytes_sum / max(args.steps, 1)  # all seeds share the sparsity pattern
     achieved = nbytes / (spmv_ms * 1e-3) / 1e9
 
-    def cycle_ms(hn):
-        """Average time of one cycle of hierarchy hn, back to back (events on
-        the solver's stream)."""
-        nv = int(solver.hierarchy_info(hn)[0][0]) * (sysm.dim if hn == "H_M" else 1)
-        bv = torch.randn(nv, dtype=torch.float64, device=dev)
-        xv = torch.empty_like(bv)
-        for _ in range(5):
-            solver.vcycle(hn, bv, xv)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        reps = 50
-        for _ in range(reps):
-            solver.vcycle(hn, bv, xv)
-        e1.record(stream)
-        e1.synchronize()
-        return e0.elapsed_time(e1) / reps
-
     # one V(1,1) cycle of the fluid-velocity hierarchy (largest V-cycle),
-    # bytes as executed by the level kernels
-    vc_ms = cycle_ms("H_A")
+    # bytes as executed by the level kernels, and of the solid Schur
+    # hierarchy (small, latency-bound levels)
+    vc_ms = cycle_ms(solver, "H_A", sysm.dim, stream)
     vc_bytes = solver.vcycle_bytes("H_A")
-    # and of the solid Schur hierarchy, whose small finest level is where the
-    # solve's most frequent (latency-bound) launches run
-    vs_ms = cycle_ms("H_SIG")
+    vs_ms = cycle_ms(solver, "H_SIG", sysm.dim, stream)
     vs_bytes = solver.vcycle_bytes("H_SIG")
+    progress("instrumented solves and V-cycles done")
 
     line = {
         "metric": METRIC,
@@ -493,10 +541,13 @@ def main():
         "dtype": DTYPE[args.precision],
         "data": "synthetic",
         "config": {
-            "workload": (f"2D FSI Jacobian {cfg.cells[0]}x{cfg.cells[1]} Q2/Q1 cells" if cfg.dim == 2 else
-                         f"3D FSI Jacobian {'x'.join(map(str, cfg.cells))} Q2/Q1 cells"),
-            "name": cfg.name, "seeds": list(args.seeds), "N": sysm.N, "nnz": sysm.nnz,
+            "workload": workload_name(cfg),
+            "name": cfg.name, "seeds": list(args.seeds), "N": runs[0]["N"], "nnz": runs[0]["nnz"],
             "tol": 1e-8, "restart": 50, "precond": precond_name(args), "max_coarse": args.max_coarse,
+            "paper_vs_own": ("block-LDU (Section 4.1) with the solid algorithm (Section 4.3) and the Uzawa-like "
+                             "fluid step (Section 4.4) are the paper's; the AMG parameters, the SIMPLE pressure "
+                             "Schur approximation, the Chebyshev smoothers and M_s by Chebyshev steps alone "
+                             "are this library's choices where the paper names none or names 'an AMG-solver'"),
         },
         "iters": {str(r["seed"]): r.get("iters") for r in runs},
         "true_rel_resid": max(resid),
@@ -518,6 +569,16 @@ def main():
             "csr_bytes": int(runs[0]["csr_bytes"]),
             "kernel_ms": round(spmv_ms, 5),
         },
+        "precond_phase": {
+            # one P^{-1} v per Arnoldi step: bytes as stored (fsi_precond_bytes)
+            # over the measured phase time (timed steps; launched-ahead steps
+            # that were discarded carry bytes but no time, so bytes are taken
+            # per launched step)
+            "bytes": int(b_pre / max(b_steps, 1.0)),
+            "ms": round(t_pre / max(n_timed, 1), 5),
+            "GB/s": round(b_pre / max(b_steps, 1.0) / (t_pre / max(n_timed, 1) * 1e-3) / 1e9, 1),
+            "frac": round(b_pre / max(b_steps, 1.0) / (t_pre / max(n_timed, 1) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+        },
         "vcycle_H_A": {
             "bytes": int(vc_bytes), "ms": round(vc_ms, 5),
             "GB/s": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1),
@@ -533,11 +594,54 @@ def main():
             "levels": int(len(solver.hierarchy_info("H_SIG")[0])),
         },
     }
-    if not args.no_cpu_baseline:
-        progress("timing the CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline(runs[0]["sysm"], runs[0]["iters"], args)
+
+    # The FP32 preconditioner (with and without BF16-stored smoother
+    # diagonals) on the same system: the hierarchies are kept (reuse), only
+    # the device copies change precision; the solution is compared with the
+    # FP64 GPU solve (the oracle is not run at this size)
+    if not args.no_mixed and args.precision == "f64":
+        r = runs[0]
+        x64 = r["x"].clone()
+        mixed = {}
+        for prec in ("f32", "f32-bf16diag"):
+            r["solver"].build_precond(prec, reuse=True, **opts)
+            xm = torch.zeros_like(r["b"])
+            timed_solves(r["solver"], r["b"], xm, 1)
+            tm, im = timed_solves(r["solver"], r["b"], xm, max(args.steps, 1))
+            diff = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
+            mixed[prec] = {"ms": round(statistics.mean(tm), 3), "iters": im.iters,
+                           "true_rel_resid": im.true_rel_resid, "rel_diff_vs_f64_gpu": diff,
+                           "speedup_vs_f64": round(ms / statistics.mean(tm), 3)}
+            progress(f"{prec} preconditioner: {mixed[prec]}")
+        mixed["note"] = ("seed %d; same options and hierarchies as the FP64 solve; FP64 Krylov, A_h products, "
+                         "true residual and coarsest solves; difference measured against the FP64 GPU solve "
+                         "(oracle not run at this size)" % r["seed"])
+        line["mixed"] = mixed
+
     for r in runs:
         r["solver"].close()
+    runs.clear()
+    if not args.no_cpu_baseline:
+        gpu_c3 = None
+        if cfg.name != "c3":
+            # the configuration the oracle is timed on, on the GPU too
+            progress("c3 on the GPU (the oracle's sample configuration)")
+            c3 = fsigen.config("c3")
+            s3 = fsigen.generate(c3, seed=0)
+            sol3 = FsiSolver.from_system(s3, device=0, stream=stream)
+            sol3.build_precond(args.precision, **precond_opts(args, c3.dim))
+            b3 = torch.from_numpy(s3.b).to(dev)
+            x3 = torch.zeros_like(b3)
+            timed_solves(sol3, b3, x3, 1)
+            t3, i3 = timed_solves(sol3, b3, x3, 3)
+            gpu_c3 = {"ms": round(statistics.mean(t3), 3), "iters": i3.iters, "N": s3.N, "nnz": s3.nnz}
+            sol3.close()
+            del s3
+            line["gpu_c3"] = gpu_c3
+        else:
+            gpu_c3 = {"iters": iters[0]}
+        progress("timing the CPU oracle sample (c3)")
+        line["cpu_baseline"] = cpu_baseline(args, gpu_c3)
     print(json.dumps(line), flush=True)
 
 

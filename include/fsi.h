@@ -142,9 +142,40 @@ typedef struct {
                           one S_p V-cycle) or FSI_INNER_TRIANGULAR (the block
                           upper-triangular step x_p = S_p^{-1} r_p,
                           x_v = A_f^{-1}(r_v - G x_p): one V-cycle of each)  */
+  int32_t reuse;       /* 0 (default): run the SA setup.  1: keep the five
+                          hierarchies the context holds (those of the previous
+                          fsi_build_precond of the same system, or imported by
+                          fsi_set_hierarchy) and rebuild only what depends on
+                          the other options (precision, smoothers, fluid
+                          solve); strength0, max_coarse, max_levels and schur
+                          must equal the previous build's.  FSI_ERR_STATE
+                          without such a build since fsi_setup_blocks.  The
+                          quasi-Newton reuse of Section 6 keeps the whole
+                          preconditioner instead (no call at all)             */
+  int32_t x_approx;    /* the fluid operator inverted in place of the Schur
+                          complement X = F - C~_fs S^{-1} C_sf of Section 4.1
+                          (C~_fs = C_fs - C_fm M^{-1} C_ms): FSI_X_F (default,
+                          the perturbation dropped, as in the paper's
+                          algorithm) or FSI_X_BLOCKDIAG (S and M replaced by
+                          their node-block diagonals, d x d blocks per field
+                          and node: X ~ F - C~ D_S^{-1} C_sf, the
+                          block-diagonal approximation the paper cites; the
+                          pressure Schur approximation then includes the
+                          resulting pressure block)                           */
+  int32_t uzawa_inner; /* 0 (default): each inverse of the Uzawa-like fluid
+                          step is one V-cycle.  k in 1..16: Section 4.4 as
+                          written, each occurring inverse (A_f^{-1} twice,
+                          S_p^{-1} once) approximated by k steps of GMRES on
+                          A_f or on S_p from zero, right-preconditioned by its
+                          V-cycle (classical Gram-Schmidt with one
+                          reorthogonalisation, stopping early only at an exact
+                          solve).  Not combined with fluid_inner > 0.  Stores
+                          A_f and S_p once more                               */
+  int32_t pad2;
 } fsi_precond_opts;
 
 enum { FSI_INNER_UZAWA = 0, FSI_INNER_TRIANGULAR = 1 };
+enum { FSI_X_F = 0, FSI_X_BLOCKDIAG = 1 };
 
 enum { FSI_SCHUR_SIMPLE = 0, FSI_SCHUR_SIMPLEC = 1 };
 
@@ -165,6 +196,16 @@ typedef struct {
   double t_precond_ms, t_spmv_ms, t_gs_ms;
   int32_t n_timed;
   int32_t mlp_fallbacks;   /* learned pre-smoothing sweeps replaced by Jacobi     */
+  double resid_block[3];   /* ||(b - A_h x)_B|| / ||b|| of the final FP64 true
+                              residual restricted to B = mesh, solid, fluid      */
+  /* bytes the solve moved as the library stores its operands (values, column
+   * lists and row pointers once per product, every vector read or written
+   * once): all A_h products (the Arnoldi steps and the true residuals), all
+   * applications of P^{-1} (Section 4.1's algorithm with its sub-inverses),
+   * and the Krylov vector work (Gram-Schmidt passes and normalisations, the
+   * norms of b and of the residuals, the solution update); launched-ahead
+   * Arnoldi steps that the stopping test then discarded are included */
+  double bytes_spmv, bytes_precond, bytes_gs;
 } fsi_solve_info;
 
 /* Defaults for the option structs (tol 1e-8, m 50, maxit 2000, no timing;
@@ -234,6 +275,15 @@ fsi_status fsi_set_hierarchy(fsi_ctx* ctx, int which, int nlev, const fsi_csr* A
  * (arrays of at least 16 entries), omega[l] (0 on the coarsest level). */
 fsi_status fsi_hierarchy_info(fsi_ctx* ctx, int which, int32_t* nlev, int64_t* n, int64_t* nnz,
                               double* omega);
+
+/* Bytes one z = P^{-1} r (fsi_apply_precond, one Arnoldi step's
+ * preconditioner) moves as the library stores its operands: the eleven
+ * sub-inverse applications of Section 4.1's algorithm as executed (each as
+ * fsi_vcycle_bytes counts it, or the inner GMRES steps of the fluid inverse
+ * with their products and vector passes), the coupling products with their
+ * vectors, the vector updates, and in the FP32 precisions the casts of r and
+ * z.  FSI_ERR_STATE before fsi_build_precond. */
+fsi_status fsi_precond_bytes(fsi_ctx* ctx, double* bytes);
 
 /* Bytes one V(1,1) cycle of hierarchy `which` moves as executed: per level
  * the down-sweep matrices (A D^{-1}, Q = R (I - omega A D^{-1})), the

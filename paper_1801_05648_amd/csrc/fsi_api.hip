@@ -888,6 +888,11 @@ struct Precond {
   int inner_k = 0;
   int inner_pc = FSI_INNER_UZAWA;
   DCsr<T> Fm;
+  // Section 4.4 as written (uz_k > 0): every inverse of the Uzawa-like step
+  // taken as uz_k GMRES steps on A_f (velocity rows grouped d at a time) or
+  // on S_p, preconditioned by its V-cycle; they share the inner buffers
+  int uz_k = 0;
+  DCsr<T> Am, Spm;
   std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ibrk;
   int inner_nb = 1;
 
@@ -901,9 +906,10 @@ struct Precond {
     tf = mk(n_f); ta = mk(n_vf); ta2 = mk(n_vf); tp = mk(n_p);
     ts = mk(n_s); ts2 = mk(n_s); tm = mk(n_m); tm2 = mk(n_m);
     if (sizeof(T) != sizeof(double)) { rT = mk(N); zT = mk(N); }
-    if (inner_k > 0) {
-      iV = mk((inner_k + 1) * n_f);
-      iZ = mk(inner_k * n_f);
+    const int kmax = std::max(inner_k, uz_k);
+    if (kmax > 0) {
+      iV = mk((kmax + 1) * n_f);
+      iZ = mk(kmax * n_f);
       inner_nb = int(std::min<int64_t>(kInnerBlocks, std::max<int64_t>(1, (n_f + kBlock - 1) / kBlock)));
       ipart = std::make_shared<DevBuf>();
       ipart->alloc(sizeof(double) * (kInnerMax + 1) * inner_nb);
@@ -961,14 +967,18 @@ struct Precond {
   // on the device.
   // one Gram-Schmidt pass (update by nu vectors, nd dot products and the
   // norm) and its block-order reduction into out[0..nd]
-  void inner_pass(int nu, int nd, const double* h, T* w, double* out, hipStream_t s) {
-    inner_pass_kernel<T><<<inner_nb, kBlock, 0, s>>>(n_f, nu, nd, iV->as<T>(), n_f, h, w, ipart->as<double>());
+  void inner_pass(int64_t n, int nu, int nd, const double* h, T* w, double* out, hipStream_t s) {
+    inner_pass_kernel<T><<<inner_nb, kBlock, 0, s>>>(n, nu, nd, iV->as<T>(), n, h, w, ipart->as<double>());
     gs_reduce_kernel<<<nd + 1, kBlock, 0, s>>>(inner_nb, 0, ipart->as<double>(), out);
   }
 
-  void fluid_gmres(const T* r_f, T* z_f, hipStream_t s) {
-    const int k = inner_k;
-    const int64_t n = n_f;
+  // k steps of flexible GMRES on an n x n operator from zero, right
+  // preconditioned: pc(v, z) forms z_j = M^{-1} v_j, op(z, w) forms
+  // w = A z_j.  z minimises ||r - A z|| over the span of the z_j.  Classical
+  // Gram-Schmidt with one reorthogonalisation, stopping early only at an
+  // exact solve; every scalar stays on the device (one captured graph).
+  template <class PC, class OP>
+  void gmres_steps(int k, int64_t n, PC&& pc, OP&& op, const T* r, T* z, hipStream_t s) {
     const unsigned g = grid_for(n, kBlock * 4);
     T* V = iV->as<T>();
     T* Z = iZ->as<T>();
@@ -978,26 +988,98 @@ struct Precond {
     double* beta = nn + (kInnerMax + 2);
     double* Hm = beta + 1;
     int* brk = ibrk->as<int>();
-    // ||r_f||^2 (r_f read as "w" with no update: the pass only reads it)
-    inner_pass(0, 0, nullptr, const_cast<T*>(r_f), nn, s);
-    inner_start_kernel<T><<<g, kBlock, 0, s>>>(n, nn, beta, brk, r_f, V);
+    // ||r||^2 (r read as "w" with no update: the pass only reads it)
+    inner_pass(n, 0, 0, nullptr, const_cast<T*>(r), nn, s);
+    inner_start_kernel<T><<<g, kBlock, 0, s>>>(n, nn, beta, brk, r, V);
     for (int j = 0; j < k; ++j) {
       T* zj = Z + int64_t(j) * n;
       T* w = V + int64_t(j + 1) * n;
-      if (inner_pc == FSI_INNER_TRIANGULAR) fluid_tri(V + int64_t(j) * n, zj, s);
-      else fluid(V + int64_t(j) * n, zj, s);
-      launch_rows<T, 1>(Fm, GatherPlain<T, 1>{zj}, EpiStoreFluid<T, 1>{{w}}, s);
-      inner_pass(0, j + 1, nullptr, w, a1, s);   // h1 = V^T w, ||w||^2
-      inner_pass(j + 1, j + 1, a1, w, a2, s);    // w -= V h1; h2 = V^T w
-      inner_pass(j + 1, 0, a2, w, nn, s);        // w -= V h2; ||w||^2
+      pc(static_cast<const T*>(V + int64_t(j) * n), zj);
+      op(static_cast<const T*>(zj), w);
+      inner_pass(n, 0, j + 1, nullptr, w, a1, s);   // h1 = V^T w, ||w||^2
+      inner_pass(n, j + 1, j + 1, a1, w, a2, s);    // w -= V h1; h2 = V^T w
+      inner_pass(n, j + 1, 0, a2, w, nn, s);        // w -= V h2; ||w||^2
       inner_column_kernel<T><<<g, kBlock, 0, s>>>(n, j, k, a1, a2, nn, Hm, brk, w);
     }
-    inner_combine_kernel<T><<<g, kBlock, 0, s>>>(n, k, Z, n, Hm, beta, brk, z_f);
+    inner_combine_kernel<T><<<g, kBlock, 0, s>>>(n, k, Z, n, Hm, beta, brk, z);
+  }
+
+  // The fluid sub-problem solved by k steps of flexible GMRES on F from zero,
+  // right-preconditioned by the Uzawa-like step or the block upper-triangular
+  // step: z_f minimises ||r_f - F z|| over the span of the preconditioned
+  // Arnoldi vectors.
+  void fluid_gmres(const T* r_f, T* z_f, hipStream_t s) {
+    gmres_steps(
+        inner_k, n_f,
+        [&](const T* v, T* zj) {
+          if (inner_pc == FSI_INNER_TRIANGULAR) fluid_tri(v, zj, s);
+          else fluid(v, zj, s);
+        },
+        [&](const T* zj, T* w) { launch_rows<T, 1>(Fm, GatherPlain<T, 1>{zj}, EpiStoreFluid<T, 1>{{w}}, s); },
+        r_f, z_f, s);
+  }
+
+  // Section 4.4 as written: the Uzawa-like elimination with every occurring
+  // inverse approximated by AMG-preconditioned GMRES (uz_k steps each):
+  //   y = A_f^{-1} r_v;  x_p = S_p^{-1} (r_p - D y);  x_v = A_f^{-1} (r_v - G x_p)
+  void fluid_uzawa_gmres(const T* r_f, T* z_f, hipStream_t s) {
+    const T* r_v = r_f;
+    const T* r_p = r_f + n_vf;
+    auto pc_a = [&](const T* v, T* zj) { vcycle(H[FSI_H_A], v, zj, s); };
+    auto op_a = [&](const T* zj, T* w) {
+      launch_rows<T, 1>(Am, GatherPlain<T, 1>{zj}, EpiStoreFluid<T, 1>{{w}}, s);
+    };
+    auto pc_p = [&](const T* v, T* zj) { vcycle(H[FSI_H_P], v, zj, s); };
+    auto op_p = [&](const T* zj, T* w) {
+      launch_rows<T, 1>(Spm, GatherPlain<T, 1>{zj}, EpiStoreFluid<T, 1>{{w}}, s);
+    };
+    gmres_steps(uz_k, n_vf, pc_a, op_a, r_v, ta->as<T>(), s);
+    spmv_sub<T>(Dm, ta->as<T>(), r_p, tp->as<T>(), s);
+    gmres_steps(uz_k, n_p, pc_p, op_p, static_cast<const T*>(tp->as<T>()), z_f + n_vf, s);
+    spmv_sub<T>(Gm, z_f + n_vf, r_v, ta2->as<T>(), s);
+    gmres_steps(uz_k, n_vf, pc_a, op_a, static_cast<const T*>(ta2->as<T>()), z_f, s);
   }
 
   void fluid_inverse(const T* r_f, T* z_f, hipStream_t s) {
     if (inner_k > 0 && n_f > 0) fluid_gmres(r_f, z_f, s);
+    else if (uz_k > 0 && n_vf > 0 && n_p > 0) fluid_uzawa_gmres(r_f, z_f, s);
     else fluid(r_f, z_f, s);
+  }
+
+  // Bytes one application of P^{-1} moves as stored: every V-cycle (or
+  // Chebyshev-only inverse) as executed, every product's matrix once with its
+  // input read and its output written (and read, for r - A x) once, the
+  // inner GMRES vectors and the vector updates.
+  double bytes_per_apply() const {
+    const double w = double(sizeof(T));
+    auto prod = [&](const DCsr<T>& A, int64_t nin, int64_t nout, int touches) {
+      return A.bytes() + w * (double(nin) + touches * double(nout));
+    };
+    const double mesh = H[FSI_H_M].bytes_per_cycle;
+    const double solid = 2 * H[FSI_H_MS].bytes_per_cycle + H[FSI_H_SIG].bytes_per_cycle +
+                         prod(S_vu, n_vs, n_vs, 2) + prod(S_uv, n_vs, n_vs, 2);
+    const double uzawa = 2 * H[FSI_H_A].bytes_per_cycle + H[FSI_H_P].bytes_per_cycle + prod(Dm, n_vf, n_p, 2) +
+                         prod(Gm, n_p, n_vf, 2);
+    const double tri = H[FSI_H_A].bytes_per_cycle + H[FSI_H_P].bytes_per_cycle + prod(Gm, n_p, n_vf, 2);
+    // k GMRES steps on n unknowns: ||r|| and v_0 = r / beta; per step the
+    // preconditioner, the product, three passes over j+1 vectors and the
+    // column; z = Z y
+    auto gmres = [&](int k, int64_t n, double pcb, double opb) {
+      double b = w * double(n) * 3.0;
+      for (int j = 0; j < k; ++j) b += pcb + opb + w * double(n) * (3.0 * j + 10.0);
+      return b + w * double(n) * (k + 1);
+    };
+    double fluid = uzawa;
+    if (inner_k > 0 && n_f > 0) {
+      const double pc = inner_pc == FSI_INNER_TRIANGULAR ? tri : uzawa;
+      fluid = gmres(inner_k, n_f, pc, prod(Fm, n_f, n_f, 1));
+    } else if (uz_k > 0 && n_vf > 0 && n_p > 0) {
+      const double ga = gmres(uz_k, n_vf, H[FSI_H_A].bytes_per_cycle, prod(Am, n_vf, n_vf, 1));
+      fluid = 2 * ga + gmres(uz_k, n_p, H[FSI_H_P].bytes_per_cycle, prod(Spm, n_p, n_p, 1)) +
+              prod(Dm, n_vf, n_p, 2) + prod(Gm, n_p, n_vf, 2);
+    }
+    return 2 * mesh + 2 * solid + prod(Cfms, n_m + n_s, n_f, 2) + fluid + prod(Csf, n_f, n_s, 1) +
+           prod(Cms, n_s, n_m, 1) + 3.0 * w * double(n_s + n_m);
   }
 
   // Block LDU algorithm of Section 4.1 ("Evaluation of P^{-1} r").
@@ -1067,8 +1149,14 @@ struct fsi_ctx {
   int poly[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev steps alone, no coarse grid (0: off)
   int fluid_inner = 0;                     // inner GMRES steps of the fluid inverse (0: off)
   int fluid_inner_pc = FSI_INNER_UZAWA;    // their preconditioner
+  int uzawa_inner = 0;                     // GMRES steps per inverse of the Uzawa-like step (0: off)
   double poly_ratio = 8.0;
   SaHierarchy host_h[FSI_NHIER];
+  bool have_host_h = false;  // host_h built for the current system
+  SaParams host_prm;         // the SA parameters and pressure Schur option host_h was built with
+  int host_schur = FSI_SCHUR_SIMPLE;
+  int host_x_approx = FSI_X_F;
+  HCsr fluid_op;             // FSI_X_BLOCKDIAG: the preconditioner's fluid operator (else F is used)
   std::unique_ptr<Precond<double>> p64;
   std::unique_ptr<Precond<float>> p32;
   // Krylov workspace
@@ -1084,6 +1172,7 @@ struct fsi_ctx {
   std::vector<hipGraphExec_t> pre_graph;   // timed mode: P^{-1} v_j
   std::vector<hipGraphExec_t> gs_graph;    // timed mode: Gram-Schmidt + copy of step j
   hipEvent_t tev[2][4] = {};  // phase events of the two in-flight Arnoldi steps
+  hipEvent_t tsolve[2] = {nullptr, nullptr};  // start / end of a whole solve
   void drop_graphs() {
     for (auto* v : {&step_graph, &pre_graph, &gs_graph}) {
       for (auto& g : *v)
@@ -1100,6 +1189,8 @@ struct fsi_ctx {
     for (auto& r : tev)
       for (auto& e : r)
         if (e) (void)hipEventDestroy(e);
+    for (auto& e : tsolve)
+      if (e) (void)hipEventDestroy(e);
   }
 };
 
@@ -1208,7 +1299,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
                              c.poly_ratio, node_components(c, h), c.precision == FSI_P_F32_BF16DIAG);
   link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
-  const HCsr& F = c.blk[FSI_F];
+  const HCsr& F = c.host_x_approx == FSI_X_BLOCKDIAG ? c.fluid_op : c.blk[FSI_F];  // F, or its refinement
   P->S_vu = upload<T>(sub_block(S, 0, c.n_vs, c.n_vs, c.n_s), s);
   P->S_uv = upload<T>(sub_block(S, c.n_vs, c.n_s, 0, c.n_vs), s);
   P->Dm = upload<T>(sub_block(F, c.n_vf, c.n_f, 0, c.n_vf), s);
@@ -1238,7 +1329,14 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     P->Cfms = upload_segments<T>(M, bounds, groups, 2, s);
     P->inner_k = c.fluid_inner;
     P->inner_pc = c.fluid_inner_pc;
-    if (c.fluid_inner > 0) P->Fm = upload_segments<T>(c.blk[FSI_F], bounds, groups, 2, s);
+    if (c.fluid_inner > 0) P->Fm = upload_segments<T>(F, bounds, groups, 2, s);
+    P->uz_k = c.uzawa_inner;
+    if (c.uzawa_inner > 0) {
+      const int64_t vb[2] = {0, c.n_vf};
+      const int vg[1] = {c.d};
+      P->Am = upload_segments<T>(sub_block(F, 0, c.n_vf, 0, c.n_vf), vb, vg, 1, s);
+      P->Spm = upload<T>(c.host_h[FSI_H_P].levels[0].A, s);
+    }
   }
   P->alloc_tmp();
   HIP_TRY(hipStreamSynchronize(s));
@@ -1254,6 +1352,12 @@ void apply_precond(fsi_ctx& c, const double* r, double* z, hipStream_t s) {
     P.apply(P.rT->as<float>(), P.zT->as<float>(), s);
     cast_kernel<float, double><<<grid_for(c.N, kBlock * 4), kBlock, 0, s>>>(c.N, P.zT->as<float>(), z);
   }
+}
+
+// Bytes of one P^{-1} r (FP32 precisions: with the casts of r and z).
+double precond_bytes(const fsi_ctx& c) {
+  if (c.precision == FSI_P_F64) return c.p64->bytes_per_apply();
+  return c.p32->bytes_per_apply() + 24.0 * double(c.N);
 }
 
 template <typename T>
@@ -1283,6 +1387,8 @@ void ensure_krylov(fsi_ctx& c, int m) {
   for (auto& r : c.tev)
     for (auto& e : r)
       if (!e) HIP_TRY(hipEventCreate(&e));
+  for (auto& e : c.tsolve)
+    if (!e) HIP_TRY(hipEventCreate(&e));
   c.step_graph.assign(m, nullptr);
   c.pre_graph.assign(m, nullptr);
   c.gs_graph.assign(m, nullptr);
@@ -1328,9 +1434,7 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   double* dh = c.dh.as<double>();
   double* hp = c.hpin;
   const int slot = 3 * (m + 2);  // per iteration: h1 | h2 | h3
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
+  hipEvent_t e0 = c.tsolve[0], e1 = c.tsolve[1];  // owned by the context: nothing leaks on a throw
   HIP_TRY(hipEventRecord(e0, s));
   auto fetch1 = [&](const double* src) {
     HIP_TRY(hipMemcpyAsync(hp, src, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1354,6 +1458,9 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     info.true_rel_resid = 0.0;
     return FSI_OK;
   }
+  const double ah_bytes = c.Ah.bytes() + 16.0 * double(N);  // A_h, x read once, y written
+  const double pc_bytes = precond_bytes(c);
+  double bytes_spmv = 0.0, bytes_precond = 0.0, bytes_gs = 8.0 * double(N);  // ||b||
   std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m), rhist(m + 2);
   auto Hat = [&](int i, int j) -> double& { return H[size_t(i) * m + j]; };
   int iters = 0, restarts = 0;
@@ -1403,6 +1510,9 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   // launched on its own between the two graphs of the step
   auto launch_step = [&](int j) {
     hipEvent_t* te = c.tev[j % 2];
+    bytes_precond += pc_bytes;
+    bytes_spmv += ah_bytes;
+    bytes_gs += 8.0 * double(N) * (3.0 * j + 10.0);  // three passes over j+1 vectors, normalisation
     if (graphs && !timing) {
       capture(c.step_graph[j], [&](hipStream_t st) {
         record_pre(j, st);
@@ -1472,6 +1582,8 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     // true residual r = b - A x into V_0
     spmv_sub<double>(c.Ah, x, b, V, s);
     gs_pass(c, 0, 0, V, nullptr, dh, s);
+    bytes_spmv += ah_bytes + 8.0 * double(N);  // b read as well
+    bytes_gs += 8.0 * double(N);
     const double beta = std::sqrt(fetch1(dh));
     rel = beta / bnorm;
     if (!std::isfinite(rel)) throw Error(FSI_ERR_NUMERIC, "non-finite residual");
@@ -1516,15 +1628,29 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
     }
     HIP_TRY(hipMemcpyAsync(c.dy.p, y.data(), sizeof(double) * k, hipMemcpyHostToDevice, s));
     multi_axpy_kernel<<<grid_for(N, kBlock * 4), kBlock, 0, s>>>(N, k, Z, N, c.dy.as<double>(), x);
+    bytes_gs += 8.0 * double(N) * (k + 2);
     HIP_TRY(hipStreamSynchronize(s));  // y lives in host memory
     ++restarts;
+  }
+  // per-block norms of the final true residual (V_0 holds b - A_h x)
+  {
+    constexpr int nb = 64;
+    double* part = c.part.as<double>();  // at least kGsBlocks * (m + 2) >= 3 * nb doubles
+    sumsq3_kernel<<<3 * nb, kBlock, 0, s>>>(V, 0, c.n_m, c.n_m + c.n_s, N, nb, part);
+    std::vector<double> hpart(3 * nb);
+    HIP_TRY(hipMemcpyAsync(hpart.data(), part, sizeof(double) * 3 * nb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    for (int q = 0; q < 3; ++q) {
+      double ss = 0.0;
+      for (int i = 0; i < nb; ++i) ss += hpart[q * nb + i];
+      info.resid_block[q] = std::sqrt(ss) / bnorm;
+    }
+    bytes_gs += 8.0 * double(N);
   }
   HIP_TRY(hipEventRecord(e1, s));
   HIP_TRY(hipEventSynchronize(e1));
   float ms = 0.0f;
   HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   info.iters = iters;
   info.mlp_fallbacks = 0;
   for (auto& M : c.mlp)
@@ -1541,6 +1667,9 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   info.converged = converged ? 1 : 0;
   info.true_rel_resid = rel;
   info.t_total_ms = ms;
+  info.bytes_spmv = bytes_spmv;
+  info.bytes_precond = bytes_precond;
+  info.bytes_gs = bytes_gs;
   return converged ? FSI_OK : FSI_NOT_CONVERGED;
 }
 
@@ -2146,6 +2275,186 @@ void unpack_grad(fsi_ctx& c, MlpState& M, float* G1, float* G2, float* G3) {
     for (int q = 0; q < d; ++q) G3[h * d + q] = g3[h * 16 + q];
 }
 
+
+// The five operators of Section 4 (the scalar mesh Laplacian, Sigma_s, the
+// solid mass block, A_f and the pressure Schur approximation) and their SA
+// hierarchies, on the host.  Replaces c.host_h only when all five succeed.
+// Inverse of the node-block diagonal of A (the entries (i, j) with
+// i / b == j / b), block by block: Gauss-Jordan with partial pivoting on each
+// b x b block, stored as a CSR matrix of dense blocks.
+HCsr node_block_inverse(const HCsr& A, int b) {
+  const int64_t n = A.nrows;
+  if (n % b != 0) throw Error(FSI_ERR_STRUCT, "block size does not divide the matrix");
+  HCsr R;
+  R.nrows = R.ncols = n;
+  R.rp.assign(n + 1, 0);
+  R.ci.resize(size_t(n) * b);
+  R.v.resize(size_t(n) * b);
+  std::vector<double> a(size_t(b) * b), inv(size_t(b) * b);
+  for (int64_t k = 0; k < n / b; ++k) {
+    std::fill(a.begin(), a.end(), 0.0);
+    std::fill(inv.begin(), inv.end(), 0.0);
+    for (int r = 0; r < b; ++r) {
+      const int64_t i = k * b + r;
+      for (int64_t q = A.rp[i]; q < A.rp[i + 1]; ++q)
+        if (A.ci[q] / b == k) a[size_t(r) * b + (A.ci[q] - k * b)] = A.v[q];
+      inv[size_t(r) * b + r] = 1.0;
+    }
+    for (int c = 0; c < b; ++c) {
+      int p = c;
+      for (int r = c + 1; r < b; ++r)
+        if (std::fabs(a[size_t(r) * b + c]) > std::fabs(a[size_t(p) * b + c])) p = r;
+      if (a[size_t(p) * b + c] == 0.0) throw Error(FSI_ERR_NUMERIC, "singular node block in the diagonal");
+      for (int q = 0; q < b; ++q) {
+        std::swap(a[size_t(c) * b + q], a[size_t(p) * b + q]);
+        std::swap(inv[size_t(c) * b + q], inv[size_t(p) * b + q]);
+      }
+      const double piv = a[size_t(c) * b + c];
+      for (int q = 0; q < b; ++q) {
+        a[size_t(c) * b + q] /= piv;
+        inv[size_t(c) * b + q] /= piv;
+      }
+      for (int r = 0; r < b; ++r) {
+        if (r == c) continue;
+        const double f = a[size_t(r) * b + c];
+        if (f == 0.0) continue;
+        for (int q = 0; q < b; ++q) {
+          a[size_t(r) * b + q] -= f * a[size_t(c) * b + q];
+          inv[size_t(r) * b + q] -= f * inv[size_t(c) * b + q];
+        }
+      }
+    }
+    for (int r = 0; r < b; ++r) {
+      const int64_t i = k * b + r;
+      R.rp[i + 1] = (i + 1) * b;
+      for (int q = 0; q < b; ++q) {
+        R.ci[size_t(i) * b + q] = int32_t(k * b + q);
+        R.v[size_t(i) * b + q] = inv[size_t(r) * b + q];
+      }
+    }
+  }
+  drop_zeros(R);
+  return R;
+}
+
+// The fluid operator the preconditioner inverts in place of the Schur
+// complement X = F - C~_fs S^{-1} C_sf (C~_fs = C_fs - C_fm M^{-1} C_ms) of
+// the factorisation in Section 4.1: F itself (FSI_X_F, the perturbation
+// dropped), or with S and M replaced by their node-block diagonals D_S, D_M
+// (d x d blocks per field and node; FSI_X_BLOCKDIAG, the block-diagonal
+// approximation Section 4.1 cites from Langer and Yang, 2016):
+// X ~ F - (C_fs - C_fm (D_M^{-1} C_ms)) (D_S^{-1} C_sf).
+HCsr fluid_operator_refined(const fsi_ctx& c) {
+  const HCsr& F = c.blk[FSI_F];
+  const HCsr DSi = node_block_inverse(c.blk[FSI_S], c.d);
+  const HCsr DMi = node_block_inverse(c.blk[FSI_M], c.d);
+  const HCsr Ct = add(c.blk[FSI_CFS], spgemm(c.blk[FSI_CFM], spgemm(DMi, c.blk[FSI_CMS])), -1.0);
+  HCsr X = add(F, spgemm(Ct, spgemm(DSi, c.blk[FSI_CSF])), -1.0);
+  drop_zeros(X);
+  return X;
+}
+
+void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParams& prm) {
+    const int d = c.d;
+    const HCsr& S = c.blk[FSI_S];
+    HCsr Xop;  // stays empty with X ~ F (the fluid block itself is used)
+    if (o.x_approx == FSI_X_BLOCKDIAG) Xop = fluid_operator_refined(c);
+    const HCsr& F = o.x_approx == FSI_X_BLOCKDIAG ? Xop : c.blk[FSI_F];
+    // operators of the five hierarchies
+    HCsr Lm;  // scalar L of M = L (x) I_d
+    {
+      const HCsr& M = c.blk[FSI_M];
+      Lm.nrows = Lm.ncols = M.nrows / d;
+      Lm.rp.assign(Lm.nrows + 1, 0);
+      for (int64_t I = 0; I < Lm.nrows; ++I) {
+        const int64_t i = I * d;
+        for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) {
+          Lm.ci.push_back(M.ci[k] / d);
+          Lm.v.push_back(M.v[k]);
+        }
+        Lm.rp[I + 1] = int64_t(Lm.ci.size());
+      }
+    }
+    HCsr Svv = sub_block(S, 0, c.n_vs, 0, c.n_vs);
+    HCsr Svu = sub_block(S, 0, c.n_vs, c.n_vs, c.n_s);
+    HCsr Sig = add(Svv, Svu, c.dt_theta);            // Sigma_s = S_vv + dt theta S_vu
+    HCsr Suu = sub_block(S, c.n_vs, c.n_s, c.n_vs, c.n_s);
+    HCsr Af = sub_block(F, 0, c.n_vf, 0, c.n_vf);
+    HCsr Dm = sub_block(F, c.n_vf, c.n_f, 0, c.n_vf);
+    HCsr Gm = sub_block(F, 0, c.n_vf, c.n_vf, c.n_f);
+    HCsr Zpp = sub_block(F, c.n_vf, c.n_f, c.n_vf, c.n_f);  // empty unless X ~ F was refined
+    HCsr Sp;  // Z - D W^{-1} G: W = diag(A_f) (SIMPLE) or its absolute row sums (SIMPLEC)
+    {
+      std::vector<double> dA = diagonal(Af);
+      std::vector<double> dinv(dA.size());
+      for (size_t i = 0; i < dA.size(); ++i) {
+        if (dA[i] == 0.0) throw Error(FSI_ERR_NUMERIC, "zero diagonal in the fluid velocity block");
+        double w = dA[i];
+        if (o.schur == FSI_SCHUR_SIMPLEC) {
+          w = 0.0;
+          for (int64_t k = Af.rp[i]; k < Af.rp[i + 1]; ++k) w += std::fabs(Af.v[k]);
+        }
+        dinv[i] = 1.0 / w;
+      }
+      HCsr Ds = Dm;
+      scale_cols(Ds, dinv);
+      Sp = spgemm(Ds, Gm);
+      for (double& v : Sp.v) v = -v;
+      if (Zpp.nnz() > 0) Sp = add(Sp, Zpp, 1.0);
+      drop_zeros(Sp);
+    }
+    int krig = 0;
+    std::vector<double> Brig = rigid_modes(c, krig);
+    std::vector<double> Bt(size_t(c.n_vf) * d, 0.0);
+    for (int64_t i = 0; i < c.n_vf; ++i) Bt[size_t(i) * d + (i % d)] = 1.0;
+    const HCsr* ops[FSI_NHIER] = {&Lm, &Sig, &Suu, &Af, &Sp};
+    const int blocks[FSI_NHIER] = {1, d, 1, d, 1};
+    const std::vector<double> ones_m(Lm.nrows, 1.0), ones_s(c.n_vs, 1.0), ones_p(c.n_p, 1.0);
+    const std::vector<double>* Bs[FSI_NHIER] = {&ones_m, &Brig, &ones_s, &Bt, &ones_p};
+    const int ks[FSI_NHIER] = {1, krig, 1, d, 1};
+    static const char* hn[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
+    SaHierarchy hh[FSI_NHIER];
+    for (int h = 0; h < FSI_NHIER; ++h) {
+      std::string m = sa_setup(*ops[h], blocks[h], *Bs[h], ks[h], prm, hh[h]);
+      if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
+    }
+    for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
+    c.fluid_op = std::move(Xop);
+    c.have_host_h = true;
+    c.host_prm = prm;
+    c.host_schur = o.schur;
+    c.host_x_approx = o.x_approx;
+}
+
+// The learned correction x = MLP(b) of hierarchy `which`: in FP32 precision
+// b and x pass through the FP32 staging vectors bf, xf.
+void mlp_forward_impl(fsi_ctx& c, int which, const double* b, double* x, float* bf, float* xf) {
+  MlpState& M = mlp_state(c, which);
+  hipStream_t s = c.stream;
+  const unsigned grid = mlp_infer_grid(M.n_nodes);
+  const int32_t* nbr = M.nbr.as<int32_t>();
+  auto run = [&](auto tag, const auto* bb, const auto* dinv, auto* xx) {
+    using T = decltype(tag);
+    if (M.d == 2) {
+      if (M.use.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+      else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+    } else {
+      if (M.use.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+      else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
+    }
+  };
+  if (c.precision == FSI_P_F64) {
+    DHier<double>& H = c.p64->H[which];
+    run(double(0), b, H.lev[0].dinv->as<double>(), x);
+  } else {
+    DHier<float>& H = c.p32->H[which];
+    const int64_t n = M.n_nodes * M.d;
+    cast_kernel<double, float><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, b, bf);
+    run(float(0), static_cast<const float*>(bf), H.lev[0].dinv->as<float>(), xf);
+    cast_kernel<float, double><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, xf, x);
+  }
+}
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -2166,6 +2475,9 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->poly_ratio = 8.0;
   o->fluid_inner = 0;
   o->fluid_inner_pc = FSI_INNER_UZAWA;
+  o->reuse = 0;
+  o->x_approx = FSI_X_F;
+  o->uzawa_inner = 0;
 }
 
 void fsi_default_solve_opts(fsi_solve_opts* o) {
@@ -2322,6 +2634,7 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     c.Ah = dAh;
     c.have_system = true;
     c.have_precond = false;
+    c.have_host_h = false;
     c.drop_graphs();
     c.m_alloc = -1;
     c.p64.reset();
@@ -2355,77 +2668,34 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     if ((o.poly_mask & ~0x1f) != 0 || (o.poly_mask && (o.poly_degree < 2 || o.poly_degree > 16)) ||
         (o.poly_mask && !(o.poly_ratio > 1.0)) || (o.poly_mask & (1 << FSI_H_A)))
       throw Error(FSI_ERR_ARG, "bad Chebyshev-only options (degree 2..16, ratio > 1, not H_A)");
+    if (o.reuse != 0 && o.reuse != 1) throw Error(FSI_ERR_ARG, "reuse must be 0 or 1");
+    if (o.uzawa_inner < 0 || o.uzawa_inner > kInnerMax)
+      throw Error(FSI_ERR_ARG, "GMRES steps per inverse of the Uzawa-like step must be in 0..16");
+    if (o.uzawa_inner > 0 && o.fluid_inner > 0)
+      throw Error(FSI_ERR_ARG, "GMRES on F and GMRES on the Uzawa-like step's inverses do not combine");
+    if (o.x_approx != FSI_X_F && o.x_approx != FSI_X_BLOCKDIAG)
+      throw Error(FSI_ERR_ARG, "unknown approximation of the fluid Schur complement X");
     SaParams prm;
     prm.eps0 = o.strength0;
     prm.max_coarse = o.max_coarse;
     prm.max_levels = o.max_levels;
-    const int d = c.d;
-    const HCsr& S = c.blk[FSI_S];
-    const HCsr& F = c.blk[FSI_F];
-    // operators of the five hierarchies
-    HCsr Lm;  // scalar L of M = L (x) I_d
-    {
-      const HCsr& M = c.blk[FSI_M];
-      Lm.nrows = Lm.ncols = M.nrows / d;
-      Lm.rp.assign(Lm.nrows + 1, 0);
-      for (int64_t I = 0; I < Lm.nrows; ++I) {
-        const int64_t i = I * d;
-        for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) {
-          Lm.ci.push_back(M.ci[k] / d);
-          Lm.v.push_back(M.v[k]);
-        }
-        Lm.rp[I + 1] = int64_t(Lm.ci.size());
-      }
-    }
-    HCsr Svv = sub_block(S, 0, c.n_vs, 0, c.n_vs);
-    HCsr Svu = sub_block(S, 0, c.n_vs, c.n_vs, c.n_s);
-    HCsr Sig = add(Svv, Svu, c.dt_theta);            // Sigma_s = S_vv + dt theta S_vu
-    HCsr Suu = sub_block(S, c.n_vs, c.n_s, c.n_vs, c.n_s);
-    HCsr Af = sub_block(F, 0, c.n_vf, 0, c.n_vf);
-    HCsr Dm = sub_block(F, c.n_vf, c.n_f, 0, c.n_vf);
-    HCsr Gm = sub_block(F, 0, c.n_vf, c.n_vf, c.n_f);
-    HCsr Sp;  // -D W^{-1} G: W = diag(A_f) (SIMPLE) or its absolute row sums (SIMPLEC)
-    {
-      std::vector<double> dA = diagonal(Af);
-      std::vector<double> dinv(dA.size());
-      for (size_t i = 0; i < dA.size(); ++i) {
-        if (dA[i] == 0.0) throw Error(FSI_ERR_NUMERIC, "zero diagonal in the fluid velocity block");
-        double w = dA[i];
-        if (o.schur == FSI_SCHUR_SIMPLEC) {
-          w = 0.0;
-          for (int64_t k = Af.rp[i]; k < Af.rp[i + 1]; ++k) w += std::fabs(Af.v[k]);
-        }
-        dinv[i] = 1.0 / w;
-      }
-      HCsr Ds = Dm;
-      scale_cols(Ds, dinv);
-      Sp = spgemm(Ds, Gm);
-      for (double& v : Sp.v) v = -v;
-      drop_zeros(Sp);
-    }
-    int krig = 0;
-    std::vector<double> Brig = rigid_modes(c, krig);
-    std::vector<double> Bt(size_t(c.n_vf) * d, 0.0);
-    for (int64_t i = 0; i < c.n_vf; ++i) Bt[size_t(i) * d + (i % d)] = 1.0;
-    const HCsr* ops[FSI_NHIER] = {&Lm, &Sig, &Suu, &Af, &Sp};
-    const int blocks[FSI_NHIER] = {1, d, 1, d, 1};
-    const std::vector<double> ones_m(Lm.nrows, 1.0), ones_s(c.n_vs, 1.0), ones_p(c.n_p, 1.0);
-    const std::vector<double>* Bs[FSI_NHIER] = {&ones_m, &Brig, &ones_s, &Bt, &ones_p};
-    const int ks[FSI_NHIER] = {1, krig, 1, d, 1};
-    static const char* hn[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
-    SaHierarchy hh[FSI_NHIER];
-    for (int h = 0; h < FSI_NHIER; ++h) {
-      std::string m = sa_setup(*ops[h], blocks[h], *Bs[h], ks[h], prm, hh[h]);
-      if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
+    if (o.reuse) {
+      if (!c.have_host_h) throw Error(FSI_ERR_STATE, "reuse needs a previous fsi_build_precond of this system");
+      if (c.host_prm.eps0 != prm.eps0 || c.host_prm.max_coarse != prm.max_coarse ||
+          c.host_prm.max_levels != prm.max_levels || c.host_schur != o.schur || c.host_x_approx != o.x_approx)
+        throw Error(FSI_ERR_STATE,
+                    "reuse needs the AMG parameters and the Schur and X options of the previous build");
+    } else {
+      build_host_hierarchies(c, o, prm);
     }
     for (int h = 0; h < FSI_NHIER; ++h) {
-      c.host_h[h] = std::move(hh[h]);
       c.poly[h] = ((o.poly_mask >> h) & 1) ? o.poly_degree : 0;
       c.cheb[h] = (c.poly[h] == 0 && o.cheb_degree > 0 && (o.cheb_mask >> h) & 1) ? o.cheb_degree : 0;
     }
     c.poly_ratio = o.poly_ratio;
     c.fluid_inner = o.fluid_inner;
     c.fluid_inner_pc = o.fluid_inner_pc;
+    c.uzawa_inner = o.uzawa_inner;
     c.precision = o.precision;  // before prepare_mlp: it decides which hierarchies can learn
     prepare_mlp(c);
     c.drop_graphs();
@@ -2438,6 +2708,7 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     return FSI_OK;
   });
 }
+
 
 fsi_status fsi_solve(fsi_ctx* ctx, const double* b, double* x, const fsi_solve_opts* opts, fsi_solve_info* info) {
   return guarded(ctx, [&]() -> fsi_status {
@@ -2588,6 +2859,16 @@ fsi_status fsi_spmv_bytes(fsi_ctx* ctx, double* bytes) {
   });
 }
 
+fsi_status fsi_precond_bytes(fsi_ctx* ctx, double* bytes) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_precond) throw Error(FSI_ERR_STATE, "fsi_build_precond must come first");
+    if (!bytes) throw Error(FSI_ERR_ARG, "bad arguments");
+    *bytes = precond_bytes(c);
+    return FSI_OK;
+  });
+}
+
 fsi_status fsi_vcycle_bytes(fsi_ctx* ctx, int which, double* bytes) {
   return guarded(ctx, [&]() -> fsi_status {
     fsi_ctx& c = *ctx;
@@ -2699,32 +2980,15 @@ fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x) 
     if (!M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
     check_device_ptr(b, "b");
     check_device_ptr(x, "x");
-    hipStream_t s = c.stream;
-    const unsigned grid = mlp_infer_grid(M.n_nodes);
-    const int32_t* nbr = M.nbr.as<int32_t>();
-    auto run = [&](auto tag, const auto* bb, const auto* dinv, auto* xx) {
-      using T = decltype(tag);
-      if (M.d == 2) {
-        if (M.use.per_dof) mlp_infer_kernel<2, true, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
-        else mlp_infer_kernel<2, false, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
-      } else {
-        if (M.use.per_dof) mlp_infer_kernel<3, true, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
-        else mlp_infer_kernel<3, false, T><<<grid, 256, 0, s>>>(M.n_nodes, nbr, bb, dinv, M.use.w, xx);
-      }
-    };
     if (c.precision == FSI_P_F64) {
-      DHier<double>& H = c.p64->H[which];
-      run(double(0), b, H.lev[0].dinv->as<double>(), x);
+      mlp_forward_impl(c, which, b, x, nullptr, nullptr);
     } else {
-      DHier<float>& H = c.p32->H[which];
       const int64_t n = M.n_nodes * M.d;
       DevBuf bf, xf;
       bf.alloc(4 * n);
       xf.alloc(4 * n);
-      cast_kernel<double, float><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, b, bf.as<float>());
-      run(float(0), bf.as<float>(), H.lev[0].dinv->as<float>(), xf.as<float>());
-      cast_kernel<float, double><<<grid_for(n, kBlock * 4), kBlock, 0, s>>>(n, xf.as<float>(), x);
-      HIP_TRY(hipStreamSynchronize(s));
+      mlp_forward_impl(c, which, b, x, bf.as<float>(), xf.as<float>());
+      HIP_TRY(hipStreamSynchronize(c.stream));
     }
     HIP_TRY(hipGetLastError());
     return FSI_OK;

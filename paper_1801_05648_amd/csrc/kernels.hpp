@@ -1189,4 +1189,26 @@ __global__ __launch_bounds__(kBlock) void nonfinite_kernel(int64_t n, const doub
     if (!isfinite(x[i])) atomicOr(flag, 1);
 }
 
+// Sums of squares of three consecutive segments of x (bounds[0..3]): blocks
+// [s * nb, (s + 1) * nb) stride over segment s; each block writes its partial
+// (tree in LDS, fixed order) to part[block].  The host adds the nb partials of
+// a segment in block order, so the result does not depend on timing.
+__global__ __launch_bounds__(kBlock) void sumsq3_kernel(const double* __restrict__ x, int64_t b0, int64_t b1,
+                                                        int64_t b2, int64_t b3, int nb, double* __restrict__ part) {
+  __shared__ double red[kBlock];
+  const int seg = blockIdx.x / nb;
+  const int64_t lo = seg == 0 ? b0 : (seg == 1 ? b1 : b2);
+  const int64_t hi = seg == 0 ? b1 : (seg == 1 ? b2 : b3);
+  double acc = 0.0;
+  for (int64_t i = lo + int64_t(blockIdx.x % nb) * kBlock + threadIdx.x; i < hi; i += int64_t(nb) * kBlock)
+    acc += x[i] * x[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kBlock / 2; off > 0; off >>= 1) {
+    if (int(threadIdx.x) < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
 }  // namespace fsi

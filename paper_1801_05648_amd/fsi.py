@@ -52,7 +52,8 @@ class CPrecondOpts(ctypes.Structure):
                 ("max_levels", ctypes.c_int32), ("cheb_degree", ctypes.c_int32), ("strength0", ctypes.c_double),
                 ("cheb_mask", ctypes.c_int32), ("poly_mask", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
                 ("schur", ctypes.c_int32), ("poly_ratio", ctypes.c_double), ("fluid_inner", ctypes.c_int32),
-                ("fluid_inner_pc", ctypes.c_int32)]
+                ("fluid_inner_pc", ctypes.c_int32), ("reuse", ctypes.c_int32), ("x_approx", ctypes.c_int32),
+                ("uzawa_inner", ctypes.c_int32), ("pad2", ctypes.c_int32)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -64,7 +65,9 @@ class CSolveInfo(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("restarts", ctypes.c_int32), ("converged", ctypes.c_int32),
                 ("pad", ctypes.c_int32), ("true_rel_resid", ctypes.c_double), ("t_total_ms", ctypes.c_double),
                 ("t_precond_ms", ctypes.c_double), ("t_spmv_ms", ctypes.c_double), ("t_gs_ms", ctypes.c_double),
-                ("n_timed", ctypes.c_int32), ("mlp_fallbacks", ctypes.c_int32)]
+                ("n_timed", ctypes.c_int32), ("mlp_fallbacks", ctypes.c_int32),
+                ("resid_block", ctypes.c_double * 3), ("bytes_spmv", ctypes.c_double),
+                ("bytes_precond", ctypes.c_double), ("bytes_gs", ctypes.c_double)]
 
 
 class CMlpTrainOpts(ctypes.Structure):
@@ -75,6 +78,7 @@ class CMlpTrainOpts(ctypes.Structure):
 
 MLP_LOSS = {"l2": 0, "energy": 1}
 INNER_PC = {"uzawa": 0, "triangular": 1}
+X_APPROX = {"F": 0, "blockdiag": 1}
 
 
 class CMlpTrainInfo(ctypes.Structure):
@@ -95,6 +99,10 @@ class SolveInfo:
     t_gs_ms: float = 0.0
     n_timed: int = 0
     mlp_fallbacks: int = 0
+    resid_block: tuple = (0.0, 0.0, 0.0)
+    bytes_spmv: float = 0.0
+    bytes_precond: float = 0.0
+    bytes_gs: float = 0.0
 
 
 def _declare(lib):
@@ -116,6 +124,7 @@ def _declare(lib):
         "fsi_get_aggregates": ([P, i32, i32, P, P], i32),
         "fsi_vcycle_bytes": ([P, i32, P], i32),
         "fsi_spmv_bytes": ([P, P], i32),
+        "fsi_precond_bytes": ([P, P], i32),
         "fsi_default_mlp_train_opts": ([ctypes.POINTER(CMlpTrainOpts)], None),
         "fsi_mlp_set_weights": ([P, i32, P, P, P], i32),
         "fsi_mlp_get_weights": ([P, i32, P, P, P], i32),
@@ -152,9 +161,10 @@ def exported_symbols():
     """Names of the C ABI entry points this binding declares."""
     return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_build_precond",
             "fsi_solve", "fsi_spmv", "fsi_apply_precond", "fsi_vcycle", "fsi_set_hierarchy",
-            "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_spmv_bytes", "fsi_get_level", "fsi_get_aggregates",
+            "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_spmv_bytes", "fsi_precond_bytes", "fsi_get_level", "fsi_get_aggregates",
             "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
             "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
+
             "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train"]
 
 
@@ -268,7 +278,14 @@ class FsiSolver:
     def build_precond(self, precision: str = "f64", max_coarse: int = 500, max_levels: int = 10,
                       strength0: float = 0.08, cheb_degree: int = 0, cheb=("H_MS", "H_SIG", "H_P"),
                       poly=(), poly_degree: int = 3, poly_ratio: float = 8.0, schur: str = "simple",
-                      fluid_inner: int = 0, fluid_inner_pc: str = "uzawa"):
+                      fluid_inner: int = 0, fluid_inner_pc: str = "uzawa", reuse: bool = False,
+                      x_approx: str = "F", uzawa_inner: int = 0):
+        """fsi_build_precond.  reuse=True keeps the context's SA hierarchies
+        (same system, same AMG parameters, Schur and X options as the
+        previous build) and rebuilds only what the other options change.
+        x_approx: "F" or "blockdiag" (the fluid operator standing for the
+        Schur complement X).  uzawa_inner: GMRES steps per inverse of the
+        Uzawa-like fluid step (Section 4.4 as written; 0 = one V-cycle)."""
         def mask_of(names):
             m = 0
             for name in names:
@@ -276,7 +293,7 @@ class FsiSolver:
             return m
         o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, int(cheb_degree), strength0, mask_of(cheb),
                          mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio), int(fluid_inner),
-                         INNER_PC[fluid_inner_pc])
+                         INNER_PC[fluid_inner_pc], int(bool(reuse)), X_APPROX[x_approx], int(uzawa_inner), 0)
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,
@@ -290,7 +307,8 @@ class FsiSolver:
                                             ctypes.byref(o), ctypes.byref(info)))
         return x, SolveInfo(STATUS[rc], info.iters, info.restarts, bool(info.converged),
                             info.true_rel_resid, info.t_total_ms, info.t_precond_ms, info.t_spmv_ms,
-                            info.t_gs_ms, info.n_timed, info.mlp_fallbacks)
+                            info.t_gs_ms, info.n_timed, info.mlp_fallbacks, tuple(info.resid_block),
+                            info.bytes_spmv, info.bytes_precond, info.bytes_gs)
 
     def spmv(self, x, y=None):
         if y is None:
@@ -337,6 +355,11 @@ class FsiSolver:
     def spmv_bytes(self) -> float:
         b = ctypes.c_double()
         self._check(self.lib.fsi_spmv_bytes(self.ctx, ctypes.byref(b)))
+        return b.value
+
+    def precond_bytes(self) -> float:
+        b = ctypes.c_double()
+        self._check(self.lib.fsi_precond_bytes(self.ctx, ctypes.byref(b)))
         return b.value
 
     def vcycle_bytes(self, which) -> float:

@@ -502,19 +502,26 @@ def test_simplec_pressure_schur_matches_oracle():
     assert err <= 1e-6
 
 
-@pytest.mark.parametrize("precision,k,pc", [("f64", 2, "uzawa"), ("f32", 2, "uzawa"), ("f64", 3, "triangular")])
+@pytest.mark.parametrize("precision,k,pc", [("f64", 2, "uzawa"), ("f32", 2, "uzawa"), ("f64", 2, "triangular"),
+                                             ("f64", 3, "triangular")])
 def test_inner_gmres_solve_matches_oracle(precision, k, pc):
     """The 3D benchmark preconditioner with k inner GMRES steps for the
     fluid inverse (Uzawa-like or block-triangular inner preconditioner), on
-    the 32x8x8-cell system with the library's own
-    hierarchies: the GPU solve reaches 1e-8 by the oracle's mat-vec and
-    takes the oracle's iteration count within 3.  Every iterate below the
-    1e-8 residual is a correct solution; what is unique is the Krylov
-    iterate, so with equal counts the GPU's agrees with the oracle's 1e-8
-    iterate within 1e-6, and both lie within 1e-5 of the oracle's 1e-10
-    solution (measured 1.7e-7 for two Uzawa-preconditioned steps, 1.7e-6 for
-    three triangular ones, whose 13-step iterate is less converged); with
-    the FP32 preconditioner as well."""
+    the 32x8x8-cell system with the library's own hierarchies, against the
+    oracle's FGMRES with the same preconditioner.
+
+    FP64: the GPU takes exactly the oracle's iteration count to 1e-8, and the
+    Krylov iterate with that count is unique, so the GPU's agrees with the
+    oracle's 1e-8 iterate within 1e-9.  Every case's solution is within 1e-6
+    of the oracle's 1e-12 solution, except three triangular steps: that
+    preconditioner reaches 1e-8 in 13 outer steps and its 1e-8 iterate, the
+    oracle's own as much as the GPU's, lies 1.7e-6 from the solution
+    (kappa_2(A_h) of this system is at least 1.1e12: sigma_max ~8.0e3 by
+    power iteration, ||A_h^{-1} v|| = 1.4e8 for a random unit v by the oracle
+    solver, so a 1e-8 residual alone bounds the forward error by nothing
+    useful); there the bound is the oracle iterate's own forward error
+    (x 1.05).  FP32 preconditioner: a different (rounded) operator, so the
+    count may move by a few steps; its solution is held to the same 1e-6."""
     from oracle import blocks, krylov, precond
     from paper_1801_05648_amd import FsiSolver
     sysm = system("m3")
@@ -531,16 +538,47 @@ def test_inner_gmres_solve_matches_oracle(precision, k, pc):
                                    fluid_inner_pc=pc)
     xo8, io8 = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-8, restart=50, maxit=500)
     it8 = io8.iters
-    xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-10, restart=50, maxit=500)
+    xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
     err = _rel(xg, xo)
     err8 = _rel(xg, xo8)
+    err_o8 = _rel(xo8, xo)
     print(f"m3 inner GMRES({k}, {pc}) {precision}: GPU {info.iters} it, oracle {it8} it at 1e-8, "
-          f"rel. diff {err8:.2e} to the oracle's 1e-8 iterate, {err:.2e} to its 1e-10 solution")
+          f"rel. diff {err8:.2e} to the oracle's 1e-8 iterate, {err:.2e} to its 1e-12 solution "
+          f"(the oracle's own 1e-8 iterate: {err_o8:.2e})")
     assert info.converged and r <= 1e-8 * 1.001
-    assert abs(info.iters - it8) <= 3
-    if info.iters == it8:
-        assert err8 <= 1e-6
-    assert err <= 1e-5
+    if precision == "f64":
+        assert info.iters == it8, (info.iters, it8)
+        assert err8 <= 1e-9
+    else:
+        assert abs(info.iters - it8) <= 3
+    bound = 1.05 * err_o8 if (k, pc) == (3, "triangular") else 1e-6
+    assert err <= bound
+
+
+def test_apply_precond_parity_c3_benchmark_options():
+    """The 3D benchmark preconditioner (Chebyshev(4) V-cycles on H_SIG and H_P,
+    Jacobi V(1,1) on H_M and H_A with its large levels stored in groups of
+    three rows, M_s by three Chebyshev steps alone, 2000-row dense coarse
+    grids) at the full 64x16x16-cell size (753,740 unknowns) on the oracle's
+    five hierarchies: one application of P^{-1}, element-wise per block
+    within 1e-12 of the block's largest entry."""
+    from oracle import blocks, precond
+    from paper_1801_05648_amd import FsiSolver
+    sysm = system("c3")
+    bs = blocks.BlockSystem(sysm)
+    H = precond.build_hierarchies(bs, max_coarse=2000)
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f64", max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3)
+    _import_oracle_hierarchies(s, H)
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4, "H_P": 4}, poly={"H_MS": (3, 8.0)})
+    r = np.random.default_rng(23).standard_normal(bs.N)
+    z = s.apply_precond(_dev(r)).cpu().numpy()
+    s.close()
+    ref = P(r)
+    for part, a, b in zip(("mesh", "solid", "fluid"), bs.split(z), bs.split(ref)):
+        e_inf = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        print(f"c3 P^-1 r {part}: max-abs {e_inf:.2e}, rel L2 {_rel(a, b):.2e}")
+        assert e_inf <= 1e-12 and _rel(a, b) <= 1e-12, part
 
 
 def test_spmv_parity_c3_full_size():
@@ -556,3 +594,128 @@ def test_spmv_parity_c3_full_size():
     s.close()
     ref = bs.matvec(x)
     assert _rel(y, ref) <= 1e-12, _rel(y, ref)
+
+
+def test_solve_info_block_residuals_and_bytes():
+    """fsi_solve_info: the per-block true residuals make up the whole one and
+    match the blocks of b - A_h x formed by the oracle's mat-vec from the
+    returned x (a 1e-8 residual recomputed in another summation order: 1e-3
+    relative); the byte counts are whole multiples of the per-step figures
+    (A_h as stored, fsi_precond_bytes) over the launched Arnoldi steps, at
+    least the finished ones."""
+    from oracle import blocks
+    sysm = system("c1")
+    bs = blocks.BlockSystem(sysm)
+    s = _solver("c1")
+    x, info = s.solve(_dev(sysm.b), tol=1e-8)
+    pc = s.precond_bytes()
+    ah = s.spmv_bytes()
+    s.close()
+    assert info.converged
+    rb = np.array(info.resid_block)
+    assert abs(np.sqrt(np.sum(rb ** 2)) - info.true_rel_resid) <= 1e-12 * info.true_rel_resid
+    r = sysm.b - bs.matvec(x.cpu().numpy())
+    nb = np.linalg.norm(sysm.b)
+    ref = np.array([np.linalg.norm(p) / nb for p in bs.split(r)])
+    print(f"c1 block residuals GPU {rb}, oracle mat-vec {ref}")
+    assert np.all(np.abs(rb - ref) <= 1e-3 * ref.max())
+    steps = info.bytes_precond / pc
+    assert abs(steps - round(steps)) <= 1e-9 * steps and round(steps) >= info.iters
+    true_res = info.restarts + 1
+    spmv_steps = (info.bytes_spmv - true_res * (ah + 8.0 * bs.N)) / ah
+    assert abs(spmv_steps - round(steps)) <= 1e-9 * steps
+    assert info.bytes_gs > 8.0 * bs.N * info.iters
+
+
+@pytest.mark.parametrize("name", ["tiny3d", "c1"])
+def test_blockdiag_x_precond_matches_oracle(name):
+    """The block-diagonal approximation of the Schur complement X
+    (x_approx="blockdiag"): the library's pressure Schur approximation (now
+    with the pressure block of the refined operator) and A_f equal the
+    oracle's (1e-13), P^{-1} r on the oracle's hierarchies of the refined
+    operator matches element-wise per block (1e-12), and a solve matches the
+    oracle's FGMRES solution within 1e-6."""
+    import scipy.sparse as sp
+    from oracle import blocks, krylov, precond
+    from paper_1801_05648_amd import FsiSolver
+    sysm = system(name)
+    bs = blocks.BlockSystem(sysm)
+    fl = bs.fluid_x("blockdiag")
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f64", max_coarse=40, x_approx="blockdiag")
+    for hname, ref in (("H_P", fl.schur()), ("H_A", fl.A_f)):
+        nr, nc, rp, ci, v = s.get_level(hname, 0, "A")
+        got = sp.csr_matrix((v, ci, rp), shape=(nr, nc))
+        assert abs(got - ref).max() <= 1e-13 * abs(ref).max(), hname
+    H = precond.build_hierarchies(bs, max_coarse=40, x_approx="blockdiag")
+    P = precond.amg_preconditioner(bs, H, x_approx="blockdiag")
+    x, info = s.solve(_dev(sysm.b), tol=1e-8)
+    xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
+    err = _rel(x.cpu().numpy(), xo)
+    _import_oracle_hierarchies(s, H)
+    r = np.random.default_rng(29).standard_normal(bs.N)
+    z = s.apply_precond(_dev(r)).cpu().numpy()
+    s.close()
+    ref = P(r)
+    for part, a, b in zip(("mesh", "solid", "fluid"), bs.split(z), bs.split(ref)):
+        e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        print(f"{name} blockdiag-X P^-1 r {part}: max-abs {e:.2e}")
+        assert e <= 1e-12, part
+    print(f"{name} blockdiag-X solve: {info.iters} iterations, rel. diff to the oracle {err:.2e}")
+    assert info.converged
+    if name == "c1":  # the tiny grids' conditioning (~1e13) puts their 1e-8 iterates farther apart
+        assert err <= 1e-6
+
+
+@pytest.mark.parametrize("name,k", [("tiny3d", 2), ("c1", 1), ("c1", 3), ("c2", 2)])
+def test_uzawa_gmres_inverses_precond_matches_oracle(name, k):
+    """Section 4.4 as written: each inverse of the Uzawa-like fluid step
+    taken as k GMRES steps preconditioned by its V-cycle (uzawa_inner = k).
+    P^{-1} r on the oracle's hierarchies, GPU (classical Gram-Schmidt twice,
+    device Givens) against the oracle (modified Gram-Schmidt, host Givens):
+    the same Krylov minimisers, so rounding amplified by the small least-
+    squares problems only: 1e-10 per block."""
+    from oracle import precond
+    bs, H = _oracle(name)
+    from paper_1801_05648_amd import FsiSolver
+    s = FsiSolver.from_system(system(name, 0), device=0)
+    s.build_precond("f64", uzawa_inner=k)
+    _import_oracle_hierarchies(s, H)
+    P = precond.amg_preconditioner(bs, H, uzawa_inner=k)
+    r = np.random.default_rng(31).standard_normal(bs.N)
+    z = s.apply_precond(_dev(r)).cpu().numpy()
+    ref = P(r)
+    for part, (a, b) in zip(("mesh", "solid", "fluid"), zip(bs.split(z), bs.split(ref))):
+        print(f"{name} uzawa_inner={k} {part}: rel. error {_rel(a, b):.2e}")
+        assert _rel(a, b) <= 1e-10, (part, _rel(a, b))
+    s.close()
+
+
+def test_uzawa_gmres_inverses_solve_matches_oracle():
+    """The whole solve with the Section 4.4 fluid step (two GMRES steps per
+    inverse) on the 32x8x8-cell system and the library's own hierarchies:
+    the oracle's iteration count and its 1e-8 iterate within 1e-9 (the
+    Krylov iterate with that count is unique).  Like three triangular inner
+    steps, this preconditioner reaches 1e-8 in 13 outer steps with an
+    iterate 2.9e-6 from the solution (the oracle's own; kappa_2(A_h) of this
+    system is at least 1.1e12), so the forward-error bound is that of the
+    oracle's iterate (x 1.05), not 1e-6: a named exception."""
+    from oracle import blocks, krylov, precond
+    from paper_1801_05648_amd import FsiSolver
+    sysm = system("m3")
+    bs = blocks.BlockSystem(sysm)
+    opts = dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3, uzawa_inner=2)
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f64", **opts)
+    x, info = s.solve(_dev(sysm.b), tol=1e-8)
+    s.close()
+    xg = x.cpu().numpy()
+    H = precond.build_hierarchies(bs, max_coarse=2000)
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4, "H_P": 4}, poly={"H_MS": (3, 8.0)}, uzawa_inner=2)
+    xo8, io8 = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-8, restart=50, maxit=500)
+    xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
+    print(f"m3 uzawa_inner=2: GPU {info.iters} it, oracle {io8.iters} it; {_rel(xg, xo8):.2e} to the oracle's "
+          f"1e-8 iterate, {_rel(xg, xo):.2e} to its 1e-12 solution")
+    assert info.converged and info.iters == io8.iters
+    assert _rel(xg, xo8) <= 1e-9
+    assert _rel(xg, xo) <= 1.05 * _rel(xo8, xo)
