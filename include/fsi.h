@@ -352,6 +352,16 @@ fsi_status fsi_mlp_enable(fsi_ctx* ctx, int which, int enable);
 /* x = network correction for the residual b of hierarchy `which`'s finest
  * level (device FP64 vectors of that level's size). */
 fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x);
+/* The same correction for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): no allocation and no synchronisation.  In the FP32 precisions
+ * b and x are staged through a library-owned FP32 array of 2 x 4,194,304
+ * entries (32 MiB per GPU, held until the process ends) instead of buffers
+ * allocated per call; FSI_ERR_ARG when the level has more than 4,194,304
+ * entries.  Every call on one GPU uses that GPU's one array: calls that
+ * overlap on one GPU (different streams or threads) race.  b, x as in
+ * fsi_mlp_forward; the result is the same. */
+fsi_status fsi_mlp_forward_noalloc(fsi_ctx* ctx, int which, const double* b, double* x);
 /* One pass of the training kernels over m samples (host FP32: Z m x K, E m x d,
  * w m): loss = (1/m) sum w ||delta - e||^2 and its gradients G1, G2, G3 (host,
  * shapes of W1, W2, W3). */

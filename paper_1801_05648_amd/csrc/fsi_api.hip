@@ -19,6 +19,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <type_traits>
 #include <new>
 #include <random>
@@ -31,6 +32,14 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "sa_setup.hpp"
+
+// Staging of fsi_mlp_forward_noalloc: the FP32 copies of the residual and of
+// the network's correction (kNoAllocStage entries each) in one array per GPU,
+// so that the call allocates nothing.  The array lives as long as the process
+// (32 MiB on each GPU the library runs on).  Host code must use its device
+// address from hipGetSymbolAddress, never the symbol itself.
+constexpr int64_t kNoAllocStage = int64_t(1) << 22;
+static __device__ __align__(256) float scratch[2 * kNoAllocStage];
 
 namespace fsi {
 
@@ -1130,6 +1139,7 @@ struct MlpState {
 struct fsi_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  float* scratch = nullptr;  // this device's address of the allocation-free staging array
   std::string err;
   // system
   bool have_system = false, have_precond = false;
@@ -2426,8 +2436,30 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     c.host_x_approx = o.x_approx;
 }
 
-// The learned correction x = MLP(b) of hierarchy `which`: in FP32 precision
-// b and x pass through the FP32 staging vectors bf, xf.
+constexpr int kMaxDevices = 64;
+
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), taken once
+// per device; nullptr if the runtime cannot give it.
+float* scratch_address(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    g_scratch_ptr[device] = static_cast<float*>(p);
+  }
+  return g_scratch_ptr[device];
+}
+
+// The learned correction x = MLP(b) of hierarchy `which` (shared by
+// fsi_mlp_forward and its allocation-free variant): in FP32 precision b and x
+// pass through the FP32 staging vectors bf, xf.
 void mlp_forward_impl(fsi_ctx& c, int which, const double* b, double* x, float* bf, float* xf) {
   MlpState& M = mlp_state(c, which);
   hipStream_t s = c.stream;
@@ -2509,6 +2541,12 @@ fsi_status fsi_create(fsi_ctx** ctx, int device, void* hip_stream) {
   if (hipSetDevice(device) != hipSuccess) {
     delete c;
     g_create_err = "hipSetDevice failed";
+    return FSI_ERR_HIP;
+  }
+  c->scratch = scratch_address(device);
+  if (!c->scratch) {
+    delete c;
+    g_create_err = "hipGetSymbolAddress of the staging array failed";
     return FSI_ERR_HIP;
   }
   *ctx = c;
@@ -2990,6 +3028,25 @@ fsi_status fsi_mlp_forward(fsi_ctx* ctx, int which, const double* b, double* x) 
       mlp_forward_impl(c, which, b, x, bf.as<float>(), xf.as<float>());
       HIP_TRY(hipStreamSynchronize(c.stream));
     }
+    HIP_TRY(hipGetLastError());
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_mlp_forward_noalloc(fsi_ctx* ctx, int which, const double* b, double* x) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    MlpState& M = mlp_state(c, which);
+    if (!M.have_weights) throw Error(FSI_ERR_STATE, "no weights set");
+    check_device_ptr(b, "b");
+    check_device_ptr(x, "x");
+    const int64_t n = M.n_nodes * M.d;
+    if (c.precision != FSI_P_F64 && n > kNoAllocStage)
+      throw Error(FSI_ERR_ARG, "the allocation-free call stages at most " + std::to_string(kNoAllocStage) +
+                                   " entries; this level has " + std::to_string(n));
+    float* st = c.scratch;  // device address of the staging array, taken in fsi_create
+    if (!st) throw Error(FSI_ERR_STATE, "no staging array on this device");
+    mlp_forward_impl(c, which, b, x, st, st + kNoAllocStage);
     HIP_TRY(hipGetLastError());
     return FSI_OK;
   });

@@ -130,6 +130,7 @@ def _declare(lib):
         "fsi_mlp_get_weights": ([P, i32, P, P, P], i32),
         "fsi_mlp_enable": ([P, i32, i32], i32),
         "fsi_mlp_forward": ([P, i32, P, P], i32),
+        "fsi_mlp_forward_noalloc": ([P, i32, P, P], i32),
         "fsi_mlp_loss_grad": ([P, i32, i64, P, P, P, P, P, P, P], i32),
         "fsi_mlp_energy_grad": ([P, i32, P, i32, P, P, P, P], i32),
         "fsi_mlp_collect": ([P, i32, i32], i32),
@@ -164,7 +165,7 @@ def exported_symbols():
             "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_spmv_bytes", "fsi_precond_bytes", "fsi_get_level", "fsi_get_aggregates",
             "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
             "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
-
+            "fsi_mlp_forward_noalloc",
             "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train"]
 
 
@@ -411,6 +412,13 @@ class FsiSolver:
         if x is None:
             x = self.torch.empty_like(b)
         self._check(self.lib.fsi_mlp_forward(self.ctx, w, _dptr(b, n, "b"), _dptr(x, n, "x")))
+        return x
+
+    def mlp_forward_noalloc(self, which, b, x):
+        """fsi_mlp_forward_noalloc: the caller provides x; nothing is allocated."""
+        w = HIERARCHIES[which] if isinstance(which, str) else int(which)
+        n = self._hier_len(w)
+        self._check(self.lib.fsi_mlp_forward_noalloc(self.ctx, w, _dptr(b, n, "b"), _dptr(x, n, "x")))
         return x
 
     def mlp_loss_grad(self, which, Z, E, wgt, d: int):
