@@ -10,9 +10,10 @@ upload) is reported separately and is not part of a step.
 
 Prints one JSON line.  Extra objects: ``roofline`` for the dominant kernel
 (the A_h block product, timed with HIP events on the solver's stream),
-``vcycle_H_A`` (one V-cycle of the largest hierarchy), ``mixed`` (the same
-solve with the FP32 preconditioner, with and without BF16-stored smoother
-diagonals, against the FP64 solve), ``gpu_c3`` (the 64x16x16-cell system on
+``vcycle_H_A`` (one V-cycle of the largest hierarchy), ``alternatives``
+(the same solve with the FP32 preconditioner, with and without BF16-stored
+smoother diagonals, and with the paper's own forms of the fluid step,
+against the FP64 solve), ``gpu_c3`` (the 64x16x16-cell system on
 the GPU, the configuration the CPU oracle is timed on) and ``cpu_baseline``
 (the CPU oracle on a bounded sample, rank 0 only).
 """
@@ -33,7 +34,7 @@ HBM_PEAK_GBS = 8000.0
 # 256 MiB device copy in the same runs); see profiles/a_h_spmv_hbm_traffic.md.
 # Valid only for the kernel and workload it was measured on (empty: the
 # kernel changed since the counters were taken).
-MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563}
+MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563, "c4": 15873201262}
 # The same for one H_A V-cycle of the benchmark preconditioner (bench.py
 # --pmc-vcycle); see profiles/h_a_vcycle_hbm_traffic.md.
 MEASURED_VCYCLE_TRAFFIC = {"c2": 129161151, "c3": 1614689335}
@@ -71,13 +72,15 @@ def cpu_baseline(args, gpu_c3=None, sample_iters: int = 2):
     try:
         bs = blocks.BlockSystem(sysm)
         t0 = time.perf_counter()
-        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=args.schur)
+        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=args.schur,
+                                      x_approx=args.x_approx)
         t_setup = time.perf_counter() - t0
         o = precond_opts(args, cfg.dim)
         cheb = {h: o["cheb_degree"] for h in o["cheb"]} if o["cheb_degree"] > 0 else None
         poly = {h: (o["poly_degree"], o["poly_ratio"]) for h in o["poly"]}
         P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=o["fluid_inner"],
-                                       fluid_inner_pc=o["fluid_inner_pc"])
+                                       fluid_inner_pc=o["fluid_inner_pc"], x_approx=o["x_approx"],
+                                       uzawa_inner=o["uzawa_inner"])
         t0 = time.perf_counter()
         x, info = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-30, restart=50, maxit=sample_iters)
         t_iter = (time.perf_counter() - t0) / max(info.iters, 1)
@@ -125,7 +128,11 @@ def precond_name(args) -> str:
     poly = poly_on(args)
     ptxt = f"; {'/'.join(poly)} by {args.poly_degree} Chebyshev steps alone" if poly else ""
     ptxt += f"; S_p {args.schur.upper()}"
-    if args.fluid_inner > 0:
+    if args.x_approx != "F":
+        ptxt += "; X by its block-diagonal approximation"
+    if args.uzawa_inner > 0:
+        ptxt += f"; each inverse of the Uzawa-like step by {args.uzawa_inner} AMG-preconditioned GMRES steps"
+    elif args.fluid_inner > 0:
         ptxt += f"; F^-1 by {args.fluid_inner} inner GMRES steps ({args.fluid_inner_pc} step)"
     if args.cheb <= 0:
         return "block-LDU + SA-AMG V(1,1) Jacobi" + ptxt
@@ -248,12 +255,39 @@ def precond_opts(args, dim: int) -> dict:
     workload of dimension `dim` (defaults resolved in main)."""
     cheb_on = args.cheb_on_arg if args.cheb_on_arg is not None else ("H_MS,H_SIG" if dim == 2 else "H_MS,H_SIG,H_P")
     fluid_inner = (args.fluid_inner_arg if args.fluid_inner_arg is not None
-                   else (2 if dim == 2 and not args.learned else 0))
+                   else (0 if args.learned else 2))
     poly = poly_on(args)
     return dict(max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                 cheb=tuple(h for h in cheb_on.split(",") if h and h not in poly), poly=poly,
                 poly_degree=args.poly_degree, poly_ratio=args.poly_ratio, schur=args.schur,
-                fluid_inner=fluid_inner, fluid_inner_pc=args.fluid_inner_pc)
+                fluid_inner=0 if args.uzawa_inner > 0 else fluid_inner, fluid_inner_pc=args.fluid_inner_pc,
+                uzawa_inner=args.uzawa_inner, x_approx=args.x_approx)
+
+
+def paper_vs_own(args, opts) -> str:
+    """Which parts of the benchmarked preconditioner are the paper's and which
+    are this library's choices."""
+    own = ["smoothed-aggregation parameters (the paper names only ML)",
+           f"{args.schur.upper()} pressure Schur approximation (the paper states none)"]
+    if opts["cheb_degree"] > 0 and opts["cheb"]:
+        own.append(f"Chebyshev({opts['cheb_degree']}) smoothing on {'/'.join(opts['cheb'])}")
+    if opts["poly"]:
+        own.append(f"{'/'.join(opts['poly'])} by {opts['poly_degree']} Chebyshev steps alone "
+                   "(the paper: an AMG solver)")
+    if opts["uzawa_inner"] > 0:
+        fluid = (f"the fluid inverse as the paper's Section 4.4 step: GMRES ({opts['uzawa_inner']} steps) on "
+                 "each inverse of the Uzawa-like elimination")
+    elif opts["fluid_inner"] > 0:
+        own.append(f"the fluid inverse as {opts['fluid_inner']} GMRES steps on the whole F preconditioned by the "
+                   f"{opts['fluid_inner_pc']} step (the paper puts GMRES on each inverse of the Uzawa-like "
+                   "elimination: alternatives.paper_uzawa_gmres2)")
+        fluid = None
+    else:
+        fluid = "the Uzawa-like fluid step with one V-cycle per inverse"
+    paper = "the block-LDU algorithm (Section 4.1), the solid algorithm (Section 4.3)"
+    if fluid:
+        paper += ", " + fluid
+    return f"paper's: {paper}; this library's: " + "; ".join(own)
 
 
 def workload_name(cfg) -> str:
@@ -278,6 +312,33 @@ def cycle_ms(solver, hn, dim, stream, reps=50):
     e1.record(stream)
     e1.synchronize()
     return e0.elapsed_time(e1) / reps
+
+
+def stream_ceilings(stream, gib: int = 4):
+    """Bandwidth of plain device streams in this run, for scale: a copy of
+    `gib` GiB (read + write) and a sum over `gib` GiB (read), timed with
+    events on the stream (best of 5 after a warm-up)."""
+    import torch
+    n = gib * 2 ** 30 // 8
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn, nbytes in (("copy", lambda: b.copy_(a), 16.0 * n), ("read", lambda: a.sum(), 8.0 * n)):
+        fn()
+        best = None
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            t = e0.elapsed_time(e1)
+            best = t if best is None else min(best, t)
+        out[name + "_GBps"] = round(nbytes / (best * 1e-3) / 1e9, 1)
+    del a, b
+    torch.cuda.empty_cache()
+    return out
 
 
 def timed_solves(solver, b, x, k):
@@ -311,7 +372,7 @@ def main():
     ap.add_argument("--precision", default="f64", choices=["f64", "f32", "f32-bf16diag"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true",
-                    help="skip the FP32-preconditioner solves reported beside the FP64 ones")
+                    help="skip the other preconditioner forms reported beside the headline solve")
     ap.add_argument("--cheb", type=int, default=None,
                     help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
                          "default 4, and 0 with --learned (the learned smoother replaces a Jacobi sweep)")
@@ -328,10 +389,15 @@ def main():
                          "absolute row sums (simplec); default simple")
     ap.add_argument("--fluid-inner", type=int, default=None,
                     help="inner flexible GMRES steps for the fluid inverse (0: the Uzawa-like step "
-                         "alone; default 2 in 2D, 0 in 3D and with --learned)")
+                         "alone; default 2, 0 with --learned)")
     ap.add_argument("--fluid-inner-pc", default="triangular", choices=["uzawa", "triangular"],
                     help="preconditioner of the inner fluid GMRES: the Uzawa-like step or the block "
                          "upper-triangular step (one A_f V-cycle fewer; default)")
+    ap.add_argument("--uzawa-inner", type=int, default=0,
+                    help="GMRES steps per inverse of the Uzawa-like fluid step (Section 4.4 as written; "
+                         "0: one V-cycle per inverse)")
+    ap.add_argument("--x-approx", default="F", choices=["F", "blockdiag"],
+                    help="fluid operator standing for the Schur complement X (Section 4.1)")
     ap.add_argument("--strength", type=float, default=0.08,
                     help="SA strength threshold of the finest level (halved per level)")
     ap.add_argument("--poly-degree", type=int, default=None,
@@ -377,11 +443,11 @@ def main():
         # GMRES, three take 17/18/21 instead of 19/20/23 iterations (256x64:
         # 11.5 vs 12.3 ms)
         args.poly_degree = 3
-    # fluid_inner: two inner GMRES steps on the fluid block halve the 2D outer
-    # iterations (256x64: 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms with the
-    # triangular inner step, 14.4 ms with the Uzawa-like one).  In 3D the
-    # Uzawa-like steps cut iterations but not time (64x16x16: 46 -> 31
-    # iterations, 93.8 -> 103.8 ms).
+    # fluid_inner: two inner GMRES steps on the fluid block, preconditioned by
+    # the block upper-triangular step, halve the 2D outer iterations (256x64:
+    # 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms; 14.4 ms with the Uzawa-like
+    # inner step) and cut the 3D ones by a third (64x16x16: 46 -> 33
+    # iterations, 93.8 -> 85.3 ms; 128x32x32: 47 -> 31, 635.6 -> 517.6 ms).
     if args.schur is None:
         # SIMPLE throughout: SIMPLEC (absolute row sums) cuts the 64x16x16
         # solve from 46 to 36 iterations but raises the 128x32x32 one from 47
@@ -518,6 +584,7 @@ def main():
     nbytes = nbytes_sum / max(args.steps, 1)  # all seeds share the sparsity pattern
     achieved = nbytes / (spmv_ms * 1e-3) / 1e9
 
+    ceil = stream_ceilings(stream)
     # one V(1,1) cycle of the fluid-velocity hierarchy (largest V-cycle),
     # bytes as executed by the level kernels, and of the solid Schur
     # hierarchy (small, latency-bound levels)
@@ -544,10 +611,7 @@ def main():
             "workload": workload_name(cfg),
             "name": cfg.name, "seeds": list(args.seeds), "N": runs[0]["N"], "nnz": runs[0]["nnz"],
             "tol": 1e-8, "restart": 50, "precond": precond_name(args), "max_coarse": args.max_coarse,
-            "paper_vs_own": ("block-LDU (Section 4.1) with the solid algorithm (Section 4.3) and the Uzawa-like "
-                             "fluid step (Section 4.4) are the paper's; the AMG parameters, the SIMPLE pressure "
-                             "Schur approximation, the Chebyshev smoothers and M_s by Chebyshev steps alone "
-                             "are this library's choices where the paper names none or names 'an AMG-solver'"),
+            "paper_vs_own": paper_vs_own(args, opts),
         },
         "iters": {str(r["seed"]): r.get("iters") for r in runs},
         "true_rel_resid": max(resid),
@@ -568,6 +632,10 @@ def main():
             "algorithmic_bytes": int(nbytes),
             "csr_bytes": int(runs[0]["csr_bytes"]),
             "kernel_ms": round(spmv_ms, 5),
+            # plain device streams in this run (torch copy and sum of 4 GiB):
+            # the practical ceiling next to the 8 TB/s peak
+            "stream_ceiling": ceil,
+            "frac_of_read_stream": round(achieved / ceil["read_GBps"], 4),
         },
         "precond_phase": {
             # one P^{-1} v per Arnoldi step: bytes as stored (fsi_precond_bytes)
@@ -595,28 +663,39 @@ def main():
         },
     }
 
-    # The FP32 preconditioner (with and without BF16-stored smoother
-    # diagonals) on the same system: the hierarchies are kept (reuse), only
-    # the device copies change precision; the solution is compared with the
-    # FP64 GPU solve (the oracle is not run at this size)
+    # Other forms of the preconditioner on the same system, built from the
+    # FP64 build's hierarchies (reuse: only the device copies, smoothers and
+    # the fluid solve change), timed the same way, each solution compared
+    # with the FP64 GPU solve (the oracle is not run at this size): the FP32
+    # preconditioner with and without BF16-stored smoother diagonals, the
+    # paper's Section 4.4 fluid step (GMRES on each inverse of the Uzawa-like
+    # elimination), and the Uzawa-like step with one V-cycle per inverse
+    # (the plain reading of the paper's algorithm)
     if not args.no_mixed and args.precision == "f64":
         r = runs[0]
         x64 = r["x"].clone()
-        mixed = {}
-        for prec in ("f32", "f32-bf16diag"):
-            r["solver"].build_precond(prec, reuse=True, **opts)
+        alts = {}
+        forms = [("f32", "f32", {}), ("f32-bf16diag", "f32-bf16diag", {})]
+        if args.uzawa_inner == 0:
+            forms.append(("paper_uzawa_gmres2", "f64", dict(fluid_inner=0, uzawa_inner=2)))
+        if opts["fluid_inner"] > 0:
+            forms.append(("uzawa_vcycles", "f64", dict(fluid_inner=0, uzawa_inner=0)))
+        for label, prec, over in forms:
+            o2 = dict(opts)
+            o2.update(over)
+            r["solver"].build_precond(prec, reuse=True, **o2)
             xm = torch.zeros_like(r["b"])
             timed_solves(r["solver"], r["b"], xm, 1)
-            tm, im = timed_solves(r["solver"], r["b"], xm, max(args.steps, 1))
+            tm, im = timed_solves(r["solver"], r["b"], xm, max(min(args.steps, 3), 1))
             diff = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
-            mixed[prec] = {"ms": round(statistics.mean(tm), 3), "iters": im.iters,
+            alts[label] = {"precision": prec, "ms": round(statistics.mean(tm), 3), "iters": im.iters,
                            "true_rel_resid": im.true_rel_resid, "rel_diff_vs_f64_gpu": diff,
-                           "speedup_vs_f64": round(ms / statistics.mean(tm), 3)}
-            progress(f"{prec} preconditioner: {mixed[prec]}")
-        mixed["note"] = ("seed %d; same options and hierarchies as the FP64 solve; FP64 Krylov, A_h products, "
-                         "true residual and coarsest solves; difference measured against the FP64 GPU solve "
-                         "(oracle not run at this size)" % r["seed"])
-        line["mixed"] = mixed
+                           "speedup_vs_headline": round(ms / statistics.mean(tm), 3), **over}
+            progress(f"{label}: {alts[label]}")
+        alts["note"] = ("seed %d; hierarchies of the headline build; FP64 Krylov, A_h products, true residual and "
+                        "coarsest solves in every form; difference measured against the FP64 GPU solve (oracle not "
+                        "run at this size)" % r["seed"])
+        line["alternatives"] = alts
 
     for r in runs:
         r["solver"].close()

@@ -68,24 +68,28 @@ def loss(y, e, w):
     return float(np.sum(w[:, None] * (y - e) ** 2) / y.shape[0])
 
 
-def backward(W, cache, dy):
-    """Gradients of sum(dy * y) with respect to W1, W2, W3 (chain rule by hand)."""
+def backward(W, cache, dy, grad_round=None):
+    """Gradients of sum(dy * y) with respect to W1, W2, W3 (chain rule by hand).
+    grad_round optionally rounds the back-propagated dy, da2, da1 (the GPU
+    stores them in bfloat16 before the weight-gradient products)."""
     W1, W2, W3 = W
     z, a1, h1, a2, h2 = cache
+    rnd = grad_round if grad_round is not None else (lambda t: t)
+    dy = rnd(dy)
     dW3 = h2.T @ dy
     dh2 = dy @ W3.T
-    da2 = dh2 * (a2 > 0.0)
+    da2 = rnd(dh2 * (a2 > 0.0))
     dW2 = h1.T @ da2
     dh1 = da2 @ W2.T
-    da1 = dh1 * (a1 > 0.0)
+    da1 = rnd(dh1 * (a1 > 0.0))
     dW1 = z.T @ da1
     return dW1, dW2, dW3
 
 
-def loss_and_grad(W, z, e, w, act_round=None):
+def loss_and_grad(W, z, e, w, act_round=None, grad_round=None):
     y, cache = forward(W, z, act_round)
     dy = (2.0 / y.shape[0]) * w[:, None] * (y - e)
-    return loss(y, e, w), backward(W, cache, dy)
+    return loss(y, e, w), backward(W, cache, dy, grad_round)
 
 
 def adam_step(W, G, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
@@ -153,9 +157,9 @@ def two_grid_energy(delta: np.ndarray, b: np.ndarray, A, P, Ac) -> tuple:
     return L, -2.0 * (Ad @ w)
 
 
-def energy_loss_and_grad(W, z, b, A, P, Ac, act_round=None):
+def energy_loss_and_grad(W, z, b, A, P, Ac, act_round=None, grad_round=None):
     """Network-level energy loss: delta = forward(W, z) (one row per node, d
     components, node-major like b), then two_grid_energy and the chain rule."""
     y, cache = forward(W, z, act_round)
     L, g = two_grid_energy(y.reshape(-1), b, A, P, Ac)
-    return L, backward(W, cache, g.reshape(y.shape))
+    return L, backward(W, cache, g.reshape(y.shape), grad_round)

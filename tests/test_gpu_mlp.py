@@ -5,7 +5,12 @@ oracle is fed the same BF16-rounded weights and inputs and rounds its hidden
 activations to BF16 as the GPU stores them, so forward results agree to FP32
 accumulation error (a rare flip of one activation's BF16 rounding aside).  The
 backward pass also stores dY, dA2 and dA1 in BF16, which bounds the gradient
-agreement at a few BF16 roundings (2^-9 relative each)."""
+agreement at a few BF16 roundings (2^-9 relative each) unless the oracle
+rounds them too: with the oracle given the same BF16 roundings of the
+activations and of the back-propagated dY, dA2, dA1, the gradients agree to
+FP32 accumulation and the occasional flip of one value's BF16 rounding
+(1e-3 relative asserted; before the backward roundings were mirrored the
+agreement was 2.9e-3)."""
 import itertools
 
 import numpy as np
@@ -151,14 +156,14 @@ def test_loss_and_gradients_match_oracle(d, m):
     s.mlp_set_weights(which, *[x.astype(np.float32) for x in W])
     loss, G = s.mlp_loss_grad(which, Z, E, w, d)
     lref, Gref = mlp.loss_and_grad(_bf16_weights(W), mlp.round_bf16(Z), E.astype(np.float64),
-                                   w.astype(np.float64), act_round=mlp.round_bf16)
+                                   w.astype(np.float64), act_round=mlp.round_bf16, grad_round=mlp.round_bf16)
     print(f"d={d} m={m}: loss {loss:.6e} oracle {lref:.6e}")
     assert abs(loss - lref) <= 1e-4 * lref
     for g, gr in zip(G, Gref):
         rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
         cos = float(np.sum(g * gr) / (np.linalg.norm(g) * np.linalg.norm(gr)))
         print(f"   grad rel err {rel:.2e} cos {cos:.6f}")
-        assert rel <= 2e-2
+        assert rel <= 1e-3
         assert cos >= 0.999
     s.close()
 
@@ -304,14 +309,14 @@ def test_energy_gradient_matches_oracle(name, which, max_coarse):
     z = mlp.round_bf16(_net_inputs(bs, sysm, which, b).astype(np.float32))
     L0 = h.levels[0]
     lref, Gref = mlp.energy_loss_and_grad(_bf16_weights(W), z, b.reshape(n0, nv), L0.A, L0.P, h.levels[1].A,
-                                          act_round=mlp.round_bf16)
+                                          act_round=mlp.round_bf16, grad_round=mlp.round_bf16)
     print(f"{name} {which}: energy loss {loss:.8e} oracle {lref:.8e}")
     assert abs(loss - lref) <= 1e-3 * abs(lref)
     for g, gr in zip(G, Gref):
         rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
         cos = float(np.sum(g * gr) / (np.linalg.norm(g) * np.linalg.norm(gr)))
         print(f"   grad rel err {rel:.2e} cos {cos:.6f}")
-        assert rel <= 2e-2
+        assert rel <= 1e-3
         assert cos >= 0.999
     s.close()
 
