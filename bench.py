@@ -669,8 +669,7 @@ def main():
     # with the FP64 GPU solve (the oracle is not run at this size): the FP32
     # preconditioner with and without BF16-stored smoother diagonals, the
     # paper's Section 4.4 fluid step (GMRES on each inverse of the Uzawa-like
-    # elimination), and the Uzawa-like step with one V-cycle per inverse
-    # (the plain reading of the paper's algorithm)
+    # elimination)
     if not args.no_mixed and args.precision == "f64":
         r = runs[0]
         x64 = r["x"].clone()
@@ -678,8 +677,6 @@ def main():
         forms = [("f32", "f32", {}), ("f32-bf16diag", "f32-bf16diag", {})]
         if args.uzawa_inner == 0:
             forms.append(("paper_uzawa_gmres2", "f64", dict(fluid_inner=0, uzawa_inner=2)))
-        if opts["fluid_inner"] > 0:
-            forms.append(("uzawa_vcycles", "f64", dict(fluid_inner=0, uzawa_inner=0)))
         for label, prec, over in forms:
             o2 = dict(opts)
             o2.update(over)

@@ -30,6 +30,10 @@
  *     synchronise except fsi_solve, which synchronises before filling info.
  *   - Sizes: row pointers are int64, column indices int32 (N < 2^31).
  *   - Threading: a context must not be used from two threads at once.
+ *   - Logging: with FSI_LOG set in the environment (to anything but "0") the
+ *     library writes one stderr line per setup phase (A_h upload, operators
+ *     and SA setup per hierarchy, device upload per hierarchy) and per solve
+ *     (iterations, true residual per block, time, bytes per phase).
  */
 #ifndef FSI_H
 #define FSI_H

@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -56,6 +57,39 @@ struct Error : std::runtime_error {
       throw ::fsi::Error(e_ == hipErrorOutOfMemory ? FSI_ERR_OOM : FSI_ERR_HIP,               \
                          std::string(#expr) + ": " + hipGetErrorString(e_));                  \
   } while (0)
+
+// ------------------------------------------------------------------ logging
+// FSI_LOG set (to anything but "0") in the environment: one stderr line per
+// setup phase and per solve, with wall times (the phases are host work or end
+// with a stream synchronisation, so the times are the phases' own).
+inline bool log_on() {
+  static const bool on = [] {
+    const char* v = std::getenv("FSI_LOG");
+    return v && std::strcmp(v, "0") != 0;
+  }();
+  return on;
+}
+
+__attribute__((format(printf, 1, 2))) inline void log_line(const char* fmt, ...) {
+  if (!log_on()) return;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  std::fprintf(stderr, "[fsi] %s\n", buf);
+}
+
+// Wall clock of a phase, logged when it ends.
+struct PhaseTimer {
+  const char* what;
+  std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+  explicit PhaseTimer(const char* w) : what(w) {}
+  double ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  void done(const char* extra = "") const { log_line("%s: %.1f ms%s", what, ms(), extra); }
+};
 
 // ---------------------------------------------------------- device memory
 struct DevBuf {
@@ -1304,9 +1338,17 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   P->d = c.d;
   P->n_m = c.n_m; P->n_s = c.n_s; P->n_f = c.n_f; P->n_vs = c.n_vs; P->n_vf = c.n_vf;
   P->n_p = c.n_p; P->N = c.N;
-  for (int h = 0; h < FSI_NHIER; ++h)
+  static const char* hname[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
+  for (int h = 0; h < FSI_NHIER; ++h) {
+    PhaseTimer t("upload (products, grouping, copies)");
     P->H[h] = upload_hier<T>(c.host_h[h], h == FSI_H_M ? c.d : 1, s, learned_capable(c, h), c.cheb[h], c.poly[h],
                              c.poly_ratio, node_components(c, h), c.precision == FSI_P_F32_BF16DIAG);
+    if (log_on()) {
+      HIP_TRY(hipStreamSynchronize(s));
+      log_line("upload %s: %.1f ms (%zu levels, %.3f GB per cycle)", hname[h], t.ms(), P->H[h].lev.size(),
+           P->H[h].bytes_per_cycle / 1e9);
+    }
+  }
   link_mlp(c, *P);
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.host_x_approx == FSI_X_BLOCKDIAG ? c.fluid_op : c.blk[FSI_F];  // F, or its refinement
@@ -1680,6 +1722,10 @@ fsi_status solve_impl(fsi_ctx& c, const double* b, double* x, const fsi_solve_op
   info.bytes_spmv = bytes_spmv;
   info.bytes_precond = bytes_precond;
   info.bytes_gs = bytes_gs;
+  log_line("solve: %d iterations, %d restarts, true rel. residual %.3e (mesh %.2e, solid %.2e, fluid %.2e), %.3f ms, "
+       "%.2f GB moved (A_h %.2f, P^-1 %.2f, Krylov %.2f)",
+       iters, restarts, rel, info.resid_block[0], info.resid_block[1], info.resid_block[2], ms,
+       (bytes_spmv + bytes_precond + bytes_gs) / 1e9, bytes_spmv / 1e9, bytes_precond / 1e9, bytes_gs / 1e9);
   return converged ? FSI_OK : FSI_NOT_CONVERGED;
 }
 
@@ -2425,8 +2471,11 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     static const char* hn[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
     SaHierarchy hh[FSI_NHIER];
     for (int h = 0; h < FSI_NHIER; ++h) {
+      PhaseTimer t("sa_setup");
       std::string m = sa_setup(*ops[h], blocks[h], *Bs[h], ks[h], prm, hh[h]);
       if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
+      log_line("SA setup %s: %.1f ms (%lld rows, %zu levels)", hn[h], t.ms(), (long long)ops[h]->nrows,
+           hh[h].levels.size());
     }
     for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
     c.fluid_op = std::move(Xop);
@@ -2656,8 +2705,10 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     // values.  Solid rows differ in about half their columns: plain rows.
     const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
     const int groups[4] = {1, 1, d, 1};
+    PhaseTimer t_up("setup_blocks: A_h segments upload");
     DCsr<double> dAh = upload_segments<double>(Ah, bounds, groups, 4, ctx->stream);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
+    t_up.done();
     // commit
     fsi_ctx& c = *ctx;
     c.d = d;
@@ -2717,6 +2768,7 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     prm.eps0 = o.strength0;
     prm.max_coarse = o.max_coarse;
     prm.max_levels = o.max_levels;
+    PhaseTimer t_build("build_precond");
     if (o.reuse) {
       if (!c.have_host_h) throw Error(FSI_ERR_STATE, "reuse needs a previous fsi_build_precond of this system");
       if (c.host_prm.eps0 != prm.eps0 || c.host_prm.max_coarse != prm.max_coarse ||
@@ -2724,7 +2776,9 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
         throw Error(FSI_ERR_STATE,
                     "reuse needs the AMG parameters and the Schur and X options of the previous build");
     } else {
+      PhaseTimer t("host hierarchies (operators and SA setups)");
       build_host_hierarchies(c, o, prm);
+      t.done();
     }
     for (int h = 0; h < FSI_NHIER; ++h) {
       c.poly[h] = ((o.poly_mask >> h) & 1) ? o.poly_degree : 0;
@@ -2740,9 +2794,14 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     c.m_alloc = -1;
     c.p64.reset();
     c.p32.reset();
-    if (o.precision == FSI_P_F64) c.p64 = make_precond<double>(c);
-    else c.p32 = make_precond<float>(c);
+    {
+      PhaseTimer t("device preconditioner (uploads, coupling blocks, workspace)");
+      if (o.precision == FSI_P_F64) c.p64 = make_precond<double>(c);
+      else c.p32 = make_precond<float>(c);
+      t.done();
+    }
     c.have_precond = true;
+    t_build.done(o.reuse ? " (hierarchies reused)" : "");
     return FSI_OK;
   });
 }
