@@ -71,11 +71,11 @@ def cpu_baseline(args, gpu_c3=None, sample_iters: int = 2):
     ctx = threadpool_limits(limits=1) if threadpool_limits else None
     try:
         bs = blocks.BlockSystem(sysm)
+        o = precond_opts(args, cfg.dim)
         t0 = time.perf_counter()
-        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=args.schur,
+        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=o["schur"],
                                       x_approx=args.x_approx)
         t_setup = time.perf_counter() - t0
-        o = precond_opts(args, cfg.dim)
         cheb = {h: o["cheb_degree"] for h in o["cheb"]} if o["cheb_degree"] > 0 else None
         poly = {h: (o["poly_degree"], o["poly_ratio"]) for h in o["poly"]}
         P = precond.amg_preconditioner(bs, H, cheb=cheb, poly=poly, fluid_inner=o["fluid_inner"],
@@ -257,9 +257,13 @@ def precond_opts(args, dim: int) -> dict:
     fluid_inner = (args.fluid_inner_arg if args.fluid_inner_arg is not None
                    else (0 if args.learned else 2))
     poly = poly_on(args)
+    # SIMPLEC in 3D: with the inner GMRES on F it cuts 64x16x16 from 33 to 26
+    # iterations (85.3 -> 66.8 ms) and 128x32x32 from 31 to 28 (519 -> 467 ms);
+    # without the inner GMRES it had raised 128x32x32 from 47 to 68
+    schur = args.schur_arg if args.schur_arg is not None else ("simple" if dim == 2 or args.learned else "simplec")
     return dict(max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
                 cheb=tuple(h for h in cheb_on.split(",") if h and h not in poly), poly=poly,
-                poly_degree=args.poly_degree, poly_ratio=args.poly_ratio, schur=args.schur,
+                poly_degree=args.poly_degree, poly_ratio=args.poly_ratio, schur=schur,
                 fluid_inner=0 if args.uzawa_inner > 0 else fluid_inner, fluid_inner_pc=args.fluid_inner_pc,
                 uzawa_inner=args.uzawa_inner, x_approx=args.x_approx)
 
@@ -386,7 +390,7 @@ def main():
                          "(default H_MS, none with --learned)")
     ap.add_argument("--schur", default=None, choices=["simple", "simplec"],
                     help="pressure Schur approximation -D W^{-1} G: W = diag(A_f) (simple) or its "
-                         "absolute row sums (simplec); default simple")
+                         "absolute row sums (simplec); default simplec in 3D, simple in 2D")
     ap.add_argument("--fluid-inner", type=int, default=None,
                     help="inner flexible GMRES steps for the fluid inverse (0: the Uzawa-like step "
                          "alone; default 2, 0 with --learned)")
@@ -417,7 +421,7 @@ def main():
                     help="only launch the A_h product 20 times and a 256 MiB device copy "
                          "(for hardware byte counters); prints nothing else")
     args = ap.parse_args()
-    args.cheb_on_arg, args.fluid_inner_arg = args.cheb_on, args.fluid_inner
+    args.cheb_on_arg, args.fluid_inner_arg, args.schur_arg = args.cheb_on, args.fluid_inner, args.schur
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
@@ -448,17 +452,13 @@ def main():
     # 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms; 14.4 ms with the Uzawa-like
     # inner step) and cut the 3D ones by a third (64x16x16: 46 -> 33
     # iterations, 93.8 -> 85.3 ms; 128x32x32: 47 -> 31, 635.6 -> 517.6 ms).
-    if args.schur is None:
-        # SIMPLE throughout: SIMPLEC (absolute row sums) cuts the 64x16x16
-        # solve from 46 to 36 iterations but raises the 128x32x32 one from 47
-        # to 68 and the 2D one from 39 to 69 (oracle), so it stays an option
-        args.schur = "simple"
     # cheb_on: the 2D pressure Schur approximation does best with Jacobi
     # sweeps (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one
     # needs the Chebyshev sweeps (64x16x16: 46 vs 530 iterations)
     opts = precond_opts(args, cfg.dim)
     args.cheb_on = ",".join(opts["cheb"])
     args.fluid_inner = opts["fluid_inner"]
+    args.schur = opts["schur"]
     if args.learned:
         learned_run(args, cfg)
         return

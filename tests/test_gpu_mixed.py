@@ -85,12 +85,12 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(name):
 
 def _bench_precond(dim):
     """The benchmarked preconditioner: Chebyshev(4) V-cycles on H_SIG (and on
-    H_P in 3D), M_s by three Chebyshev steps; in 2D the
-    fluid inverse by two inner GMRES steps preconditioned by the block
-    upper-triangular step."""
+    H_P in 3D), M_s by three Chebyshev steps, the fluid inverse by two inner
+    GMRES steps preconditioned by the block upper-triangular step, the
+    SIMPLEC pressure Schur approximation in 3D (SIMPLE in 2D)."""
     return dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG",) if dim == 2 else ("H_SIG", "H_P"),
-                poly=("H_MS",), poly_degree=3, fluid_inner=2 if dim == 2 else 0,
-                fluid_inner_pc="triangular")
+                poly=("H_MS",), poly_degree=3, fluid_inner=2, fluid_inner_pc="triangular",
+                schur="simple" if dim == 2 else "simplec")
 
 
 @pytest.mark.parametrize("name", ["c2", "m3"])
@@ -121,7 +121,7 @@ def test_fp32_preconditioner_in_the_benchmark_configuration(name):
     x32, _ = s.solve(b)
     s.close()
     assert np.array_equal(x32.cpu().numpy(), res["f32"][0])
-    H = precond.build_hierarchies(bs, max_coarse=opts["max_coarse"])
+    H = precond.build_hierarchies(bs, max_coarse=opts["max_coarse"], schur=opts["schur"])
     P = precond.amg_preconditioner(bs, H, cheb={h: opts["cheb_degree"] for h in opts["cheb"]},
                                    poly={h: (opts["poly_degree"], 8.0) for h in opts["poly"]},
                                    fluid_inner=opts["fluid_inner"], fluid_inner_pc=opts["fluid_inner_pc"])
@@ -165,7 +165,7 @@ def test_fp32_apply_precond_vs_fp64_oracle(name, precision, bench):
     mc = 40 if name == "c1" else 2000
     opts = _bench_precond(sysm.dim) if bench else {}
     opts["max_coarse"] = mc
-    H = precond.build_hierarchies(bs, max_coarse=mc)
+    H = precond.build_hierarchies(bs, max_coarse=mc, schur=opts.get("schur", "simple"))
     s = FsiSolver.from_system(sysm, device=0)
     s.build_precond(precision, **opts)
     import test_gpu_parity as tp
