@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -110,6 +111,89 @@ struct DevBuf {
   template <typename T> T* as() const { return static_cast<T*>(p); }
 };
 
+// ---------------------------------------------------------- host -> device
+// Setup uploads: the source image is written, on the host threads, into one
+// of two pinned staging buffers while the other one is in flight to the
+// device; every upload has finished when the call returns, so the host source
+// may be released right after.  fill(buf, off, n) writes bytes [off, off + n)
+// of the destination image into buf (a copy, or a conversion to the device
+// type); off and n are multiples of 8 except at the end of the image.
+struct Staging {
+  static constexpr size_t kChunk = size_t(32) << 20;
+  std::mutex mu;
+  char* buf[2] = {nullptr, nullptr};
+};
+
+inline Staging& staging() {
+  // pinned once per process and kept until it ends
+  static Staging* st = new Staging;
+  return *st;
+}
+
+template <class Fill>
+void staged_upload(void* dst, size_t bytes, hipStream_t s, Fill&& fill) {
+  if (bytes == 0) return;
+  constexpr size_t kPiece = size_t(1) << 20;  // bytes per host thread item
+  if (bytes <= kPiece) {
+    std::vector<char> tmp(bytes);
+    fill(tmp.data(), 0, bytes);
+    HIP_TRY(hipMemcpyAsync(dst, tmp.data(), bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return;
+  }
+  Staging& st = staging();
+  std::lock_guard<std::mutex> lock(st.mu);
+  for (auto& b : st.buf)
+    if (!b) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b), Staging::kChunk, hipHostMallocPortable));
+  struct Events {  // both buffers idle again on any exit
+    hipEvent_t e[2] = {nullptr, nullptr};
+    hipStream_t s;
+    ~Events() {
+      (void)hipStreamSynchronize(s);
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev{{nullptr, nullptr}, s};
+  for (auto& e : ev.e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  bool busy[2] = {false, false};
+  for (size_t off = 0, c = 0; off < bytes; off += Staging::kChunk, ++c) {
+    const int b = int(c & 1);
+    const size_t n = std::min(Staging::kChunk, bytes - off);
+    if (busy[b]) HIP_TRY(hipEventSynchronize(ev.e[b]));
+    char* buf = st.buf[b];
+    parallel_for(int64_t((n + kPiece - 1) / kPiece), [&](int64_t p0, int64_t p1) {
+      const size_t a = size_t(p0) * kPiece, z = std::min(n, size_t(p1) * kPiece);
+      fill(buf + a, off + a, z - a);
+    }, 2);
+    HIP_TRY(hipMemcpyAsync(static_cast<char*>(dst) + off, buf, n, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipEventRecord(ev.e[b], s));
+    busy[b] = true;
+  }
+  HIP_TRY(hipStreamSynchronize(s));
+}
+
+// count elements of src to dst (same type)
+template <typename U>
+void h2d(void* dst, const U* src, size_t count, hipStream_t s) {
+  staged_upload(dst, sizeof(U) * count, s, [src](char* buf, size_t off, size_t n) {
+    std::memcpy(buf, reinterpret_cast<const char*>(src) + off, n);
+  });
+}
+
+// count FP64 values of src to dst as T (rounded to nearest when T is float)
+template <typename T>
+void h2d_as(void* dst, const double* src, size_t count, hipStream_t s) {
+  if constexpr (std::is_same_v<T, double>) {
+    h2d(dst, src, count, s);
+  } else {
+    staged_upload(dst, sizeof(T) * count, s, [src](char* buf, size_t off, size_t n) {
+      T* o = reinterpret_cast<T*>(buf);
+      const double* x = src + off / sizeof(T);
+      for (size_t i = 0; i < n / sizeof(T); ++i) o[i] = T(x[i]);
+    });
+  }
+}
+
 template <typename T>
 struct DCsr {
   int64_t nrows = 0, ncols = 0, nnz = 0;
@@ -151,31 +235,33 @@ DCsr<T> upload(const HCsr& A, hipStream_t s) {
   D.group = pick_group(D.nnz, D.nrows, D.deep ? 8 : 3);
   D.rp = std::make_shared<DevBuf>();
   D.rp->alloc(sizeof(int64_t) * (A.nrows + 1));
-  HIP_TRY(hipMemcpyAsync(D.rp->p, A.rp.data(), sizeof(int64_t) * (A.nrows + 1), hipMemcpyHostToDevice, s));
+  h2d(D.rp->p, A.rp.data(), size_t(A.nrows + 1), s);
   if (D.nnz) {
     D.ci = std::make_shared<DevBuf>();
     D.ci->alloc(sizeof(int32_t) * D.nnz);
-    HIP_TRY(hipMemcpyAsync(D.ci->p, A.ci.data(), sizeof(int32_t) * D.nnz, hipMemcpyHostToDevice, s));
+    h2d(D.ci->p, A.ci.data(), size_t(D.nnz), s);
     D.val = std::make_shared<DevBuf>();
     D.val->alloc(sizeof(T) * D.nnz);
-    if (sizeof(T) == sizeof(double)) {
-      HIP_TRY(hipMemcpyAsync(D.val->p, A.v.data(), sizeof(double) * D.nnz, hipMemcpyHostToDevice, s));
-    } else {
-      std::vector<T> tmp(A.v.begin(), A.v.end());
-      HIP_TRY(hipMemcpyAsync(D.val->p, tmp.data(), sizeof(T) * D.nnz, hipMemcpyHostToDevice, s));
-      HIP_TRY(hipStreamSynchronize(s));
-    }
+    h2d_as<T>(D.val->p, A.v.data(), size_t(D.nnz), s);
   }
   return D;
 }
 
-// Device copy of a host array (setup only; synchronous, so the host array may
-// be released right after).
+// Device copy of a host array (setup only; finished on return).
 template <typename U>
-std::shared_ptr<DevBuf> upload_raw(const std::vector<U>& v) {
+std::shared_ptr<DevBuf> upload_raw(const std::vector<U>& v, hipStream_t s = nullptr) {
   auto b = std::make_shared<DevBuf>();
   b->alloc(sizeof(U) * std::max<size_t>(v.size(), 1));
-  if (!v.empty()) HIP_TRY(hipMemcpy(b->p, v.data(), sizeof(U) * v.size(), hipMemcpyHostToDevice));
+  h2d(b->p, v.data(), v.size(), s);
+  return b;
+}
+
+// Device copy of FP64 host values as T (setup only; finished on return).
+template <typename T>
+std::shared_ptr<DevBuf> upload_as(const std::vector<double>& v, hipStream_t s = nullptr) {
+  auto b = std::make_shared<DevBuf>();
+  b->alloc(sizeof(T) * std::max<size_t>(v.size(), 1));
+  h2d_as<T>(b->p, v.data(), v.size(), s);
   return b;
 }
 
@@ -194,7 +280,7 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
   D.deep = true;
   D.rp = upload_raw(G.rp);
   D.ci = upload_raw(G.ci);
-  D.val = upload_raw(std::vector<T>(gv.begin(), gv.end()));
+  D.val = upload_as<T>(gv);
   if (as_segment) {
     const int64_t units = G.nrows;
     const double avg = units ? double(D.nnz) / double(units) : 1.0;
@@ -221,11 +307,36 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
 // entries per lane, 4 to 32 lanes; measured best for long rows); segment q is
 // stored in groups of group[q] rows where that costs at most 5% zero fill.
 // bytes(): the matrix as stored (values, column lists, row or group pointers).
+// The plain arrays hold the rows of the ungrouped segments only (the rows of a
+// grouped segment are empty there); nnz stays the matrix's own count.
 template <typename T>
 DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, hipStream_t s) {
   if (nseg < 1 || nseg > 4 || bounds[0] != 0 || bounds[nseg] != A.nrows)
     throw Error(FSI_ERR_ARG, "row segments must cover the matrix in at most four parts");
-  DCsr<T> D = upload<T>(A, s);
+  int grs[4];
+  for (int q = 0; q < nseg; ++q) {
+    const int64_t r0 = bounds[q], r1 = bounds[q + 1];
+    const int64_t units = r1 - r0, nz = r1 > r0 ? A.rp[r1] - A.rp[r0] : 0;
+    int gr = group[q];
+    if (gr > 1 && (units <= 0 || units % gr != 0 ||
+                   double(group_entries(A, r0, r1, gr)) * gr > 1.05 * double(nz)))
+      gr = 1;
+    grs[q] = gr;
+  }
+  auto plain_row = [&](int64_t i) {
+    int q = 0;
+    while (q + 1 < nseg && i >= bounds[q + 1]) ++q;
+    return grs[q] == 1;
+  };
+  DCsr<T> D = upload<T>(build_rows(A.nrows, A.ncols,
+                                   [&](int64_t i) { return plain_row(i) ? A.rp[i + 1] - A.rp[i] : int64_t(0); },
+                                   [&](int64_t i, int32_t* oc, double* ov) {
+                                     if (!plain_row(i)) return;
+                                     std::copy(A.ci.begin() + A.rp[i], A.ci.begin() + A.rp[i + 1], oc);
+                                     std::copy(A.v.begin() + A.rp[i], A.v.begin() + A.rp[i + 1], ov);
+                                   }),
+                        s);
+  D.nnz = A.nnz();
   D.deep = true;
   RowSegments sg{};
   sg.nseg = 0;
@@ -237,8 +348,7 @@ DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, 
     if (r1 <= r0) continue;
     const int k = sg.nseg++;
     int64_t units = r1 - r0, nz = A.rp[r1] - A.rp[r0];
-    int gr = group[q];
-    if (gr > 1 && (units % gr != 0 || double(group_entries(A, r0, r1, gr)) * gr > 1.05 * double(nz))) gr = 1;
+    const int gr = grs[q];
     if (gr > 1) {
       std::vector<double> gv;
       const HCsr Gm = group_rows(A, r0, r1, gr, gv);
@@ -246,7 +356,7 @@ DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, 
       nz = Gm.nnz();
       D.grp_rp[k] = upload_raw(Gm.rp);
       D.grp_ci[k] = upload_raw(Gm.ci);
-      D.grp_val[k] = upload_raw(std::vector<T>(gv.begin(), gv.end()));
+      D.grp_val[k] = upload_as<T>(gv, s);
       sg.grp_rp[k] = D.grp_rp[k]->template as<int64_t>();
       sg.grp_ci[k] = D.grp_ci[k]->template as<int32_t>();
       sg.grp_val[k] = D.grp_val[k]->template as<T>();
@@ -301,14 +411,7 @@ template <typename T>
 std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) {
   auto b = std::make_shared<DevBuf>();
   b->alloc(sizeof(T) * v.size());
-  if (v.empty()) return b;
-  if (sizeof(T) == sizeof(double)) {
-    HIP_TRY(hipMemcpyAsync(b->p, v.data(), sizeof(double) * v.size(), hipMemcpyHostToDevice, s));
-  } else {
-    std::vector<T> tmp(v.begin(), v.end());
-    HIP_TRY(hipMemcpyAsync(b->p, tmp.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s));
-    HIP_TRY(hipStreamSynchronize(s));
-  }
+  h2d_as<T>(b->p, v.data(), v.size(), s);
   return b;
 }
 
@@ -2664,41 +2767,50 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
       if (Fpp.nnz() != 0) throw Error(FSI_ERR_STRUCT, "pressure-pressure block of F must be empty");
       // M = L (x) I_d
       const HCsr& M = H[FSI_M];
-      for (int64_t i = 0; i < M.nrows; ++i) {
-        const int64_t I = i / d, ci = i % d;
-        const int64_t r0 = I * d;
-        if (M.rp[i + 1] - M.rp[i] != M.rp[r0 + 1] - M.rp[r0])
-          throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
-        for (int64_t k = M.rp[i], k0 = M.rp[r0]; k < M.rp[i + 1]; ++k, ++k0) {
-          if (M.ci[k] % d != ci || M.ci[k] / d != M.ci[k0] / d || M.v[k] != M.v[k0])
-            throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
+      std::atomic<bool> kron_ok{true};
+      parallel_for(M.nrows, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e && kron_ok.load(std::memory_order_relaxed); ++i) {
+          const int64_t I = i / d, ci = i % d;
+          const int64_t r0 = I * d;
+          bool ok = M.rp[i + 1] - M.rp[i] == M.rp[r0 + 1] - M.rp[r0];
+          for (int64_t k = M.rp[i], k0 = M.rp[r0]; ok && k < M.rp[i + 1]; ++k, ++k0)
+            ok = M.ci[k] % d == ci && M.ci[k] / d == M.ci[k0] / d && M.v[k] == M.v[k0];
+          if (!ok) kron_ok.store(false);
         }
-      }
+      });
+      if (!kron_ok.load()) throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
     }
     // monolithic A_h with global columns for the outer product
-    HCsr Ah;
-    Ah.nrows = Ah.ncols = N;
-    Ah.rp.assign(N + 1, 0);
-    {
-      const int64_t off[3] = {0, L->n_m, L->n_m + L->n_s};
-      int64_t total = 0;
-      for (int b = 0; b < FSI_NBLK; ++b) total += H[b].nnz();
-      Ah.ci.reserve(total);
-      Ah.v.reserve(total);
-      for (int r = 0; r < 3; ++r) {
-        for (int64_t i = 0; i < sz[r]; ++i) {
+    // (row i of block row r: the blocks of that row in column order, their
+    // columns shifted to global ones; built on the host threads)
+    const int64_t off[3] = {0, L->n_m, L->n_m + L->n_s};
+    auto block_row = [&](int64_t gi, int& r, int64_t& i) {
+      r = gi < off[1] ? 0 : gi < off[2] ? 1 : 2;
+      i = gi - off[r];
+    };
+    HCsr Ah = build_rows(
+        N, N,
+        [&](int64_t gi) {
+          int r;
+          int64_t i, n = 0;
+          block_row(gi, r, i);
+          for (int b = 0; b < FSI_NBLK; ++b)
+            if (bi[b] == r) n += H[b].rp[i + 1] - H[b].rp[i];
+          return n;
+        },
+        [&](int64_t gi, int32_t* oc, double* ov) {
+          int r;
+          int64_t i;
+          block_row(gi, r, i);
           for (int b = 0; b < FSI_NBLK; ++b) {
             if (bi[b] != r) continue;
             const HCsr& A = H[b];
             for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-              Ah.ci.push_back(int32_t(A.ci[k] + off[bj[b]]));
-              Ah.v.push_back(A.v[k]);
+              *oc++ = int32_t(A.ci[k] + off[bj[b]]);
+              *ov++ = A.v[k];
             }
           }
-          Ah.rp[off[r] + i + 1] = int64_t(Ah.ci.size());
-        }
-      }
-    }
+        });
     // mesh, solid, fluid-velocity and pressure rows as four segments; the d
     // velocity rows of a fluid node share their columns (the stress couples
     // the components): stored as groups of d rows, one column index per d

@@ -4,6 +4,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <stdexcept>
 #include <thread>
 
 namespace fsi {
@@ -38,27 +39,44 @@ std::string csr_check(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* 
     std::snprintf(buf, sizeof buf, "rowptr[nrows] = %lld != nnz = %lld", (long long)rp[nrows], (long long)nnz);
     return buf;
   }
-  for (int64_t i = 0; i < nrows; ++i) {
+  for (int64_t i = 0; i < nrows; ++i)
     if (rp[i + 1] < rp[i]) {
       std::snprintf(buf, sizeof buf, "rowptr decreases at row %lld", (long long)i);
       return buf;
     }
-    for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
-      if (ci[k] < 0 || ci[k] >= ncols) {
-        std::snprintf(buf, sizeof buf, "column %d out of range in row %lld", ci[k], (long long)i);
-        return buf;
-      }
-      if (k > rp[i] && ci[k] <= ci[k - 1]) {
-        std::snprintf(buf, sizeof buf, "columns not strictly increasing in row %lld", (long long)i);
-        return buf;
-      }
-      if (!std::isfinite(v[k])) {
-        std::snprintf(buf, sizeof buf, "non-finite value in row %lld", (long long)i);
-        return buf;
+  // rows checked on the host threads; the first failing row (in row order)
+  // is reported, whatever the thread count
+  std::atomic<int64_t> bad{nrows};
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e && i < bad.load(); ++i) {
+      bool ok = true;
+      for (int64_t k = rp[i]; k < rp[i + 1] && ok; ++k)
+        ok = ci[k] >= 0 && ci[k] < ncols && (k == rp[i] || ci[k] > ci[k - 1]) && std::isfinite(v[k]);
+      if (!ok) {
+        int64_t cur = bad.load();
+        while (i < cur && !bad.compare_exchange_weak(cur, i)) {
+        }
+        return;
       }
     }
+  }, int64_t(1) << 14);
+  const int64_t i = bad.load();
+  if (i == nrows) return "";
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+    if (ci[k] < 0 || ci[k] >= ncols) {
+      std::snprintf(buf, sizeof buf, "column %d out of range in row %lld", ci[k], (long long)i);
+      return buf;
+    }
+    if (k > rp[i] && ci[k] <= ci[k - 1]) {
+      std::snprintf(buf, sizeof buf, "columns not strictly increasing in row %lld", (long long)i);
+      return buf;
+    }
+    if (!std::isfinite(v[k])) {
+      std::snprintf(buf, sizeof buf, "non-finite value in row %lld", (long long)i);
+      return buf;
+    }
   }
-  return "";
+  return "invalid row";
 }
 
 HCsr csr_copy(int64_t nrows, int64_t ncols, const int64_t* rp, const int32_t* ci, const double* v) {
@@ -148,77 +166,89 @@ HCsr spgemm(const HCsr& A, const HCsr& B) {
 }
 
 HCsr add(const HCsr& A, const HCsr& B, double alpha) {
-  HCsr C;
-  C.nrows = A.nrows;
-  C.ncols = A.ncols;
-  C.rp.assign(A.nrows + 1, 0);
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    int64_t ka = A.rp[i], kb = B.rp[i];
+  // merge of row i of A and alpha * row i of B: out == nullptr only counts
+  auto merge = [&](int64_t i, int32_t* oc, double* ov) {
+    int64_t ka = A.rp[i], kb = B.rp[i], n = 0;
     while (ka < A.rp[i + 1] || kb < B.rp[i + 1]) {
-      int32_t ja = ka < A.rp[i + 1] ? A.ci[ka] : INT32_MAX;
-      int32_t jb = kb < B.rp[i + 1] ? B.ci[kb] : INT32_MAX;
+      const int32_t ja = ka < A.rp[i + 1] ? A.ci[ka] : INT32_MAX;
+      const int32_t jb = kb < B.rp[i + 1] ? B.ci[kb] : INT32_MAX;
       double val;
       int32_t j;
       if (ja == jb) { j = ja; val = A.v[ka++] + alpha * B.v[kb++]; }
       else if (ja < jb) { j = ja; val = A.v[ka++]; }
       else { j = jb; val = alpha * B.v[kb++]; }
       if (val != 0.0) {
-        C.ci.push_back(j);
-        C.v.push_back(val);
+        if (oc) { oc[n] = j; ov[n] = val; }
+        ++n;
       }
     }
-    C.rp[i + 1] = int64_t(C.ci.size());
-  }
-  return C;
+    return n;
+  };
+  return build_rows(A.nrows, A.ncols, [&](int64_t i) { return merge(i, nullptr, nullptr); },
+                    [&](int64_t i, int32_t* oc, double* ov) { merge(i, oc, ov); });
 }
 
 HCsr sub_block(const HCsr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1) {
-  HCsr C;
-  C.nrows = r1 - r0;
-  C.ncols = c1 - c0;
-  C.rp.assign(C.nrows + 1, 0);
-  for (int64_t i = r0; i < r1; ++i) {
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.ci[k] >= c0 && A.ci[k] < c1) {
-        C.ci.push_back(int32_t(A.ci[k] - c0));
-        C.v.push_back(A.v[k]);
-      }
-    C.rp[i - r0 + 1] = int64_t(C.ci.size());
-  }
-  return C;
+  // the columns of a row are sorted: the block's part is one contiguous run
+  auto run = [&](int64_t i, int64_t& k0, int64_t& k1) {
+    const int32_t* b = A.ci.data() + A.rp[i];
+    const int32_t* e = A.ci.data() + A.rp[i + 1];
+    k0 = std::lower_bound(b, e, int64_t(c0), [](int32_t c, int64_t x) { return c < x; }) - A.ci.data();
+    k1 = std::lower_bound(b, e, int64_t(c1), [](int32_t c, int64_t x) { return c < x; }) - A.ci.data();
+  };
+  return build_rows(r1 - r0, c1 - c0,
+                    [&](int64_t q) {
+                      int64_t k0, k1;
+                      run(r0 + q, k0, k1);
+                      return k1 - k0;
+                    },
+                    [&](int64_t q, int32_t* oc, double* ov) {
+                      int64_t k0, k1;
+                      run(r0 + q, k0, k1);
+                      for (int64_t k = k0; k < k1; ++k) {
+                        *oc++ = int32_t(A.ci[k] - c0);
+                        *ov++ = A.v[k];
+                      }
+                    });
 }
 
 void drop_zeros(HCsr& A) {
-  int64_t w = 0;
-  std::vector<int64_t> rp(A.nrows + 1, 0);
-  for (int64_t i = 0; i < A.nrows; ++i) {
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.v[k] != 0.0) {
-        A.ci[w] = A.ci[k];
-        A.v[w] = A.v[k];
-        ++w;
-      }
-    rp[i + 1] = w;
-  }
-  A.rp.swap(rp);
-  A.ci.resize(w);
-  A.v.resize(w);
+  HCsr C = build_rows(A.nrows, A.ncols,
+                      [&](int64_t i) {
+                        int64_t n = 0;
+                        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) n += A.v[k] != 0.0;
+                        return n;
+                      },
+                      [&](int64_t i, int32_t* oc, double* ov) {
+                        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+                          if (A.v[k] != 0.0) {
+                            *oc++ = A.ci[k];
+                            *ov++ = A.v[k];
+                          }
+                      });
+  A = std::move(C);
 }
 
 void scale_rows(HCsr& A, const std::vector<double>& s) {
-  for (int64_t i = 0; i < A.nrows; ++i)
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) A.v[k] = s[i] * A.v[k];
+  parallel_for(A.nrows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) A.v[k] = s[i] * A.v[k];
+  });
 }
 
 void scale_cols(HCsr& A, const std::vector<double>& s) {
-  for (int64_t k = 0; k < A.nnz(); ++k) A.v[k] = A.v[k] * s[A.ci[k]];
+  parallel_for(A.nrows, [&](int64_t b, int64_t e) {
+    for (int64_t k = A.rp[b]; k < A.rp[e]; ++k) A.v[k] = A.v[k] * s[A.ci[k]];
+  });
 }
 
 std::vector<double> diagonal(const HCsr& A) {
   std::vector<double> d(A.nrows, 0.0);
-  for (int64_t i = 0; i < A.nrows; ++i)
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
-      if (A.ci[k] == i) d[i] = A.v[k];
+  parallel_for(A.nrows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i)
+      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+        if (A.ci[k] == i) d[i] = A.v[k];
+  });
   return d;
 }
 
@@ -234,28 +264,41 @@ void matvec(const HCsr& A, const double* x, double* y) {
 }
 
 HCsr group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, std::vector<double>& val) {
-  HCsr G;
-  G.nrows = (r1 - r0) / g;
-  G.ncols = A.ncols;
-  G.rp.assign(G.nrows + 1, 0);
-  val.clear();
-  std::vector<int64_t> k(g);
-  for (int64_t q = 0; q < G.nrows; ++q) {
+  // merge of the g sorted column lists of group q: cols == nullptr only counts
+  auto merge = [&](int64_t q, int32_t* cols, double* vals) {
     const int64_t row = r0 + q * g;
+    int64_t k[8];
     for (int r = 0; r < g; ++r) k[r] = A.rp[row + r];
-    while (true) {  // merge the g sorted column lists
+    int64_t n = 0;
+    while (true) {
       int32_t c = INT32_MAX;
       for (int r = 0; r < g; ++r)
         if (k[r] < A.rp[row + r + 1]) c = std::min(c, A.ci[k[r]]);
       if (c == INT32_MAX) break;
-      G.ci.push_back(c);
+      if (cols) cols[n] = c;
       for (int r = 0; r < g; ++r) {
-        if (k[r] < A.rp[row + r + 1] && A.ci[k[r]] == c) val.push_back(A.v[k[r]++]);
-        else val.push_back(0.0);
+        const bool has = k[r] < A.rp[row + r + 1] && A.ci[k[r]] == c;
+        if (cols) vals[n * g + r] = has ? A.v[k[r]] : 0.0;
+        if (has) ++k[r];
       }
+      ++n;
     }
-    G.rp[q + 1] = int64_t(G.ci.size());
-  }
+    return n;
+  };
+  if (g < 1 || g > 8) throw std::invalid_argument("group_rows: group size must be in 1..8");
+  HCsr G;
+  G.nrows = (r1 - r0) / g;
+  G.ncols = A.ncols;
+  G.rp.assign(G.nrows + 1, 0);
+  parallel_for(G.nrows, [&](int64_t b, int64_t e) {
+    for (int64_t q = b; q < e; ++q) G.rp[q + 1] = merge(q, nullptr, nullptr);
+  });
+  for (int64_t q = 0; q < G.nrows; ++q) G.rp[q + 1] += G.rp[q];
+  G.ci.resize(G.rp[G.nrows]);
+  val.assign(size_t(G.rp[G.nrows]) * g, 0.0);
+  parallel_for(G.nrows, [&](int64_t b, int64_t e) {
+    for (int64_t q = b; q < e; ++q) merge(q, G.ci.data() + G.rp[q], val.data() + size_t(G.rp[q]) * g);
+  });
   return G;
 }
 

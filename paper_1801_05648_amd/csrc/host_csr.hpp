@@ -22,6 +22,28 @@ struct HCsr {
 // calling thread alone when n < min_n: items too small to pay for threads).
 void parallel_for(int64_t n, const std::function<void(int64_t, int64_t)>& f, int64_t min_n = 4096);
 
+// Rows [0, nrows) of a CSR matrix built on the host threads in two passes:
+// count(i) gives the length of row i, fill(i, ci, v) writes the row at ci, v.
+// Every row is formed the same way on any thread, so the result does not
+// depend on the thread count.
+template <class Count, class Fill>
+HCsr build_rows(int64_t nrows, int64_t ncols, Count&& count, Fill&& fill, int64_t min_n = 4096) {
+  HCsr C;
+  C.nrows = nrows;
+  C.ncols = ncols;
+  C.rp.assign(nrows + 1, 0);
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) C.rp[i + 1] = count(i);
+  }, min_n);
+  for (int64_t i = 0; i < nrows; ++i) C.rp[i + 1] += C.rp[i];
+  C.ci.resize(C.rp[nrows]);
+  C.v.resize(C.rp[nrows]);
+  parallel_for(nrows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) fill(i, C.ci.data() + C.rp[i], C.v.data() + C.rp[i]);
+  }, min_n);
+  return C;
+}
+
 // Well-formedness: row pointers, column range, strictly increasing columns,
 // finite values.  Returns an empty string when valid.
 std::string csr_check(int64_t nrows, int64_t ncols, int64_t nnz, const int64_t* rp, const int32_t* ci,
