@@ -34,6 +34,7 @@
 #include "kernels.hpp"
 #include "mlp.hpp"
 #include "sa_setup.hpp"
+#include "spgemm.hpp"
 
 // Staging of fsi_mlp_forward_noalloc: the FP32 copies of the residual and of
 // the network's correction (kNoAllocStage entries each) in one array per GPU,
@@ -194,6 +195,59 @@ void h2d_as(void* dst, const double* src, size_t count, hipStream_t s) {
   }
 }
 
+// count elements of device array src to host array dst, through the same
+// staging buffers (filled by the DMA engine, emptied on the host threads)
+template <typename U>
+void d2h(U* dst, const void* src, size_t count, hipStream_t s) {
+  const size_t bytes = sizeof(U) * count;
+  if (bytes == 0) return;
+  constexpr size_t kPiece = size_t(1) << 20;
+  if (bytes <= kPiece) {
+    HIP_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    return;
+  }
+  Staging& st = staging();
+  std::lock_guard<std::mutex> lock(st.mu);
+  for (auto& b : st.buf)
+    if (!b) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b), Staging::kChunk, hipHostMallocPortable));
+  auto drain = [&](int b, size_t off, size_t n) {
+    char* out = reinterpret_cast<char*>(dst) + off;
+    const char* buf = st.buf[b];
+    parallel_for(int64_t((n + kPiece - 1) / kPiece), [&](int64_t p0, int64_t p1) {
+      const size_t a = size_t(p0) * kPiece, z = std::min(n, size_t(p1) * kPiece);
+      std::memcpy(out + a, buf + a, z - a);
+    }, 2);
+  };
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    hipStream_t s;
+    ~Events() {
+      (void)hipStreamSynchronize(s);
+      for (auto& x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev{{nullptr, nullptr}, s};
+  for (auto& e : ev.e) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  size_t prev_off = 0, prev_n = 0;
+  int prev_b = -1;
+  for (size_t off = 0, c = 0; off < bytes; off += Staging::kChunk, ++c) {
+    const int b = int(c & 1);
+    const size_t n = std::min(Staging::kChunk, bytes - off);
+    HIP_TRY(hipMemcpyAsync(st.buf[b], static_cast<const char*>(src) + off, n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipEventRecord(ev.e[b], s));
+    if (prev_b >= 0) {
+      HIP_TRY(hipEventSynchronize(ev.e[prev_b]));
+      drain(prev_b, prev_off, prev_n);
+    }
+    prev_b = b;
+    prev_off = off;
+    prev_n = n;
+  }
+  HIP_TRY(hipEventSynchronize(ev.e[prev_b]));
+  drain(prev_b, prev_off, prev_n);
+}
+
 template <typename T>
 struct DCsr {
   int64_t nrows = 0, ncols = 0, nnz = 0;
@@ -264,6 +318,95 @@ std::shared_ptr<DevBuf> upload_as(const std::vector<double>& v, hipStream_t s = 
   h2d_as<T>(b->p, v.data(), v.size(), s);
   return b;
 }
+
+// C = A B on the device, bitwise equal to the host product spgemm(A, B) (the
+// kernels form every row as the host does).  Rows with more than 4096
+// distinct columns are formed on the host.  Small products stay on the host.
+HCsr device_spgemm(const HCsr& A, const HCsr& B, hipStream_t s) {
+  if (A.ncols != B.nrows) throw Error(FSI_ERR_ARG, "sparse product of mismatched shapes");
+  const int64_t m = A.nrows;
+  if (m > INT32_MAX || A.nnz() + B.nnz() < (int64_t(1) << 16) || A.nnz() == 0 || B.nnz() == 0)
+    return spgemm(A, B);
+  auto up = [&](const auto& v) { return upload_raw(v, s); };
+  auto arp = up(A.rp), aci = up(A.ci), av = up(A.v), brp = up(B.rp), bci = up(B.ci), bv = up(B.v);
+  DevBuf cnt;
+  cnt.alloc(sizeof(int64_t) * m);
+  const int64_t* drp = arp->as<int64_t>();
+  const int32_t* dci = aci->as<int32_t>();
+  const double* dv = av->as<double>();
+  const int64_t* ebp = brp->as<int64_t>();
+  const int32_t* eci = bci->as<int32_t>();
+  const double* ev = bv->as<double>();
+  int64_t* dcnt = cnt.as<int64_t>();
+  // counts: every row with the small table, the overflowing rows with the large one
+  spgemm_rows_kernel<kSpgSmall, false><<<unsigned(m), 64, 0, s>>>(nullptr, drp, dci, dv, ebp, eci, ev, dcnt,
+                                                                  nullptr, nullptr, nullptr);
+  HIP_TRY(hipGetLastError());
+  std::vector<int64_t> hc(m);
+  d2h(hc.data(), dcnt, size_t(m), s);
+  std::vector<int32_t> small_rows, large_rows, host_rows;
+  for (int64_t i = 0; i < m; ++i)
+    if (hc[i] < 0) large_rows.push_back(int32_t(i));
+  std::shared_ptr<DevBuf> dlarge;
+  if (!large_rows.empty()) {
+    dlarge = up(large_rows);
+    spgemm_rows_kernel<kSpgLarge, false><<<unsigned(large_rows.size()), 64, 0, s>>>(
+        dlarge->as<int32_t>(), drp, dci, dv, ebp, eci, ev, dcnt, nullptr, nullptr, nullptr);
+    HIP_TRY(hipGetLastError());
+    d2h(hc.data(), dcnt, size_t(m), s);
+  }
+  std::vector<char> cls(m, 0);  // 0: small table, 1: large table, 2: host
+  for (int32_t i : large_rows) cls[i] = hc[i] < 0 ? 2 : 1;
+  for (int64_t i = 0; i < m; ++i) {
+    if (cls[i] == 0) small_rows.push_back(int32_t(i));
+    else if (cls[i] == 2) host_rows.push_back(int32_t(i));
+  }
+  // rows formed on the host
+  std::vector<std::vector<int32_t>> hcols(host_rows.size());
+  std::vector<std::vector<double>> hvals(host_rows.size());
+  parallel_for(int64_t(host_rows.size()), [&](int64_t b, int64_t e) {
+    SpgemmWork w;
+    for (int64_t q = b; q < e; ++q) spgemm_row(A, B, host_rows[q], w, hcols[q], hvals[q]);
+  }, 2);
+  for (size_t q = 0; q < host_rows.size(); ++q) hc[host_rows[q]] = int64_t(hcols[q].size());
+  HCsr C;
+  C.nrows = m;
+  C.ncols = B.ncols;
+  C.rp.assign(m + 1, 0);
+  for (int64_t i = 0; i < m; ++i) C.rp[i + 1] = C.rp[i] + hc[i];
+  const int64_t nnz = C.rp[m];
+  auto crp = up(C.rp);
+  DevBuf cci, cv;
+  cci.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
+  cv.alloc(sizeof(double) * std::max<int64_t>(nnz, 1));
+  if (!small_rows.empty()) {
+    auto dsmall = up(small_rows);
+    spgemm_rows_kernel<kSpgSmall, true><<<unsigned(small_rows.size()), 64, 0, s>>>(
+        dsmall->as<int32_t>(), drp, dci, dv, ebp, eci, ev, dcnt, crp->as<int64_t>(), cci.as<int32_t>(),
+        cv.as<double>());
+    HIP_TRY(hipGetLastError());
+  }
+  std::vector<int32_t> dev_large;
+  for (int32_t i : large_rows)
+    if (cls[i] == 1) dev_large.push_back(i);
+  if (!dev_large.empty()) {
+    auto dl = up(dev_large);
+    spgemm_rows_kernel<kSpgLarge, true><<<unsigned(dev_large.size()), 64, 0, s>>>(
+        dl->as<int32_t>(), drp, dci, dv, ebp, eci, ev, dcnt, crp->as<int64_t>(), cci.as<int32_t>(),
+        cv.as<double>());
+    HIP_TRY(hipGetLastError());
+  }
+  C.ci.resize(nnz);
+  C.v.resize(nnz);
+  d2h(C.ci.data(), cci.p, size_t(nnz), s);
+  d2h(C.v.data(), cv.p, size_t(nnz), s);
+  for (size_t q = 0; q < host_rows.size(); ++q) {
+    std::copy(hcols[q].begin(), hcols[q].end(), C.ci.begin() + C.rp[host_rows[q]]);
+    std::copy(hvals[q].begin(), hvals[q].end(), C.v.begin() + C.rp[host_rows[q]]);
+  }
+  return C;
+}
+
 
 // A in groups of g consecutive rows sharing one column list (g values per
 // entry), for the grouped level sweeps; with `as_segment` also described as a
@@ -644,7 +787,8 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
     d.omega = T(h.omega);
     if (l < L && cheb > 0) {
       if (!(h.omega > 0.0)) throw Error(FSI_ERR_NUMERIC, "Chebyshev smoothing needs a positive spectral estimate");
-      HCsr AP = spgemm(h.A, h.P);
+      const HCsr APc = h.AP.nrows ? HCsr{} : device_spgemm(h.A, h.P, s);  // A P unless the setup kept it
+      const HCsr& AP = h.AP.nrows ? h.AP : APc;
       d.cheb = cheb;
       cheb_coefficients<T>(h.omega, cheb, d.ca, d.cc);
       d.A0 = upload<T>(h.A, s);
@@ -653,7 +797,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       // Above 2^18 entries of R A, or on coarser levels (where R A's rows are
       // long next to the level's own), the fused coarse rows outlast the
       // launch saved (measured on the 2D and 3D workloads).
-      const HCsr RA = spgemm(h.R, h.A);
+      const HCsr RA = device_spgemm(h.R, h.A, s);
       if (l == 0 && RA.nnz() < kFuseRestrictNnz) {
         d.RRA = upload_pair<T>(h.R, RA);
         d.gres = d.RRA.group >= 32 ? 64 : 16;
@@ -680,9 +824,11 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       D.bytes_per_cycle += d.A0.bytes() * (2 * cheb - 1) + rbytes + d.P.bytes() + d.AP.bytes() +
                            double(d.n) * (6.0 * cheb * vb + 2 * db) + double(h.P.ncols) * 2 * vb;
     } else if (l < L) {
-      // setup-time products for the two-launch level sweeps
-      HCsr AP = spgemm(h.A, h.P);
-      HCsr RA = spgemm(h.R, h.A);
+      // setup-time products for the two-launch level sweeps (A P unless the
+      // setup kept it)
+      const HCsr APc = h.AP.nrows ? HCsr{} : device_spgemm(h.A, h.P, s);
+      const HCsr& AP = h.AP.nrows ? h.AP : APc;
+      HCsr RA = device_spgemm(h.R, h.A, s);
       const std::vector<double> dv = level_dinv(h.dinv);
       std::vector<double> wd(dv.size());
       for (size_t i = 0; i < wd.size(); ++i) wd[i] = h.omega * dv[i];
@@ -1453,6 +1599,11 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     }
   }
   link_mlp(c, *P);
+  // the setup's A P products are on the device now: release the host copies
+  // (a later build recomputes them)
+  for (auto& H : c.host_h)
+    for (auto& L : H.levels) L.AP = HCsr{};
+  PhaseTimer t_cb("coupling blocks (and F for the inner steps)");
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.host_x_approx == FSI_X_BLOCKDIAG ? c.fluid_op : c.blk[FSI_F];  // F, or its refinement
   P->S_vu = upload<T>(sub_block(S, 0, c.n_vs, c.n_vs, c.n_s), s);
@@ -1465,18 +1616,13 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   {
     const HCsr& A = c.blk[FSI_CFM];
     const HCsr& B = c.blk[FSI_CFS];
-    HCsr M;
-    M.nrows = c.n_f;
-    M.ncols = c.n_m + c.n_s;
-    M.rp.assign(c.n_f + 1, 0);
-    for (int64_t i = 0; i < c.n_f; ++i) {
-      for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) { M.ci.push_back(A.ci[k]); M.v.push_back(A.v[k]); }
-      for (int64_t k = B.rp[i]; k < B.rp[i + 1]; ++k) {
-        M.ci.push_back(int32_t(B.ci[k] + c.n_m));
-        M.v.push_back(B.v[k]);
-      }
-      M.rp[i + 1] = int64_t(M.ci.size());
-    }
+    const int32_t nm = int32_t(c.n_m);
+    HCsr M = build_rows(
+        c.n_f, c.n_m + c.n_s, [&](int64_t i) { return A.rp[i + 1] - A.rp[i] + B.rp[i + 1] - B.rp[i]; },
+        [&](int64_t i, int32_t* oc, double* ov) {
+          for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) { *oc++ = A.ci[k]; *ov++ = A.v[k]; }
+          for (int64_t k = B.rp[i]; k < B.rp[i + 1]; ++k) { *oc++ = B.ci[k] + nm; *ov++ = B.v[k]; }
+        });
     // velocity rows in groups of d (a node's rows share their columns), then
     // the pressure rows
     const int64_t bounds[3] = {0, c.n_vf, c.n_f};
@@ -1495,6 +1641,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
   }
   P->alloc_tmp();
   HIP_TRY(hipStreamSynchronize(s));
+  t_cb.done();
   return P;
 }
 
@@ -2520,20 +2667,16 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     if (o.x_approx == FSI_X_BLOCKDIAG) Xop = fluid_operator_refined(c);
     const HCsr& F = o.x_approx == FSI_X_BLOCKDIAG ? Xop : c.blk[FSI_F];
     // operators of the five hierarchies
-    HCsr Lm;  // scalar L of M = L (x) I_d
-    {
-      const HCsr& M = c.blk[FSI_M];
-      Lm.nrows = Lm.ncols = M.nrows / d;
-      Lm.rp.assign(Lm.nrows + 1, 0);
-      for (int64_t I = 0; I < Lm.nrows; ++I) {
-        const int64_t i = I * d;
-        for (int64_t k = M.rp[i]; k < M.rp[i + 1]; ++k) {
-          Lm.ci.push_back(M.ci[k] / d);
-          Lm.v.push_back(M.v[k]);
-        }
-        Lm.rp[I + 1] = int64_t(Lm.ci.size());
-      }
-    }
+    // scalar L of M = L (x) I_d: the first row of every node, columns / d
+    const HCsr& M = c.blk[FSI_M];
+    HCsr Lm = build_rows(
+        M.nrows / d, M.nrows / d, [&](int64_t I) { return M.rp[I * d + 1] - M.rp[I * d]; },
+        [&](int64_t I, int32_t* oc, double* ov) {
+          for (int64_t k = M.rp[I * d]; k < M.rp[I * d + 1]; ++k) {
+            *oc++ = M.ci[k] / d;
+            *ov++ = M.v[k];
+          }
+        });
     HCsr Svv = sub_block(S, 0, c.n_vs, 0, c.n_vs);
     HCsr Svu = sub_block(S, 0, c.n_vs, c.n_vs, c.n_s);
     HCsr Sig = add(Svv, Svu, c.dt_theta);            // Sigma_s = S_vv + dt theta S_vu
@@ -2557,7 +2700,7 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
       }
       HCsr Ds = Dm;
       scale_cols(Ds, dinv);
-      Sp = spgemm(Ds, Gm);
+      Sp = device_spgemm(Ds, Gm, c.stream);
       for (double& v : Sp.v) v = -v;
       if (Zpp.nnz() > 0) Sp = add(Sp, Zpp, 1.0);
       drop_zeros(Sp);
@@ -2566,19 +2709,21 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     std::vector<double> Brig = rigid_modes(c, krig);
     std::vector<double> Bt(size_t(c.n_vf) * d, 0.0);
     for (int64_t i = 0; i < c.n_vf; ++i) Bt[size_t(i) * d + (i % d)] = 1.0;
-    const HCsr* ops[FSI_NHIER] = {&Lm, &Sig, &Suu, &Af, &Sp};
+    HCsr* ops[FSI_NHIER] = {&Lm, &Sig, &Suu, &Af, &Sp};
     const int blocks[FSI_NHIER] = {1, d, 1, d, 1};
     const std::vector<double> ones_m(Lm.nrows, 1.0), ones_s(c.n_vs, 1.0), ones_p(c.n_p, 1.0);
     const std::vector<double>* Bs[FSI_NHIER] = {&ones_m, &Brig, &ones_s, &Bt, &ones_p};
     const int ks[FSI_NHIER] = {1, krig, 1, d, 1};
     static const char* hn[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
     SaHierarchy hh[FSI_NHIER];
+    // the sparse products on the device (bitwise equal to the host's)
+    const SpgemmFn mul = [&](const HCsr& X, const HCsr& Y) { return device_spgemm(X, Y, c.stream); };
     for (int h = 0; h < FSI_NHIER; ++h) {
       PhaseTimer t("sa_setup");
-      std::string m = sa_setup(*ops[h], blocks[h], *Bs[h], ks[h], prm, hh[h]);
+      const long long rows = (long long)ops[h]->nrows;
+      std::string m = sa_setup(std::move(*ops[h]), blocks[h], *Bs[h], ks[h], prm, hh[h], mul);
       if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
-      log_line("SA setup %s: %.1f ms (%lld rows, %zu levels)", hn[h], t.ms(), (long long)ops[h]->nrows,
-           hh[h].levels.size());
+      log_line("SA setup %s: %.1f ms (%lld rows, %zu levels)", hn[h], t.ms(), rows, hh[h].levels.size());
     }
     for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
     c.fluid_op = std::move(Xop);

@@ -94,18 +94,80 @@ HCsr transpose(const HCsr& A) {
   T.nrows = A.ncols;
   T.ncols = A.nrows;
   T.rp.assign(T.nrows + 1, 0);
-  for (int64_t k = 0; k < A.nnz(); ++k) T.rp[A.ci[k] + 1]++;
-  for (int64_t i = 0; i < T.nrows; ++i) T.rp[i + 1] += T.rp[i];
   T.ci.resize(A.nnz());
   T.v.resize(A.nnz());
-  std::vector<int64_t> pos(T.rp.begin(), T.rp.end() - 1);
-  for (int64_t i = 0; i < A.nrows; ++i)
-    for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-      int64_t p = pos[A.ci[k]]++;
-      T.ci[p] = int32_t(i);
-      T.v[p] = A.v[k];
+  // row ranges of A on nt host threads, each with its own column counts (so
+  // at most 256 MiB of counts); a thread's entries of column c go after those
+  // of the threads before it, so every row of T stays in ascending order
+  unsigned hw = std::thread::hardware_concurrency();
+  int64_t nt = std::max<int64_t>(1, std::min<int64_t>(hw ? hw : 1, 32));
+  nt = std::min<int64_t>(nt, std::max<int64_t>(1, (int64_t(1) << 25) / std::max<int64_t>(A.ncols, 1)));
+  if (A.nnz() < (int64_t(1) << 20)) nt = 1;
+  std::vector<std::vector<int64_t>> pos(nt, std::vector<int64_t>(A.ncols, 0));
+  auto range = [&](int64_t t, int64_t& b, int64_t& e) {
+    b = A.nrows * t / nt;
+    e = A.nrows * (t + 1) / nt;
+  };
+  parallel_for(nt, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      int64_t b, e;
+      range(t, b, e);
+      for (int64_t k = A.rp[b]; k < A.rp[e]; ++k) pos[t][A.ci[k]]++;
     }
+  }, 2);
+  int64_t off = 0;
+  for (int64_t c = 0; c < A.ncols; ++c) {
+    T.rp[c] = off;
+    for (int64_t t = 0; t < nt; ++t) {
+      const int64_t n = pos[t][c];
+      pos[t][c] = off;
+      off += n;
+    }
+  }
+  T.rp[A.ncols] = off;
+  parallel_for(nt, [&](int64_t t0, int64_t t1) {
+    for (int64_t t = t0; t < t1; ++t) {
+      int64_t b, e;
+      range(t, b, e);
+      std::vector<int64_t>& p = pos[t];
+      for (int64_t i = b; i < e; ++i)
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+          const int64_t q = p[A.ci[k]]++;
+          T.ci[q] = int32_t(i);
+          T.v[q] = A.v[k];
+        }
+    }
+  }, 2);
   return T;
+}
+
+void spgemm_row(const HCsr& A, const HCsr& B, int64_t i, SpgemmWork& w, std::vector<int32_t>& oc,
+                std::vector<double>& ov) {
+  if (w.acc.size() != size_t(B.ncols)) {
+    w.acc.assign(B.ncols, 0.0);
+    w.mark.assign(B.ncols, -1);
+  }
+  w.cols.clear();
+  for (int64_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
+    const int32_t k = A.ci[ka];
+    const double a = A.v[ka];
+    for (int64_t kb = B.rp[k]; kb < B.rp[k + 1]; ++kb) {
+      const int32_t j = B.ci[kb];
+      if (w.mark[j] != i) {
+        w.mark[j] = i;
+        w.acc[j] = 0.0;
+        w.cols.push_back(j);
+      }
+      w.acc[j] += a * B.v[kb];
+    }
+  }
+  std::sort(w.cols.begin(), w.cols.end());
+  for (int32_t j : w.cols) {
+    if (w.acc[j] != 0.0) {
+      oc.push_back(j);
+      ov.push_back(w.acc[j]);
+    }
+  }
 }
 
 HCsr spgemm(const HCsr& A, const HCsr& B) {
@@ -121,36 +183,13 @@ HCsr spgemm(const HCsr& A, const HCsr& B) {
   std::vector<std::vector<double>> cv(nchunk);
   std::vector<int64_t> rowlen(n, 0);
   parallel_for(nchunk, [&](int64_t cb, int64_t ce) {
-    std::vector<double> acc(B.ncols, 0.0);
-    std::vector<int64_t> mark(B.ncols, -1);
-    std::vector<int32_t> cols;
+    SpgemmWork w;
     for (int64_t ch = cb; ch < ce; ++ch) {
       int64_t r0 = n * ch / nchunk, r1 = n * (ch + 1) / nchunk;
       for (int64_t i = r0; i < r1; ++i) {
-        cols.clear();
-        for (int64_t ka = A.rp[i]; ka < A.rp[i + 1]; ++ka) {
-          const int32_t k = A.ci[ka];
-          const double a = A.v[ka];
-          for (int64_t kb = B.rp[k]; kb < B.rp[k + 1]; ++kb) {
-            const int32_t j = B.ci[kb];
-            if (mark[j] != i) {
-              mark[j] = i;
-              acc[j] = 0.0;
-              cols.push_back(j);
-            }
-            acc[j] += a * B.v[kb];
-          }
-        }
-        std::sort(cols.begin(), cols.end());
-        int64_t len = 0;
-        for (int32_t j : cols) {
-          if (acc[j] != 0.0) {
-            cc[ch].push_back(j);
-            cv[ch].push_back(acc[j]);
-            ++len;
-          }
-        }
-        rowlen[i] = len;
+        const size_t before = cc[ch].size();
+        spgemm_row(A, B, i, w, cc[ch], cv[ch]);
+        rowlen[i] = int64_t(cc[ch].size() - before);
       }
     }
   }, 2);

@@ -54,6 +54,16 @@ HCsr transpose(const HCsr& A);
 // C = A B; entry (i, j) summed over the stored entries of row i of A in
 // storage order, each contributing A_ik * B_kj in the storage order of row k.
 HCsr spgemm(const HCsr& A, const HCsr& B);
+// Work arrays of one host thread for spgemm_row (sized on first use).
+struct SpgemmWork {
+  std::vector<double> acc;
+  std::vector<int64_t> mark;
+  std::vector<int32_t> cols;
+};
+// Row i of A B exactly as spgemm forms it (columns ascending, exact zeros
+// dropped), appended to oc, ov.
+void spgemm_row(const HCsr& A, const HCsr& B, int64_t i, SpgemmWork& w, std::vector<int32_t>& oc,
+                std::vector<double>& ov);
 // C = A + alpha B (union pattern, exact zeros dropped).
 HCsr add(const HCsr& A, const HCsr& B, double alpha);
 HCsr sub_block(const HCsr& A, int64_t r0, int64_t r1, int64_t c0, int64_t c1);

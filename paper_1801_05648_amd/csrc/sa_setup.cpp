@@ -361,10 +361,10 @@ std::string sa_finalize(SaHierarchy& H) {
   return "";
 }
 
-std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, int k0, const SaParams& prm,
-                     SaHierarchy& H) {
+std::string sa_setup(HCsr A, int block, const std::vector<double>& B0, int k0, const SaParams& prm,
+                     SaHierarchy& H, const SpgemmFn& mul) {
+  auto product = [&](const HCsr& X, const HCsr& Y) { return mul ? mul(X, Y) : spgemm(X, Y); };
   H.levels.clear();
-  HCsr A = A0;
   std::vector<double> B = B0;
   int b = block, k = k0;
   double eps = prm.eps0;
@@ -402,7 +402,7 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
       if (dF[i] == 0.0) return "zero diagonal in the filtered AMG matrix";
       scale[i] = lev.omega / dF[i];
     }
-    HCsr T = spgemm(AF, Pt);
+    HCsr T = product(AF, Pt);
     scale_rows(T, scale);
     HCsr P = add(Pt, T, -1.0);
     drop_zeros(P);
@@ -412,8 +412,8 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
       break;
     }
     HCsr R = transpose(P);
-    HCsr AP = spgemm(Al, P);
-    HCsr Ac = spgemm(R, AP);
+    HCsr AP = product(Al, P);
+    HCsr Ac = product(R, AP);
     drop_zeros(Ac);
     // a coarse dof with an empty row (rank-deficient aggregate column) gets 1
     bool any_empty = false;
@@ -433,6 +433,7 @@ std::string sa_setup(const HCsr& A0, int block, const std::vector<double>& B0, i
     }
     lev.P = std::move(P);
     lev.R = std::move(R);
+    lev.AP = std::move(AP);
     lev.agg = std::move(agg);
     A = std::move(Ac);
     B = std::move(Bc);

@@ -1,6 +1,8 @@
-// Smoothed-aggregation AMG setup on the host (preconditioner build only).
+// Smoothed-aggregation AMG setup (preconditioner build only): the steps on
+// the host, the sparse products wherever the caller runs them.
 #pragma once
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -16,6 +18,7 @@ struct SaParams {
 
 struct SaLevel {
   HCsr A, P, R;
+  HCsr AP;  // A P of the Galerkin product, kept for the level sweeps (may be released)
   std::vector<double> dinv;
   double omega = 0.0;
   int block = 1;
@@ -29,8 +32,11 @@ struct SaHierarchy {
 
 // Build the hierarchy of A with node block size `block` and near-nullspace B
 // (row-major n x k).  Returns an empty string on success, else a message.
-std::string sa_setup(const HCsr& A, int block, const std::vector<double>& B, int k, const SaParams& prm,
-                     SaHierarchy& H);
+// The sparse products C = A B of the setup; a replacement of the host
+// product must return spgemm's result bit for bit (empty: spgemm).
+using SpgemmFn = std::function<HCsr(const HCsr&, const HCsr&)>;
+std::string sa_setup(HCsr A, int block, const std::vector<double>& B, int k, const SaParams& prm,
+                     SaHierarchy& H, const SpgemmFn& mul = {});
 
 // Dense inverse (LU with partial pivoting, smallest row index on ties) of the
 // n x n row-major matrix a; returns false on a zero pivot.
