@@ -123,6 +123,8 @@ struct Staging {
   static constexpr size_t kChunk = size_t(32) << 20;
   std::mutex mu;
   char* buf[2] = {nullptr, nullptr};
+  // bytes and wall time of the copies through the buffers (for the log)
+  std::atomic<int64_t> up_bytes{0}, up_ns{0}, down_bytes{0}, down_ns{0};
 };
 
 inline Staging& staging() {
@@ -144,6 +146,7 @@ void staged_upload(void* dst, size_t bytes, hipStream_t s, Fill&& fill) {
   }
   Staging& st = staging();
   std::lock_guard<std::mutex> lock(st.mu);
+  const auto t0 = std::chrono::steady_clock::now();
   for (auto& b : st.buf)
     if (!b) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b), Staging::kChunk, hipHostMallocPortable));
   struct Events {  // both buffers idle again on any exit
@@ -171,6 +174,8 @@ void staged_upload(void* dst, size_t bytes, hipStream_t s, Fill&& fill) {
     busy[b] = true;
   }
   HIP_TRY(hipStreamSynchronize(s));
+  st.up_bytes += int64_t(bytes);
+  st.up_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
 }
 
 // count elements of src to dst (same type)
@@ -209,6 +214,7 @@ void d2h(U* dst, const void* src, size_t count, hipStream_t s) {
   }
   Staging& st = staging();
   std::lock_guard<std::mutex> lock(st.mu);
+  const auto t0 = std::chrono::steady_clock::now();
   for (auto& b : st.buf)
     if (!b) HIP_TRY(hipHostMalloc(reinterpret_cast<void**>(&b), Staging::kChunk, hipHostMallocPortable));
   auto drain = [&](int b, size_t off, size_t n) {
@@ -246,6 +252,16 @@ void d2h(U* dst, const void* src, size_t count, hipStream_t s) {
   }
   HIP_TRY(hipEventSynchronize(ev.e[prev_b]));
   drain(prev_b, prev_off, prev_n);
+  st.down_bytes += int64_t(bytes);
+  st.down_ns += std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// Log line of the staged copies so far.
+void log_staging(const char* when) {
+  if (!log_on()) return;
+  const Staging& st = staging();
+  log_line("%s: staged copies %.2f GB up in %.1f ms, %.2f GB down in %.1f ms", when, st.up_bytes.load() / 1e9,
+           st.up_ns.load() / 1e6, st.down_bytes.load() / 1e9, st.down_ns.load() / 1e6);
 }
 
 template <typename T>
@@ -322,7 +338,9 @@ std::shared_ptr<DevBuf> upload_as(const std::vector<double>& v, hipStream_t s = 
 // C = A B on the device, bitwise equal to the host product spgemm(A, B) (the
 // kernels form every row as the host does).  Rows with more than 4096
 // distinct columns are formed on the host.  Small products stay on the host.
-HCsr device_spgemm(const HCsr& A, const HCsr& B, hipStream_t s) {
+// With count_only the result holds only the row pointers (C.rp.back() is the
+// number of nonzeros) and nothing is written or copied back.
+HCsr device_spgemm(const HCsr& A, const HCsr& B, hipStream_t s, bool count_only = false) {
   if (A.ncols != B.nrows) throw Error(FSI_ERR_ARG, "sparse product of mismatched shapes");
   const int64_t m = A.nrows;
   if (m > INT32_MAX || A.nnz() + B.nnz() < (int64_t(1) << 16) || A.nnz() == 0 || B.nnz() == 0)
@@ -375,6 +393,7 @@ HCsr device_spgemm(const HCsr& A, const HCsr& B, hipStream_t s) {
   C.rp.assign(m + 1, 0);
   for (int64_t i = 0; i < m; ++i) C.rp[i + 1] = C.rp[i] + hc[i];
   const int64_t nnz = C.rp[m];
+  if (count_only) return C;
   auto crp = up(C.rp);
   DevBuf cci, cv;
   cci.alloc(sizeof(int32_t) * std::max<int64_t>(nnz, 1));
@@ -797,9 +816,8 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       // Above 2^18 entries of R A, or on coarser levels (where R A's rows are
       // long next to the level's own), the fused coarse rows outlast the
       // launch saved (measured on the 2D and 3D workloads).
-      const HCsr RA = device_spgemm(h.R, h.A, s);
-      if (l == 0 && RA.nnz() < kFuseRestrictNnz) {
-        d.RRA = upload_pair<T>(h.R, RA);
+      if (l == 0 && device_spgemm(h.R, h.A, s, true).rp.back() < kFuseRestrictNnz) {
+        d.RRA = upload_pair<T>(h.R, device_spgemm(h.R, h.A, s));
         d.gres = d.RRA.group >= 32 ? 64 : 16;
       } else {
         d.R0 = upload<T>(h.R, s);
@@ -828,20 +846,26 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       // setup kept it)
       const HCsr APc = h.AP.nrows ? HCsr{} : device_spgemm(h.A, h.P, s);
       const HCsr& AP = h.AP.nrows ? h.AP : APc;
-      HCsr RA = device_spgemm(h.R, h.A, s);
       const std::vector<double> dv = level_dinv(h.dinv);
-      std::vector<double> wd(dv.size());
-      for (size_t i = 0; i < wd.size(); ++i) wd[i] = h.omega * dv[i];
-      scale_cols(RA, wd);
-      HCsr Q = add(h.R, RA, -1.0);
       HCsr AD = h.A;
       scale_cols(AD, dv);
-      // Restricting through Q fuses the restriction into the down-sweep but
-      // reads nnz(Q) instead of nnz(R) entries; where the difference costs
-      // more than a launch, restrict the residual with R in a launch of its own.
-      const bool split_worthy = Q.nnz() - h.R.nnz() >= kSplitNnz;
+      // Restricting through Q = R (I - omega A D^{-1}) fuses the restriction
+      // into the down-sweep but reads Q's entries (about R A's pattern)
+      // instead of R's; where R A has kSplitNnz more nonzeros than R (counted
+      // on the device), restrict the residual with R in a launch of its own
+      // and leave Q unformed (unless the learned smoother's sweep needs it).
+      const int64_t ra_nnz = device_spgemm(h.R, h.A, s, true).rp.back();
+      const bool split_worthy = ra_nnz - h.R.nnz() >= kSplitNnz;
       d.split = !(l == 0 && keep_a0) && split_worthy;
       d.split_plain = l == 0 && keep_a0 && split_worthy;  // R is uploaded for that level below
+      HCsr Q;
+      if (!d.split) {
+        HCsr RA = device_spgemm(h.R, h.A, s);
+        std::vector<double> wd(dv.size());
+        for (size_t i = 0; i < wd.size(); ++i) wd[i] = h.omega * dv[i];
+        scale_cols(RA, wd);
+        Q = add(h.R, RA, -1.0);
+      }
       // Large levels of a vector problem (group = components per node): where
       // the rows of a node share their columns in all four matrices (at most
       // 5% zero fill), store them in groups of `group` rows.  Decided on the
@@ -2966,6 +2990,7 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     DCsr<double> dAh = upload_segments<double>(Ah, bounds, groups, 4, ctx->stream);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
     t_up.done();
+    log_staging("setup_blocks");
     // commit
     fsi_ctx& c = *ctx;
     c.d = d;
@@ -3059,6 +3084,7 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
     }
     c.have_precond = true;
     t_build.done(o.reuse ? " (hierarchies reused)" : "");
+    log_staging("build_precond");
     return FSI_OK;
   });
 }

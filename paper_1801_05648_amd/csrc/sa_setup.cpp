@@ -15,7 +15,6 @@
 #include <cmath>
 #include <cstdio>
 #include <thread>
-#include <unordered_map>
 
 namespace fsi {
 
@@ -66,43 +65,67 @@ Strength strength(const HCsr& A, int b, double eps) {
   const int64_t nn = A.nrows / b;
   Strength S;
   S.sdiag.assign(nn, 0.0);
-  std::vector<std::vector<std::pair<int32_t, double>>> rows(nn);
+  // s_II first (every node's test needs the diagonals of its neighbours)
   parallel_for(nn, [&](int64_t I0, int64_t I1) {
-    std::unordered_map<int32_t, size_t> pos;
     for (int64_t I = I0; I < I1; ++I) {
-      auto& r = rows[I];
-      pos.clear();
+      double sII = 0.0;
       for (int c = 0; c < b; ++c) {
         const int64_t i = I * b + c;
-        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-          const int32_t J = A.ci[k] / b;
-          auto it = pos.find(J);
-          if (it == pos.end()) {
-            pos.emplace(J, r.size());
-            r.emplace_back(J, A.v[k] * A.v[k]);
-          } else {
-            r[it->second].second += A.v[k] * A.v[k];
-          }
-        }
+        for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k)
+          if (A.ci[k] / b == I) sII += A.v[k] * A.v[k];
       }
-      std::sort(r.begin(), r.end(), [](const auto& a, const auto& c) { return a.first < c.first; });
-      for (auto& e : r)
-        if (e.first == I) S.sdiag[I] = e.second;
+      S.sdiag[I] = sII;
     }
   });
+  // then each node's s_IJ in a dense per-thread accumulator (first-touch
+  // list, sorted by J), the strong ones kept; chunks of nodes on the host
+  // threads, concatenated in node order
   const double e2 = eps * eps, e4 = e2 * e2;
-  S.ptr.assign(nn + 1, 0);
-  for (int64_t I = 0; I < nn; ++I) {
-    for (auto& e : rows[I]) {
-      const int32_t J = e.first;
-      const double s = e.second;
-      if (J == I || !(s > 0.0)) continue;
-      if (s * s >= e4 * (S.sdiag[I] * S.sdiag[J])) {
-        S.nbr.push_back(J);
-        S.sval.push_back(s);
+  const int64_t nchunk = std::max<int64_t>(1, std::min<int64_t>(256, nn / 256));
+  std::vector<std::vector<int32_t>> cn(nchunk);
+  std::vector<std::vector<double>> cs(nchunk);
+  std::vector<int64_t> len(nn, 0);
+  parallel_for(nchunk, [&](int64_t cb, int64_t ce) {
+    std::vector<double> acc(nn, 0.0);
+    std::vector<int64_t> mark(nn, -1);
+    std::vector<int32_t> js;
+    for (int64_t ch = cb; ch < ce; ++ch) {
+      const int64_t I0 = nn * ch / nchunk, I1 = nn * (ch + 1) / nchunk;
+      for (int64_t I = I0; I < I1; ++I) {
+        js.clear();
+        for (int c = 0; c < b; ++c) {
+          const int64_t i = I * b + c;
+          for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            const int32_t J = A.ci[k] / b;
+            if (mark[J] != I) {
+              mark[J] = I;
+              acc[J] = 0.0;
+              js.push_back(J);
+            }
+            acc[J] += A.v[k] * A.v[k];
+          }
+        }
+        std::sort(js.begin(), js.end());
+        const size_t before = cn[ch].size();
+        for (int32_t J : js) {
+          const double sIJ = acc[J];
+          if (J == I || !(sIJ > 0.0)) continue;
+          if (sIJ * sIJ >= e4 * (S.sdiag[I] * S.sdiag[J])) {
+            cn[ch].push_back(J);
+            cs[ch].push_back(sIJ);
+          }
+        }
+        len[I] = int64_t(cn[ch].size() - before);
       }
     }
-    S.ptr[I + 1] = int64_t(S.nbr.size());
+  }, 2);
+  S.ptr.assign(nn + 1, 0);
+  for (int64_t I = 0; I < nn; ++I) S.ptr[I + 1] = S.ptr[I] + len[I];
+  S.nbr.reserve(S.ptr[nn]);
+  S.sval.reserve(S.ptr[nn]);
+  for (int64_t ch = 0; ch < nchunk; ++ch) {
+    S.nbr.insert(S.nbr.end(), cn[ch].begin(), cn[ch].end());
+    S.sval.insert(S.sval.end(), cs[ch].begin(), cs[ch].end());
   }
   return S;
 }

@@ -360,9 +360,10 @@ def _cycle_bytes(h, g, allow_groups=True):
         A, P, R = lev.A.tocsr(), lev.P.tocsr(), lev.R.tocsr()
         n, nc = A.shape[0], P.shape[1]
         absA, absR = abs(A), abs(R)
-        Q = (absR + absR @ absA).tocsr()
+        RA = (absR @ absA).tocsr()
+        Q = (absR + RA).tocsr()
         AP = (absA @ abs(P)).tocsr()
-        split = Q.nnz - R.nnz >= 2 ** 21
+        split = RA.nnz - R.nnz >= 2 ** 21  # R A's nonzeros decide whether Q is formed
         Rq = R if split else Q
         mats = [A, Rq, P, AP]
         grouped = allow_groups and A.nnz >= 2 ** 21 and all(M.shape[0] % g == 0 for M in mats)
