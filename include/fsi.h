@@ -153,9 +153,9 @@ typedef struct {
                           the other options (precision, smoothers, fluid
                           solve); strength0, max_coarse, max_levels and schur
                           must equal the previous build's.  FSI_ERR_STATE
-                          without such a build since fsi_setup_blocks.  The
-                          quasi-Newton reuse of Section 6 keeps the whole
-                          preconditioner instead (no call at all)             */
+                          without such a build since fsi_setup_blocks.  After
+                          fsi_update_values the kept hierarchies are those of
+                          the earlier values                                  */
   int32_t x_approx;    /* the fluid operator inverted in place of the Schur
                           complement X = F - C~_fs S^{-1} C_sf of Section 4.1
                           (C~_fs = C_fs - C_fm M^{-1} C_ms): FSI_X_F (default,
@@ -233,6 +233,20 @@ const char* fsi_last_error(const fsi_ctx* ctx);
  * invalidates the preconditioner. */
 fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* layout, const fsi_csr blk[FSI_NBLK],
                             int mem);
+
+/* New values for the eight blocks of the system in the context, with the
+ * same sparsity patterns (equal row pointers and column indices, checked) and
+ * the same structural identities (checked as by fsi_setup_blocks): the device
+ * copy of A_h is rewritten in place, in its stored layout.  The preconditioner
+ * (if built) is kept as it was built from the earlier values, so fsi_solve
+ * then runs FGMRES on the new A_h with the earlier P^{-1}: the reuse of a
+ * quasi-Newton step (the scheme of Section 6 reassembles the Jacobian only
+ * when the last Newton step cut the residual's max-norm by less than a factor
+ * of ten; a caller can keep the preconditioner by the same test).
+ * fsi_build_precond rebuilds it from the new values; with `reuse` it keeps
+ * the SA hierarchies of the earlier values and takes everything else from the
+ * new ones.  On error nothing changes. */
+fsi_status fsi_update_values(fsi_ctx* ctx, const fsi_csr blk[FSI_NBLK]);
 
 /* Build the preconditioner of Section 4: Sigma_s, the pressure Schur
  * approximation and the five SA-AMG hierarchies (host setup, then upload).

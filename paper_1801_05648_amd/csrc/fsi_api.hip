@@ -471,11 +471,12 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
 // bytes(): the matrix as stored (values, column lists, row or group pointers).
 // The plain arrays hold the rows of the ungrouped segments only (the rows of a
 // grouped segment are empty there); nnz stays the matrix's own count.
-template <typename T>
-DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, hipStream_t s) {
+// The row grouping of each segment (group[q], or 1 where the segment does
+// not split into whole groups or grouping costs more than 5% zero fill) and
+// the plain arrays: the rows of the ungrouped segments, grouped rows empty.
+HCsr segment_plan(const HCsr& A, const int64_t* bounds, const int* group, int nseg, int* grs) {
   if (nseg < 1 || nseg > 4 || bounds[0] != 0 || bounds[nseg] != A.nrows)
     throw Error(FSI_ERR_ARG, "row segments must cover the matrix in at most four parts");
-  int grs[4];
   for (int q = 0; q < nseg; ++q) {
     const int64_t r0 = bounds[q], r1 = bounds[q + 1];
     const int64_t units = r1 - r0, nz = r1 > r0 ? A.rp[r1] - A.rp[r0] : 0;
@@ -490,14 +491,43 @@ DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, 
     while (q + 1 < nseg && i >= bounds[q + 1]) ++q;
     return grs[q] == 1;
   };
-  DCsr<T> D = upload<T>(build_rows(A.nrows, A.ncols,
-                                   [&](int64_t i) { return plain_row(i) ? A.rp[i + 1] - A.rp[i] : int64_t(0); },
-                                   [&](int64_t i, int32_t* oc, double* ov) {
-                                     if (!plain_row(i)) return;
-                                     std::copy(A.ci.begin() + A.rp[i], A.ci.begin() + A.rp[i + 1], oc);
-                                     std::copy(A.v.begin() + A.rp[i], A.v.begin() + A.rp[i + 1], ov);
-                                   }),
-                        s);
+  return build_rows(A.nrows, A.ncols,
+                    [&](int64_t i) { return plain_row(i) ? A.rp[i + 1] - A.rp[i] : int64_t(0); },
+                    [&](int64_t i, int32_t* oc, double* ov) {
+                      if (!plain_row(i)) return;
+                      std::copy(A.ci.begin() + A.rp[i], A.ci.begin() + A.rp[i + 1], oc);
+                      std::copy(A.v.begin() + A.rp[i], A.v.begin() + A.rp[i + 1], ov);
+                    });
+}
+
+// New values for a matrix uploaded by upload_segments from a matrix of the
+// same sparsity pattern: written in place into the same device arrays (the
+// layout, and any captured graph that reads them, stay valid).
+template <typename T>
+void refresh_segments(const DCsr<T>& D, const HCsr& A, const int64_t* bounds, const int* group, int nseg,
+                      hipStream_t s) {
+  int grs[4];
+  const HCsr plain = segment_plan(A, bounds, group, nseg, grs);
+  auto fits = [](const std::shared_ptr<DevBuf>& b, size_t n) { return n == 0 || (b && b->bytes == sizeof(T) * n); };
+  if (!fits(D.val, size_t(plain.nnz()))) throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
+  if (plain.nnz()) h2d_as<T>(D.val->p, plain.v.data(), size_t(plain.nnz()), s);
+  for (int q = 0, k = 0; q < nseg; ++q) {
+    if (bounds[q + 1] <= bounds[q]) continue;
+    const int kk = k++;
+    if ((D.seg.grp[kk] > 1) != (grs[q] > 1) || (grs[q] > 1 && D.seg.grp[kk] != grs[q]))
+      throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
+    if (grs[q] == 1) continue;
+    std::vector<double> gv;
+    const HCsr Gm = group_rows(A, bounds[q], bounds[q + 1], grs[q], gv);
+    if (!fits(D.grp_val[kk], gv.size())) throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
+    h2d_as<T>(D.grp_val[kk]->p, gv.data(), gv.size(), s);
+  }
+}
+
+template <typename T>
+DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, hipStream_t s) {
+  int grs[4];
+  DCsr<T> D = upload<T>(segment_plan(A, bounds, group, nseg, grs), s);
   D.nnz = A.nnz();
   D.deep = true;
   RowSegments sg{};
@@ -2886,6 +2916,85 @@ const char* fsi_last_error(const fsi_ctx* ctx) {
   return ctx ? ctx->err.c_str() : g_create_err.c_str();
 }
 
+// The structural identities the preconditioner relies on (Sections 4.3,
+// 4.4 and the mesh model): S_uv = -dt_theta S_uu within 1e-12 relative, an
+// empty pressure block of F, and M = L (x) I_d.  Throws FSI_ERR_STRUCT.
+void check_structure(const HCsr* H, int d, int64_t nvs, int64_t nvf, int64_t nf, double dt_theta) {
+  HCsr Suv = sub_block(H[FSI_S], nvs, 2 * nvs, 0, nvs);
+  HCsr Suu = sub_block(H[FSI_S], nvs, 2 * nvs, nvs, 2 * nvs);
+  double mx = 0.0;
+  for (double v : Suu.v) mx = std::max(mx, std::fabs(v));
+  HCsr diff = add(Suv, Suu, dt_theta);
+  double dmax = 0.0;
+  for (double v : diff.v) dmax = std::max(dmax, std::fabs(v));
+  if (!(dmax <= 1e-12 * dt_theta * mx))
+    throw Error(FSI_ERR_STRUCT, "S_uv != -dt_theta S_uu (equal-order solid mass identity)");
+  HCsr Fpp = sub_block(H[FSI_F], nvf, nf, nvf, nf);
+  if (Fpp.nnz() != 0) throw Error(FSI_ERR_STRUCT, "pressure-pressure block of F must be empty");
+  const HCsr& M = H[FSI_M];
+  std::atomic<bool> kron_ok{true};
+  parallel_for(M.nrows, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e && kron_ok.load(std::memory_order_relaxed); ++i) {
+      const int64_t I = i / d, ci = i % d;
+      const int64_t r0 = I * d;
+      bool ok = M.rp[i + 1] - M.rp[i] == M.rp[r0 + 1] - M.rp[r0];
+      for (int64_t k = M.rp[i], k0 = M.rp[r0]; ok && k < M.rp[i + 1]; ++k, ++k0)
+        ok = M.ci[k] % d == ci && M.ci[k] / d == M.ci[k0] / d && M.v[k] == M.v[k0];
+      if (!ok) kron_ok.store(false);
+    }
+  });
+  if (!kron_ok.load()) throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
+}
+
+// Block rows and columns of the eight stored blocks (mesh 0, solid 1, fluid 2).
+constexpr int kBlkRow[FSI_NBLK] = {0, 0, 1, 1, 1, 2, 2, 2};
+constexpr int kBlkCol[FSI_NBLK] = {0, 1, 0, 1, 2, 0, 1, 2};
+
+// Monolithic A_h with global columns (row i of block row r: the blocks of
+// that row in column order, their columns shifted; built on the host threads).
+HCsr assemble_ah(const HCsr* H, int64_t n_m, int64_t n_s, int64_t N) {
+  const int64_t off[3] = {0, n_m, n_m + n_s};
+  auto block_row = [&](int64_t gi, int& r, int64_t& i) {
+    r = gi < off[1] ? 0 : gi < off[2] ? 1 : 2;
+    i = gi - off[r];
+  };
+  return build_rows(
+      N, N,
+      [&](int64_t gi) {
+        int r;
+        int64_t i, n = 0;
+        block_row(gi, r, i);
+        for (int b = 0; b < FSI_NBLK; ++b)
+          if (kBlkRow[b] == r) n += H[b].rp[i + 1] - H[b].rp[i];
+        return n;
+      },
+      [&](int64_t gi, int32_t* oc, double* ov) {
+        int r;
+        int64_t i;
+        block_row(gi, r, i);
+        for (int b = 0; b < FSI_NBLK; ++b) {
+          if (kBlkRow[b] != r) continue;
+          const HCsr& A = H[b];
+          for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
+            *oc++ = int32_t(A.ci[k] + off[kBlkCol[b]]);
+            *ov++ = A.v[k];
+          }
+        }
+      });
+}
+
+// The row segments of the stored A_h: mesh, solid, fluid-velocity and
+// pressure rows; the d velocity rows of a fluid node share their columns (the
+// stress couples the components) and are stored as groups of d rows, one
+// column index per d values.  Solid rows differ in about half their columns:
+// plain rows.
+void ah_segments(int64_t n_m, int64_t n_s, int64_t n_vf, int64_t N, int d, int64_t* bounds, int* groups) {
+  const int64_t b[5] = {0, n_m, n_m + n_s, n_m + n_s + n_vf, N};
+  const int g[4] = {1, 1, d, 1};
+  std::copy(b, b + 5, bounds);
+  std::copy(g, g + 4, groups);
+}
+
 fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk[FSI_NBLK], int mem) {
   return guarded(ctx, [&]() -> fsi_status {
     if (!L || !blk) throw Error(FSI_ERR_ARG, "layout or blocks is NULL");
@@ -2920,72 +3029,12 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     // host copies (the context is only modified once everything validated)
     HCsr H[FSI_NBLK];
     for (int b = 0; b < FSI_NBLK; ++b) H[b] = csr_copy(blk[b].nrows, blk[b].ncols, blk[b].rowptr, blk[b].col, blk[b].val);
-    // structural identities
     const int64_t nvs = L->n_vs, nvf = L->n_vf;
-    {
-      HCsr Suv = sub_block(H[FSI_S], nvs, 2 * nvs, 0, nvs);
-      HCsr Suu = sub_block(H[FSI_S], nvs, 2 * nvs, nvs, 2 * nvs);
-      double mx = 0.0;
-      for (double v : Suu.v) mx = std::max(mx, std::fabs(v));
-      HCsr diff = add(Suv, Suu, L->dt_theta);
-      double dmax = 0.0;
-      for (double v : diff.v) dmax = std::max(dmax, std::fabs(v));
-      if (!(dmax <= 1e-12 * L->dt_theta * mx))
-        throw Error(FSI_ERR_STRUCT, "S_uv != -dt_theta S_uu (equal-order solid mass identity)");
-      HCsr Fpp = sub_block(H[FSI_F], nvf, L->n_f, nvf, L->n_f);
-      if (Fpp.nnz() != 0) throw Error(FSI_ERR_STRUCT, "pressure-pressure block of F must be empty");
-      // M = L (x) I_d
-      const HCsr& M = H[FSI_M];
-      std::atomic<bool> kron_ok{true};
-      parallel_for(M.nrows, [&](int64_t b, int64_t e) {
-        for (int64_t i = b; i < e && kron_ok.load(std::memory_order_relaxed); ++i) {
-          const int64_t I = i / d, ci = i % d;
-          const int64_t r0 = I * d;
-          bool ok = M.rp[i + 1] - M.rp[i] == M.rp[r0 + 1] - M.rp[r0];
-          for (int64_t k = M.rp[i], k0 = M.rp[r0]; ok && k < M.rp[i + 1]; ++k, ++k0)
-            ok = M.ci[k] % d == ci && M.ci[k] / d == M.ci[k0] / d && M.v[k] == M.v[k0];
-          if (!ok) kron_ok.store(false);
-        }
-      });
-      if (!kron_ok.load()) throw Error(FSI_ERR_STRUCT, "mesh block is not L (x) I_d");
-    }
-    // monolithic A_h with global columns for the outer product
-    // (row i of block row r: the blocks of that row in column order, their
-    // columns shifted to global ones; built on the host threads)
-    const int64_t off[3] = {0, L->n_m, L->n_m + L->n_s};
-    auto block_row = [&](int64_t gi, int& r, int64_t& i) {
-      r = gi < off[1] ? 0 : gi < off[2] ? 1 : 2;
-      i = gi - off[r];
-    };
-    HCsr Ah = build_rows(
-        N, N,
-        [&](int64_t gi) {
-          int r;
-          int64_t i, n = 0;
-          block_row(gi, r, i);
-          for (int b = 0; b < FSI_NBLK; ++b)
-            if (bi[b] == r) n += H[b].rp[i + 1] - H[b].rp[i];
-          return n;
-        },
-        [&](int64_t gi, int32_t* oc, double* ov) {
-          int r;
-          int64_t i;
-          block_row(gi, r, i);
-          for (int b = 0; b < FSI_NBLK; ++b) {
-            if (bi[b] != r) continue;
-            const HCsr& A = H[b];
-            for (int64_t k = A.rp[i]; k < A.rp[i + 1]; ++k) {
-              *oc++ = int32_t(A.ci[k] + off[bj[b]]);
-              *ov++ = A.v[k];
-            }
-          }
-        });
-    // mesh, solid, fluid-velocity and pressure rows as four segments; the d
-    // velocity rows of a fluid node share their columns (the stress couples
-    // the components): stored as groups of d rows, one column index per d
-    // values.  Solid rows differ in about half their columns: plain rows.
-    const int64_t bounds[5] = {0, L->n_m, L->n_m + L->n_s, L->n_m + L->n_s + L->n_vf, N};
-    const int groups[4] = {1, 1, d, 1};
+    check_structure(H, d, nvs, nvf, L->n_f, L->dt_theta);
+    HCsr Ah = assemble_ah(H, L->n_m, L->n_s, N);
+    int64_t bounds[5];
+    int groups[4];
+    ah_segments(L->n_m, L->n_s, nvf, N, d, bounds, groups);
     PhaseTimer t_up("setup_blocks: A_h segments upload");
     DCsr<double> dAh = upload_segments<double>(Ah, bounds, groups, 4, ctx->stream);
     HIP_TRY(hipStreamSynchronize(ctx->stream));
@@ -3011,6 +3060,45 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     c.p64.reset();
     c.p32.reset();
     c.m_alloc = -1;
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_update_values(fsi_ctx* ctx, const fsi_csr blk[FSI_NBLK]) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
+    if (!blk) throw Error(FSI_ERR_ARG, "blocks is NULL");
+    static const char* names[FSI_NBLK] = {"M", "C_ms", "C_sm", "S", "C_sf", "C_fm", "C_fs", "F"};
+    for (int b = 0; b < FSI_NBLK; ++b) {
+      const fsi_csr& A = blk[b];
+      const HCsr& O = c.blk[b];
+      if (A.nrows != O.nrows || A.ncols != O.ncols || A.nnz != O.nnz() || !A.rowptr || (A.nnz && (!A.col || !A.val)))
+        throw Error(FSI_ERR_ARG, std::string("block ") + names[b] + ": not the stored sparsity pattern");
+      std::atomic<bool> same{true};
+      parallel_for(A.nrows, [&](int64_t i0, int64_t i1) {
+        bool ok = std::memcmp(A.rowptr + i0, O.rp.data() + i0, sizeof(int64_t) * size_t(i1 - i0 + 1)) == 0;
+        if (ok && O.rp[i1] > O.rp[i0])
+          ok = std::memcmp(A.col + O.rp[i0], O.ci.data() + O.rp[i0], sizeof(int32_t) * size_t(O.rp[i1] - O.rp[i0])) == 0;
+        if (ok)
+          for (int64_t k = O.rp[i0]; k < O.rp[i1] && ok; ++k) ok = std::isfinite(A.val[k]);
+        if (!ok) same.store(false);
+      });
+      if (!same.load())
+        throw Error(FSI_ERR_ARG, std::string("block ") + names[b] + ": not the stored sparsity pattern, or non-finite values");
+    }
+    HCsr H[FSI_NBLK];
+    for (int b = 0; b < FSI_NBLK; ++b) H[b] = csr_copy(blk[b].nrows, blk[b].ncols, blk[b].rowptr, blk[b].col, blk[b].val);
+    check_structure(H, c.d, c.n_vs, c.n_vf, c.n_f, c.dt_theta);
+    const HCsr Ah = assemble_ah(H, c.n_m, c.n_s, c.N);
+    int64_t bounds[5];
+    int groups[4];
+    ah_segments(c.n_m, c.n_s, c.n_vf, c.N, c.d, bounds, groups);
+    PhaseTimer t_up("update_values: A_h values refresh");
+    refresh_segments<double>(c.Ah, Ah, bounds, groups, 4, c.stream);
+    HIP_TRY(hipStreamSynchronize(c.stream));
+    t_up.done();
+    for (int b = 0; b < FSI_NBLK; ++b) c.blk[b] = std::move(H[b]);
     return FSI_OK;
   });
 }

@@ -113,6 +113,7 @@ def _declare(lib):
         "fsi_destroy": ([P], i32),
         "fsi_last_error": ([P], ctypes.c_char_p),
         "fsi_setup_blocks": ([P, ctypes.POINTER(CLayout), ctypes.POINTER(CCsr), i32], i32),
+        "fsi_update_values": ([P, ctypes.POINTER(CCsr)], i32),
         "fsi_build_precond": ([P, ctypes.POINTER(CPrecondOpts)], i32),
         "fsi_solve": ([P, P, P, ctypes.POINTER(CSolveOpts), ctypes.POINTER(CSolveInfo)], i32),
         "fsi_spmv": ([P, P, P], i32),
@@ -160,7 +161,8 @@ def load():
 
 def exported_symbols():
     """Names of the C ABI entry points this binding declares."""
-    return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_build_precond",
+    return ["fsi_create", "fsi_destroy", "fsi_last_error", "fsi_setup_blocks", "fsi_update_values",
+            "fsi_build_precond",
             "fsi_solve", "fsi_spmv", "fsi_apply_precond", "fsi_vcycle", "fsi_set_hierarchy",
             "fsi_hierarchy_info", "fsi_vcycle_bytes", "fsi_spmv_bytes", "fsi_precond_bytes", "fsi_get_level", "fsi_get_aggregates",
             "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
@@ -234,6 +236,21 @@ class FsiSolver:
         self._check(self.lib.fsi_setup_blocks(self.ctx, ctypes.byref(lay), arr, 0))
         self.N = int(layout["n_m"] + layout["n_s"] + layout["n_f"])
         self.layout = dict(layout)
+
+    def update_values(self, blocks):
+        """fsi_update_values: new values of the same sparsity patterns; A_h is
+        rewritten in place, the preconditioner kept.  On failure nothing
+        changes."""
+        keep = []
+        arr = (CCsr * 8)()
+        for i, name in enumerate(BLOCKS):
+            b = blocks[name]
+            if isinstance(b, tuple):
+                nr, ncl, rp, ci, vv = b
+            else:
+                nr, ncl, rp, ci, vv = b.nrows, b.ncols, b.rowptr, b.col, b.val
+            arr[i] = _csr_struct(nr, ncl, rp, ci, vv, keep)
+        self._check(self.lib.fsi_update_values(self.ctx, arr))
 
     @staticmethod
     def layout_of(sysm):
