@@ -427,24 +427,124 @@ HCsr device_spgemm(const HCsr& A, const HCsr& B, hipStream_t s, bool count_only 
 }
 
 
+// Rows per group of a grouped level (the components of a node).
+template <class F>
+void with_rgroup(int g, F&& f) {
+  if (g == 2) f(std::integral_constant<int, 2>{});
+  else f(std::integral_constant<int, 3>{});
+}
+
+// Rows [r0, r1) of A grouped g at a time (g = 2 or 3) on the device: the
+// rows' entries are uploaded once, a count pass gives each group's entries (the
+// union of its rows' columns), a fill pass writes the group row pointers,
+// column lists and g values per entry as T (times colscale[column] when given),
+// exactly as the host's group_rows followed by a conversion to T.
+struct DevGroups {
+  int64_t ngroups = 0, entries = 0;
+  std::shared_ptr<DevBuf> rp, ci, val;
+};
+
+struct DevRows {  // rows [r0, r1) of a host CSR on the device, row pointers from 0
+  int64_t nrows = 0, nnz = 0;
+  std::shared_ptr<DevBuf> rp, ci, v;
+};
+
+DevRows upload_rows(const HCsr& A, int64_t r0, int64_t r1, hipStream_t s) {
+  DevRows R;
+  R.nrows = r1 - r0;
+  const int64_t e0 = A.rp[r0];
+  R.nnz = A.rp[r1] - e0;
+  std::vector<int64_t> rp(size_t(R.nrows + 1));
+  parallel_for(R.nrows + 1, [&](int64_t b, int64_t e) {
+    for (int64_t i = b; i < e; ++i) rp[i] = A.rp[r0 + i] - e0;
+  });
+  R.rp = upload_raw(rp, s);
+  R.ci = std::make_shared<DevBuf>();
+  R.ci->alloc(sizeof(int32_t) * std::max<int64_t>(R.nnz, 1));
+  h2d(R.ci->p, A.ci.data() + e0, size_t(R.nnz), s);
+  R.v = std::make_shared<DevBuf>();
+  R.v->alloc(sizeof(double) * std::max<int64_t>(R.nnz, 1));
+  h2d(R.v->p, A.v.data() + e0, size_t(R.nnz), s);
+  return R;
+}
+
+// Entries of each group (count pass); g must be 2 or 3.
+std::vector<int64_t> device_group_counts(const DevRows& R, int g, hipStream_t s) {
+  const int64_t ng = R.nrows / g;
+  std::vector<int64_t> cnt(size_t(ng), 0);
+  if (ng == 0) return cnt;
+  DevBuf dc;
+  dc.alloc(sizeof(int64_t) * ng);
+  with_rgroup(g, [&](auto gc) {
+    constexpr int G = decltype(gc)::value;
+    group_merge_kernel<G, false, double><<<unsigned((ng + 255) / 256), 256, 0, s>>>(
+        ng, R.rp->as<int64_t>(), R.ci->as<int32_t>(), R.v->as<double>(), nullptr, dc.as<int64_t>(), nullptr,
+        nullptr, nullptr);
+  });
+  HIP_TRY(hipGetLastError());
+  d2h(cnt.data(), dc.p, size_t(ng), s);
+  return cnt;
+}
+
+// The grouped arrays from the counts (fill pass).
+template <typename T>
+DevGroups device_group_fill(const DevRows& R, int g, const std::vector<int64_t>& cnt, const double* dcolscale,
+                            hipStream_t s) {
+  DevGroups out;
+  out.ngroups = int64_t(cnt.size());
+  std::vector<int64_t> grp(cnt.size() + 1, 0);
+  for (size_t q = 0; q < cnt.size(); ++q) grp[q + 1] = grp[q] + cnt[q];
+  out.entries = grp.back();
+  out.rp = upload_raw(grp, s);
+  out.ci = std::make_shared<DevBuf>();
+  out.ci->alloc(sizeof(int32_t) * std::max<int64_t>(out.entries, 1));
+  out.val = std::make_shared<DevBuf>();
+  out.val->alloc(sizeof(T) * std::max<int64_t>(out.entries * g, 1));
+  if (out.ngroups) {
+    with_rgroup(g, [&](auto gc) {
+      constexpr int G = decltype(gc)::value;
+      group_merge_kernel<G, true, T><<<unsigned((out.ngroups + 255) / 256), 256, 0, s>>>(
+          out.ngroups, R.rp->as<int64_t>(), R.ci->as<int32_t>(), R.v->as<double>(), dcolscale, nullptr,
+          out.rp->as<int64_t>(), out.ci->as<int32_t>(), out.val->as<T>());
+    });
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize(s));
+  }
+  return out;
+}
+
+// Rows [r0, r1) of A grouped g at a time on the device; colscale: optional
+// host column scale (A D^{-1}).
+template <typename T>
+DevGroups device_group_rows(const HCsr& A, int64_t r0, int64_t r1, int g, const std::vector<double>* colscale,
+                            hipStream_t s) {
+  if (g != 2 && g != 3) throw Error(FSI_ERR_ARG, "row groups of 2 or 3 rows only");
+  const DevRows R = upload_rows(A, r0, r1, s);
+  const std::vector<int64_t> cnt = device_group_counts(R, g, s);
+  std::shared_ptr<DevBuf> dscale;
+  if (colscale) dscale = upload_raw(*colscale, s);
+  return device_group_fill<T>(R, g, cnt, dscale ? dscale->as<double>() : nullptr, s);
+}
+
 // A in groups of g consecutive rows sharing one column list (g values per
-// entry), for the grouped level sweeps; with `as_segment` also described as a
+// entry), for the grouped level sweeps, grouped on the device (A's columns
+// scaled by colscale when given); with `as_segment` also described as a
 // one-segment RowSegments, so that launch_rows runs it.
 template <typename T>
-DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
-  std::vector<double> gv;
-  const HCsr G = group_rows(A, 0, A.nrows, g, gv);
+DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false, const std::vector<double>* colscale = nullptr,
+                       hipStream_t s = nullptr) {
+  DevGroups G = device_group_rows<T>(A, 0, A.nrows, g, colscale, s);
   DCsr<T> D;
   D.nrows = A.nrows;
   D.ncols = A.ncols;
-  D.nnz = G.nnz();
+  D.nnz = G.entries;
   D.rgroup = g;
   D.deep = true;
-  D.rp = upload_raw(G.rp);
-  D.ci = upload_raw(G.ci);
-  D.val = upload_as<T>(gv);
+  D.rp = G.rp;
+  D.ci = G.ci;
+  D.val = G.val;
   if (as_segment) {
-    const int64_t units = G.nrows;
+    const int64_t units = G.ngroups;
     const double avg = units ? double(D.nnz) / double(units) : 1.0;
     int lanes = 4;
     while (lanes < 32 && lanes * 12 < avg) lanes *= 2;
@@ -473,10 +573,14 @@ DCsr<T> upload_grouped(const HCsr& A, int g, bool as_segment = false) {
 // grouped segment are empty there); nnz stays the matrix's own count.
 // The row grouping of each segment (group[q], or 1 where the segment does
 // not split into whole groups or grouping costs more than 5% zero fill) and
-// the plain arrays: the rows of the ungrouped segments, grouped rows empty.
-HCsr segment_plan(const HCsr& A, const int64_t* bounds, const int* group, int nseg, int* grs) {
+// the row pointers of the plain arrays: the rows of the ungrouped segments,
+// grouped rows empty (segment q's entries follow those of the ungrouped
+// segments before it).
+std::vector<int64_t> segment_plan(const HCsr& A, const int64_t* bounds, const int* group, int nseg, int* grs) {
   if (nseg < 1 || nseg > 4 || bounds[0] != 0 || bounds[nseg] != A.nrows)
     throw Error(FSI_ERR_ARG, "row segments must cover the matrix in at most four parts");
+  std::vector<int64_t> rp(size_t(A.nrows + 1), 0);
+  int64_t skipped = 0;  // entries of the grouped segments before the current one
   for (int q = 0; q < nseg; ++q) {
     const int64_t r0 = bounds[q], r1 = bounds[q + 1];
     const int64_t units = r1 - r0, nz = r1 > r0 ? A.rp[r1] - A.rp[r0] : 0;
@@ -485,19 +589,32 @@ HCsr segment_plan(const HCsr& A, const int64_t* bounds, const int* group, int ns
                    double(group_entries(A, r0, r1, gr)) * gr > 1.05 * double(nz)))
       gr = 1;
     grs[q] = gr;
+    const int64_t sk = skipped;
+    if (gr == 1) {
+      parallel_for(units + 1, [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) rp[r0 + i] = A.rp[r0 + i] - sk;
+      });
+    } else {
+      std::fill(rp.begin() + r0, rp.begin() + r1 + 1, A.rp[r0] - sk);
+      skipped += nz;
+    }
   }
-  auto plain_row = [&](int64_t i) {
-    int q = 0;
-    while (q + 1 < nseg && i >= bounds[q + 1]) ++q;
-    return grs[q] == 1;
-  };
-  return build_rows(A.nrows, A.ncols,
-                    [&](int64_t i) { return plain_row(i) ? A.rp[i + 1] - A.rp[i] : int64_t(0); },
-                    [&](int64_t i, int32_t* oc, double* ov) {
-                      if (!plain_row(i)) return;
-                      std::copy(A.ci.begin() + A.rp[i], A.ci.begin() + A.rp[i + 1], oc);
-                      std::copy(A.v.begin() + A.rp[i], A.v.begin() + A.rp[i + 1], ov);
-                    });
+  return rp;
+}
+
+// The plain arrays' entries (segments with grs[q] == 1), ci and/or values as T,
+// copied straight from A's arrays into the device arrays.
+template <typename T>
+void upload_plain_entries(const HCsr& A, const int64_t* bounds, int nseg, const int* grs, DevBuf* ci, DevBuf* val,
+                          hipStream_t s) {
+  int64_t dst = 0;
+  for (int q = 0; q < nseg; ++q) {
+    if (grs[q] != 1 || bounds[q + 1] <= bounds[q]) continue;
+    const int64_t e0 = A.rp[bounds[q]], n = A.rp[bounds[q + 1]] - e0;
+    if (ci) h2d(ci->as<int32_t>() + dst, A.ci.data() + e0, size_t(n), s);
+    if (val) h2d_as<T>(val->as<T>() + dst, A.v.data() + e0, size_t(n), s);
+    dst += n;
+  }
 }
 
 // New values for a matrix uploaded by upload_segments from a matrix of the
@@ -507,29 +624,45 @@ template <typename T>
 void refresh_segments(const DCsr<T>& D, const HCsr& A, const int64_t* bounds, const int* group, int nseg,
                       hipStream_t s) {
   int grs[4];
-  const HCsr plain = segment_plan(A, bounds, group, nseg, grs);
+  const std::vector<int64_t> rp = segment_plan(A, bounds, group, nseg, grs);
+  const int64_t plain_nnz = rp.back();
   auto fits = [](const std::shared_ptr<DevBuf>& b, size_t n) { return n == 0 || (b && b->bytes == sizeof(T) * n); };
-  if (!fits(D.val, size_t(plain.nnz()))) throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
-  if (plain.nnz()) h2d_as<T>(D.val->p, plain.v.data(), size_t(plain.nnz()), s);
+  if (!fits(D.val, size_t(plain_nnz))) throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
+  if (plain_nnz) upload_plain_entries<T>(A, bounds, nseg, grs, nullptr, D.val.get(), s);
   for (int q = 0, k = 0; q < nseg; ++q) {
     if (bounds[q + 1] <= bounds[q]) continue;
     const int kk = k++;
     if ((D.seg.grp[kk] > 1) != (grs[q] > 1) || (grs[q] > 1 && D.seg.grp[kk] != grs[q]))
       throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
     if (grs[q] == 1) continue;
-    std::vector<double> gv;
-    const HCsr Gm = group_rows(A, bounds[q], bounds[q + 1], grs[q], gv);
-    if (!fits(D.grp_val[kk], gv.size())) throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
-    h2d_as<T>(D.grp_val[kk]->p, gv.data(), gv.size(), s);
+    DevGroups Gm = device_group_rows<T>(A, bounds[q], bounds[q + 1], grs[q], nullptr, s);
+    if (!fits(D.grp_val[kk], size_t(Gm.entries * grs[q])))
+      throw Error(FSI_ERR_ARG, "new values do not fit the stored layout");
+    HIP_TRY(hipMemcpyAsync(D.grp_val[kk]->p, Gm.val->p, sizeof(T) * size_t(Gm.entries * grs[q]),
+                           hipMemcpyDeviceToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));
   }
 }
 
 template <typename T>
 DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, int nseg, hipStream_t s) {
   int grs[4];
-  DCsr<T> D = upload<T>(segment_plan(A, bounds, group, nseg, grs), s);
+  const std::vector<int64_t> prp = segment_plan(A, bounds, group, nseg, grs);
+  DCsr<T> D;
+  D.nrows = A.nrows;
+  D.ncols = A.ncols;
   D.nnz = A.nnz();
   D.deep = true;
+  D.rp = upload_raw(prp, s);
+  const int64_t plain_nnz = prp.back();
+  D.group = pick_group(plain_nnz, A.nrows, plain_nnz >= (int64_t(1) << 21) ? 8 : 3);
+  if (plain_nnz) {
+    D.ci = std::make_shared<DevBuf>();
+    D.ci->alloc(sizeof(int32_t) * plain_nnz);
+    D.val = std::make_shared<DevBuf>();
+    D.val->alloc(sizeof(T) * plain_nnz);
+    upload_plain_entries<T>(A, bounds, nseg, grs, D.ci.get(), D.val.get(), s);
+  }
   RowSegments sg{};
   sg.nseg = 0;
   sg.blk0[0] = 0;
@@ -542,13 +675,12 @@ DCsr<T> upload_segments(const HCsr& A, const int64_t* bounds, const int* group, 
     int64_t units = r1 - r0, nz = A.rp[r1] - A.rp[r0];
     const int gr = grs[q];
     if (gr > 1) {
-      std::vector<double> gv;
-      const HCsr Gm = group_rows(A, r0, r1, gr, gv);
-      units = Gm.nrows;
-      nz = Gm.nnz();
-      D.grp_rp[k] = upload_raw(Gm.rp);
-      D.grp_ci[k] = upload_raw(Gm.ci);
-      D.grp_val[k] = upload_as<T>(gv, s);
+      DevGroups Gm = device_group_rows<T>(A, r0, r1, gr, nullptr, s);
+      units = Gm.ngroups;
+      nz = Gm.entries;
+      D.grp_rp[k] = Gm.rp;
+      D.grp_ci[k] = Gm.ci;
+      D.grp_val[k] = Gm.val;
       sg.grp_rp[k] = D.grp_rp[k]->template as<int64_t>();
       sg.grp_ci[k] = D.grp_ci[k]->template as<int32_t>();
       sg.grp_val[k] = D.grp_val[k]->template as<T>();
@@ -607,12 +739,6 @@ std::shared_ptr<DevBuf> upload_vec(const std::vector<double>& v, hipStream_t s) 
   return b;
 }
 
-// Rows per group of a grouped level (the components of a node).
-template <class F>
-void with_rgroup(int g, F&& f) {
-  if (g == 2) f(std::integral_constant<int, 2>{});
-  else f(std::integral_constant<int, 3>{});
-}
 
 inline unsigned grid_for(int64_t n, int per_block) {
   int64_t g = (n + per_block - 1) / per_block;
@@ -877,8 +1003,6 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       const HCsr APc = h.AP.nrows ? HCsr{} : device_spgemm(h.A, h.P, s);
       const HCsr& AP = h.AP.nrows ? h.AP : APc;
       const std::vector<double> dv = level_dinv(h.dinv);
-      HCsr AD = h.A;
-      scale_cols(AD, dv);
       // Restricting through Q = R (I - omega A D^{-1}) fuses the restriction
       // into the down-sweep but reads Q's entries (about R A's pattern)
       // instead of R's; where R A has kSplitNnz more nonzeros than R (counted
@@ -904,16 +1028,19 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       auto fits = [&](const HCsr& M) {
         return M.nrows % group == 0 && double(group_entries(M, 0, M.nrows, group)) * group <= 1.05 * double(M.nnz());
       };
-      if (group > 1 && nv == 1 && !(l == 0 && keep_a0) && AD.nnz() >= kDeepNnz && fits(AD) && fits(Rq) &&
+      // (A D^{-1} has A's pattern: it is formed from A where it is stored)
+      if (group > 1 && nv == 1 && !(l == 0 && keep_a0) && h.A.nnz() >= kDeepNnz && fits(h.A) && fits(Rq) &&
           fits(h.P) && fits(AP))
         d.rgroup = group;
       if (d.rgroup > 1) {
-        d.AD = upload_grouped<T>(AD, group);
-        if (d.split) d.R0 = upload_grouped<T>(h.R, group, true);
-        else d.Q = upload_grouped<T>(Q, group);
-        d.P = upload_grouped<T>(h.P, group);
-        d.AP = upload_grouped<T>(AP, group);
+        d.AD = upload_grouped<T>(h.A, group, false, &dv, s);  // grouped and scaled on the device
+        if (d.split) d.R0 = upload_grouped<T>(h.R, group, true, nullptr, s);
+        else d.Q = upload_grouped<T>(Q, group, false, nullptr, s);
+        d.P = upload_grouped<T>(h.P, group, false, nullptr, s);
+        d.AP = upload_grouped<T>(AP, group, false, nullptr, s);
       } else {
+        HCsr AD = h.A;
+        scale_cols(AD, dv);
         d.AD = upload<T>(AD, s);
         if (d.split) d.R0 = upload<T>(h.R, s);
         else d.Q = upload<T>(Q, s);
@@ -932,7 +1059,7 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       }
       // large levels are bandwidth streams (about ten entries per lane, four
       // loads in flight); small ones latency chains (about three per lane)
-      d.deep = AD.nnz() >= kDeepNnz;
+      d.deep = h.A.nnz() >= kDeepNnz;
       const int per_lane = d.deep ? 10 : 3;
       const int64_t units = d.n / d.rgroup;  // rows or row groups
       d.gdown = pick_group(d.AD.nnz, units, per_lane);

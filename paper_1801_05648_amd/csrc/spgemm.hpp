@@ -1,6 +1,7 @@
-// Sparse products C = A B of the AMG setup (prolongator smoothing, the
-// Galerkin product, the products of the level sweeps) on the device, one
-// wavefront per row of C.
+// Device kernels of the preconditioner setup: the sparse products C = A B of
+// the AMG setup (prolongator smoothing, the Galerkin product, the products of
+// the level sweeps), one wavefront per row of C, and the grouping of rows
+// that share their columns (at the end of the file).
 //
 // Every row is formed as the host product forms it: the products a_ik b_kj
 // are rounded and added in the order of k along row i of A, and entries that
@@ -153,6 +154,54 @@ __global__ __launch_bounds__(64) void spgemm_rows_kernel(const int32_t* __restri
     nz += __popcll(m);
   }
   if (!kFill && lane == 0) cnt[r] = nz;
+}
+
+}  // namespace fsi
+
+namespace fsi {
+
+// Rows of a matrix in groups of G consecutive rows sharing one column list
+// (the sorted union of the G rows' columns, G values per listed column, 0
+// where a row has no entry), one thread per group: the G sorted lists are
+// merged in column order.  kFill false: cnt[q] = entries of group q.  kFill
+// true: group q written at grp[q] (columns gci, values gval, value times
+// colscale[column] when colscale is not null, rounded to T).  Rows are rows
+// r0 + q G + r of the device CSR rp, ci, v (rp[0] need not be 0).
+template <int G, bool kFill, typename T>
+__global__ __launch_bounds__(256) void group_merge_kernel(int64_t ngroups, const int64_t* __restrict__ rp,
+                                                          const int32_t* __restrict__ ci,
+                                                          const double* __restrict__ v,
+                                                          const double* __restrict__ colscale,
+                                                          int64_t* __restrict__ cnt, const int64_t* __restrict__ grp,
+                                                          int32_t* __restrict__ gci, T* __restrict__ gval) {
+#pragma clang fp contract(off)
+  const int64_t q = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (q >= ngroups) return;
+  int64_t k[G], e[G];
+  for (int r = 0; r < G; ++r) {
+    k[r] = rp[q * G + r];
+    e[r] = rp[q * G + r + 1];
+  }
+  int64_t n = 0;
+  const int64_t out = kFill ? grp[q] : 0;
+  while (true) {
+    int32_t c = 0x7fffffff;
+    for (int r = 0; r < G; ++r)
+      if (k[r] < e[r]) c = min(c, ci[k[r]]);
+    if (c == 0x7fffffff) break;
+    if (kFill) gci[out + n] = c;
+    for (int r = 0; r < G; ++r) {
+      const bool has = k[r] < e[r] && ci[k[r]] == c;
+      if (kFill) {
+        double x = 0.0;
+        if (has) x = colscale ? v[k[r]] * colscale[c] : v[k[r]];
+        gval[(out + n) * G + r] = T(x);
+      }
+      if (has) ++k[r];
+    }
+    ++n;
+  }
+  if (!kFill) cnt[q] = n;
 }
 
 }  // namespace fsi
