@@ -5,8 +5,9 @@ One step = one full FGMRES(50) solve of A_h x = b to a 1e-8 true relative
 residual (x0 = 0), right-preconditioned by the block-LDU algorithm with AMG
 sub-inverses, inputs resident in HBM.  Default workload: the 3D
 128x32x32-cell Q2/Q1 FSI Jacobian (6.2M unknowns, 1.44e9 entries; seeded,
-synthetic), FP64 throughout.  The preconditioner build (host AMG setup +
-upload) is reported separately and is not part of a step.
+synthetic), FP64 throughout.  The preconditioner build (AMG setup steps on
+the host threads, its sparse products on the GPU, uploads) is reported
+separately (``setup_ms``) and is not part of a step.
 
 Prints one JSON line.  Extra objects: ``roofline`` for the dominant kernel
 (the A_h block product, timed with HIP events on the solver's stream),
@@ -37,7 +38,7 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563, "c4": 15873201262}
 # The same for one H_A V-cycle of the benchmark preconditioner (bench.py
 # --pmc-vcycle); see profiles/h_a_vcycle_hbm_traffic.md.
-MEASURED_VCYCLE_TRAFFIC = {"c2": 129161151, "c3": 1614689335}
+MEASURED_VCYCLE_TRAFFIC = {"c2": 129161151, "c3": 1614689335, "c4": 12483874808}
 DTYPE = {"f64": "f64", "f32": "f64-krylov/f32-precond", "f32-bf16diag": "f64-krylov/f32-precond/bf16-diag"}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
@@ -164,14 +165,28 @@ def learned_run(args, cfg):
     import fsigen
     from paper_1801_05648_amd import FsiSolver
 
+    from concurrent.futures import ThreadPoolExecutor
+
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     stream = torch.cuda.current_stream(dev)
     phase = fsigen.pseudo_time_phase
     train = [(k, i) for k in range(args.train_steps) for i in range(3)]
-    evals = [(k, 0) for k in args.eval_steps]
+    eval_steps = (list(range(args.train_steps, 50)) if args.eval_steps == ["all"]
+                  else [int(k) for k in args.eval_steps])
+    evals = [(k, i) for k in eval_steps for i in range(args.eval_solves)]
     progress(f"{cfg.name}: training on {len(train)} Newton systems, evaluating {len(evals)}")
-    sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(*train[0]))
+    # the next system is assembled on a host thread while the GPU solves this one
+    gen = ThreadPoolExecutor(max_workers=1)
+    systems = train + evals
+    ahead = {0: gen.submit(fsigen.generate, cfg, seed=args.seed, t_phase=phase(*systems[0]))}
+
+    def system_at(n):
+        if n + 1 < len(systems):
+            ahead[n + 1] = gen.submit(fsigen.generate, cfg, seed=args.seed, t_phase=phase(*systems[n + 1]))
+        return ahead.pop(n).result()
+
+    sysm = system_at(0)
     solver = FsiSolver.from_system(sysm, device=0, stream=stream)
     solver.build_precond(args.precision, **precond_opts(args, cfg.dim))
     d = sysm.dim
@@ -182,7 +197,7 @@ def learned_run(args, cfg):
     t_rec = time.perf_counter()
     for n, (k, i) in enumerate(train):
         if n:
-            sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
+            sysm = system_at(n)
             solver.set_from_system(sysm)
             solver.build_precond(args.precision, **precond_opts(args, cfg.dim))
         b = torch.from_numpy(sysm.b).to(dev)
@@ -196,8 +211,8 @@ def learned_run(args, cfg):
     train_ms = (time.perf_counter() - t0) * 1e3
     progress(f"trained in {train_ms:.0f} ms: {tinfo}")
     rows = []
-    for k, i in evals:
-        sysm = fsigen.generate(cfg, seed=args.seed, t_phase=phase(k, i))
+    for n, (k, i) in enumerate(evals):
+        sysm = system_at(len(train) + n)
         solver.set_from_system(sysm)
         solver.build_precond(args.precision, **precond_opts(args, cfg.dim))
         b = torch.from_numpy(sysm.b).to(dev)
@@ -230,6 +245,7 @@ def learned_run(args, cfg):
         progress(f"step {k}: {row}")
         rows.append(row)
     solver.close()
+    gen.shutdown()
     pm = statistics.mean(r["plain_ms"] for r in rows)
     lm = statistics.mean(r["learned_ms"] for r in rows)
     line = {
@@ -241,8 +257,11 @@ def learned_run(args, cfg):
         "config": {"workload": f"pseudo-time FSI Jacobians {'x'.join(map(str, cfg.cells))} cells",
                    "name": cfg.name, "seed": args.seed, "train_systems": len(train),
                    "precond": precond_name(args),
-                   "eval_steps": list(args.eval_steps)},
+                   "eval_steps": [eval_steps[0], eval_steps[-1]] if args.eval_steps == ["all"] else eval_steps,
+                   "eval_solves_per_step": args.eval_solves, "eval_systems": len(evals)},
         "plain_ms": round(pm, 3), "learned_over_plain_time": round(lm / pm, 4),
+        "learned_faster_on": sum(r["learned_ms"] < r["plain_ms"] for r in rows),
+        "max_solution_rel_diff": max(r["solution_rel_diff"] for r in rows),
         "plain_iters_mean": statistics.mean(r["plain_iters"] for r in rows),
         "learned_iters_mean": statistics.mean(r["learned_iters"] for r in rows),
         "record_s": round(t_rec, 1), "train_ms": round(train_ms, 1), "training": tinfo, "per_system": rows,
@@ -253,7 +272,8 @@ def learned_run(args, cfg):
 def precond_opts(args, dim: int) -> dict:
     """build_precond keyword arguments of the benchmarked preconditioner for a
     workload of dimension `dim` (defaults resolved in main)."""
-    cheb_on = args.cheb_on_arg if args.cheb_on_arg is not None else ("H_MS,H_SIG" if dim == 2 else "H_MS,H_SIG,H_P")
+    cheb_on = (args.cheb_on_arg if args.cheb_on_arg is not None
+               else "H_MS,H_SIG" if dim == 2 else "H_P" if args.learned else "H_MS,H_SIG,H_P")
     fluid_inner = (args.fluid_inner_arg if args.fluid_inner_arg is not None
                    else (0 if args.learned else 2))
     poly = poly_on(args)
@@ -411,7 +431,10 @@ def main():
     ap.add_argument("--learned", action="store_true",
                     help="pseudo-time workload of the learned smoother (plain vs learned cycles)")
     ap.add_argument("--train-steps", type=int, default=10)
-    ap.add_argument("--eval-steps", type=int, nargs="+", default=[10, 20, 30, 40, 49])
+    ap.add_argument("--eval-steps", nargs="+", default=["all"],
+                    help="pseudo-time steps evaluated by --learned ('all': every step after training, to 49)")
+    ap.add_argument("--eval-solves", type=int, default=3, choices=[1, 2, 3],
+                    help="Newton solves evaluated per step by --learned (3: all of them)")
     ap.add_argument("--train-iters", type=int, default=600)
     ap.add_argument("--max-vectors", type=int, default=192)
     ap.add_argument("--record-every", type=int, default=37)
@@ -435,12 +458,17 @@ def main():
     cfg = fsigen.config(args.config)
     if args.seeds is None:
         args.seeds = [0] if cfg.name == "c4" else [0, 1, 2]
+    # the learned smoother's workload: Jacobi V(1,1) with 500-row coarse grids
+    # in 2D; in 3D, where Jacobi sweeps everywhere take about 1300 iterations
+    # (64x16x16), Chebyshev(4) on H_P and M_s by Chebyshev steps, H_M and
+    # H_SIG left to the Jacobi sweeps the network replaces
+    learned2d = args.learned and cfg.dim == 2
     if args.cheb is None:
-        args.cheb = 0 if args.learned else 4
+        args.cheb = 0 if learned2d else 4
     if args.max_coarse is None:
-        args.max_coarse = 500 if args.learned else 2000
+        args.max_coarse = 500 if learned2d else 2000
     if args.poly_on is None:
-        args.poly_on = "" if args.learned else "H_MS"
+        args.poly_on = "" if learned2d else "H_MS"
     if args.poly_degree is None:
         # three Chebyshev steps for the solid mass matrix: in 3D two raise the
         # iterations from 46 to 78 (64x16x16); in 2D, with the inner fluid
@@ -663,35 +691,44 @@ def main():
         },
     }
 
-    # Other forms of the preconditioner on the same system, built from the
-    # FP64 build's hierarchies (reuse: only the device copies, smoothers and
-    # the fluid solve change), timed the same way, each solution compared
-    # with the FP64 GPU solve (the oracle is not run at this size): the FP32
-    # preconditioner with and without BF16-stored smoother diagonals, the
-    # paper's Section 4.4 fluid step (GMRES on each inverse of the Uzawa-like
-    # elimination)
+    # Other forms of the preconditioner on the same system, timed the same
+    # way, each solution compared with the FP64 GPU solve (the oracle is not
+    # run at this size): the FP32 preconditioner with and without BF16-stored
+    # smoother diagonals and the paper's Section 4.4 fluid step (GMRES on each
+    # inverse of the Uzawa-like elimination), from the FP64 build's
+    # hierarchies (reuse: only the device copies, smoothers and the fluid
+    # solve change); where the headline takes SIMPLEC, the paper's step again
+    # with SIMPLE (a build of its own), and the Uzawa-like step with one
+    # V-cycle per inverse and SIMPLE (the reading without inner Krylov steps)
     if not args.no_mixed and args.precision == "f64":
         r = runs[0]
         x64 = r["x"].clone()
         alts = {}
-        forms = [("f32", "f32", {}), ("f32-bf16diag", "f32-bf16diag", {})]
+        forms = [("f32", "f32", {}, True), ("f32-bf16diag", "f32-bf16diag", {}, True)]
         if args.uzawa_inner == 0:
-            forms.append(("paper_uzawa_gmres2", "f64", dict(fluid_inner=0, uzawa_inner=2)))
-        for label, prec, over in forms:
+            forms.append(("paper_uzawa_gmres2", "f64", dict(fluid_inner=0, uzawa_inner=2), True))
+            if opts["schur"] != "simple":
+                forms.append(("paper_uzawa_gmres2_simple", "f64",
+                              dict(fluid_inner=0, uzawa_inner=2, schur="simple"), False))
+            forms.append(("uzawa_vcycle_simple", "f64", dict(fluid_inner=0, uzawa_inner=0, schur="simple"), True))
+        for label, prec, over, reuse in forms:
             o2 = dict(opts)
             o2.update(over)
-            r["solver"].build_precond(prec, reuse=True, **o2)
+            t0 = time.perf_counter()
+            r["solver"].build_precond(prec, reuse=reuse, **o2)
+            build_ms = (time.perf_counter() - t0) * 1e3
             xm = torch.zeros_like(r["b"])
             timed_solves(r["solver"], r["b"], xm, 1)
             tm, im = timed_solves(r["solver"], r["b"], xm, max(min(args.steps, 3), 1))
             diff = float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))
             alts[label] = {"precision": prec, "ms": round(statistics.mean(tm), 3), "iters": im.iters,
                            "true_rel_resid": im.true_rel_resid, "rel_diff_vs_f64_gpu": diff,
-                           "speedup_vs_headline": round(ms / statistics.mean(tm), 3), **over}
+                           "speedup_vs_headline": round(ms / statistics.mean(tm), 3), **over,
+                           "build_ms": round(build_ms, 1), "hierarchies": "reused" if reuse else "built"}
             progress(f"{label}: {alts[label]}")
-        alts["note"] = ("seed %d; hierarchies of the headline build; FP64 Krylov, A_h products, true residual and "
-                        "coarsest solves in every form; difference measured against the FP64 GPU solve (oracle not "
-                        "run at this size)" % r["seed"])
+        alts["note"] = ("seed %d; hierarchies reused from the previous build where marked; FP64 Krylov, A_h "
+                        "products, true residual and coarsest solves in every form; difference measured against "
+                        "the FP64 GPU solve (oracle not run at this size)" % r["seed"])
         line["alternatives"] = alts
 
     for r in runs:

@@ -513,6 +513,37 @@ DevGroups device_group_fill(const DevRows& R, int g, const std::vector<int64_t>&
   return out;
 }
 
+// y = D^{-1} A x of the setup's power iteration on the device, the host's
+// product bit for bit (one thread per row, storage order); A and D^{-1} are
+// uploaded once per level, x and y travel per step.  Small levels keep the
+// host product (empty function).
+ScaledProduct device_scaled_product(const HCsr& A, const std::vector<double>& dinv, hipStream_t s) {
+  if (A.nnz() < (int64_t(1) << 20)) return {};
+  struct State {
+    DevRows R;
+    std::shared_ptr<DevBuf> dinv, x, y;
+    int64_t n = 0;
+    hipStream_t s = nullptr;
+  };
+  auto st = std::make_shared<State>();
+  st->n = A.nrows;
+  st->s = s;
+  st->R = upload_rows(A, 0, A.nrows, s);
+  st->dinv = upload_raw(dinv, s);
+  st->x = std::make_shared<DevBuf>();
+  st->x->alloc(sizeof(double) * st->n);
+  st->y = std::make_shared<DevBuf>();
+  st->y->alloc(sizeof(double) * st->n);
+  return [st](const double* x, double* y) {
+    h2d(st->x->p, x, size_t(st->n), st->s);
+    rowseq_scaled_matvec_kernel<<<unsigned((st->n + 255) / 256), 256, 0, st->s>>>(
+        st->n, st->R.rp->as<int64_t>(), st->R.ci->as<int32_t>(), st->R.v->as<double>(), st->dinv->as<double>(),
+        st->x->as<double>(), st->y->as<double>());
+    HIP_TRY(hipGetLastError());
+    d2h(y, st->y->p, size_t(st->n), st->s);
+  };
+}
+
 // Rows [r0, r1) of A grouped g at a time on the device; colscale: optional
 // host column scale (A D^{-1}).
 template <typename T>
@@ -902,7 +933,7 @@ constexpr int64_t kSplitNnz = int64_t(1) << 21;
 constexpr int64_t kFuseRestrictNnz = int64_t(1) << 18;
 
 template <typename T>
-DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
+DHier<T> upload_hier(SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 = false, int cheb = 0,
                      int poly = 0, double poly_ratio = 8.0, int group = 1, bool bf16diag = false) {
   DHier<T> D;
   D.nv = nv;
@@ -956,14 +987,14 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
     return D;
   }
   for (int l = 0; l <= L; ++l) {
-    const SaLevel& h = H.levels[l];
+    SaLevel& h = H.levels[l];
     DLevel<T> d;
     d.n = h.A.nrows;
     d.omega = T(h.omega);
     if (l < L && cheb > 0) {
       if (!(h.omega > 0.0)) throw Error(FSI_ERR_NUMERIC, "Chebyshev smoothing needs a positive spectral estimate");
-      const HCsr APc = h.AP.nrows ? HCsr{} : device_spgemm(h.A, h.P, s);  // A P unless the setup kept it
-      const HCsr& AP = h.AP.nrows ? h.AP : APc;
+      if (!h.AP.nrows) h.AP = device_spgemm(h.A, h.P, s);  // A P unless the setup kept it
+      const HCsr& AP = h.AP;
       d.cheb = cheb;
       cheb_coefficients<T>(h.omega, cheb, d.ca, d.cc);
       d.A0 = upload<T>(h.A, s);
@@ -972,7 +1003,8 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
       // Above 2^18 entries of R A, or on coarser levels (where R A's rows are
       // long next to the level's own), the fused coarse rows outlast the
       // launch saved (measured on the 2D and 3D workloads).
-      if (l == 0 && device_spgemm(h.R, h.A, s, true).rp.back() < kFuseRestrictNnz) {
+      if (l == 0 && h.ra_nnz < 0) h.ra_nnz = device_spgemm(h.R, h.A, s, true).rp.back();
+      if (l == 0 && h.ra_nnz < kFuseRestrictNnz) {
         d.RRA = upload_pair<T>(h.R, device_spgemm(h.R, h.A, s));
         d.gres = d.RRA.group >= 32 ? 64 : 16;
       } else {
@@ -1000,16 +1032,16 @@ DHier<T> upload_hier(const SaHierarchy& H, int nv, hipStream_t s, bool keep_a0 =
     } else if (l < L) {
       // setup-time products for the two-launch level sweeps (A P unless the
       // setup kept it)
-      const HCsr APc = h.AP.nrows ? HCsr{} : device_spgemm(h.A, h.P, s);
-      const HCsr& AP = h.AP.nrows ? h.AP : APc;
+      if (!h.AP.nrows) h.AP = device_spgemm(h.A, h.P, s);  // kept for later builds
+      const HCsr& AP = h.AP;
       const std::vector<double> dv = level_dinv(h.dinv);
       // Restricting through Q = R (I - omega A D^{-1}) fuses the restriction
       // into the down-sweep but reads Q's entries (about R A's pattern)
       // instead of R's; where R A has kSplitNnz more nonzeros than R (counted
       // on the device), restrict the residual with R in a launch of its own
       // and leave Q unformed (unless the learned smoother's sweep needs it).
-      const int64_t ra_nnz = device_spgemm(h.R, h.A, s, true).rp.back();
-      const bool split_worthy = ra_nnz - h.R.nnz() >= kSplitNnz;
+      if (h.ra_nnz < 0) h.ra_nnz = device_spgemm(h.R, h.A, s, true).rp.back();  // kept for later builds
+      const bool split_worthy = h.ra_nnz - h.R.nnz() >= kSplitNnz;
       d.split = !(l == 0 && keep_a0) && split_worthy;
       d.split_plain = l == 0 && keep_a0 && split_worthy;  // R is uploaded for that level below
       HCsr Q;
@@ -1780,10 +1812,6 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     }
   }
   link_mlp(c, *P);
-  // the setup's A P products are on the device now: release the host copies
-  // (a later build recomputes them)
-  for (auto& H : c.host_h)
-    for (auto& L : H.levels) L.AP = HCsr{};
   PhaseTimer t_cb("coupling blocks (and F for the inner steps)");
   const HCsr& S = c.blk[FSI_S];
   const HCsr& F = c.host_x_approx == FSI_X_BLOCKDIAG ? c.fluid_op : c.blk[FSI_F];  // F, or its refinement
@@ -2870,19 +2898,25 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     {
       std::vector<double> dA = diagonal(Af);
       std::vector<double> dinv(dA.size());
-      for (size_t i = 0; i < dA.size(); ++i) {
-        if (dA[i] == 0.0) throw Error(FSI_ERR_NUMERIC, "zero diagonal in the fluid velocity block");
-        double w = dA[i];
-        if (o.schur == FSI_SCHUR_SIMPLEC) {
-          w = 0.0;
-          for (int64_t k = Af.rp[i]; k < Af.rp[i + 1]; ++k) w += std::fabs(Af.v[k]);
+      std::atomic<bool> zero{false};
+      parallel_for(int64_t(dA.size()), [&](int64_t b, int64_t e) {
+        for (int64_t i = b; i < e; ++i) {
+          if (dA[i] == 0.0) zero.store(true);
+          double w = dA[i];
+          if (o.schur == FSI_SCHUR_SIMPLEC) {
+            w = 0.0;
+            for (int64_t k = Af.rp[i]; k < Af.rp[i + 1]; ++k) w += std::fabs(Af.v[k]);
+          }
+          dinv[i] = 1.0 / w;
         }
-        dinv[i] = 1.0 / w;
-      }
+      });
+      if (zero.load()) throw Error(FSI_ERR_NUMERIC, "zero diagonal in the fluid velocity block");
       HCsr Ds = Dm;
       scale_cols(Ds, dinv);
       Sp = device_spgemm(Ds, Gm, c.stream);
-      for (double& v : Sp.v) v = -v;
+      parallel_for(Sp.nnz(), [&](int64_t b, int64_t e) {
+        for (int64_t k = b; k < e; ++k) Sp.v[k] = -Sp.v[k];
+      });
       if (Zpp.nnz() > 0) Sp = add(Sp, Zpp, 1.0);
       drop_zeros(Sp);
     }
@@ -2897,12 +2931,16 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     const int ks[FSI_NHIER] = {1, krig, 1, d, 1};
     static const char* hn[FSI_NHIER] = {"H_M", "H_SIG", "H_MS", "H_A", "H_P"};
     SaHierarchy hh[FSI_NHIER];
-    // the sparse products on the device (bitwise equal to the host's)
+    // the sparse products and the power iteration's products on the device
+    // (bitwise equal to the host's)
     const SpgemmFn mul = [&](const HCsr& X, const HCsr& Y) { return device_spgemm(X, Y, c.stream); };
+    const ScaledProductFactory power = [&](const HCsr& X, const std::vector<double>& dv) {
+      return device_scaled_product(X, dv, c.stream);
+    };
     for (int h = 0; h < FSI_NHIER; ++h) {
       PhaseTimer t("sa_setup");
       const long long rows = (long long)ops[h]->nrows;
-      std::string m = sa_setup(std::move(*ops[h]), blocks[h], *Bs[h], ks[h], prm, hh[h], mul);
+      std::string m = sa_setup(std::move(*ops[h]), blocks[h], *Bs[h], ks[h], prm, hh[h], mul, power);
       if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
       log_line("SA setup %s: %.1f ms (%lld rows, %zu levels)", hn[h], t.ms(), rows, hh[h].levels.size());
     }

@@ -32,21 +32,27 @@ double norm2(const std::vector<double>& x) {
 }
 
 // rho(D^{-1} A): 30 normalised power steps from x_i = 1 + (i mod 7)/7, then
-// the norm of one more application.
-double spectral_radius(const HCsr& A, const std::vector<double>& dinv) {
+// the norm of one more application; `product` (if set) forms y = D^{-1} A x.
+double spectral_radius(const HCsr& A, const std::vector<double>& dinv, const ScaledProduct& product) {
   const int64_t n = A.nrows;
   std::vector<double> x(n), y(n);
+  auto apply = [&]() {
+    if (product) {
+      product(x.data(), y.data());
+      return;
+    }
+    matvec(A, x.data(), y.data());
+    for (int64_t i = 0; i < n; ++i) y[i] = dinv[i] * y[i];
+  };
   for (int64_t i = 0; i < n; ++i) x[i] = 1.0 + double(i % 7) / 7.0;
   double nx = norm2(x);
   for (int64_t i = 0; i < n; ++i) x[i] /= nx;
   for (int it = 0; it < kPowerIters; ++it) {
-    matvec(A, x.data(), y.data());
-    for (int64_t i = 0; i < n; ++i) y[i] = dinv[i] * y[i];
+    apply();
     double ny = norm2(y);
     for (int64_t i = 0; i < n; ++i) x[i] = y[i] / ny;
   }
-  matvec(A, x.data(), y.data());
-  for (int64_t i = 0; i < n; ++i) y[i] = dinv[i] * y[i];
+  apply();
   return norm2(y);
 }
 
@@ -385,7 +391,7 @@ std::string sa_finalize(SaHierarchy& H) {
 }
 
 std::string sa_setup(HCsr A, int block, const std::vector<double>& B0, int k0, const SaParams& prm,
-                     SaHierarchy& H, const SpgemmFn& mul) {
+                     SaHierarchy& H, const SpgemmFn& mul, const ScaledProductFactory& power) {
   auto product = [&](const HCsr& X, const HCsr& Y) { return mul ? mul(X, Y) : spgemm(X, Y); };
   H.levels.clear();
   std::vector<double> B = B0;
@@ -407,7 +413,7 @@ std::string sa_setup(HCsr A, int block, const std::vector<double>& B0, int k0, c
     const HCsr& Al = lev.A;
     const int64_t n = Al.nrows;
     if (n <= prm.max_coarse || int(H.levels.size()) == prm.max_levels) break;
-    const double rho = spectral_radius(Al, lev.dinv);
+    const double rho = spectral_radius(Al, lev.dinv, power ? power(Al, lev.dinv) : ScaledProduct{});
     if (!(rho > 0.0) || !std::isfinite(rho)) return "non-finite spectral radius estimate";
     lev.omega = (4.0 / 3.0) / rho;
     Strength S = strength(Al, b, eps);

@@ -18,7 +18,8 @@ struct SaParams {
 
 struct SaLevel {
   HCsr A, P, R;
-  HCsr AP;  // A P of the Galerkin product, kept for the level sweeps (may be released)
+  HCsr AP;  // A P of the Galerkin product, kept for the level sweeps (empty: not formed yet)
+  int64_t ra_nnz = -1;  // nonzeros of R A once counted (-1: not yet)
   std::vector<double> dinv;
   double omega = 0.0;
   int block = 1;
@@ -35,8 +36,14 @@ struct SaHierarchy {
 // The sparse products C = A B of the setup; a replacement of the host
 // product must return spgemm's result bit for bit (empty: spgemm).
 using SpgemmFn = std::function<HCsr(const HCsr&, const HCsr&)>;
+// y = D^{-1} A x of the power iteration behind the Jacobi weight; a
+// replacement must return the host product bit for bit (each row summed in
+// storage order, then scaled).  The factory prepares it for one level
+// matrix; an empty factory keeps the host product.
+using ScaledProduct = std::function<void(const double* x, double* y)>;
+using ScaledProductFactory = std::function<ScaledProduct(const HCsr& A, const std::vector<double>& dinv)>;
 std::string sa_setup(HCsr A, int block, const std::vector<double>& B, int k, const SaParams& prm,
-                     SaHierarchy& H, const SpgemmFn& mul = {});
+                     SaHierarchy& H, const SpgemmFn& mul = {}, const ScaledProductFactory& power = {});
 
 // Dense inverse (LU with partial pivoting, smallest row index on ties) of the
 // n x n row-major matrix a; returns false on a zero pivot.

@@ -205,3 +205,24 @@ __global__ __launch_bounds__(256) void group_merge_kernel(int64_t ngroups, const
 }
 
 }  // namespace fsi
+
+namespace fsi {
+
+// y_i = dinv_i * sum_k a_ik x_k with the row summed in storage order by one
+// thread (FMA contraction off): the host power iteration's product bit for
+// bit, for the spectral estimate of the AMG setup.
+__global__ __launch_bounds__(256) void rowseq_scaled_matvec_kernel(int64_t n, const int64_t* __restrict__ rp,
+                                                                   const int32_t* __restrict__ ci,
+                                                                   const double* __restrict__ v,
+                                                                   const double* __restrict__ dinv,
+                                                                   const double* __restrict__ x,
+                                                                   double* __restrict__ y) {
+#pragma clang fp contract(off)
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double s = 0.0;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) s += v[k] * x[ci[k]];
+  y[i] = dinv[i] * s;
+}
+
+}  // namespace fsi
