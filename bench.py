@@ -38,7 +38,10 @@ HBM_PEAK_GBS = 8000.0
 MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563, "c4": 15873201262}
 # The same for one H_A V-cycle of the benchmark preconditioner (bench.py
 # --pmc-vcycle); see profiles/h_a_vcycle_hbm_traffic.md.
-MEASURED_VCYCLE_TRAFFIC = {"c2": 129161151, "c3": 1614689335, "c4": 12483874808}
+# Keyed by workload: (traffic, the cycle's bytes as stored when measured); a
+# hierarchy of other bytes (other AMG options) has no figure.
+MEASURED_VCYCLE_TRAFFIC = {"c2": (129161151, 108663072), "c3": (1614689335, 1520085216),
+                           "c4": (12483874808, 11782010640)}
 DTYPE = {"f64": "f64", "f32": "f64-krylov/f32-precond", "f32-bf16diag": "f64-krylov/f32-precond/bf16-diag"}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
@@ -463,18 +466,22 @@ def main():
     # (64x16x16), Chebyshev(4) on H_P and M_s by Chebyshev steps, H_M and
     # H_SIG left to the Jacobi sweeps the network replaces
     learned2d = args.learned and cfg.dim == 2
+    # 3D solver: Chebyshev(5) sweeps, M_s by four Chebyshev steps and 4000-row
+    # coarse grids cut 64x16x16 from 26 to 19 iterations (68.6 -> 49.9 ms)
+    # and 128x32x32 from 28 to 24 (466 -> 409 ms; the larger dense coarse
+    # inverses add 2.5 s to its build); in 2D they gain nothing (256x64:
+    # 11.5-11.7 ms either way).  In 3D two M_s steps raise the iterations
+    # from 46 to 78 (64x16x16, the split fluid step); in 2D, with the inner
+    # fluid GMRES, three take 17/18/21 instead of 19/20/23 (11.5 vs 12.3 ms)
+    solver3d = cfg.dim == 3 and not args.learned
     if args.cheb is None:
-        args.cheb = 0 if learned2d else 4
+        args.cheb = 0 if learned2d else 5 if solver3d else 4
     if args.max_coarse is None:
-        args.max_coarse = 500 if learned2d else 2000
+        args.max_coarse = 500 if learned2d else 4000 if solver3d else 2000
     if args.poly_on is None:
         args.poly_on = "" if learned2d else "H_MS"
     if args.poly_degree is None:
-        # three Chebyshev steps for the solid mass matrix: in 3D two raise the
-        # iterations from 46 to 78 (64x16x16); in 2D, with the inner fluid
-        # GMRES, three take 17/18/21 instead of 19/20/23 iterations (256x64:
-        # 11.5 vs 12.3 ms)
-        args.poly_degree = 3
+        args.poly_degree = 4 if solver3d else 3
     # fluid_inner: two inner GMRES steps on the fluid block, preconditioned by
     # the block upper-triangular step, halve the 2D outer iterations (256x64:
     # 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms; 14.4 ms with the Uzawa-like
@@ -680,8 +687,9 @@ def main():
             "GB/s": round(vc_bytes / (vc_ms * 1e-3) / 1e9, 1),
             "frac": round(vc_bytes / (vc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "levels": int(len(solver.hierarchy_info("H_A")[0])),
-            "traffic": (MEASURED_VCYCLE_TRAFFIC.get(cfg.name)
-                        if (args.precision, args.max_coarse, args.strength) == ("f64", 2000, 0.08) else None),
+            "traffic": (MEASURED_VCYCLE_TRAFFIC[cfg.name][0]
+                        if args.precision == "f64" and cfg.name in MEASURED_VCYCLE_TRAFFIC
+                        and int(vc_bytes) == MEASURED_VCYCLE_TRAFFIC[cfg.name][1] else None),
         },
         "vcycle_H_SIG": {
             "bytes": int(vs_bytes), "ms": round(vs_ms, 5),

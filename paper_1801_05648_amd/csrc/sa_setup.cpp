@@ -346,22 +346,42 @@ bool dense_inverse(std::vector<double> a, int64_t n, std::vector<double>& inv) {
       }
       bar.wait();
     }
-    std::vector<double> x(n);
-    for (int64_t col = tid; col < n; col += nt) {
-      for (int64_t i = 0; i < n; ++i) x[i] = i == col ? 1.0 : 0.0;
-      for (int64_t k = 0; k < n; ++k)
-        if (piv[k] != k) std::swap(x[k], x[piv[k]]);
+    // the columns of the inverse, in a contiguous range per thread, solved
+    // together row by row: entry (i, col) takes its updates in the order of
+    // c, as a column-by-column substitution would, but the updates of a row
+    // run along the range (vectorisable)
+    const int64_t c0 = n * tid / nt, c1 = n * (tid + 1) / nt, w = c1 - c0;
+    if (w > 0) {
+      std::vector<double> X(size_t(n) * w, 0.0);  // rows of the range, row-major
+      for (int64_t col = c0; col < c1; ++col) {
+        int64_t r = col;  // where the row swaps take the 1 of e_col
+        for (int64_t k = 0; k < n; ++k) {
+          if (piv[k] == k) continue;
+          if (r == k) r = piv[k];
+          else if (r == piv[k]) r = k;
+        }
+        X[size_t(r) * w + (col - c0)] = 1.0;
+      }
       for (int64_t i = 0; i < n; ++i) {
-        double s = x[i];
-        for (int64_t c = 0; c < i; ++c) s -= a[i * n + c] * x[c];
-        x[i] = s;
+        double* xi = X.data() + size_t(i) * w;
+        for (int64_t c = 0; c < i; ++c) {
+          const double l = a[i * n + c];
+          const double* xc = X.data() + size_t(c) * w;
+          for (int64_t j = 0; j < w; ++j) xi[j] -= l * xc[j];
+        }
       }
       for (int64_t i = n - 1; i >= 0; --i) {
-        double s = x[i];
-        for (int64_t c = i + 1; c < n; ++c) s -= a[i * n + c] * x[c];
-        x[i] = s / a[i * n + i];
+        double* xi = X.data() + size_t(i) * w;
+        for (int64_t c = i + 1; c < n; ++c) {
+          const double u = a[i * n + c];
+          const double* xc = X.data() + size_t(c) * w;
+          for (int64_t j = 0; j < w; ++j) xi[j] -= u * xc[j];
+        }
+        const double d = a[i * n + i];
+        for (int64_t j = 0; j < w; ++j) xi[j] = xi[j] / d;
       }
-      for (int64_t i = 0; i < n; ++i) inv[i * n + col] = x[i];
+      for (int64_t i = 0; i < n; ++i)
+        std::copy(X.begin() + size_t(i) * w, X.begin() + size_t(i + 1) * w, inv.begin() + i * n + c0);
     }
   };
   std::vector<std::thread> team;

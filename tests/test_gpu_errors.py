@@ -144,13 +144,16 @@ def test_call_order_and_argument_checks():
     F.load().fsi_destroy(ctx)
 
 
-def test_hierarchy_reuse_rules():
+@pytest.mark.parametrize("name", ["c1", "m3"])
+def test_hierarchy_reuse_rules(name):
     """reuse=True needs a previous build of the same system with the same AMG
     parameters and Schur option (else FSI_ERR_STATE, context unchanged); a
     new system drops the right to reuse; a reused build solves like a fresh
-    one (bit-identical: the same host hierarchies are uploaded)."""
+    one (bit-identical: the same host hierarchies, with the A P products and
+    R A counts they keep, are uploaded; on the 3D system the products and
+    the row grouping run on the device)."""
     from paper_1801_05648_amd import FsiError, FsiSolver
-    sysm = system("c1")
+    sysm = system(name)
     s = FsiSolver.from_system(sysm, device=0)
     with pytest.raises(FsiError) as e:
         s.build_precond("f32", reuse=True)

@@ -440,29 +440,30 @@ def test_bench_configuration_full_size_matches_oracle():
     assert err <= 1e-6
 
 
+BENCH3D_OPTS = dict(max_coarse=4000, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=4,
+                   schur="simplec", fluid_inner=2, fluid_inner_pc="triangular")
+
+
 def test_3d_bench_configuration_matches_oracle():
-    """The 3D benchmark preconditioner (Chebyshev(4) V-cycles on H_SIG and H_P,
-    M_s by three Chebyshev steps, 2000-row coarse grids; grouped H_A levels,
-    the mesh level restricting apart; the SIMPLEC pressure Schur
-    approximation; the fluid inverse by two inner GMRES steps on F
-    preconditioned by the block upper-triangular step) on the 32x8x8-cell
-    system: the GPU takes the oracle's iteration count to 1e-8 (13), its
-    iterate agrees with the oracle's 1e-8 iterate within 1e-9 (unique Krylov
-    iterate) and with the oracle's 1e-12 solution within 1e-6 (the oracle's
-    own 1e-8 iterate: 5.2e-7)."""
+    """The 3D benchmark preconditioner (Chebyshev(5) V-cycles on H_SIG and H_P,
+    M_s by four Chebyshev steps, 4000-row coarse grids; grouped H_A levels;
+    the SIMPLEC pressure Schur approximation; the fluid inverse by two inner
+    GMRES steps on F preconditioned by the block upper-triangular step) on the
+    32x8x8-cell system: the GPU takes the oracle's iteration count to 1e-8,
+    its iterate agrees with the oracle's 1e-8 iterate within 1e-9 (unique
+    Krylov iterate) and with the oracle's 1e-12 solution within 1e-6."""
     from oracle import blocks, krylov, precond
     from paper_1801_05648_amd import FsiSolver
     sysm = system("m3")
     bs = blocks.BlockSystem(sysm)
     s = FsiSolver.from_system(sysm, device=0)
-    s.build_precond("f64", max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3,
-                    schur="simplec", fluid_inner=2, fluid_inner_pc="triangular")
+    s.build_precond("f64", **BENCH3D_OPTS)
     x, info = s.solve(_dev(sysm.b), tol=1e-8)
     s.close()
     xg = x.cpu().numpy()
     r = np.linalg.norm(sysm.b - bs.matvec(xg)) / np.linalg.norm(sysm.b)
-    H = precond.build_hierarchies(bs, max_coarse=2000, schur="simplec")
-    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4, "H_P": 4}, poly={"H_MS": (3, 8.0)}, fluid_inner=2,
+    H = precond.build_hierarchies(bs, max_coarse=4000, schur="simplec")
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 5, "H_P": 5}, poly={"H_MS": (4, 8.0)}, fluid_inner=2,
                                    fluid_inner_pc="triangular")
     xo8, io8 = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-8, restart=50, maxit=500)
     xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
@@ -590,29 +591,41 @@ def test_inner_gmres_solve_matches_oracle(precision, k, pc):
     assert err <= bound
 
 
-def test_apply_precond_parity_c3_benchmark_options():
-    """The 3D benchmark preconditioner (Chebyshev(4) V-cycles on H_SIG and H_P,
-    Jacobi V(1,1) on H_M and H_A with its large levels stored in groups of
-    three rows, M_s by three Chebyshev steps alone, 2000-row dense coarse
-    grids) at the full 64x16x16-cell size (753,740 unknowns) on the oracle's
-    five hierarchies: one application of P^{-1}, element-wise per block
-    within 1e-12 of the block's largest entry."""
+@pytest.mark.parametrize("form", ["split", "bench"])
+def test_apply_precond_parity_c3_benchmark_options(form):
+    """3D preconditioners at the full 64x16x16-cell size (753,740 unknowns) on
+    the oracle's five hierarchies: one application of P^{-1}, element-wise per
+    block within 1e-12 of the block's largest entry.  "split": Chebyshev(4)
+    V-cycles on H_SIG and H_P, Jacobi V(1,1) on H_M and H_A (large levels in
+    groups of three rows), M_s by three Chebyshev steps, 2000-row dense coarse
+    grids, the Uzawa-like fluid step with SIMPLE.  "bench": the benchmark's
+    3D preconditioner (Chebyshev(5), four M_s steps, 4000-row coarse grids,
+    SIMPLEC, two inner GMRES steps on F with the triangular step; measured
+    3.7e-14)."""
     from oracle import blocks, precond
     from paper_1801_05648_amd import FsiSolver
     sysm = system("c3")
     bs = blocks.BlockSystem(sysm)
-    H = precond.build_hierarchies(bs, max_coarse=2000)
+    if form == "split":
+        opts = dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3)
+        kw = {}
+    else:
+        opts = dict(BENCH3D_OPTS)
+        kw = dict(fluid_inner=2, fluid_inner_pc="triangular")
+    H = precond.build_hierarchies(bs, max_coarse=opts["max_coarse"], schur=opts.get("schur", "simple"))
     s = FsiSolver.from_system(sysm, device=0)
-    s.build_precond("f64", max_coarse=2000, cheb_degree=4, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=3)
+    s.build_precond("f64", **opts)
     _import_oracle_hierarchies(s, H)
-    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 4, "H_P": 4}, poly={"H_MS": (3, 8.0)})
+    deg = opts["cheb_degree"]
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": deg, "H_P": deg}, poly={"H_MS": (opts["poly_degree"], 8.0)},
+                                   **kw)
     r = np.random.default_rng(23).standard_normal(bs.N)
     z = s.apply_precond(_dev(r)).cpu().numpy()
     s.close()
     ref = P(r)
     for part, a, b in zip(("mesh", "solid", "fluid"), bs.split(z), bs.split(ref)):
         e_inf = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
-        print(f"c3 P^-1 r {part}: max-abs {e_inf:.2e}, rel L2 {_rel(a, b):.2e}")
+        print(f"c3 {form} P^-1 r {part}: max-abs {e_inf:.2e}, rel L2 {_rel(a, b):.2e}")
         assert e_inf <= 1e-12 and _rel(a, b) <= 1e-12, part
 
 
