@@ -77,7 +77,7 @@ def cpu_baseline(args, gpu_c3=None, sample_iters: int = 2):
         bs = blocks.BlockSystem(sysm)
         o = precond_opts(args, cfg.dim)
         t0 = time.perf_counter()
-        H = precond.build_hierarchies(bs, eps0=args.strength, max_coarse=args.max_coarse, schur=o["schur"],
+        H = precond.build_hierarchies(bs, eps0=o["strength0"], max_coarse=o["max_coarse"], schur=o["schur"],
                                       x_approx=args.x_approx)
         t_setup = time.perf_counter() - t0
         cheb = {h: o["cheb_degree"] for h in o["cheb"]} if o["cheb_degree"] > 0 else None
@@ -274,19 +274,42 @@ def learned_run(args, cfg):
 
 def precond_opts(args, dim: int) -> dict:
     """build_precond keyword arguments of the benchmarked preconditioner for a
-    workload of dimension `dim` (defaults resolved in main)."""
+    workload of dimension `dim`: the options given on the command line, the
+    defaults of that dimension for the others."""
+    def given(name, default):
+        v = getattr(args, name + "_arg")
+        return default if v is None else v
+    # the learned smoother's workload: Jacobi V(1,1) with 500-row coarse grids
+    # in 2D; in 3D, where Jacobi sweeps everywhere take about 1300 iterations
+    # (64x16x16), Chebyshev(4) on H_P and M_s by Chebyshev steps, H_M and
+    # H_SIG left to the Jacobi sweeps the network replaces
+    learned2d = args.learned and dim == 2
+    # 3D solver: Chebyshev(5) sweeps, M_s by five Chebyshev steps, 4000-row
+    # coarse grids and the strength threshold 0.04 cut 64x16x16 from 26 to 15
+    # iterations (68.6 -> 36.7 ms) and 128x32x32 from 28 to 20 (466 -> 306 ms;
+    # the larger dense coarse inverses cost about a second of its build).  In
+    # 3D two M_s steps raise the iterations from 46 to 78 (64x16x16, the split
+    # fluid step); in 2D, with the inner fluid GMRES, three take 17/18/21
+    # instead of 19/20/23 (11.5 vs 12.3 ms), and the 3D changes gain nothing
+    # there (256x64: 11.4-11.7 ms)
+    solver3d = dim == 3 and not args.learned
+    cheb = given("cheb", 0 if learned2d else 5 if solver3d else 4)
+    max_coarse = given("max_coarse", 500 if learned2d else 4000 if solver3d else 2000)
+    poly_on_s = given("poly_on", "" if learned2d else "H_MS")
+    poly_degree = given("poly_degree", 5 if solver3d else 3)
+    strength = given("strength", 0.04 if solver3d else 0.08)
     cheb_on = (args.cheb_on_arg if args.cheb_on_arg is not None
                else "H_MS,H_SIG" if dim == 2 else "H_P" if args.learned else "H_MS,H_SIG,H_P")
     fluid_inner = (args.fluid_inner_arg if args.fluid_inner_arg is not None
                    else (0 if args.learned else 2))
-    poly = poly_on(args)
+    poly = tuple(h for h in poly_on_s.split(",") if h)
     # SIMPLEC in 3D: with the inner GMRES on F it cuts 64x16x16 from 33 to 26
     # iterations (85.3 -> 66.8 ms) and 128x32x32 from 31 to 28 (519 -> 467 ms);
     # without the inner GMRES it had raised 128x32x32 from 47 to 68
     schur = args.schur_arg if args.schur_arg is not None else ("simple" if dim == 2 or args.learned else "simplec")
-    return dict(max_coarse=args.max_coarse, strength0=args.strength, cheb_degree=args.cheb,
+    return dict(max_coarse=max_coarse, strength0=strength, cheb_degree=cheb,
                 cheb=tuple(h for h in cheb_on.split(",") if h and h not in poly), poly=poly,
-                poly_degree=args.poly_degree, poly_ratio=args.poly_ratio, schur=schur,
+                poly_degree=poly_degree, poly_ratio=args.poly_ratio, schur=schur,
                 fluid_inner=0 if args.uzawa_inner > 0 else fluid_inner, fluid_inner_pc=args.fluid_inner_pc,
                 uzawa_inner=args.uzawa_inner, x_approx=args.x_approx)
 
@@ -402,9 +425,10 @@ def main():
                     help="skip the other preconditioner forms reported beside the headline solve")
     ap.add_argument("--cheb", type=int, default=None,
                     help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
-                         "default 4, and 0 with --learned (the learned smoother replaces a Jacobi sweep)")
+                         "default 5 in 3D, 4 in 2D, 0 with --learned in 2D")
     ap.add_argument("--max-coarse", type=int, default=None,
-                    help="AMG: coarsest level size bound (dense inverse below it); default 2000, 500 with --learned")
+                    help="AMG: coarsest level size bound (dense inverse below it); default 4000 in 3D, 2000 in 2D, "
+                         "500 with --learned in 2D")
     ap.add_argument("--cheb-on", default=None,
                     help="comma-separated hierarchies that get the Chebyshev sweeps "
                          "(default: H_SIG in 2D, H_SIG and H_P in 3D)")
@@ -425,10 +449,10 @@ def main():
                          "0: one V-cycle per inverse)")
     ap.add_argument("--x-approx", default="F", choices=["F", "blockdiag"],
                     help="fluid operator standing for the Schur complement X (Section 4.1)")
-    ap.add_argument("--strength", type=float, default=0.08,
-                    help="SA strength threshold of the finest level (halved per level)")
+    ap.add_argument("--strength", type=float, default=None,
+                    help="SA strength threshold of the finest level (halved per level); default 0.04 in 3D, 0.08 in 2D")
     ap.add_argument("--poly-degree", type=int, default=None,
-                    help="Chebyshev-alone steps (default 3)")
+                    help="Chebyshev-alone steps (default 5 in 3D, 3 in 2D)")
     ap.add_argument("--poly-ratio", type=float, default=8.0,
                     help="Chebyshev-alone inverses: interval [lam/ratio, lam]")
     ap.add_argument("--learned", action="store_true",
@@ -448,6 +472,8 @@ def main():
                          "(for hardware byte counters); prints nothing else")
     args = ap.parse_args()
     args.cheb_on_arg, args.fluid_inner_arg, args.schur_arg = args.cheb_on, args.fluid_inner, args.schur
+    args.cheb_arg, args.max_coarse_arg, args.poly_on_arg = args.cheb, args.max_coarse, args.poly_on
+    args.poly_degree_arg, args.strength_arg = args.poly_degree, args.strength
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
@@ -461,39 +487,13 @@ def main():
     cfg = fsigen.config(args.config)
     if args.seeds is None:
         args.seeds = [0] if cfg.name == "c4" else [0, 1, 2]
-    # the learned smoother's workload: Jacobi V(1,1) with 500-row coarse grids
-    # in 2D; in 3D, where Jacobi sweeps everywhere take about 1300 iterations
-    # (64x16x16), Chebyshev(4) on H_P and M_s by Chebyshev steps, H_M and
-    # H_SIG left to the Jacobi sweeps the network replaces
-    learned2d = args.learned and cfg.dim == 2
-    # 3D solver: Chebyshev(5) sweeps, M_s by four Chebyshev steps and 4000-row
-    # coarse grids cut 64x16x16 from 26 to 19 iterations (68.6 -> 49.9 ms)
-    # and 128x32x32 from 28 to 24 (466 -> 409 ms; the larger dense coarse
-    # inverses add 2.5 s to its build); in 2D they gain nothing (256x64:
-    # 11.5-11.7 ms either way).  In 3D two M_s steps raise the iterations
-    # from 46 to 78 (64x16x16, the split fluid step); in 2D, with the inner
-    # fluid GMRES, three take 17/18/21 instead of 19/20/23 (11.5 vs 12.3 ms)
-    solver3d = cfg.dim == 3 and not args.learned
-    if args.cheb is None:
-        args.cheb = 0 if learned2d else 5 if solver3d else 4
-    if args.max_coarse is None:
-        args.max_coarse = 500 if learned2d else 4000 if solver3d else 2000
-    if args.poly_on is None:
-        args.poly_on = "" if learned2d else "H_MS"
-    if args.poly_degree is None:
-        args.poly_degree = 4 if solver3d else 3
-    # fluid_inner: two inner GMRES steps on the fluid block, preconditioned by
-    # the block upper-triangular step, halve the 2D outer iterations (256x64:
-    # 39/42/47 -> 19/20/23; 20.6 -> 12.3 ms; 14.4 ms with the Uzawa-like
-    # inner step) and cut the 3D ones by a third (64x16x16: 46 -> 33
-    # iterations, 93.8 -> 85.3 ms; 128x32x32: 47 -> 31, 635.6 -> 517.6 ms).
-    # cheb_on: the 2D pressure Schur approximation does best with Jacobi
-    # sweeps (256x64: 20.9 vs 23.5 ms, 39-47 vs 41-49 iterations); the 3D one
-    # needs the Chebyshev sweeps (64x16x16: 46 vs 530 iterations)
     opts = precond_opts(args, cfg.dim)
+    # the resolved options of the main workload, for the line's description
     args.cheb_on = ",".join(opts["cheb"])
     args.fluid_inner = opts["fluid_inner"]
     args.schur = opts["schur"]
+    args.cheb, args.max_coarse, args.strength = opts["cheb_degree"], opts["max_coarse"], opts["strength0"]
+    args.poly_on, args.poly_degree = ",".join(opts["poly"]), opts["poly_degree"]
     if args.learned:
         learned_run(args, cfg)
         return
@@ -645,7 +645,7 @@ def main():
         "config": {
             "workload": workload_name(cfg),
             "name": cfg.name, "seeds": list(args.seeds), "N": runs[0]["N"], "nnz": runs[0]["nnz"],
-            "tol": 1e-8, "restart": 50, "precond": precond_name(args), "max_coarse": args.max_coarse,
+            "tol": 1e-8, "restart": 50, "precond": precond_name(args), "max_coarse": args.max_coarse, "strength": args.strength,
             "paper_vs_own": paper_vs_own(args, opts),
         },
         "iters": {str(r["seed"]): r.get("iters") for r in runs},

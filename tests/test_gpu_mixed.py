@@ -86,14 +86,14 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(name):
 def _bench_precond(dim):
     """The benchmarked preconditioner: in 2D Chebyshev(4) V-cycles on H_SIG,
     M_s by three Chebyshev steps, 2000-row coarse grids, SIMPLE; in 3D
-    Chebyshev(5) on H_SIG and H_P, M_s by four steps, 4000-row coarse grids,
-    SIMPLEC; in both the fluid inverse by two inner GMRES steps
+    Chebyshev(5) on H_SIG and H_P, M_s by five steps, 4000-row coarse grids,
+    strength threshold 0.04, SIMPLEC; in both the fluid inverse by two inner GMRES steps
     preconditioned by the block upper-triangular step."""
     if dim == 2:
         return dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG",), poly=("H_MS",), poly_degree=3, fluid_inner=2,
                     fluid_inner_pc="triangular", schur="simple")
-    return dict(max_coarse=4000, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=4, fluid_inner=2,
-                fluid_inner_pc="triangular", schur="simplec")
+    return dict(max_coarse=4000, strength0=0.04, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=5,
+                fluid_inner=2, fluid_inner_pc="triangular", schur="simplec")
 
 
 @pytest.mark.parametrize("name", ["c2", "m3"])
@@ -124,7 +124,8 @@ def test_fp32_preconditioner_in_the_benchmark_configuration(name):
     x32, _ = s.solve(b)
     s.close()
     assert np.array_equal(x32.cpu().numpy(), res["f32"][0])
-    H = precond.build_hierarchies(bs, max_coarse=opts["max_coarse"], schur=opts["schur"])
+    H = precond.build_hierarchies(bs, eps0=opts.get("strength0", 0.08), max_coarse=opts["max_coarse"],
+                                  schur=opts["schur"])
     P = precond.amg_preconditioner(bs, H, cheb={h: opts["cheb_degree"] for h in opts["cheb"]},
                                    poly={h: (opts["poly_degree"], 8.0) for h in opts["poly"]},
                                    fluid_inner=opts["fluid_inner"], fluid_inner_pc=opts["fluid_inner_pc"])
@@ -168,7 +169,8 @@ def test_fp32_apply_precond_vs_fp64_oracle(name, precision, bench):
     mc = 40 if name == "c1" else 2000
     opts = _bench_precond(sysm.dim) if bench else {}
     opts["max_coarse"] = mc
-    H = precond.build_hierarchies(bs, max_coarse=mc, schur=opts.get("schur", "simple"))
+    H = precond.build_hierarchies(bs, eps0=opts.get("strength0", 0.08), max_coarse=mc,
+                                  schur=opts.get("schur", "simple"))
     s = FsiSolver.from_system(sysm, device=0)
     s.build_precond(precision, **opts)
     import test_gpu_parity as tp

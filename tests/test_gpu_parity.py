@@ -440,13 +440,14 @@ def test_bench_configuration_full_size_matches_oracle():
     assert err <= 1e-6
 
 
-BENCH3D_OPTS = dict(max_coarse=4000, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=4,
-                   schur="simplec", fluid_inner=2, fluid_inner_pc="triangular")
+BENCH3D_OPTS = dict(max_coarse=4000, strength0=0.04, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",),
+                   poly_degree=5, schur="simplec", fluid_inner=2, fluid_inner_pc="triangular")
 
 
 def test_3d_bench_configuration_matches_oracle():
     """The 3D benchmark preconditioner (Chebyshev(5) V-cycles on H_SIG and H_P,
-    M_s by four Chebyshev steps, 4000-row coarse grids; grouped H_A levels;
+    M_s by five Chebyshev steps, 4000-row coarse grids, strength threshold
+    0.04; grouped H_A levels;
     the SIMPLEC pressure Schur approximation; the fluid inverse by two inner
     GMRES steps on F preconditioned by the block upper-triangular step) on the
     32x8x8-cell system: the GPU takes the oracle's iteration count to 1e-8,
@@ -462,8 +463,8 @@ def test_3d_bench_configuration_matches_oracle():
     s.close()
     xg = x.cpu().numpy()
     r = np.linalg.norm(sysm.b - bs.matvec(xg)) / np.linalg.norm(sysm.b)
-    H = precond.build_hierarchies(bs, max_coarse=4000, schur="simplec")
-    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 5, "H_P": 5}, poly={"H_MS": (4, 8.0)}, fluid_inner=2,
+    H = precond.build_hierarchies(bs, eps0=0.04, max_coarse=4000, schur="simplec")
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 5, "H_P": 5}, poly={"H_MS": (5, 8.0)}, fluid_inner=2,
                                    fluid_inner_pc="triangular")
     xo8, io8 = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-8, restart=50, maxit=500)
     xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
@@ -599,9 +600,9 @@ def test_apply_precond_parity_c3_benchmark_options(form):
     V-cycles on H_SIG and H_P, Jacobi V(1,1) on H_M and H_A (large levels in
     groups of three rows), M_s by three Chebyshev steps, 2000-row dense coarse
     grids, the Uzawa-like fluid step with SIMPLE.  "bench": the benchmark's
-    3D preconditioner (Chebyshev(5), four M_s steps, 4000-row coarse grids,
-    SIMPLEC, two inner GMRES steps on F with the triangular step; measured
-    3.7e-14)."""
+    3D preconditioner (Chebyshev(5), five M_s steps, 4000-row coarse grids,
+    strength threshold 0.04, SIMPLEC, two inner GMRES steps on F with the
+    triangular step)."""
     from oracle import blocks, precond
     from paper_1801_05648_amd import FsiSolver
     sysm = system("c3")
@@ -612,7 +613,8 @@ def test_apply_precond_parity_c3_benchmark_options(form):
     else:
         opts = dict(BENCH3D_OPTS)
         kw = dict(fluid_inner=2, fluid_inner_pc="triangular")
-    H = precond.build_hierarchies(bs, max_coarse=opts["max_coarse"], schur=opts.get("schur", "simple"))
+    H = precond.build_hierarchies(bs, eps0=opts.get("strength0", 0.08), max_coarse=opts["max_coarse"],
+                                  schur=opts.get("schur", "simple"))
     s = FsiSolver.from_system(sysm, device=0)
     s.build_precond("f64", **opts)
     _import_oracle_hierarchies(s, H)
