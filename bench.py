@@ -40,8 +40,8 @@ MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563, "c4": 15873201262}
 # --pmc-vcycle); see profiles/h_a_vcycle_hbm_traffic.md.
 # Keyed by workload: (traffic, the cycle's bytes as stored when measured); a
 # hierarchy of other bytes (other AMG options) has no figure.
-MEASURED_VCYCLE_TRAFFIC = {"c2": (129161151, 108663072), "c3": (1614689335, 1520085216),
-                           "c4": (12483874808, 11782010640)}
+MEASURED_VCYCLE_TRAFFIC = {"c2": (129161151, 108663072), "c3": (1356138742, 1279777388),
+                           "c4": (9589515807, 9096401408)}
 DTYPE = {"f64": "f64", "f32": "f64-krylov/f32-precond", "f32-bf16diag": "f64-krylov/f32-precond/bf16-diag"}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
