@@ -20,6 +20,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <exception>
 #include <memory>
 #include <mutex>
 #include <type_traits>
@@ -27,6 +28,7 @@
 #include <random>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/fsi.h"
@@ -2937,12 +2939,39 @@ void build_host_hierarchies(fsi_ctx& c, const fsi_precond_opts& o, const SaParam
     const ScaledProductFactory power = [&](const HCsr& X, const std::vector<double>& dv) {
       return device_scaled_product(X, dv, c.stream);
     };
-    for (int h = 0; h < FSI_NHIER; ++h) {
+    // H_A (by far the largest) on a host thread of its own while this thread
+    // sets up the other four; each setup is deterministic, so the hierarchies
+    // do not depend on the overlap
+    std::string msg[FSI_NHIER];
+    double ms[FSI_NHIER] = {};
+    long long rows[FSI_NHIER];
+    for (int h = 0; h < FSI_NHIER; ++h) rows[h] = (long long)ops[h]->nrows;
+    auto run = [&](int h) {
       PhaseTimer t("sa_setup");
-      const long long rows = (long long)ops[h]->nrows;
-      std::string m = sa_setup(std::move(*ops[h]), blocks[h], *Bs[h], ks[h], prm, hh[h], mul, power);
-      if (!m.empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + m);
-      log_line("SA setup %s: %.1f ms (%lld rows, %zu levels)", hn[h], t.ms(), rows, hh[h].levels.size());
+      msg[h] = sa_setup(std::move(*ops[h]), blocks[h], *Bs[h], ks[h], prm, hh[h], mul, power);
+      ms[h] = t.ms();
+    };
+    std::exception_ptr err_a, err_o;
+    std::thread ta([&] {
+      try {
+        HIP_TRY(hipSetDevice(c.device));  // the current device is per thread
+        run(FSI_H_A);
+      } catch (...) {
+        err_a = std::current_exception();
+      }
+    });
+    try {
+      for (int h = 0; h < FSI_NHIER; ++h)
+        if (h != FSI_H_A) run(h);
+    } catch (...) {
+      err_o = std::current_exception();
+    }
+    ta.join();
+    if (err_o) std::rethrow_exception(err_o);
+    if (err_a) std::rethrow_exception(err_a);
+    for (int h = 0; h < FSI_NHIER; ++h) {
+      if (!msg[h].empty()) throw Error(FSI_ERR_NUMERIC, std::string(hn[h]) + ": " + msg[h]);
+      log_line("SA setup %s: %.1f ms (%lld rows, %zu levels)", hn[h], ms[h], rows[h], hh[h].levels.size());
     }
     for (int h = 0; h < FSI_NHIER; ++h) c.host_h[h] = std::move(hh[h]);
     c.fluid_op = std::move(Xop);
