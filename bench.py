@@ -284,16 +284,16 @@ def precond_opts(args, dim: int) -> dict:
     # (64x16x16), Chebyshev(4) on H_P and M_s by Chebyshev steps, H_M and
     # H_SIG left to the Jacobi sweeps the network replaces
     learned2d = args.learned and dim == 2
-    # 3D solver: Chebyshev(5) sweeps, M_s by five Chebyshev steps, 4000-row
+    # 3D solver: Chebyshev(6) sweeps, M_s by five Chebyshev steps, 4000-row
     # coarse grids and the strength threshold 0.04 cut 64x16x16 from 26 to 15
-    # iterations (68.6 -> 36.7 ms) and 128x32x32 from 28 to 20 (466 -> 306 ms;
+    # iterations (68.6 -> 38 ms) and 128x32x32 from 28 to 17 (466 -> 268 ms;
     # the larger dense coarse inverses cost about a second of its build).  In
     # 3D two M_s steps raise the iterations from 46 to 78 (64x16x16, the split
     # fluid step); in 2D, with the inner fluid GMRES, three take 17/18/21
     # instead of 19/20/23 (11.5 vs 12.3 ms), and the 3D changes gain nothing
     # there (256x64: 11.4-11.7 ms)
     solver3d = dim == 3 and not args.learned
-    cheb = given("cheb", 0 if learned2d else 5 if solver3d else 4)
+    cheb = given("cheb", 0 if learned2d else 6 if solver3d else 4)
     max_coarse = given("max_coarse", 500 if learned2d else 4000 if solver3d else 2000)
     poly_on_s = given("poly_on", "" if learned2d else "H_MS")
     poly_degree = given("poly_degree", 5 if solver3d else 3)
@@ -425,7 +425,7 @@ def main():
                     help="skip the other preconditioner forms reported beside the headline solve")
     ap.add_argument("--cheb", type=int, default=None,
                     help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
-                         "default 5 in 3D, 4 in 2D, 0 with --learned in 2D")
+                         "default 6 in 3D, 4 in 2D, 0 with --learned in 2D")
     ap.add_argument("--max-coarse", type=int, default=None,
                     help="AMG: coarsest level size bound (dense inverse below it); default 4000 in 3D, 2000 in 2D, "
                          "500 with --learned in 2D")

@@ -81,7 +81,7 @@ __global__ __launch_bounds__(64) void spgemm_rows_kernel(const int32_t* __restri
         if (prev == j) break;
         h = (h + 1) & (kHash - 1);
       }
-      if (t == kHash) s_over = 1;  // table full: the row goes to the host
+      if (t == kHash) atomicOr(&s_over, 1);  // table full: the row goes to the host
     }
     __syncthreads();
     if (s_over || s_n > CAP) break;  // uniform: shared values after the barrier

@@ -86,13 +86,13 @@ def test_fp32_preconditioner_reaches_fp64_accuracy(name):
 def _bench_precond(dim):
     """The benchmarked preconditioner: in 2D Chebyshev(4) V-cycles on H_SIG,
     M_s by three Chebyshev steps, 2000-row coarse grids, SIMPLE; in 3D
-    Chebyshev(5) on H_SIG and H_P, M_s by five steps, 4000-row coarse grids,
+    Chebyshev(6) on H_SIG and H_P, M_s by five steps, 4000-row coarse grids,
     strength threshold 0.04, SIMPLEC; in both the fluid inverse by two inner GMRES steps
     preconditioned by the block upper-triangular step."""
     if dim == 2:
         return dict(max_coarse=2000, cheb_degree=4, cheb=("H_SIG",), poly=("H_MS",), poly_degree=3, fluid_inner=2,
                     fluid_inner_pc="triangular", schur="simple")
-    return dict(max_coarse=4000, strength0=0.04, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=5,
+    return dict(max_coarse=4000, strength0=0.04, cheb_degree=6, cheb=("H_SIG", "H_P"), poly=("H_MS",), poly_degree=5,
                 fluid_inner=2, fluid_inner_pc="triangular", schur="simplec")
 
 

@@ -440,12 +440,12 @@ def test_bench_configuration_full_size_matches_oracle():
     assert err <= 1e-6
 
 
-BENCH3D_OPTS = dict(max_coarse=4000, strength0=0.04, cheb_degree=5, cheb=("H_SIG", "H_P"), poly=("H_MS",),
+BENCH3D_OPTS = dict(max_coarse=4000, strength0=0.04, cheb_degree=6, cheb=("H_SIG", "H_P"), poly=("H_MS",),
                    poly_degree=5, schur="simplec", fluid_inner=2, fluid_inner_pc="triangular")
 
 
 def test_3d_bench_configuration_matches_oracle():
-    """The 3D benchmark preconditioner (Chebyshev(5) V-cycles on H_SIG and H_P,
+    """The 3D benchmark preconditioner (Chebyshev(6) V-cycles on H_SIG and H_P,
     M_s by five Chebyshev steps, 4000-row coarse grids, strength threshold
     0.04; grouped H_A levels;
     the SIMPLEC pressure Schur approximation; the fluid inverse by two inner
@@ -464,7 +464,7 @@ def test_3d_bench_configuration_matches_oracle():
     xg = x.cpu().numpy()
     r = np.linalg.norm(sysm.b - bs.matvec(xg)) / np.linalg.norm(sysm.b)
     H = precond.build_hierarchies(bs, eps0=0.04, max_coarse=4000, schur="simplec")
-    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 5, "H_P": 5}, poly={"H_MS": (5, 8.0)}, fluid_inner=2,
+    P = precond.amg_preconditioner(bs, H, cheb={"H_SIG": 6, "H_P": 6}, poly={"H_MS": (5, 8.0)}, fluid_inner=2,
                                    fluid_inner_pc="triangular")
     xo8, io8 = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-8, restart=50, maxit=500)
     xo, _ = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
@@ -600,7 +600,7 @@ def test_apply_precond_parity_c3_benchmark_options(form):
     V-cycles on H_SIG and H_P, Jacobi V(1,1) on H_M and H_A (large levels in
     groups of three rows), M_s by three Chebyshev steps, 2000-row dense coarse
     grids, the Uzawa-like fluid step with SIMPLE.  "bench": the benchmark's
-    3D preconditioner (Chebyshev(5), five M_s steps, 4000-row coarse grids,
+    3D preconditioner (Chebyshev(6), five M_s steps, 4000-row coarse grids,
     strength threshold 0.04, SIMPLEC, two inner GMRES steps on F with the
     triangular step)."""
     from oracle import blocks, precond
