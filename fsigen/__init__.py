@@ -159,6 +159,7 @@ def _load():
         lib.fsigen_nodes.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 5
         lib.fsigen_jrange.argtypes = [ctypes.c_void_p, P(ctypes.c_double)]
         lib.fsigen_free.argtypes = [ctypes.c_void_p]
+        lib.fsigen_fe_data.argtypes = [ctypes.c_void_p] * 11
         lib.fsigen_residual.argtypes = [P(_Cfg), ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p,
                                         ctypes.c_int64, ctypes.c_char_p, ctypes.c_int]
         lib.fsigen_residual.restype = ctypes.c_int
@@ -203,6 +204,7 @@ class FsiSystem:
     dof_node: np.ndarray    # (N,) node id of every dof
     dof_comp: np.ndarray    # (N,) vector component of every dof (0 for p)
     j_range: tuple
+    fe: dict = None         # finite-element description (generate(..., fe=True)), see FE_FIELDS
 
     @property
     def N(self) -> int:
@@ -221,8 +223,21 @@ class FsiSystem:
         return (0, self.n_m, self.n_m + self.n_s, self.N)
 
 
-def generate(name_or_cfg, seed: int = 0, t_phase: float = 0.0) -> FsiSystem:
-    """Assemble the seeded system for a configuration (name or Config)."""
+# Finite-element description of a workload (node arrays on the Q2 lattice,
+# nodes numbered row-major with axis 0 slowest): first velocity dof, first
+# displacement dof and pressure dof of every node (-1: none), the linearisation
+# state v, u, p (also the Dirichlet data on constrained dofs), the previous time
+# level v_old, u_old, the advecting velocity w of the convective term and the
+# displacement u_fz whose Jacobian determinant scales the mesh stiffness.
+FE_FIELDS = ("vdof", "udof", "pdof", "v", "u", "p", "v_old", "u_old", "w", "u_fz")
+
+
+def generate(name_or_cfg, seed: int = 0, t_phase: float = 0.0, fe: bool = False) -> FsiSystem:
+    """Assemble the seeded system for a configuration (name or Config).
+
+    With ``fe`` the system also carries its finite-element description
+    (``FsiSystem.fe``, keys FE_FIELDS), for assembling residual and Jacobian
+    elsewhere."""
     cfg = config(name_or_cfg) if isinstance(name_or_cfg, str) else name_or_cfg
     lib = _load()
     c = _ccfg(cfg, seed, t_phase)
@@ -256,10 +271,17 @@ def generate(name_or_cfg, seed: int = 0, t_phase: float = 0.0) -> FsiSystem:
                          dof_node.ctypes.data, dof_comp.ctypes.data)
         jr = (ctypes.c_double * 2)()
         lib.fsigen_jrange(h, jr)
+        fed = None
+        if fe:
+            fed = {k: np.empty(nnodes, np.int64) for k in ("vdof", "udof", "pdof")}
+            fed["p"] = np.empty(nnodes, np.float64)
+            for k in ("v", "u", "v_old", "u_old", "w", "u_fz"):
+                fed[k] = np.empty((nnodes, dim), np.float64)
+            lib.fsigen_fe_data(h, *(fed[k].ctypes.data for k in FE_FIELDS))
     finally:
         lib.fsigen_free(h)
     return FsiSystem(cfg, seed, t_phase, dim, n_m, n_s, n_f, n_vs, n_vf, n_p, blocks, b,
-                     coords, ijk, flags, dof_node, dof_comp, (jr[0], jr[1]))
+                     coords, ijk, flags, dof_node, dof_comp, (jr[0], jr[1]), fed)
 
 
 def residual(name_or_cfg, seed: int, direction: np.ndarray, eps: float, t_phase: float = 0.0) -> np.ndarray:

@@ -975,6 +975,30 @@ void fsigen_nodes(const fsigen_handle* h, double* coords, int32_t* ijk, uint8_t*
   }
 }
 void fsigen_jrange(const fsigen_handle* h, double* jr) { jr[0] = h->g.min_J; jr[1] = h->g.max_J; }
+// Finite-element description of the workload, for assembling it elsewhere:
+// first dof of each node's velocity / displacement and its pressure dof (-1:
+// none, i.e. Dirichlet or absent), and the nodal fields at Q2 nodes
+// (component-interleaved): the linearisation state v, u, p (also the Dirichlet
+// data), the previous time level v_old, u_old, the advecting velocity w of the
+// convective term and the displacement u_fz whose Jacobian scales the mesh
+// stiffness.
+void fsigen_fe_data(const fsigen_handle* h, int64_t* vdof, int64_t* udof, int64_t* pdof, double* v, double* u,
+                    double* p, double* v_old, double* u_old, double* w, double* u_fz) {
+  const Gen& g = h->g;
+  const int64_t nd = g.nnodes * g.D;
+  std::memcpy(vdof, g.vdof.data(), sizeof(int64_t) * g.nnodes);
+  std::memcpy(udof, g.udof.data(), sizeof(int64_t) * g.nnodes);
+  std::memcpy(pdof, g.pdof.data(), sizeof(int64_t) * g.nnodes);
+  for (int64_t i = 0; i < nd; ++i) {
+    v[i] = g.vbar[i];
+    u[i] = g.ubar[i];
+    v_old[i] = 0.9 * g.vbar[i];
+    u_old[i] = 0.9 * g.ubar[i];
+    w[i] = g.vbar[i];
+    u_fz[i] = g.ubar[i];
+  }
+  std::memcpy(p, g.pbar.data(), sizeof(double) * g.nnodes);
+}
 void fsigen_free(fsigen_handle* h) { delete h; }
 
 // Residual R(U_bar + eps * dU) on the free dofs, frozen fields held at U_bar
