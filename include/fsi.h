@@ -400,6 +400,106 @@ fsi_status fsi_mlp_collect(fsi_ctx* ctx, int max_vectors, int every);
  * initial weights are an input).  opts/info may be NULL. */
 fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_train_info* info);
 
+/* ------------------------------------------------------------------------
+ * Finite-element assembly and the quasi-Newton loop.
+ *
+ * Section 3: the discrete residual R(U) = A(U)(Phi) - F(Phi) of the monolithic
+ * ALE-FSI problem (the sum of the variational equations, equation fsi:all,
+ * one step of the one-step-theta scheme with theta = 1) on the structured
+ * channel of Q2 velocity / displacement and Q1 pressure quads (d = 2) or hexes
+ * (d = 3), every integral by the tensor 3-point Gauss rule, the outflow term
+ * on the face x_0 = extent[0]; and its Jacobian A'(U), the matrix of the
+ * Newton step (Algorithm newton of Section 3.3).  The unknowns are numbered as
+ * the system of fsi_setup_blocks (mesh | solid v, u | fluid v | p); a state is
+ * the given node fields plus an offset dU on the free dofs (constrained dofs
+ * hold the given values).  The advecting velocity w of the convective term,
+ * v_old, u_old and the displacement u_fz whose det(I + grad u_fz) scales the
+ * mesh stiffness are given fields (with newton_mesh the stiffness uses the
+ * current J instead).  Mesh-equation test functions vanish on nodes of solid
+ * cells (the interface), velocity test functions on Dirichlet nodes.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+  int32_t dim;                 /* 2 or 3: the system's d                                   */
+  int32_t cells[3];            /* cells per axis (1..65535; unused axes ignored)          */
+  double extent[3];            /* channel lengths                                          */
+  int32_t solid_lo[3];         /* solid cells: solid_lo[a] <= C[a] < solid_hi[a], all a    */
+  int32_t solid_hi[3];
+  double rho_f, nu_f, rho_s, mu_s, lambda_s;  /* fluid density, viscosity; solid density, Lame */
+  double dt, theta;            /* theta must be 1; dt * theta must equal the layout's      */
+  int32_t newton_mesh;         /* 1: 1/J of the mesh equation from the current state       */
+  int32_t pad;
+  int64_t n_nodes;             /* prod_a (2 cells[a] + 1): the Q2 lattice, row-major,
+                                  axis 0 slowest                                           */
+  /* host arrays of n_nodes entries: first velocity dof, first displacement dof
+   * (components follow) and pressure dof of each node, -1 where none (Dirichlet
+   * node, or no such field there); every free dof must appear exactly once */
+  const int64_t* vdof;
+  const int64_t* udof;
+  const int64_t* pdof;
+  /* host node fields, d values per node (component-interleaved), p: one */
+  const double* v;
+  const double* u;
+  const double* p;
+  const double* v_old;
+  const double* u_old;
+  const double* w;
+  const double* u_fz;
+} fsi_fe_mesh;
+
+#define FSI_NEWTON_MAX 64
+enum {
+  FSI_NEWTON_PC_REBUILD = 0, /* on reassembly: a new preconditioner (new SA hierarchies)   */
+  FSI_NEWTON_PC_REUSE = 1,   /* on reassembly: new preconditioner, SA hierarchies kept      */
+  FSI_NEWTON_PC_KEEP = 2     /* the preconditioner of the last fsi_build_precond throughout */
+};
+
+typedef struct {
+  double rtol;              /* stop once ||r_k||_inf < rtol ||r_0||_inf (1e-6, Section 6)   */
+  double reassemble_ratio;  /* reassemble when ||r_k||_inf > ratio ||r_{k-1}||_inf (0.1)     */
+  int32_t max_steps;        /* Newton steps, at most FSI_NEWTON_MAX (25)                     */
+  int32_t precond;          /* FSI_NEWTON_PC_* (REBUILD)                                     */
+  double lin_tol;           /* FGMRES relative residual per step (1e-3, Section 6)          */
+  int32_t restart, maxit;   /* FGMRES(restart), at most maxit iterations per step (50, 2000) */
+} fsi_newton_opts;
+
+typedef struct {
+  int32_t converged, steps, reassemblies, lin_iters_total;
+  double resid[FSI_NEWTON_MAX + 1];      /* ||r_k||_inf, k = 0 .. steps                     */
+  int32_t reassembled[FSI_NEWTON_MAX];   /* step k assembled A'(U_k)                         */
+  int32_t lin_iters[FSI_NEWTON_MAX];     /* FGMRES iterations of step k                      */
+  double t_assemble_ms, t_precond_ms, t_solve_ms, t_total_ms;
+} fsi_newton_info;
+
+void fsi_default_newton_opts(fsi_newton_opts* o);
+
+/* Upload the finite-element description of the system in the context (after
+ * fsi_setup_blocks; a new system drops it).  Checks the sizes, the dof maps
+ * against N and the fields for NaN/Inf.  Host arrays; copied. */
+fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* mesh);
+
+/* R = R(U) of Section 3 at U = given fields + dU.  dU: device, length N, or
+ * NULL (dU = 0); R: device, length N.  FSI_ERR_NUMERIC when J <= 0 at a
+ * quadrature point of a fluid cell or a value is not finite. */
+fsi_status fsi_fe_residual(fsi_ctx* ctx, const double* dU, double* R);
+
+/* A'(U) assembled into the context's A_h in place (its stored layout; the
+ * sparsity pattern of fsi_setup_blocks must hold every cell matrix entry,
+ * else FSI_ERR_STRUCT): fsi_spmv and fsi_solve use it at once.  With
+ * host_blocks the host copies of the eight blocks take the new values too
+ * (checked as by fsi_setup_blocks), so that fsi_build_precond builds from
+ * them; else the preconditioner's blocks keep their values.  dU as above. */
+fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks);
+
+/* Algorithm newton with Section 6's quasi-Newton scheme: r_k = R(U_k) on the
+ * device; stop once ||r_k||_inf < rtol ||r_0||_inf; at k = 0, and whenever
+ * ||r_k||_inf > ratio ||r_{k-1}||_inf, assemble A'(U_k) (and, unless
+ * FSI_NEWTON_PC_KEEP, rebuild the preconditioner with the options of the last
+ * fsi_build_precond, or the defaults); solve A' delta = r_k by FGMRES to
+ * lin_tol; U_{k+1} = U_k - delta.  dU: device, length N: the initial offset
+ * on entry, the last iterate's on return.  FSI_NOT_CONVERGED after max_steps
+ * steps.  opts/info may be NULL. */
+fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi_newton_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -208,10 +208,12 @@ class FeProblem:
         return v, u, p
 
     # ------------------------------------------------------------ cell forms
-    def cell_residual(self, v, u, p):
-        """Local residual of every cell, (cells, nloc), all local test functions."""
+    def cell_residual(self, v, u, p, sel=slice(None)):
+        """Local residual of every cell (or of cells[sel]), (cells, nloc), all
+        local test functions."""
         m, D = self.mat, self.D
         fe = self.fe
+        nodes, solid, outflow = self.nodes[sel], self.solid[sel], self.outflow[sel]
         S = self.vol
         N, dN, M, w = S["N"], S["dN"], S["M"], S["w"]
         I = np.eye(D)
@@ -220,10 +222,10 @@ class FeProblem:
         Gv = np.einsum("qlk,cld->cqdk", dN, v)
         Gu = np.einsum("qlk,cld->cqdk", dN, u)
         pq = np.einsum("ql,cl->cq", M, p)
-        wq = np.einsum("ql,cld->cqd", N, fe["w"][self.nodes])
-        vo = np.einsum("ql,cld->cqd", N, fe["v_old"][self.nodes])
-        uo = np.einsum("ql,cld->cqd", N, fe["u_old"][self.nodes])
-        Gz = np.einsum("qlk,cld->cqdk", dN, fe["u_fz"][self.nodes])
+        wq = np.einsum("ql,cld->cqd", N, fe["w"][nodes])
+        vo = np.einsum("ql,cld->cqd", N, fe["v_old"][nodes])
+        uo = np.einsum("ql,cld->cqd", N, fe["u_old"][nodes])
+        Gz = np.einsum("qlk,cld->cqdk", dN, fe["u_fz"][nodes])
         F = I + Gu
         J = _det(F)
         Fi = _inv(F, J)
@@ -244,7 +246,7 @@ class FeProblem:
         gV_s = m.dt_theta * _mm(F, Ss)
         fV_s = m.rho_s * (vq - vo)
         fU_s = (uq - uo) - m.dt_theta * vq
-        sol = self.solid[:, None]
+        sol = solid[:, None]
         fV = np.where(sol[..., None], fV_s, fV_f)
         gV = np.where(sol[..., None, None], gV_s, gV_f)
         fU = np.where(sol[..., None], fU_s, 0.0)
@@ -254,7 +256,7 @@ class FeProblem:
         Ru = np.einsum("q,cqd,ql->cld", w, fU, N) + np.einsum("q,cqdk,qlk->cld", w, gU, dN)
         Rp = np.einsum("q,cq,ql->cl", w, fP, M)
         # outflow face (normal e_0) of the fluid cells at x = L
-        out = np.nonzero(self.outflow)[0]
+        out = np.nonzero(outflow)[0]
         if len(out):
             Sf = self.face
             Nf, dNf, wf = Sf["N"], Sf["dN"], Sf["w"]
@@ -280,11 +282,13 @@ class FeProblem:
         np.add.at(R, self.gd[self.test], Rl[self.test])
         return R
 
-    def cell_jacobians(self, dU=None) -> np.ndarray:
-        """d R_cell / d U_cell of every cell, (cells, nloc, nloc), by complex steps."""
-        v, u, p = self.local_state(dU)
+    def cell_jacobians(self, dU=None, cells=None) -> np.ndarray:
+        """d R_cell / d U_cell of every cell (or of the listed cells), (cells,
+        nloc, nloc), by complex steps."""
+        sel = slice(None) if cells is None else np.asarray(cells)
+        v, u, p = (a[sel] for a in self.local_state(dU))
         NV, D = self.NV, self.D
-        K = np.zeros((self.ncells, self.nloc, self.nloc))
+        K = np.zeros((v.shape[0], self.nloc, self.nloc))
         for s in range(self.nloc):
             vc, uc, pc = v.astype(complex), u.astype(complex), p.astype(complex)
             if s < NV:
@@ -293,18 +297,32 @@ class FeProblem:
                 uc[:, (s - NV) // D, (s - NV) % D] += 1j * CS_STEP
             else:
                 pc[:, s - 2 * NV] += 1j * CS_STEP
-            K[:, :, s] = self.cell_residual(vc, uc, pc).imag / CS_STEP
+            K[:, :, s] = self.cell_residual(vc, uc, pc, sel).imag / CS_STEP
         return K
 
-    def jacobian(self, dU=None) -> sp.csr_matrix:
-        """A'(U) over the free dofs, rows = tested equations, columns = free dofs."""
-        K = self.cell_jacobians(dU)
-        rows = np.broadcast_to(self.gd[:, :, None], K.shape)
-        cols = np.broadcast_to(self.gd[:, None, :], K.shape)
-        keep = self.test[:, :, None] & (self.gd[:, None, :] >= 0)
+    def jacobian(self, dU=None, cells=None) -> sp.csr_matrix:
+        """A'(U) over the free dofs, rows = tested equations, columns = free
+        dofs; with `cells` only their contributions (complete in the rows
+        that rows_covered(cells) lists)."""
+        K = self.cell_jacobians(dU, cells)
+        sel = slice(None) if cells is None else np.asarray(cells)
+        gd, test = self.gd[sel], self.test[sel]
+        rows = np.broadcast_to(gd[:, :, None], K.shape)
+        cols = np.broadcast_to(gd[:, None, :], K.shape)
+        keep = test[:, :, None] & (gd[:, None, :] >= 0)
         A = sp.coo_matrix((K[keep], (rows[keep], cols[keep])), shape=(self.N, self.N)).tocsr()
         A.sum_duplicates()
         return A
+
+
+def rows_covered(prob: FeProblem, cells) -> np.ndarray:
+    """Rows (tested equations) all of whose cell contributions come from `cells`."""
+    total = np.zeros(prob.N, np.int64)
+    np.add.at(total, prob.gd[prob.test], 1)
+    part = np.zeros(prob.N, np.int64)
+    sel = np.asarray(cells)
+    np.add.at(part, prob.gd[sel][prob.test[sel]], 1)
+    return np.nonzero((total > 0) & (part == total))[0]
 
 
 def max_norm(r) -> float:

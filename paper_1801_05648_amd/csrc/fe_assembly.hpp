@@ -1,0 +1,578 @@
+// Finite-element assembly of the ALE-FSI residual and Jacobian on the GPU.
+//
+// The residual is the semi-linear form A(U)(Phi) minus the linear form F(Phi)
+// of Section 3 (the sum of the variational equations, equation fsi:all, with
+// theta = 1) on a structured channel of Q2 (velocity, displacement) / Q1
+// (pressure) quads or hexes; the Jacobian is its derivative A'(U), the matrix
+// of the Newton step (Algorithm newton).  Per quadrature point the integrand
+// maps the local field values q = (v, grad v, u, grad u, p) to outputs
+// (f_v, g_v, f_u, g_u, f_p), and a test function phi of field X, component c
+// receives f_X[c] phi + sum_k g_X[c][k] d_k phi.  The derivative d out / d q
+// (the derivatives of F, J, F^{-1} of Section 3.3's derivative theorem enter
+// through it) is evaluated by forward-mode dual numbers with one direction
+// per thread: thread i of the workgroup seeds q_i.
+//
+// Launch: one workgroup of 256 threads per (cell, chunk of 32 local test
+// rows); the cells of one launch share one parity class per axis (2^d
+// launches), so no two cells of a launch share a node and every row is
+// written by one workgroup: plain read-add-write, deterministic.  A thread
+// owns one test row t and the trial columns s = lane + 8 j of the cell matrix
+// in registers across the quadrature loop; the per-point tables (shape
+// values, d out / d q, and DB[s][o] = sum over the inputs of trial s of
+// d out_o / d q_i times its basis value) sit in LDS.  The cell matrix entries
+// are added into the stored A_h (its row segments and row groups) at the
+// position of (global row, global column), found by binary search in the
+// row's sorted column list.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fsi {
+
+struct FeParams {
+  int D;
+  int nc[3];       // cells per axis
+  int NN[3];       // Q2 lattice nodes per axis (2 nc + 1)
+  double h[3];     // cell size per axis
+  int solid_lo[3], solid_hi[3];  // solid cells: solid_lo <= C < solid_hi on every axis
+  double rho_f, nu_f, rho_s, mu_s, lambda_s, dtth;
+  int newton_mesh;  // 1: the mesh stiffness 1/J uses the current J (else the given u_fz's)
+};
+
+struct FeNodes {   // per Q2 lattice node (row-major, axis 0 slowest)
+  const int64_t* vdof;  // first velocity dof or -1
+  const int64_t* udof;  // first displacement dof or -1
+  const int64_t* pdof;  // pressure dof or -1
+  const double* v;      // state fields (D per node; p: 1)
+  const double* u;
+  const double* p;
+  const double* v_old;  // previous time level
+  const double* u_old;
+  const double* w;      // advecting velocity of the convective term
+  const double* u_fz;   // displacement whose J scales the mesh stiffness
+};
+
+// Positions in the stored A_h: rows in up to four segments, each plain CSR
+// (row pointers into ci/val, rows of grouped segments empty) or in groups of
+// grp rows sharing one sorted column list (values grp per entry).
+struct AhSlots {
+  int nseg;
+  int64_t row0[5];
+  int grp[4];
+  const int64_t* rp;
+  const int32_t* ci;
+  double* val;
+  const int64_t* grp_rp[4];
+  const int32_t* grp_ci[4];
+  double* grp_val[4];
+};
+
+__device__ __forceinline__ double* ah_slot(const AhSlots& a, int64_t row, int32_t col) {
+  int q = 0;
+  while (q + 1 < a.nseg && row >= a.row0[q + 1]) ++q;
+  const int32_t* ci;
+  int64_t lo, end;
+  double* base;
+  int stride = 1, off = 0;
+  if (a.grp[q] <= 1) {
+    lo = a.rp[row];
+    end = a.rp[row + 1];
+    ci = a.ci;
+    base = a.val;
+  } else {
+    const int g = a.grp[q];
+    const int64_t lr = row - a.row0[q];
+    const int64_t gi = lr / g;
+    lo = a.grp_rp[q][gi];
+    end = a.grp_rp[q][gi + 1];
+    ci = a.grp_ci[q];
+    base = a.grp_val[q];
+    stride = g;
+    off = int(lr - gi * g);
+  }
+  int64_t hi = end;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (ci[mid] < col) lo = mid + 1;
+    else hi = mid;
+  }
+  if (lo < end && ci[lo] == col) return base + lo * stride + off;
+  return nullptr;
+}
+
+// A value with one directional derivative.
+struct Dn {
+  double v, d;
+};
+__device__ __forceinline__ Dn dn(double c) { return Dn{c, 0.0}; }
+__device__ __forceinline__ Dn operator+(Dn a, Dn b) { return Dn{a.v + b.v, a.d + b.d}; }
+__device__ __forceinline__ Dn operator-(Dn a, Dn b) { return Dn{a.v - b.v, a.d - b.d}; }
+__device__ __forceinline__ Dn operator*(Dn a, Dn b) { return Dn{a.v * b.v, a.d * b.v + a.v * b.d}; }
+__device__ __forceinline__ Dn operator*(double s, Dn a) { return Dn{s * a.v, s * a.d}; }
+__device__ __forceinline__ Dn operator/(Dn a, Dn b) {
+  const double r = 1.0 / b.v;
+  return Dn{a.v * r, (a.d - a.v * r * b.d) * r};
+}
+__device__ __forceinline__ Dn operator+(Dn a, double s) { return Dn{a.v + s, a.d}; }
+__device__ __forceinline__ Dn operator-(Dn a, double s) { return Dn{a.v - s, a.d}; }
+
+template <int D> struct FeDims {
+  static constexpr int NQ2 = D == 2 ? 9 : 27;   // Q2 nodes of a cell
+  static constexpr int NQ1 = D == 2 ? 4 : 8;    // Q1 vertices
+  static constexpr int NV = NQ2 * D;            // velocity (or displacement) dofs of a cell
+  static constexpr int NLOC = 2 * NV + NQ1;     // local dofs: v | u | p
+  static constexpr int QV = 0, QGV = D, QU = D + D * D, QGU = 2 * D + D * D, QP = 2 * D + 2 * D * D;
+  static constexpr int NQ = QP + 1;             // integrand inputs (= outputs)
+  static constexpr int NVOL = NQ2, NFACE = D == 2 ? 3 : 9;
+  static constexpr int RT = 32, SL = 8;         // test rows per workgroup, trial lanes per row
+  static constexpr int NCHUNK = (NLOC + RT - 1) / RT;
+  static constexpr int NJ = (NLOC + SL - 1) / SL;
+  static constexpr int NFR = 3 * D + D * D;     // interpolated given fields: w, v_old, u_old, grad u_fz
+};
+
+template <int D>
+__device__ __forceinline__ Dn det_d(const Dn (&F)[D][D]) {
+  if constexpr (D == 2) {
+    return F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  } else {
+    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  }
+}
+
+// G = F^{-1} by cofactors.
+template <int D>
+__device__ __forceinline__ void inv_d(const Dn (&F)[D][D], Dn J, Dn (&G)[D][D]) {
+  if constexpr (D == 2) {
+    G[0][0] = F[1][1] / J;
+    G[0][1] = dn(0.0) - F[0][1] / J;
+    G[1][0] = dn(0.0) - F[1][0] / J;
+    G[1][1] = F[0][0] / J;
+  } else {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        // cofactor of F[j][i]: rows != j, columns != i
+        const int r0 = j == 0 ? 1 : 0, r1 = j == 2 ? 1 : 2;
+        const int c0 = i == 0 ? 1 : 0, c1 = i == 2 ? 1 : 2;
+        const Dn m = F[r0][c0] * F[r1][c1] - F[r0][c1] * F[r1][c0];
+        G[i][j] = ((i + j) % 2 == 0 ? m : dn(0.0) - m) / J;
+      }
+  }
+}
+
+// The integrand at one quadrature point.  kind: 0 fluid cell, 1 solid cell,
+// 2 outflow face (normal e_0).  fr: w[D] | v_old[D] | u_old[D] | grad u_fz[D][D].
+template <int D>
+__device__ void fe_integrand(int kind, const Dn* q, const double* fr, const FeParams& P, Dn* out) {
+  using Q = FeDims<D>;
+  for (int o = 0; o < Q::NQ; ++o) out[o] = dn(0.0);
+  Dn F[D][D], Fi[D][D];
+  for (int c = 0; c < D; ++c)
+    for (int k = 0; k < D; ++k) F[c][k] = q[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
+  const Dn J = det_d<D>(F);
+  if (kind == 1) {
+    // St. Venant-Kirchhoff: F S with S = 2 mu E + lambda tr(E) I
+    Dn E[D][D];
+    for (int c = 0; c < D; ++c)
+      for (int k = 0; k < D; ++k) {
+        Dn s = F[0][c] * F[0][k];
+        for (int m = 1; m < D; ++m) s = s + F[m][c] * F[m][k];
+        E[c][k] = 0.5 * (s - (c == k ? 1.0 : 0.0));
+      }
+    Dn tr = E[0][0];
+    for (int c = 1; c < D; ++c) tr = tr + E[c][c];
+    Dn S[D][D];
+    for (int c = 0; c < D; ++c)
+      for (int k = 0; k < D; ++k) {
+        S[c][k] = (2.0 * P.mu_s) * E[c][k];
+        if (c == k) S[c][k] = S[c][k] + P.lambda_s * tr;
+      }
+    for (int c = 0; c < D; ++c) {
+      for (int k = 0; k < D; ++k) {
+        Dn s = F[c][0] * S[0][k];
+        for (int m = 1; m < D; ++m) s = s + F[c][m] * S[m][k];
+        out[Q::QGV + c * D + k] = P.dtth * s;
+      }
+      out[Q::QV + c] = P.rho_s * (q[Q::QV + c] - fr[D + c]);
+      out[Q::QU + c] = (q[Q::QU + c] - fr[2 * D + c]) - P.dtth * q[Q::QV + c];
+    }
+    return;
+  }
+  inv_d<D>(F, J, Fi);
+  if (kind == 2) {
+    // -dt theta rho nu J F^{-T} grad v^T F^{-T} e_0
+    Dn a[D], b[D];
+    for (int m = 0; m < D; ++m) a[m] = Fi[0][m];
+    for (int k = 0; k < D; ++k) {
+      Dn s = q[Q::QGV + 0 * D + k] * a[0];
+      for (int m = 1; m < D; ++m) s = s + q[Q::QGV + m * D + k] * a[m];
+      b[k] = s;
+    }
+    const double coef = -P.dtth * P.rho_f * P.nu_f;
+    for (int c = 0; c < D; ++c) {
+      Dn s = Fi[0][c] * b[0];
+      for (int k = 1; k < D; ++k) s = s + Fi[k][c] * b[k];
+      out[Q::QV + c] = coef * (J * s);
+    }
+    return;
+  }
+  // fluid: ALE momentum, incompressibility, mesh motion
+  Dn GF[D][D];  // grad v F^{-1}
+  for (int c = 0; c < D; ++c)
+    for (int k = 0; k < D; ++k) {
+      Dn s = q[Q::QGV + c * D + 0] * Fi[0][k];
+      for (int m = 1; m < D; ++m) s = s + q[Q::QGV + c * D + m] * Fi[m][k];
+      GF[c][k] = s;
+    }
+  const double rho = P.rho_f, mu = P.rho_f * P.nu_f;
+  for (int c = 0; c < D; ++c) {
+    Dn adv = GF[c][0] * dn(fr[0]);
+    Dn mv = GF[c][0] * (q[Q::QU + 0] - fr[2 * D + 0]);
+    for (int k = 1; k < D; ++k) {
+      adv = adv + GF[c][k] * dn(fr[k]);
+      mv = mv + GF[c][k] * (q[Q::QU + k] - fr[2 * D + k]);
+    }
+    out[Q::QV + c] = rho * (J * (q[Q::QV + c] - fr[D + c])) + (P.dtth * rho) * (J * adv) - rho * (J * mv);
+    for (int k = 0; k < D; ++k) {
+      Dn s = (GF[c][0] + GF[0][c]) * Fi[k][0];
+      for (int m = 1; m < D; ++m) s = s + (GF[c][m] + GF[m][c]) * Fi[k][m];
+      out[Q::QGV + c * D + k] = (P.dtth * mu) * (J * s) - J * (q[Q::QP] * Fi[k][c]);
+    }
+  }
+  Dn tr = GF[0][0];
+  for (int c = 1; c < D; ++c) tr = tr + GF[c][c];
+  out[Q::QP] = J * tr;
+  Dn Jm;
+  if (P.newton_mesh) {
+    Jm = J;
+  } else {
+    Dn Fz[D][D];
+    for (int c = 0; c < D; ++c)
+      for (int k = 0; k < D; ++k) Fz[c][k] = dn(fr[3 * D + c * D + k] + (c == k ? 1.0 : 0.0));
+    Jm = det_d<D>(Fz);
+  }
+  for (int c = 0; c < D; ++c)
+    for (int k = 0; k < D; ++k) out[Q::QGU + c * D + k] = q[Q::QGU + c * D + k] / Jm;
+}
+
+__device__ __forceinline__ void q2_basis(double x, double* n, double* dn1) {
+  n[0] = (2.0 * x - 1.0) * (x - 1.0);
+  n[1] = 4.0 * x * (1.0 - x);
+  n[2] = x * (2.0 * x - 1.0);
+  dn1[0] = 4.0 * x - 3.0;
+  dn1[1] = 4.0 - 8.0 * x;
+  dn1[2] = 4.0 * x - 1.0;
+}
+
+// flag bits: 1 J <= 0 (current or mesh-stiffness), 2 a cell entry outside
+// the stored pattern, 4 a non-finite residual or matrix value.
+template <int D>
+__global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd, const double* __restrict__ dU,
+                                                          int color, int want_res, int want_mat,
+                                                          double* __restrict__ R, AhSlots ah, int* flag) {
+  using Q = FeDims<D>;
+  constexpr int NQ2 = Q::NQ2, NQ1 = Q::NQ1, NV = Q::NV, NLOC = Q::NLOC, NQ = Q::NQ;
+  __shared__ double s_f[7 * NV + NQ1];  // v | u | w | v_old | u_old | u_fz (node-major, comp) | p
+  __shared__ int64_t s_gd[NLOC];
+  __shared__ unsigned char s_ton[NLOC];
+  __shared__ double s_N[NQ2], s_dN[NQ2 * D], s_M[NQ1];
+  __shared__ double s_q[NQ + Q::NFR];
+  __shared__ double s_Dm[NQ * NQ];  // s_Dm[o * NQ + i] = d out_o / d q_i
+  __shared__ double s_ov[NQ];
+  __shared__ double s_DB[NLOC * NQ];
+  __shared__ int s_cellflag;
+  const int tid = threadIdx.x;
+  // the cell of this workgroup within its parity class
+  int C[3] = {0, 0, 0};
+  {
+    int64_t r = blockIdx.x;
+    for (int a = D - 1; a >= 0; --a) {
+      const int bit = (color >> a) & 1;
+      const int m = (P.nc[a] - bit + 1) / 2;
+      C[a] = 2 * int(r % m) + bit;
+      r /= m;
+    }
+  }
+  bool solid = true;
+  for (int a = 0; a < D; ++a) solid = solid && C[a] >= P.solid_lo[a] && C[a] < P.solid_hi[a];
+  const bool outflow = !solid && C[0] == P.nc[0] - 1;
+  const int t0 = blockIdx.y * Q::RT;
+  auto node_of = [&](const int* off) {
+    int64_t id = 0;
+    for (int a = 0; a < D; ++a) id = id * P.NN[a] + (2 * C[a] + off[a]);
+    return id;
+  };
+  // gather the cell's fields, dof numbers and test flags
+  if (tid == 0) s_cellflag = 0;
+  for (int l = tid; l < NQ2; l += blockDim.x) {
+    int off[3], r = l;
+    for (int a = 0; a < D; ++a) { off[a] = r % 3; r /= 3; }
+    const int64_t n = node_of(off);
+    const int64_t vd = nd.vdof[n], ud = nd.udof[n];
+    // is the node in a solid cell: on every axis a neighbouring cell lies in the box
+    bool in_solid = true;
+    for (int a = 0; a < D; ++a) {
+      const int I = 2 * C[a] + off[a];
+      int lo = I % 2 ? (I - 1) / 2 : I / 2 - 1, hi = I % 2 ? (I - 1) / 2 : I / 2;
+      lo = lo < 0 ? 0 : lo;
+      hi = hi > P.nc[a] - 1 ? P.nc[a] - 1 : hi;
+      in_solid = in_solid && hi >= P.solid_lo[a] && lo < P.solid_hi[a];
+    }
+    for (int c = 0; c < D; ++c) {
+      const int k = l * D + c;
+      s_f[k] = nd.v[n * D + c] + (vd >= 0 && dU ? dU[vd + c] : 0.0);
+      s_f[NV + k] = nd.u[n * D + c] + (ud >= 0 && dU ? dU[ud + c] : 0.0);
+      s_f[2 * NV + k] = nd.w[n * D + c];
+      s_f[3 * NV + k] = nd.v_old[n * D + c];
+      s_f[4 * NV + k] = nd.u_old[n * D + c];
+      s_f[5 * NV + k] = nd.u_fz[n * D + c];
+      s_gd[k] = vd >= 0 ? vd + c : -1;
+      s_gd[NV + k] = ud >= 0 ? ud + c : -1;
+      s_ton[k] = vd >= 0;
+      s_ton[NV + k] = ud >= 0 && (solid || !in_solid);
+    }
+  }
+  for (int l = tid; l < NQ1; l += blockDim.x) {
+    int off[3], r = l;
+    for (int a = 0; a < D; ++a) { off[a] = 2 * (r % 2); r /= 2; }
+    const int64_t n = node_of(off);
+    const int64_t pd = solid ? -1 : nd.pdof[n];
+    s_f[6 * NV + l] = nd.p[n] + (pd >= 0 && dU ? dU[pd] : 0.0);
+    s_gd[2 * NV + l] = pd;
+    s_ton[2 * NV + l] = pd >= 0;
+  }
+  __syncthreads();
+  const int tr = tid / Q::SL, sl = tid % Q::SL;
+  const int t = t0 + tr;
+  const bool row_on = t < NLOC && s_ton[t] && s_gd[t] >= 0;
+  double acc[Q::NJ];
+  for (int j = 0; j < Q::NJ; ++j) acc[j] = 0.0;
+  double res = 0.0;
+  const double gx[3] = {0.5 - 0.38729833462074168852, 0.5, 0.5 + 0.38729833462074168852};
+  const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  const int npts = Q::NVOL + (outflow ? Q::NFACE : 0);
+  for (int ip = 0; ip < npts; ++ip) {
+    const bool face = ip >= Q::NVOL;
+    double xi[3] = {0.0, 0.0, 0.0}, w = 1.0;
+    if (!face) {
+      int r = ip;
+      for (int a = 0; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
+    } else {
+      int r = ip - Q::NVOL;
+      xi[0] = 1.0;
+      for (int a = 1; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
+    }
+    // basis values at the point
+    if (tid < NQ2) {
+      double n1[3][3], d1[3][3];
+      for (int a = 0; a < D; ++a) q2_basis(xi[a], n1[a], d1[a]);
+      int ia[3], r = tid;
+      for (int a = 0; a < D; ++a) { ia[a] = r % 3; r /= 3; }
+      double prod = 1.0;
+      for (int a = 0; a < D; ++a) prod *= n1[a][ia[a]];
+      s_N[tid] = prod;
+      for (int k = 0; k < D; ++k) {
+        double g = d1[k][ia[k]] / P.h[k];
+        for (int a = 0; a < D; ++a)
+          if (a != k) g *= n1[a][ia[a]];
+        s_dN[tid * D + k] = g;
+      }
+    } else if (tid < NQ2 + NQ1) {
+      int r = tid - NQ2;
+      double prod = 1.0;
+      for (int a = 0; a < D; ++a) { prod *= (r % 2) ? xi[a] : 1.0 - xi[a]; r /= 2; }
+      s_M[tid - NQ2] = prod;
+    }
+    __syncthreads();
+    // interpolated inputs q and given fields
+    if (tid < NQ + Q::NFR) {
+      double s = 0.0;
+      if (tid < NQ) {
+        const int i = tid;
+        if (i == Q::QP) {
+          for (int l = 0; l < NQ1; ++l) s += s_M[l] * s_f[6 * NV + l];
+        } else {
+          const bool vel = i < Q::QU;
+          const int j = vel ? i : i - Q::QU;  // 0..D-1 value, D.. gradient
+          const double* f = s_f + (vel ? 0 : NV);
+          if (j < D) {
+            for (int l = 0; l < NQ2; ++l) s += s_N[l] * f[l * D + j];
+          } else {
+            const int c = (j - D) / D, k = (j - D) % D;
+            for (int l = 0; l < NQ2; ++l) s += s_dN[l * D + k] * f[l * D + c];
+          }
+        }
+      } else {
+        const int j = tid - NQ;
+        if (j < 3 * D) {  // w, v_old, u_old
+          const double* f = s_f + (2 + j / D) * NV;
+          const int c = j % D;
+          for (int l = 0; l < NQ2; ++l) s += s_N[l] * f[l * D + c];
+        } else {          // grad u_fz
+          const int c = (j - 3 * D) / D, k = (j - 3 * D) % D;
+          for (int l = 0; l < NQ2; ++l) s += s_dN[l * D + k] * s_f[5 * NV + l * D + c];
+        }
+      }
+      s_q[tid] = s;
+    }
+    __syncthreads();
+    // d out / d q_i, one direction per thread
+    if (tid < NQ) {
+      Dn qd[NQ], out[NQ];
+      for (int i = 0; i < NQ; ++i) qd[i] = Dn{s_q[i], i == tid ? 1.0 : 0.0};
+      const int kind = face ? 2 : (solid ? 1 : 0);
+      fe_integrand<D>(kind, qd, s_q + NQ, P, out);
+      for (int o = 0; o < NQ; ++o) s_Dm[o * NQ + tid] = out[o].d;
+      if (tid == 0) {
+        for (int o = 0; o < NQ; ++o) s_ov[o] = out[o].v;
+        // J of the current state and of the mesh-stiffness field must stay positive
+        if (!solid && !face) {
+          double Fv[D][D], Fz[D][D];
+          for (int c = 0; c < D; ++c)
+            for (int k = 0; k < D; ++k) {
+              Fv[c][k] = s_q[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
+              Fz[c][k] = s_q[NQ + 3 * D + c * D + k] + (c == k ? 1.0 : 0.0);
+            }
+          double Jv, Jz;
+          if constexpr (D == 2) {
+            Jv = Fv[0][0] * Fv[1][1] - Fv[0][1] * Fv[1][0];
+            Jz = Fz[0][0] * Fz[1][1] - Fz[0][1] * Fz[1][0];
+          } else {
+            Jv = Fv[0][0] * (Fv[1][1] * Fv[2][2] - Fv[1][2] * Fv[2][1]) -
+                 Fv[0][1] * (Fv[1][0] * Fv[2][2] - Fv[1][2] * Fv[2][0]) +
+                 Fv[0][2] * (Fv[1][0] * Fv[2][1] - Fv[1][1] * Fv[2][0]);
+            Jz = Fz[0][0] * (Fz[1][1] * Fz[2][2] - Fz[1][2] * Fz[2][1]) -
+                 Fz[0][1] * (Fz[1][0] * Fz[2][2] - Fz[1][2] * Fz[2][0]) +
+                 Fz[0][2] * (Fz[1][0] * Fz[2][1] - Fz[1][1] * Fz[2][0]);
+          }
+          if (!(Jv > 0.0) || !(Jz > 0.0)) s_cellflag |= 1;
+        }
+      }
+    }
+    __syncthreads();
+    // residual of this workgroup's test rows
+    if (want_res && sl == 0 && row_on) {
+      if (t < 2 * NV) {
+        const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
+        const int l = (t % NV) / D, c = (t % NV) % D;
+        double s = s_ov[fo + c] * s_N[l];
+        for (int k = 0; k < D; ++k) s += s_ov[go + c * D + k] * s_dN[l * D + k];
+        res += w * s;
+      } else {
+        res += w * s_ov[Q::QP] * s_M[t - 2 * NV];
+      }
+    }
+    if (want_mat) {
+      for (int idx = tid; idx < NLOC * NQ; idx += blockDim.x) {
+        const int s = idx / NQ, o = idx % NQ;
+        double val = 0.0;
+        if (s_gd[s] >= 0) {
+          if (s < 2 * NV) {
+            const int fi = s < NV ? Q::QV : Q::QU, gi = s < NV ? Q::QGV : Q::QGU;
+            const int l = (s % NV) / D, e = (s % NV) % D;
+            val = s_Dm[o * NQ + fi + e] * s_N[l];
+            for (int k = 0; k < D; ++k) val += s_Dm[o * NQ + gi + e * D + k] * s_dN[l * D + k];
+          } else {
+            val = s_Dm[o * NQ + Q::QP] * s_M[s - 2 * NV];
+          }
+        }
+        s_DB[idx] = val;
+      }
+      __syncthreads();
+      if (row_on) {
+        if (t < 2 * NV) {
+          const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
+          const int l = (t % NV) / D, c = (t % NV) % D;
+          double tw[4];
+          tw[0] = w * s_N[l];
+          for (int k = 0; k < D; ++k) tw[1 + k] = w * s_dN[l * D + k];
+          for (int j = 0; j < Q::NJ; ++j) {
+            const int s = sl + Q::SL * j;
+            if (s >= NLOC) break;
+            const double* db = s_DB + s * NQ;
+            double v = tw[0] * db[fo + c];
+            for (int k = 0; k < D; ++k) v += tw[1 + k] * db[go + c * D + k];
+            acc[j] += v;
+          }
+        } else {
+          const double tw = w * s_M[t - 2 * NV];
+          for (int j = 0; j < Q::NJ; ++j) {
+            const int s = sl + Q::SL * j;
+            if (s >= NLOC) break;
+            acc[j] += tw * s_DB[s * NQ + Q::QP];
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+  int bad = 0;
+  if (row_on) {
+    const int64_t grow = s_gd[t];
+    if (want_res && sl == 0) {
+      if (!isfinite(res)) bad |= 4;
+      R[grow] += res;
+    }
+    if (want_mat) {
+      for (int j = 0; j < Q::NJ; ++j) {
+        const int s = sl + Q::SL * j;
+        if (s >= NLOC) break;
+        const int64_t gcol = s_gd[s];
+        if (gcol < 0) continue;
+        const double v = acc[j];
+        if (!isfinite(v)) bad |= 4;
+        double* slot = ah_slot(ah, grow, int32_t(gcol));
+        if (slot) *slot += v;
+        else if (v != 0.0) bad |= 2;
+      }
+    }
+  }
+  if (tid == 0) bad |= s_cellflag;
+  if (bad) atomicOr(flag, bad);
+}
+
+// Values of one block's entries read back from the stored A_h (block rows and
+// columns offset by row_off / col_off); one thread per row.
+__global__ __launch_bounds__(256) void ah_block_gather_kernel(int64_t nrows, const int64_t* __restrict__ rp,
+                                                              const int32_t* __restrict__ ci, int64_t row_off,
+                                                              int64_t col_off, AhSlots ah, double* __restrict__ out,
+                                                              int* flag) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i >= nrows) return;
+  for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+    const double* slot = ah_slot(ah, row_off + i, int32_t(col_off + ci[k]));
+    if (!slot) {
+      atomicOr(flag, 2);
+      out[k] = 0.0;
+    } else {
+      out[k] = *slot;
+    }
+  }
+}
+
+// Block-wise max |x_i| (NaN counts as +inf).
+__global__ __launch_bounds__(256) void absmax_kernel(int64_t n, const double* __restrict__ x, double* __restrict__ part) {
+  __shared__ double red[256];
+  double m = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += int64_t(gridDim.x) * blockDim.x) {
+    const double a = fabs(x[i]);
+    m = (a != a) ? INFINITY : (a > m ? a : m);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// y -= x (the Newton update U_{k+1} = U_k + delta with delta = -x).
+__global__ __launch_bounds__(256) void sub_inplace_kernel(int64_t n, const double* __restrict__ x, double* __restrict__ y) {
+  const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (i < n) y[i] -= x[i];
+}
+
+}  // namespace fsi

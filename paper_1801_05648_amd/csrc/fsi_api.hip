@@ -37,6 +37,7 @@
 #include "mlp.hpp"
 #include "sa_setup.hpp"
 #include "spgemm.hpp"
+#include "fe_assembly.hpp"
 
 // Staging of fsi_mlp_forward_noalloc: the FP32 copies of the residual and of
 // the network's correction (kNoAllocStage entries each) in one array per GPU,
@@ -1633,6 +1634,21 @@ struct MlpState {
   int kin() const { return d == 2 ? MlpDims<2>::KIN : MlpDims<3>::KIN; }
 };
 
+// Finite-element description uploaded by fsi_fe_setup: the grid, the
+// material data and the node arrays; the block patterns are uploaded on the
+// first read-back of block values.
+struct FeState {
+  FeParams prm{};
+  int64_t n_nodes = 0;
+  DevBuf vdof, udof, pdof, v, u, p, v_old, u_old, w, u_fz, flag, part;
+  std::shared_ptr<DevBuf> brp[FSI_NBLK], bci[FSI_NBLK];
+  FeNodes nodes() const {
+    return FeNodes{vdof.as<int64_t>(), udof.as<int64_t>(), pdof.as<int64_t>(), v.as<double>(),
+                   u.as<double>(),     p.as<double>(),     v_old.as<double>(), u_old.as<double>(),
+                   w.as<double>(),     u_fz.as<double>()};
+  }
+};
+
 // ------------------------------------------------------------------ context
 struct fsi_ctx {
   int device = 0;
@@ -1650,7 +1666,10 @@ struct fsi_ctx {
   HCsr blk[FSI_NBLK];
   MlpState mlp[2];
   DCsr<double> Ah;
+  std::unique_ptr<FeState> fe;  // fsi_fe_setup
   // preconditioner
+  fsi_precond_opts popts{};     // options of the last fsi_build_precond
+  bool have_popts = false;
   int precision = FSI_P_F64;
   int gs_blocks = kGsBlocks;
   int cheb[FSI_NHIER] = {0, 0, 0, 0, 0};  // Chebyshev degree per hierarchy (0: Jacobi)
@@ -3032,6 +3051,7 @@ void mlp_forward_impl(fsi_ctx& c, int which, const double* b, double* x, float* 
   }
 }
 
+
 }  // namespace
 
 // =================================================================== C ABI
@@ -3246,6 +3266,7 @@ fsi_status fsi_setup_blocks(fsi_ctx* ctx, const fsi_layout* L, const fsi_csr blk
     c.dof_node.assign(L->dof_node, L->dof_node + N);
     for (int b = 0; b < FSI_NBLK; ++b) c.blk[b] = std::move(H[b]);
     c.Ah = dAh;
+    c.fe.reset();
     c.have_system = true;
     c.have_precond = false;
     c.have_host_h = false;
@@ -3297,9 +3318,14 @@ fsi_status fsi_update_values(fsi_ctx* ctx, const fsi_csr blk[FSI_NBLK]) {
   });
 }
 
+static fsi_status build_precond_impl(fsi_ctx& c, const fsi_precond_opts* opts);
+
 fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
-  return guarded(ctx, [&]() -> fsi_status {
-    fsi_ctx& c = *ctx;
+  return guarded(ctx, [&]() -> fsi_status { return build_precond_impl(*ctx, opts); });
+}
+
+static fsi_status build_precond_impl(fsi_ctx& c, const fsi_precond_opts* opts) {
+  {
     if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
     fsi_precond_opts o;
     fsi_default_precond_opts(&o);
@@ -3365,10 +3391,12 @@ fsi_status fsi_build_precond(fsi_ctx* ctx, const fsi_precond_opts* opts) {
       t.done();
     }
     c.have_precond = true;
+    c.popts = o;
+    c.have_popts = true;
     t_build.done(o.reuse ? " (hierarchies reused)" : "");
     log_staging("build_precond");
     return FSI_OK;
-  });
+  }
 }
 
 
@@ -3772,6 +3800,324 @@ fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_t
     HIP_TRY(hipStreamSynchronize(c.stream));
     if (info) *info = local;
     return FSI_OK;
+  });
+}
+
+// ------------------------------------------------- finite-element assembly
+// The stored A_h as kernel-visible slot tables.
+static AhSlots ah_slots(fsi_ctx& c) {
+  AhSlots a{};
+  const RowSegments& sg = c.Ah.seg;
+  a.nseg = sg.nseg;
+  for (int q = 0; q <= sg.nseg; ++q) a.row0[q] = sg.row0[q];
+  for (int q = 0; q < sg.nseg; ++q) {
+    a.grp[q] = sg.grp[q];
+    a.grp_rp[q] = sg.grp_rp[q];
+    a.grp_ci[q] = sg.grp_ci[q];
+    a.grp_val[q] = static_cast<double*>(const_cast<void*>(sg.grp_val[q]));
+  }
+  a.rp = c.Ah.drp();
+  a.ci = c.Ah.dci();
+  a.val = c.Ah.val ? c.Ah.val->as<double>() : nullptr;
+  return a;
+}
+
+// Residual R(U) into R (when R is given) and, with want_mat, the Jacobian's
+// values into the stored A_h (cleared first); U = the given fields + dU.
+static void fe_assemble(fsi_ctx& c, const double* dU, double* R, bool want_mat) {
+  FeState& F = *c.fe;
+  hipStream_t s = c.stream;
+  AhSlots ah = ah_slots(c);
+  if (R) HIP_TRY(hipMemsetAsync(R, 0, sizeof(double) * size_t(c.N), s));
+  if (want_mat) {
+    if (ah.val) HIP_TRY(hipMemsetAsync(ah.val, 0, c.Ah.val->bytes, s));
+    for (int q = 0; q < ah.nseg; ++q)
+      if (ah.grp[q] > 1) HIP_TRY(hipMemsetAsync(ah.grp_val[q], 0, c.Ah.grp_val[q]->bytes, s));
+  }
+  HIP_TRY(hipMemsetAsync(F.flag.p, 0, sizeof(int), s));
+  const int D = F.prm.D;
+  for (int color = 0; color < (1 << D); ++color) {
+    int64_t ncell = 1;
+    for (int a = 0; a < D; ++a) ncell *= (F.prm.nc[a] - ((color >> a) & 1) + 1) / 2;
+    if (ncell == 0) continue;
+    if (D == 2) {
+      dim3 grid(unsigned(ncell), FeDims<2>::NCHUNK);
+      fe_assemble_kernel<2><<<grid, 256, 0, s>>>(F.prm, F.nodes(), dU, color, R != nullptr, want_mat, R, ah,
+                                                 F.flag.as<int>());
+    } else {
+      dim3 grid(unsigned(ncell), FeDims<3>::NCHUNK);
+      fe_assemble_kernel<3><<<grid, 256, 0, s>>>(F.prm, F.nodes(), dU, color, R != nullptr, want_mat, R, ah,
+                                                 F.flag.as<int>());
+    }
+    HIP_TRY(hipGetLastError());
+  }
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, F.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (flag & 1) throw Error(FSI_ERR_NUMERIC, "the state has J <= 0 at a quadrature point of a fluid cell");
+  if (flag & 4) throw Error(FSI_ERR_NUMERIC, "non-finite residual or Jacobian value");
+  if (flag & 2) throw Error(FSI_ERR_STRUCT, "a cell matrix entry lies outside the stored sparsity pattern");
+}
+
+// The host copies of the eight blocks take the values of the stored A_h (for
+// a preconditioner built from the assembled Jacobian).
+static void fe_refresh_host_blocks(fsi_ctx& c) {
+  FeState& F = *c.fe;
+  hipStream_t s = c.stream;
+  const int64_t off[4] = {0, c.n_m, c.n_m + c.n_s, c.N};
+  const int bi[FSI_NBLK] = {0, 0, 1, 1, 1, 2, 2, 2};
+  const int bj[FSI_NBLK] = {0, 1, 0, 1, 2, 0, 1, 2};
+  AhSlots ah = ah_slots(c);
+  HCsr H[FSI_NBLK];
+  HIP_TRY(hipMemsetAsync(F.flag.p, 0, sizeof(int), s));
+  for (int b = 0; b < FSI_NBLK; ++b) {
+    const HCsr& O = c.blk[b];
+    if (!F.brp[b]) {
+      F.brp[b] = upload_raw(O.rp, s);
+      F.bci[b] = upload_raw(O.ci, s);
+    }
+    H[b] = O;
+    if (O.nnz() == 0) continue;
+    DevBuf vals;
+    vals.alloc(sizeof(double) * size_t(O.nnz()));
+    ah_block_gather_kernel<<<grid_for(O.nrows, kBlock), kBlock, 0, s>>>(
+        O.nrows, F.brp[b]->as<int64_t>(), F.bci[b]->as<int32_t>(), off[bi[b]], off[bj[b]], ah, vals.as<double>(),
+        F.flag.as<int>());
+    HIP_TRY(hipGetLastError());
+    d2h(H[b].v.data(), vals.p, size_t(O.nnz()), s);
+  }
+  int flag = 0;
+  HIP_TRY(hipMemcpyAsync(&flag, F.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (flag) throw Error(FSI_ERR_STRUCT, "a block entry is missing from the stored A_h");
+  check_structure(H, c.d, c.n_vs, c.n_vf, c.n_f, c.dt_theta);
+  for (int b = 0; b < FSI_NBLK; ++b) c.blk[b] = std::move(H[b]);
+}
+
+// max |x_i| over a device vector (NaN reads as +inf).
+static double device_absmax(fsi_ctx& c, const double* x, int64_t n) {
+  FeState& F = *c.fe;
+  const unsigned nb = std::min<unsigned>(grid_for(n, kBlock * 4), 1024u);
+  absmax_kernel<<<nb, kBlock, 0, c.stream>>>(n, x, F.part.as<double>());
+  HIP_TRY(hipGetLastError());
+  std::vector<double> h(nb);
+  HIP_TRY(hipMemcpyAsync(h.data(), F.part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, c.stream));
+  HIP_TRY(hipStreamSynchronize(c.stream));
+  double m = 0.0;
+  for (double v : h) m = std::max(m, v);
+  return m;
+}
+
+
+void fsi_default_newton_opts(fsi_newton_opts* o) {
+  if (!o) return;
+  *o = fsi_newton_opts{};
+  o->rtol = 1e-6;
+  o->reassemble_ratio = 0.1;
+  o->max_steps = 25;
+  o->precond = FSI_NEWTON_PC_REBUILD;
+  o->lin_tol = 1e-3;
+  o->restart = 50;
+  o->maxit = 2000;
+}
+
+fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* m) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
+    if (!m) throw Error(FSI_ERR_ARG, "mesh is NULL");
+    if (m->dim != c.d) throw Error(FSI_ERR_ARG, "mesh dimension differs from the system's");
+    if (m->theta != 1.0) throw Error(FSI_ERR_ARG, "theta = 1 only");
+    if (!(m->dt > 0.0) || !(m->rho_f > 0.0) || !(m->nu_f > 0.0) || !(m->rho_s > 0.0) || !(m->mu_s > 0.0) ||
+        !(m->lambda_s >= 0.0))
+      throw Error(FSI_ERR_ARG, "material data and dt must be positive");
+    if (std::fabs(m->dt * m->theta - c.dt_theta) > 1e-14 * c.dt_theta)
+      throw Error(FSI_ERR_ARG, "dt * theta differs from the system's");
+    const int D = m->dim;
+    FeParams P{};
+    P.D = D;
+    int64_t nn = 1;
+    for (int a = 0; a < 3; ++a) {
+      P.nc[a] = a < D ? m->cells[a] : 1;
+      P.NN[a] = 2 * P.nc[a] + 1;
+      P.h[a] = a < D ? m->extent[a] / double(m->cells[a]) : 1.0;
+      P.solid_lo[a] = a < D ? m->solid_lo[a] : 0;
+      P.solid_hi[a] = a < D ? m->solid_hi[a] : 1;
+      if (a < D) {
+        if (m->cells[a] < 1 || m->cells[a] > 65535 || !(m->extent[a] > 0.0))
+          throw Error(FSI_ERR_ARG, "cells must be in 1..65535 and extents positive");
+        nn *= P.NN[a];
+      }
+    }
+    if (nn != m->n_nodes) throw Error(FSI_ERR_ARG, "n_nodes must be the product of 2 cells + 1");
+    P.rho_f = m->rho_f; P.nu_f = m->nu_f; P.rho_s = m->rho_s; P.mu_s = m->mu_s; P.lambda_s = m->lambda_s;
+    P.dtth = m->dt * m->theta;
+    P.newton_mesh = m->newton_mesh ? 1 : 0;
+    const int64_t* dofs[3] = {m->vdof, m->udof, m->pdof};
+    const double* fields[7] = {m->v, m->u, m->p, m->v_old, m->u_old, m->w, m->u_fz};
+    for (auto* q : dofs)
+      if (!q) throw Error(FSI_ERR_ARG, "dof arrays are required");
+    for (auto* q : fields)
+      if (!q) throw Error(FSI_ERR_ARG, "node fields are required");
+    // dof numbers within range; every free dof named exactly once
+    std::vector<unsigned char> seen(size_t(c.N), 0);
+    for (int64_t n = 0; n < nn; ++n) {
+      for (int f = 0; f < 2; ++f) {
+        const int64_t b = dofs[f][n];
+        if (b < -1 || b + D > c.N) throw Error(FSI_ERR_ARG, "dof number out of range");
+        if (b >= 0)
+          for (int k = 0; k < D; ++k) {
+            if (seen[size_t(b + k)]) throw Error(FSI_ERR_ARG, "a dof is named twice");
+            seen[size_t(b + k)] = 1;
+          }
+      }
+      const int64_t pd = m->pdof[n];
+      if (pd < -1 || pd >= c.N) throw Error(FSI_ERR_ARG, "dof number out of range");
+      if (pd >= 0) {
+        if (seen[size_t(pd)]) throw Error(FSI_ERR_ARG, "a dof is named twice");
+        seen[size_t(pd)] = 1;
+      }
+    }
+    for (unsigned char x : seen)
+      if (!x) throw Error(FSI_ERR_ARG, "a free dof belongs to no node");
+    for (int f = 0; f < 7; ++f) {
+      const int64_t len = f == 2 ? nn : nn * D;
+      for (int64_t i = 0; i < len; ++i)
+        if (!std::isfinite(fields[f][i])) throw Error(FSI_ERR_NUMERIC, "node fields hold NaN or Inf");
+    }
+    auto fe = std::make_unique<FeState>();
+    fe->prm = P;
+    fe->n_nodes = nn;
+    hipStream_t s = c.stream;
+    DevBuf* db[3] = {&fe->vdof, &fe->udof, &fe->pdof};
+    for (int f = 0; f < 3; ++f) {
+      db[f]->alloc(sizeof(int64_t) * size_t(nn));
+      h2d(db[f]->p, dofs[f], size_t(nn), s);
+    }
+    DevBuf* fb[7] = {&fe->v, &fe->u, &fe->p, &fe->v_old, &fe->u_old, &fe->w, &fe->u_fz};
+    for (int f = 0; f < 7; ++f) {
+      const int64_t len = f == 2 ? nn : nn * D;
+      fb[f]->alloc(sizeof(double) * size_t(len));
+      h2d(fb[f]->p, fields[f], size_t(len), s);
+    }
+    fe->flag.alloc(sizeof(int));
+    fe->part.alloc(sizeof(double) * 1024);
+    HIP_TRY(hipStreamSynchronize(s));
+    c.fe = std::move(fe);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_fe_residual(fsi_ctx* ctx, const double* dU, double* R) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
+    if (dU) check_device_ptr(dU, "dU");
+    check_device_ptr(R, "R");
+    if (dU == R) throw Error(FSI_ERR_ARG, "dU and R must not alias");
+    fe_assemble(c, dU, R, false);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
+    if (dU) check_device_ptr(dU, "dU");
+    PhaseTimer t("fe_jacobian: A_h assembled on the device");
+    fe_assemble(c, dU, nullptr, true);
+    t.done();
+    if (host_blocks) fe_refresh_host_blocks(c);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi_newton_info* info) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
+    fsi_newton_opts o;
+    fsi_default_newton_opts(&o);
+    if (opts) o = *opts;
+    if (!(o.rtol > 0.0) || !(o.reassemble_ratio >= 0.0) || o.max_steps < 0 || o.max_steps > FSI_NEWTON_MAX ||
+        !(o.lin_tol > 0.0) || o.restart < 1 || o.restart > kMaxBasis - 8 || o.maxit < 1 ||
+        (o.precond != FSI_NEWTON_PC_REBUILD && o.precond != FSI_NEWTON_PC_REUSE && o.precond != FSI_NEWTON_PC_KEEP))
+      throw Error(FSI_ERR_ARG, "bad Newton options");
+    if (o.precond == FSI_NEWTON_PC_KEEP && !c.have_precond)
+      throw Error(FSI_ERR_STATE, "keeping the preconditioner needs a fsi_build_precond first");
+    check_device_ptr(dU, "dU");
+    const auto t_start = std::chrono::steady_clock::now();
+    auto ms_since = [](std::chrono::steady_clock::time_point t0) {
+      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    };
+    fsi_newton_info out{};
+    const int64_t N = c.N;
+    DevBuf R, delta;
+    R.alloc(sizeof(double) * size_t(N));
+    delta.alloc(sizeof(double) * size_t(N));
+    auto tic = std::chrono::steady_clock::now();
+    fe_assemble(c, dU, R.as<double>(), false);
+    out.t_assemble_ms += ms_since(tic);
+    out.resid[0] = device_absmax(c, R.as<double>(), N);
+    if (!std::isfinite(out.resid[0])) throw Error(FSI_ERR_NUMERIC, "the initial residual is not finite");
+    fsi_precond_opts po;
+    fsi_default_precond_opts(&po);
+    if (c.have_popts) po = c.popts;
+    fsi_solve_opts so;
+    fsi_default_solve_opts(&so);
+    so.tol = o.lin_tol;
+    so.restart = o.restart;
+    so.maxit = o.maxit;
+    for (int k = 0;; ++k) {
+      const double rk = out.resid[k];
+      if (rk == 0.0 || rk < o.rtol * out.resid[0]) {
+        out.converged = 1;
+        break;
+      }
+      if (k == o.max_steps) break;
+      // Section 6: assemble at the first step, then only when the last step
+      // reduced the max-norm residual by less than 1 / ratio
+      const bool assemble = k == 0 || rk > o.reassemble_ratio * out.resid[k - 1];
+      out.reassembled[k] = assemble ? 1 : 0;
+      if (assemble) {
+        tic = std::chrono::steady_clock::now();
+        fe_assemble(c, dU, nullptr, true);
+        if (o.precond != FSI_NEWTON_PC_KEEP) fe_refresh_host_blocks(c);
+        out.t_assemble_ms += ms_since(tic);
+        ++out.reassemblies;
+        if (o.precond != FSI_NEWTON_PC_KEEP) {
+          tic = std::chrono::steady_clock::now();
+          fsi_precond_opts pk = po;
+          pk.reuse = (o.precond == FSI_NEWTON_PC_REUSE && c.have_host_h) ? 1 : 0;
+          build_precond_impl(c, &pk);
+          out.t_precond_ms += ms_since(tic);
+        }
+      }
+      // J delta = R, then U_{k+1} = U_k - delta
+      tic = std::chrono::steady_clock::now();
+      HIP_TRY(hipMemsetAsync(delta.p, 0, sizeof(double) * size_t(N), c.stream));
+      fsi_solve_info si{};
+      solve_impl(c, R.as<double>(), delta.as<double>(), so, si);
+      out.lin_iters[k] = si.iters;
+      out.lin_iters_total += si.iters;
+      sub_inplace_kernel<<<grid_for(N, kBlock), kBlock, 0, c.stream>>>(N, delta.as<double>(), dU);
+      HIP_TRY(hipGetLastError());
+      out.t_solve_ms += ms_since(tic);
+      tic = std::chrono::steady_clock::now();
+      fe_assemble(c, dU, R.as<double>(), false);
+      out.t_assemble_ms += ms_since(tic);
+      out.resid[k + 1] = device_absmax(c, R.as<double>(), N);
+      out.steps = k + 1;
+      if (!std::isfinite(out.resid[k + 1])) throw Error(FSI_ERR_NUMERIC, "the Newton residual is not finite");
+    }
+    out.t_total_ms = ms_since(t_start);
+    log_line("newton: %d steps, %d assemblies, %d GMRES iterations, ||r||_inf %.3e -> %.3e, %.1f ms "
+             "(assembly %.1f, preconditioner %.1f, solves %.1f)",
+             out.steps, out.reassemblies, out.lin_iters_total, out.resid[0], out.resid[out.steps], out.t_total_ms,
+             out.t_assemble_ms, out.t_precond_ms, out.t_solve_ms);
+    if (info) *info = out;
+    return out.converged ? FSI_OK : FSI_NOT_CONVERGED;
   });
 }
 

@@ -27,6 +27,50 @@ STATUS = {0: "FSI_OK", 1: "FSI_NOT_CONVERGED", -1: "FSI_ERR_ARG", -2: "FSI_ERR_C
           -7: "FSI_ERR_STATE"}
 
 
+NEWTON_MAX = 64
+NEWTON_PC = {"rebuild": 0, "reuse": 1, "keep": 2}
+
+
+class CFeMesh(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("cells", ctypes.c_int32 * 3), ("extent", ctypes.c_double * 3),
+                ("solid_lo", ctypes.c_int32 * 3), ("solid_hi", ctypes.c_int32 * 3),
+                ("rho_f", ctypes.c_double), ("nu_f", ctypes.c_double), ("rho_s", ctypes.c_double),
+                ("mu_s", ctypes.c_double), ("lambda_s", ctypes.c_double), ("dt", ctypes.c_double),
+                ("theta", ctypes.c_double), ("newton_mesh", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("n_nodes", ctypes.c_int64)] + [(k, ctypes.c_void_p) for k in
+                                                ("vdof", "udof", "pdof", "v", "u", "p", "v_old", "u_old", "w",
+                                                 "u_fz")]
+
+
+class CNewtonOpts(ctypes.Structure):
+    _fields_ = [("rtol", ctypes.c_double), ("reassemble_ratio", ctypes.c_double), ("max_steps", ctypes.c_int32),
+                ("precond", ctypes.c_int32), ("lin_tol", ctypes.c_double), ("restart", ctypes.c_int32),
+                ("maxit", ctypes.c_int32)]
+
+
+class CNewtonInfo(ctypes.Structure):
+    _fields_ = [("converged", ctypes.c_int32), ("steps", ctypes.c_int32), ("reassemblies", ctypes.c_int32),
+                ("lin_iters_total", ctypes.c_int32), ("resid", ctypes.c_double * (NEWTON_MAX + 1)),
+                ("reassembled", ctypes.c_int32 * NEWTON_MAX), ("lin_iters", ctypes.c_int32 * NEWTON_MAX),
+                ("t_assemble_ms", ctypes.c_double), ("t_precond_ms", ctypes.c_double),
+                ("t_solve_ms", ctypes.c_double), ("t_total_ms", ctypes.c_double)]
+
+
+@dataclasses.dataclass
+class NewtonInfo:
+    status: str
+    converged: bool
+    steps: int
+    reassemblies: int
+    residuals: list      # ||r_k||_inf, k = 0 .. steps
+    reassembled: list    # per step
+    lin_iters: list      # per step
+    t_assemble_ms: float
+    t_precond_ms: float
+    t_solve_ms: float
+    t_total_ms: float
+
+
 class FsiError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"{STATUS.get(code, code)}: {msg}")
@@ -136,6 +180,11 @@ def _declare(lib):
         "fsi_mlp_energy_grad": ([P, i32, P, i32, P, P, P, P], i32),
         "fsi_mlp_collect": ([P, i32, i32], i32),
         "fsi_mlp_train": ([P, ctypes.POINTER(CMlpTrainOpts), ctypes.POINTER(CMlpTrainInfo)], i32),
+        "fsi_fe_setup": ([P, ctypes.POINTER(CFeMesh)], i32),
+        "fsi_fe_residual": ([P, P, P], i32),
+        "fsi_fe_jacobian": ([P, P, i32], i32),
+        "fsi_newton": ([P, ctypes.POINTER(CNewtonOpts), P, ctypes.POINTER(CNewtonInfo)], i32),
+        "fsi_default_newton_opts": ([ctypes.POINTER(CNewtonOpts)], None),
         "fsi_default_precond_opts": ([ctypes.POINTER(CPrecondOpts)], None),
         "fsi_default_solve_opts": ([ctypes.POINTER(CSolveOpts)], None),
     }
@@ -168,7 +217,8 @@ def exported_symbols():
             "fsi_default_precond_opts", "fsi_default_solve_opts", "fsi_default_mlp_train_opts",
             "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
             "fsi_mlp_forward_noalloc",
-            "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train"]
+            "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train",
+            "fsi_fe_setup", "fsi_fe_residual", "fsi_fe_jacobian", "fsi_newton", "fsi_default_newton_opts"]
 
 
 def _csr_struct(nrows, ncols, rowptr, col, val, keep):
@@ -260,10 +310,17 @@ class FsiSolver:
 
     @classmethod
     def from_system(cls, sysm, **kw):
-        return cls(sysm.blocks, cls.layout_of(sysm), **kw)
+        """A context on the generated system; with its finite-element
+        description (generate(..., fe=True)) the assembly is set up too."""
+        s = cls(sysm.blocks, cls.layout_of(sysm), **kw)
+        if getattr(sysm, "fe", None) is not None:
+            s.fe_setup(sysm.cfg, sysm.fe)
+        return s
 
     def set_from_system(self, sysm):
         self.set_system(sysm.blocks, self.layout_of(sysm))
+        if getattr(sysm, "fe", None) is not None:
+            self.fe_setup(sysm.cfg, sysm.fe)
 
     # -- plumbing ------------------------------------------------------------
     def _check(self, rc):
@@ -313,6 +370,65 @@ class FsiSolver:
                          mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio), int(fluid_inner),
                          INNER_PC[fluid_inner_pc], int(bool(reuse)), X_APPROX[x_approx], int(uzawa_inner), 0)
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
+
+    def fe_setup(self, cfg, fe: dict):
+        """fsi_fe_setup: the grid and material data of a workload config (dim,
+        cells, extent, solid_lo, solid_hi, rho_f, nu_f, rho_s, mu_s, lambda_s,
+        dt, theta, newton_mesh) and its node arrays (vdof, udof, pdof, v, u,
+        p, v_old, u_old, w, u_fz)."""
+        d = int(cfg.dim)
+        m = CFeMesh()
+        m.dim = d
+        for a in range(3):
+            m.cells[a] = int(cfg.cells[a]) if a < d else 1
+            m.extent[a] = float(cfg.extent[a]) if a < d else 1.0
+            m.solid_lo[a] = int(cfg.solid_lo[a]) if a < d else 0
+            m.solid_hi[a] = int(cfg.solid_hi[a]) if a < d else 1
+        for k in ("rho_f", "nu_f", "rho_s", "mu_s", "lambda_s", "dt", "theta"):
+            setattr(m, k, float(getattr(cfg, k)))
+        m.newton_mesh = int(cfg.newton_mesh)
+        keep = []
+        m.n_nodes = int(np.asarray(fe["vdof"]).shape[0])
+        for k in ("vdof", "udof", "pdof"):
+            a = np.ascontiguousarray(fe[k], dtype=np.int64)
+            keep.append(a)
+            setattr(m, k, a.ctypes.data)
+        for k in ("v", "u", "p", "v_old", "u_old", "w", "u_fz"):
+            a = np.ascontiguousarray(fe[k], dtype=np.float64)
+            keep.append(a)
+            setattr(m, k, a.ctypes.data)
+        self._check(self.lib.fsi_fe_setup(self.ctx, ctypes.byref(m)))
+
+    def fe_residual(self, dU=None, R=None):
+        """fsi_fe_residual: R(U) at U = the given fields + dU (device FP64)."""
+        torch = self.torch
+        if R is None:
+            R = torch.empty(self.N, dtype=torch.float64, device=f"cuda:{self.device}")
+        du = None if dU is None else _dptr(dU, self.N, "dU")
+        self._check(self.lib.fsi_fe_residual(self.ctx, du, _dptr(R, self.N, "R")))
+        return R
+
+    def fe_jacobian(self, dU=None, host_blocks: bool = True):
+        """fsi_fe_jacobian: A'(U) into the context's A_h (and the host blocks)."""
+        du = None if dU is None else _dptr(dU, self.N, "dU")
+        self._check(self.lib.fsi_fe_jacobian(self.ctx, du, int(bool(host_blocks))))
+
+    def newton(self, dU=None, rtol: float = 1e-6, reassemble_ratio: float = 0.1, max_steps: int = 25,
+               precond: str = "rebuild", lin_tol: float = 1e-3, restart: int = 50, maxit: int = 2000):
+        """fsi_newton: the quasi-Newton loop of Section 6 from U = fields + dU."""
+        torch = self.torch
+        if dU is None:
+            dU = torch.zeros(self.N, dtype=torch.float64, device=f"cuda:{self.device}")
+        o = CNewtonOpts(float(rtol), float(reassemble_ratio), int(max_steps), NEWTON_PC[precond], float(lin_tol),
+                        int(restart), int(maxit))
+        info = CNewtonInfo()
+        rc = self._check(self.lib.fsi_newton(self.ctx, ctypes.byref(o), _dptr(dU, self.N, "dU"),
+                                             ctypes.byref(info)))
+        n = info.steps
+        return dU, NewtonInfo(STATUS[rc], bool(info.converged), n, info.reassemblies,
+                              list(info.resid[:n + 1]), [bool(x) for x in info.reassembled[:n]],
+                              list(info.lin_iters[:n]), info.t_assemble_ms, info.t_precond_ms, info.t_solve_ms,
+                              info.t_total_ms)
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,
               timing: bool = False):

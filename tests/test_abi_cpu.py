@@ -69,12 +69,28 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.fsi_build_precond(None, None) == -1
     assert L.fsi_solve(None, None, None, None, None) == -1
     assert L.fsi_spmv(None, None, None) == -1
+    assert L.fsi_fe_setup(None, None) == -1
+    assert L.fsi_fe_residual(None, None, None) == -1
+    assert L.fsi_fe_jacobian(None, None, 0) == -1
+    assert L.fsi_newton(None, None, None, None) == -1
     assert L.fsi_destroy(None) == 0
+
+
+def test_default_newton_options_follow_section_6(lib):
+    """The quasi-Newton defaults: reassemble when the last step cut the
+    max-norm residual by less than ten, stop at a 1e-6 reduction, GMRES to a
+    reduction of 1e3 per step."""
+    from paper_1801_05648_amd import fsi
+    o = fsi.CNewtonOpts()
+    lib.fsi_default_newton_opts(ctypes.byref(o))
+    assert (o.rtol, o.reassemble_ratio, o.lin_tol) == (1e-6, 0.1, 1e-3)
+    assert (o.max_steps, o.precond, o.restart, o.maxit) == (25, fsi.NEWTON_PC["rebuild"], 50, 2000)
 
 
 STRUCTS = [("fsi_csr", "CCsr"), ("fsi_layout", "CLayout"), ("fsi_precond_opts", "CPrecondOpts"),
            ("fsi_solve_opts", "CSolveOpts"), ("fsi_solve_info", "CSolveInfo"),
-           ("fsi_mlp_train_opts", "CMlpTrainOpts"), ("fsi_mlp_train_info", "CMlpTrainInfo")]
+           ("fsi_mlp_train_opts", "CMlpTrainOpts"), ("fsi_mlp_train_info", "CMlpTrainInfo"),
+           ("fsi_fe_mesh", "CFeMesh"), ("fsi_newton_opts", "CNewtonOpts"), ("fsi_newton_info", "CNewtonInfo")]
 
 
 def test_ctypes_structs_match_the_header_layout(tmp_path):
