@@ -13,7 +13,8 @@
 // per thread: thread i of the workgroup seeds q_i.
 //
 // Launch: one workgroup of 256 threads per (cell, chunk of 32 local test
-// rows); the cells of one launch share one parity class per axis (2^d
+// rows), or per cell for the residual alone; the cells of one launch share
+// one parity class per axis (2^d
 // launches), so no two cells of a launch share a node and every row is
 // written by one workgroup: plain read-add-write, deterministic.  A thread
 // owns one test row t and the trial columns s = lane + 8 j of the cell matrix
@@ -344,8 +345,10 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
     s_ton[2 * NV + l] = pd >= 0;
   }
   __syncthreads();
-  const int tr = tid / Q::SL, sl = tid % Q::SL;
-  const int t = t0 + tr;
+  // matrix launches: 32 test rows per workgroup, 8 threads per row; residual
+  // launches: one workgroup per cell, one thread per row
+  const int tr = tid / Q::SL, sl = want_mat ? tid % Q::SL : 0;
+  const int t = want_mat ? t0 + tr : tid;
   const bool row_on = t < NLOC && s_ton[t] && s_gd[t] >= 0;
   double acc[Q::NJ];
   for (int j = 0; j < Q::NJ; ++j) acc[j] = 0.0;
@@ -418,8 +421,8 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
       s_q[tid] = s;
     }
     __syncthreads();
-    // d out / d q_i, one direction per thread
-    if (tid < NQ) {
+    // d out / d q_i, one direction per thread (the values alone for a residual)
+    if (tid < (want_mat ? NQ : 1)) {
       Dn qd[NQ], out[NQ];
       for (int i = 0; i < NQ; ++i) qd[i] = Dn{s_q[i], i == tid ? 1.0 : 0.0};
       const int kind = face ? 2 : (solid ? 1 : 0);

@@ -3841,11 +3841,11 @@ static void fe_assemble(fsi_ctx& c, const double* dU, double* R, bool want_mat) 
     for (int a = 0; a < D; ++a) ncell *= (F.prm.nc[a] - ((color >> a) & 1) + 1) / 2;
     if (ncell == 0) continue;
     if (D == 2) {
-      dim3 grid(unsigned(ncell), FeDims<2>::NCHUNK);
+      dim3 grid(unsigned(ncell), want_mat ? FeDims<2>::NCHUNK : 1);
       fe_assemble_kernel<2><<<grid, 256, 0, s>>>(F.prm, F.nodes(), dU, color, R != nullptr, want_mat, R, ah,
                                                  F.flag.as<int>());
     } else {
-      dim3 grid(unsigned(ncell), FeDims<3>::NCHUNK);
+      dim3 grid(unsigned(ncell), want_mat ? FeDims<3>::NCHUNK : 1);
       fe_assemble_kernel<3><<<grid, 256, 0, s>>>(F.prm, F.nodes(), dU, color, R != nullptr, want_mat, R, ah,
                                                  F.flag.as<int>());
     }
@@ -3868,7 +3868,8 @@ static void fe_refresh_host_blocks(fsi_ctx& c) {
   const int bi[FSI_NBLK] = {0, 0, 1, 1, 1, 2, 2, 2};
   const int bj[FSI_NBLK] = {0, 1, 0, 1, 2, 0, 1, 2};
   AhSlots ah = ah_slots(c);
-  HCsr H[FSI_NBLK];
+  PhaseTimer t("fe_jacobian: host block values read back");
+  std::vector<double> vals[FSI_NBLK];  // new values; the patterns stay where they are
   HIP_TRY(hipMemsetAsync(F.flag.p, 0, sizeof(int), s));
   for (int b = 0; b < FSI_NBLK; ++b) {
     const HCsr& O = c.blk[b];
@@ -3876,22 +3877,29 @@ static void fe_refresh_host_blocks(fsi_ctx& c) {
       F.brp[b] = upload_raw(O.rp, s);
       F.bci[b] = upload_raw(O.ci, s);
     }
-    H[b] = O;
+    vals[b].resize(size_t(O.nnz()));
     if (O.nnz() == 0) continue;
-    DevBuf vals;
-    vals.alloc(sizeof(double) * size_t(O.nnz()));
+    DevBuf dv;
+    dv.alloc(sizeof(double) * size_t(O.nnz()));
     ah_block_gather_kernel<<<grid_for(O.nrows, kBlock), kBlock, 0, s>>>(
-        O.nrows, F.brp[b]->as<int64_t>(), F.bci[b]->as<int32_t>(), off[bi[b]], off[bj[b]], ah, vals.as<double>(),
+        O.nrows, F.brp[b]->as<int64_t>(), F.bci[b]->as<int32_t>(), off[bi[b]], off[bj[b]], ah, dv.as<double>(),
         F.flag.as<int>());
     HIP_TRY(hipGetLastError());
-    d2h(H[b].v.data(), vals.p, size_t(O.nnz()), s);
+    d2h(vals[b].data(), dv.p, size_t(O.nnz()), s);
   }
   int flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, F.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (flag) throw Error(FSI_ERR_STRUCT, "a block entry is missing from the stored A_h");
-  check_structure(H, c.d, c.n_vs, c.n_vf, c.n_f, c.dt_theta);
-  for (int b = 0; b < FSI_NBLK; ++b) c.blk[b] = std::move(H[b]);
+  // swap the values in, check the structural identities, swap back on failure
+  for (int b = 0; b < FSI_NBLK; ++b) c.blk[b].v.swap(vals[b]);
+  try {
+    check_structure(c.blk, c.d, c.n_vs, c.n_vf, c.n_f, c.dt_theta);
+  } catch (...) {
+    for (int b = 0; b < FSI_NBLK; ++b) c.blk[b].v.swap(vals[b]);
+    throw;
+  }
+  t.done();
 }
 
 // max |x_i| over a device vector (NaN reads as +inf).
