@@ -487,7 +487,10 @@ fsi_status fsi_fe_residual(fsi_ctx* ctx, const double* dU, double* R);
  * else FSI_ERR_STRUCT): fsi_spmv and fsi_solve use it at once.  With
  * host_blocks the host copies of the eight blocks take the new values too
  * (checked as by fsi_setup_blocks), so that fsi_build_precond builds from
- * them; else the preconditioner's blocks keep their values.  dU as above. */
+ * them; else the preconditioner's blocks keep their values.  dU as above.
+ * On error (J <= 0, a non-finite value, an entry outside the pattern, a block
+ * identity violated) A_h and the blocks keep their previous values; the call
+ * holds a device copy of A_h's values (its stored bytes) while it runs. */
 fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks);
 
 /* Algorithm newton with Section 6's quasi-Newton scheme: r_k = R(U_k) on the
@@ -496,8 +499,9 @@ fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks);
  * FSI_NEWTON_PC_KEEP, rebuild the preconditioner with the options of the last
  * fsi_build_precond, or the defaults); solve A' delta = r_k by FGMRES to
  * lin_tol; U_{k+1} = U_k - delta.  dU: device, length N: the initial offset
- * on entry, the last iterate's on return.  FSI_NOT_CONVERGED after max_steps
- * steps.  opts/info may be NULL. */
+ * on entry, the last iterate's on return (also on an error, which ends the
+ * loop at the step that failed; A_h then holds the last assembled Jacobian).
+ * FSI_NOT_CONVERGED after max_steps steps.  opts/info may be NULL. */
 fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi_newton_info* info);
 
 #ifdef __cplusplus

@@ -3902,6 +3902,39 @@ static void fe_refresh_host_blocks(fsi_ctx& c) {
   t.done();
 }
 
+// A'(U) into A_h (and, with host_blocks, into the host blocks); on any
+// failure the stored values are restored from a device copy taken first, so
+// the context is left as it was.
+static void fe_jacobian_into_ah(fsi_ctx& c, const double* dU, bool host_blocks) {
+  hipStream_t s = c.stream;
+  AhSlots ah = ah_slots(c);
+  std::vector<std::pair<double*, size_t>> arrays;
+  if (ah.val) arrays.emplace_back(ah.val, c.Ah.val->bytes);
+  for (int q = 0; q < ah.nseg; ++q)
+    if (ah.grp[q] > 1) arrays.emplace_back(ah.grp_val[q], c.Ah.grp_val[q]->bytes);
+  size_t total = 0;
+  for (auto& a : arrays) total += a.second;
+  DevBuf backup;
+  backup.alloc(total);
+  size_t off = 0;
+  for (auto& a : arrays) {
+    HIP_TRY(hipMemcpyAsync(backup.as<char>() + off, a.first, a.second, hipMemcpyDeviceToDevice, s));
+    off += a.second;
+  }
+  try {
+    fe_assemble(c, dU, nullptr, true);
+    if (host_blocks) fe_refresh_host_blocks(c);
+  } catch (...) {
+    off = 0;
+    for (auto& a : arrays) {
+      (void)hipMemcpyAsync(a.first, backup.as<char>() + off, a.second, hipMemcpyDeviceToDevice, s);
+      off += a.second;
+    }
+    (void)hipStreamSynchronize(s);
+    throw;
+  }
+}
+
 // max |x_i| over a device vector (NaN reads as +inf).
 static double device_absmax(fsi_ctx& c, const double* x, int64_t n) {
   FeState& F = *c.fe;
@@ -4034,9 +4067,8 @@ fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks) {
     if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
     if (dU) check_device_ptr(dU, "dU");
     PhaseTimer t("fe_jacobian: A_h assembled on the device");
-    fe_assemble(c, dU, nullptr, true);
+    fe_jacobian_into_ah(c, dU, host_blocks != 0);
     t.done();
-    if (host_blocks) fe_refresh_host_blocks(c);
     return FSI_OK;
   });
 }
@@ -4090,8 +4122,7 @@ fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi
       out.reassembled[k] = assemble ? 1 : 0;
       if (assemble) {
         tic = std::chrono::steady_clock::now();
-        fe_assemble(c, dU, nullptr, true);
-        if (o.precond != FSI_NEWTON_PC_KEEP) fe_refresh_host_blocks(c);
+        fe_jacobian_into_ah(c, dU, o.precond != FSI_NEWTON_PC_KEEP);
         out.t_assemble_ms += ms_since(tic);
         ++out.reassemblies;
         if (o.precond != FSI_NEWTON_PC_KEEP) {

@@ -167,6 +167,13 @@ def test_fe_errors_are_reported():
     with pytest.raises(FsiError) as e:
         g.fe_residual(_dev(dU))
     assert e.value.name == "FSI_ERR_NUMERIC"
+    # a failed Jacobian assembly leaves A_h as it was
+    x = _dev(np.random.default_rng(6).standard_normal(s.N))
+    y0 = g.spmv(x).cpu().numpy()
+    with pytest.raises(FsiError) as e:
+        g.fe_jacobian(_dev(dU), host_blocks=True)
+    assert e.value.name == "FSI_ERR_NUMERIC"
+    assert np.array_equal(g.spmv(x).cpu().numpy(), y0)
     R = g.fe_residual(None).cpu().numpy()  # the context still works
     assert np.max(np.abs(R - P.residual())) <= 1e-12 * np.max(np.abs(R))
     g.close()
