@@ -10,7 +10,7 @@
 // receives f_X[c] phi + sum_k g_X[c][k] d_k phi.  The derivative d out / d q
 // (the derivatives of F, J, F^{-1} of Section 3.3's derivative theorem enter
 // through it) is evaluated by forward-mode dual numbers with one direction
-// per thread: thread i of the workgroup seeds q_i.
+// per thread: the thread of direction i seeds q_i.
 //
 // Launch: one workgroup of 256 threads per (cell, chunk of 32 local test
 // rows), or per cell for the residual alone; the cells of one launch share
@@ -18,9 +18,12 @@
 // launches), so no two cells of a launch share a node and every row is
 // written by one workgroup: plain read-add-write, deterministic.  A thread
 // owns one test row t and the trial columns s = lane + 8 j of the cell matrix
-// in registers across the quadrature loop; the per-point tables (shape
-// values, d out / d q, and DB[s][o] = sum over the inputs of trial s of
-// d out_o / d q_i times its basis value) sit in LDS.  The cell matrix entries
+// in registers across the quadrature loop.  The basis values and the
+// interpolated inputs of every quadrature point are formed once per
+// workgroup; the integrand derivatives for nine points at a time (225
+// (point, direction) pairs in 3D on the 256 threads); then, point by point,
+// DB[s][o] = sum over the inputs of trial s of d out_o / d q_i times its basis
+// value, and the cell-matrix update.  All tables sit in LDS (133 KB in 3D).  The cell matrix entries
 // are added into the stored A_h (its row segments and row groups) at the
 // position of (global row, global column), found by binary search in the
 // row's sorted column list.
@@ -131,6 +134,7 @@ template <int D> struct FeDims {
   static constexpr int NCHUNK = (NLOC + RT - 1) / RT;
   static constexpr int NJ = (NLOC + SL - 1) / SL;
   static constexpr int NFR = 3 * D + D * D;     // interpolated given fields: w, v_old, u_old, grad u_fz
+  static constexpr int QB = 9;                  // points whose integrand derivatives are formed together
 };
 
 template <int D>
@@ -278,10 +282,11 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
   __shared__ double s_f[7 * NV + NQ1];  // v | u | w | v_old | u_old | u_fz (node-major, comp) | p
   __shared__ int64_t s_gd[NLOC];
   __shared__ unsigned char s_ton[NLOC];
-  __shared__ double s_N[NQ2], s_dN[NQ2 * D], s_M[NQ1];
-  __shared__ double s_q[NQ + Q::NFR];
-  __shared__ double s_Dm[NQ * NQ];  // s_Dm[o * NQ + i] = d out_o / d q_i
-  __shared__ double s_ov[NQ];
+  constexpr int NPT = Q::NVOL + Q::NFACE, NIN = NQ + Q::NFR, QB = Q::QB;
+  __shared__ double s_N[NPT * NQ2], s_dN[NPT * NQ2 * D], s_M[NPT * NQ1], s_w[NPT];  // every point
+  __shared__ double s_q[NPT * NIN];     // inputs q and the given fields at every point
+  __shared__ double s_Dm[QB * NQ * NQ];  // per point of a batch: s_Dm[o * NQ + i] = d out_o / d q_i
+  __shared__ double s_ov[QB * NQ];
   __shared__ double s_DB[NLOC * NQ];
   __shared__ int s_cellflag;
   const int tid = threadIdx.x;
@@ -356,10 +361,12 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
   const double gx[3] = {0.5 - 0.38729833462074168852, 0.5, 0.5 + 0.38729833462074168852};
   const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
   const int npts = Q::NVOL + (outflow ? Q::NFACE : 0);
-  for (int ip = 0; ip < npts; ++ip) {
-    const bool face = ip >= Q::NVOL;
+  // basis values and weights at every point: volume points, then the
+  // outflow face x_0 = 1 (reference coordinates)
+  for (int job = tid; job < npts * (NQ2 + NQ1); job += blockDim.x) {
+    const int ip = job / (NQ2 + NQ1), l = job % (NQ2 + NQ1);
     double xi[3] = {0.0, 0.0, 0.0}, w = 1.0;
-    if (!face) {
+    if (ip < Q::NVOL) {
       int r = ip;
       for (int a = 0; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
     } else {
@@ -367,76 +374,86 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
       xi[0] = 1.0;
       for (int a = 1; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
     }
-    // basis values at the point
-    if (tid < NQ2) {
+    if (l < NQ2) {
       double n1[3][3], d1[3][3];
       for (int a = 0; a < D; ++a) q2_basis(xi[a], n1[a], d1[a]);
-      int ia[3], r = tid;
+      int ia[3], r = l;
       for (int a = 0; a < D; ++a) { ia[a] = r % 3; r /= 3; }
       double prod = 1.0;
       for (int a = 0; a < D; ++a) prod *= n1[a][ia[a]];
-      s_N[tid] = prod;
+      s_N[ip * NQ2 + l] = prod;
       for (int k = 0; k < D; ++k) {
         double g = d1[k][ia[k]] / P.h[k];
         for (int a = 0; a < D; ++a)
           if (a != k) g *= n1[a][ia[a]];
-        s_dN[tid * D + k] = g;
+        s_dN[(ip * NQ2 + l) * D + k] = g;
       }
-    } else if (tid < NQ2 + NQ1) {
-      int r = tid - NQ2;
+      if (l == 0) s_w[ip] = w;
+    } else {
+      int r = l - NQ2;
       double prod = 1.0;
       for (int a = 0; a < D; ++a) { prod *= (r % 2) ? xi[a] : 1.0 - xi[a]; r /= 2; }
-      s_M[tid - NQ2] = prod;
+      s_M[ip * NQ1 + (l - NQ2)] = prod;
     }
-    __syncthreads();
-    // interpolated inputs q and given fields
-    if (tid < NQ + Q::NFR) {
-      double s = 0.0;
-      if (tid < NQ) {
-        const int i = tid;
-        if (i == Q::QP) {
-          for (int l = 0; l < NQ1; ++l) s += s_M[l] * s_f[6 * NV + l];
-        } else {
-          const bool vel = i < Q::QU;
-          const int j = vel ? i : i - Q::QU;  // 0..D-1 value, D.. gradient
-          const double* f = s_f + (vel ? 0 : NV);
-          if (j < D) {
-            for (int l = 0; l < NQ2; ++l) s += s_N[l] * f[l * D + j];
-          } else {
-            const int c = (j - D) / D, k = (j - D) % D;
-            for (int l = 0; l < NQ2; ++l) s += s_dN[l * D + k] * f[l * D + c];
-          }
-        }
+  }
+  __syncthreads();
+  // interpolated inputs q and given fields at every point
+  for (int job = tid; job < npts * NIN; job += blockDim.x) {
+    const int ip = job / NIN, i = job % NIN;
+    const double* N = s_N + ip * NQ2;
+    const double* dN = s_dN + ip * NQ2 * D;
+    double s = 0.0;
+    if (i < NQ) {
+      if (i == Q::QP) {
+        for (int l = 0; l < NQ1; ++l) s += s_M[ip * NQ1 + l] * s_f[6 * NV + l];
       } else {
-        const int j = tid - NQ;
-        if (j < 3 * D) {  // w, v_old, u_old
-          const double* f = s_f + (2 + j / D) * NV;
-          const int c = j % D;
-          for (int l = 0; l < NQ2; ++l) s += s_N[l] * f[l * D + c];
-        } else {          // grad u_fz
-          const int c = (j - 3 * D) / D, k = (j - 3 * D) % D;
-          for (int l = 0; l < NQ2; ++l) s += s_dN[l * D + k] * s_f[5 * NV + l * D + c];
+        const bool vel = i < Q::QU;
+        const int j = vel ? i : i - Q::QU;  // 0..D-1 value, D.. gradient
+        const double* f = s_f + (vel ? 0 : NV);
+        if (j < D) {
+          for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + j];
+        } else {
+          const int c = (j - D) / D, k = (j - D) % D;
+          for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * f[l * D + c];
         }
       }
-      s_q[tid] = s;
+    } else {
+      const int j = i - NQ;
+      if (j < 3 * D) {  // w, v_old, u_old
+        const double* f = s_f + (2 + j / D) * NV;
+        const int c = j % D;
+        for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + c];
+      } else {          // grad u_fz
+        const int c = (j - 3 * D) / D, k = (j - 3 * D) % D;
+        for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * s_f[5 * NV + l * D + c];
+      }
     }
-    __syncthreads();
-    // d out / d q_i, one direction per thread (the values alone for a residual)
-    if (tid < (want_mat ? NQ : 1)) {
+    s_q[ip * NIN + i] = s;
+  }
+  __syncthreads();
+  for (int b0 = 0; b0 < npts; b0 += QB) {
+    const int nb = npts - b0 < QB ? npts - b0 : QB;
+    // d out / d q_i at the batch's points, one (point, direction) per thread
+    // (the values alone for a residual)
+    const int ndir = want_mat ? NQ : 1;
+    for (int job = tid; job < nb * ndir; job += blockDim.x) {
+      const int jb = job / ndir, dir = job % ndir, ip = b0 + jb;
+      const double* qv = s_q + ip * NIN;
       Dn qd[NQ], out[NQ];
-      for (int i = 0; i < NQ; ++i) qd[i] = Dn{s_q[i], i == tid ? 1.0 : 0.0};
-      const int kind = face ? 2 : (solid ? 1 : 0);
-      fe_integrand<D>(kind, qd, s_q + NQ, P, out);
-      for (int o = 0; o < NQ; ++o) s_Dm[o * NQ + tid] = out[o].d;
-      if (tid == 0) {
-        for (int o = 0; o < NQ; ++o) s_ov[o] = out[o].v;
+      for (int i = 0; i < NQ; ++i) qd[i] = Dn{qv[i], (want_mat && i == dir) ? 1.0 : 0.0};
+      const bool face = ip >= Q::NVOL;
+      fe_integrand<D>(face ? 2 : (solid ? 1 : 0), qd, qv + NQ, P, out);
+      if (want_mat)
+        for (int o = 0; o < NQ; ++o) s_Dm[jb * NQ * NQ + o * NQ + dir] = out[o].d;
+      if (dir == 0) {
+        for (int o = 0; o < NQ; ++o) s_ov[jb * NQ + o] = out[o].v;
         // J of the current state and of the mesh-stiffness field must stay positive
         if (!solid && !face) {
           double Fv[D][D], Fz[D][D];
           for (int c = 0; c < D; ++c)
             for (int k = 0; k < D; ++k) {
-              Fv[c][k] = s_q[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
-              Fz[c][k] = s_q[NQ + 3 * D + c * D + k] + (c == k ? 1.0 : 0.0);
+              Fv[c][k] = qv[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
+              Fz[c][k] = qv[NQ + 3 * D + c * D + k] + (c == k ? 1.0 : 0.0);
             }
           double Jv, Jz;
           if constexpr (D == 2) {
@@ -450,66 +467,76 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
                  Fz[0][1] * (Fz[1][0] * Fz[2][2] - Fz[1][2] * Fz[2][0]) +
                  Fz[0][2] * (Fz[1][0] * Fz[2][1] - Fz[1][1] * Fz[2][0]);
           }
-          if (!(Jv > 0.0) || !(Jz > 0.0)) s_cellflag |= 1;
+          if (!(Jv > 0.0) || !(Jz > 0.0)) atomicOr(&s_cellflag, 1);
         }
       }
     }
     __syncthreads();
-    // residual of this workgroup's test rows
-    if (want_res && sl == 0 && row_on) {
-      if (t < 2 * NV) {
-        const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
-        const int l = (t % NV) / D, c = (t % NV) % D;
-        double s = s_ov[fo + c] * s_N[l];
-        for (int k = 0; k < D; ++k) s += s_ov[go + c * D + k] * s_dN[l * D + k];
-        res += w * s;
-      } else {
-        res += w * s_ov[Q::QP] * s_M[t - 2 * NV];
-      }
-    }
-    if (want_mat) {
-      for (int idx = tid; idx < NLOC * NQ; idx += blockDim.x) {
-        const int s = idx / NQ, o = idx % NQ;
-        double val = 0.0;
-        if (s_gd[s] >= 0) {
-          if (s < 2 * NV) {
-            const int fi = s < NV ? Q::QV : Q::QU, gi = s < NV ? Q::QGV : Q::QGU;
-            const int l = (s % NV) / D, e = (s % NV) % D;
-            val = s_Dm[o * NQ + fi + e] * s_N[l];
-            for (int k = 0; k < D; ++k) val += s_Dm[o * NQ + gi + e * D + k] * s_dN[l * D + k];
-          } else {
-            val = s_Dm[o * NQ + Q::QP] * s_M[s - 2 * NV];
-          }
-        }
-        s_DB[idx] = val;
-      }
-      __syncthreads();
-      if (row_on) {
+    for (int jb = 0; jb < nb; ++jb) {
+      const int ip = b0 + jb;
+      const double w = s_w[ip];
+      const double* N = s_N + ip * NQ2;
+      const double* dN = s_dN + ip * NQ2 * D;
+      const double* M = s_M + ip * NQ1;
+      const double* ov = s_ov + jb * NQ;
+      const double* Dm = s_Dm + jb * NQ * NQ;
+      // residual of this workgroup's test rows
+      if (want_res && sl == 0 && row_on) {
         if (t < 2 * NV) {
           const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
           const int l = (t % NV) / D, c = (t % NV) % D;
-          double tw[4];
-          tw[0] = w * s_N[l];
-          for (int k = 0; k < D; ++k) tw[1 + k] = w * s_dN[l * D + k];
-          for (int j = 0; j < Q::NJ; ++j) {
-            const int s = sl + Q::SL * j;
-            if (s >= NLOC) break;
-            const double* db = s_DB + s * NQ;
-            double v = tw[0] * db[fo + c];
-            for (int k = 0; k < D; ++k) v += tw[1 + k] * db[go + c * D + k];
-            acc[j] += v;
-          }
+          double s = ov[fo + c] * N[l];
+          for (int k = 0; k < D; ++k) s += ov[go + c * D + k] * dN[l * D + k];
+          res += w * s;
         } else {
-          const double tw = w * s_M[t - 2 * NV];
-          for (int j = 0; j < Q::NJ; ++j) {
-            const int s = sl + Q::SL * j;
-            if (s >= NLOC) break;
-            acc[j] += tw * s_DB[s * NQ + Q::QP];
-          }
+          res += w * ov[Q::QP] * M[t - 2 * NV];
         }
       }
+      if (want_mat) {
+        for (int idx = tid; idx < NLOC * NQ; idx += blockDim.x) {
+          const int s = idx / NQ, o = idx % NQ;
+          double val = 0.0;
+          if (s_gd[s] >= 0) {
+            if (s < 2 * NV) {
+              const int fi = s < NV ? Q::QV : Q::QU, gi = s < NV ? Q::QGV : Q::QGU;
+              const int l = (s % NV) / D, e = (s % NV) % D;
+              val = Dm[o * NQ + fi + e] * N[l];
+              for (int k = 0; k < D; ++k) val += Dm[o * NQ + gi + e * D + k] * dN[l * D + k];
+            } else {
+              val = Dm[o * NQ + Q::QP] * M[s - 2 * NV];
+            }
+          }
+          s_DB[idx] = val;
+        }
+        __syncthreads();
+        if (row_on) {
+          if (t < 2 * NV) {
+            const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
+            const int l = (t % NV) / D, c = (t % NV) % D;
+            double tw[4];
+            tw[0] = w * N[l];
+            for (int k = 0; k < D; ++k) tw[1 + k] = w * dN[l * D + k];
+            for (int j = 0; j < Q::NJ; ++j) {
+              const int s = sl + Q::SL * j;
+              if (s >= NLOC) break;
+              const double* db = s_DB + s * NQ;
+              double v = tw[0] * db[fo + c];
+              for (int k = 0; k < D; ++k) v += tw[1 + k] * db[go + c * D + k];
+              acc[j] += v;
+            }
+          } else {
+            const double tw = w * M[t - 2 * NV];
+            for (int j = 0; j < Q::NJ; ++j) {
+              const int s = sl + Q::SL * j;
+              if (s >= NLOC) break;
+              acc[j] += tw * s_DB[s * NQ + Q::QP];
+            }
+          }
+        }
+        __syncthreads();
+      }
     }
-    __syncthreads();
+    __syncthreads();  // the next batch overwrites the derivative tables
   }
   int bad = 0;
   if (row_on) {
