@@ -209,6 +209,24 @@ struct RowSegments {
   int nseg;
 };
 
+// Workgroups are handed to the 8 XCDs round-robin by index.  Within a range
+// [b0, b0 + n) of workgroups, renumber them so that the ones an XCD receives
+// take one contiguous run of the range (sizes differ by at most one): rows
+// that share columns then share that XCD's L2, and every XCD still gets an
+// equal share of each range.  A bijection of [0, n).
+__device__ __forceinline__ unsigned xcd_contiguous(unsigned b, unsigned b0, unsigned n) {
+  constexpr unsigned kXcd = 8;
+  const unsigned x = b % kXcd;
+  unsigned before = 0, first = 0;
+  for (unsigned y = 0; y < kXcd; ++y) {
+    const unsigned off = (y + kXcd - b0 % kXcd) % kXcd;  // first workgroup of the range on XCD y
+    const unsigned cnt = n > off ? (n - off + kXcd - 1) / kXcd : 0;
+    if (y < x) before += cnt;
+    if (y == x) first = b0 + off;
+  }
+  return before + (b - first) / kXcd;
+}
+
 template <typename T, int G, class Gather, class Epi>
 __device__ __forceinline__ void segment_rows(int64_t r0, int64_t r1, unsigned blk, const int64_t* __restrict__ rp,
                                              const int32_t* __restrict__ ci, const T* __restrict__ val,
@@ -265,7 +283,7 @@ __global__ __launch_bounds__(kBlock) void csr_segments_kernel(RowSegments sg, co
                                                                const T* __restrict__ val, Gather gx, Epi epi) {
   int s = 0;
   while (s + 1 < sg.nseg && blockIdx.x >= sg.blk0[s + 1]) ++s;
-  const unsigned blk = blockIdx.x - sg.blk0[s];
+  const unsigned blk = xcd_contiguous(blockIdx.x, sg.blk0[s], sg.blk0[s + 1] - sg.blk0[s]);
   switch (sg.g[s]) {
     case 4: segment_any<T, 4>(sg, s, blk, rp, ci, val, gx, epi); break;
     case 8: segment_any<T, 8>(sg, s, blk, rp, ci, val, gx, epi); break;
@@ -289,7 +307,9 @@ __global__ __launch_bounds__(kBlock) void vdown_kernel(
   T acc[NV];
 #pragma unroll
   for (int n = 0; n < NV; ++n) acc[n] = T(0);
-  const unsigned blk = blockIdx.x;
+  // each of the two row sets is spread over the XCDs in contiguous runs
+  const unsigned blk = blockIdx.x < nblk_a ? xcd_contiguous(blockIdx.x, 0, nblk_a)
+                                           : nblk_a + xcd_contiguous(blockIdx.x, nblk_a, gridDim.x - nblk_a);
   if (blk < nblk_a) {
     const int64_t row = int64_t(blk) * (kBlock / GA) + threadIdx.x / GA;
     const int lane = threadIdx.x % GA;
@@ -325,7 +345,7 @@ __global__ __launch_bounds__(kBlock) void vup_kernel(
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
     const T* __restrict__ e, const T* b, Diag<T> dinv, T omega, const T* __restrict__ r, T* y) {
   constexpr int RPB = kBlock / G;
-  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int64_t row = int64_t(xcd_contiguous(blockIdx.x, 0, gridDim.x)) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
   T ap[NV], pe[NV], bi[NV], ri[NV];
@@ -361,7 +381,8 @@ __global__ __launch_bounds__(kBlock) void vdown_grp_kernel(
   T acc[GR];
 #pragma unroll
   for (int q = 0; q < GR; ++q) acc[q] = T(0);
-  const unsigned blk = blockIdx.x;
+  const unsigned blk = blockIdx.x < nblk_a ? xcd_contiguous(blockIdx.x, 0, nblk_a)
+                                           : nblk_a + xcd_contiguous(blockIdx.x, nblk_a, gridDim.x - nblk_a);
   const GatherPlain<T, 1> gb{b};
   if (blk < nblk_a) {
     const int64_t grp = int64_t(blk) * (kBlock / GA) + threadIdx.x / GA;
@@ -394,7 +415,7 @@ __global__ __launch_bounds__(kBlock) void vup_grp_kernel(
     int64_t n, const int64_t* __restrict__ rpp, const int32_t* __restrict__ cip, const T* __restrict__ vp,
     const int64_t* __restrict__ rpap, const int32_t* __restrict__ ciap, const T* __restrict__ vap,
     const T* __restrict__ e, const T* b, Diag<T> dinv, T omega, const T* __restrict__ r, T* y) {
-  const int64_t grp = int64_t(blockIdx.x) * (kBlock / G) + threadIdx.x / G;
+  const int64_t grp = int64_t(xcd_contiguous(blockIdx.x, 0, gridDim.x)) * (kBlock / G) + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   const int64_t row = grp * GR;
   if (row >= n) return;
@@ -628,7 +649,7 @@ __global__ __launch_bounds__(kBlock) void cheb_step_kernel(int64_t n, const int6
                                                             T* __restrict__ dout, T* __restrict__ rout, T* x,
                                                             int xinit, int fuse, T a2, T c2) {
   constexpr int RPB = kBlock / G;
-  const int64_t row = int64_t(blockIdx.x) * RPB + threadIdx.x / G;
+  const int64_t row = int64_t(xcd_contiguous(blockIdx.x, 0, gridDim.x)) * RPB + threadIdx.x / G;
   const int lane = threadIdx.x % G;
   if (row >= n) return;
   T acc[NV], dj[NV], rp0[NV], xi[NV];
