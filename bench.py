@@ -35,13 +35,13 @@ HBM_PEAK_GBS = 8000.0
 # 256 MiB device copy in the same runs); see profiles/a_h_spmv_hbm_traffic.md.
 # Valid only for the kernel and workload it was measured on (empty: the
 # kernel changed since the counters were taken).
-MEASURED_TRAFFIC = {"c2": 174369840, "c3": 1875711563, "c4": 15873201262}
+MEASURED_TRAFFIC = {"c2": 155605299, "c3": 1752204761, "c4": 15363719875}
 # The same for one H_A V-cycle of the benchmark preconditioner (bench.py
 # --pmc-vcycle); see profiles/h_a_vcycle_hbm_traffic.md.
 # Keyed by workload: (traffic, the cycle's bytes as stored when measured); a
 # hierarchy of other bytes (other AMG options) has no figure.
-MEASURED_VCYCLE_TRAFFIC = {"c2": (129161151, 108663072), "c3": (1356138742, 1279777388),
-                           "c4": (9589515807, 9096401408)}
+MEASURED_VCYCLE_TRAFFIC = {"c2": (115217321, 108663072), "c3": (1306569344, 1279777388),
+                           "c4": (9351010137, 9096401408)}
 DTYPE = {"f64": "f64", "f32": "f64-krylov/f32-precond", "f32-bf16diag": "f64-krylov/f32-precond/bf16-diag"}
 METRIC = "FGMRES time-to-solution per Newton solve @1e-8 resid; SpMV/V-cycle HBM GB/s"
 
