@@ -3,9 +3,15 @@
 What is computed.  The nonlinear residual of the monolithic ALE-FSI problem
 of Section 3: the semi-linear form A(U)(Phi) minus the linear form F(Phi),
 i.e. the sum of the variational equations (equation fsi:all), for one time
-step of the one-step-theta scheme (Section 3.2) with theta = 1, and its
-Jacobian A'(U) -- the matrix of the Newton step (Algorithm newton, Section
-3.3).  Unknowns and test functions (Section 3.1):
+step of the one-step-theta scheme (Section 3.2), and its Jacobian A'(U) --
+the matrix of the Newton step (Algorithm newton, Section 3.3).  The terms
+below are those of theta = 1; for theta < 1 the convection, viscous stress,
+outflow correction and solid stress carry dt theta at the new level and
+dt (1 - theta) at the previous one (its velocity advecting itself), the fluid
+mass term J^theta = theta J + (1 - theta) J_old, the kinematics
+dt (theta v + (1 - theta) v_old); pressure, mesh velocity, incompressibility
+and mesh motion stay implicit (the paper treats the pressure implicitly for
+every theta).  Unknowns and test functions (Section 3.1):
 
 * fluid cells -- momentum in ALE form
     ( rho J (v - v_old), phi ) + dt theta ( rho J (grad v F^{-1}) w, phi )
@@ -114,6 +120,8 @@ class Material:
     lambda_s: float
     dt_theta: float
     newton_mesh: bool
+    theta: float = 1.0
+    dt: float = 0.0
 
 
 class FeProblem:
@@ -128,15 +136,15 @@ class FeProblem:
     """
 
     def __init__(self, cfg, fe: dict, N: int):
-        if cfg.theta != 1.0:
-            raise ValueError("theta = 1 only")
+        if not (0.0 < cfg.theta <= 1.0):
+            raise ValueError("theta must lie in (0, 1]")
         D = self.D = int(cfg.dim)
         nc = np.array(cfg.cells[:D])
         h = np.array(cfg.extent[:D], float) / nc
         NN = 2 * nc + 1
         self.N, self.h, self.nc = int(N), h, nc
         self.mat = Material(cfg.rho_f, cfg.nu_f, cfg.rho_s, cfg.mu_s, cfg.lambda_s, cfg.dt * cfg.theta,
-                            bool(cfg.newton_mesh))
+                            bool(cfg.newton_mesh), float(cfg.theta), float(cfg.dt))
         self.fe = fe
         # cells, row-major over (C_0, ..., C_{D-1})
         C = np.stack(np.meshgrid(*[np.arange(n) for n in nc], indexing="ij"), -1).reshape(-1, D)
@@ -246,6 +254,30 @@ class FeProblem:
         gV_s = m.dt_theta * _mm(F, Ss)
         fV_s = m.rho_s * (vq - vo)
         fU_s = (uq - uo) - m.dt_theta * vq
+        if m.theta < 1.0:
+            # the one-step-theta scheme (Section 3.2): the explicit share (1 - theta) dt of the
+            # convection, viscous stress and solid stress at the previous level (the previous
+            # velocity advecting itself), J^theta = theta J + (1 - theta) J_old in the fluid mass
+            # term, and (1 - theta) dt v_old in the kinematics; pressure, mesh velocity,
+            # incompressibility and mesh motion stay implicit
+            dto = (1.0 - m.theta) * m.dt
+            Gvo = np.einsum("qlk,cld->cqdk", dN, fe["v_old"][nodes])
+            Guo = np.einsum("qlk,cld->cqdk", dN, fe["u_old"][nodes])
+            Fo = I + Guo
+            Jo = _det(Fo)
+            Fio = _inv(Fo, Jo)
+            GFo = _mm(Gvo, Fio)
+            Jth = m.theta * J + (1.0 - m.theta) * Jo
+            fV_f = (m.rho_f * Jth[..., None] * (vq - vo)
+                    + m.dt_theta * m.rho_f * J[..., None] * np.einsum("cqdk,cqk->cqd", GF, wq)
+                    - m.rho_f * J[..., None] * np.einsum("cqdk,cqk->cqd", GF, uq - uo)
+                    + dto * m.rho_f * Jo[..., None] * np.einsum("cqdk,cqk->cqd", GFo, vo))
+            sigo = dto * m.rho_f * m.nu_f * (GFo + _T(GFo))
+            gV_f = gV_f + Jo[..., None, None] * _mm(sigo, _T(Fio))
+            Eo = 0.5 * (_mm(_T(Fo), Fo) - I)
+            So = 2.0 * m.mu_s * Eo + m.lambda_s * np.trace(Eo, axis1=-2, axis2=-1)[..., None, None] * I
+            gV_s = gV_s + dto * _mm(Fo, So)
+            fU_s = fU_s - dto * vo
         sol = solid[:, None]
         fV = np.where(sol[..., None], fV_s, fV_f)
         gV = np.where(sol[..., None, None], gV_s, gV_f)
@@ -270,6 +302,16 @@ class FeProblem:
             b = np.einsum("cqmk,cqm->cqk", Gvf, a)          # grad v^T F^{-T} n
             t = np.einsum("cqdk,cqk->cqd", _T(Fif), b)      # F^{-T} grad v^T F^{-T} n
             fO = -m.dt_theta * m.rho_f * m.nu_f * Jf[..., None] * t
+            if m.theta < 1.0:  # the previous level's share of the outflow correction
+                no = nodes[out]
+                Gvfo = np.einsum("qlk,cld->cqdk", dNf, fe["v_old"][no])
+                Ffo = I + np.einsum("qlk,cld->cqdk", dNf, fe["u_old"][no])
+                Jfo = _det(Ffo)
+                Fifo = _inv(Ffo, Jfo)
+                ao = np.einsum("cqkm,m->cqk", _T(Fifo), n)
+                bo = np.einsum("cqmk,cqm->cqk", Gvfo, ao)
+                to = np.einsum("cqdk,cqk->cqd", _T(Fifo), bo)
+                fO = fO - (1.0 - m.theta) * m.dt * m.rho_f * m.nu_f * Jfo[..., None] * to
             Rv[out] = Rv[out] + np.einsum("q,cqd,ql->cld", wf, fO, Nf)
         nc = v.shape[0]
         return np.concatenate([Rv.reshape(nc, -1), Ru.reshape(nc, -1), Rp], axis=1)
@@ -323,6 +365,23 @@ def rows_covered(prob: FeProblem, cells) -> np.ndarray:
     sel = np.asarray(cells)
     np.add.at(part, prob.gd[sel][prob.test[sel]], 1)
     return np.nonzero((total > 0) & (part == total))[0]
+
+
+def advance(prob: FeProblem, dU) -> dict:
+    """The node fields of the next time step after a converged step: the state
+    becomes the previous level and the linearisation fields (v_old, u_old, w,
+    u_fz and the state v, u, p all take the new values; constrained dofs keep
+    theirs)."""
+    fe, D = prob.fe, prob.D
+    new = {k: np.array(fe[k], copy=True) for k in fe}
+    for key, dof in (("v", "vdof"), ("u", "udof")):
+        idx = fe[dof] >= 0
+        new[key][idx] = fe[key][idx] + np.asarray(dU)[fe[dof][idx][:, None] + np.arange(D)]
+    idx = fe["pdof"] >= 0
+    new["p"][idx] = fe["p"][idx] + np.asarray(dU)[fe["pdof"][idx]]
+    new["v_old"], new["u_old"] = new["v"].copy(), new["u"].copy()
+    new["w"], new["u_fz"] = new["v"].copy(), new["u"].copy()
+    return new
 
 
 def max_norm(r) -> float:
