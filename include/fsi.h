@@ -405,7 +405,7 @@ fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_t
  *
  * Section 3: the discrete residual R(U) = A(U)(Phi) - F(Phi) of the monolithic
  * ALE-FSI problem (the sum of the variational equations, equation fsi:all,
- * one step of the one-step-theta scheme with theta = 1) on the structured
+ * one step of the one-step-theta scheme of Section 3.2) on the structured
  * channel of Q2 velocity / displacement and Q1 pressure quads (d = 2) or hexes
  * (d = 3), every integral by the tensor 3-point Gauss rule, the outflow term
  * on the face x_0 = extent[0]; and its Jacobian A'(U), the matrix of the
@@ -417,6 +417,12 @@ fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_t
  * mesh stiffness are given fields (with newton_mesh the stiffness uses the
  * current J instead).  Mesh-equation test functions vanish on nodes of solid
  * cells (the interface), velocity test functions on Dirichlet nodes.
+ * With theta < 1 the convection, viscous stress, outflow correction and solid
+ * stress carry dt theta at the new level and dt (1 - theta) at the previous
+ * one (v_old, u_old; v_old advecting itself), the fluid mass term uses
+ * theta J + (1 - theta) J_old and the kinematics dt (theta v + (1 - theta)
+ * v_old); pressure, mesh velocity, incompressibility and mesh motion stay
+ * implicit (theta = 1/2: Crank-Nicolson, 1/2 + dt: its shifted variant).
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t dim;                 /* 2 or 3: the system's d                                   */
@@ -425,7 +431,7 @@ typedef struct {
   int32_t solid_lo[3];         /* solid cells: solid_lo[a] <= C[a] < solid_hi[a], all a    */
   int32_t solid_hi[3];
   double rho_f, nu_f, rho_s, mu_s, lambda_s;  /* fluid density, viscosity; solid density, Lame */
-  double dt, theta;            /* theta must be 1; dt * theta must equal the layout's      */
+  double dt, theta;            /* theta in (0, 1]; dt * theta must equal the layout's       */
   int32_t newton_mesh;         /* 1: 1/J of the mesh equation from the current state       */
   int32_t pad;
   int64_t n_nodes;             /* prod_a (2 cells[a] + 1): the Q2 lattice, row-major,
@@ -503,6 +509,22 @@ fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks);
  * loop at the step that failed; A_h then holds the last assembled Jacobian).
  * FSI_NOT_CONVERGED after max_steps steps.  opts/info may be NULL. */
 fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi_newton_info* info);
+
+/* End a time step (Section 3.2): the state U = fields + dU (dU: device,
+ * length N) becomes the fields of the next step and its previous level
+ * (v_old, u_old), the advecting velocity w and the mesh-stiffness
+ * displacement u_fz; constrained dofs keep their values. */
+fsi_status fsi_fe_advance(fsi_ctx* ctx, const double* dU);
+
+/* One time step: fsi_newton from dU = 0, then, once it converged,
+ * fsi_fe_advance with its iterate (not on FSI_NOT_CONVERGED: the fields are
+ * then unchanged).  The system's pattern and dt * theta carry over; the
+ * preconditioner follows opts.precond.  opts/info may be NULL. */
+fsi_status fsi_time_step(fsi_ctx* ctx, const fsi_newton_opts* opts, fsi_newton_info* info);
+
+/* Copy the current state fields to host arrays: v and u (n_nodes * d,
+ * component-interleaved), p (n_nodes). */
+fsi_status fsi_fe_get_fields(fsi_ctx* ctx, double* v, double* u, double* p);
 
 #ifdef __cplusplus
 }

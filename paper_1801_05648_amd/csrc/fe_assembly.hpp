@@ -42,6 +42,7 @@ struct FeParams {
   double h[3];     // cell size per axis
   int solid_lo[3], solid_hi[3];  // solid cells: solid_lo <= C < solid_hi on every axis
   double rho_f, nu_f, rho_s, mu_s, lambda_s, dtth;
+  double theta, dt;  // one-step-theta scheme: dtth = dt theta; dt (1 - theta) at the previous level
   int newton_mesh;  // 1: the mesh stiffness 1/J uses the current J (else the given u_fz's)
 };
 
@@ -133,7 +134,8 @@ template <int D> struct FeDims {
   static constexpr int RT = 32, SL = 8;         // test rows per workgroup, trial lanes per row
   static constexpr int NCHUNK = (NLOC + RT - 1) / RT;
   static constexpr int NJ = (NLOC + SL - 1) / SL;
-  static constexpr int NFR = 3 * D + D * D;     // interpolated given fields: w, v_old, u_old, grad u_fz
+  // interpolated given fields: w, v_old, u_old, grad u_fz, grad v_old, grad u_old
+  static constexpr int NFR = 3 * D + 3 * D * D;
   static constexpr int QB = 9;                  // points whose integrand derivatives are formed together
 };
 
@@ -168,11 +170,53 @@ __device__ __forceinline__ void inv_d(const Dn (&F)[D][D], Dn J, Dn (&G)[D][D]) 
 }
 
 // The integrand at one quadrature point.  kind: 0 fluid cell, 1 solid cell,
-// 2 outflow face (normal e_0).  fr: w[D] | v_old[D] | u_old[D] | grad u_fz[D][D].
+// 2 outflow face (normal e_0).  fr: w[D] | v_old[D] | u_old[D] | grad u_fz[D][D]
+// | grad v_old[D][D] | grad u_old[D][D].  With theta < 1 the previous level's
+// explicit share (Section 3.2) enters as constants: dt (1 - theta) times the
+// convection (the previous velocity advecting itself), viscous stress, outflow
+// correction and solid stress of v_old, u_old; the fluid mass term takes
+// theta J + (1 - theta) J_old and the kinematics dt (theta v + (1 - theta) v_old).
+template <int D>
+__device__ __forceinline__ double det_plain(const double (&F)[D][D]) {
+  if constexpr (D == 2) {
+    return F[0][0] * F[1][1] - F[0][1] * F[1][0];
+  } else {
+    return F[0][0] * (F[1][1] * F[2][2] - F[1][2] * F[2][1]) - F[0][1] * (F[1][0] * F[2][2] - F[1][2] * F[2][0]) +
+           F[0][2] * (F[1][0] * F[2][1] - F[1][1] * F[2][0]);
+  }
+}
+
+// The previous level's F_old = I + grad u_old, J_old and F_old^{-1} (plain values).
+template <int D>
+__device__ __forceinline__ double previous_level(const double* fr, double (&Fo)[D][D], double (&Fio)[D][D]) {
+  const double* gu = fr + 3 * D + 2 * D * D;
+  for (int c = 0; c < D; ++c)
+    for (int k = 0; k < D; ++k) Fo[c][k] = gu[c * D + k] + (c == k ? 1.0 : 0.0);
+  const double Jo = det_plain<D>(Fo);
+  if constexpr (D == 2) {
+    Fio[0][0] = Fo[1][1] / Jo;
+    Fio[0][1] = -Fo[0][1] / Jo;
+    Fio[1][0] = -Fo[1][0] / Jo;
+    Fio[1][1] = Fo[0][0] / Jo;
+  } else {
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const int r0 = j == 0 ? 1 : 0, r1 = j == 2 ? 1 : 2;
+        const int c0 = i == 0 ? 1 : 0, c1 = i == 2 ? 1 : 2;
+        const double m = Fo[r0][c0] * Fo[r1][c1] - Fo[r0][c1] * Fo[r1][c0];
+        Fio[i][j] = ((i + j) % 2 == 0 ? m : -m) / Jo;
+      }
+  }
+  return Jo;
+}
+
 template <int D>
 __device__ void fe_integrand(int kind, const Dn* q, const double* fr, const FeParams& P, Dn* out) {
   using Q = FeDims<D>;
   for (int o = 0; o < Q::NQ; ++o) out[o] = dn(0.0);
+  const bool explicit_share = P.theta < 1.0;
+  const double dto = (1.0 - P.theta) * P.dt;
+  const double* gvo = fr + 3 * D + D * D;  // grad v_old
   Dn F[D][D], Fi[D][D];
   for (int c = 0; c < D; ++c)
     for (int k = 0; k < D; ++k) F[c][k] = q[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
@@ -203,6 +247,26 @@ __device__ void fe_integrand(int kind, const Dn* q, const double* fr, const FePa
       out[Q::QV + c] = P.rho_s * (q[Q::QV + c] - fr[D + c]);
       out[Q::QU + c] = (q[Q::QU + c] - fr[2 * D + c]) - P.dtth * q[Q::QV + c];
     }
+    if (explicit_share) {
+      double Fo[D][D], Fio[D][D], Eo[D][D];
+      (void)previous_level<D>(fr, Fo, Fio);
+      double tro = 0.0;
+      for (int c = 0; c < D; ++c)
+        for (int k = 0; k < D; ++k) {
+          double s = 0.0;
+          for (int m = 0; m < D; ++m) s += Fo[m][c] * Fo[m][k];
+          Eo[c][k] = 0.5 * (s - (c == k ? 1.0 : 0.0));
+        }
+      for (int c = 0; c < D; ++c) tro += Eo[c][c];
+      for (int c = 0; c < D; ++c) {
+        for (int k = 0; k < D; ++k) {
+          double s = 0.0;
+          for (int m = 0; m < D; ++m) s += Fo[c][m] * ((2.0 * P.mu_s) * Eo[m][k] + (m == k ? P.lambda_s * tro : 0.0));
+          out[Q::QGV + c * D + k] = out[Q::QGV + c * D + k] + dto * s;
+        }
+        out[Q::QU + c] = out[Q::QU + c] - dto * fr[D + c];
+      }
+    }
     return;
   }
   inv_d<D>(F, J, Fi);
@@ -221,6 +285,20 @@ __device__ void fe_integrand(int kind, const Dn* q, const double* fr, const FePa
       for (int k = 1; k < D; ++k) s = s + Fi[k][c] * b[k];
       out[Q::QV + c] = coef * (J * s);
     }
+    if (explicit_share) {
+      double Fo[D][D], Fio[D][D], bo[D];
+      const double Jo = previous_level<D>(fr, Fo, Fio);
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < D; ++m) s += gvo[m * D + k] * Fio[0][m];
+        bo[k] = s;
+      }
+      for (int c = 0; c < D; ++c) {
+        double s = 0.0;
+        for (int k = 0; k < D; ++k) s += Fio[k][c] * bo[k];
+        out[Q::QV + c] = out[Q::QV + c] - (dto * P.rho_f * P.nu_f) * (Jo * s);
+      }
+    }
     return;
   }
   // fluid: ALE momentum, incompressibility, mesh motion
@@ -232,6 +310,19 @@ __device__ void fe_integrand(int kind, const Dn* q, const double* fr, const FePa
       GF[c][k] = s;
     }
   const double rho = P.rho_f, mu = P.rho_f * P.nu_f;
+  // previous level (theta < 1): F_old, J_old, grad v_old F_old^{-1}
+  double Jo = 1.0, Fo[D][D], Fio[D][D], GFo[D][D];
+  Dn Jmass = J;  // the mass term's J: theta J + (1 - theta) J_old
+  if (explicit_share) {
+    Jo = previous_level<D>(fr, Fo, Fio);
+    for (int c = 0; c < D; ++c)
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < D; ++m) s += gvo[c * D + m] * Fio[m][k];
+        GFo[c][k] = s;
+      }
+    Jmass = P.theta * J + dn((1.0 - P.theta) * Jo);
+  }
   for (int c = 0; c < D; ++c) {
     Dn adv = GF[c][0] * dn(fr[0]);
     Dn mv = GF[c][0] * (q[Q::QU + 0] - fr[2 * D + 0]);
@@ -239,11 +330,23 @@ __device__ void fe_integrand(int kind, const Dn* q, const double* fr, const FePa
       adv = adv + GF[c][k] * dn(fr[k]);
       mv = mv + GF[c][k] * (q[Q::QU + k] - fr[2 * D + k]);
     }
-    out[Q::QV + c] = rho * (J * (q[Q::QV + c] - fr[D + c])) + (P.dtth * rho) * (J * adv) - rho * (J * mv);
+    out[Q::QV + c] = rho * (Jmass * (q[Q::QV + c] - fr[D + c])) + (P.dtth * rho) * (J * adv) - rho * (J * mv);
     for (int k = 0; k < D; ++k) {
       Dn s = (GF[c][0] + GF[0][c]) * Fi[k][0];
       for (int m = 1; m < D; ++m) s = s + (GF[c][m] + GF[m][c]) * Fi[k][m];
       out[Q::QGV + c * D + k] = (P.dtth * mu) * (J * s) - J * (q[Q::QP] * Fi[k][c]);
+    }
+    if (explicit_share) {
+      // dt (1 - theta) times the previous level's convection (v_old advecting
+      // itself) and viscous stress
+      double cv = 0.0;
+      for (int k = 0; k < D; ++k) cv += GFo[c][k] * fr[D + k];
+      out[Q::QV + c] = out[Q::QV + c] + dto * rho * (Jo * cv);
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+        for (int m = 0; m < D; ++m) s += (GFo[c][m] + GFo[m][c]) * Fio[k][m];
+        out[Q::QGV + c * D + k] = out[Q::QGV + c * D + k] + (dto * mu) * (Jo * s);
+      }
     }
   }
   Dn tr = GF[0][0];
@@ -423,9 +526,11 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
         const double* f = s_f + (2 + j / D) * NV;
         const int c = j % D;
         for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + c];
-      } else {          // grad u_fz
-        const int c = (j - 3 * D) / D, k = (j - 3 * D) % D;
-        for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * s_f[5 * NV + l * D + c];
+      } else {          // grad u_fz, grad v_old, grad u_old
+        const int g = (j - 3 * D) / (D * D), r = (j - 3 * D) % (D * D);
+        const int c = r / D, k = r % D;
+        const double* f = s_f + (g == 0 ? 5 : g == 1 ? 3 : 4) * NV;
+        for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * f[l * D + c];
       }
     }
     s_q[ip * NIN + i] = s;
@@ -597,6 +702,30 @@ __global__ __launch_bounds__(256) void absmax_kernel(int64_t n, const double* __
     __syncthreads();
   }
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// End of a time step: the state U = fields + dU becomes the fields of the next
+// step and its previous level (v_old, u_old), the advecting velocity w and
+// the mesh-stiffness displacement u_fz; constrained dofs keep their values.
+__global__ __launch_bounds__(256) void fe_advance_kernel(int64_t nn, int D, const int64_t* __restrict__ vdof,
+                                                         const int64_t* __restrict__ udof,
+                                                         const int64_t* __restrict__ pdof, double* v, double* u,
+                                                         double* p, double* v_old, double* u_old, double* w,
+                                                         double* u_fz, const double* __restrict__ dU) {
+  const int64_t n = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (n >= nn) return;
+  for (int c = 0; c < D; ++c) {
+    const int64_t k = n * D + c;
+    const double vn = v[k] + (vdof[n] >= 0 ? dU[vdof[n] + c] : 0.0);
+    const double un = u[k] + (udof[n] >= 0 ? dU[udof[n] + c] : 0.0);
+    v[k] = vn;
+    v_old[k] = vn;
+    w[k] = vn;
+    u[k] = un;
+    u_old[k] = un;
+    u_fz[k] = un;
+  }
+  if (pdof[n] >= 0) p[n] = p[n] + dU[pdof[n]];
 }
 
 // y -= x (the Newton update U_{k+1} = U_k + delta with delta = -x).

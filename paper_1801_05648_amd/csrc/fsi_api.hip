@@ -1642,6 +1642,7 @@ struct FeState {
   int64_t n_nodes = 0;
   DevBuf vdof, udof, pdof, v, u, p, v_old, u_old, w, u_fz, flag, part;
   std::shared_ptr<DevBuf> brp[FSI_NBLK], bci[FSI_NBLK];
+  std::vector<double> spare[FSI_NBLK];  // host value arrays of the blocks' previous values, reused
   FeNodes nodes() const {
     return FeNodes{vdof.as<int64_t>(), udof.as<int64_t>(), pdof.as<int64_t>(), v.as<double>(),
                    u.as<double>(),     p.as<double>(),     v_old.as<double>(), u_old.as<double>(),
@@ -3877,6 +3878,7 @@ static void fe_refresh_host_blocks(fsi_ctx& c) {
       F.brp[b] = upload_raw(O.rp, s);
       F.bci[b] = upload_raw(O.ci, s);
     }
+    vals[b] = std::move(F.spare[b]);  // the previous read-back's array: no fresh zero-filled pages
     vals[b].resize(size_t(O.nnz()));
     if (O.nnz() == 0) continue;
     DevBuf dv;
@@ -3896,9 +3898,13 @@ static void fe_refresh_host_blocks(fsi_ctx& c) {
   try {
     check_structure(c.blk, c.d, c.n_vs, c.n_vf, c.n_f, c.dt_theta);
   } catch (...) {
-    for (int b = 0; b < FSI_NBLK; ++b) c.blk[b].v.swap(vals[b]);
+    for (int b = 0; b < FSI_NBLK; ++b) {
+      c.blk[b].v.swap(vals[b]);
+      F.spare[b] = std::move(vals[b]);
+    }
     throw;
   }
+  for (int b = 0; b < FSI_NBLK; ++b) F.spare[b] = std::move(vals[b]);  // the old values' arrays
   t.done();
 }
 
@@ -3968,7 +3974,7 @@ fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* m) {
     if (!c.have_system) throw Error(FSI_ERR_STATE, "fsi_setup_blocks must come first");
     if (!m) throw Error(FSI_ERR_ARG, "mesh is NULL");
     if (m->dim != c.d) throw Error(FSI_ERR_ARG, "mesh dimension differs from the system's");
-    if (m->theta != 1.0) throw Error(FSI_ERR_ARG, "theta = 1 only");
+    if (!(m->theta > 0.0 && m->theta <= 1.0)) throw Error(FSI_ERR_ARG, "theta must lie in (0, 1]");
     if (!(m->dt > 0.0) || !(m->rho_f > 0.0) || !(m->nu_f > 0.0) || !(m->rho_s > 0.0) || !(m->mu_s > 0.0) ||
         !(m->lambda_s >= 0.0))
       throw Error(FSI_ERR_ARG, "material data and dt must be positive");
@@ -3993,6 +3999,8 @@ fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* m) {
     if (nn != m->n_nodes) throw Error(FSI_ERR_ARG, "n_nodes must be the product of 2 cells + 1");
     P.rho_f = m->rho_f; P.nu_f = m->nu_f; P.rho_s = m->rho_s; P.mu_s = m->mu_s; P.lambda_s = m->lambda_s;
     P.dtth = m->dt * m->theta;
+    P.theta = m->theta;
+    P.dt = m->dt;
     P.newton_mesh = m->newton_mesh ? 1 : 0;
     const int64_t* dofs[3] = {m->vdof, m->udof, m->pdof};
     const double* fields[7] = {m->v, m->u, m->p, m->v_old, m->u_old, m->w, m->u_fz};
@@ -4073,6 +4081,88 @@ fsi_status fsi_fe_jacobian(fsi_ctx* ctx, const double* dU, int host_blocks) {
   });
 }
 
+static void check_newton_opts(const fsi_ctx& c, const fsi_newton_opts& o) {
+  if (!(o.rtol > 0.0) || !(o.reassemble_ratio >= 0.0) || o.max_steps < 0 || o.max_steps > FSI_NEWTON_MAX ||
+      !(o.lin_tol > 0.0) || o.restart < 1 || o.restart > kMaxBasis - 8 || o.maxit < 1 ||
+      (o.precond != FSI_NEWTON_PC_REBUILD && o.precond != FSI_NEWTON_PC_REUSE && o.precond != FSI_NEWTON_PC_KEEP))
+    throw Error(FSI_ERR_ARG, "bad Newton options");
+  if (o.precond == FSI_NEWTON_PC_KEEP && !c.have_precond)
+    throw Error(FSI_ERR_STATE, "keeping the preconditioner needs a fsi_build_precond first");
+}
+
+// Algorithm newton with Section 6's quasi-Newton rule from U = fields + dU.
+static fsi_status newton_impl(fsi_ctx& c, const fsi_newton_opts& o, double* dU, fsi_newton_info& out) {
+  const auto t_start = std::chrono::steady_clock::now();
+  auto ms_since = [](std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  };
+  out = fsi_newton_info{};
+  const int64_t N = c.N;
+  DevBuf R, delta;
+  R.alloc(sizeof(double) * size_t(N));
+  delta.alloc(sizeof(double) * size_t(N));
+  auto tic = std::chrono::steady_clock::now();
+  fe_assemble(c, dU, R.as<double>(), false);
+  out.t_assemble_ms += ms_since(tic);
+  out.resid[0] = device_absmax(c, R.as<double>(), N);
+  if (!std::isfinite(out.resid[0])) throw Error(FSI_ERR_NUMERIC, "the initial residual is not finite");
+  fsi_precond_opts po;
+  fsi_default_precond_opts(&po);
+  if (c.have_popts) po = c.popts;
+  fsi_solve_opts so;
+  fsi_default_solve_opts(&so);
+  so.tol = o.lin_tol;
+  so.restart = o.restart;
+  so.maxit = o.maxit;
+  for (int k = 0;; ++k) {
+    const double rk = out.resid[k];
+    if (rk == 0.0 || rk < o.rtol * out.resid[0]) {
+      out.converged = 1;
+      break;
+    }
+    if (k == o.max_steps) break;
+    // Section 6: assemble at the first step, then only when the last step
+    // reduced the max-norm residual by less than 1 / ratio
+    const bool assemble = k == 0 || rk > o.reassemble_ratio * out.resid[k - 1];
+    out.reassembled[k] = assemble ? 1 : 0;
+    if (assemble) {
+      tic = std::chrono::steady_clock::now();
+      fe_jacobian_into_ah(c, dU, o.precond != FSI_NEWTON_PC_KEEP);
+      out.t_assemble_ms += ms_since(tic);
+      ++out.reassemblies;
+      if (o.precond != FSI_NEWTON_PC_KEEP) {
+        tic = std::chrono::steady_clock::now();
+        fsi_precond_opts pk = po;
+        pk.reuse = (o.precond == FSI_NEWTON_PC_REUSE && c.have_host_h) ? 1 : 0;
+        build_precond_impl(c, &pk);
+        out.t_precond_ms += ms_since(tic);
+      }
+    }
+    // J delta = R, then U_{k+1} = U_k - delta
+    tic = std::chrono::steady_clock::now();
+    HIP_TRY(hipMemsetAsync(delta.p, 0, sizeof(double) * size_t(N), c.stream));
+    fsi_solve_info si{};
+    solve_impl(c, R.as<double>(), delta.as<double>(), so, si);
+    out.lin_iters[k] = si.iters;
+    out.lin_iters_total += si.iters;
+    sub_inplace_kernel<<<grid_for(N, kBlock), kBlock, 0, c.stream>>>(N, delta.as<double>(), dU);
+    HIP_TRY(hipGetLastError());
+    out.t_solve_ms += ms_since(tic);
+    tic = std::chrono::steady_clock::now();
+    fe_assemble(c, dU, R.as<double>(), false);
+    out.t_assemble_ms += ms_since(tic);
+    out.resid[k + 1] = device_absmax(c, R.as<double>(), N);
+    out.steps = k + 1;
+    if (!std::isfinite(out.resid[k + 1])) throw Error(FSI_ERR_NUMERIC, "the Newton residual is not finite");
+  }
+  out.t_total_ms = ms_since(t_start);
+  log_line("newton: %d steps, %d assemblies, %d GMRES iterations, ||r||_inf %.3e -> %.3e, %.1f ms "
+           "(assembly %.1f, preconditioner %.1f, solves %.1f)",
+           out.steps, out.reassemblies, out.lin_iters_total, out.resid[0], out.resid[out.steps], out.t_total_ms,
+           out.t_assemble_ms, out.t_precond_ms, out.t_solve_ms);
+  return out.converged ? FSI_OK : FSI_NOT_CONVERGED;
+}
+
 fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi_newton_info* info) {
   return guarded(ctx, [&]() -> fsi_status {
     fsi_ctx& c = *ctx;
@@ -4080,83 +4170,64 @@ fsi_status fsi_newton(fsi_ctx* ctx, const fsi_newton_opts* opts, double* dU, fsi
     fsi_newton_opts o;
     fsi_default_newton_opts(&o);
     if (opts) o = *opts;
-    if (!(o.rtol > 0.0) || !(o.reassemble_ratio >= 0.0) || o.max_steps < 0 || o.max_steps > FSI_NEWTON_MAX ||
-        !(o.lin_tol > 0.0) || o.restart < 1 || o.restart > kMaxBasis - 8 || o.maxit < 1 ||
-        (o.precond != FSI_NEWTON_PC_REBUILD && o.precond != FSI_NEWTON_PC_REUSE && o.precond != FSI_NEWTON_PC_KEEP))
-      throw Error(FSI_ERR_ARG, "bad Newton options");
-    if (o.precond == FSI_NEWTON_PC_KEEP && !c.have_precond)
-      throw Error(FSI_ERR_STATE, "keeping the preconditioner needs a fsi_build_precond first");
+    check_newton_opts(c, o);
     check_device_ptr(dU, "dU");
-    const auto t_start = std::chrono::steady_clock::now();
-    auto ms_since = [](std::chrono::steady_clock::time_point t0) {
-      return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-    };
     fsi_newton_info out{};
-    const int64_t N = c.N;
-    DevBuf R, delta;
-    R.alloc(sizeof(double) * size_t(N));
-    delta.alloc(sizeof(double) * size_t(N));
-    auto tic = std::chrono::steady_clock::now();
-    fe_assemble(c, dU, R.as<double>(), false);
-    out.t_assemble_ms += ms_since(tic);
-    out.resid[0] = device_absmax(c, R.as<double>(), N);
-    if (!std::isfinite(out.resid[0])) throw Error(FSI_ERR_NUMERIC, "the initial residual is not finite");
-    fsi_precond_opts po;
-    fsi_default_precond_opts(&po);
-    if (c.have_popts) po = c.popts;
-    fsi_solve_opts so;
-    fsi_default_solve_opts(&so);
-    so.tol = o.lin_tol;
-    so.restart = o.restart;
-    so.maxit = o.maxit;
-    for (int k = 0;; ++k) {
-      const double rk = out.resid[k];
-      if (rk == 0.0 || rk < o.rtol * out.resid[0]) {
-        out.converged = 1;
-        break;
-      }
-      if (k == o.max_steps) break;
-      // Section 6: assemble at the first step, then only when the last step
-      // reduced the max-norm residual by less than 1 / ratio
-      const bool assemble = k == 0 || rk > o.reassemble_ratio * out.resid[k - 1];
-      out.reassembled[k] = assemble ? 1 : 0;
-      if (assemble) {
-        tic = std::chrono::steady_clock::now();
-        fe_jacobian_into_ah(c, dU, o.precond != FSI_NEWTON_PC_KEEP);
-        out.t_assemble_ms += ms_since(tic);
-        ++out.reassemblies;
-        if (o.precond != FSI_NEWTON_PC_KEEP) {
-          tic = std::chrono::steady_clock::now();
-          fsi_precond_opts pk = po;
-          pk.reuse = (o.precond == FSI_NEWTON_PC_REUSE && c.have_host_h) ? 1 : 0;
-          build_precond_impl(c, &pk);
-          out.t_precond_ms += ms_since(tic);
-        }
-      }
-      // J delta = R, then U_{k+1} = U_k - delta
-      tic = std::chrono::steady_clock::now();
-      HIP_TRY(hipMemsetAsync(delta.p, 0, sizeof(double) * size_t(N), c.stream));
-      fsi_solve_info si{};
-      solve_impl(c, R.as<double>(), delta.as<double>(), so, si);
-      out.lin_iters[k] = si.iters;
-      out.lin_iters_total += si.iters;
-      sub_inplace_kernel<<<grid_for(N, kBlock), kBlock, 0, c.stream>>>(N, delta.as<double>(), dU);
-      HIP_TRY(hipGetLastError());
-      out.t_solve_ms += ms_since(tic);
-      tic = std::chrono::steady_clock::now();
-      fe_assemble(c, dU, R.as<double>(), false);
-      out.t_assemble_ms += ms_since(tic);
-      out.resid[k + 1] = device_absmax(c, R.as<double>(), N);
-      out.steps = k + 1;
-      if (!std::isfinite(out.resid[k + 1])) throw Error(FSI_ERR_NUMERIC, "the Newton residual is not finite");
-    }
-    out.t_total_ms = ms_since(t_start);
-    log_line("newton: %d steps, %d assemblies, %d GMRES iterations, ||r||_inf %.3e -> %.3e, %.1f ms "
-             "(assembly %.1f, preconditioner %.1f, solves %.1f)",
-             out.steps, out.reassemblies, out.lin_iters_total, out.resid[0], out.resid[out.steps], out.t_total_ms,
-             out.t_assemble_ms, out.t_precond_ms, out.t_solve_ms);
+    const fsi_status st = newton_impl(c, o, dU, out);
     if (info) *info = out;
-    return out.converged ? FSI_OK : FSI_NOT_CONVERGED;
+    return st;
+  });
+}
+
+static void fe_advance(fsi_ctx& c, const double* dU) {
+  FeState& F = *c.fe;
+  fe_advance_kernel<<<grid_for(F.n_nodes, kBlock), kBlock, 0, c.stream>>>(
+      F.n_nodes, F.prm.D, F.vdof.as<int64_t>(), F.udof.as<int64_t>(), F.pdof.as<int64_t>(), F.v.as<double>(),
+      F.u.as<double>(), F.p.as<double>(), F.v_old.as<double>(), F.u_old.as<double>(), F.w.as<double>(),
+      F.u_fz.as<double>(), dU);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c.stream));
+}
+
+fsi_status fsi_fe_advance(fsi_ctx* ctx, const double* dU) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
+    check_device_ptr(dU, "dU");
+    fe_advance(c, dU);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_fe_get_fields(fsi_ctx* ctx, double* v, double* u, double* p) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
+    if (!v || !u || !p) throw Error(FSI_ERR_ARG, "field arrays are required");
+    FeState& F = *c.fe;
+    d2h(v, F.v.p, size_t(F.n_nodes * F.prm.D), c.stream);
+    d2h(u, F.u.p, size_t(F.n_nodes * F.prm.D), c.stream);
+    d2h(p, F.p.p, size_t(F.n_nodes), c.stream);
+    return FSI_OK;
+  });
+}
+
+fsi_status fsi_time_step(fsi_ctx* ctx, const fsi_newton_opts* opts, fsi_newton_info* info) {
+  return guarded(ctx, [&]() -> fsi_status {
+    fsi_ctx& c = *ctx;
+    if (!c.fe) throw Error(FSI_ERR_STATE, "fsi_fe_setup must come first");
+    fsi_newton_opts o;
+    fsi_default_newton_opts(&o);
+    if (opts) o = *opts;
+    check_newton_opts(c, o);
+    DevBuf dU;
+    dU.alloc(sizeof(double) * size_t(c.N));
+    HIP_TRY(hipMemsetAsync(dU.p, 0, sizeof(double) * size_t(c.N), c.stream));
+    fsi_newton_info out{};
+    const fsi_status st = newton_impl(c, o, dU.as<double>(), out);
+    if (info) *info = out;
+    if (st == FSI_OK) fe_advance(c, dU.as<double>());
+    return st;
   });
 }
 

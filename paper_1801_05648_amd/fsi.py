@@ -185,6 +185,9 @@ def _declare(lib):
         "fsi_fe_jacobian": ([P, P, i32], i32),
         "fsi_newton": ([P, ctypes.POINTER(CNewtonOpts), P, ctypes.POINTER(CNewtonInfo)], i32),
         "fsi_default_newton_opts": ([ctypes.POINTER(CNewtonOpts)], None),
+        "fsi_fe_advance": ([P, P], i32),
+        "fsi_time_step": ([P, ctypes.POINTER(CNewtonOpts), ctypes.POINTER(CNewtonInfo)], i32),
+        "fsi_fe_get_fields": ([P, P, P, P], i32),
         "fsi_default_precond_opts": ([ctypes.POINTER(CPrecondOpts)], None),
         "fsi_default_solve_opts": ([ctypes.POINTER(CSolveOpts)], None),
     }
@@ -218,7 +221,8 @@ def exported_symbols():
             "fsi_mlp_set_weights", "fsi_mlp_get_weights", "fsi_mlp_enable", "fsi_mlp_forward",
             "fsi_mlp_forward_noalloc",
             "fsi_mlp_loss_grad", "fsi_mlp_energy_grad", "fsi_mlp_collect", "fsi_mlp_train",
-            "fsi_fe_setup", "fsi_fe_residual", "fsi_fe_jacobian", "fsi_newton", "fsi_default_newton_opts"]
+            "fsi_fe_setup", "fsi_fe_residual", "fsi_fe_jacobian", "fsi_newton", "fsi_default_newton_opts",
+            "fsi_fe_advance", "fsi_time_step", "fsi_fe_get_fields"]
 
 
 def _csr_struct(nrows, ncols, rowptr, col, val, keep):
@@ -424,11 +428,35 @@ class FsiSolver:
         info = CNewtonInfo()
         rc = self._check(self.lib.fsi_newton(self.ctx, ctypes.byref(o), _dptr(dU, self.N, "dU"),
                                              ctypes.byref(info)))
+        return dU, self._newton_info(rc, info)
+
+    def _newton_info(self, rc, info):
         n = info.steps
-        return dU, NewtonInfo(STATUS[rc], bool(info.converged), n, info.reassemblies,
-                              list(info.resid[:n + 1]), [bool(x) for x in info.reassembled[:n]],
-                              list(info.lin_iters[:n]), info.t_assemble_ms, info.t_precond_ms, info.t_solve_ms,
-                              info.t_total_ms)
+        return NewtonInfo(STATUS[rc], bool(info.converged), n, info.reassemblies,
+                          list(info.resid[:n + 1]), [bool(x) for x in info.reassembled[:n]],
+                          list(info.lin_iters[:n]), info.t_assemble_ms, info.t_precond_ms, info.t_solve_ms,
+                          info.t_total_ms)
+
+    def fe_advance(self, dU):
+        """fsi_fe_advance: U = fields + dU becomes the next step's fields."""
+        self._check(self.lib.fsi_fe_advance(self.ctx, _dptr(dU, self.N, "dU")))
+
+    def time_step(self, rtol: float = 1e-6, reassemble_ratio: float = 0.1, max_steps: int = 25,
+                  precond: str = "rebuild", lin_tol: float = 1e-3, restart: int = 50, maxit: int = 2000):
+        """fsi_time_step: the quasi-Newton loop from the current fields, then the advance."""
+        o = CNewtonOpts(float(rtol), float(reassemble_ratio), int(max_steps), NEWTON_PC[precond], float(lin_tol),
+                        int(restart), int(maxit))
+        info = CNewtonInfo()
+        rc = self._check(self.lib.fsi_time_step(self.ctx, ctypes.byref(o), ctypes.byref(info)))
+        return self._newton_info(rc, info)
+
+    def fe_fields(self, n_nodes: int, dim: int):
+        """fsi_fe_get_fields: the current state fields (host copies)."""
+        v = np.empty((n_nodes, dim))
+        u = np.empty((n_nodes, dim))
+        p = np.empty(n_nodes)
+        self._check(self.lib.fsi_fe_get_fields(self.ctx, v.ctypes.data, u.ctypes.data, p.ctypes.data))
+        return v, u, p
 
     def solve(self, b, x=None, tol: float = 1e-8, restart: int = 50, maxit: int = 2000,
               timing: bool = False):

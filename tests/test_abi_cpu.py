@@ -73,6 +73,9 @@ def test_null_context_arguments_are_rejected(lib):
     assert L.fsi_fe_residual(None, None, None) == -1
     assert L.fsi_fe_jacobian(None, None, 0) == -1
     assert L.fsi_newton(None, None, None, None) == -1
+    assert L.fsi_fe_advance(None, None) == -1
+    assert L.fsi_time_step(None, None, None) == -1
+    assert L.fsi_fe_get_fields(None, None, None, None) == -1
     assert L.fsi_destroy(None) == 0
 
 

@@ -177,3 +177,69 @@ def test_fe_errors_are_reported():
     R = g.fe_residual(None).cpu().numpy()  # the context still works
     assert np.max(np.abs(R - P.residual())) <= 1e-12 * np.max(np.abs(R))
     g.close()
+
+
+# ---------------------------------------------------------------- theta scheme
+def _theta_case(name, theta, seed=21):
+    """A theta step on a workload: the generator's pattern and layout at dt theta
+    (so that the layout's dt theta is the step's), the workload's fields with a
+    previous level off the given one."""
+    base = fsigen.config(name)
+    s = fsigen.generate(base.with_(dt=base.dt * theta), fe=True)
+    f = {k: np.array(v, copy=True) for k, v in s.fe.items()}
+    rng = np.random.default_rng(seed)
+    f["v_old"] = 0.8 * f["v"] + 0.05 * rng.standard_normal(f["v"].shape)
+    f["u_old"] = 0.7 * f["u"]
+    return s, base.with_(theta=theta), f
+
+
+@pytest.mark.parametrize("name,theta", [("tiny2d", 0.5), ("tiny3d", 0.51), ("c1", 0.51)])
+def test_theta_residual_and_jacobian_match_oracle(name, theta):
+    from paper_1801_05648_amd import FsiSolver
+    s, cfg, f = _theta_case(name, theta)
+    P = fe.FeProblem(cfg, f, s.N)
+    g = FsiSolver.from_system(s, device=0)
+    g.fe_setup(cfg, f)
+    dU = _state(s, 3)
+    Rg = g.fe_residual(_dev(dU)).cpu().numpy()
+    Ro = P.residual(dU)
+    err = np.max(np.abs(Rg - Ro))
+    assert err <= 1e-12 * np.max(np.abs(Ro)), err
+    g.fe_jacobian(_dev(dU), host_blocks=True)
+    A = P.jacobian(dU)
+    x = np.random.default_rng(4).standard_normal(s.N)
+    y = g.spmv(_dev(x)).cpu().numpy()
+    bound = abs(A) @ np.abs(x)
+    rel = np.max(np.abs(y - A @ x) / (bound + 1e-300))
+    print(f"{name} theta={theta}: residual {err:.2e} of {np.max(np.abs(Ro)):.2e}, Jacobian product {rel:.2e}")
+    assert rel <= 1e-12, rel
+    g.close()
+
+
+@pytest.mark.parametrize("name,theta", [("tiny2d", 0.5 + 1e-2), ("c1", 0.5)])
+def test_theta_time_steps_match_oracle(name, theta):
+    """Three steps of the shifted Crank-Nicolson (tiny2d) and Crank-Nicolson
+    (c1) schemes: quasi-Newton on the GPU, exact Newton in the oracle, the
+    fields after every step compared."""
+    from paper_1801_05648_amd import FsiSolver
+    s, cfg, f = _theta_case(name, theta)
+    g = FsiSolver.from_system(s, device=0)
+    g.fe_setup(cfg, f)
+    g.build_precond("f64")
+    fo = f
+    n_nodes = f["vdof"].shape[0]
+    for step in range(3):
+        info = g.time_step(rtol=1e-11, precond="reuse")
+        assert info.converged, info
+        P = fe.FeProblem(cfg, fo, s.N)
+        dUo, io = fe.quasi_newton(P.residual, P.jacobian, s.N, rtol=1e-13, ratio=0.0)
+        assert io.converged
+        fo = fe.advance(P, dUo)
+        v, u, p = g.fe_fields(n_nodes, s.dim)
+        dv = np.max(np.abs(v - fo["v"])) / np.max(np.abs(fo["v"]))
+        du = np.max(np.abs(u - fo["u"])) / np.max(np.abs(fo["u"]))
+        dp = np.max(np.abs(p - fo["p"])) / np.max(np.abs(fo["p"]))
+        print(f"{name} theta={theta} step {step}: {info.steps} Newton steps ({info.reassemblies} assemblies), "
+              f"oracle {io.steps}; fields v {dv:.1e} u {du:.1e} p {dp:.1e}")
+        assert max(dv, du, dp) <= 1e-7, (dv, du, dp)
+    g.close()
