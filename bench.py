@@ -408,6 +408,42 @@ def timed_solves(solver, b, x, k):
     return times, info
 
 
+def theta_steps_run(args, dim, stream):
+    """One-step-theta time steps (Section 3.2) with the shifted Crank-Nicolson
+    theta = 1/2 + dt on the mid-size system of the headline's dimension: the
+    system handed to the library carries dt theta, the assembly the scheme's
+    previous-level terms; each step is the quasi-Newton loop (SA hierarchies
+    kept across reassemblies) followed by the advance of the fields."""
+    import torch
+
+    import fsigen
+    from paper_1801_05648_amd import FsiSolver
+    name = "c3" if dim == 3 else "c2"
+    base = fsigen.config(name)
+    theta = 0.5 + base.dt
+    sysm = fsigen.generate(base.with_(dt=base.dt * theta), seed=0, fe=True)
+    solver = FsiSolver.from_system(sysm, device=0, stream=stream)
+    solver.fe_setup(base.with_(theta=theta), sysm.fe)
+    solver.build_precond("f64", **precond_opts(args, dim))
+    steps = []
+    for _ in range(args.time_steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = solver.time_step(precond="reuse")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        if not info.converged:
+            raise SystemExit(f"time step did not converge: {info}")
+        steps.append({"ms": round(ms, 1), "newton_steps": info.steps, "reassemblies": info.reassemblies,
+                      "gmres_iters": info.lin_iters, "resid_inf": [float("%.4e" % v) for v in info.residuals],
+                      "assembly_ms": round(info.t_assemble_ms, 1), "precond_ms": round(info.t_precond_ms, 1),
+                      "solve_ms": round(info.t_solve_ms, 1)})
+    solver.close()
+    return {"workload": workload_name(base), "theta": theta, "dt": base.dt, "steps": steps,
+            "note": "shifted Crank-Nicolson; each step: quasi-Newton (Section 6 rule) from the previous "
+                    "step's state, then the fields advance"}
+
+
 def fe_newton_run(r, opts):
     """The steps on either side of the solve (Section 3's residual and
     Jacobian assembled on the GPU, Section 6's quasi-Newton loop) on the
@@ -469,6 +505,9 @@ def main():
                     help="skip the other preconditioner forms reported beside the headline solve")
     ap.add_argument("--no-fe", action="store_true",
                     help="skip the finite-element assembly and quasi-Newton loop reported after the solves")
+    ap.add_argument("--time-steps", type=int, default=3,
+                    help="shifted Crank-Nicolson time steps on the 64x16x16 (3D) or 256x64 (2D) system "
+                         "reported after the solves (0: none)")
     ap.add_argument("--cheb", type=int, default=None,
                     help="Chebyshev degree of the sweeps on --cheb-on (0: Jacobi V(1,1) everywhere); "
                          "default 6 in 3D, 4 in 2D, 0 with --learned in 2D")
@@ -793,6 +832,10 @@ def main():
     for r in runs:
         r["solver"].close()
     runs.clear()
+    if args.time_steps > 0 and args.precision == "f64":
+        progress("one-step-theta time steps")
+        line["theta_steps"] = theta_steps_run(args, cfg.dim, stream)
+        progress(f"theta_steps: {line['theta_steps']}")
     if not args.no_cpu_baseline:
         gpu_c3 = None
         if cfg.name != "c3":
