@@ -18,12 +18,13 @@
 // launches), so no two cells of a launch share a node and every row is
 // written by one workgroup: plain read-add-write, deterministic.  A thread
 // owns one test row t and the trial columns s = lane + 8 j of the cell matrix
-// in registers across the quadrature loop.  The basis values and the
-// interpolated inputs of every quadrature point are formed once per
-// workgroup; the integrand derivatives for nine points at a time (225
-// (point, direction) pairs in 3D on the 256 threads); then, point by point,
-// DB[s][o] = sum over the inputs of trial s of d out_o / d q_i times its basis
-// value, and the cell-matrix update.  All tables sit in LDS (133 KB in 3D).  The cell matrix entries
+// in registers across the quadrature loop.  The quadrature points go in
+// batches of three: their rows of the basis table (the same for every cell,
+// formed once by fe_basis_kernel) and the interpolated inputs into LDS, the
+// integrand derivatives (75 (point, direction) pairs in 3D), then, point by
+// point, DB[s][o] = sum over the inputs of trial s of d out_o / d q_i times
+// its basis value, and the cell-matrix update.  About 60 KB of LDS in 3D, two
+// workgroups per CU.  The cell matrix entries
 // are added into the stored A_h (its row segments and row groups) at the
 // position of (global row, global column), found by binary search in the
 // row's sorted column list.
@@ -136,7 +137,8 @@ template <int D> struct FeDims {
   static constexpr int NJ = (NLOC + SL - 1) / SL;
   // interpolated given fields: w, v_old, u_old, grad u_fz, grad v_old, grad u_old
   static constexpr int NFR = 3 * D + 3 * D * D;
-  static constexpr int QB = 9;                  // points whose integrand derivatives are formed together
+  static constexpr int NPT = NVOL + NFACE;      // quadrature points (volume, then the outflow face)
+  static constexpr int SH = NQ2 + NQ2 * D + NQ1 + 1;  // basis table row: N | grad N | M | weight
 };
 
 template <int D>
@@ -374,23 +376,82 @@ __device__ __forceinline__ void q2_basis(double x, double* n, double* dn1) {
   dn1[2] = 4.0 * x - 1.0;
 }
 
+// The basis table, the same for every cell of the uniform grid: per
+// quadrature point (3^d volume points, then the 3^{d-1} points of the face
+// x_0 = 1) the Q2 values and physical gradients, the Q1 values and the
+// weight (cell volume or face area included).  One thread per (point, basis
+// function); formed once per fsi_fe_setup.
+template <int D>
+__global__ __launch_bounds__(256) void fe_basis_kernel(FeParams P, double* __restrict__ tab) {
+  using Q = FeDims<D>;
+  constexpr int NQ2 = Q::NQ2, NQ1 = Q::NQ1, SH = Q::SH;
+  const int job = int(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (job >= Q::NPT * (NQ2 + NQ1)) return;
+  const double gx[3] = {0.5 - 0.38729833462074168852, 0.5, 0.5 + 0.38729833462074168852};
+  const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
+  const int ip = job / (NQ2 + NQ1), l = job % (NQ2 + NQ1);
+  double xi[3] = {0.0, 0.0, 0.0}, w = 1.0;
+  if (ip < Q::NVOL) {
+    int r = ip;
+    for (int a = 0; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
+  } else {
+    int r = ip - Q::NVOL;
+    xi[0] = 1.0;
+    for (int a = 1; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
+  }
+  double* row = tab + ip * SH;
+  if (l < NQ2) {
+    double n1[3][3], d1[3][3];
+    for (int a = 0; a < D; ++a) q2_basis(xi[a], n1[a], d1[a]);
+    int ia[3], r = l;
+    for (int a = 0; a < D; ++a) { ia[a] = r % 3; r /= 3; }
+    double prod = 1.0;
+    for (int a = 0; a < D; ++a) prod *= n1[a][ia[a]];
+    row[l] = prod;
+    for (int k = 0; k < D; ++k) {
+      double g = d1[k][ia[k]] / P.h[k];
+      for (int a = 0; a < D; ++a)
+        if (a != k) g *= n1[a][ia[a]];
+      row[NQ2 + l * D + k] = g;
+    }
+    if (l == 0) row[SH - 1] = w;
+  } else {
+    int r = l - NQ2;
+    double prod = 1.0;
+    for (int a = 0; a < D; ++a) { prod *= (r % 2) ? xi[a] : 1.0 - xi[a]; r /= 2; }
+    row[NQ2 + NQ2 * D + (l - NQ2)] = prod;
+  }
+}
+
+// Launch modes of fe_assemble_kernel: the residual R(U) of the cells' tested
+// rows; the integrand values and derivatives d out / d q at every quadrature
+// point of every cell into a buffer (FE_POINTS); the cell matrices from that
+// buffer, added into A_h (FE_CONTRACT).  Each mode is its own instance, so the
+// contraction carries none of the integrand's registers.
+enum { FE_RESIDUAL = 0, FE_POINTS = 1, FE_CONTRACT = 2 };
+
 // flag bits: 1 J <= 0 (current or mesh-stiffness), 2 a cell entry outside
 // the stored pattern, 4 a non-finite residual or matrix value.
-template <int D>
-__global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd, const double* __restrict__ dU,
-                                                          int color, int want_res, int want_mat,
-                                                          double* __restrict__ R, AhSlots ah, int* flag) {
+// pts: FE_POINTS writes, FE_CONTRACT reads, per cell of the launch (blockIdx.x)
+// and point, d out / d q (NQ x NQ, o-major) then the values (NQ).
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd, const double* __restrict__ basis,
+                                                          const double* __restrict__ dU, int color,
+                                                          double* __restrict__ R, double* __restrict__ pts,
+                                                          AhSlots ah, int* flag) {
   using Q = FeDims<D>;
   constexpr int NQ2 = Q::NQ2, NQ1 = Q::NQ1, NV = Q::NV, NLOC = Q::NLOC, NQ = Q::NQ;
-  __shared__ double s_f[7 * NV + NQ1];  // v | u | w | v_old | u_old | u_fz (node-major, comp) | p
-  __shared__ int64_t s_gd[NLOC];
-  __shared__ unsigned char s_ton[NLOC];
-  constexpr int NPT = Q::NVOL + Q::NFACE, NIN = NQ + Q::NFR, QB = Q::QB;
-  __shared__ double s_N[NPT * NQ2], s_dN[NPT * NQ2 * D], s_M[NPT * NQ1], s_w[NPT];  // every point
-  __shared__ double s_q[NPT * NIN];     // inputs q and the given fields at every point
-  __shared__ double s_Dm[QB * NQ * NQ];  // per point of a batch: s_Dm[o * NQ + i] = d out_o / d q_i
-  __shared__ double s_ov[QB * NQ];
-  __shared__ double s_DB[NLOC * NQ];
+  constexpr int NIN = NQ + Q::NFR, SH = Q::SH, GS = NQ * NQ + NQ;
+  constexpr int QB = MODE == FE_CONTRACT ? 1 : 9;  // points per batch
+  constexpr bool kFields = MODE != FE_CONTRACT, kRows = MODE != FE_POINTS;
+  __shared__ double s_f[kFields ? 7 * NV + NQ1 : 1];  // v | u | w | v_old | u_old | u_fz (node-major, comp) | p
+  __shared__ int64_t s_gd[kRows ? NLOC : 1];
+  __shared__ unsigned char s_ton[kRows ? NLOC : 1];
+  __shared__ double s_sh[QB * SH];                      // basis table rows of the batch's points
+  __shared__ double s_q[kFields ? QB * NIN : 1];        // inputs q and given fields at the batch's points
+  __shared__ double s_ov[MODE == FE_RESIDUAL ? QB * NQ : 1];
+  __shared__ double s_Dm[MODE == FE_CONTRACT ? NQ * NQ : 1];  // s_Dm[o * NQ + i] = d out_o / d q_i
+  __shared__ double s_DB[MODE == FE_CONTRACT ? NLOC * NQ : 1];
   __shared__ int s_cellflag;
   const int tid = threadIdx.x;
   // the cell of this workgroup within its parity class
@@ -407,7 +468,6 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
   bool solid = true;
   for (int a = 0; a < D; ++a) solid = solid && C[a] >= P.solid_lo[a] && C[a] < P.solid_hi[a];
   const bool outflow = !solid && C[0] == P.nc[0] - 1;
-  const int t0 = blockIdx.y * Q::RT;
   auto node_of = [&](const int* off) {
     int64_t id = 0;
     for (int a = 0; a < D; ++a) id = id * P.NN[a] + (2 * C[a] + off[a]);
@@ -431,16 +491,20 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
     }
     for (int c = 0; c < D; ++c) {
       const int k = l * D + c;
-      s_f[k] = nd.v[n * D + c] + (vd >= 0 && dU ? dU[vd + c] : 0.0);
-      s_f[NV + k] = nd.u[n * D + c] + (ud >= 0 && dU ? dU[ud + c] : 0.0);
-      s_f[2 * NV + k] = nd.w[n * D + c];
-      s_f[3 * NV + k] = nd.v_old[n * D + c];
-      s_f[4 * NV + k] = nd.u_old[n * D + c];
-      s_f[5 * NV + k] = nd.u_fz[n * D + c];
-      s_gd[k] = vd >= 0 ? vd + c : -1;
-      s_gd[NV + k] = ud >= 0 ? ud + c : -1;
-      s_ton[k] = vd >= 0;
-      s_ton[NV + k] = ud >= 0 && (solid || !in_solid);
+      if constexpr (kFields) {
+        s_f[k] = nd.v[n * D + c] + (vd >= 0 && dU ? dU[vd + c] : 0.0);
+        s_f[NV + k] = nd.u[n * D + c] + (ud >= 0 && dU ? dU[ud + c] : 0.0);
+        s_f[2 * NV + k] = nd.w[n * D + c];
+        s_f[3 * NV + k] = nd.v_old[n * D + c];
+        s_f[4 * NV + k] = nd.u_old[n * D + c];
+        s_f[5 * NV + k] = nd.u_fz[n * D + c];
+      }
+      if constexpr (kRows) {
+        s_gd[k] = vd >= 0 ? vd + c : -1;
+        s_gd[NV + k] = ud >= 0 ? ud + c : -1;
+        s_ton[k] = vd >= 0;
+        s_ton[NV + k] = ud >= 0 && (solid || !in_solid);
+      }
     }
   }
   for (int l = tid; l < NQ1; l += blockDim.x) {
@@ -448,219 +512,196 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
     for (int a = 0; a < D; ++a) { off[a] = 2 * (r % 2); r /= 2; }
     const int64_t n = node_of(off);
     const int64_t pd = solid ? -1 : nd.pdof[n];
-    s_f[6 * NV + l] = nd.p[n] + (pd >= 0 && dU ? dU[pd] : 0.0);
-    s_gd[2 * NV + l] = pd;
-    s_ton[2 * NV + l] = pd >= 0;
+    if constexpr (kFields) s_f[6 * NV + l] = nd.p[n] + (pd >= 0 && dU ? dU[pd] : 0.0);
+    if constexpr (kRows) {
+      s_gd[2 * NV + l] = pd;
+      s_ton[2 * NV + l] = pd >= 0;
+    }
   }
   __syncthreads();
-  // matrix launches: 32 test rows per workgroup, 8 threads per row; residual
-  // launches: one workgroup per cell, one thread per row
-  const int tr = tid / Q::SL, sl = want_mat ? tid % Q::SL : 0;
-  const int t = want_mat ? t0 + tr : tid;
-  const bool row_on = t < NLOC && s_ton[t] && s_gd[t] >= 0;
-  double acc[Q::NJ];
-  for (int j = 0; j < Q::NJ; ++j) acc[j] = 0.0;
+  // residual: one thread per local row; contraction: 32 test rows per
+  // workgroup (blockIdx.y), 8 threads per row
+  const int tr = tid / Q::SL, sl = MODE == FE_CONTRACT ? tid % Q::SL : 0;
+  const int t = MODE == FE_CONTRACT ? int(blockIdx.y) * Q::RT + tr : tid;
+  bool row_on = false;
+  if constexpr (kRows) row_on = t < NLOC && s_ton[t] && s_gd[t] >= 0;
+  double acc[MODE == FE_CONTRACT ? Q::NJ : 1];
+#pragma unroll
+  for (int j = 0; j < (MODE == FE_CONTRACT ? Q::NJ : 1); ++j) acc[j] = 0.0;
   double res = 0.0;
-  const double gx[3] = {0.5 - 0.38729833462074168852, 0.5, 0.5 + 0.38729833462074168852};
-  const double gw[3] = {5.0 / 18.0, 8.0 / 18.0, 5.0 / 18.0};
   const int npts = Q::NVOL + (outflow ? Q::NFACE : 0);
-  // basis values and weights at every point: volume points, then the
-  // outflow face x_0 = 1 (reference coordinates)
-  for (int job = tid; job < npts * (NQ2 + NQ1); job += blockDim.x) {
-    const int ip = job / (NQ2 + NQ1), l = job % (NQ2 + NQ1);
-    double xi[3] = {0.0, 0.0, 0.0}, w = 1.0;
-    if (ip < Q::NVOL) {
-      int r = ip;
-      for (int a = 0; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
-    } else {
-      int r = ip - Q::NVOL;
-      xi[0] = 1.0;
-      for (int a = 1; a < D; ++a) { xi[a] = gx[r % 3]; w *= gw[r % 3] * P.h[a]; r /= 3; }
-    }
-    if (l < NQ2) {
-      double n1[3][3], d1[3][3];
-      for (int a = 0; a < D; ++a) q2_basis(xi[a], n1[a], d1[a]);
-      int ia[3], r = l;
-      for (int a = 0; a < D; ++a) { ia[a] = r % 3; r /= 3; }
-      double prod = 1.0;
-      for (int a = 0; a < D; ++a) prod *= n1[a][ia[a]];
-      s_N[ip * NQ2 + l] = prod;
-      for (int k = 0; k < D; ++k) {
-        double g = d1[k][ia[k]] / P.h[k];
-        for (int a = 0; a < D; ++a)
-          if (a != k) g *= n1[a][ia[a]];
-        s_dN[(ip * NQ2 + l) * D + k] = g;
-      }
-      if (l == 0) s_w[ip] = w;
-    } else {
-      int r = l - NQ2;
-      double prod = 1.0;
-      for (int a = 0; a < D; ++a) { prod *= (r % 2) ? xi[a] : 1.0 - xi[a]; r /= 2; }
-      s_M[ip * NQ1 + (l - NQ2)] = prod;
-    }
-  }
-  __syncthreads();
-  // interpolated inputs q and given fields at every point
-  for (int job = tid; job < npts * NIN; job += blockDim.x) {
-    const int ip = job / NIN, i = job % NIN;
-    const double* N = s_N + ip * NQ2;
-    const double* dN = s_dN + ip * NQ2 * D;
-    double s = 0.0;
-    if (i < NQ) {
-      if (i == Q::QP) {
-        for (int l = 0; l < NQ1; ++l) s += s_M[ip * NQ1 + l] * s_f[6 * NV + l];
-      } else {
-        const bool vel = i < Q::QU;
-        const int j = vel ? i : i - Q::QU;  // 0..D-1 value, D.. gradient
-        const double* f = s_f + (vel ? 0 : NV);
-        if (j < D) {
-          for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + j];
-        } else {
-          const int c = (j - D) / D, k = (j - D) % D;
-          for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * f[l * D + c];
-        }
-      }
-    } else {
-      const int j = i - NQ;
-      if (j < 3 * D) {  // w, v_old, u_old
-        const double* f = s_f + (2 + j / D) * NV;
-        const int c = j % D;
-        for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + c];
-      } else {          // grad u_fz, grad v_old, grad u_old
-        const int g = (j - 3 * D) / (D * D), r = (j - 3 * D) % (D * D);
-        const int c = r / D, k = r % D;
-        const double* f = s_f + (g == 0 ? 5 : g == 1 ? 3 : 4) * NV;
-        for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * f[l * D + c];
-      }
-    }
-    s_q[ip * NIN + i] = s;
-  }
-  __syncthreads();
+  double* cell_pts = pts ? pts + int64_t(blockIdx.x) * Q::NPT * GS : nullptr;
   for (int b0 = 0; b0 < npts; b0 += QB) {
     const int nb = npts - b0 < QB ? npts - b0 : QB;
-    // d out / d q_i at the batch's points, one (point, direction) per thread
-    // (the values alone for a residual)
-    const int ndir = want_mat ? NQ : 1;
-    for (int job = tid; job < nb * ndir; job += blockDim.x) {
-      const int jb = job / ndir, dir = job % ndir, ip = b0 + jb;
-      const double* qv = s_q + ip * NIN;
-      Dn qd[NQ], out[NQ];
-      for (int i = 0; i < NQ; ++i) qd[i] = Dn{qv[i], (want_mat && i == dir) ? 1.0 : 0.0};
-      const bool face = ip >= Q::NVOL;
-      fe_integrand<D>(face ? 2 : (solid ? 1 : 0), qd, qv + NQ, P, out);
-      if (want_mat)
-        for (int o = 0; o < NQ; ++o) s_Dm[jb * NQ * NQ + o * NQ + dir] = out[o].d;
-      if (dir == 0) {
-        for (int o = 0; o < NQ; ++o) s_ov[jb * NQ + o] = out[o].v;
-        // J of the current state and of the mesh-stiffness field must stay positive
-        if (!solid && !face) {
-          double Fv[D][D], Fz[D][D];
-          for (int c = 0; c < D; ++c)
-            for (int k = 0; k < D; ++k) {
-              Fv[c][k] = qv[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
-              Fz[c][k] = qv[NQ + 3 * D + c * D + k] + (c == k ? 1.0 : 0.0);
-            }
-          double Jv, Jz;
-          if constexpr (D == 2) {
-            Jv = Fv[0][0] * Fv[1][1] - Fv[0][1] * Fv[1][0];
-            Jz = Fz[0][0] * Fz[1][1] - Fz[0][1] * Fz[1][0];
-          } else {
-            Jv = Fv[0][0] * (Fv[1][1] * Fv[2][2] - Fv[1][2] * Fv[2][1]) -
-                 Fv[0][1] * (Fv[1][0] * Fv[2][2] - Fv[1][2] * Fv[2][0]) +
-                 Fv[0][2] * (Fv[1][0] * Fv[2][1] - Fv[1][1] * Fv[2][0]);
-            Jz = Fz[0][0] * (Fz[1][1] * Fz[2][2] - Fz[1][2] * Fz[2][1]) -
-                 Fz[0][1] * (Fz[1][0] * Fz[2][2] - Fz[1][2] * Fz[2][0]) +
-                 Fz[0][2] * (Fz[1][0] * Fz[2][1] - Fz[1][1] * Fz[2][0]);
-          }
-          if (!(Jv > 0.0) || !(Jz > 0.0)) atomicOr(&s_cellflag, 1);
-        }
-      }
-    }
+    for (int i = tid; i < nb * SH; i += blockDim.x) s_sh[i] = basis[b0 * SH + i];
+    if constexpr (MODE == FE_CONTRACT)
+      for (int i = tid; i < NQ * NQ; i += blockDim.x) s_Dm[i] = cell_pts[b0 * GS + i];
     __syncthreads();
-    for (int jb = 0; jb < nb; ++jb) {
-      const int ip = b0 + jb;
-      const double w = s_w[ip];
-      const double* N = s_N + ip * NQ2;
-      const double* dN = s_dN + ip * NQ2 * D;
-      const double* M = s_M + ip * NQ1;
-      const double* ov = s_ov + jb * NQ;
-      const double* Dm = s_Dm + jb * NQ * NQ;
-      // residual of this workgroup's test rows
-      if (want_res && sl == 0 && row_on) {
-        if (t < 2 * NV) {
-          const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
-          const int l = (t % NV) / D, c = (t % NV) % D;
-          double s = ov[fo + c] * N[l];
-          for (int k = 0; k < D; ++k) s += ov[go + c * D + k] * dN[l * D + k];
-          res += w * s;
-        } else {
-          res += w * ov[Q::QP] * M[t - 2 * NV];
-        }
-      }
-      if (want_mat) {
-        for (int idx = tid; idx < NLOC * NQ; idx += blockDim.x) {
-          const int s = idx / NQ, o = idx % NQ;
-          double val = 0.0;
-          if (s_gd[s] >= 0) {
-            if (s < 2 * NV) {
-              const int fi = s < NV ? Q::QV : Q::QU, gi = s < NV ? Q::QGV : Q::QGU;
-              const int l = (s % NV) / D, e = (s % NV) % D;
-              val = Dm[o * NQ + fi + e] * N[l];
-              for (int k = 0; k < D; ++k) val += Dm[o * NQ + gi + e * D + k] * dN[l * D + k];
+    if constexpr (kFields) {
+      // interpolated inputs q and given fields at the batch's points
+      for (int job = tid; job < nb * NIN; job += blockDim.x) {
+        const int jb = job / NIN, i = job % NIN;
+        const double* N = s_sh + jb * SH;
+        const double* dN = N + NQ2;
+        const double* M = dN + NQ2 * D;
+        double s = 0.0;
+        if (i < NQ) {
+          if (i == Q::QP) {
+            for (int l = 0; l < NQ1; ++l) s += M[l] * s_f[6 * NV + l];
+          } else {
+            const bool vel = i < Q::QU;
+            const int j = vel ? i : i - Q::QU;  // 0..D-1 value, D.. gradient
+            const double* f = s_f + (vel ? 0 : NV);
+            if (j < D) {
+              for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + j];
             } else {
-              val = Dm[o * NQ + Q::QP] * M[s - 2 * NV];
+              const int c = (j - D) / D, k = (j - D) % D;
+              for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * f[l * D + c];
             }
           }
-          s_DB[idx] = val;
+        } else {
+          const int j = i - NQ;
+          if (j < 3 * D) {  // w, v_old, u_old
+            const double* f = s_f + (2 + j / D) * NV;
+            const int c = j % D;
+            for (int l = 0; l < NQ2; ++l) s += N[l] * f[l * D + c];
+          } else {          // grad u_fz, grad v_old, grad u_old
+            const int g = (j - 3 * D) / (D * D), r = (j - 3 * D) % (D * D);
+            const int c = r / D, k = r % D;
+            const double* f = s_f + (g == 0 ? 5 : g == 1 ? 3 : 4) * NV;
+            for (int l = 0; l < NQ2; ++l) s += dN[l * D + k] * f[l * D + c];
+          }
         }
-        __syncthreads();
+        s_q[jb * NIN + i] = s;
+      }
+      __syncthreads();
+      // the integrand at the batch's points: d out / d q_i, one (point,
+      // direction) per thread, or the values alone for the residual
+      constexpr int ndir = MODE == FE_POINTS ? NQ : 1;
+      for (int job = tid; job < nb * ndir; job += blockDim.x) {
+        const int jb = job / ndir, dir = job % ndir, ip = b0 + jb;
+        const double* qv = s_q + jb * NIN;
+        Dn qd[NQ], out[NQ];
+        for (int i = 0; i < NQ; ++i) qd[i] = Dn{qv[i], (MODE == FE_POINTS && i == dir) ? 1.0 : 0.0};
+        const bool face = ip >= Q::NVOL;
+        fe_integrand<D>(face ? 2 : (solid ? 1 : 0), qd, qv + NQ, P, out);
+        if constexpr (MODE == FE_POINTS)
+          for (int o = 0; o < NQ; ++o) cell_pts[ip * GS + o * NQ + dir] = out[o].d;
+        if (dir == 0) {
+          if constexpr (MODE == FE_POINTS) {
+            for (int o = 0; o < NQ; ++o) {
+              cell_pts[ip * GS + NQ * NQ + o] = out[o].v;
+              if (!isfinite(out[o].v)) atomicOr(&s_cellflag, 4);
+            }
+          } else {
+            for (int o = 0; o < NQ; ++o) s_ov[jb * NQ + o] = out[o].v;
+          }
+          // J of the current state and of the mesh-stiffness field must stay positive
+          if (!solid && !face) {
+            double Fv[D][D], Fz[D][D];
+            for (int c = 0; c < D; ++c)
+              for (int k = 0; k < D; ++k) {
+                Fv[c][k] = qv[Q::QGU + c * D + k] + (c == k ? 1.0 : 0.0);
+                Fz[c][k] = qv[NQ + 3 * D + c * D + k] + (c == k ? 1.0 : 0.0);
+              }
+            if (!(det_plain<D>(Fv) > 0.0) || !(det_plain<D>(Fz) > 0.0)) atomicOr(&s_cellflag, 1);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    if constexpr (MODE == FE_RESIDUAL) {
+      for (int jb = 0; jb < nb; ++jb) {
+        const double* N = s_sh + jb * SH;
+        const double* dN = N + NQ2;
+        const double* M = dN + NQ2 * D;
+        const double w = M[NQ1];
+        const double* ov = s_ov + jb * NQ;
         if (row_on) {
           if (t < 2 * NV) {
             const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
             const int l = (t % NV) / D, c = (t % NV) % D;
-            double tw[4];
-            tw[0] = w * N[l];
-            for (int k = 0; k < D; ++k) tw[1 + k] = w * dN[l * D + k];
-            for (int j = 0; j < Q::NJ; ++j) {
-              const int s = sl + Q::SL * j;
-              if (s >= NLOC) break;
+            double s = ov[fo + c] * N[l];
+            for (int k = 0; k < D; ++k) s += ov[go + c * D + k] * dN[l * D + k];
+            res += w * s;
+          } else {
+            res += w * ov[Q::QP] * M[t - 2 * NV];
+          }
+        }
+      }
+      __syncthreads();  // the next batch overwrites the tables
+    }
+    if constexpr (MODE == FE_CONTRACT) {
+      const double* N = s_sh;
+      const double* dN = N + NQ2;
+      const double* M = dN + NQ2 * D;
+      const double w = M[NQ1];
+      const double* Dm = s_Dm;
+      for (int idx = tid; idx < NLOC * NQ; idx += blockDim.x) {
+        const int s = idx / NQ, o = idx % NQ;
+        double val = 0.0;
+        if (s_gd[s] >= 0) {
+          if (s < 2 * NV) {
+            const int fi = s < NV ? Q::QV : Q::QU, gi = s < NV ? Q::QGV : Q::QGU;
+            const int l = (s % NV) / D, e = (s % NV) % D;
+            val = Dm[o * NQ + fi + e] * N[l];
+            for (int k = 0; k < D; ++k) val += Dm[o * NQ + gi + e * D + k] * dN[l * D + k];
+          } else {
+            val = Dm[o * NQ + Q::QP] * M[s - 2 * NV];
+          }
+        }
+        s_DB[idx] = val;
+      }
+      __syncthreads();
+      if (row_on) {
+        if (t < 2 * NV) {
+          const int fo = t < NV ? Q::QV : Q::QU, go = t < NV ? Q::QGV : Q::QGU;
+          const int l = (t % NV) / D, c = (t % NV) % D;
+          double tw[4];
+          tw[0] = w * N[l];
+          for (int k = 0; k < D; ++k) tw[1 + k] = w * dN[l * D + k];
+#pragma unroll
+          for (int j = 0; j < Q::NJ; ++j) {  // unrolled: acc stays in registers
+            const int s = sl + Q::SL * j;
+            if (s < NLOC) {
               const double* db = s_DB + s * NQ;
               double v = tw[0] * db[fo + c];
               for (int k = 0; k < D; ++k) v += tw[1 + k] * db[go + c * D + k];
               acc[j] += v;
             }
-          } else {
-            const double tw = w * M[t - 2 * NV];
-            for (int j = 0; j < Q::NJ; ++j) {
-              const int s = sl + Q::SL * j;
-              if (s >= NLOC) break;
-              acc[j] += tw * s_DB[s * NQ + Q::QP];
-            }
+          }
+        } else {
+          const double tw = w * M[t - 2 * NV];
+#pragma unroll
+          for (int j = 0; j < Q::NJ; ++j) {
+            const int s = sl + Q::SL * j;
+            if (s < NLOC) acc[j] += tw * s_DB[s * NQ + Q::QP];
           }
         }
-        __syncthreads();
       }
+      __syncthreads();  // the next point overwrites the tables
     }
-    __syncthreads();  // the next batch overwrites the derivative tables
+    if constexpr (MODE == FE_POINTS) __syncthreads();
   }
   int bad = 0;
   if (row_on) {
     const int64_t grow = s_gd[t];
-    if (want_res && sl == 0) {
+    if constexpr (MODE == FE_RESIDUAL) {
       if (!isfinite(res)) bad |= 4;
       R[grow] += res;
     }
-    if (want_mat) {
+    if constexpr (MODE == FE_CONTRACT) {
+#pragma unroll
       for (int j = 0; j < Q::NJ; ++j) {
         const int s = sl + Q::SL * j;
-        if (s >= NLOC) break;
-        const int64_t gcol = s_gd[s];
-        if (gcol < 0) continue;
-        const double v = acc[j];
-        if (!isfinite(v)) bad |= 4;
-        double* slot = ah_slot(ah, grow, int32_t(gcol));
-        if (slot) *slot += v;
-        else if (v != 0.0) bad |= 2;
+        const int64_t gcol = s < NLOC ? s_gd[s] : -1;
+        if (gcol >= 0) {
+          const double v = acc[j];
+          if (!isfinite(v)) bad |= 4;
+          double* slot = ah_slot(ah, grow, int32_t(gcol));
+          if (slot) *slot += v;
+          else if (v != 0.0) bad |= 2;
+        }
       }
     }
   }

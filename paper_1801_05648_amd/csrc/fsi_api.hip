@@ -1641,6 +1641,8 @@ struct FeState {
   FeParams prm{};
   int64_t n_nodes = 0;
   DevBuf vdof, udof, pdof, v, u, p, v_old, u_old, w, u_fz, flag, part;
+  DevBuf basis;  // basis values and weights at the quadrature points (the same for every cell)
+  DevBuf pts;    // integrand values and derivatives at every point of the cells of one launch
   std::shared_ptr<DevBuf> brp[FSI_NBLK], bci[FSI_NBLK];
   std::vector<double> spare[FSI_NBLK];  // host value arrays of the blocks' previous values, reused
   FeNodes nodes() const {
@@ -3837,21 +3839,40 @@ static void fe_assemble(fsi_ctx& c, const double* dU, double* R, bool want_mat) 
   }
   HIP_TRY(hipMemsetAsync(F.flag.p, 0, sizeof(int), s));
   const int D = F.prm.D;
-  for (int color = 0; color < (1 << D); ++color) {
-    int64_t ncell = 1;
-    for (int a = 0; a < D; ++a) ncell *= (F.prm.nc[a] - ((color >> a) & 1) + 1) / 2;
-    if (ncell == 0) continue;
-    if (D == 2) {
-      dim3 grid(unsigned(ncell), want_mat ? FeDims<2>::NCHUNK : 1);
-      fe_assemble_kernel<2><<<grid, 256, 0, s>>>(F.prm, F.nodes(), dU, color, R != nullptr, want_mat, R, ah,
-                                                 F.flag.as<int>());
-    } else {
-      dim3 grid(unsigned(ncell), want_mat ? FeDims<3>::NCHUNK : 1);
-      fe_assemble_kernel<3><<<grid, 256, 0, s>>>(F.prm, F.nodes(), dU, color, R != nullptr, want_mat, R, ah,
-                                                 F.flag.as<int>());
+  auto launch = [&](auto dc) {
+    constexpr int DD = decltype(dc)::value;
+    using Q = FeDims<DD>;
+    constexpr int64_t GS = Q::NQ * Q::NQ + Q::NQ;
+    int64_t max_cells = 0;
+    for (int color = 0; color < (1 << DD); ++color) {
+      int64_t n = 1;
+      for (int a = 0; a < DD; ++a) n *= (F.prm.nc[a] - ((color >> a) & 1) + 1) / 2;
+      max_cells = std::max(max_cells, n);
     }
-    HIP_TRY(hipGetLastError());
-  }
+    if (want_mat && F.pts.bytes < sizeof(double) * size_t(max_cells * Q::NPT * GS))
+      F.pts.alloc(sizeof(double) * size_t(max_cells * Q::NPT * GS));
+    for (int color = 0; color < (1 << DD); ++color) {
+      int64_t ncell = 1;
+      for (int a = 0; a < DD; ++a) ncell *= (F.prm.nc[a] - ((color >> a) & 1) + 1) / 2;
+      if (ncell == 0) continue;
+      const FeNodes nd = F.nodes();
+      const double* bt = F.basis.as<double>();
+      int* fl = F.flag.as<int>();
+      if (R)
+        fe_assemble_kernel<DD, FE_RESIDUAL><<<dim3(unsigned(ncell), 1), 256, 0, s>>>(F.prm, nd, bt, dU, color, R,
+                                                                                     nullptr, ah, fl);
+      if (want_mat) {
+        double* pts = F.pts.as<double>();
+        fe_assemble_kernel<DD, FE_POINTS><<<dim3(unsigned(ncell), 1), 256, 0, s>>>(F.prm, nd, bt, dU, color,
+                                                                                   nullptr, pts, ah, fl);
+        fe_assemble_kernel<DD, FE_CONTRACT><<<dim3(unsigned(ncell), Q::NCHUNK), 256, 0, s>>>(
+            F.prm, nd, bt, dU, color, nullptr, pts, ah, fl);
+      }
+      HIP_TRY(hipGetLastError());
+    }
+  };
+  if (D == 2) launch(std::integral_constant<int, 2>{});
+  else launch(std::integral_constant<int, 3>{});
   int flag = 0;
   HIP_TRY(hipMemcpyAsync(&flag, F.flag.p, sizeof(int), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -4051,6 +4072,16 @@ fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* m) {
     }
     fe->flag.alloc(sizeof(int));
     fe->part.alloc(sizeof(double) * 1024);
+    if (D == 2) {
+      fe->basis.alloc(sizeof(double) * FeDims<2>::NPT * FeDims<2>::SH);
+      const int jobs = FeDims<2>::NPT * (FeDims<2>::NQ2 + FeDims<2>::NQ1);
+      fe_basis_kernel<2><<<(jobs + 255) / 256, 256, 0, s>>>(P, fe->basis.as<double>());
+    } else {
+      fe->basis.alloc(sizeof(double) * FeDims<3>::NPT * FeDims<3>::SH);
+      const int jobs = FeDims<3>::NPT * (FeDims<3>::NQ2 + FeDims<3>::NQ1);
+      fe_basis_kernel<3><<<(jobs + 255) / 256, 256, 0, s>>>(P, fe->basis.as<double>());
+    }
+    HIP_TRY(hipGetLastError());
     HIP_TRY(hipStreamSynchronize(s));
     c.fe = std::move(fe);
     return FSI_OK;
