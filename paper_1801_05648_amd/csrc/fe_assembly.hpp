@@ -452,6 +452,8 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
   __shared__ double s_ov[MODE == FE_RESIDUAL ? QB * NQ : 1];
   __shared__ double s_Dm[MODE == FE_CONTRACT ? NQ * NQ : 1];  // s_Dm[o * NQ + i] = d out_o / d q_i
   __shared__ double s_DB[MODE == FE_CONTRACT ? NLOC * NQ : 1];
+  __shared__ int s_olist[NQ];  // FE_CONTRACT: the outputs this chunk's test rows use
+  __shared__ int s_nout;
   __shared__ int s_cellflag;
   const int tid = threadIdx.x;
   // the cell of this workgroup within its parity class
@@ -525,6 +527,29 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
   const int t = MODE == FE_CONTRACT ? int(blockIdx.y) * Q::RT + tr : tid;
   bool row_on = false;
   if constexpr (kRows) row_on = t < NLOC && s_ton[t] && s_gd[t] >= 0;
+  if constexpr (MODE == FE_CONTRACT) {
+    // a test row of field X, component c reads f_X[c] and g_X[c][k] only
+    if (tid == 0) {
+      bool need[NQ];
+      for (int o = 0; o < NQ; ++o) need[o] = false;
+      const int r0 = int(blockIdx.y) * Q::RT;
+      for (int r = r0; r < r0 + Q::RT && r < NLOC; ++r) {
+        if (r < 2 * NV) {
+          const int c = (r % NV) % D;
+          const int fo = r < NV ? Q::QV : Q::QU, go = r < NV ? Q::QGV : Q::QGU;
+          need[fo + c] = true;
+          for (int k = 0; k < D; ++k) need[go + c * D + k] = true;
+        } else {
+          need[Q::QP] = true;
+        }
+      }
+      int n = 0;
+      for (int o = 0; o < NQ; ++o)
+        if (need[o]) s_olist[n++] = o;
+      s_nout = n;
+    }
+    __syncthreads();
+  }
   double acc[MODE == FE_CONTRACT ? Q::NJ : 1];
 #pragma unroll
   for (int j = 0; j < (MODE == FE_CONTRACT ? Q::NJ : 1); ++j) acc[j] = 0.0;
@@ -637,8 +662,9 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
       const double* M = dN + NQ2 * D;
       const double w = M[NQ1];
       const double* Dm = s_Dm;
-      for (int idx = tid; idx < NLOC * NQ; idx += blockDim.x) {
-        const int s = idx / NQ, o = idx % NQ;
+      const int nout = s_nout;
+      for (int idx = tid; idx < NLOC * nout; idx += blockDim.x) {
+        const int s = idx / nout, o = s_olist[idx % nout];
         double val = 0.0;
         if (s_gd[s] >= 0) {
           if (s < 2 * NV) {
@@ -650,7 +676,7 @@ __global__ __launch_bounds__(256) void fe_assemble_kernel(FeParams P, FeNodes nd
             val = Dm[o * NQ + Q::QP] * M[s - 2 * NV];
           }
         }
-        s_DB[idx] = val;
+        s_DB[s * NQ + o] = val;
       }
       __syncthreads();
       if (row_on) {
