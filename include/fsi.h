@@ -426,7 +426,8 @@ fsi_status fsi_mlp_train(fsi_ctx* ctx, const fsi_mlp_train_opts* opts, fsi_mlp_t
  * ---------------------------------------------------------------------- */
 typedef struct {
   int32_t dim;                 /* 2 or 3: the system's d                                   */
-  int32_t cells[3];            /* cells per axis (1..65535; unused axes ignored)          */
+  int32_t cells[3];            /* cells per axis (1..65535, at most 2^31 - 1 in all;
+                                  unused axes ignored)                                    */
   double extent[3];            /* channel lengths                                          */
   int32_t solid_lo[3];         /* solid cells: solid_lo[a] <= C[a] < solid_hi[a], all a    */
   int32_t solid_hi[3];
@@ -479,8 +480,9 @@ typedef struct {
 void fsi_default_newton_opts(fsi_newton_opts* o);
 
 /* Upload the finite-element description of the system in the context (after
- * fsi_setup_blocks; a new system drops it).  Checks the sizes, the dof maps
- * against N and the fields for NaN/Inf.  Host arrays; copied. */
+ * fsi_setup_blocks; a new system drops it).  Checks the sizes (FSI_ERR_ARG
+ * before any array is read), the dof maps against N and the fields for
+ * NaN/Inf.  Host arrays; copied. */
 fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* mesh);
 
 /* R = R(U) of Section 3 at U = given fields + dU.  dU: device, length N, or

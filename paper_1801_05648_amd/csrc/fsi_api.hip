@@ -4018,6 +4018,9 @@ fsi_status fsi_fe_setup(fsi_ctx* ctx, const fsi_fe_mesh* m) {
       }
     }
     if (nn != m->n_nodes) throw Error(FSI_ERR_ARG, "n_nodes must be the product of 2 cells + 1");
+    // one launch per parity class holds its cells in blockIdx.x
+    if (int64_t(P.nc[0]) * P.nc[1] * P.nc[2] > int64_t(INT32_MAX))
+      throw Error(FSI_ERR_ARG, "more than 2^31 - 1 cells");
     P.rho_f = m->rho_f; P.nu_f = m->nu_f; P.rho_s = m->rho_s; P.mu_s = m->mu_s; P.lambda_s = m->lambda_s;
     P.dtth = m->dt * m->theta;
     P.theta = m->theta;

@@ -19,6 +19,8 @@ evaluates the same residual with numpy and the Jacobian by complex steps.
   iterate, the reassembly decisions follow the rule on the reported norms, and
   the iterate is near the oracle's exact-Newton root.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -160,6 +162,21 @@ def test_fe_errors_are_reported():
     with pytest.raises(FsiError) as e:
         g.fe_setup(s.cfg.with_(dt=2e-2), s.fe)
     assert e.value.name == "FSI_ERR_ARG"
+    # a grid whose parity classes do not fit one launch each is refused before
+    # any node array is read (the arrays are NULL here)
+    from paper_1801_05648_amd.fsi import CFeMesh
+    m = CFeMesh()
+    m.dim = 2
+    for a in range(3):
+        m.cells[a] = 65535 if a < 2 else 1
+        m.extent[a] = 1.0
+        m.solid_hi[a] = 1
+    for k in ("rho_f", "nu_f", "rho_s", "mu_s", "lambda_s", "dt", "theta"):
+        setattr(m, k, float(getattr(s.cfg, k)))
+    m.n_nodes = 131071 ** 2
+    with pytest.raises(FsiError) as e:
+        g._check(g.lib.fsi_fe_setup(g.ctx, ctypes.byref(m)))
+    assert e.value.name == "FSI_ERR_ARG" and "2^31" in str(e.value)
     g.fe_setup(s.cfg, s.fe)
     # a displacement offset that folds a fluid cell: J <= 0 is reported, not assembled
     dU = np.zeros(s.N)
