@@ -75,14 +75,50 @@ class BlockLDU:
     used in step 3 (C_fs in the paper's algorithm; the exact factorisation
     uses C_fs - C_fm M^{-1} C_ms there) and ``fluid_inv`` may be replaced by
     an exact inverse of the Schur complement X for identity tests.
+
+    ``order``: "msf" (default) factorises with the blocks in the paper's
+    order, mesh, solid, fluid (Section 4.1, algorithm "Evaluation of P^{-1} r"); "fsm" takes them
+    in the reverse order (the remark after the factorisation in Section 4.1:
+    the LDU factorisation, and so the preconditioner, depends on the block
+    order).  With C_sm dropped as in the paper, eliminating the fluid first
+    gives the pivots F, S - C_sf F^{-1} C_fs and a mesh pivot perturbed by
+    C_ms (...)^{-1} C_sf F^{-1} C_fm; dropping those perturbations as the
+    paper drops its own (S and M for the pivots, no solid update from the
+    mesh) leaves
+
+        x_f = F^{-1} r_f;  x_s = S^{-1} (r_s - C_sf x_f);
+        x_m = M^{-1} (r_m - C_ms x_s);  x_f -= F^{-1} (C_fm x_m + C_fs x_s).
+
+    ``csm`` (order "fsm" only) is the coupling of the solid update from the
+    mesh, x_s -= S^{-1} csm(x_m), that the exact factorisation has
+    (-C_sf F^{-1} C_fm); it is off in the preconditioner and set only by
+    identity tests with exact pivots.
     """
 
-    def __init__(self, bs: BlockSystem, mesh_inv, solid_inv, fluid_inv, cfs=None):
+    def __init__(self, bs: BlockSystem, mesh_inv, solid_inv, fluid_inv, cfs=None, order: str = "msf", csm=None):
+        if order not in ("msf", "fsm"):
+            raise ValueError(f"unknown block order {order!r}")
         self.bs = bs
         self.mesh_inv, self.solid_inv, self.fluid_inv = mesh_inv, solid_inv, fluid_inv
         self.cfs = cfs
+        self.order = order
+        self.csm = csm
+
+    def _apply_fsm(self, r: np.ndarray) -> np.ndarray:
+        bs = self.bs
+        B = bs.B
+        r_m, r_s, r_f = bs.split(r)
+        x_f = self.fluid_inv(r_f)
+        x_s = self.solid_inv(r_s - B["C_sf"] @ x_f)
+        x_m = self.mesh_inv(r_m - B["C_ms"] @ x_s)
+        if self.csm is not None:
+            x_s = x_s - self.solid_inv(self.csm(x_m))
+        x_f = x_f - self.fluid_inv(B["C_fm"] @ x_m + B["C_fs"] @ x_s)
+        return bs.join(x_m, x_s, x_f)
 
     def apply(self, r: np.ndarray) -> np.ndarray:
+        if self.order == "fsm":
+            return self._apply_fsm(r)
         bs = self.bs
         B = bs.B
         r_m, r_s, r_f = bs.split(r)
@@ -174,7 +210,7 @@ def mesh_solve(bs: BlockSystem, l_inv, r_m: np.ndarray) -> np.ndarray:
 
 def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly: dict | None = None,
                        fluid_inner: int = 0, fluid_inner_pc: str = "uzawa", x_approx: str = "F",
-                       uzawa_inner: int = 0) -> BlockLDU:
+                       uzawa_inner: int = 0, order: str = "msf") -> BlockLDU:
     """The preconditioner of the hot path: every inverse one V(1,1) cycle
     (Jacobi sweeps; Chebyshev sweeps of degree cheb[name] for the hierarchies
     named in `cheb`).  For the names in `poly`, {name: (k, ratio)}, the
@@ -187,7 +223,8 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
     its block-diagonal approximation; the hierarchies H must be built with
     the same choice).  uzawa_inner = k > 0: the Uzawa-like step with every
     occurring inverse taken as k GMRES steps preconditioned by its V-cycle
-    (fluid_schur_gmres_solve; not combined with fluid_inner)."""
+    (fluid_schur_gmres_solve; not combined with fluid_inner).  order: the
+    block order of the factorisation (BlockLDU)."""
     cheb = cheb or {}
     fl = bs.fluid_x(x_approx)
     poly = poly or {}
@@ -220,4 +257,4 @@ def amg_preconditioner(bs: BlockSystem, H: dict, cheb: dict | None = None, poly:
         else:
             raise ValueError(f"unknown inner fluid preconditioner {fluid_inner_pc!r}")
         fluid = lambda r: fluid_gmres_solve(fl, inner, r, fluid_inner)
-    return BlockLDU(bs, mesh, solid, fluid)
+    return BlockLDU(bs, mesh, solid, fluid, order=order)
