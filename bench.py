@@ -792,7 +792,8 @@ def main():
     # hierarchies (reuse: only the device copies, smoothers and the fluid
     # solve change); where the headline takes SIMPLEC, the paper's step again
     # with SIMPLE (a build of its own), and the Uzawa-like step with one
-    # V-cycle per inverse and SIMPLE (the reading without inner Krylov steps)
+    # V-cycle per inverse and SIMPLE (the reading without inner Krylov steps);
+    # the headline options with the blocks factorised in the reverse order
     if not args.no_mixed and args.precision == "f64":
         r = runs[0]
         x64 = r["x"].clone()
@@ -804,6 +805,7 @@ def main():
                 forms.append(("paper_uzawa_gmres2_simple", "f64",
                               dict(fluid_inner=0, uzawa_inner=2, schur="simple"), False))
             forms.append(("uzawa_vcycle_simple", "f64", dict(fluid_inner=0, uzawa_inner=0, schur="simple"), True))
+        forms.append(("reverse_block_order", "f64", dict(order="fsm"), True))
         for label, prec, over, reuse in forms:
             o2 = dict(opts)
             o2.update(over)

@@ -175,11 +175,22 @@ typedef struct {
                           reorthogonalisation, stopping early only at an exact
                           solve).  Not combined with fluid_inner > 0.  Stores
                           A_f and S_p once more                               */
-  int32_t pad2;
+  int32_t order;       /* block order of the LDU factorisation (Section 4.1
+                          remarks that it decides the preconditioner):
+                          FSI_ORDER_MSF (default; mesh, solid, fluid: the
+                          paper's algorithm) or FSI_ORDER_FSM (fluid, solid,
+                          mesh, with C_sm dropped and the perturbed pivots
+                          replaced by S and M as the paper does for its own
+                          order: x_f = F^{-1} r_f, x_s = S^{-1}(r_s - C_sf x_f),
+                          x_m = M^{-1}(r_m - C_ms x_s), then
+                          x_f -= F^{-1}(C_fm x_m + C_fs x_s); two fluid
+                          inverses and one mesh and solid inverse per
+                          application, one more fluid vector stored)         */
 } fsi_precond_opts;
 
 enum { FSI_INNER_UZAWA = 0, FSI_INNER_TRIANGULAR = 1 };
 enum { FSI_X_F = 0, FSI_X_BLOCKDIAG = 1 };
+enum { FSI_ORDER_MSF = 0, FSI_ORDER_FSM = 1 };
 
 enum { FSI_SCHUR_SIMPLE = 0, FSI_SCHUR_SIMPLEC = 1 };
 

@@ -1401,6 +1401,8 @@ struct Precond {
   // on S_p, preconditioned by its V-cycle; they share the inner buffers
   int uz_k = 0;
   DCsr<T> Am, Spm;
+  int order = FSI_ORDER_MSF;  // block order of the factorisation
+  std::shared_ptr<DevBuf> tf2;  // FSI_ORDER_FSM: the second fluid inverse's output
   std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ibrk;
   int inner_nb = 1;
 
@@ -1413,6 +1415,7 @@ struct Precond {
     tu = mk(n_vs); tu2 = mk(n_vs); tv = mk(n_vs);
     tf = mk(n_f); ta = mk(n_vf); ta2 = mk(n_vf); tp = mk(n_p);
     ts = mk(n_s); ts2 = mk(n_s); tm = mk(n_m); tm2 = mk(n_m);
+    if (order == FSI_ORDER_FSM) tf2 = mk(n_f);
     if (sizeof(T) != sizeof(double)) { rT = mk(N); zT = mk(N); }
     const int kmax = std::max(inner_k, uz_k);
     if (kmax > 0) {
@@ -1586,6 +1589,9 @@ struct Precond {
       fluid = 2 * ga + gmres(uz_k, n_p, H[FSI_H_P].bytes_per_cycle, prod(Spm, n_p, n_p, 1)) +
               prod(Dm, n_vf, n_p, 2) + prod(Gm, n_p, n_vf, 2);
     }
+    if (order == FSI_ORDER_FSM)
+      return mesh + solid + 2 * fluid + prod(Csf, n_f, n_s, 2) + prod(Cms, n_s, n_m, 2) +
+             prod(Cfms, n_m + n_s, n_f, 1) + 3.0 * w * double(n_f);
     return 2 * mesh + 2 * solid + prod(Cfms, n_m + n_s, n_f, 2) + fluid + prod(Csf, n_f, n_s, 1) +
            prod(Cms, n_s, n_m, 1) + 3.0 * w * double(n_s + n_m);
   }
@@ -1598,6 +1604,18 @@ struct Precond {
     T* z_m = z;
     T* z_s = z + n_m;
     T* z_f = z + n_m + n_s;
+    if (order == FSI_ORDER_FSM) {
+      // the blocks in the reverse order (fluid, solid, mesh)
+      fluid_inverse(r_f, z_f, s);                            // x_f = F^{-1} r_f
+      spmv_sub<T>(Csf, z_f, r_s, ts->as<T>(), s);            // x_s = S^{-1} (r_s - C_sf x_f)
+      solid(ts->as<T>(), z_s, s);
+      spmv_sub<T>(Cms, z_s, r_m, tm->as<T>(), s);            // x_m = M^{-1} (r_m - C_ms x_s)
+      vcycle(H[FSI_H_M], tm->as<T>(), z_m, s);
+      spmv<T>(Cfms, z, tf->as<T>(), s);                      // x_f -= F^{-1} (C_fm x_m + C_fs x_s)
+      fluid_inverse(tf->as<T>(), tf2->as<T>(), s);
+      vsub<T>(n_f, z_f, tf2->as<T>(), s);
+      return;
+    }
     vcycle(H[FSI_H_M], r_m, z_m, s);                         // 1. x_m = M^{-1} r_m
     solid(r_s, z_s, s);                                      // 2. x_s = S^{-1} r_s
     spmv_sub<T>(Cfms, z, r_f, tf->as<T>(), s);               // 3. r_f - C_fm x_m - C_fs x_s
@@ -1680,6 +1698,7 @@ struct fsi_ctx {
   int fluid_inner = 0;                     // inner GMRES steps of the fluid inverse (0: off)
   int fluid_inner_pc = FSI_INNER_UZAWA;    // their preconditioner
   int uzawa_inner = 0;                     // GMRES steps per inverse of the Uzawa-like step (0: off)
+  int order = FSI_ORDER_MSF;               // block order of the factorisation
   double poly_ratio = 8.0;
   SaHierarchy host_h[FSI_NHIER];
   bool have_host_h = false;  // host_h built for the current system
@@ -1864,6 +1883,7 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     P->inner_k = c.fluid_inner;
     P->inner_pc = c.fluid_inner_pc;
     if (c.fluid_inner > 0) P->Fm = upload_segments<T>(F, bounds, groups, 2, s);
+    P->order = c.order;
     P->uz_k = c.uzawa_inner;
     if (c.uzawa_inner > 0) {
       const int64_t vb[2] = {0, c.n_vf};
@@ -3078,6 +3098,7 @@ void fsi_default_precond_opts(fsi_precond_opts* o) {
   o->reuse = 0;
   o->x_approx = FSI_X_F;
   o->uzawa_inner = 0;
+  o->order = FSI_ORDER_MSF;
 }
 
 void fsi_default_solve_opts(fsi_solve_opts* o) {
@@ -3357,6 +3378,7 @@ static fsi_status build_precond_impl(fsi_ctx& c, const fsi_precond_opts* opts) {
       throw Error(FSI_ERR_ARG, "GMRES on F and GMRES on the Uzawa-like step's inverses do not combine");
     if (o.x_approx != FSI_X_F && o.x_approx != FSI_X_BLOCKDIAG)
       throw Error(FSI_ERR_ARG, "unknown approximation of the fluid Schur complement X");
+    if (o.order != FSI_ORDER_MSF && o.order != FSI_ORDER_FSM) throw Error(FSI_ERR_ARG, "unknown block order");
     SaParams prm;
     prm.eps0 = o.strength0;
     prm.max_coarse = o.max_coarse;
@@ -3381,6 +3403,7 @@ static fsi_status build_precond_impl(fsi_ctx& c, const fsi_precond_opts* opts) {
     c.fluid_inner = o.fluid_inner;
     c.fluid_inner_pc = o.fluid_inner_pc;
     c.uzawa_inner = o.uzawa_inner;
+    c.order = o.order;
     c.precision = o.precision;  // before prepare_mlp: it decides which hierarchies can learn
     prepare_mlp(c);
     c.drop_graphs();

@@ -97,7 +97,7 @@ class CPrecondOpts(ctypes.Structure):
                 ("cheb_mask", ctypes.c_int32), ("poly_mask", ctypes.c_int32), ("poly_degree", ctypes.c_int32),
                 ("schur", ctypes.c_int32), ("poly_ratio", ctypes.c_double), ("fluid_inner", ctypes.c_int32),
                 ("fluid_inner_pc", ctypes.c_int32), ("reuse", ctypes.c_int32), ("x_approx", ctypes.c_int32),
-                ("uzawa_inner", ctypes.c_int32), ("pad2", ctypes.c_int32)]
+                ("uzawa_inner", ctypes.c_int32), ("order", ctypes.c_int32)]
 
 
 class CSolveOpts(ctypes.Structure):
@@ -123,6 +123,7 @@ class CMlpTrainOpts(ctypes.Structure):
 MLP_LOSS = {"l2": 0, "energy": 1}
 INNER_PC = {"uzawa": 0, "triangular": 1}
 X_APPROX = {"F": 0, "blockdiag": 1}
+ORDER = {"msf": 0, "fsm": 1}
 
 
 class CMlpTrainInfo(ctypes.Structure):
@@ -358,13 +359,14 @@ class FsiSolver:
                       strength0: float = 0.08, cheb_degree: int = 0, cheb=("H_MS", "H_SIG", "H_P"),
                       poly=(), poly_degree: int = 3, poly_ratio: float = 8.0, schur: str = "simple",
                       fluid_inner: int = 0, fluid_inner_pc: str = "uzawa", reuse: bool = False,
-                      x_approx: str = "F", uzawa_inner: int = 0):
+                      x_approx: str = "F", uzawa_inner: int = 0, order: str = "msf"):
         """fsi_build_precond.  reuse=True keeps the context's SA hierarchies
         (same system, same AMG parameters, Schur and X options as the
         previous build) and rebuilds only what the other options change.
         x_approx: "F" or "blockdiag" (the fluid operator standing for the
         Schur complement X).  uzawa_inner: GMRES steps per inverse of the
-        Uzawa-like fluid step (Section 4.4 as written; 0 = one V-cycle)."""
+        Uzawa-like fluid step (Section 4.4 as written; 0 = one V-cycle).
+        order: "msf" (the paper's block order) or "fsm" (the reverse order)."""
         def mask_of(names):
             m = 0
             for name in names:
@@ -372,7 +374,8 @@ class FsiSolver:
             return m
         o = CPrecondOpts(PRECISION[precision], max_coarse, max_levels, int(cheb_degree), strength0, mask_of(cheb),
                          mask_of(poly), int(poly_degree), SCHUR[schur], float(poly_ratio), int(fluid_inner),
-                         INNER_PC[fluid_inner_pc], int(bool(reuse)), X_APPROX[x_approx], int(uzawa_inner), 0)
+                         INNER_PC[fluid_inner_pc], int(bool(reuse)), X_APPROX[x_approx], int(uzawa_inner),
+                         ORDER[order])
         self._check(self.lib.fsi_build_precond(self.ctx, ctypes.byref(o)))
 
     def fe_setup(self, cfg, fe: dict):
