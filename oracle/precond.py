@@ -76,27 +76,34 @@ class BlockLDU:
     uses C_fs - C_fm M^{-1} C_ms there) and ``fluid_inv`` may be replaced by
     an exact inverse of the Schur complement X for identity tests.
 
-    ``order``: "msf" (default) factorises with the blocks in the paper's
-    order, mesh, solid, fluid (Section 4.1, algorithm "Evaluation of P^{-1} r"); "fsm" takes them
-    in the reverse order (the remark after the factorisation in Section 4.1:
-    the LDU factorisation, and so the preconditioner, depends on the block
-    order).  With C_sm dropped as in the paper, eliminating the fluid first
-    gives the pivots F, S - C_sf F^{-1} C_fs and a mesh pivot perturbed by
-    C_ms (...)^{-1} C_sf F^{-1} C_fm; dropping those perturbations as the
-    paper drops its own (S and M for the pivots, no solid update from the
-    mesh) leaves
+    ``order``: the block order of the factorisation, a permutation of
+    "msf" (m mesh, s solid, f fluid).  "msf" (default) is the paper's order
+    and its algorithm "Evaluation of P^{-1} r" (Section 4.1), written out in
+    ``apply``.  The remark after the factorisation in Section 4.1 notes that
+    another order gives another preconditioner.  Factorising A' (C_sm
+    dropped, as in the paper) in the order (a, b, c) and dropping every
+    perturbation of the pivots and multipliers, as the paper does for its own
+    order (X by F, C~_fs by C_fs), leaves a block symmetric Gauss-Seidel
+    sweep in that order,
 
-        x_f = F^{-1} r_f;  x_s = S^{-1} (r_s - C_sf x_f);
-        x_m = M^{-1} (r_m - C_ms x_s);  x_f -= F^{-1} (C_fm x_m + C_fs x_s).
+        forward:   x_i = A_ii^{-1} (r_i - sum_{j before i} A_ij x_j),
+        backward:  x_i -= A_ii^{-1} sum_{j after i} A_ij x_j  (i = b, then a),
 
-    ``csm`` (order "fsm" only) is the coupling of the solid update from the
-    mesh, x_s -= S^{-1} csm(x_m), that the exact factorisation has
-    (-C_sf F^{-1} C_fm); it is off in the preconditioner and set only by
-    identity tests with exact pivots.
+    with A_mm = M, A_ss = S, A_ff = F and the couplings C_fm, C_fs, C_sf,
+    C_ms (C_sm and C_mf are zero).  For "msf" these are exactly the paper's
+    five steps.  E.g. the reverse order "fsm":
+    x_f = F^{-1} r_f;  x_s = S^{-1} (r_s - C_sf x_f);
+    x_m = M^{-1} (r_m - C_ms x_s);  x_f -= F^{-1} (C_fm x_m + C_fs x_s).
+
+    ``csm`` (orders other than "msf") stands for the solid-mesh coupling,
+    which the preconditioner drops; identity tests with the exact pivots of
+    an elimination set it to the entry that elimination leaves there.
     """
 
+    ORDERS = ("msf", "fsm", "mfs", "smf", "sfm", "fms")
+
     def __init__(self, bs: BlockSystem, mesh_inv, solid_inv, fluid_inv, cfs=None, order: str = "msf", csm=None):
-        if order not in ("msf", "fsm"):
+        if order not in self.ORDERS:
             raise ValueError(f"unknown block order {order!r}")
         self.bs = bs
         self.mesh_inv, self.solid_inv, self.fluid_inv = mesh_inv, solid_inv, fluid_inv
@@ -104,21 +111,48 @@ class BlockLDU:
         self.order = order
         self.csm = csm
 
-    def _apply_fsm(self, r: np.ndarray) -> np.ndarray:
+    def _coupling(self, i: str, j: str):
+        """x_j -> A_ij x_j for the off-diagonal block (i, j) of A', or None."""
+        B = self.bs.B
+        if (i, j) == ("f", "m"):
+            return lambda x: B["C_fm"] @ x
+        if (i, j) == ("f", "s"):
+            return self.cfs if self.cfs is not None else (lambda x: B["C_fs"] @ x)
+        if (i, j) == ("s", "f"):
+            return lambda x: B["C_sf"] @ x
+        if (i, j) == ("m", "s"):
+            return lambda x: B["C_ms"] @ x
+        if (i, j) == ("s", "m"):
+            return self.csm
+        return None  # (m, f): no mesh-fluid coupling
+
+    def _apply_ordered(self, r: np.ndarray) -> np.ndarray:
         bs = self.bs
-        B = bs.B
-        r_m, r_s, r_f = bs.split(r)
-        x_f = self.fluid_inv(r_f)
-        x_s = self.solid_inv(r_s - B["C_sf"] @ x_f)
-        x_m = self.mesh_inv(r_m - B["C_ms"] @ x_s)
-        if self.csm is not None:
-            x_s = x_s - self.solid_inv(self.csm(x_m))
-        x_f = x_f - self.fluid_inv(B["C_fm"] @ x_m + B["C_fs"] @ x_s)
-        return bs.join(x_m, x_s, x_f)
+        inv = {"m": self.mesh_inv, "s": self.solid_inv, "f": self.fluid_inv}
+        rb = dict(zip("msf", bs.split(r)))
+        o = self.order
+        x = {}
+
+        def coupled(i, js):
+            terms = [(self._coupling(i, j), j) for j in js]
+            terms = [(A, j) for A, j in terms if A is not None]
+            if not terms:
+                return None
+            return sum(A(x[j]) for A, j in terms)
+
+        for k, i in enumerate(o):
+            c = coupled(i, o[:k])
+            x[i] = inv[i](rb[i] if c is None else rb[i] - c)
+        for k in (1, 0):
+            i = o[k]
+            c = coupled(i, o[k + 1:])
+            if c is not None:
+                x[i] = x[i] - inv[i](c)
+        return bs.join(x["m"], x["s"], x["f"])
 
     def apply(self, r: np.ndarray) -> np.ndarray:
-        if self.order == "fsm":
-            return self._apply_fsm(r)
+        if self.order != "msf":
+            return self._apply_ordered(r)
         bs = self.bs
         B = bs.B
         r_m, r_s, r_f = bs.split(r)
