@@ -793,7 +793,8 @@ def main():
     # solve change); where the headline takes SIMPLEC, the paper's step again
     # with SIMPLE (a build of its own), and the Uzawa-like step with one
     # V-cycle per inverse and SIMPLE (the reading without inner Krylov steps);
-    # the headline options with the blocks factorised in the reverse order
+    # the headline options with the blocks factorised in the reverse order,
+    # and in the order solid, mesh, fluid (one mesh inverse fewer)
     if not args.no_mixed and args.precision == "f64":
         r = runs[0]
         x64 = r["x"].clone()
@@ -802,6 +803,7 @@ def main():
         # the forms that keep the headline's hierarchies come first: a build
         # with another Schur option replaces them
         forms.append(("reverse_block_order", "f64", dict(order="fsm"), True))
+        forms.append(("block_order_smf", "f64", dict(order="smf"), True))
         if args.uzawa_inner == 0:
             forms.append(("paper_uzawa_gmres2", "f64", dict(fluid_inner=0, uzawa_inner=2), True))
             if opts["schur"] != "simple":

@@ -176,21 +176,33 @@ typedef struct {
                           solve).  Not combined with fluid_inner > 0.  Stores
                           A_f and S_p once more                               */
   int32_t order;       /* block order of the LDU factorisation (Section 4.1
-                          remarks that it decides the preconditioner):
-                          FSI_ORDER_MSF (default; mesh, solid, fluid: the
-                          paper's algorithm) or FSI_ORDER_FSM (fluid, solid,
-                          mesh, with C_sm dropped and the perturbed pivots
-                          replaced by S and M as the paper does for its own
-                          order: x_f = F^{-1} r_f, x_s = S^{-1}(r_s - C_sf x_f),
-                          x_m = M^{-1}(r_m - C_ms x_s), then
-                          x_f -= F^{-1}(C_fm x_m + C_fs x_s); two fluid
-                          inverses and one mesh and solid inverse per
-                          application, one more fluid vector stored)         */
+                          remarks that it decides the preconditioner), one of
+                          FSI_ORDER_*: FSI_ORDER_MSF (default; mesh, solid,
+                          fluid: the paper's algorithm).  Another order
+                          (a, b, c), its pivot and multiplier perturbations
+                          dropped as the paper drops its own (C_sm dropped,
+                          S, M, F as pivots), is a block symmetric
+                          Gauss-Seidel sweep in that order: forward
+                          x_i = A_ii^{-1}(r_i - sum_{j before i} A_ij x_j),
+                          then x_b, x_a -= A_ii^{-1} sum_{j after i} A_ij x_j
+                          (e.g. FSI_ORDER_FSM: x_f = F^{-1} r_f,
+                          x_s = S^{-1}(r_s - C_sf x_f),
+                          x_m = M^{-1}(r_m - C_ms x_s),
+                          x_f -= F^{-1}(C_fm x_m + C_fs x_s)).  Each stores
+                          one more fluid vector; the orders with the fluid in
+                          the middle store C_fm and C_fs once more          */
 } fsi_precond_opts;
 
 enum { FSI_INNER_UZAWA = 0, FSI_INNER_TRIANGULAR = 1 };
 enum { FSI_X_F = 0, FSI_X_BLOCKDIAG = 1 };
-enum { FSI_ORDER_MSF = 0, FSI_ORDER_FSM = 1 };
+enum {
+  FSI_ORDER_MSF = 0, /* mesh, solid, fluid: the paper's order */
+  FSI_ORDER_FSM = 1, /* the reverse order */
+  FSI_ORDER_MFS = 2,
+  FSI_ORDER_SMF = 3,
+  FSI_ORDER_SFM = 4,
+  FSI_ORDER_FMS = 5
+};
 
 enum { FSI_SCHUR_SIMPLE = 0, FSI_SCHUR_SIMPLEC = 1 };
 

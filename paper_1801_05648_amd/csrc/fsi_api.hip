@@ -1402,7 +1402,8 @@ struct Precond {
   int uz_k = 0;
   DCsr<T> Am, Spm;
   int order = FSI_ORDER_MSF;  // block order of the factorisation
-  std::shared_ptr<DevBuf> tf2;  // FSI_ORDER_FSM: the second fluid inverse's output
+  std::shared_ptr<DevBuf> tf2;  // other orders: the second fluid inverse's output
+  DCsr<T> Cfm, Cfs;             // orders with the fluid in the middle: C_fm and C_fs apart
   std::shared_ptr<DevBuf> iV, iZ, ipart, iscal, ibrk;
   int inner_nb = 1;
 
@@ -1415,7 +1416,7 @@ struct Precond {
     tu = mk(n_vs); tu2 = mk(n_vs); tv = mk(n_vs);
     tf = mk(n_f); ta = mk(n_vf); ta2 = mk(n_vf); tp = mk(n_p);
     ts = mk(n_s); ts2 = mk(n_s); tm = mk(n_m); tm2 = mk(n_m);
-    if (order == FSI_ORDER_FSM) tf2 = mk(n_f);
+    if (order != FSI_ORDER_MSF) tf2 = mk(n_f);
     if (sizeof(T) != sizeof(double)) { rT = mk(N); zT = mk(N); }
     const int kmax = std::max(inner_k, uz_k);
     if (kmax > 0) {
@@ -1557,6 +1558,89 @@ struct Precond {
     else fluid(r_f, z_f, s);
   }
 
+  // Fields of a block order (0 mesh, 1 solid, 2 fluid), in FSI_ORDER_* order.
+  static constexpr int kOrderFields[6][3] = {{0, 1, 2}, {2, 1, 0}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}};
+
+  int64_t field_off(int i) const { return i == 0 ? 0 : (i == 1 ? n_m : n_m + n_s); }
+
+  // Which couplings A_ij x_j (j among o[j0..j1)) row field i has: the
+  // fluid rows couple to mesh and solid, the solid rows to the fluid, the
+  // mesh rows to the solid (C_sm is dropped; there is no mesh-fluid block).
+  static void coupled_to(int i, const int* o, int j0, int j1, bool& m, bool& sd, bool& f) {
+    m = sd = f = false;
+    for (int k = j0; k < j1; ++k) {
+      if (i == 2 && o[k] == 0) m = true;
+      if (i == 2 && o[k] == 1) sd = true;
+      if (i == 1 && o[k] == 2) f = true;
+      if (i == 0 && o[k] == 1) sd = true;
+    }
+  }
+
+  // Bytes of sum_j A_ij x_j over j among o[j0..j1) (0 when there is none);
+  // touches 2 for r - A x.
+  double coupling_bytes(int i, const int* o, int j0, int j1, int touches) const {
+    const double w = double(sizeof(T));
+    bool m, sd, f;
+    coupled_to(i, o, j0, j1, m, sd, f);
+    auto prod = [&](const DCsr<T>& A, int64_t nin, int64_t nout) {
+      return A.bytes() + w * (double(nin) + touches * double(nout));
+    };
+    if (i == 2 && m && sd) return prod(Cfms, n_m + n_s, n_f);
+    if (i == 2 && m) return prod(Cfm, n_m, n_f);
+    if (i == 2 && sd) return prod(Cfs, n_s, n_f);
+    if (i == 1 && f) return prod(Csf, n_f, n_s);
+    if (i == 0 && sd) return prod(Cms, n_s, n_m);
+    return 0.0;
+  }
+
+  // out = sum_j A_ij z_j (sub: out = r_i - sum_j A_ij z_j) over j among
+  // o[j0..j1); false (nothing written) when row field i has none of them.
+  bool couple(int i, const int* o, int j0, int j1, const T* r_i, const T* z, T* out, bool sub, hipStream_t s) {
+    bool m, sd, f;
+    coupled_to(i, o, j0, j1, m, sd, f);
+    const DCsr<T>* A = nullptr;
+    const T* x = nullptr;
+    if (i == 2 && m && sd) { A = &Cfms; x = z; }  // [x_m | x_s] are contiguous
+    else if (i == 2 && m) { A = &Cfm; x = z; }
+    else if (i == 2 && sd) { A = &Cfs; x = z + n_m; }
+    else if (i == 1 && f) { A = &Csf; x = z + n_m + n_s; }
+    else if (i == 0 && sd) { A = &Cms; x = z + n_m; }
+    if (!A) return false;
+    if (sub) spmv_sub<T>(*A, x, r_i, out, s);
+    else spmv<T>(*A, x, out, s);
+    return true;
+  }
+
+  void field_inverse(int i, const T* in, T* out, hipStream_t s) {
+    if (i == 0) vcycle(H[FSI_H_M], in, out, s);
+    else if (i == 1) solid(in, out, s);
+    else fluid_inverse(in, out, s);
+  }
+
+  // The factorisation with the fields in another order (a, b, c), its
+  // perturbations dropped as the paper drops its own: a block symmetric
+  // Gauss-Seidel sweep in that order,
+  //   forward   x_i = A_ii^{-1} (r_i - sum_{j before i} A_ij x_j),
+  //   backward  x_i -= A_ii^{-1} sum_{j after i} A_ij x_j   (i = b, then a).
+  void apply_ordered(const T* r, T* z, hipStream_t s) {
+    const int* o = kOrderFields[order];
+    T* t_in[3] = {tm->as<T>(), ts->as<T>(), tf->as<T>()};
+    T* t_out[3] = {tm2->as<T>(), ts2->as<T>(), tf2->as<T>()};
+    const int64_t nb[3] = {n_m, n_s, n_f};
+    for (int k = 0; k < 3; ++k) {
+      const int i = o[k];
+      const T* r_i = r + field_off(i);
+      const bool c = couple(i, o, 0, k, r_i, z, t_in[i], true, s);
+      field_inverse(i, c ? static_cast<const T*>(t_in[i]) : r_i, z + field_off(i), s);
+    }
+    for (int k = 1; k >= 0; --k) {
+      const int i = o[k];
+      if (!couple(i, o, k + 1, 3, nullptr, z, t_in[i], false, s)) continue;
+      field_inverse(i, t_in[i], t_out[i], s);
+      vsub<T>(nb[i], z + field_off(i), t_out[i], s);
+    }
+  }
+
   // Bytes one application of P^{-1} moves as stored: every V-cycle (or
   // Chebyshev-only inverse) as executed, every product's matrix once with its
   // input read and its output written (and read, for r - A x) once, the
@@ -1589,9 +1673,23 @@ struct Precond {
       fluid = 2 * ga + gmres(uz_k, n_p, H[FSI_H_P].bytes_per_cycle, prod(Spm, n_p, n_p, 1)) +
               prod(Dm, n_vf, n_p, 2) + prod(Gm, n_p, n_vf, 2);
     }
-    if (order == FSI_ORDER_FSM)
-      return mesh + solid + 2 * fluid + prod(Csf, n_f, n_s, 2) + prod(Cms, n_s, n_m, 2) +
-             prod(Cfms, n_m + n_s, n_f, 1) + 3.0 * w * double(n_f);
+    if (order != FSI_ORDER_MSF) {
+      // the steps of apply_ordered: an inverse per field, a second one for
+      // every backward update, the coupling products (r - A x reads r too)
+      const double inv_b[3] = {mesh, solid, fluid};
+      const int64_t nb[3] = {n_m, n_s, n_f};
+      const int* o = kOrderFields[order];
+      double b = 0.0;
+      for (int k = 0; k < 3; ++k) {
+        b += inv_b[o[k]];
+        b += coupling_bytes(o[k], o, 0, k, 2);
+      }
+      for (int k = 1; k >= 0; --k) {
+        const double cb = coupling_bytes(o[k], o, k + 1, 3, 1);
+        if (cb > 0.0) b += inv_b[o[k]] + cb + 3.0 * w * double(nb[o[k]]);
+      }
+      return b;
+    }
     return 2 * mesh + 2 * solid + prod(Cfms, n_m + n_s, n_f, 2) + fluid + prod(Csf, n_f, n_s, 1) +
            prod(Cms, n_s, n_m, 1) + 3.0 * w * double(n_s + n_m);
   }
@@ -1604,16 +1702,8 @@ struct Precond {
     T* z_m = z;
     T* z_s = z + n_m;
     T* z_f = z + n_m + n_s;
-    if (order == FSI_ORDER_FSM) {
-      // the blocks in the reverse order (fluid, solid, mesh)
-      fluid_inverse(r_f, z_f, s);                            // x_f = F^{-1} r_f
-      spmv_sub<T>(Csf, z_f, r_s, ts->as<T>(), s);            // x_s = S^{-1} (r_s - C_sf x_f)
-      solid(ts->as<T>(), z_s, s);
-      spmv_sub<T>(Cms, z_s, r_m, tm->as<T>(), s);            // x_m = M^{-1} (r_m - C_ms x_s)
-      vcycle(H[FSI_H_M], tm->as<T>(), z_m, s);
-      spmv<T>(Cfms, z, tf->as<T>(), s);                      // x_f -= F^{-1} (C_fm x_m + C_fs x_s)
-      fluid_inverse(tf->as<T>(), tf2->as<T>(), s);
-      vsub<T>(n_f, z_f, tf2->as<T>(), s);
+    if (order != FSI_ORDER_MSF) {
+      apply_ordered(r, z, s);
       return;
     }
     vcycle(H[FSI_H_M], r_m, z_m, s);                         // 1. x_m = M^{-1} r_m
@@ -1884,6 +1974,10 @@ std::unique_ptr<Precond<T>> make_precond(fsi_ctx& c) {
     P->inner_pc = c.fluid_inner_pc;
     if (c.fluid_inner > 0) P->Fm = upload_segments<T>(F, bounds, groups, 2, s);
     P->order = c.order;
+    if (c.order == FSI_ORDER_MFS || c.order == FSI_ORDER_SFM) {  // the fluid in the middle
+      P->Cfm = upload<T>(c.blk[FSI_CFM], s);
+      P->Cfs = upload<T>(c.blk[FSI_CFS], s);
+    }
     P->uz_k = c.uzawa_inner;
     if (c.uzawa_inner > 0) {
       const int64_t vb[2] = {0, c.n_vf};
@@ -3378,7 +3472,7 @@ static fsi_status build_precond_impl(fsi_ctx& c, const fsi_precond_opts* opts) {
       throw Error(FSI_ERR_ARG, "GMRES on F and GMRES on the Uzawa-like step's inverses do not combine");
     if (o.x_approx != FSI_X_F && o.x_approx != FSI_X_BLOCKDIAG)
       throw Error(FSI_ERR_ARG, "unknown approximation of the fluid Schur complement X");
-    if (o.order != FSI_ORDER_MSF && o.order != FSI_ORDER_FSM) throw Error(FSI_ERR_ARG, "unknown block order");
+    if (o.order < FSI_ORDER_MSF || o.order > FSI_ORDER_FMS) throw Error(FSI_ERR_ARG, "unknown block order");
     SaParams prm;
     prm.eps0 = o.strength0;
     prm.max_coarse = o.max_coarse;

@@ -123,7 +123,7 @@ class CMlpTrainOpts(ctypes.Structure):
 MLP_LOSS = {"l2": 0, "energy": 1}
 INNER_PC = {"uzawa": 0, "triangular": 1}
 X_APPROX = {"F": 0, "blockdiag": 1}
-ORDER = {"msf": 0, "fsm": 1}
+ORDER = {"msf": 0, "fsm": 1, "mfs": 2, "smf": 3, "sfm": 4, "fms": 5}
 
 
 class CMlpTrainInfo(ctypes.Structure):
@@ -366,7 +366,8 @@ class FsiSolver:
         x_approx: "F" or "blockdiag" (the fluid operator standing for the
         Schur complement X).  uzawa_inner: GMRES steps per inverse of the
         Uzawa-like fluid step (Section 4.4 as written; 0 = one V-cycle).
-        order: "msf" (the paper's block order) or "fsm" (the reverse order)."""
+        order: the block order of the factorisation, "msf" (the paper's)
+        or another permutation of m(esh), s(olid), f(luid)."""
         def mask_of(names):
             m = 0
             for name in names:

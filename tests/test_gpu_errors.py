@@ -131,7 +131,7 @@ def test_call_order_and_argument_checks():
     o.precision = 0
     o.fluid_inner, o.fluid_inner_pc = 2, 5  # an unknown inner preconditioner
     assert F.STATUS[s.lib.fsi_build_precond(s.ctx, ctypes.byref(o))] == "FSI_ERR_ARG"
-    o.fluid_inner, o.fluid_inner_pc, o.order = 0, 0, 2  # an unknown block order
+    o.fluid_inner, o.fluid_inner_pc, o.order = 0, 0, 6  # an unknown block order
     assert F.STATUS[s.lib.fsi_build_precond(s.ctx, ctypes.byref(o))] == "FSI_ERR_ARG"
     _, info = s.solve(_dev(sysm.b))  # the failed calls left the preconditioner in place
     assert info.converged

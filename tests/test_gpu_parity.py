@@ -173,30 +173,36 @@ def test_apply_precond_inner_gmres_parity_on_imported_hierarchies(name, k, pc):
     s.close()
 
 
-@pytest.mark.parametrize("name,k", [("tiny3d", 0), ("c1", 0), ("c2", 0), ("c1", 2), ("c2", 2)])
-def test_reverse_block_order_precond_matches_oracle(name, k):
-    """The factorisation with the blocks in the reverse order (order="fsm":
-    fluid, solid, mesh; the remark on block orders in Section 4.1): P^{-1} r
-    on the oracle's hierarchies, element-wise per block, within 1e-12 with
-    V-cycle inverses and 1e-10 with the fluid inverse as k inner GMRES steps
-    (the same Krylov minimiser by different Gram-Schmidt and Givens codes,
-    taken twice per application here).  The result differs from the paper's
-    order (another preconditioner), and on c1 a solve with the library's own
-    hierarchies converges and agrees with the oracle's FGMRES solution with
-    the same preconditioner within 1e-6."""
+ORDER_CASES = ([("tiny3d", "fsm", 0), ("c1", "fsm", 0), ("c2", "fsm", 0), ("c1", "fsm", 2), ("c2", "fsm", 2)] +
+               [(n, o, 0) for o in ("mfs", "smf", "sfm", "fms") for n in ("tiny3d", "c1")] +
+               [("c2", "mfs", 0), ("c2", "sfm", 2), ("c1", "smf", 2)])
+
+
+@pytest.mark.parametrize("name,order,k", ORDER_CASES)
+def test_block_order_precond_matches_oracle(name, order, k):
+    """The factorisation with the blocks in another order (the remark on
+    block orders in Section 4.1; "fsm" the reverse of the paper's mesh,
+    solid, fluid): P^{-1} r on the oracle's hierarchies, element-wise per
+    block, within 1e-12 with V-cycle inverses and 1e-10 with the fluid
+    inverse as k inner GMRES steps (the same Krylov minimiser by different
+    Gram-Schmidt and Givens codes, taken twice per application in some
+    orders).  The result differs from the paper's order (another
+    preconditioner), and on c1 a solve with the library's own hierarchies
+    converges and agrees with the oracle's FGMRES solution with the same
+    preconditioner within 1e-6."""
     from oracle import krylov, precond
     from paper_1801_05648_amd import FsiSolver
     bs, H = _oracle(name)
     sysm = system(name, 0)
     kw = dict(fluid_inner=k, fluid_inner_pc="triangular") if k else {}
     s = FsiSolver.from_system(sysm, device=0)
-    s.build_precond("f64", order="fsm", **kw)
-    P = precond.amg_preconditioner(bs, H, order="fsm", **kw)
+    s.build_precond("f64", order=order, **kw)
+    P = precond.amg_preconditioner(bs, H, order=order, **kw)
     if name == "c1":
         x, info = s.solve(_dev(sysm.b), tol=1e-8)
         xo, io = krylov.fgmres(bs.matvec, P, sysm.b, tol=1e-12, restart=50, maxit=500)
         err = _rel(x.cpu().numpy(), xo)
-        print(f"c1 reverse order (k={k}): GPU {info.iters} it, oracle {io.iters} it to 1e-12, rel. diff {err:.2e}")
+        print(f"c1 order {order} (k={k}): GPU {info.iters} it, oracle {io.iters} it to 1e-12, rel. diff {err:.2e}")
         assert info.converged and err <= 1e-6
     _import_oracle_hierarchies(s, H)
     r = np.random.default_rng(31).standard_normal(bs.N)
@@ -206,7 +212,7 @@ def test_reverse_block_order_precond_matches_oracle(name, k):
     tol = 1e-10 if k else 1e-12
     for part, (a, b) in zip(("mesh", "solid", "fluid"), zip(bs.split(z), bs.split(ref))):
         e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
-        print(f"{name} reverse order (k={k}) P^-1 r {part}: max-abs {e:.2e}")
+        print(f"{name} order {order} (k={k}) P^-1 r {part}: max-abs {e:.2e}")
         assert e <= tol, part
     assert _rel(precond.amg_preconditioner(bs, H, **kw)(r), ref) > 1e-6
 
