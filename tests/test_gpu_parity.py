@@ -217,6 +217,27 @@ def test_block_order_precond_matches_oracle(name, order, k):
     assert _rel(precond.amg_preconditioner(bs, H, **kw)(r), ref) > 1e-6
 
 
+@pytest.mark.parametrize("order", ["fsm", "smf", "mfs"])
+def test_block_order_fp32_precond_solve_matches_oracle(order):
+    """Another block order with the FP32 preconditioner (FP64 Krylov loop):
+    the c1 solve reaches 1e-8 and lies within 1e-6 of the FP64 oracle's
+    FGMRES solution with the same order."""
+    from oracle import krylov, precond
+    from paper_1801_05648_amd import FsiSolver
+    bs, H = _oracle("c1")
+    sysm = system("c1", 0)
+    s = FsiSolver.from_system(sysm, device=0)
+    s.build_precond("f32", order=order)
+    x, info = s.solve(_dev(sysm.b), tol=1e-8)
+    s.close()
+    xo, io = krylov.fgmres(bs.matvec, precond.amg_preconditioner(bs, H, order=order), sysm.b, tol=1e-12,
+                           restart=50, maxit=500)
+    err = _rel(x.cpu().numpy(), xo)
+    print(f"c1 order {order} FP32 preconditioner: GPU {info.iters} it, oracle {io.iters} it to 1e-12, "
+          f"rel. diff {err:.2e}")
+    assert info.converged and err <= 1e-6
+
+
 def test_library_setup_reproduces_oracle_aggregates_c1():
     """Level-0 aggregation is integer work on identical inputs: bit-exact."""
     bs, H = _oracle("c1")
